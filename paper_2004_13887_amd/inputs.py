@@ -1,0 +1,281 @@
+"""Seeded synthetic workloads: grids, materials and initial states.
+
+This module generates inputs only.  It contains none of the time-stepping
+method's arithmetic and imports nothing else from this package, so the CPU
+oracle's tests and the GPU path can both draw their inputs from it.
+
+Workloads (shapes of the paper's own test problems; the paper uses no public
+dataset):
+
+* ``parity``    32 (phi) x 32 (theta) x 16 (r) regional sector, 30 x 30 deg,
+                Mach 1e-2, 1 step, K = 3.
+* ``global``    512 x 256 x 128 full sphere (phi periodic, theta in [0, pi]),
+                Mach 1e-4, 10 steps, K = 3; bubble at 45 deg latitude.
+* ``sweeps``    1024 x 512 x 64 regional sector with 100 m horizontal spacing,
+                Mach 1e-6, 5 steps, K = 3.
+* ``ensemble``  64 regional members, each size uniform in [64, 256] per
+                direction, 10 steps, K = 3.
+* ``adjoint``   256 x 128 x 64 sector, 100 m horizontal, 10 steps.
+
+Initial data (paper section "Rising thermal bubble" for the physical constants
+of dry air and the potential temperature / Exner relation):
+
+* isothermal T0 = 300 K background in discrete hydrostatic balance: the radial
+  momentum equation at rest, (1/rho_face)(p_i - p_{i-1})/dr + g = 0 with
+  rho_face the mean of the two cell densities, is integrated upward from
+  p_0 = p00 exp(-g dr / (2 R T0)), p00 = 1e5 Pa;
+* a Gaussian potential-temperature bubble dTheta = A exp(-(L/R_b)^2), L the
+  chord distance from the bubble centre, T = T0 + dTheta (p/p00)^{R/c_p};
+* face velocities u = M c0 xi, xi ~ U[-1, 1] i.i.d. (u_r array first, then
+  u_theta, then u_phi, each in C order), c0 = sqrt(gamma R T0); Dirichlet
+  (boundary-normal) faces set to 0.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field, replace
+
+import numpy as np
+
+EARTH_R1 = 6371.0e3
+SHELL_DEPTH = 10.0e3
+P00 = 1.0e5
+T0 = 300.0
+SEED_BASE = 200413887
+
+
+@dataclass(frozen=True)
+class MaterialSpec:
+    cp: float
+    cv: float
+    pi_inf: float
+    mu: float
+    prandtl: float
+    omega: float
+    g_r: float
+
+    @property
+    def gamma(self) -> float:
+        return self.cp / self.cv
+
+    @property
+    def R(self) -> float:
+        return self.cp - self.cv
+
+    def astuple(self):
+        return (self.cp, self.cv, self.pi_inf, self.mu, self.prandtl, self.omega, self.g_r)
+
+
+# dry air at about 300 K, as in the paper's bubble tests
+AIR = MaterialSpec(cp=1000.0, cv=713.0, pi_inf=0.0, mu=1.846e-5, prandtl=0.71, omega=0.0,
+                   g_r=9.80665)
+# manufactured-solution test: gamma = 1.6, mu = Pr = 1, no rotation, no gravity
+# (c_v = 1 and pi_inf = 0 are not printed in the paper; rho = 1 with
+# T = p / (c_v (gamma-1)) requires pi_inf = 0)
+MMS = MaterialSpec(cp=1.6, cv=1.0, pi_inf=0.0, mu=1.0, prandtl=1.0, omega=0.0, g_r=0.0)
+
+
+@dataclass(frozen=True)
+class GridSpec:
+    nr: int
+    nt: int
+    np: int
+    r1: float
+    r2: float
+    t1: float
+    t2: float
+    p1: float
+    p2: float
+    periodic: bool = False
+
+    @property
+    def npf(self) -> int:
+        return self.np if self.periodic else self.np + 1
+
+    @property
+    def ncells(self) -> int:
+        return self.nr * self.nt * self.np
+
+    def shapes(self):
+        nr, nt, np_, npf = self.nr, self.nt, self.np, self.npf
+        return {"p": (nr, nt, np_), "ur": (nr + 1, nt, np_), "ut": (nr, nt + 1, np_),
+                "uf": (nr, nt, npf), "T": (nr, nt, np_)}
+
+    def args(self):
+        return (self.nr, self.nt, self.np, self.r1, self.r2, self.t1, self.t2, self.p1, self.p2,
+                self.periodic)
+
+    @property
+    def pole_lo(self) -> bool:
+        return self.t1 == 0.0
+
+    @property
+    def pole_hi(self) -> bool:
+        return abs(self.t2 - math.pi) <= 1e-12
+
+
+@dataclass(frozen=True)
+class Workload:
+    name: str
+    grid: GridSpec
+    mach: float
+    amplitude: float
+    steps: int
+    K: int
+    seed: object
+    bubble_theta: float = math.pi / 2
+    bubble_phi: float = math.pi
+    bubble_height: float = 2.0e3
+    bubble_radius: float = 2.0e3
+    material: MaterialSpec = AIR
+    cfl: float = 5.0
+
+
+def sector(nr, nt, np_, dtheta, dphi, theta_c=math.pi / 2, phi_c=math.pi):
+    return GridSpec(nr, nt, np_, EARTH_R1, EARTH_R1 + SHELL_DEPTH,
+                    theta_c - 0.5 * nt * dtheta, theta_c + 0.5 * nt * dtheta,
+                    phi_c - 0.5 * np_ * dphi, phi_c + 0.5 * np_ * dphi, False)
+
+
+def full_sphere(nr, nt, np_):
+    return GridSpec(nr, nt, np_, EARTH_R1, EARTH_R1 + SHELL_DEPTH, 0.0, math.pi, 0.0,
+                    2.0 * math.pi, True)
+
+
+H100 = 100.0 / EARTH_R1  # 100 m of arc at r1
+
+WORKLOADS = {
+    "parity": Workload("parity", sector(16, 32, 32, math.radians(30) / 32, math.radians(30) / 32),
+                       mach=1e-2, amplitude=0.5, steps=1, K=3, seed=SEED_BASE + 1),
+    "global": Workload("global", full_sphere(128, 256, 512), mach=1e-4, amplitude=0.5, steps=10,
+                       K=3, seed=SEED_BASE + 2, bubble_theta=math.pi / 4),
+    "sweeps": Workload("sweeps", sector(64, 512, 1024, H100, H100), mach=1e-6, amplitude=0.5,
+                       steps=5, K=3, seed=SEED_BASE + 3),
+    "adjoint": Workload("adjoint", sector(64, 128, 256, H100, H100), mach=1e-2, amplitude=0.5,
+                        steps=10, K=3, seed=SEED_BASE + 5),
+}
+
+
+def scaled(w: Workload, nr: int, nt: int, np_: int, name: str | None = None) -> Workload:
+    """Same recipe on a different grid size (keeps the extents)."""
+    g = replace(w.grid, nr=nr, nt=nt, np=np_)
+    return replace(w, grid=g, name=name or f"{w.name}-{np_}x{nt}x{nr}")
+
+
+def ensemble_members(n=64, steps=10, K=3):
+    """Uneven regional members: sizes U{64..256} per direction, amplitude
+    U[0.1, 1] K, log10 Mach U[-6, -2]; member m drawn from PCG64([200413891, m])
+    in the order sizes -> amplitude -> Mach (velocities are drawn later from
+    the same generator by ``initial_state``)."""
+    out = []
+    for m in range(n):
+        rng = np.random.Generator(np.random.PCG64([SEED_BASE + 4, m]))
+        nphi, nth, nr = (int(x) for x in rng.integers(64, 257, 3))
+        amp = float(rng.uniform(0.1, 1.0))
+        mach = float(10.0 ** rng.uniform(-6.0, -2.0))
+        g = sector(nr, nth, nphi, H100, H100)
+        out.append(Workload(f"member{m}", g, mach=mach, amplitude=amp, steps=steps, K=K,
+                            seed=("member", m)))
+    return out
+
+
+def _rng(w: Workload):
+    if isinstance(w.seed, tuple) and w.seed[0] == "member":
+        rng = np.random.Generator(np.random.PCG64([SEED_BASE + 4, w.seed[1]]))
+        rng.integers(64, 257, 3)  # replay the draws that fixed the member
+        rng.uniform(0.1, 1.0)
+        rng.uniform(-6.0, -2.0)
+        return rng
+    return np.random.Generator(np.random.PCG64(w.seed))
+
+
+def coords(g: GridSpec):
+    dr = (g.r2 - g.r1) / g.nr
+    dt = (g.t2 - g.t1) / g.nt
+    dp = (g.p2 - g.p1) / g.np
+    return {
+        "rc": g.r1 + (np.arange(g.nr) + 0.5) * dr, "rf": g.r1 + np.arange(g.nr + 1) * dr,
+        "tc": g.t1 + (np.arange(g.nt) + 0.5) * dt, "tf": g.t1 + np.arange(g.nt + 1) * dt,
+        "pc": g.p1 + (np.arange(g.np) + 0.5) * dp, "pf": g.p1 + np.arange(g.npf) * dp,
+        "dr": dr, "dt": dt, "dp": dp,
+    }
+
+
+def hydrostatic_pressure(g: GridSpec, mat: MaterialSpec, T_bg: float = T0):
+    """Discretely balanced isothermal column p_i (cell centres)."""
+    dr = (g.r2 - g.r1) / g.nr
+    a = mat.g_r * dr / (2.0 * mat.R * T_bg)
+    p = np.empty(g.nr)
+    p[0] = P00 * math.exp(-a)
+    for i in range(1, g.nr):
+        p[i] = p[i - 1] * (1.0 - a) / (1.0 + a)
+    return p
+
+
+def time_step(w: Workload, T_max: float) -> float:
+    """tau at the workload's acoustic CFL number: cfl * d_min / c_max, with
+    d_min = min(dr, r1 dtheta, r1 sin(theta_min) dphi) over cell centres."""
+    g, mat = w.grid, w.material
+    c = coords(g)
+    smin = float(np.min(np.sin(c["tc"])))
+    dmin = min(c["dr"], g.r1 * c["dt"], g.r1 * smin * c["dp"])
+    cmax = math.sqrt(mat.gamma * mat.R * T_max)
+    return w.cfl * dmin / cmax
+
+
+def initial_state(w: Workload):
+    """(fields, tau) for a workload; fields is a dict of C-contiguous float64."""
+    g, mat = w.grid, w.material
+    rng = _rng(w)
+    c = coords(g)
+    sh = g.shapes()
+    pcol = hydrostatic_pressure(g, mat)
+    p = np.broadcast_to(pcol[:, None, None], sh["p"]).copy()
+    # bubble: chord distance from the centre, 2 km above r1
+    rc, tc, pc = np.meshgrid(c["rc"], c["tc"], c["pc"], indexing="ij")
+    rb = g.r1 + w.bubble_height
+    xb = rb * np.sin(w.bubble_theta) * np.cos(w.bubble_phi)
+    yb = rb * np.sin(w.bubble_theta) * np.sin(w.bubble_phi)
+    zb = rb * np.cos(w.bubble_theta)
+    x = rc * np.sin(tc) * np.cos(pc) - xb
+    y = rc * np.sin(tc) * np.sin(pc) - yb
+    z = rc * np.cos(tc) - zb
+    L2 = (x * x + y * y + z * z) / (w.bubble_radius ** 2)
+    dtheta = w.amplitude * np.exp(-L2)
+    T = T0 + dtheta * (p / P00) ** (mat.R / mat.cp)
+    c0 = math.sqrt(mat.gamma * mat.R * T0)
+    scale = w.mach * c0
+    ur = scale * rng.uniform(-1.0, 1.0, sh["ur"])
+    ut = scale * rng.uniform(-1.0, 1.0, sh["ut"])
+    uf = scale * rng.uniform(-1.0, 1.0, sh["uf"])
+    ur[0] = 0.0
+    ur[-1] = 0.0
+    ut[:, 0] = 0.0
+    ut[:, -1] = 0.0
+    if not g.periodic:
+        uf[:, :, 0] = 0.0
+        uf[:, :, -1] = 0.0
+    fields = {"p": p, "ur": ur, "ut": ut, "uf": uf, "T": np.ascontiguousarray(T)}
+    fields = {k: np.ascontiguousarray(v, dtype=np.float64) for k, v in fields.items()}
+    tau = time_step(w, float(T.max()))
+    return fields, tau
+
+
+def random_fields(g: GridSpec, seed: int, base=None, scale=1.0):
+    """Random perturbation fields (for line-solve tests): base + scale * U[-1,1]
+    at every unknown, 0 on boundary-normal faces."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    out = {}
+    for k, s in g.shapes().items():
+        a = scale * rng.uniform(-1.0, 1.0, s)
+        if base is not None:
+            a = a + base[k]
+        out[k] = np.ascontiguousarray(a)
+    out["ur"][0] = 0.0
+    out["ur"][-1] = 0.0
+    out["ut"][:, 0] = 0.0
+    out["ut"][:, -1] = 0.0
+    if not g.periodic:
+        out["uf"][:, :, 0] = 0.0
+        out["uf"][:, :, -1] = 0.0
+    return out
