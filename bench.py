@@ -1,0 +1,185 @@
+"""Benchmark: split time steps of the full-sphere global workload on one GPU.
+
+    python bench.py [--gpus 1] [--steps 10] [--warmup 2] [--no-cpu]
+
+Workload: 512 (phi, periodic) x 256 (theta, poles) x 128 (r) cells over a
+10 km shell, FP64, K = 3 nonlinear iterations per split step, Mach 1e-4,
+seeded synthetic initial data (hydrostatic isothermal atmosphere, Gaussian
+potential-temperature bubble, seeded velocity noise).  A "step" is one call of
+dsw_split_step (K x (residual + three line sweeps)); inputs are resident in
+HBM before the timed region.  Prints one JSON line.
+"""
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM = 8.0e12  # MI355X HBM3E, bytes/s
+WORKLOAD = "global"
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_sources_sha():
+    h = hashlib.sha256()
+    for f in ("dsw_common.hpp", "residual.hip", "sweeps.hip", "api.hip"):
+        with open(os.path.join(ROOT, "paper_2004_13887_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def algorithmic_bytes(counts):
+    """per-launch algorithmic bytes of each kernel kind (each array read or
+    written once; neighbour re-reads are not counted)"""
+    S = 8 * sum(counts)
+    return {"residual": 4 * S, "sweep_r": 3 * S, "sweep_theta": 3 * S, "sweep_phi_update": 4 * S,
+            "state_copy": 2 * S}
+
+
+def measured_traffic(kind, sha):
+    """HBM bytes per launch from committed rocprofv3 counter summaries, only if
+    they were taken on the current kernel sources."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            t = json.load(fh)
+    except OSError:
+        return None
+    e = t.get(kind)
+    if not e or e.get("source_sha") != sha:
+        return None
+    return e.get("bytes_per_launch")
+
+
+def cpu_baseline():
+    """The oracle timed on the host on a bounded sample of the same workload:
+    the global grid recipe with 16 radial levels (512 x 256 x 16 cells), one
+    split step with K = 3."""
+    import oracle
+    from paper_2004_13887_amd import inputs as I
+    w = I.scaled(I.WORKLOADS[WORKLOAD], 16, 256, 512, name="global-16-levels")
+    U0, tau = I.initial_state(w)
+    g = oracle.Grid(*w.grid.args())
+    m = oracle.Material(*w.material.astuple())
+    t0 = time.perf_counter()
+    oracle.split_step(g, m, U0, tau, w.K)
+    dt = time.perf_counter() - t0
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except AttributeError:
+        cores = os.cpu_count()
+    if os.environ.get("OMP_NUM_THREADS"):
+        cores = min(cores, int(os.environ["OMP_NUM_THREADS"]))
+    return {"value": w.grid.ncells / dt, "unit": "grid-point updates/s", "cores": cores,
+            "kind": "oracle",
+            "sample": f"one split step (K={w.K}) of the global recipe on 512x256x16 cells "
+                      f"({w.grid.ncells} cells), {dt:.2f} s wall"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the multi-GPU path is "
+              "not part of this build", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2004_13887_amd import dsw
+    from paper_2004_13887_amd import inputs as I
+
+    w = I.WORKLOADS[WORKLOAD]
+    log(f"[bench] generating {w.name}: {w.grid.np}x{w.grid.nt}x{w.grid.nr} cells")
+    U0, tau = I.initial_state(w)
+    grid = dsw.Grid.from_spec(w.grid, w.material)
+    bufs = [dsw.to_device(U0), grid.empty()]
+    counts = [v.numel() for v in bufs[0].values()]
+    stream = torch.cuda.current_stream()
+
+    def step(n):
+        src, dst = bufs[n % 2], bufs[(n + 1) % 2]
+        grid.split_step(src, dst, tau, w.K, stream)
+
+    log(f"[bench] warmup {args.warmup} steps (tau = {tau:.4f} s, K = {w.K})")
+    for n in range(args.warmup):
+        step(n)
+    torch.cuda.synchronize()
+    grid.get_status()
+
+    grid.set_timing(True)
+    grid.read_timing(stream)  # clear
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    for n in range(args.steps):
+        step(args.warmup + n)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    per_kernel = grid.read_timing(stream)
+    grid.set_timing(False)
+    grid.get_status()
+    gpu_ms = ev0.elapsed_time(ev1)
+    ms_per_step = gpu_ms / args.steps
+    log(f"[bench] {args.steps} steps: {gpu_ms:.2f} ms GPU, {wall * 1e3:.2f} ms wall")
+
+    cells = w.grid.ncells
+    value = cells * args.steps / (gpu_ms * 1e-3)
+    model_bytes = 8 * (55 + 70 * (w.K - 1)) * cells  # per split step, fixed traffic model
+    alg = algorithmic_bytes(counts)
+    kstats = {}
+    for k, (ms, n) in per_kernel.items():
+        if n:
+            avg = ms / n * 1e-3
+            kstats[k] = {"avg_ms": avg * 1e3, "launches": n, "total_ms": ms,
+                         "GBps": alg[k] / avg / 1e9}
+            log(f"[bench] {k:17s} {n:4d} launches, avg {avg * 1e3:8.3f} ms, "
+                f"{alg[k] / avg / 1e9:8.1f} GB/s algorithmic")
+    dom = max(kstats, key=lambda k: kstats[k]["total_ms"])
+    sha = kernel_sources_sha()
+    achieved = alg[dom] / (kstats[dom]["avg_ms"] * 1e-3) / 1e9
+    traffic = measured_traffic(dom, sha)
+    out = {
+        "metric": "grid-point updates/s per split step (FP64)",
+        "value": value,
+        "unit": "grid-point updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "global: 512 (phi, periodic) x 256 (theta) x 128 (r) full sphere, "
+                               "10 km shell, K=3, Mach 1e-4, seeded bubble + noise",
+                   "cells": cells, "K": w.K, "tau_s": tau},
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": PEAK_HBM / 1e9,
+                     "unit": "GB/s", "frac": achieved / (PEAK_HBM / 1e9),
+                     "traffic": traffic, "source_sha": sha},
+        "step_model_GBps": model_bytes / (ms_per_step * 1e-3) / 1e9,
+        "step_model_frac": model_bytes / (ms_per_step * 1e-3) / PEAK_HBM,
+        "kernels": kstats,
+    }
+    if not args.no_cpu:
+        log("[bench] timing the CPU oracle on a bounded sample")
+        out["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,150 @@
+/*
+ * dsw.h -- C-ABI of the MI355X direction-splitting library (libdsw.so).
+ *
+ * One time step of the direction-split nonlinear iteration of Frolov, Minev &
+ * Takhirov, "An efficient algorithm for weakly compressible flows in spherical
+ * geometries" (arXiv 2004.13887), section 2.2, eqs. (chapter3mainsd),
+ * (splitting2) and (spl1)-(spl3), for the compressible Navier-Stokes system in
+ * primitive variables U = [p, u_r, u_theta, u_phi, T] of section 2.1,
+ * eqs. (nonconservmass)-(nonconservener) with the stiffened-gas equation of
+ * state (nonconserveos), on a staggered (MAC) grid over a spherical shell
+ * sector or the full sphere.  The direction operators D_r, D_theta, D_phi are
+ * those of Appendix B, eqs. (dr), (dtheta), (dphi).
+ *
+ * Conventions
+ * -----------
+ * Every field argument is a dsw_fields of five DEVICE pointers (FP64), each a
+ * dense C-order array (phi fastest):
+ *     p, T : [n_r][n_theta][n_phi]           cell centres
+ *     ur   : [n_r+1][n_theta][n_phi]         r faces
+ *     ut   : [n_r][n_theta+1][n_phi]         theta faces
+ *     uf   : [n_r][n_theta][n_phi_f]         phi faces, n_phi_f = n_phi if
+ *                                            periodic_phi else n_phi + 1
+ * Boundary-normal faces (r = r1, r2; theta walls or poles; phi walls) carry
+ * Dirichlet velocities and are never changed by the library; they are 0 for
+ * the no-slip walls and the poles this library implements.  Pressure and
+ * temperature have zero normal gradient at every non-periodic boundary.  At a
+ * pole (theta1 = 0 or theta2 = pi) u_theta = 0 on the pole face and the ghost
+ * values are u_r: +interior, u_phi: -interior, p and T: +interior.
+ *
+ * The caller owns all field buffers (they must not alias unless stated) and
+ * passes a HIP stream (hipStream_t as void*, NULL = the null stream); calls
+ * enqueue work on that stream and return without synchronising.  A handle is
+ * not thread safe; calls on one handle must be ordered (one stream).  The
+ * library owns the handle, its metric tables and its workspace.
+ *
+ * Return codes: DSW_OK (0) or a negative DSW_E* code; dsw_last_error() gives
+ * a thread-local message.  Device-side conditions (a vanishing pivot, a
+ * non-positive temperature or p + pi_inf) set a status word read by
+ * dsw_get_status().
+ */
+#ifndef DSW_H
+#define DSW_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define DSW_OK 0
+#define DSW_EINVAL (-1)    /* invalid argument or descriptor               */
+#define DSW_ENOMEM (-2)    /* device allocation failed                     */
+#define DSW_EHIP (-3)      /* a HIP runtime call failed                    */
+#define DSW_ENONPHYS (-4)  /* T <= 0 or p + pi_inf <= 0 met on the device  */
+#define DSW_ESINGULAR (-5) /* zero pivot in a line solve                   */
+
+/* Grid: n_r x n_theta x n_phi cells on [r1,r2] x [theta1,theta2] x [phi1,phi2]
+ * (paper section 2.1, domain Omega).  Uniform spacing in r, theta and phi.
+ * Requirements: all n >= 3; 0 < r1 < r2; 0 <= theta1 < theta2 <= pi;
+ * phi1 < phi2; periodic_phi != 0 requires phi2 - phi1 = 2 pi (full sphere in
+ * longitude; the phi line systems are then cyclic). */
+typedef struct {
+  int32_t n_r, n_theta, n_phi;
+  int32_t periodic_phi;
+  double r1, r2, theta1, theta2, phi1, phi2;
+} dsw_grid_desc;
+
+/* Material constants (paper section 2.1): c_p, c_v (gamma = c_p/c_v), the
+ * stiffened-gas pi_inf, dynamic viscosity mu, Prandtl number, the rotation
+ * rate omega about the polar axis, and the radial gravity g_r (the equations
+ * carry +g on the left-hand side, so g_r > 0 pulls inward). */
+typedef struct {
+  double cp, cv, pi_inf, mu, prandtl, omega, g_r;
+} dsw_material;
+
+/* Five device pointers, layout as above. */
+typedef struct {
+  double *p, *ur, *ut, *uf, *T;
+} dsw_fields;
+
+/* Element counts and shapes of the five arrays (order p, ur, ut, uf, T). */
+typedef struct {
+  int64_t shape[5][3];
+  int64_t count[5];
+  int64_t bytes_per_state; /* sum of the five arrays in bytes */
+} dsw_layout_info;
+
+typedef struct dsw_grid dsw_grid;
+
+/* Validate the descriptors, build the metric tables and allocate the
+ * workspace on the current HIP device.  *out receives the handle.
+ * Errors: DSW_EINVAL, DSW_ENOMEM, DSW_EHIP. */
+int dsw_init_grid(const dsw_grid_desc *desc, const dsw_material *mat, dsw_grid **out);
+
+/* Release the handle and its device memory (synchronises the device). */
+int dsw_free_grid(dsw_grid *grid);
+
+/* Shapes and sizes of the field arrays the caller must allocate. */
+int dsw_layout(const dsw_grid *grid, dsw_layout_info *info);
+
+/* Right-hand side of eq. (spl1), simplified: with Ubar = (Uk + Un)/2,
+ *   R = -(Uk - Un) - tau * F_h(Ubar),  F_h(V) = (D + D_M)(V) V + G
+ * (D, D_M, G of eq. (chapter3main)), at every unknown; R = 0 on
+ * boundary-normal faces.  Ubar is written everywhere.  Un, Uk: inputs
+ * (may alias each other); R, Ubar: outputs (must not alias the inputs). */
+int dsw_residual(dsw_grid *grid, const dsw_fields *Un, const dsw_fields *Uk, double tau,
+                 dsw_fields *R, dsw_fields *Ubar, void *stream);
+
+/* Line solves of eqs. (spl1), (spl2), (spl3): x = (I + tau/2 D_d(Ubar))^{-1} rhs
+ * for d = r, theta, phi, with homogeneous increment boundary conditions.  Each
+ * line carries one 3x3-block tridiagonal system in (p, T, u_d) and one scalar
+ * tridiagonal system per transverse velocity; _phi is cyclic when the grid is
+ * periodic.  rhs must be 0 on boundary-normal faces; x is 0 there.
+ * rhs and x must not alias. */
+int dsw_line_solve_r(dsw_grid *grid, const dsw_fields *Ubar, double tau, const dsw_fields *rhs,
+                     dsw_fields *x, void *stream);
+int dsw_line_solve_theta(dsw_grid *grid, const dsw_fields *Ubar, double tau,
+                         const dsw_fields *rhs, dsw_fields *x, void *stream);
+int dsw_line_solve_phi(dsw_grid *grid, const dsw_fields *Ubar, double tau, const dsw_fields *rhs,
+                       dsw_fields *x, void *stream);
+
+/* One split time step (eqs. (spl1)-(spl3) iterated K times, U^{n+1,0} = U^n,
+ * U^{n+1} = U^{n+1,K}): Unp1 receives U^{n+1}.  Un is not modified; Unp1 must
+ * not alias Un.  K >= 1, tau > 0.  Uses the handle's workspace. */
+int dsw_split_step(dsw_grid *grid, const dsw_fields *Un, dsw_fields *Unp1, double tau, int32_t K,
+                   void *stream);
+
+/* Optional per-kernel timing of dsw_split_step.  While enabled, every kernel
+ * the step enqueues is bracketed by a pair of HIP events recorded on the same
+ * stream.  dsw_read_timing synchronises that stream, stores in ms[kind] the
+ * total elapsed time and in launches[kind] the number of launches recorded
+ * since the previous read (kind 0: residual, 1: r sweep, 2: theta sweep,
+ * 3: phi sweep with update, 4: state copy U^{n+1,0} = U^n), then clears the
+ * record. */
+#define DSW_TIMING_KINDS 5
+int dsw_set_timing(dsw_grid *grid, int32_t enable);
+int dsw_read_timing(dsw_grid *grid, void *stream, double ms[DSW_TIMING_KINDS],
+                    int64_t launches[DSW_TIMING_KINDS]);
+
+/* Synchronise the stream, read and clear the device status word.  Returns
+ * DSW_OK, DSW_ENONPHYS or DSW_ESINGULAR (or DSW_EHIP). */
+int dsw_get_status(dsw_grid *grid, void *stream);
+
+/* Thread-local description of the last error (never NULL). */
+const char *dsw_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DSW_H */

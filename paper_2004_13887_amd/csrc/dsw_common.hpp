@@ -1,0 +1,167 @@
+// dsw_common.hpp -- device-side geometry, ghost rules and coefficient fields
+// shared by the residual and line-solve kernels of libdsw (gfx950, FP64).
+//
+// MAC grid (paper section 2.2, "standard central differences on the MAC
+// stencil"): p, T at cell centres, u_r / u_theta / u_phi on the r / theta /
+// phi faces; arrays are C-order with phi fastest.  Ghost values outside the
+// grid: p, T copy the interior value (zero normal gradient); a velocity
+// component tangential to a wall takes minus the interior value (no-slip);
+// across a pole u_r is copied and u_phi negated; phi wraps when periodic.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace dsw {
+
+enum { F_P = 0, F_UR = 1, F_UT = 2, F_UF = 3, F_T = 4 };
+
+struct Geo {
+  int nr, nt, np, npf;
+  int periodic, pole_lo, pole_hi;
+  double dr, dt, dp;
+  const double *rc, *rf; // centre radii [nr], face radii [nr+1]
+  const double *sc, *cc; // sin, cos of theta at centres [nt]
+  const double *sf, *cf; // sin, cos of theta at faces [nt+1]
+};
+
+struct Mat {
+  double gam, Rg, pinf, mu, kap, omega, g_r;
+};
+
+__device__ __forceinline__ long idx_c(const Geo &g, int i, int j, int k) {
+  return ((long)i * g.nt + j) * g.np + k;
+}
+__device__ __forceinline__ long idx_r(const Geo &g, int f, int j, int k) {
+  return ((long)f * g.nt + j) * g.np + k;
+}
+__device__ __forceinline__ long idx_t(const Geo &g, int i, int f, int k) {
+  return ((long)i * (g.nt + 1) + f) * g.np + k;
+}
+__device__ __forceinline__ long idx_f(const Geo &g, int i, int j, int f) {
+  return ((long)i * g.nt + j) * g.npf + f;
+}
+__device__ __forceinline__ int wrapk(const Geo &g, int k) {
+  return k < 0 ? k + g.np : (k >= g.np ? k - g.np : k);
+}
+__device__ __forceinline__ int clampi(int x, int lo, int hi) { return x < lo ? lo : (x > hi ? hi : x); }
+
+// State sources: a single array set, or the midpoint of two.
+struct SrcOne {
+  const double *a[5];
+  __device__ __forceinline__ double ld(int f, long x) const { return a[f][x]; }
+};
+struct SrcMid {
+  const double *n[5], *k[5];
+  __device__ __forceinline__ double ld(int f, long x) const { return 0.5 * (k[f][x] + n[f][x]); }
+};
+
+// p or T at a (possibly ghost) centre
+template <class S>
+__device__ __forceinline__ double gC(const Geo &g, const S &s, int fid, int i, int j, int k) {
+  i = clampi(i, 0, g.nr - 1);
+  j = clampi(j, 0, g.nt - 1);
+  k = g.periodic ? wrapk(g, k) : clampi(k, 0, g.np - 1);
+  return s.ld(fid, idx_c(g, i, j, k));
+}
+// u_r at r-face f (0..nr), ghosts across theta and phi boundaries
+template <class S>
+__device__ __forceinline__ double gR(const Geo &g, const S &s, int f, int j, int k) {
+  double sg = 1.0;
+  if (k < 0 || k >= g.np) {
+    if (g.periodic) k = wrapk(g, k);
+    else { sg = -sg; k = k < 0 ? 0 : g.np - 1; }
+  }
+  if (j < 0) { if (!g.pole_lo) sg = -sg; j = 0; }
+  else if (j >= g.nt) { if (!g.pole_hi) sg = -sg; j = g.nt - 1; }
+  return sg * s.ld(F_UR, idx_r(g, f, j, k));
+}
+// u_theta at theta-face f (0..nt), ghosts across r and phi boundaries
+template <class S>
+__device__ __forceinline__ double gT(const Geo &g, const S &s, int i, int f, int k) {
+  double sg = 1.0;
+  if (k < 0 || k >= g.np) {
+    if (g.periodic) k = wrapk(g, k);
+    else { sg = -sg; k = k < 0 ? 0 : g.np - 1; }
+  }
+  if (i < 0) { sg = -sg; i = 0; }
+  else if (i >= g.nr) { sg = -sg; i = g.nr - 1; }
+  return sg * s.ld(F_UT, idx_t(g, i, f, k));
+}
+// u_phi at phi-face f, ghosts across r and theta boundaries (poles included)
+template <class S>
+__device__ __forceinline__ double gF(const Geo &g, const S &s, int i, int j, int f) {
+  double sg = 1.0;
+  if (g.periodic) f = wrapk(g, f);
+  if (j < 0) { sg = -sg; j = 0; }
+  else if (j >= g.nt) { sg = -sg; j = g.nt - 1; }
+  if (i < 0) { sg = -sg; i = 0; }
+  else if (i >= g.nr) { sg = -sg; i = g.nr - 1; }
+  return sg * s.ld(F_UF, idx_f(g, i, j, f));
+}
+
+template <class S>
+__device__ __forceinline__ double rho_at(const Geo &g, const Mat &m, const S &s, int i, int j, int k) {
+  return (gC(g, s, F_P, i, j, k) + m.pinf) / (m.Rg * gC(g, s, F_T, i, j, k));
+}
+
+// Coefficient fields at a centre: centre-averaged velocities, thermodynamic
+// factors and the velocity gradient (physical spherical components; only the
+// symmetric off-diagonal sums S_ab = G_ab + G_ba are needed).
+struct Cent {
+  double ur, ut, uf, P, T, chi;
+  double Grr, Gtt, Gff, Srt, Srf, Stf, tr, div;
+};
+
+template <class S>
+__device__ __forceinline__ double avgR(const Geo &g, const S &s, int i, int j, int k) {
+  return 0.5 * (gR(g, s, i, j, k) + gR(g, s, i + 1, j, k));
+}
+template <class S>
+__device__ __forceinline__ double avgT(const Geo &g, const S &s, int i, int j, int k) {
+  return 0.5 * (gT(g, s, i, j, k) + gT(g, s, i, j + 1, k));
+}
+template <class S>
+__device__ __forceinline__ double avgF(const Geo &g, const S &s, int i, int j, int k) {
+  return 0.5 * (gF(g, s, i, j, k) + gF(g, s, i, j, k + 1));
+}
+
+template <class S>
+__device__ __forceinline__ void centre(const Geo &g, const Mat &m, const S &s, int i, int j, int k,
+                                       Cent &c) {
+  const double r = g.rc[i], sn = g.sc[j], ct = g.cc[j] / g.sc[j];
+  const double r0 = gR(g, s, i, j, k), r1 = gR(g, s, i + 1, j, k);
+  const double t0 = gT(g, s, i, j, k), t1 = gT(g, s, i, j + 1, k);
+  const double f0 = gF(g, s, i, j, k), f1 = gF(g, s, i, j, k + 1);
+  c.ur = 0.5 * (r0 + r1);
+  c.ut = 0.5 * (t0 + t1);
+  c.uf = 0.5 * (f0 + f1);
+  c.P = gC(g, s, F_P, i, j, k) + m.pinf;
+  c.T = gC(g, s, F_T, i, j, k);
+  c.chi = (m.gam - 1.0) * c.T / c.P;
+  c.Grr = (r1 - r0) / g.dr;
+  c.Gtt = (t1 - t0) / (r * g.dt) + c.ur / r;
+  c.Gff = (f1 - f0) / (r * sn * g.dp) + c.ur / r + c.ut * ct / r;
+  c.Srt = (avgT(g, s, i + 1, j, k) - avgT(g, s, i - 1, j, k)) / (2.0 * g.dr) +
+          (avgR(g, s, i, j + 1, k) - avgR(g, s, i, j - 1, k)) / (2.0 * r * g.dt) - c.ut / r;
+  c.Srf = (avgF(g, s, i + 1, j, k) - avgF(g, s, i - 1, j, k)) / (2.0 * g.dr) +
+          (avgR(g, s, i, j, k + 1) - avgR(g, s, i, j, k - 1)) / (2.0 * r * sn * g.dp) - c.uf / r;
+  c.Stf = (avgF(g, s, i, j + 1, k) - avgF(g, s, i, j - 1, k)) / (2.0 * r * g.dt) +
+          (avgT(g, s, i, j, k + 1) - avgT(g, s, i, j, k - 1)) / (2.0 * r * sn * g.dp) - c.uf * ct / r;
+  c.tr = c.Grr + c.Gtt + c.Gff;
+  c.div = (g.rf[i + 1] * g.rf[i + 1] * r1 - g.rf[i] * g.rf[i] * r0) / (r * r * g.dr) +
+          (g.sf[j + 1] * t1 - g.sf[j] * t0) / (r * sn * g.dt) + (f1 - f0) / (r * sn * g.dp);
+}
+
+// full compact divergence at a centre (for the grad-div term of the momentum
+// equations at the faces between two cells)
+template <class S>
+__device__ __forceinline__ double divc(const Geo &g, const S &s, int i, int j, int k) {
+  const double r = g.rc[i], sn = g.sc[j];
+  return (g.rf[i + 1] * g.rf[i + 1] * gR(g, s, i + 1, j, k) - g.rf[i] * g.rf[i] * gR(g, s, i, j, k)) /
+             (r * r * g.dr) +
+         (g.sf[j + 1] * gT(g, s, i, j + 1, k) - g.sf[j] * gT(g, s, i, j, k)) / (r * sn * g.dt) +
+         (gF(g, s, i, j, k + 1) - gF(g, s, i, j, k)) / (r * sn * g.dp);
+}
+
+} // namespace dsw

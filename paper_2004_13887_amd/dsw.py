@@ -1,0 +1,184 @@
+"""Python binding of libdsw.so (the C-ABI in include/dsw.h).
+
+Argument marshalling only: every step of the time step runs in the HIP
+kernels of the library.  PyTorch supplies device memory and the stream.  The
+library must have been built (``__graft_entry__.build()`` or
+``python paper_2004_13887_amd/build.py``); importing this module without it
+raises, there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libdsw.so")
+FIELDS = ("p", "ur", "ut", "uf", "T")
+
+DSW_OK, DSW_EINVAL, DSW_ENOMEM, DSW_EHIP, DSW_ENONPHYS, DSW_ESINGULAR = 0, -1, -2, -3, -4, -5
+_NAMES = {DSW_EINVAL: "DSW_EINVAL", DSW_ENOMEM: "DSW_ENOMEM", DSW_EHIP: "DSW_EHIP",
+          DSW_ENONPHYS: "DSW_ENONPHYS", DSW_ESINGULAR: "DSW_ESINGULAR"}
+
+# every extern "C" symbol the header declares
+SYMBOLS = ("dsw_init_grid", "dsw_free_grid", "dsw_layout", "dsw_residual", "dsw_line_solve_r",
+           "dsw_line_solve_theta", "dsw_line_solve_phi", "dsw_split_step", "dsw_set_timing",
+           "dsw_read_timing", "dsw_get_status", "dsw_last_error")
+TIMING_KINDS = ("residual", "sweep_r", "sweep_theta", "sweep_phi_update", "state_copy")
+
+
+class DswError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+class GridDesc(C.Structure):
+    _fields_ = [("n_r", C.c_int32), ("n_theta", C.c_int32), ("n_phi", C.c_int32),
+                ("periodic_phi", C.c_int32), ("r1", C.c_double), ("r2", C.c_double),
+                ("theta1", C.c_double), ("theta2", C.c_double), ("phi1", C.c_double),
+                ("phi2", C.c_double)]
+
+
+class Material(C.Structure):
+    _fields_ = [(n, C.c_double) for n in ("cp", "cv", "pi_inf", "mu", "prandtl", "omega", "g_r")]
+
+
+class Fields(C.Structure):
+    _fields_ = [(n, C.c_void_p) for n in FIELDS]
+
+
+class LayoutInfo(C.Structure):
+    _fields_ = [("shape", (C.c_int64 * 3) * 5), ("count", C.c_int64 * 5),
+                ("bytes_per_state", C.c_int64)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libdsw.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise FileNotFoundError(
+                f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                "(there is no CPU fallback)")
+        L = C.CDLL(LIB_PATH)
+        P, D, I = C.c_void_p, C.c_double, C.c_int32
+        FP = C.POINTER(Fields)
+        L.dsw_init_grid.argtypes = [C.POINTER(GridDesc), C.POINTER(Material), C.POINTER(C.c_void_p)]
+        L.dsw_free_grid.argtypes = [P]
+        L.dsw_layout.argtypes = [P, C.POINTER(LayoutInfo)]
+        L.dsw_residual.argtypes = [P, FP, FP, D, FP, FP, P]
+        for n in ("dsw_line_solve_r", "dsw_line_solve_theta", "dsw_line_solve_phi"):
+            getattr(L, n).argtypes = [P, FP, D, FP, FP, P]
+        L.dsw_split_step.argtypes = [P, FP, FP, D, I, P]
+        L.dsw_get_status.argtypes = [P, P]
+        L.dsw_set_timing.argtypes = [P, I]
+        L.dsw_read_timing.argtypes = [P, P, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
+        L.dsw_last_error.restype = C.c_char_p
+        for n in SYMBOLS[:-1]:
+            getattr(L, n).restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def _check(rc):
+    if rc != DSW_OK:
+        raise DswError(rc, lib().dsw_last_error().decode())
+
+
+def _fields(d) -> Fields:
+    f = Fields()
+    for n in FIELDS:
+        t = d[n]
+        if not (t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
+            raise ValueError(f"field {n}: need a contiguous float64 device tensor")
+        setattr(f, n, t.data_ptr())
+    return f
+
+
+def _stream(stream):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream)
+
+
+class Grid:
+    """Handle of dsw_init_grid; methods are the C-ABI calls of the same names."""
+
+    def __init__(self, nr, nt, np_, r1, r2, t1, t2, p1, p2, periodic, material):
+        self.desc = GridDesc(int(nr), int(nt), int(np_), 1 if periodic else 0, float(r1), float(r2),
+                             float(t1), float(t2), float(p1), float(p2))
+        self.mat = Material(*(float(x) for x in material))
+        h = C.c_void_p()
+        _check(lib().dsw_init_grid(C.byref(self.desc), C.byref(self.mat), C.byref(h)))
+        self._h = h
+
+    @classmethod
+    def from_spec(cls, spec, material):
+        return cls(*spec.args(), material.astuple())
+
+    def free_grid(self):
+        if getattr(self, "_h", None):
+            lib().dsw_free_grid(self._h)
+            self._h = None
+
+    __del__ = free_grid
+
+    def layout(self):
+        info = LayoutInfo()
+        _check(lib().dsw_layout(self._h, C.byref(info)))
+        return {n: tuple(int(x) for x in info.shape[q]) for q, n in enumerate(FIELDS)}
+
+    def empty(self, device="cuda"):
+        return {n: torch.zeros(s, dtype=torch.float64, device=device) for n, s in self.layout().items()}
+
+    def residual(self, Un, Uk, tau, R, Ubar, stream=None):
+        _check(lib().dsw_residual(self._h, C.byref(_fields(Un)), C.byref(_fields(Uk)), float(tau),
+                                  C.byref(_fields(R)), C.byref(_fields(Ubar)), _stream(stream)))
+
+    def line_solve_r(self, Ubar, tau, rhs, x, stream=None):
+        _check(lib().dsw_line_solve_r(self._h, C.byref(_fields(Ubar)), float(tau),
+                                      C.byref(_fields(rhs)), C.byref(_fields(x)), _stream(stream)))
+
+    def line_solve_theta(self, Ubar, tau, rhs, x, stream=None):
+        _check(lib().dsw_line_solve_theta(self._h, C.byref(_fields(Ubar)), float(tau),
+                                          C.byref(_fields(rhs)), C.byref(_fields(x)), _stream(stream)))
+
+    def line_solve_phi(self, Ubar, tau, rhs, x, stream=None):
+        _check(lib().dsw_line_solve_phi(self._h, C.byref(_fields(Ubar)), float(tau),
+                                        C.byref(_fields(rhs)), C.byref(_fields(x)), _stream(stream)))
+
+    def line_solve(self, d, Ubar, tau, rhs, x, stream=None):
+        (self.line_solve_r, self.line_solve_theta, self.line_solve_phi)[d](Ubar, tau, rhs, x, stream)
+
+    def split_step(self, Un, Unp1, tau, K, stream=None):
+        _check(lib().dsw_split_step(self._h, C.byref(_fields(Un)), C.byref(_fields(Unp1)),
+                                    float(tau), int(K), _stream(stream)))
+
+    def set_timing(self, enable=True):
+        _check(lib().dsw_set_timing(self._h, 1 if enable else 0))
+
+    def read_timing(self, stream=None):
+        """{kind: (total ms, launches)} since the last read."""
+        ms = (C.c_double * len(TIMING_KINDS))()
+        n = (C.c_int64 * len(TIMING_KINDS))()
+        _check(lib().dsw_read_timing(self._h, _stream(stream), ms, n))
+        return {k: (float(ms[q]), int(n[q])) for q, k in enumerate(TIMING_KINDS)}
+
+    def get_status(self, stream=None):
+        """DSW_OK, or raises DswError(DSW_ENONPHYS / DSW_ESINGULAR)."""
+        _check(lib().dsw_get_status(self._h, _stream(stream)))
+        return DSW_OK
+
+
+def to_device(fields, device="cuda"):
+    return {k: torch.as_tensor(v).to(device=device, dtype=torch.float64).contiguous()
+            for k, v in fields.items()}
+
+
+def to_host(fields):
+    return {k: v.detach().cpu().numpy() for k, v in fields.items()}

@@ -1,0 +1,177 @@
+"""Parity at the full benchmark sizes, in the launch configuration the
+benchmark times, on sampled outputs the oracle computes one by one:
+
+* residual: every field at ~3000 sampled points (random, next to every
+  boundary, at the poles and the periodic seam);
+* line solves r, theta, phi: sampled lines of every family (first, last,
+  middle, random), each solved by the oracle from the same seeded inputs;
+* properties of the whole step that hold at any size: phi-shift equivariance
+  on the full sphere (exercises the cyclic solves) and the discretely
+  hydrostatic rest state.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2004_13887_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-11
+FULL = ["global", "sweeps"]
+
+
+@pytest.fixture(scope="module")
+def dsw():
+    from paper_2004_13887_amd import dsw as D
+    assert torch.cuda.is_available()
+    D.lib()
+    return D
+
+
+_cache = {}
+
+
+def setup(name, dsw):
+    if name not in _cache:
+        _cache.clear()
+        torch.cuda.empty_cache()
+        w = I.WORKLOADS[name]
+        print(f"[setup] {name} {w.grid.np}x{w.grid.nt}x{w.grid.nr}", flush=True)
+        U0, tau = I.initial_state(w)
+        _cache[name] = (w, U0, tau, oracle.Grid(*w.grid.args()),
+                        oracle.Material(*w.material.astuple()), dsw.Grid.from_spec(w.grid, w.material))
+    return _cache[name]
+
+
+def sample_points(spec, rng, n=400):
+    """(field ids, flat indices): random points plus every boundary layer"""
+    fids, idx = [], []
+    for fid, (k, shp) in enumerate(spec.shapes().items()):
+        a = [rng.integers(0, s, n) for s in shp]
+        for ax in range(3):  # first / second / last / second-to-last layers
+            for v in (0, 1, shp[ax] - 2, shp[ax] - 1):
+                b = [rng.integers(0, s, 16) for s in shp]
+                b[ax] = np.full(16, v)
+                a = [np.concatenate([x, y]) for x, y in zip(a, b)]
+        flat = np.ravel_multi_index(a, shp)
+        fids.append(np.full(flat.size, fid))
+        idx.append(flat)
+    return np.concatenate(fids), np.concatenate(idx)
+
+
+@pytest.mark.parametrize("name", FULL)
+def test_full_residual_sampled(name, dsw):
+    w, U0, tau, og, om, gg = setup(name, dsw)
+    Uk = I.random_fields(w.grid, 21, base=U0, scale=10.0 * w.mach)
+    Uk["p"] = np.ascontiguousarray(U0["p"] + 1e-3 * I.random_fields(w.grid, 22)["p"])
+    Ub = {k: np.ascontiguousarray(0.5 * (Uk[k] + U0[k])) for k in U0}
+    R, dUb = gg.empty(), gg.empty()
+    gg.residual(dsw.to_device(U0), dsw.to_device(Uk), tau, R, dUb)
+    torch.cuda.synchronize()
+    gg.get_status()
+    rng = np.random.Generator(np.random.PCG64(23))
+    fids, idx = sample_points(w.grid, rng)
+    ref = oracle.residual_at(og, om, U0, Uk, Ub, tau, fids, idx)
+    Rh = dsw.to_host(R)
+    names = list(w.grid.shapes())
+    got = np.array([Rh[names[f]].ravel()[i] for f, i in zip(fids, idx)])
+    worst = 0.0
+    for f, k in enumerate(names):
+        m = fids == f
+        s = np.linalg.norm(ref[m])
+        if k == "ur":  # cancellation of pressure gradient and gravity (see test_gpu_parity)
+            s = max(s, tau * abs(w.material.g_r) * np.sqrt(m.sum()))
+        e = float(np.linalg.norm(got[m] - ref[m]) / s)
+        print(f"{name} R[{k}] sampled rel err = {e:.3e} ({m.sum()} points)", flush=True)
+        worst = max(worst, e)
+    ub_h = dsw.to_host(dUb)
+    for k in names:
+        assert np.array_equal(ub_h[k], Ub[k]), k
+    assert worst <= TOL
+
+
+def sample_lines(fam_sizes, rng, nrand=24):
+    out = []
+    for kind, (na, nb) in fam_sizes:
+        pick = {(0, 0), (na - 1, nb - 1), (na // 2, nb // 2), (0, nb - 1), (na - 1, 0)}
+        for _ in range(nrand):
+            pick.add((int(rng.integers(0, na)), int(rng.integers(0, nb))))
+        out += [(kind, a, b) for (a, b) in sorted(pick)]
+    return out
+
+
+def families(spec, d):
+    nr, nt, np_ = spec.nr, spec.nt, spec.np
+    kf = (0, np_) if spec.periodic else (1, np_ - 1)  # (offset, count) of interior phi faces
+    if d == 0:
+        return [(-1, (nt, np_), (0, 0)), (2, (nt - 1, np_), (1, 0)), (3, (nt, kf[1]), (0, kf[0]))]
+    if d == 1:
+        return [(-1, (nr, np_), (0, 0)), (1, (nr - 1, np_), (1, 0)), (3, (nr, kf[1]), (0, kf[0]))]
+    return [(-1, (nr, nt), (0, 0)), (1, (nr - 1, nt), (1, 0)), (2, (nr, nt - 1), (0, 1))]
+
+
+@pytest.mark.parametrize("d", [0, 1, 2])
+@pytest.mark.parametrize("name", FULL)
+def test_full_line_solve_sampled(name, d, dsw):
+    w, U0, tau, og, om, gg = setup(name, dsw)
+    rhs = I.random_fields(w.grid, 31 + d)
+    x = gg.empty()
+    gg.line_solve(d, dsw.to_device(U0), tau, dsw.to_device(rhs), x)
+    torch.cuda.synchronize()
+    gg.get_status()
+    xh = dsw.to_host(x)
+    rng = np.random.Generator(np.random.PCG64(41 + d))
+    fams = families(w.grid, d)
+    lines = []
+    for kind, (na, nb), (oa, ob) in fams:
+        lines += [(kind, a + oa, b + ob) for (_, a, b) in sample_lines([(kind, (na, nb))], rng)]
+    kinds, as_, bs_ = zip(*lines)
+    ref = oracle.line_solve_some(og, om, U0, tau, d, kinds, as_, bs_, rhs)
+    worst = 0.0
+    for k in ref:
+        m = ~np.isnan(ref[k])
+        if not m.any():
+            continue
+        e = float(np.linalg.norm(xh[k][m] - ref[k][m]) / max(np.linalg.norm(ref[k][m]), 1e-300))
+        print(f"{name} x{d}[{k}] sampled rel err = {e:.3e} ({m.sum()} values)", flush=True)
+        worst = max(worst, e)
+    assert worst <= TOL
+
+
+def test_full_global_phi_shift_equivariance(dsw):
+    w, U0, tau, og, om, gg = setup("global", dsw)
+    s = 7
+    dU = dsw.to_device(U0)
+    dUs = {k: torch.roll(v, s, dims=2).contiguous() for k, v in dU.items()}
+    a, b = gg.empty(), gg.empty()
+    gg.split_step(dU, a, tau, w.K)
+    gg.split_step(dUs, b, tau, w.K)
+    torch.cuda.synchronize()
+    gg.get_status()
+    for k in a:
+        ar = torch.roll(a[k], s, dims=2)
+        e = float(torch.linalg.norm(ar - b[k]) / torch.linalg.norm(b[k]))
+        d0 = float(torch.linalg.norm((ar - dUs[k]) - (b[k] - dUs[k])) /
+                   max(float(torch.linalg.norm(b[k] - dUs[k])), 1e-300))
+        print(f"global shift {k}: relL2 {e:.3e}, of the change {d0:.3e}", flush=True)
+        assert e <= 1e-13 and d0 <= 1e-9
+
+
+def test_full_hydrostatic_rest_is_steady(dsw):
+    w = I.WORKLOADS["sweeps"]
+    gg = dsw.Grid.from_spec(w.grid, w.material)
+    U = {k: np.zeros(s) for k, s in w.grid.shapes().items()}
+    U["T"][:] = I.T0
+    U["p"][:] = I.hydrostatic_pressure(w.grid, I.AIR)[:, None, None]
+    tau = I.time_step(w, I.T0)
+    dU = dsw.to_device(U)
+    out = gg.empty()
+    gg.split_step(dU, out, tau, 3)
+    torch.cuda.synchronize()
+    gg.get_status()
+    o = dsw.to_host(out)
+    e = float(np.linalg.norm(o["p"] - U["p"]) / np.linalg.norm(U["p"]))
+    vmax = max(float(np.abs(o[k]).max()) for k in ("ur", "ut", "uf"))
+    print(f"hydrostatic: p relL2 change {e:.3e}, max |u| {vmax:.3e}", flush=True)
+    assert e < 1e-13 and vmax < 1e-10
