@@ -32,6 +32,11 @@ void launch_sweep(int d, const Geo &g, const Mat &m, const Fields &Ub, double ta
                   const Fields &rhs, const Fields &x, const Scratch &sc, int *status,
                   hipStream_t st, bool accum);
 
+// partitioned phi solver (one workgroup per line slot), when the line fits
+bool phi_part_supported(const Geo &g);
+void launch_phi_part(const Geo &g, const Mat &m, const Fields &Ub, double tau, const Fields &rhs,
+                     const Fields &x, int *status, hipStream_t st, bool accum);
+
 // doubles of scratch needed by the sweeps of a grid
 void sweep_scratch_size(const Geo &g, long *blk, long *sca);
 

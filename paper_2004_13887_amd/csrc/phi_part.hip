@@ -1,0 +1,412 @@
+// phi_part.hip -- partitioned line solver for the phi sweep (paper eq. (spl3),
+// operator D_phi of Appendix B eq. (dphi)).
+//
+// One workgroup per line slot (i, j).  It solves the 3x3-block line in
+// (p, T, u_phi) and the two scalar lines (u_r on r-face i, u_theta on
+// theta-face j) that share that slot.  Thread t owns rows [4t, 4t + 4):
+//   1. it assembles its rows (consecutive threads read consecutive phi cells:
+//      contiguous loads) and eliminates its interior rows with the block
+//      Thomas recurrence, carrying the dependence on the previous chunk's last
+//      row ("spike"), then sweeps back so that every interior row reads
+//      x_q = g_q + V_q x_left + W_q x_sep;
+//   2. the chunks' last rows ("separators") form a block-tridiagonal system
+//      (cyclic when phi is periodic) that is solved in LDS by parallel cyclic
+//      reduction, log2(#chunks) steps;
+//   3. interior rows are filled in from the separators.
+// All intermediates stay in registers and LDS: no scratch traffic.
+#include "rows.hpp"
+
+namespace dsw {
+
+constexpr int PM = 4;        // rows per thread
+constexpr int PT_MAX = 256;  // chunks per line (so lines up to 1024 cells)
+
+__host__ __device__ inline int part_chunks(int n) { return (n + PM - 1) / PM; }
+
+// ---------------------------------------------------------- 3x3 helpers --
+__device__ __forceinline__ void mm3s(const double *A, const double *B, double *C, double s) {
+  mm3(A, B, C);
+#pragma unroll
+  for (int q = 0; q < 9; q++) C[q] *= s;
+}
+
+// ------------------------------------------------------- block: PCR step --
+// Solve the T separator rows A x_{t-1} + B x_t + C x_{t+1} = r (t < T) held
+// in registers of threads t < T; LDS holds T x 33 doubles.  Returns x_t.
+__device__ void pcr_block(int t, int T, int cyc, double *A, double *B, double *C, double *r,
+                          double *lds, double *x, int *status) {
+  double *sA = lds, *sC = lds + 9 * T, *sR = lds + 18 * T, *sBi = lds + 21 * T;
+  const bool act = t < T;
+  for (int h = 1; h < T; h *= 2) {
+    if (act) {
+      double Bi[9];
+      inv3(B, Bi, status);
+#pragma unroll
+      for (int q = 0; q < 9; q++) { sA[t * 9 + q] = A[q]; sC[t * 9 + q] = C[q]; sBi[t * 9 + q] = Bi[q]; }
+#pragma unroll
+      for (int q = 0; q < 3; q++) sR[t * 3 + q] = r[q];
+    }
+    __syncthreads();
+    if (act) {
+      int lo = t - h, hi = t + h;
+      bool has_lo = lo >= 0, has_hi = hi < T;
+      if (cyc) { lo = (lo % T + T) % T; hi = hi % T; has_lo = has_hi = true; }
+      double nA[9], nC[9], nB[9], nr[3], al[9], be[9], t9[9], t3[3];
+#pragma unroll
+      for (int q = 0; q < 9; q++) { nA[q] = 0.0; nC[q] = 0.0; nB[q] = B[q]; }
+#pragma unroll
+      for (int q = 0; q < 3; q++) nr[q] = r[q];
+      if (has_lo) {
+        mm3s(A, &sBi[lo * 9], al, -1.0);        // alpha = -A B_lo^{-1}
+        mm3(al, &sA[lo * 9], nA);               // A' = alpha A_lo
+        mm3(al, &sC[lo * 9], t9);               // B' += alpha C_lo
+#pragma unroll
+        for (int q = 0; q < 9; q++) nB[q] += t9[q];
+        mv3(al, &sR[lo * 3], t3);
+#pragma unroll
+        for (int q = 0; q < 3; q++) nr[q] += t3[q];
+      }
+      if (has_hi) {
+        mm3s(C, &sBi[hi * 9], be, -1.0);        // beta = -C B_hi^{-1}
+        mm3(be, &sC[hi * 9], nC);               // C' = beta C_hi
+        mm3(be, &sA[hi * 9], t9);               // B' += beta A_hi
+#pragma unroll
+        for (int q = 0; q < 9; q++) nB[q] += t9[q];
+        mv3(be, &sR[hi * 3], t3);
+#pragma unroll
+        for (int q = 0; q < 3; q++) nr[q] += t3[q];
+      }
+#pragma unroll
+      for (int q = 0; q < 9; q++) { A[q] = nA[q]; B[q] = nB[q]; C[q] = nC[q]; }
+#pragma unroll
+      for (int q = 0; q < 3; q++) r[q] = nr[q];
+    }
+    __syncthreads();
+  }
+  if (act) {
+    // every remaining coupling points at x_t itself (cyclic) or is zero
+    double S[9], Si[9];
+#pragma unroll
+    for (int q = 0; q < 9; q++) S[q] = A[q] + B[q] + C[q];
+    inv3(S, Si, status);
+    mv3(Si, r, x);
+  }
+}
+
+__device__ void pcr_scalar(int t, int T, int cyc, double &A, double &B, double &C, double &r,
+                           double *lds, double &x, int *status) {
+  double *sA = lds, *sC = lds + T, *sR = lds + 2 * T, *sB = lds + 3 * T;
+  const bool act = t < T;
+  for (int h = 1; h < T; h *= 2) {
+    if (act) { sA[t] = A; sC[t] = C; sR[t] = r; sB[t] = B; }
+    __syncthreads();
+    if (act) {
+      int lo = t - h, hi = t + h;
+      bool has_lo = lo >= 0, has_hi = hi < T;
+      if (cyc) { lo = (lo % T + T) % T; hi = hi % T; has_lo = has_hi = true; }
+      double nA = 0.0, nC = 0.0, nB = B, nr = r;
+      if (has_lo) {
+        const double al = -A / sB[lo];
+        nA = al * sA[lo];
+        nB += al * sC[lo];
+        nr += al * sR[lo];
+      }
+      if (has_hi) {
+        const double be = -C / sB[hi];
+        nC = be * sC[hi];
+        nB += be * sA[hi];
+        nr += be * sR[hi];
+      }
+      A = nA; B = nB; C = nC; r = nr;
+    }
+    __syncthreads();
+  }
+  if (act) {
+    const double S = A + B + C;
+    if (!(S != 0.0)) status[ST_SINGULAR] = 1;
+    x = r / S;
+  }
+}
+
+// ------------------------------------------------------------ block line --
+__device__ void part_block_line(const Geo &g, const Mat &m, const SrcOne &u, const Fields &rhs,
+                                const Fields &x, int i, int j, double hs, bool accum, double *lds,
+                                int *status) {
+  const int N = g.np, T = part_chunks(N), cyc = g.periodic;
+  const int t = threadIdx.x;
+  const bool act = t < T;
+  const int a0 = t * PM;
+  const int len = act ? min(PM, N - a0) : 0;
+  double Cm[PM - 1][9], Em[PM - 1][9], Ym[PM - 1][3];
+  BRow R;
+  // 1. forward elimination over interior rows with the left spike
+#pragma unroll
+  for (int q = 0; q < PM - 1; q++) {
+    if (q < len - 1) {
+      block_row<2>(g, m, u, rhs, i, j, a0 + q, N, cyc, hs, R);
+      double Dp[9], rr[3], Lx[9], Ai[9];
+      if (q == 0) {
+#pragma unroll
+        for (int z = 0; z < 9; z++) { Dp[z] = R.D[z]; Lx[z] = R.L[z]; }
+#pragma unroll
+        for (int z = 0; z < 3; z++) rr[z] = R.b[z];
+      } else {
+        double t9[9], t3[3];
+        mm3(R.L, Cm[q - 1], t9);
+#pragma unroll
+        for (int z = 0; z < 9; z++) Dp[z] = R.D[z] - t9[z];
+        mv3(R.L, Ym[q - 1], t3);
+#pragma unroll
+        for (int z = 0; z < 3; z++) rr[z] = R.b[z] - t3[z];
+        mm3s(R.L, Em[q - 1], Lx, -1.0);
+      }
+      inv3(Dp, Ai, status);
+      mm3(Ai, R.U, Cm[q]);
+      mv3(Ai, rr, Ym[q]);
+      mm3(Ai, Lx, Em[q]);
+    }
+  }
+  // separator row (last row of the chunk)
+  BRow S;
+  if (act) block_row<2>(g, m, u, rhs, i, j, a0 + len - 1, N, cyc, hs, S);
+  // backward sweep: (Y, E, C) -> (g, V, W), x_q = g_q + V_q x_left + W_q x_sep
+#pragma unroll
+  for (int q = PM - 2; q >= 0; q--) {
+    if (q == len - 2) {
+#pragma unroll
+      for (int z = 0; z < 9; z++) { Em[q][z] = -Em[q][z]; Cm[q][z] = -Cm[q][z]; }
+    } else if (q < len - 2) {
+      double t9[9], t3[3];
+      mv3(Cm[q], Ym[q + 1], t3);
+#pragma unroll
+      for (int z = 0; z < 3; z++) Ym[q][z] -= t3[z];
+      mm3(Cm[q], Em[q + 1], t9);
+#pragma unroll
+      for (int z = 0; z < 9; z++) Em[q][z] = -Em[q][z] - t9[z];
+      mm3s(Cm[q], Cm[q + 1], t9, -1.0);
+#pragma unroll
+      for (int z = 0; z < 9; z++) Cm[q][z] = t9[z];
+    }
+  }
+  // 2. exchange the first interior row of each chunk with its left neighbour
+  double *sG = lds, *sV = lds + 3 * T, *sW = lds + 12 * T, *sL = lds + 21 * T;
+  if (act) {
+    sL[t] = (double)len;
+    if (len >= 2) {
+#pragma unroll
+      for (int z = 0; z < 3; z++) sG[t * 3 + z] = Ym[0][z];
+#pragma unroll
+      for (int z = 0; z < 9; z++) { sV[t * 9 + z] = Em[0][z]; sW[t * 9 + z] = Cm[0][z]; }
+    }
+  }
+  __syncthreads();
+  double A[9], B[9], Cc[9], r[3];
+  if (act) {
+    int nt_ = t + 1;
+    bool has_next = nt_ < T;
+    if (cyc) { nt_ %= T; has_next = true; }
+    const int nlen = has_next ? (int)sL[nt_] : 0;
+    // last interior row of this chunk
+    double Gl[3] = {0, 0, 0}, Vl[9], Wl[9];
+#pragma unroll
+    for (int z = 0; z < 9; z++) { Vl[z] = 0.0; Wl[z] = 0.0; }
+#pragma unroll
+    for (int q = 0; q < PM - 1; q++)
+      if (q == len - 2) {
+#pragma unroll
+        for (int z = 0; z < 3; z++) Gl[z] = Ym[q][z];
+#pragma unroll
+        for (int z = 0; z < 9; z++) { Vl[z] = Em[q][z]; Wl[z] = Cm[q][z]; }
+      }
+    double t9[9], t3[3];
+#pragma unroll
+    for (int z = 0; z < 9; z++) B[z] = S.D[z];
+#pragma unroll
+    for (int z = 0; z < 3; z++) r[z] = S.b[z];
+    if (len >= 2) {
+      mm3(S.L, Vl, A);
+      mm3(S.L, Wl, t9);
+#pragma unroll
+      for (int z = 0; z < 9; z++) B[z] += t9[z];
+      mv3(S.L, Gl, t3);
+#pragma unroll
+      for (int z = 0; z < 3; z++) r[z] -= t3[z];
+    } else {
+#pragma unroll
+      for (int z = 0; z < 9; z++) A[z] = S.L[z];
+    }
+    if (nlen >= 2) {
+      mm3(S.U, &sV[nt_ * 9], t9);
+#pragma unroll
+      for (int z = 0; z < 9; z++) B[z] += t9[z];
+      mm3(S.U, &sW[nt_ * 9], Cc);
+      mv3(S.U, &sG[nt_ * 3], t3);
+#pragma unroll
+      for (int z = 0; z < 3; z++) r[z] -= t3[z];
+    } else {
+#pragma unroll
+      for (int z = 0; z < 9; z++) Cc[z] = S.U[z];
+    }
+  }
+  __syncthreads(); // exchange area is reused by the reduction
+  double xs[3] = {0, 0, 0};
+  pcr_block(t, T, cyc, A, B, Cc, r, lds, xs, status);
+  // 3. fill in the interior rows
+  double *sX = lds + 30 * T;
+  if (act) {
+#pragma unroll
+    for (int z = 0; z < 3; z++) sX[t * 3 + z] = xs[z];
+  }
+  __syncthreads();
+  if (act) {
+    double xl[3] = {0, 0, 0};
+    if (t > 0 || cyc) {
+      const int lt = t > 0 ? t - 1 : T - 1;
+#pragma unroll
+      for (int z = 0; z < 3; z++) xl[z] = sX[lt * 3 + z];
+    }
+#pragma unroll
+    for (int q = 0; q < PM - 1; q++) {
+      if (q < len - 1) {
+        double v[3], t3[3];
+        mv3(Em[q], xl, v);
+        mv3(Cm[q], xs, t3);
+#pragma unroll
+        for (int z = 0; z < 3; z++) v[z] += Ym[q][z] + t3[z];
+        block_store<2>(g, x, i, j, a0 + q, v, accum);
+      }
+    }
+    block_store<2>(g, x, i, j, a0 + len - 1, xs, accum);
+  }
+  __syncthreads();
+}
+
+// ----------------------------------------------------------- scalar line --
+template <int FAM>
+__device__ void part_scalar_line(const Geo &g, const Mat &m, const SrcOne &u, const Fields &rhs,
+                                 const Fields &x, int a, int b, double hs, bool accum, double *lds,
+                                 int *status) {
+  const int N = g.np, T = part_chunks(N), cyc = g.periodic;
+  const int t = threadIdx.x;
+  const bool act = t < T;
+  const int a0 = t * PM;
+  const int len = act ? min(PM, N - a0) : 0;
+  double *out = FAM == 0 ? x.ur : x.ut;
+  double Cm[PM - 1], Em[PM - 1], Ym[PM - 1];
+  SRow R;
+  long xi;
+  double *arr;
+#pragma unroll
+  for (int q = 0; q < PM - 1; q++) {
+    if (q < len - 1) {
+      scalar_row<2, FAM>(g, m, u, rhs, a, b, a0 + q, N, cyc, hs, R, xi, arr);
+      double dp = R.b, rr = R.r, lx = R.a;
+      if (q > 0) { dp -= R.a * Cm[q - 1]; rr -= R.a * Ym[q - 1]; lx = -R.a * Em[q - 1]; }
+      if (!(dp != 0.0)) status[ST_SINGULAR] = 1;
+      const double id = 1.0 / dp;
+      Cm[q] = R.c * id;
+      Ym[q] = rr * id;
+      Em[q] = lx * id;
+    }
+  }
+  SRow S{0, 1, 0, 0};
+  if (act) scalar_row<2, FAM>(g, m, u, rhs, a, b, a0 + len - 1, N, cyc, hs, S, xi, arr);
+#pragma unroll
+  for (int q = PM - 2; q >= 0; q--) {
+    if (q == len - 2) { Em[q] = -Em[q]; Cm[q] = -Cm[q]; }
+    else if (q < len - 2) {
+      Ym[q] -= Cm[q] * Ym[q + 1];
+      Em[q] = -Em[q] - Cm[q] * Em[q + 1];
+      Cm[q] = -Cm[q] * Cm[q + 1];
+    }
+  }
+  double *sG = lds, *sV = lds + T, *sW = lds + 2 * T, *sL = lds + 3 * T;
+  if (act) {
+    sL[t] = (double)len;
+    if (len >= 2) { sG[t] = Ym[0]; sV[t] = Em[0]; sW[t] = Cm[0]; }
+  }
+  __syncthreads();
+  double A = 0.0, B = 1.0, C = 0.0, r = 0.0;
+  if (act) {
+    int nt_ = t + 1;
+    bool has_next = nt_ < T;
+    if (cyc) { nt_ %= T; has_next = true; }
+    const int nlen = has_next ? (int)sL[nt_] : 0;
+    double Gl = 0.0, Vl = 0.0, Wl = 0.0;
+#pragma unroll
+    for (int q = 0; q < PM - 1; q++)
+      if (q == len - 2) { Gl = Ym[q]; Vl = Em[q]; Wl = Cm[q]; }
+    B = S.b;
+    r = S.r;
+    if (len >= 2) { A = S.a * Vl; B += S.a * Wl; r -= S.a * Gl; }
+    else A = S.a;
+    if (nlen >= 2) { B += S.c * sV[nt_]; C = S.c * sW[nt_]; r -= S.c * sG[nt_]; }
+    else C = S.c;
+  }
+  __syncthreads();
+  double xs = 0.0;
+  pcr_scalar(t, T, cyc, A, B, C, r, lds, xs, status);
+  double *sX = lds + 4 * T;
+  if (act) sX[t] = xs;
+  __syncthreads();
+  if (act) {
+    double xl = 0.0;
+    if (t > 0 || cyc) xl = sX[t > 0 ? t - 1 : T - 1];
+#pragma unroll
+    for (int q = 0; q < PM - 1; q++) {
+      if (q < len - 1) {
+        const double v = Ym[q] + Em[q] * xl + Cm[q] * xs;
+        const long xq = FAM == 0 ? idx_r(g, a, b, a0 + q) : idx_t(g, a, b, a0 + q);
+        if (accum) out[xq] += v; else out[xq] = v;
+      }
+    }
+    const long xq = FAM == 0 ? idx_r(g, a, b, a0 + len - 1) : idx_t(g, a, b, a0 + len - 1);
+    if (accum) out[xq] += xs; else out[xq] = xs;
+  }
+  __syncthreads();
+}
+
+// one workgroup per (i, j): block line (i, j), u_r line on r-face i (i >= 1),
+// u_theta line on theta-face j (j >= 1)
+__global__ void __launch_bounds__(256) k_phi_part(Geo g, Mat m, SrcOne u, double hs, Fields rhs,
+                                                  Fields x, int accum, int *status) {
+  extern __shared__ double lds[];
+  const int j = blockIdx.x, i = blockIdx.y;
+  const int t = threadIdx.x;
+  if (!accum) { // boundary-normal faces of x that no phi line owns
+    for (int k = t; k < g.np; k += blockDim.x) {
+      if (i == 0) x.ur[idx_r(g, 0, j, k)] = 0.0;
+      if (i == g.nr - 1) x.ur[idx_r(g, g.nr, j, k)] = 0.0;
+      if (j == 0) x.ut[idx_t(g, i, 0, k)] = 0.0;
+      if (j == g.nt - 1) x.ut[idx_t(g, i, g.nt, k)] = 0.0;
+    }
+    if (!g.periodic && t == 0) x.uf[idx_f(g, i, j, 0)] = 0.0;
+  }
+  part_block_line(g, m, u, rhs, x, i, j, hs, accum != 0, lds, status);
+  if (i >= 1) part_scalar_line<0>(g, m, u, rhs, x, i, j, hs, accum != 0, lds, status);
+  if (j >= 1) part_scalar_line<1>(g, m, u, rhs, x, i, j, hs, accum != 0, lds, status);
+}
+
+bool phi_part_supported(const Geo &g) {
+  const int T = part_chunks(g.np);
+  if (T > PT_MAX) return false;
+  if (g.periodic) { // cyclic reduction needs a power-of-two number of equal chunks
+    if (g.np % PM != 0) return false;
+    if (T & (T - 1)) return false;
+  }
+  return true;
+}
+
+void launch_phi_part(const Geo &g, const Mat &m, const Fields &Ub, double tau, const Fields &rhs,
+                     const Fields &x, int *status, hipStream_t st, bool accum) {
+  SrcOne u;
+  u.a[F_P] = Ub.p; u.a[F_UR] = Ub.ur; u.a[F_UT] = Ub.ut; u.a[F_UF] = Ub.uf; u.a[F_T] = Ub.T;
+  const int T = part_chunks(g.np);
+  const int bs = ((T + 63) / 64) * 64;
+  const size_t lds = sizeof(double) * 33 * T;
+  dim3 grid(g.nt, g.nr);
+  hipLaunchKernelGGL(k_phi_part, grid, dim3(bs), lds, st, g, m, u, 0.5 * tau, rhs, x, accum ? 1 : 0,
+                     status);
+}
+
+} // namespace dsw

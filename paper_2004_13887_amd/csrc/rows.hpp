@@ -1,0 +1,310 @@
+// rows.hpp -- assembly of one row of the line systems (I + tau/2 D_d(Ubar))
+// of the three split sweeps (paper eqs. (spl1)-(spl3); direction operators
+// of Appendix B, eqs. (dr), (dtheta), (dphi)), and 3x3 helpers.  Shared by the
+// thread-per-line and the partitioned line solvers.
+#pragma once
+
+#include "dsw_common.hpp"
+#include "dsw_internal.hpp"
+
+namespace dsw {
+
+struct BRow {
+  double L[9], D[9], U[9], b[3];
+};
+
+__device__ __forceinline__ void inv3(const double *A, double *X, int *status) {
+  const double c00 = A[4] * A[8] - A[5] * A[7];
+  const double c01 = A[5] * A[6] - A[3] * A[8];
+  const double c02 = A[3] * A[7] - A[4] * A[6];
+  const double det = A[0] * c00 + A[1] * c01 + A[2] * c02;
+  if (!(det != 0.0) || !isfinite(det)) status[ST_SINGULAR] = 1;
+  const double id = 1.0 / det;
+  X[0] = c00 * id;
+  X[1] = (A[2] * A[7] - A[1] * A[8]) * id;
+  X[2] = (A[1] * A[5] - A[2] * A[4]) * id;
+  X[3] = c01 * id;
+  X[4] = (A[0] * A[8] - A[2] * A[6]) * id;
+  X[5] = (A[2] * A[3] - A[0] * A[5]) * id;
+  X[6] = c02 * id;
+  X[7] = (A[1] * A[6] - A[0] * A[7]) * id;
+  X[8] = (A[0] * A[4] - A[1] * A[3]) * id;
+}
+
+// C = A * B (3x3)
+__device__ __forceinline__ void mm3(const double *A, const double *B, double *C) {
+#pragma unroll
+  for (int r = 0; r < 3; r++)
+#pragma unroll
+    for (int c = 0; c < 3; c++) C[r * 3 + c] = A[r * 3] * B[c] + A[r * 3 + 1] * B[3 + c] + A[r * 3 + 2] * B[6 + c];
+}
+// y = A * x (3x3 . 3)
+__device__ __forceinline__ void mv3(const double *A, const double *x, double *y) {
+#pragma unroll
+  for (int r = 0; r < 3; r++) y[r] = A[r * 3] * x[0] + A[r * 3 + 1] * x[1] + A[r * 3 + 2] * x[2];
+}
+
+// ------------------------------------------------------------------ lines --
+
+// number of lines per family: block, scalar A, scalar B
+struct Families {
+  int nb, na, nbb, n, cyclic;
+};
+
+__host__ __device__ inline Families families(const Geo &g, int d) {
+  Families f;
+  const int nkf = g.periodic ? g.np : g.np - 1; // interior phi faces
+  if (d == 0) { f.nb = g.nt * g.np; f.na = (g.nt - 1) * g.np; f.nbb = g.nt * nkf; f.n = g.nr; }
+  else if (d == 1) { f.nb = g.nr * g.np; f.na = (g.nr - 1) * g.np; f.nbb = g.nr * nkf; f.n = g.nt; }
+  else { f.nb = g.nr * g.nt; f.na = (g.nr - 1) * g.nt; f.nbb = g.nr * (g.nt - 1); f.n = g.np; }
+  f.cyclic = (d == 2 && g.periodic) ? 1 : 0;
+  return f;
+}
+
+// ------------------------------------------------------------ block rows --
+
+// Assemble block row s of (I + tau/2 D_d) on block line (a, b).  hs = tau/2.
+// Unknown order within a block: p, T, w.
+template <int D>
+__device__ void block_row(const Geo &g, const Mat &m, const SrcOne &u, const Fields &rhs, int a,
+                          int b, int s, int n, int cyc, double hs, BRow &R) {
+  int i, j, k;
+  if (D == 0) { i = s; j = a; k = b; }
+  else if (D == 1) { i = a; j = s; k = b; }
+  else { i = a; j = b; k = s; }
+  Cent c;
+  centre(g, m, u, i, j, k, c);
+  const double r = g.rc[i], sn = g.sc[j];
+  double adv, dp_, dm_, ap, am, lp, lm;
+  if (D == 0) {
+    adv = c.ur / (2.0 * g.dr);
+    dp_ = g.rf[i + 1] * g.rf[i + 1] / (r * r * g.dr);
+    dm_ = -g.rf[i] * g.rf[i] / (r * r * g.dr);
+    const double gg = (c.Gtt + c.Gff) / r;
+    ap = m.mu * (2.0 * c.Grr / g.dr + gg - (2.0 / 3.0) * c.tr * dp_);
+    am = m.mu * (-2.0 * c.Grr / g.dr + gg - (2.0 / 3.0) * c.tr * dm_);
+    lp = g.rf[i + 1] * g.rf[i + 1] / (r * r * g.dr * g.dr);
+    lm = g.rf[i] * g.rf[i] / (r * r * g.dr * g.dr);
+  } else if (D == 1) {
+    const double ct = g.cc[j] / sn;
+    adv = c.ut / (r * 2.0 * g.dt);
+    dp_ = g.sf[j + 1] / (r * sn * g.dt);
+    dm_ = -g.sf[j] / (r * sn * g.dt);
+    const double gg = c.Gff * ct / r - 0.5 * c.Srt / r;
+    ap = m.mu * (2.0 * c.Gtt / (r * g.dt) + gg - (2.0 / 3.0) * c.tr * dp_);
+    am = m.mu * (-2.0 * c.Gtt / (r * g.dt) + gg - (2.0 / 3.0) * c.tr * dm_);
+    lp = g.sf[j + 1] / (r * r * sn * g.dt * g.dt);
+    lm = g.sf[j] / (r * r * sn * g.dt * g.dt);
+  } else {
+    const double ct = g.cc[j] / sn;
+    adv = c.uf / (r * sn * 2.0 * g.dp);
+    dp_ = 1.0 / (r * sn * g.dp);
+    dm_ = -1.0 / (r * sn * g.dp);
+    const double gg = -0.5 * (c.Srf + c.Stf * ct) / r;
+    ap = m.mu * (2.0 * c.Gff / (r * sn * g.dp) + gg - (2.0 / 3.0) * c.tr * dp_);
+    am = m.mu * (-2.0 * c.Gff / (r * sn * g.dp) + gg - (2.0 / 3.0) * c.tr * dm_);
+    lp = 1.0 / (r * r * sn * sn * g.dp * g.dp);
+    lm = lp;
+  }
+  const bool first = !cyc && s == 0, last = !cyc && s == n - 1;
+  if (first) lm = 0.0; // zero flux through the boundary (copy ghost)
+  if (last) lp = 0.0;
+  const double g1 = m.gam - 1.0;
+  const double kp = g1 * m.kap, kT = c.chi * m.kap;
+#pragma unroll
+  for (int q = 0; q < 9; q++) { R.L[q] = 0.0; R.D[q] = 0.0; R.U[q] = 0.0; }
+  // p row
+  R.L[0] = -adv; R.U[0] = adv;
+  R.L[1] = -kp * lm; R.D[1] = kp * (lp + lm); R.U[1] = -kp * lp;
+  R.L[2] = m.gam * c.P * dm_ - g1 * am;
+  R.D[2] = m.gam * c.P * dp_ - g1 * ap;
+  // T row
+  R.L[4] = -adv - kT * lm; R.D[4] = kT * (lp + lm); R.U[4] = adv - kT * lp;
+  R.L[5] = g1 * c.T * dm_ - c.chi * am;
+  R.D[5] = g1 * c.T * dp_ - c.chi * ap;
+  if (first) { R.D[0] += R.L[0]; R.D[4] += -adv; } // advection ghost p_{-1} = p_0
+  if (last) { R.D[0] += R.U[0]; R.U[0] = 0.0; R.D[4] += adv; R.U[4] = 0.0; }
+  if (first) { R.L[0] = 0.0; R.L[4] = 0.0; }
+  // w row (face after cell s)
+  const bool w_unknown = cyc || s < n - 1;
+  double gp = 0.0, cm = 0.0, c0 = 0.0, cp = 0.0;
+  if (w_unknown) {
+    if (D == 0) {
+      const int f = i + 1;
+      const double rho = 0.5 * (rho_at(g, m, u, i, j, k) + rho_at(g, m, u, i + 1, j, k));
+      const double nu = m.mu / rho, un = u.ld(F_UR, idx_r(g, f, j, k));
+      const double rF2 = g.rf[f] * g.rf[f], d2 = g.dr * g.dr;
+      const double ra2 = g.rc[i] * g.rc[i], rb2 = g.rc[i + 1] * g.rc[i + 1];
+      gp = 1.0 / (rho * g.dr);
+      cp = un / (2.0 * g.dr) - nu * rb2 / (rF2 * d2) - nu / 3.0 * g.rf[i + 2] * g.rf[i + 2] / (rb2 * d2);
+      c0 = nu * (rb2 + ra2) / (rF2 * d2) + nu / 3.0 * rF2 * (1.0 / rb2 + 1.0 / ra2) / d2;
+      cm = -un / (2.0 * g.dr) - nu * ra2 / (rF2 * d2) - nu / 3.0 * g.rf[i] * g.rf[i] / (ra2 * d2);
+    } else if (D == 1) {
+      const int f = j + 1;
+      const double rho = 0.5 * (rho_at(g, m, u, i, j, k) + rho_at(g, m, u, i, j + 1, k));
+      const double nu = m.mu / rho, un = u.ld(F_UT, idx_t(g, i, f, k));
+      const double sF = g.sf[f], r2d2 = r * r * g.dt * g.dt;
+      const double sa = g.sc[j], sb = g.sc[j + 1];
+      gp = 1.0 / (rho * r * g.dt);
+      cp = un / (2.0 * r * g.dt) - nu * sb / (r2d2 * sF) - nu / 3.0 * g.sf[j + 2] / (r2d2 * sb);
+      c0 = nu * (sb + sa) / (r2d2 * sF) + nu / 3.0 * sF * (1.0 / sb + 1.0 / sa) / r2d2;
+      cm = -un / (2.0 * r * g.dt) - nu * sa / (r2d2 * sF) - nu / 3.0 * g.sf[j] / (r2d2 * sa);
+    } else {
+      const int f = g.periodic ? wrapk(g, k + 1) : k + 1;
+      const double rho = 0.5 * (rho_at(g, m, u, i, j, k) + rho_at(g, m, u, i, j, k + 1));
+      const double nu = m.mu / rho, un = u.ld(F_UF, idx_f(g, i, j, f));
+      const double q2 = r * r * sn * sn * g.dp * g.dp;
+      gp = 1.0 / (rho * r * sn * g.dp);
+      cp = un / (2.0 * r * sn * g.dp) - 4.0 * nu / 3.0 / q2;
+      c0 = 8.0 * nu / 3.0 / q2;
+      cm = -un / (2.0 * r * sn * g.dp) - 4.0 * nu / 3.0 / q2;
+    }
+    R.D[6] = -gp; R.U[6] = gp;
+    R.L[8] = cm; R.D[8] = c0; R.U[8] = cp;
+    if (!cyc && s == n - 2) R.U[8] = 0.0; // w_{s+1} is the boundary face
+  }
+  if (!w_unknown) { R.D[2] = 0.0; R.D[5] = 0.0; } // w_{n-1} is the boundary face
+  if (first) { // no row before the first one: the L block couples to nothing
+#pragma unroll
+    for (int q = 0; q < 9; q++) R.L[q] = 0.0;
+  }
+  // scale and add the identity
+#pragma unroll
+  for (int q = 0; q < 9; q++) { R.L[q] *= hs; R.D[q] *= hs; R.U[q] *= hs; }
+  R.D[0] += 1.0; R.D[4] += 1.0; R.D[8] += 1.0;
+  if (!w_unknown) { R.L[6] = R.L[7] = R.L[8] = 0.0; R.D[6] = R.D[7] = 0.0; R.D[8] = 1.0; R.U[6] = R.U[7] = R.U[8] = 0.0; }
+  // right-hand side
+  const long xc = idx_c(g, i, j, k);
+  R.b[0] = rhs.p[xc];
+  R.b[1] = rhs.T[xc];
+  if (w_unknown) {
+    if (D == 0) R.b[2] = rhs.ur[idx_r(g, i + 1, j, k)];
+    else if (D == 1) R.b[2] = rhs.ut[idx_t(g, i, j + 1, k)];
+    else R.b[2] = rhs.uf[idx_f(g, i, j, g.periodic ? wrapk(g, k + 1) : k + 1)];
+  } else {
+    R.b[2] = 0.0;
+  }
+}
+
+// ----------------------------------------------------------- scalar rows --
+
+struct SRow {
+  double a, b, c, r;
+};
+
+// Scalar line of family FAM (0: A, 1: B) in direction D, transverse coords
+// (a, b); row s.  Ghost folding at non-cyclic ends: walls -1, poles (u_r
+// along theta) +1.
+template <int D, int FAM>
+__device__ void scalar_row(const Geo &g, const Mat &m, const SrcOne &u, const Fields &rhs, int a,
+                           int b, int s, int n, int cyc, double hs, SRow &R, long &xi,
+                           double *&arr) {
+  double ca, cb, cc_, sglo = -1.0, sghi = -1.0;
+  if (D == 0) {
+    const int i = s;
+    const double r = g.rc[i], r2d2 = r * r * g.dr * g.dr;
+    double ua, rho;
+    if (FAM == 0) { // u_theta at theta-face (jf, k)
+      const int jf = a, k = b;
+      ua = 0.25 * (u.ld(F_UR, idx_r(g, i, jf - 1, k)) + u.ld(F_UR, idx_r(g, i, jf, k)) +
+                   u.ld(F_UR, idx_r(g, i + 1, jf - 1, k)) + u.ld(F_UR, idx_r(g, i + 1, jf, k)));
+      rho = 0.5 * (rho_at(g, m, u, i, jf - 1, k) + rho_at(g, m, u, i, jf, k));
+      xi = idx_t(g, i, jf, k); arr = rhs.ut;
+    } else { // u_phi at phi-face (j, kf)
+      const int j = a, kf = b;
+      const int k0 = g.periodic ? wrapk(g, kf - 1) : kf - 1, k1 = g.periodic ? wrapk(g, kf) : kf;
+      ua = 0.25 * (u.ld(F_UR, idx_r(g, i, j, k0)) + u.ld(F_UR, idx_r(g, i, j, k1)) +
+                   u.ld(F_UR, idx_r(g, i + 1, j, k0)) + u.ld(F_UR, idx_r(g, i + 1, j, k1)));
+      rho = 0.5 * (rho_at(g, m, u, i, j, k0) + rho_at(g, m, u, i, j, k1));
+      xi = idx_f(g, i, j, kf); arr = rhs.uf;
+    }
+    const double nu = m.mu / rho;
+    const double fp = g.rf[i + 1] * g.rf[i + 1], fm = g.rf[i] * g.rf[i];
+    ca = -ua / (2.0 * g.dr) - nu * fm / r2d2;
+    cb = nu * (fp + fm) / r2d2;
+    cc_ = ua / (2.0 * g.dr) - nu * fp / r2d2;
+  } else if (D == 1) {
+    const int j = s;
+    const double sn = g.sc[j];
+    double ua, rho, rr;
+    if (FAM == 0) { // u_r at r-face (fr, k)
+      const int fr = a, k = b;
+      rr = g.rf[fr];
+      ua = 0.25 * (u.ld(F_UT, idx_t(g, fr - 1, j, k)) + u.ld(F_UT, idx_t(g, fr - 1, j + 1, k)) +
+                   u.ld(F_UT, idx_t(g, fr, j, k)) + u.ld(F_UT, idx_t(g, fr, j + 1, k)));
+      rho = 0.5 * (rho_at(g, m, u, fr - 1, j, k) + rho_at(g, m, u, fr, j, k));
+      xi = idx_r(g, fr, j, k); arr = rhs.ur;
+      sglo = g.pole_lo ? 1.0 : -1.0;
+      sghi = g.pole_hi ? 1.0 : -1.0;
+    } else { // u_phi at phi-face (i, kf)
+      const int i = a, kf = b;
+      rr = g.rc[i];
+      const int k0 = g.periodic ? wrapk(g, kf - 1) : kf - 1, k1 = g.periodic ? wrapk(g, kf) : kf;
+      ua = 0.25 * (u.ld(F_UT, idx_t(g, i, j, k0)) + u.ld(F_UT, idx_t(g, i, j, k1)) +
+                   u.ld(F_UT, idx_t(g, i, j + 1, k0)) + u.ld(F_UT, idx_t(g, i, j + 1, k1)));
+      rho = 0.5 * (rho_at(g, m, u, i, j, k0) + rho_at(g, m, u, i, j, k1));
+      xi = idx_f(g, i, j, kf); arr = rhs.uf;
+    }
+    const double nu = m.mu / rho, q = rr * rr * sn * g.dt * g.dt;
+    ca = -ua / (2.0 * rr * g.dt) - nu * g.sf[j] / q;
+    cb = nu * (g.sf[j + 1] + g.sf[j]) / q;
+    cc_ = ua / (2.0 * rr * g.dt) - nu * g.sf[j + 1] / q;
+  } else {
+    const int k = s;
+    double ua, rho, rr, ss;
+    if (FAM == 0) { // u_r at r-face (fr, j)
+      const int fr = a, j = b;
+      rr = g.rf[fr]; ss = g.sc[j];
+      const int kp = g.periodic ? wrapk(g, k + 1) : k + 1;
+      ua = 0.25 * (u.ld(F_UF, idx_f(g, fr - 1, j, k)) + u.ld(F_UF, idx_f(g, fr - 1, j, kp)) +
+                   u.ld(F_UF, idx_f(g, fr, j, k)) + u.ld(F_UF, idx_f(g, fr, j, kp)));
+      rho = 0.5 * (rho_at(g, m, u, fr - 1, j, k) + rho_at(g, m, u, fr, j, k));
+      xi = idx_r(g, fr, j, k); arr = rhs.ur;
+    } else { // u_theta at theta-face (i, ft)
+      const int i = a, ft = b;
+      rr = g.rc[i]; ss = g.sf[ft];
+      const int kp = g.periodic ? wrapk(g, k + 1) : k + 1;
+      ua = 0.25 * (u.ld(F_UF, idx_f(g, i, ft - 1, k)) + u.ld(F_UF, idx_f(g, i, ft - 1, kp)) +
+                   u.ld(F_UF, idx_f(g, i, ft, k)) + u.ld(F_UF, idx_f(g, i, ft, kp)));
+      rho = 0.5 * (rho_at(g, m, u, i, ft - 1, k) + rho_at(g, m, u, i, ft, k));
+      xi = idx_t(g, i, ft, k); arr = rhs.ut;
+    }
+    const double nu = m.mu / rho, q = rr * rr * ss * ss * g.dp * g.dp;
+    ca = -ua / (2.0 * rr * ss * g.dp) - nu / q;
+    cb = 2.0 * nu / q;
+    cc_ = ua / (2.0 * rr * ss * g.dp) - nu / q;
+  }
+  if (!cyc && s == 0) { cb += sglo * ca; ca = 0.0; }
+  if (!cyc && s == n - 1) { cb += sghi * cc_; cc_ = 0.0; }
+  R.a = hs * ca;
+  R.b = 1.0 + hs * cb;
+  R.c = hs * cc_;
+  R.r = arr[xi];
+}
+
+
+template <int D>
+__device__ __forceinline__ void block_store(const Geo &g, const Fields &x, int a, int b, int s,
+                                            const double *v, bool accum) {
+  int i, j, k;
+  if (D == 0) { i = s; j = a; k = b; }
+  else if (D == 1) { i = a; j = s; k = b; }
+  else { i = a; j = b; k = s; }
+  const long xc = idx_c(g, i, j, k);
+  long xw;
+  double *w;
+  if (D == 0) { xw = idx_r(g, i + 1, j, k); w = x.ur; }
+  else if (D == 1) { xw = idx_t(g, i, j + 1, k); w = x.ut; }
+  else { xw = idx_f(g, i, j, g.periodic ? wrapk(g, k + 1) : k + 1); w = x.uf; }
+  if (accum) {
+    x.p[xc] += v[0];
+    x.T[xc] += v[1];
+    w[xw] += v[2];
+  } else {
+    x.p[xc] = v[0];
+    x.T[xc] = v[1];
+    w[xw] = v[2];
+  }
+}
+
+} // namespace dsw

@@ -42,4 +42,11 @@ def small_cases():
                                  amplitude=0.5, steps=1, K=2, seed=79),
         "sphere-min": I.Workload("sphere-min", I.full_sphere(3, 3, 3), mach=1e-2, amplitude=0.5,
                                  steps=1, K=2, seed=80),
+        # phi lines split into a power-of-two number of 4-cell chunks (16, 2, 1)
+        "sphere-chunks16": I.Workload("sphere-chunks16", I.full_sphere(9, 14, 64), mach=1e-3,
+                                      amplitude=0.5, steps=1, K=3, seed=81),
+        "sphere-chunks2": I.Workload("sphere-chunks2", I.full_sphere(4, 5, 8), mach=1e-2,
+                                     amplitude=0.5, steps=1, K=2, seed=82),
+        "sphere-chunks1": I.Workload("sphere-chunks1", I.full_sphere(3, 4, 4), mach=1e-2,
+                                     amplitude=0.5, steps=1, K=2, seed=83),
     }
