@@ -31,18 +31,32 @@ def log(*a):
 
 def kernel_sources_sha():
     h = hashlib.sha256()
-    for f in ("dsw_common.hpp", "residual.hip", "sweeps.hip", "api.hip"):
+    for f in ("dsw_common.hpp", "dsw_internal.hpp", "rows.hpp", "residual.hip", "sweeps.hip",
+              "phi_part.hip", "api.hip"):
         with open(os.path.join(ROOT, "paper_2004_13887_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
 
-def algorithmic_bytes(counts):
-    """per-launch algorithmic bytes of each kernel kind (each array read or
-    written once; neighbour re-reads are not counted)"""
+def algorithmic_bytes(counts, K):
+    """algorithmic bytes per split step of each kernel kind: every array a
+    kernel reads or writes counted once (neighbour re-reads not counted);
+    S = one five-field state.
+      residual   k=0: U^n -> R (2S);  k>0: Ubar, U^k, U^n -> R (4S)
+      sweep r    Ubar, R -> X1 (3S);  sweep theta: Ubar, X1 -> X2 (3S)
+      sweep phi  k=0: U^n, X2 -> U^1, Ubar^1 (4S);  0<k<K-1: Ubar, X2, U^k,
+                 U^n -> U^{k+1}, Ubar^{k+1} (6S);  k=K-1>0: Ubar, X2, U^k -> U^K (4S)"""
     S = 8 * sum(counts)
-    return {"residual": 4 * S, "sweep_r": 3 * S, "sweep_theta": 3 * S, "sweep_phi_update": 4 * S,
-            "state_copy": 2 * S}
+    res = 2 * S + 4 * S * (K - 1)
+    phi = 0
+    for k in range(K):
+        last = k == K - 1
+        if k == 0:
+            phi += (3 if last else 4) * S
+        else:
+            phi += (4 if last else 6) * S
+    return {"residual": res, "sweep_r": 3 * S * K, "sweep_theta": 3 * S * K,
+            "sweep_phi_update": phi, "boundary_copy": 0}
 
 
 def measured_traffic(kind, sha):
@@ -90,6 +104,8 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--calib", action="store_true",
+                    help="also run a plain 1 GiB device copy (to scale hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the multi-GPU path is "
@@ -112,6 +128,13 @@ def main():
         src, dst = bufs[n % 2], bufs[(n + 1) % 2]
         grid.split_step(src, dst, tau, w.K, stream)
 
+    if args.calib:  # known traffic: 1 GiB read + 1 GiB written
+        a = torch.empty(2 ** 27, dtype=torch.float64, device="cuda").fill_(1.0)
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
     log(f"[bench] warmup {args.warmup} steps (tau = {tau:.4f} s, K = {w.K})")
     for n in range(args.warmup):
         step(n)
@@ -139,18 +162,19 @@ def main():
     cells = w.grid.ncells
     value = cells * args.steps / (gpu_ms * 1e-3)
     model_bytes = 8 * (55 + 70 * (w.K - 1)) * cells  # per split step, fixed traffic model
-    alg = algorithmic_bytes(counts)
+    alg = algorithmic_bytes(counts, w.K)  # per step
     kstats = {}
     for k, (ms, n) in per_kernel.items():
         if n:
             avg = ms / n * 1e-3
+            per_launch = alg[k] * args.steps / n  # average algorithmic bytes per launch
             kstats[k] = {"avg_ms": avg * 1e3, "launches": n, "total_ms": ms,
-                         "GBps": alg[k] / avg / 1e9}
+                         "bytes_per_launch": per_launch, "GBps": per_launch / avg / 1e9}
             log(f"[bench] {k:17s} {n:4d} launches, avg {avg * 1e3:8.3f} ms, "
-                f"{alg[k] / avg / 1e9:8.1f} GB/s algorithmic")
+                f"{per_launch / avg / 1e9:8.1f} GB/s algorithmic")
     dom = max(kstats, key=lambda k: kstats[k]["total_ms"])
     sha = kernel_sources_sha()
-    achieved = alg[dom] / (kstats[dom]["avg_ms"] * 1e-3) / 1e9
+    achieved = kstats[dom]["GBps"]
     traffic = measured_traffic(dom, sha)
     out = {
         "metric": "grid-point updates/s per split step (FP64)",
@@ -170,7 +194,8 @@ def main():
                    "cells": cells, "K": w.K, "tau_s": tau},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": PEAK_HBM / 1e9,
                      "unit": "GB/s", "frac": achieved / (PEAK_HBM / 1e9),
-                     "traffic": traffic, "source_sha": sha},
+                     "traffic": traffic, "bytes_per_launch": kstats[dom]["bytes_per_launch"],
+                     "source_sha": sha},
         "step_model_GBps": model_bytes / (ms_per_step * 1e-3) / 1e9,
         "step_model_frac": model_bytes / (ms_per_step * 1e-3) / PEAK_HBM,
         "kernels": kstats,

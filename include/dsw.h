@@ -130,8 +130,8 @@ int dsw_split_step(dsw_grid *grid, const dsw_fields *Un, dsw_fields *Unp1, doubl
  * stream.  dsw_read_timing synchronises that stream, stores in ms[kind] the
  * total elapsed time and in launches[kind] the number of launches recorded
  * since the previous read (kind 0: residual, 1: r sweep, 2: theta sweep,
- * 3: phi sweep with update, 4: state copy U^{n+1,0} = U^n), then clears the
- * record. */
+ * 3: phi sweep with update, 4: copy of the Dirichlet boundary faces), then
+ * clears the record. */
 #define DSW_TIMING_KINDS 5
 int dsw_set_timing(dsw_grid *grid, int32_t enable);
 int dsw_read_timing(dsw_grid *grid, void *stream, double ms[DSW_TIMING_KINDS],

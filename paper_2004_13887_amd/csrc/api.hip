@@ -20,7 +20,7 @@ struct dsw_grid {
   Geo geo;
   Mat m;
   double *tables = nullptr; // rc | rf | sc | cc | sf | cf
-  Fields ub{}, r{}, x1{}, x2{};
+  Fields ub{}, ub2{}, r{}, x1{}, x2{}; // ub, ub2: midpoint states of consecutive iterations
   double *fields_mem = nullptr;
   Scratch sc{};
   double *scratch_mem = nullptr;
@@ -119,8 +119,11 @@ extern "C" int dsw_init_grid(const dsw_grid_desc *desc, const dsw_material *mat,
   HIPCHK(hipGetDevice(&G->device));
   const int nr = desc->n_r, nt = desc->n_theta, np = desc->n_phi;
   // metric tables (host, then device)
-  std::vector<double> h((size_t)nr + (nr + 1) + 2 * nt + 2 * (nt + 1));
-  double *rc = h.data(), *rf = rc + nr, *sc = rf + nr + 1, *cc = sc + nt, *sf = cc + nt, *cf = sf + nt + 1;
+  const size_t nt1 = (size_t)nt + 1, nr1 = (size_t)nr + 1;
+  std::vector<double> h(2 * (nr + nr1) + 4 * (nt + nt1));
+  double *rc = h.data(), *rf = rc + nr, *sc = rf + nr1, *cc = sc + nt, *sf = cc + nt, *cf = sf + nt1;
+  double *irc = cf + nt1, *irf = irc + nr, *isc = irf + nr1, *ctc = isc + nt, *isf = ctc + nt,
+         *ctf = isf + nt1;
   const double dr = (desc->r2 - desc->r1) / nr, dt = (desc->theta2 - desc->theta1) / nt,
                dp = (desc->phi2 - desc->phi1) / np;
   for (int i = 0; i < nr; i++) rc[i] = desc->r1 + (i + 0.5) * dr;
@@ -138,6 +141,13 @@ extern "C" int dsw_init_grid(const dsw_grid_desc *desc, const dsw_material *mat,
   const int pole_lo = desc->theta1 == 0.0, pole_hi = std::fabs(desc->theta2 - M_PI) <= 1e-12;
   if (pole_lo) { sf[0] = 0.0; cf[0] = 1.0; }
   if (pole_hi) { sf[nt] = 0.0; cf[nt] = -1.0; }
+  for (int i = 0; i < nr; i++) irc[i] = 1.0 / rc[i];
+  for (int f = 0; f <= nr; f++) irf[f] = 1.0 / rf[f];
+  for (int j = 0; j < nt; j++) { isc[j] = 1.0 / sc[j]; ctc[j] = cc[j] / sc[j]; }
+  for (int f = 0; f <= nt; f++) {
+    isf[f] = sf[f] != 0.0 ? 1.0 / sf[f] : 0.0;
+    ctf[f] = sf[f] != 0.0 ? cf[f] / sf[f] : 0.0;
+  }
   if (hipMalloc(&G->tables, h.size() * sizeof(double)) != hipSuccess) {
     delete G;
     return fail(DSW_ENOMEM, "metric tables");
@@ -148,8 +158,14 @@ extern "C" int dsw_init_grid(const dsw_grid_desc *desc, const dsw_material *mat,
   g.periodic = desc->periodic_phi ? 1 : 0;
   g.pole_lo = pole_lo; g.pole_hi = pole_hi;
   g.dr = dr; g.dt = dt; g.dp = dp;
+  g.idr = 1.0 / dr; g.idt = 1.0 / dt; g.idp = 1.0 / dp;
   double *t = G->tables;
-  g.rc = t; g.rf = t + nr; g.sc = t + 2 * nr + 1; g.cc = g.sc + nt; g.sf = g.cc + nt; g.cf = g.sf + nt + 1;
+  const long o_rf = nr, o_sc = o_rf + nr1, o_cc = o_sc + nt, o_sf = o_cc + nt, o_cf = o_sf + nt1,
+             o_irc = o_cf + nt1, o_irf = o_irc + nr, o_isc = o_irf + nr1, o_ctc = o_isc + nt,
+             o_isf = o_ctc + nt, o_ctf = o_isf + nt1;
+  g.rc = t; g.rf = t + o_rf; g.sc = t + o_sc; g.cc = t + o_cc; g.sf = t + o_sf; g.cf = t + o_cf;
+  g.irc = t + o_irc; g.irf = t + o_irf; g.isc = t + o_isc; g.ctc = t + o_ctc; g.isf = t + o_isf;
+  g.ctf = t + o_ctf;
   Mat &m = G->m;
   m.gam = mat->cp / mat->cv;
   m.Rg = mat->cp - mat->cv;
@@ -161,12 +177,13 @@ extern "C" int dsw_init_grid(const dsw_grid_desc *desc, const dsw_material *mat,
   // workspace: Ubar, R, X1, X2 and the sweep scratch
   counts(*desc, G->count);
   const long per = G->count[0] + G->count[1] + G->count[2] + G->count[3] + G->count[4];
-  if (hipMalloc(&G->fields_mem, 4 * per * sizeof(double)) != hipSuccess) {
+  if (hipMalloc(&G->fields_mem, 5 * per * sizeof(double)) != hipSuccess) {
     dsw_free_grid(G);
     return fail(DSW_ENOMEM, "workspace fields");
   }
   long off = 0;
   G->ub = carve(G->fields_mem, G->count, &off);
+  G->ub2 = carve(G->fields_mem, G->count, &off);
   G->r = carve(G->fields_mem, G->count, &off);
   G->x1 = carve(G->fields_mem, G->count, &off);
   G->x2 = carve(G->fields_mem, G->count, &off);
@@ -185,7 +202,7 @@ extern "C" int dsw_init_grid(const dsw_grid_desc *desc, const dsw_material *mat,
     return fail(DSW_ENOMEM, "status word");
   }
   HIPCHK(hipMemset(G->status, 0, ST_WORDS * sizeof(int)));
-  HIPCHK(hipMemset(G->fields_mem, 0, 4 * per * sizeof(double)));
+  HIPCHK(hipMemset(G->fields_mem, 0, 5 * per * sizeof(double)));
   *out = G;
   return DSW_OK;
 }
@@ -256,7 +273,10 @@ static int line_solve(int d, dsw_grid *G, const dsw_fields *Ubar, double tau, co
   if (!(tau > 0.0)) return fail(DSW_EINVAL, "tau must be > 0");
   if (rhs->p == x->p || rhs->ur == x->ur || rhs->ut == x->ut || rhs->uf == x->uf || rhs->T == x->T)
     return fail(DSW_EINVAL, "rhs and x must not alias");
-  launch_sweep(d, G->geo, G->m, F(Ubar), tau, F(rhs), F(x), G->sc, G->status, (hipStream_t)stream, false);
+  Out o{};
+  o.x = F(x);
+  o.mode = 0;
+  launch_sweep(d, G->geo, G->m, F(Ubar), tau, F(rhs), o, G->sc, G->status, (hipStream_t)stream);
   return check_launch("sweep kernel");
 }
 
@@ -285,20 +305,26 @@ extern "C" int dsw_split_step(dsw_grid *G, const dsw_fields *Un, dsw_fields *Unp
     return fail(DSW_EINVAL, "Unp1 must not alias Un");
   hipStream_t st = (hipStream_t)stream;
   const Fields un = F(Un), uk = F(Unp1);
-  // U^{n+1,0} = U^n
-  const double *src[5] = {un.p, un.ur, un.ut, un.uf, un.T};
-  double *dst[5] = {uk.p, uk.ur, uk.ut, uk.uf, uk.T};
-  hipError_t ce = hipSuccess;
-  timed(G, 4, st, [&] {
-    for (int q = 0; q < 5 && ce == hipSuccess; q++)
-      ce = hipMemcpyAsync(dst[q], src[q], G->count[q] * sizeof(double), hipMemcpyDeviceToDevice, st);
-  });
-  if (ce != hipSuccess) return fail(DSW_EHIP, std::string("state copy: ") + hipGetErrorString(ce));
+  const Fields none{};
+  // Dirichlet data of U^{n+1} and of both midpoint buffers = those of U^n
+  timed(G, 4, st, [&] { launch_bnd_copy(G->geo, un, uk, G->ub, G->ub2, st); });
+  const Fields ubuf[2] = {G->ub, G->ub2};
   for (int it = 0; it < K; it++) {
-    timed(G, 0, st, [&] { launch_residual(G->geo, G->m, un, uk, tau, G->r, G->ub, G->status, st); });
-    timed(G, 1, st, [&] { launch_sweep(0, G->geo, G->m, G->ub, tau, G->r, G->x1, G->sc, G->status, st, false); });
-    timed(G, 2, st, [&] { launch_sweep(1, G->geo, G->m, G->ub, tau, G->x1, G->x2, G->sc, G->status, st, false); });
-    timed(G, 3, st, [&] { launch_sweep(2, G->geo, G->m, G->ub, tau, G->x2, uk, G->sc, G->status, st, true); });
+    // midpoint state of this iteration: U^n itself at the first one, else the
+    // one written by the previous iteration's phi sweep
+    const Fields ubar = it == 0 ? un : ubuf[(it - 1) % 2];
+    timed(G, 0, st, [&] {
+      launch_residual_given_mid(G->geo, G->m, un, it == 0 ? un : uk, ubar, tau, G->r, G->status, st);
+    });
+    Out o1{}, o2{}, o3{};
+    o1.x = G->x1; o1.mode = 0;
+    o2.x = G->x2; o2.mode = 0;
+    o3.x = uk; o3.base = it == 0 ? un : uk; o3.un = un;
+    o3.ub = it < K - 1 ? ubuf[it % 2] : none;
+    o3.mode = 1;
+    timed(G, 1, st, [&] { launch_sweep(0, G->geo, G->m, ubar, tau, G->r, o1, G->sc, G->status, st); });
+    timed(G, 2, st, [&] { launch_sweep(1, G->geo, G->m, ubar, tau, G->x1, o2, G->sc, G->status, st); });
+    timed(G, 3, st, [&] { launch_sweep(2, G->geo, G->m, ubar, tau, G->x2, o3, G->sc, G->status, st); });
   }
   return check_launch("split step kernels");
 }

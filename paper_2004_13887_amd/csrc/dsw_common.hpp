@@ -20,9 +20,13 @@ struct Geo {
   int nr, nt, np, npf;
   int periodic, pole_lo, pole_hi;
   double dr, dt, dp;
-  const double *rc, *rf; // centre radii [nr], face radii [nr+1]
-  const double *sc, *cc; // sin, cos of theta at centres [nt]
-  const double *sf, *cf; // sin, cos of theta at faces [nt+1]
+  double idr, idt, idp;    // reciprocals of the spacings
+  const double *rc, *rf;   // centre radii [nr], face radii [nr+1]
+  const double *sc, *cc;   // sin, cos of theta at centres [nt]
+  const double *sf, *cf;   // sin, cos of theta at faces [nt+1]
+  const double *irc, *irf; // 1/rc, 1/rf
+  const double *isc, *ctc; // 1/sin, cot at centres
+  const double *isf, *ctf; // 1/sin, cot at faces (0 at a pole face: never used there)
 };
 
 struct Mat {
@@ -129,7 +133,7 @@ __device__ __forceinline__ double avgF(const Geo &g, const S &s, int i, int j, i
 template <class S>
 __device__ __forceinline__ void centre(const Geo &g, const Mat &m, const S &s, int i, int j, int k,
                                        Cent &c) {
-  const double r = g.rc[i], sn = g.sc[j], ct = g.cc[j] / g.sc[j];
+  const double ir = g.irc[i], is = g.isc[j], ct = g.ctc[j], irs = ir * is;
   const double r0 = gR(g, s, i, j, k), r1 = gR(g, s, i + 1, j, k);
   const double t0 = gT(g, s, i, j, k), t1 = gT(g, s, i, j + 1, k);
   const double f0 = gF(g, s, i, j, k), f1 = gF(g, s, i, j, k + 1);
@@ -139,29 +143,29 @@ __device__ __forceinline__ void centre(const Geo &g, const Mat &m, const S &s, i
   c.P = gC(g, s, F_P, i, j, k) + m.pinf;
   c.T = gC(g, s, F_T, i, j, k);
   c.chi = (m.gam - 1.0) * c.T / c.P;
-  c.Grr = (r1 - r0) / g.dr;
-  c.Gtt = (t1 - t0) / (r * g.dt) + c.ur / r;
-  c.Gff = (f1 - f0) / (r * sn * g.dp) + c.ur / r + c.ut * ct / r;
-  c.Srt = (avgT(g, s, i + 1, j, k) - avgT(g, s, i - 1, j, k)) / (2.0 * g.dr) +
-          (avgR(g, s, i, j + 1, k) - avgR(g, s, i, j - 1, k)) / (2.0 * r * g.dt) - c.ut / r;
-  c.Srf = (avgF(g, s, i + 1, j, k) - avgF(g, s, i - 1, j, k)) / (2.0 * g.dr) +
-          (avgR(g, s, i, j, k + 1) - avgR(g, s, i, j, k - 1)) / (2.0 * r * sn * g.dp) - c.uf / r;
-  c.Stf = (avgF(g, s, i, j + 1, k) - avgF(g, s, i, j - 1, k)) / (2.0 * r * g.dt) +
-          (avgT(g, s, i, j, k + 1) - avgT(g, s, i, j, k - 1)) / (2.0 * r * sn * g.dp) - c.uf * ct / r;
+  c.Grr = (r1 - r0) * g.idr;
+  c.Gtt = (t1 - t0) * (ir * g.idt) + c.ur * ir;
+  c.Gff = (f1 - f0) * (irs * g.idp) + c.ur * ir + c.ut * ct * ir;
+  c.Srt = (avgT(g, s, i + 1, j, k) - avgT(g, s, i - 1, j, k)) * (0.5 * g.idr) +
+          (avgR(g, s, i, j + 1, k) - avgR(g, s, i, j - 1, k)) * (0.5 * ir * g.idt) - c.ut * ir;
+  c.Srf = (avgF(g, s, i + 1, j, k) - avgF(g, s, i - 1, j, k)) * (0.5 * g.idr) +
+          (avgR(g, s, i, j, k + 1) - avgR(g, s, i, j, k - 1)) * (0.5 * irs * g.idp) - c.uf * ir;
+  c.Stf = (avgF(g, s, i, j + 1, k) - avgF(g, s, i, j - 1, k)) * (0.5 * ir * g.idt) +
+          (avgT(g, s, i, j, k + 1) - avgT(g, s, i, j, k - 1)) * (0.5 * irs * g.idp) - c.uf * ct * ir;
   c.tr = c.Grr + c.Gtt + c.Gff;
-  c.div = (g.rf[i + 1] * g.rf[i + 1] * r1 - g.rf[i] * g.rf[i] * r0) / (r * r * g.dr) +
-          (g.sf[j + 1] * t1 - g.sf[j] * t0) / (r * sn * g.dt) + (f1 - f0) / (r * sn * g.dp);
+  c.div = (g.rf[i + 1] * g.rf[i + 1] * r1 - g.rf[i] * g.rf[i] * r0) * (ir * ir * g.idr) +
+          (g.sf[j + 1] * t1 - g.sf[j] * t0) * (irs * g.idt) + (f1 - f0) * (irs * g.idp);
 }
 
 // full compact divergence at a centre (for the grad-div term of the momentum
 // equations at the faces between two cells)
 template <class S>
 __device__ __forceinline__ double divc(const Geo &g, const S &s, int i, int j, int k) {
-  const double r = g.rc[i], sn = g.sc[j];
-  return (g.rf[i + 1] * g.rf[i + 1] * gR(g, s, i + 1, j, k) - g.rf[i] * g.rf[i] * gR(g, s, i, j, k)) /
-             (r * r * g.dr) +
-         (g.sf[j + 1] * gT(g, s, i, j + 1, k) - g.sf[j] * gT(g, s, i, j, k)) / (r * sn * g.dt) +
-         (gF(g, s, i, j, k + 1) - gF(g, s, i, j, k)) / (r * sn * g.dp);
+  const double ir = g.irc[i], irs = ir * g.isc[j];
+  return (g.rf[i + 1] * g.rf[i + 1] * gR(g, s, i + 1, j, k) - g.rf[i] * g.rf[i] * gR(g, s, i, j, k)) *
+             (ir * ir * g.idr) +
+         (g.sf[j + 1] * gT(g, s, i, j + 1, k) - g.sf[j] * gT(g, s, i, j, k)) * (irs * g.idt) +
+         (gF(g, s, i, j, k + 1) - gF(g, s, i, j, k)) * (irs * g.idp);
 }
 
 } // namespace dsw

@@ -130,8 +130,7 @@ __device__ void pcr_scalar(int t, int T, int cyc, double &A, double &B, double &
 
 // ------------------------------------------------------------ block line --
 __device__ void part_block_line(const Geo &g, const Mat &m, const SrcOne &u, const Fields &rhs,
-                                const Fields &x, int i, int j, double hs, bool accum, double *lds,
-                                int *status) {
+                                const Out &o, int i, int j, double hs, double *lds, int *status) {
   const int N = g.np, T = part_chunks(N), cyc = g.periodic;
   const int t = threadIdx.x;
   const bool act = t < T;
@@ -273,10 +272,10 @@ __device__ void part_block_line(const Geo &g, const Mat &m, const SrcOne &u, con
         mv3(Cm[q], xs, t3);
 #pragma unroll
         for (int z = 0; z < 3; z++) v[z] += Ym[q][z] + t3[z];
-        block_store<2>(g, x, i, j, a0 + q, v, accum);
+        block_store<2>(g, o, i, j, a0 + q, v);
       }
     }
-    block_store<2>(g, x, i, j, a0 + len - 1, xs, accum);
+    block_store<2>(g, o, i, j, a0 + len - 1, xs);
   }
   __syncthreads();
 }
@@ -284,14 +283,13 @@ __device__ void part_block_line(const Geo &g, const Mat &m, const SrcOne &u, con
 // ----------------------------------------------------------- scalar line --
 template <int FAM>
 __device__ void part_scalar_line(const Geo &g, const Mat &m, const SrcOne &u, const Fields &rhs,
-                                 const Fields &x, int a, int b, double hs, bool accum, double *lds,
-                                 int *status) {
+                                 const Out &o, int a, int b, double hs, double *lds, int *status) {
   const int N = g.np, T = part_chunks(N), cyc = g.periodic;
   const int t = threadIdx.x;
   const bool act = t < T;
   const int a0 = t * PM;
   const int len = act ? min(PM, N - a0) : 0;
-  double *out = FAM == 0 ? x.ur : x.ut;
+  const int ofid = FAM == 0 ? F_UR : F_UT;
   double Cm[PM - 1], Em[PM - 1], Ym[PM - 1];
   SRow R;
   long xi;
@@ -356,12 +354,10 @@ __device__ void part_scalar_line(const Geo &g, const Mat &m, const SrcOne &u, co
     for (int q = 0; q < PM - 1; q++) {
       if (q < len - 1) {
         const double v = Ym[q] + Em[q] * xl + Cm[q] * xs;
-        const long xq = FAM == 0 ? idx_r(g, a, b, a0 + q) : idx_t(g, a, b, a0 + q);
-        if (accum) out[xq] += v; else out[xq] = v;
+        put(o, ofid, FAM == 0 ? idx_r(g, a, b, a0 + q) : idx_t(g, a, b, a0 + q), v);
       }
     }
-    const long xq = FAM == 0 ? idx_r(g, a, b, a0 + len - 1) : idx_t(g, a, b, a0 + len - 1);
-    if (accum) out[xq] += xs; else out[xq] = xs;
+    put(o, ofid, FAM == 0 ? idx_r(g, a, b, a0 + len - 1) : idx_t(g, a, b, a0 + len - 1), xs);
   }
   __syncthreads();
 }
@@ -369,11 +365,12 @@ __device__ void part_scalar_line(const Geo &g, const Mat &m, const SrcOne &u, co
 // one workgroup per (i, j): block line (i, j), u_r line on r-face i (i >= 1),
 // u_theta line on theta-face j (j >= 1)
 __global__ void __launch_bounds__(256) k_phi_part(Geo g, Mat m, SrcOne u, double hs, Fields rhs,
-                                                  Fields x, int accum, int *status) {
+                                                  Out o, int *status) {
   extern __shared__ double lds[];
   const int j = blockIdx.x, i = blockIdx.y;
   const int t = threadIdx.x;
-  if (!accum) { // boundary-normal faces of x that no phi line owns
+  if (o.mode == 0) { // boundary-normal faces of x that no phi line owns
+    const Fields &x = o.x;
     for (int k = t; k < g.np; k += blockDim.x) {
       if (i == 0) x.ur[idx_r(g, 0, j, k)] = 0.0;
       if (i == g.nr - 1) x.ur[idx_r(g, g.nr, j, k)] = 0.0;
@@ -382,9 +379,9 @@ __global__ void __launch_bounds__(256) k_phi_part(Geo g, Mat m, SrcOne u, double
     }
     if (!g.periodic && t == 0) x.uf[idx_f(g, i, j, 0)] = 0.0;
   }
-  part_block_line(g, m, u, rhs, x, i, j, hs, accum != 0, lds, status);
-  if (i >= 1) part_scalar_line<0>(g, m, u, rhs, x, i, j, hs, accum != 0, lds, status);
-  if (j >= 1) part_scalar_line<1>(g, m, u, rhs, x, i, j, hs, accum != 0, lds, status);
+  part_block_line(g, m, u, rhs, o, i, j, hs, lds, status);
+  if (i >= 1) part_scalar_line<0>(g, m, u, rhs, o, i, j, hs, lds, status);
+  if (j >= 1) part_scalar_line<1>(g, m, u, rhs, o, i, j, hs, lds, status);
 }
 
 bool phi_part_supported(const Geo &g) {
@@ -398,15 +395,14 @@ bool phi_part_supported(const Geo &g) {
 }
 
 void launch_phi_part(const Geo &g, const Mat &m, const Fields &Ub, double tau, const Fields &rhs,
-                     const Fields &x, int *status, hipStream_t st, bool accum) {
+                     const Out &o, int *status, hipStream_t st) {
   SrcOne u;
   u.a[F_P] = Ub.p; u.a[F_UR] = Ub.ur; u.a[F_UT] = Ub.ut; u.a[F_UF] = Ub.uf; u.a[F_T] = Ub.T;
   const int T = part_chunks(g.np);
   const int bs = ((T + 63) / 64) * 64;
   const size_t lds = sizeof(double) * 33 * T;
   dim3 grid(g.nt, g.nr);
-  hipLaunchKernelGGL(k_phi_part, grid, dim3(bs), lds, st, g, m, u, 0.5 * tau, rhs, x, accum ? 1 : 0,
-                     status);
+  hipLaunchKernelGGL(k_phi_part, grid, dim3(bs), lds, st, g, m, u, 0.5 * tau, rhs, o, status);
 }
 
 } // namespace dsw

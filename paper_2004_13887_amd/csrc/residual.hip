@@ -8,8 +8,11 @@
 //
 // One thread per point of the extended index space (nr+1) x (nt+1) x npf; a
 // thread owns the centre (i,j,k) and the three faces with the same indices.
-// The midpoint state is formed on the fly from Un and Uk (both read through
-// the caches), so the pass reads Un, Uk and writes Ubar, R once each.
+// Two variants:
+//   * the C-ABI call forms the midpoint on the fly from Un and Uk and writes it;
+//   * inside a split step the midpoint is already resident (written by the
+//     previous iteration's last sweep, or U^n itself at the first iteration),
+//     so every neighbour read is a single load.
 #include "dsw_common.hpp"
 #include "dsw_internal.hpp"
 
@@ -19,31 +22,31 @@ template <class S>
 __device__ double F_p_T(const Geo &g, const Mat &m, const S &s, int i, int j, int k, double *FT) {
   Cent c;
   centre(g, m, s, i, j, k, c);
-  const double r = g.rc[i], sn = g.sc[j];
-  double advp = c.ur * (gC(g, s, F_P, i + 1, j, k) - gC(g, s, F_P, i - 1, j, k)) / (2.0 * g.dr) +
-                c.ut / r * (gC(g, s, F_P, i, j + 1, k) - gC(g, s, F_P, i, j - 1, k)) / (2.0 * g.dt) +
-                c.uf / (r * sn) * (gC(g, s, F_P, i, j, k + 1) - gC(g, s, F_P, i, j, k - 1)) / (2.0 * g.dp);
-  double advT = c.ur * (gC(g, s, F_T, i + 1, j, k) - gC(g, s, F_T, i - 1, j, k)) / (2.0 * g.dr) +
-                c.ut / r * (gC(g, s, F_T, i, j + 1, k) - gC(g, s, F_T, i, j - 1, k)) / (2.0 * g.dt) +
-                c.uf / (r * sn) * (gC(g, s, F_T, i, j, k + 1) - gC(g, s, F_T, i, j, k - 1)) / (2.0 * g.dp);
-  const double T0 = c.T;
-  double lap =
-      (g.rf[i + 1] * g.rf[i + 1] * (gC(g, s, F_T, i + 1, j, k) - T0) -
-       g.rf[i] * g.rf[i] * (T0 - gC(g, s, F_T, i - 1, j, k))) / (r * r * g.dr * g.dr) +
-      (g.sf[j + 1] * (gC(g, s, F_T, i, j + 1, k) - T0) - g.sf[j] * (T0 - gC(g, s, F_T, i, j - 1, k))) /
-          (r * r * sn * g.dt * g.dt) +
-      (gC(g, s, F_T, i, j, k + 1) - 2.0 * T0 + gC(g, s, F_T, i, j, k - 1)) / (r * r * sn * sn * g.dp * g.dp);
-  double phi = m.mu * (2.0 * (c.Grr * c.Grr + c.Gtt * c.Gtt + c.Gff * c.Gff) + c.Srt * c.Srt +
-                       c.Srf * c.Srf + c.Stf * c.Stf - (2.0 / 3.0) * c.tr * c.div);
+  const double ir = g.irc[i], is = g.isc[j];
+  const double hr = 0.5 * g.idr, ht = 0.5 * ir * g.idt, hp = 0.5 * ir * is * g.idp;
+  const double advp = c.ur * (gC(g, s, F_P, i + 1, j, k) - gC(g, s, F_P, i - 1, j, k)) * hr +
+                      c.ut * (gC(g, s, F_P, i, j + 1, k) - gC(g, s, F_P, i, j - 1, k)) * ht +
+                      c.uf * (gC(g, s, F_P, i, j, k + 1) - gC(g, s, F_P, i, j, k - 1)) * hp;
+  const double Tim = gC(g, s, F_T, i - 1, j, k), Tip = gC(g, s, F_T, i + 1, j, k);
+  const double Tjm = gC(g, s, F_T, i, j - 1, k), Tjp = gC(g, s, F_T, i, j + 1, k);
+  const double Tkm = gC(g, s, F_T, i, j, k - 1), Tkp = gC(g, s, F_T, i, j, k + 1);
+  const double advT = c.ur * (Tip - Tim) * hr + c.ut * (Tjp - Tjm) * ht + c.uf * (Tkp - Tkm) * hp;
+  const double T0 = c.T, ir2 = ir * ir;
+  const double lap =
+      (g.rf[i + 1] * g.rf[i + 1] * (Tip - T0) - g.rf[i] * g.rf[i] * (T0 - Tim)) * (ir2 * g.idr * g.idr) +
+      (g.sf[j + 1] * (Tjp - T0) - g.sf[j] * (T0 - Tjm)) * (ir2 * is * g.idt * g.idt) +
+      (Tkp - 2.0 * T0 + Tkm) * (ir2 * is * is * g.idp * g.idp);
+  const double phi = m.mu * (2.0 * (c.Grr * c.Grr + c.Gtt * c.Gtt + c.Gff * c.Gff) + c.Srt * c.Srt +
+                             c.Srf * c.Srf + c.Stf * c.Stf - (2.0 / 3.0) * c.tr * c.div);
   *FT = advT + (m.gam - 1.0) * c.T * c.div - c.chi * phi - c.chi * m.kap * lap;
   return advp + m.gam * c.P * c.div - (m.gam - 1.0) * phi - (m.gam - 1.0) * m.kap * lap;
 }
 
 template <class S>
 __device__ double F_ur(const Geo &g, const Mat &m, const S &s, int f, int j, int k) {
-  const double rF = g.rf[f], sn = g.sc[j];
-  const double rho = 0.5 * (rho_at(g, m, s, f - 1, j, k) + rho_at(g, m, s, f, j, k));
-  const double nu = m.mu / rho;
+  const double irF = g.irf[f], is = g.isc[j], irF2 = irF * irF;
+  const double irho = 1.0 / (0.5 * (rho_at(g, m, s, f - 1, j, k) + rho_at(g, m, s, f, j, k)));
+  const double nu = m.mu * irho;
   const double un = gR(g, s, f, j, k);
   const double ua = 0.25 * (gT(g, s, f - 1, j, k) + gT(g, s, f - 1, j + 1, k) + gT(g, s, f, j, k) +
                             gT(g, s, f, j + 1, k));
@@ -52,30 +55,30 @@ __device__ double F_ur(const Geo &g, const Mat &m, const S &s, int f, int j, int
   const double xp = gR(g, s, f + 1, j, k), xm = gR(g, s, f - 1, j, k);
   const double yp = gR(g, s, f, j + 1, k), ym = gR(g, s, f, j - 1, k);
   const double zp = gR(g, s, f, j, k + 1), zm = gR(g, s, f, j, k - 1);
-  double N = (gC(g, s, F_P, f, j, k) - gC(g, s, F_P, f - 1, j, k)) / (rho * g.dr);
-  N += un * (xp - xm) / (2.0 * g.dr) + ua / rF * (yp - ym) / (2.0 * g.dt) +
-       ub / (rF * sn) * (zp - zm) / (2.0 * g.dp) - (ua * ua + ub * ub) / rF;
-  double vis = (g.rc[f] * g.rc[f] * (xp - un) - g.rc[f - 1] * g.rc[f - 1] * (un - xm)) / (rF * rF * g.dr * g.dr) +
-               (g.sf[j + 1] * (yp - un) - g.sf[j] * (un - ym)) / (rF * rF * sn * g.dt * g.dt) +
-               (zp - 2.0 * un + zm) / (rF * rF * sn * sn * g.dp * g.dp);
+  double N = (gC(g, s, F_P, f, j, k) - gC(g, s, F_P, f - 1, j, k)) * (irho * g.idr);
+  N += un * (xp - xm) * (0.5 * g.idr) + ua * (yp - ym) * (0.5 * irF * g.idt) +
+       ub * (zp - zm) * (0.5 * irF * is * g.idp) - (ua * ua + ub * ub) * irF;
+  double vis = (g.rc[f] * g.rc[f] * (xp - un) - g.rc[f - 1] * g.rc[f - 1] * (un - xm)) * (irF2 * g.idr * g.idr) +
+               (g.sf[j + 1] * (yp - un) - g.sf[j] * (un - ym)) * (irF2 * is * g.idt * g.idt) +
+               (zp - 2.0 * un + zm) * (irF2 * is * is * g.idp * g.idp);
   const double dth = 0.5 *
                      ((g.sf[j + 1] * gT(g, s, f - 1, j + 1, k) - g.sf[j] * gT(g, s, f - 1, j, k)) +
-                      (g.sf[j + 1] * gT(g, s, f, j + 1, k) - g.sf[j] * gT(g, s, f, j, k))) / g.dt;
+                      (g.sf[j + 1] * gT(g, s, f, j + 1, k) - g.sf[j] * gT(g, s, f, j, k))) * g.idt;
   const double dph = 0.5 *
                      ((gF(g, s, f - 1, j, k + 1) - gF(g, s, f - 1, j, k)) +
-                      (gF(g, s, f, j, k + 1) - gF(g, s, f, j, k))) / g.dp;
-  vis += -2.0 * un / (rF * rF) - 2.0 / (rF * rF * sn) * dth - 2.0 / (rF * rF * sn) * dph;
-  const double gd = (divc(g, s, f, j, k) - divc(g, s, f - 1, j, k)) / g.dr;
-  N += -2.0 * m.omega * sn * ub;
+                      (gF(g, s, f, j, k + 1) - gF(g, s, f, j, k))) * g.idp;
+  vis += -2.0 * un * irF2 - 2.0 * irF2 * is * dth - 2.0 * irF2 * is * dph;
+  const double gd = (divc(g, s, f, j, k) - divc(g, s, f - 1, j, k)) * g.idr;
+  N += -2.0 * m.omega * g.sc[j] * ub;
   return N - nu * vis - nu / 3.0 * gd + m.g_r;
 }
 
 template <class S>
 __device__ double F_ut(const Geo &g, const Mat &m, const S &s, int i, int f, int k) {
-  const double r = g.rc[i], sF = g.sf[f], ctF = g.cf[f] / g.sf[f];
+  const double ir = g.irc[i], isF = g.isf[f], ctF = g.ctf[f], ir2 = ir * ir;
   const int j0 = f - 1, j1 = f;
-  const double rho = 0.5 * (rho_at(g, m, s, i, j0, k) + rho_at(g, m, s, i, j1, k));
-  const double nu = m.mu / rho;
+  const double irho = 1.0 / (0.5 * (rho_at(g, m, s, i, j0, k) + rho_at(g, m, s, i, j1, k)));
+  const double nu = m.mu * irho;
   const double un = gT(g, s, i, f, k);
   const double ua = 0.25 * (gR(g, s, i, j0, k) + gR(g, s, i, j1, k) + gR(g, s, i + 1, j0, k) +
                             gR(g, s, i + 1, j1, k));
@@ -84,26 +87,26 @@ __device__ double F_ut(const Geo &g, const Mat &m, const S &s, int i, int f, int
   const double xp = gT(g, s, i + 1, f, k), xm = gT(g, s, i - 1, f, k);
   const double yp = gT(g, s, i, f + 1, k), ym = gT(g, s, i, f - 1, k);
   const double zp = gT(g, s, i, f, k + 1), zm = gT(g, s, i, f, k - 1);
-  double N = (gC(g, s, F_P, i, j1, k) - gC(g, s, F_P, i, j0, k)) / (rho * r * g.dt);
-  N += ua * (xp - xm) / (2.0 * g.dr) + un / r * (yp - ym) / (2.0 * g.dt) +
-       ub / (r * sF) * (zp - zm) / (2.0 * g.dp) + (un * ua - ub * ub * ctF) / r;
-  double vis = (g.rf[i + 1] * g.rf[i + 1] * (xp - un) - g.rf[i] * g.rf[i] * (un - xm)) / (r * r * g.dr * g.dr) +
-               (g.sc[j1] * (yp - un) - g.sc[j0] * (un - ym)) / (r * r * sF * g.dt * g.dt) +
-               (zp - 2.0 * un + zm) / (r * r * sF * sF * g.dp * g.dp);
-  const double dthr = 0.5 * ((gR(g, s, i, j1, k) - gR(g, s, i, j0, k)) + (gR(g, s, i + 1, j1, k) - gR(g, s, i + 1, j0, k))) / g.dt;
-  const double dphf = 0.5 * ((gF(g, s, i, j0, k + 1) - gF(g, s, i, j0, k)) + (gF(g, s, i, j1, k + 1) - gF(g, s, i, j1, k))) / g.dp;
-  vis += -un / (r * r * sF * sF) + 2.0 / (r * r) * dthr - 2.0 * ctF / (r * r * sF) * dphf;
-  const double gd = (divc(g, s, i, j1, k) - divc(g, s, i, j0, k)) / (r * g.dt);
+  double N = (gC(g, s, F_P, i, j1, k) - gC(g, s, F_P, i, j0, k)) * (irho * ir * g.idt);
+  N += ua * (xp - xm) * (0.5 * g.idr) + un * (yp - ym) * (0.5 * ir * g.idt) +
+       ub * (zp - zm) * (0.5 * ir * isF * g.idp) + (un * ua - ub * ub * ctF) * ir;
+  double vis = (g.rf[i + 1] * g.rf[i + 1] * (xp - un) - g.rf[i] * g.rf[i] * (un - xm)) * (ir2 * g.idr * g.idr) +
+               (g.sc[j1] * (yp - un) - g.sc[j0] * (un - ym)) * (ir2 * isF * g.idt * g.idt) +
+               (zp - 2.0 * un + zm) * (ir2 * isF * isF * g.idp * g.idp);
+  const double dthr = 0.5 * ((gR(g, s, i, j1, k) - gR(g, s, i, j0, k)) + (gR(g, s, i + 1, j1, k) - gR(g, s, i + 1, j0, k))) * g.idt;
+  const double dphf = 0.5 * ((gF(g, s, i, j0, k + 1) - gF(g, s, i, j0, k)) + (gF(g, s, i, j1, k + 1) - gF(g, s, i, j1, k))) * g.idp;
+  vis += -un * ir2 * isF * isF + 2.0 * ir2 * dthr - 2.0 * ctF * ir2 * isF * dphf;
+  const double gd = (divc(g, s, i, j1, k) - divc(g, s, i, j0, k)) * (ir * g.idt);
   N += -2.0 * m.omega * g.cf[f] * ub;
   return N - nu * vis - nu / 3.0 * gd;
 }
 
 template <class S>
 __device__ double F_uf(const Geo &g, const Mat &m, const S &s, int i, int j, int f) {
-  const double r = g.rc[i], sn = g.sc[j], ct = g.cc[j] / g.sc[j];
+  const double ir = g.irc[i], is = g.isc[j], ct = g.ctc[j], ir2 = ir * ir;
   const int k0 = g.periodic ? wrapk(g, f - 1) : f - 1, k1 = g.periodic ? wrapk(g, f) : f;
-  const double rho = 0.5 * (rho_at(g, m, s, i, j, k0) + rho_at(g, m, s, i, j, k1));
-  const double nu = m.mu / rho;
+  const double irho = 1.0 / (0.5 * (rho_at(g, m, s, i, j, k0) + rho_at(g, m, s, i, j, k1)));
+  const double nu = m.mu * irho;
   const double un = gF(g, s, i, j, f);
   const double ua = 0.25 * (gR(g, s, i, j, k0) + gR(g, s, i, j, k1) + gR(g, s, i + 1, j, k0) +
                             gR(g, s, i + 1, j, k1));
@@ -112,68 +115,94 @@ __device__ double F_uf(const Geo &g, const Mat &m, const S &s, int i, int j, int
   const double xp = gF(g, s, i + 1, j, f), xm = gF(g, s, i - 1, j, f);
   const double yp = gF(g, s, i, j + 1, f), ym = gF(g, s, i, j - 1, f);
   const double zp = gF(g, s, i, j, f + 1), zm = gF(g, s, i, j, f - 1);
-  double N = (gC(g, s, F_P, i, j, k1) - gC(g, s, F_P, i, j, k0)) / (rho * r * sn * g.dp);
-  N += ua * (xp - xm) / (2.0 * g.dr) + ub / r * (yp - ym) / (2.0 * g.dt) +
-       un / (r * sn) * (zp - zm) / (2.0 * g.dp) + un * (ua + ub * ct) / r;
-  double vis = (g.rf[i + 1] * g.rf[i + 1] * (xp - un) - g.rf[i] * g.rf[i] * (un - xm)) / (r * r * g.dr * g.dr) +
-               (g.sf[j + 1] * (yp - un) - g.sf[j] * (un - ym)) / (r * r * sn * g.dt * g.dt) +
-               (zp - 2.0 * un + zm) / (r * r * sn * sn * g.dp * g.dp);
-  const double dphr = 0.5 * ((gR(g, s, i, j, k1) - gR(g, s, i, j, k0)) + (gR(g, s, i + 1, j, k1) - gR(g, s, i + 1, j, k0))) / g.dp;
-  const double dpht = 0.5 * ((gT(g, s, i, j, k1) - gT(g, s, i, j, k0)) + (gT(g, s, i, j + 1, k1) - gT(g, s, i, j + 1, k0))) / g.dp;
-  vis += -un / (r * r * sn * sn) + 2.0 / (r * r * sn) * dphr + 2.0 * ct / (r * r * sn) * dpht;
-  const double gd = (divc(g, s, i, j, k1) - divc(g, s, i, j, k0)) / (r * sn * g.dp);
-  N += 2.0 * m.omega * (g.cc[j] * ub + sn * ua);
+  double N = (gC(g, s, F_P, i, j, k1) - gC(g, s, F_P, i, j, k0)) * (irho * ir * is * g.idp);
+  N += ua * (xp - xm) * (0.5 * g.idr) + ub * (yp - ym) * (0.5 * ir * g.idt) +
+       un * (zp - zm) * (0.5 * ir * is * g.idp) + un * (ua + ub * ct) * ir;
+  double vis = (g.rf[i + 1] * g.rf[i + 1] * (xp - un) - g.rf[i] * g.rf[i] * (un - xm)) * (ir2 * g.idr * g.idr) +
+               (g.sf[j + 1] * (yp - un) - g.sf[j] * (un - ym)) * (ir2 * is * g.idt * g.idt) +
+               (zp - 2.0 * un + zm) * (ir2 * is * is * g.idp * g.idp);
+  const double dphr = 0.5 * ((gR(g, s, i, j, k1) - gR(g, s, i, j, k0)) + (gR(g, s, i + 1, j, k1) - gR(g, s, i + 1, j, k0))) * g.idp;
+  const double dpht = 0.5 * ((gT(g, s, i, j, k1) - gT(g, s, i, j, k0)) + (gT(g, s, i, j + 1, k1) - gT(g, s, i, j + 1, k0))) * g.idp;
+  vis += -un * ir2 * is * is + 2.0 * ir2 * is * dphr + 2.0 * ct * ir2 * is * dpht;
+  const double gd = (divc(g, s, i, j, k1) - divc(g, s, i, j, k0)) * (ir * is * g.idp);
+  N += 2.0 * m.omega * (g.cc[j] * ub + g.sc[j] * ua);
   return N - nu * vis - nu / 3.0 * gd;
 }
 
-__global__ void __launch_bounds__(256) k_residual(Geo g, Mat m, SrcMid s, double tau, Fields R,
+// -(Uk - Un) at a point; zero when the two states are the same array
+struct Diff {
+  const double *k[5], *n[5];
+  int same;
+  __device__ __forceinline__ double at(int f, long x) const { return same ? 0.0 : k[f][x] - n[f][x]; }
+};
+
+template <class S, bool WRITE_UB>
+__global__ void __launch_bounds__(256) k_residual(Geo g, Mat m, S s, Diff dU, double tau, Fields R,
                                                   Fields Ub, int *status) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   const int j = blockIdx.y;
   const int i = blockIdx.z;
   if (k >= g.npf) return;
   const bool kc = k < g.np;
-  // cell centre
-  if (i < g.nr && j < g.nt && kc) {
+  if (i < g.nr && j < g.nt && kc) { // cell centre
     const long x = idx_c(g, i, j, k);
     const double ubp = s.ld(F_P, x), ubT = s.ld(F_T, x);
-    Ub.p[x] = ubp;
-    Ub.T[x] = ubT;
+    if (WRITE_UB) { Ub.p[x] = ubp; Ub.T[x] = ubT; }
     if (!(ubT > 0.0) || !(ubp + m.pinf > 0.0)) status[ST_NONPHYS] = 1; // plain vector store
     double FT;
     const double Fp = F_p_T(g, m, s, i, j, k, &FT);
-    R.p[x] = -(s.k[F_P][x] - s.n[F_P][x]) - tau * Fp;
-    R.T[x] = -(s.k[F_T][x] - s.n[F_T][x]) - tau * FT;
+    R.p[x] = -dU.at(F_P, x) - tau * Fp;
+    R.T[x] = -dU.at(F_T, x) - tau * FT;
   }
-  // r face i
-  if (j < g.nt && kc) {
+  if (j < g.nt && kc) { // r face i
     const long x = idx_r(g, i, j, k);
-    Ub.ur[x] = s.ld(F_UR, x);
-    R.ur[x] = (i >= 1 && i < g.nr) ? -(s.k[F_UR][x] - s.n[F_UR][x]) - tau * F_ur(g, m, s, i, j, k) : 0.0;
+    if (WRITE_UB) Ub.ur[x] = s.ld(F_UR, x);
+    R.ur[x] = (i >= 1 && i < g.nr) ? -dU.at(F_UR, x) - tau * F_ur(g, m, s, i, j, k) : 0.0;
   }
-  // theta face j
-  if (i < g.nr && kc) {
+  if (i < g.nr && kc) { // theta face j
     const long x = idx_t(g, i, j, k);
-    Ub.ut[x] = s.ld(F_UT, x);
-    R.ut[x] = (j >= 1 && j < g.nt) ? -(s.k[F_UT][x] - s.n[F_UT][x]) - tau * F_ut(g, m, s, i, j, k) : 0.0;
+    if (WRITE_UB) Ub.ut[x] = s.ld(F_UT, x);
+    R.ut[x] = (j >= 1 && j < g.nt) ? -dU.at(F_UT, x) - tau * F_ut(g, m, s, i, j, k) : 0.0;
   }
-  // phi face k
-  if (i < g.nr && j < g.nt) {
+  if (i < g.nr && j < g.nt) { // phi face k
     const long x = idx_f(g, i, j, k);
-    Ub.uf[x] = s.ld(F_UF, x);
+    if (WRITE_UB) Ub.uf[x] = s.ld(F_UF, x);
     const bool interior = g.periodic || (k >= 1 && k < g.np);
-    R.uf[x] = interior ? -(s.k[F_UF][x] - s.n[F_UF][x]) - tau * F_uf(g, m, s, i, j, k) : 0.0;
+    R.uf[x] = interior ? -dU.at(F_UF, x) - tau * F_uf(g, m, s, i, j, k) : 0.0;
   }
+}
+
+static void set5(const double **dst, const Fields &f) {
+  dst[F_P] = f.p; dst[F_UR] = f.ur; dst[F_UT] = f.ut; dst[F_UF] = f.uf; dst[F_T] = f.T;
 }
 
 void launch_residual(const Geo &g, const Mat &m, const Fields &Un, const Fields &Uk, double tau,
                      const Fields &R, const Fields &Ub, int *status, hipStream_t st) {
   SrcMid s;
-  s.n[F_P] = Un.p; s.n[F_UR] = Un.ur; s.n[F_UT] = Un.ut; s.n[F_UF] = Un.uf; s.n[F_T] = Un.T;
-  s.k[F_P] = Uk.p; s.k[F_UR] = Uk.ur; s.k[F_UT] = Uk.ut; s.k[F_UF] = Uk.uf; s.k[F_T] = Uk.T;
+  set5(s.n, Un);
+  set5(s.k, Uk);
+  Diff d;
+  set5(d.n, Un);
+  set5(d.k, Uk);
+  d.same = 0;
   dim3 block(64, 1, 1);
   dim3 grid((g.npf + 63) / 64, g.nt + 1, g.nr + 1);
-  hipLaunchKernelGGL(k_residual, grid, block, 0, st, g, m, s, tau, R, Ub, status);
+  hipLaunchKernelGGL((k_residual<SrcMid, true>), grid, block, 0, st, g, m, s, d, tau, R, Ub, status);
+}
+
+void launch_residual_given_mid(const Geo &g, const Mat &m, const Fields &Un, const Fields &Uk,
+                               const Fields &Ub, double tau, const Fields &R, int *status,
+                               hipStream_t st) {
+  SrcOne s;
+  set5(s.a, Ub);
+  Diff d;
+  set5(d.n, Un);
+  set5(d.k, Uk);
+  d.same = (Un.p == Uk.p) ? 1 : 0;
+  dim3 block(64, 1, 1);
+  dim3 grid((g.npf + 63) / 64, g.nt + 1, g.nr + 1);
+  hipLaunchKernelGGL((k_residual<SrcOne, false>), grid, block, 0, st, g, m, s, d, tau, R, Fields{},
+                     status);
 }
 
 } // namespace dsw

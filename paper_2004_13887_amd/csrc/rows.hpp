@@ -74,36 +74,36 @@ __device__ void block_row(const Geo &g, const Mat &m, const SrcOne &u, const Fie
   else { i = a; j = b; k = s; }
   Cent c;
   centre(g, m, u, i, j, k, c);
-  const double r = g.rc[i], sn = g.sc[j];
+  const double ir = g.irc[i], is = g.isc[j], ir2 = ir * ir;
   double adv, dp_, dm_, ap, am, lp, lm;
   if (D == 0) {
-    adv = c.ur / (2.0 * g.dr);
-    dp_ = g.rf[i + 1] * g.rf[i + 1] / (r * r * g.dr);
-    dm_ = -g.rf[i] * g.rf[i] / (r * r * g.dr);
-    const double gg = (c.Gtt + c.Gff) / r;
-    ap = m.mu * (2.0 * c.Grr / g.dr + gg - (2.0 / 3.0) * c.tr * dp_);
-    am = m.mu * (-2.0 * c.Grr / g.dr + gg - (2.0 / 3.0) * c.tr * dm_);
-    lp = g.rf[i + 1] * g.rf[i + 1] / (r * r * g.dr * g.dr);
-    lm = g.rf[i] * g.rf[i] / (r * r * g.dr * g.dr);
+    adv = c.ur * (0.5 * g.idr);
+    dp_ = g.rf[i + 1] * g.rf[i + 1] * (ir2 * g.idr);
+    dm_ = -g.rf[i] * g.rf[i] * (ir2 * g.idr);
+    const double gg = (c.Gtt + c.Gff) * ir;
+    ap = m.mu * (2.0 * c.Grr * g.idr + gg - (2.0 / 3.0) * c.tr * dp_);
+    am = m.mu * (-2.0 * c.Grr * g.idr + gg - (2.0 / 3.0) * c.tr * dm_);
+    lp = g.rf[i + 1] * g.rf[i + 1] * (ir2 * g.idr * g.idr);
+    lm = g.rf[i] * g.rf[i] * (ir2 * g.idr * g.idr);
   } else if (D == 1) {
-    const double ct = g.cc[j] / sn;
-    adv = c.ut / (r * 2.0 * g.dt);
-    dp_ = g.sf[j + 1] / (r * sn * g.dt);
-    dm_ = -g.sf[j] / (r * sn * g.dt);
-    const double gg = c.Gff * ct / r - 0.5 * c.Srt / r;
-    ap = m.mu * (2.0 * c.Gtt / (r * g.dt) + gg - (2.0 / 3.0) * c.tr * dp_);
-    am = m.mu * (-2.0 * c.Gtt / (r * g.dt) + gg - (2.0 / 3.0) * c.tr * dm_);
-    lp = g.sf[j + 1] / (r * r * sn * g.dt * g.dt);
-    lm = g.sf[j] / (r * r * sn * g.dt * g.dt);
+    const double ct = g.ctc[j];
+    adv = c.ut * (0.5 * ir * g.idt);
+    dp_ = g.sf[j + 1] * (ir * is * g.idt);
+    dm_ = -g.sf[j] * (ir * is * g.idt);
+    const double gg = c.Gff * ct * ir - 0.5 * c.Srt * ir;
+    ap = m.mu * (2.0 * c.Gtt * (ir * g.idt) + gg - (2.0 / 3.0) * c.tr * dp_);
+    am = m.mu * (-2.0 * c.Gtt * (ir * g.idt) + gg - (2.0 / 3.0) * c.tr * dm_);
+    lp = g.sf[j + 1] * (ir2 * is * g.idt * g.idt);
+    lm = g.sf[j] * (ir2 * is * g.idt * g.idt);
   } else {
-    const double ct = g.cc[j] / sn;
-    adv = c.uf / (r * sn * 2.0 * g.dp);
-    dp_ = 1.0 / (r * sn * g.dp);
-    dm_ = -1.0 / (r * sn * g.dp);
-    const double gg = -0.5 * (c.Srf + c.Stf * ct) / r;
-    ap = m.mu * (2.0 * c.Gff / (r * sn * g.dp) + gg - (2.0 / 3.0) * c.tr * dp_);
-    am = m.mu * (-2.0 * c.Gff / (r * sn * g.dp) + gg - (2.0 / 3.0) * c.tr * dm_);
-    lp = 1.0 / (r * r * sn * sn * g.dp * g.dp);
+    const double ct = g.ctc[j];
+    adv = c.uf * (0.5 * ir * is * g.idp);
+    dp_ = ir * is * g.idp;
+    dm_ = -dp_;
+    const double gg = -0.5 * (c.Srf + c.Stf * ct) * ir;
+    ap = m.mu * (2.0 * c.Gff * dp_ + gg - (2.0 / 3.0) * c.tr * dp_);
+    am = m.mu * (-2.0 * c.Gff * dp_ + gg - (2.0 / 3.0) * c.tr * dm_);
+    lp = ir2 * is * is * g.idp * g.idp;
     lm = lp;
   }
   const bool first = !cyc && s == 0, last = !cyc && s == n - 1;
@@ -131,33 +131,34 @@ __device__ void block_row(const Geo &g, const Mat &m, const SrcOne &u, const Fie
   if (w_unknown) {
     if (D == 0) {
       const int f = i + 1;
-      const double rho = 0.5 * (rho_at(g, m, u, i, j, k) + rho_at(g, m, u, i + 1, j, k));
-      const double nu = m.mu / rho, un = u.ld(F_UR, idx_r(g, f, j, k));
-      const double rF2 = g.rf[f] * g.rf[f], d2 = g.dr * g.dr;
+      const double irho = 1.0 / (0.5 * (rho_at(g, m, u, i, j, k) + rho_at(g, m, u, i + 1, j, k)));
+      const double nu = m.mu * irho, un = u.ld(F_UR, idx_r(g, f, j, k));
+      const double irF2 = g.irf[f] * g.irf[f], d2 = g.idr * g.idr, rF2 = g.rf[f] * g.rf[f];
       const double ra2 = g.rc[i] * g.rc[i], rb2 = g.rc[i + 1] * g.rc[i + 1];
-      gp = 1.0 / (rho * g.dr);
-      cp = un / (2.0 * g.dr) - nu * rb2 / (rF2 * d2) - nu / 3.0 * g.rf[i + 2] * g.rf[i + 2] / (rb2 * d2);
-      c0 = nu * (rb2 + ra2) / (rF2 * d2) + nu / 3.0 * rF2 * (1.0 / rb2 + 1.0 / ra2) / d2;
-      cm = -un / (2.0 * g.dr) - nu * ra2 / (rF2 * d2) - nu / 3.0 * g.rf[i] * g.rf[i] / (ra2 * d2);
+      const double ira2 = g.irc[i] * g.irc[i], irb2 = g.irc[i + 1] * g.irc[i + 1];
+      gp = irho * g.idr;
+      cp = un * (0.5 * g.idr) - nu * rb2 * irF2 * d2 - nu / 3.0 * g.rf[i + 2] * g.rf[i + 2] * irb2 * d2;
+      c0 = nu * (rb2 + ra2) * irF2 * d2 + nu / 3.0 * rF2 * (irb2 + ira2) * d2;
+      cm = -un * (0.5 * g.idr) - nu * ra2 * irF2 * d2 - nu / 3.0 * g.rf[i] * g.rf[i] * ira2 * d2;
     } else if (D == 1) {
       const int f = j + 1;
-      const double rho = 0.5 * (rho_at(g, m, u, i, j, k) + rho_at(g, m, u, i, j + 1, k));
-      const double nu = m.mu / rho, un = u.ld(F_UT, idx_t(g, i, f, k));
-      const double sF = g.sf[f], r2d2 = r * r * g.dt * g.dt;
-      const double sa = g.sc[j], sb = g.sc[j + 1];
-      gp = 1.0 / (rho * r * g.dt);
-      cp = un / (2.0 * r * g.dt) - nu * sb / (r2d2 * sF) - nu / 3.0 * g.sf[j + 2] / (r2d2 * sb);
-      c0 = nu * (sb + sa) / (r2d2 * sF) + nu / 3.0 * sF * (1.0 / sb + 1.0 / sa) / r2d2;
-      cm = -un / (2.0 * r * g.dt) - nu * sa / (r2d2 * sF) - nu / 3.0 * g.sf[j] / (r2d2 * sa);
+      const double irho = 1.0 / (0.5 * (rho_at(g, m, u, i, j, k) + rho_at(g, m, u, i, j + 1, k)));
+      const double nu = m.mu * irho, un = u.ld(F_UT, idx_t(g, i, f, k));
+      const double sF = g.sf[f], isF = g.isf[f], r2d2 = ir2 * g.idt * g.idt;
+      const double sa = g.sc[j], sb = g.sc[j + 1], isa = g.isc[j], isb = g.isc[j + 1];
+      gp = irho * ir * g.idt;
+      cp = un * (0.5 * ir * g.idt) - nu * sb * r2d2 * isF - nu / 3.0 * g.sf[j + 2] * r2d2 * isb;
+      c0 = nu * (sb + sa) * r2d2 * isF + nu / 3.0 * sF * (isb + isa) * r2d2;
+      cm = -un * (0.5 * ir * g.idt) - nu * sa * r2d2 * isF - nu / 3.0 * g.sf[j] * r2d2 * isa;
     } else {
       const int f = g.periodic ? wrapk(g, k + 1) : k + 1;
-      const double rho = 0.5 * (rho_at(g, m, u, i, j, k) + rho_at(g, m, u, i, j, k + 1));
-      const double nu = m.mu / rho, un = u.ld(F_UF, idx_f(g, i, j, f));
-      const double q2 = r * r * sn * sn * g.dp * g.dp;
-      gp = 1.0 / (rho * r * sn * g.dp);
-      cp = un / (2.0 * r * sn * g.dp) - 4.0 * nu / 3.0 / q2;
-      c0 = 8.0 * nu / 3.0 / q2;
-      cm = -un / (2.0 * r * sn * g.dp) - 4.0 * nu / 3.0 / q2;
+      const double irho = 1.0 / (0.5 * (rho_at(g, m, u, i, j, k) + rho_at(g, m, u, i, j, k + 1)));
+      const double nu = m.mu * irho, un = u.ld(F_UF, idx_f(g, i, j, f));
+      const double q2 = ir2 * is * is * g.idp * g.idp;
+      gp = irho * ir * is * g.idp;
+      cp = un * (0.5 * ir * is * g.idp) - 4.0 * nu / 3.0 * q2;
+      c0 = 8.0 * nu / 3.0 * q2;
+      cm = -un * (0.5 * ir * is * g.idp) - 4.0 * nu / 3.0 * q2;
     }
     R.D[6] = -gp; R.U[6] = gp;
     R.L[8] = cm; R.D[8] = c0; R.U[8] = cp;
@@ -202,7 +203,7 @@ __device__ void scalar_row(const Geo &g, const Mat &m, const SrcOne &u, const Fi
   double ca, cb, cc_, sglo = -1.0, sghi = -1.0;
   if (D == 0) {
     const int i = s;
-    const double r = g.rc[i], r2d2 = r * r * g.dr * g.dr;
+    const double ir = g.irc[i], r2d2 = ir * ir * g.idr * g.idr;
     double ua, rho;
     if (FAM == 0) { // u_theta at theta-face (jf, k)
       const int jf = a, k = b;
@@ -220,16 +221,16 @@ __device__ void scalar_row(const Geo &g, const Mat &m, const SrcOne &u, const Fi
     }
     const double nu = m.mu / rho;
     const double fp = g.rf[i + 1] * g.rf[i + 1], fm = g.rf[i] * g.rf[i];
-    ca = -ua / (2.0 * g.dr) - nu * fm / r2d2;
-    cb = nu * (fp + fm) / r2d2;
-    cc_ = ua / (2.0 * g.dr) - nu * fp / r2d2;
+    ca = -ua * (0.5 * g.idr) - nu * fm * r2d2;
+    cb = nu * (fp + fm) * r2d2;
+    cc_ = ua * (0.5 * g.idr) - nu * fp * r2d2;
   } else if (D == 1) {
     const int j = s;
-    const double sn = g.sc[j];
-    double ua, rho, rr;
+    const double is = g.isc[j];
+    double ua, rho, irr;
     if (FAM == 0) { // u_r at r-face (fr, k)
       const int fr = a, k = b;
-      rr = g.rf[fr];
+      irr = g.irf[fr];
       ua = 0.25 * (u.ld(F_UT, idx_t(g, fr - 1, j, k)) + u.ld(F_UT, idx_t(g, fr - 1, j + 1, k)) +
                    u.ld(F_UT, idx_t(g, fr, j, k)) + u.ld(F_UT, idx_t(g, fr, j + 1, k)));
       rho = 0.5 * (rho_at(g, m, u, fr - 1, j, k) + rho_at(g, m, u, fr, j, k));
@@ -238,23 +239,23 @@ __device__ void scalar_row(const Geo &g, const Mat &m, const SrcOne &u, const Fi
       sghi = g.pole_hi ? 1.0 : -1.0;
     } else { // u_phi at phi-face (i, kf)
       const int i = a, kf = b;
-      rr = g.rc[i];
+      irr = g.irc[i];
       const int k0 = g.periodic ? wrapk(g, kf - 1) : kf - 1, k1 = g.periodic ? wrapk(g, kf) : kf;
       ua = 0.25 * (u.ld(F_UT, idx_t(g, i, j, k0)) + u.ld(F_UT, idx_t(g, i, j, k1)) +
                    u.ld(F_UT, idx_t(g, i, j + 1, k0)) + u.ld(F_UT, idx_t(g, i, j + 1, k1)));
       rho = 0.5 * (rho_at(g, m, u, i, j, k0) + rho_at(g, m, u, i, j, k1));
       xi = idx_f(g, i, j, kf); arr = rhs.uf;
     }
-    const double nu = m.mu / rho, q = rr * rr * sn * g.dt * g.dt;
-    ca = -ua / (2.0 * rr * g.dt) - nu * g.sf[j] / q;
-    cb = nu * (g.sf[j + 1] + g.sf[j]) / q;
-    cc_ = ua / (2.0 * rr * g.dt) - nu * g.sf[j + 1] / q;
+    const double nu = m.mu / rho, q = irr * irr * is * g.idt * g.idt;
+    ca = -ua * (0.5 * irr * g.idt) - nu * g.sf[j] * q;
+    cb = nu * (g.sf[j + 1] + g.sf[j]) * q;
+    cc_ = ua * (0.5 * irr * g.idt) - nu * g.sf[j + 1] * q;
   } else {
     const int k = s;
-    double ua, rho, rr, ss;
+    double ua, rho, irr, iss;
     if (FAM == 0) { // u_r at r-face (fr, j)
       const int fr = a, j = b;
-      rr = g.rf[fr]; ss = g.sc[j];
+      irr = g.irf[fr]; iss = g.isc[j];
       const int kp = g.periodic ? wrapk(g, k + 1) : k + 1;
       ua = 0.25 * (u.ld(F_UF, idx_f(g, fr - 1, j, k)) + u.ld(F_UF, idx_f(g, fr - 1, j, kp)) +
                    u.ld(F_UF, idx_f(g, fr, j, k)) + u.ld(F_UF, idx_f(g, fr, j, kp)));
@@ -262,17 +263,17 @@ __device__ void scalar_row(const Geo &g, const Mat &m, const SrcOne &u, const Fi
       xi = idx_r(g, fr, j, k); arr = rhs.ur;
     } else { // u_theta at theta-face (i, ft)
       const int i = a, ft = b;
-      rr = g.rc[i]; ss = g.sf[ft];
+      irr = g.irc[i]; iss = g.isf[ft];
       const int kp = g.periodic ? wrapk(g, k + 1) : k + 1;
       ua = 0.25 * (u.ld(F_UF, idx_f(g, i, ft - 1, k)) + u.ld(F_UF, idx_f(g, i, ft - 1, kp)) +
                    u.ld(F_UF, idx_f(g, i, ft, k)) + u.ld(F_UF, idx_f(g, i, ft, kp)));
       rho = 0.5 * (rho_at(g, m, u, i, ft - 1, k) + rho_at(g, m, u, i, ft, k));
       xi = idx_t(g, i, ft, k); arr = rhs.ut;
     }
-    const double nu = m.mu / rho, q = rr * rr * ss * ss * g.dp * g.dp;
-    ca = -ua / (2.0 * rr * ss * g.dp) - nu / q;
-    cb = 2.0 * nu / q;
-    cc_ = ua / (2.0 * rr * ss * g.dp) - nu / q;
+    const double nu = m.mu / rho, q = irr * irr * iss * iss * g.idp * g.idp;
+    ca = -ua * (0.5 * irr * iss * g.idp) - nu * q;
+    cb = 2.0 * nu * q;
+    cc_ = ua * (0.5 * irr * iss * g.idp) - nu * q;
   }
   if (!cyc && s == 0) { cb += sglo * ca; ca = 0.0; }
   if (!cyc && s == n - 1) { cb += sghi * cc_; cc_ = 0.0; }
@@ -283,28 +284,35 @@ __device__ void scalar_row(const Geo &g, const Mat &m, const SrcOne &u, const Fi
 }
 
 
+__device__ __forceinline__ double *fsel(const Fields &f, int fid) {
+  return fid == F_P ? f.p : fid == F_UR ? f.ur : fid == F_UT ? f.ut : fid == F_UF ? f.uf : f.T;
+}
+
+// store one solution value at (field, flat index) according to the sweep's
+// destination mode
+__device__ __forceinline__ void put(const Out &o, int fid, long idx, double v) {
+  if (o.mode == 0) {
+    fsel(o.x, fid)[idx] = v;
+    return;
+  }
+  const double nv = fsel(o.base, fid)[idx] + v;
+  fsel(o.x, fid)[idx] = nv;
+  if (o.ub.p) fsel(o.ub, fid)[idx] = 0.5 * (nv + fsel(o.un, fid)[idx]);
+}
+
 template <int D>
-__device__ __forceinline__ void block_store(const Geo &g, const Fields &x, int a, int b, int s,
-                                            const double *v, bool accum) {
+__device__ __forceinline__ void block_store(const Geo &g, const Out &o, int a, int b, int s,
+                                            const double *v) {
   int i, j, k;
   if (D == 0) { i = s; j = a; k = b; }
   else if (D == 1) { i = a; j = s; k = b; }
   else { i = a; j = b; k = s; }
   const long xc = idx_c(g, i, j, k);
-  long xw;
-  double *w;
-  if (D == 0) { xw = idx_r(g, i + 1, j, k); w = x.ur; }
-  else if (D == 1) { xw = idx_t(g, i, j + 1, k); w = x.ut; }
-  else { xw = idx_f(g, i, j, g.periodic ? wrapk(g, k + 1) : k + 1); w = x.uf; }
-  if (accum) {
-    x.p[xc] += v[0];
-    x.T[xc] += v[1];
-    w[xw] += v[2];
-  } else {
-    x.p[xc] = v[0];
-    x.T[xc] = v[1];
-    w[xw] = v[2];
-  }
+  put(o, F_P, xc, v[0]);
+  put(o, F_T, xc, v[1]);
+  if (D == 0) put(o, F_UR, idx_r(g, i + 1, j, k), v[2]);
+  else if (D == 1) put(o, F_UT, idx_t(g, i, j + 1, k), v[2]);
+  else put(o, F_UF, idx_f(g, i, j, g.periodic ? wrapk(g, k + 1) : k + 1), v[2]);
 }
 
 } // namespace dsw

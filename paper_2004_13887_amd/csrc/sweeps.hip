@@ -58,8 +58,8 @@ __device__ void zero_bnd(const Geo &g, const Fields &x, int a, int b) {
 
 template <int D>
 __device__ void solve_block_line(const Geo &g, const Mat &m, const SrcOne &u, const Fields &rhs,
-                                 const Fields &x, double *sc, long nl, long line, int a, int b,
-                                 int n, double hs, bool accum, int *status) {
+                                 const Out &o, double *sc, long nl, long line, int a, int b,
+                                 int n, double hs, int *status) {
   // scratch: [s][q][line], q < 12: C (9), y (3)
 #define SC(s, q) sc[((long)(s) * 12 + (q)) * nl + line]
   BRow R;
@@ -92,7 +92,7 @@ __device__ void solve_block_line(const Geo &g, const Mat &m, const SrcOne &u, co
   }
   // back substitution: x_{n-1} = y_{n-1}
   double xn[3] = {y[0], y[1], y[2]};
-  block_store<D>(g, x, a, b, n - 1, xn, accum);
+  block_store<D>(g, o, a, b, n - 1, xn);
   for (int s = n - 2; s >= 0; s--) {
 #pragma unroll
     for (int q = 0; q < 9; q++) C[q] = SC(s, q);
@@ -100,7 +100,7 @@ __device__ void solve_block_line(const Geo &g, const Mat &m, const SrcOne &u, co
     mv3(C, xn, cx);
 #pragma unroll
     for (int q = 0; q < 3; q++) xn[q] = SC(s, 9 + q) - cx[q];
-    block_store<D>(g, x, a, b, s, xn, accum);
+    block_store<D>(g, o, a, b, s, xn);
   }
 #undef SC
 }
@@ -108,8 +108,8 @@ __device__ void solve_block_line(const Geo &g, const Mat &m, const SrcOne &u, co
 // cyclic block line: bordered elimination of the last block
 template <int D>
 __device__ void solve_block_cyclic(const Geo &g, const Mat &m, const SrcOne &u, const Fields &rhs,
-                                   const Fields &x, double *sc, long nl, long line, int a, int b,
-                                   int n, double hs, bool accum, int *status) {
+                                   const Out &o, double *sc, long nl, long line, int a, int b,
+                                   int n, double hs, int *status) {
   // scratch: [s][q][line], q < 21: C (9), y (3), Z (9)
 #define SC(s, q) sc[((long)(s) * 21 + (q)) * nl + line]
   BRow R;
@@ -178,7 +178,7 @@ __device__ void solve_block_cyclic(const Geo &g, const Mat &m, const SrcOne &u, 
   for (int q = 0; q < 3; q++) t3[q] = R.b[q] - Ly[q] - Uy[q];
   inv3(Ap, Ai, status);
   mv3(Ai, t3, xl);
-  block_store<D>(g, x, a, b, n - 1, xl, accum);
+  block_store<D>(g, o, a, b, n - 1, xl);
   for (int s = 0; s < n - 1; s++) {
     double v[3];
 #pragma unroll
@@ -186,7 +186,7 @@ __device__ void solve_block_cyclic(const Geo &g, const Mat &m, const SrcOne &u, 
     mv3(Z, xl, v);
 #pragma unroll
     for (int q = 0; q < 3; q++) v[q] = SC(s, 9 + q) - v[q];
-    block_store<D>(g, x, a, b, s, v, accum);
+    block_store<D>(g, o, a, b, s, v);
   }
 #undef SC
 }
@@ -200,13 +200,13 @@ __device__ __forceinline__ long scalar_index(const Geo &g, int a, int b, int s) 
 
 template <int D, int FAM>
 __device__ void solve_scalar_line(const Geo &g, const Mat &m, const SrcOne &u, const Fields &rhs,
-                                  const Fields &x, double *sc, long nl, long line, int a, int b,
-                                  int n, int cyc, double hs, bool accum, int *status) {
-  // output array of this family
-  double *out;
-  if (D == 0) out = FAM == 0 ? x.ut : x.uf;
-  else if (D == 1) out = FAM == 0 ? x.ur : x.uf;
-  else out = FAM == 0 ? x.ur : x.ut;
+                                  const Out &o, double *sc, long nl, long line, int a, int b,
+                                  int n, int cyc, double hs, int *status) {
+  // output field of this family
+  int ofid;
+  if (D == 0) ofid = FAM == 0 ? F_UT : F_UF;
+  else if (D == 1) ofid = FAM == 0 ? F_UR : F_UF;
+  else ofid = FAM == 0 ? F_UR : F_UT;
   SRow R;
   long xi;
   double *arr;
@@ -223,11 +223,11 @@ __device__ void solve_scalar_line(const Geo &g, const Mat &m, const SrcOne &u, c
       if (s < n - 1) { SC(s, 0) = cpv; SC(s, 1) = yv; }
     }
     double xv = yv;
-    if (accum) out[xi] += xv; else out[xi] = xv;
+    put(o, ofid, xi, xv);
     for (int s = n - 2; s >= 0; s--) {
       xv = SC(s, 1) - SC(s, 0) * xv;
       const long xs = scalar_index<D, FAM>(g, a, b, s);
-      if (accum) out[xs] += xv; else out[xs] = xv;
+      put(o, ofid, xs, xv);
     }
 #undef SC
   } else {
@@ -258,11 +258,11 @@ __device__ void solve_scalar_line(const Geo &g, const Mat &m, const SrcOne &u, c
     const double den = R.b - R.a * zl - R.c * zv;
     if (!(den != 0.0)) status[ST_SINGULAR] = 1;
     const double xl = (R.r - R.a * yl - R.c * yv) / den;
-    if (accum) out[xi] += xl; else out[xi] = xl;
+    put(o, ofid, xi, xl);
     for (int s = 0; s < n - 1; s++) {
       const double xv = SC(s, 1) - SC(s, 2) * xl;
       const long xs = scalar_index<D, FAM>(g, a, b, s);
-      if (accum) out[xs] += xv; else out[xs] = xv;
+      put(o, ofid, xs, xv);
     }
 #undef SC
   }
@@ -272,8 +272,7 @@ __device__ void solve_scalar_line(const Geo &g, const Mat &m, const SrcOne &u, c
 
 template <int D>
 __global__ void __launch_bounds__(128) k_sweep(Geo g, Mat m, SrcOne u, double hs, Fields rhs,
-                                               Fields x, double *scb, double *scs, int accum,
-                                               int *status) {
+                                               Out o, double *scb, double *scs, int *status) {
   const Families F = families(g, D);
   const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
   const int nkf = g.periodic ? g.np : g.np - 1, kf0 = g.periodic ? 0 : 1;
@@ -282,9 +281,9 @@ __global__ void __launch_bounds__(128) k_sweep(Geo g, Mat m, SrcOne u, double hs
     if (D == 0) { a = (int)(t / g.np); b = (int)(t % g.np); }
     else if (D == 1) { a = (int)(t / g.np); b = (int)(t % g.np); }
     else { a = (int)(t / g.nt); b = (int)(t % g.nt); }
-    if (!accum) zero_bnd<D>(g, x, a, b);
-    if (F.cyclic) solve_block_cyclic<D>(g, m, u, rhs, x, scb, F.nb, t, a, b, F.n, hs, accum != 0, status);
-    else solve_block_line<D>(g, m, u, rhs, x, scb, F.nb, t, a, b, F.n, hs, accum != 0, status);
+    if (o.mode == 0) zero_bnd<D>(g, o.x, a, b);
+    if (F.cyclic) solve_block_cyclic<D>(g, m, u, rhs, o, scb, F.nb, t, a, b, F.n, hs, status);
+    else solve_block_line<D>(g, m, u, rhs, o, scb, F.nb, t, a, b, F.n, hs, status);
     return;
   }
   long t2 = t - F.nb;
@@ -294,7 +293,7 @@ __global__ void __launch_bounds__(128) k_sweep(Geo g, Mat m, SrcOne u, double hs
     if (D == 0) { a = 1 + (int)(t2 / g.np); b = (int)(t2 % g.np); }
     else if (D == 1) { a = 1 + (int)(t2 / g.np); b = (int)(t2 % g.np); }
     else { a = 1 + (int)(t2 / g.nt); b = (int)(t2 % g.nt); }
-    solve_scalar_line<D, 0>(g, m, u, rhs, x, scs, ns, t2, a, b, F.n, F.cyclic, hs, accum != 0, status);
+    solve_scalar_line<D, 0>(g, m, u, rhs, o, scs, ns, t2, a, b, F.n, F.cyclic, hs, status);
     return;
   }
   t2 -= F.na;
@@ -303,7 +302,7 @@ __global__ void __launch_bounds__(128) k_sweep(Geo g, Mat m, SrcOne u, double hs
     if (D == 0) { a = (int)(t2 / nkf); b = kf0 + (int)(t2 % nkf); }
     else if (D == 1) { a = (int)(t2 / nkf); b = kf0 + (int)(t2 % nkf); }
     else { a = (int)(t2 / (g.nt - 1)); b = 1 + (int)(t2 % (g.nt - 1)); }
-    solve_scalar_line<D, 1>(g, m, u, rhs, x, scs, ns, F.na + t2, a, b, F.n, F.cyclic, hs, accum != 0, status);
+    solve_scalar_line<D, 1>(g, m, u, rhs, o, scs, ns, F.na + t2, a, b, F.n, F.cyclic, hs, status);
   }
 }
 
@@ -321,8 +320,8 @@ void sweep_scratch_size(const Geo &g, long *blk, long *sca) {
 }
 
 void launch_sweep(int d, const Geo &g, const Mat &m, const Fields &Ub, double tau,
-                  const Fields &rhs, const Fields &x, const Scratch &sc, int *status,
-                  hipStream_t st, bool accum) {
+                  const Fields &rhs, const Out &o, const Scratch &sc, int *status,
+                  hipStream_t st) {
   SrcOne u;
   u.a[F_P] = Ub.p; u.a[F_UR] = Ub.ur; u.a[F_UT] = Ub.ut; u.a[F_UF] = Ub.uf; u.a[F_T] = Ub.T;
   const Families F = families(g, d);
@@ -330,10 +329,44 @@ void launch_sweep(int d, const Geo &g, const Mat &m, const Fields &Ub, double ta
   const int bs = 128;
   dim3 grid((unsigned)((nt + bs - 1) / bs));
   const double hs = 0.5 * tau;
-  if (d == 0) hipLaunchKernelGGL(k_sweep<0>, grid, dim3(bs), 0, st, g, m, u, hs, rhs, x, sc.blk, sc.sca, accum ? 1 : 0, status);
-  else if (d == 1) hipLaunchKernelGGL(k_sweep<1>, grid, dim3(bs), 0, st, g, m, u, hs, rhs, x, sc.blk, sc.sca, accum ? 1 : 0, status);
-  else if (phi_part_supported(g)) launch_phi_part(g, m, Ub, tau, rhs, x, status, st, accum);
-  else hipLaunchKernelGGL(k_sweep<2>, grid, dim3(bs), 0, st, g, m, u, hs, rhs, x, sc.blk, sc.sca, accum ? 1 : 0, status);
+  if (d == 0) hipLaunchKernelGGL(k_sweep<0>, grid, dim3(bs), 0, st, g, m, u, hs, rhs, o, sc.blk, sc.sca, status);
+  else if (d == 1) hipLaunchKernelGGL(k_sweep<1>, grid, dim3(bs), 0, st, g, m, u, hs, rhs, o, sc.blk, sc.sca, status);
+  else if (phi_part_supported(g)) launch_phi_part(g, m, Ub, tau, rhs, o, status, st);
+  else hipLaunchKernelGGL(k_sweep<2>, grid, dim3(bs), 0, st, g, m, u, hs, rhs, o, sc.blk, sc.sca, status);
+}
+
+// boundary-normal faces: u_r on r = r1, r2; u_theta on the theta boundaries;
+// u_phi on the phi walls (sector only)
+__global__ void k_bnd_copy(Geo g, Fields src, Fields d0, Fields d1, Fields d2) {
+  const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long nr_ = (long)g.nt * g.np, nt_ = (long)g.nr * g.np, nf_ = g.periodic ? 0 : (long)g.nr * g.nt;
+  long idx;
+  int fid;
+  if (t < 2 * nr_) {
+    const long q = t % nr_;
+    idx = idx_r(g, t < nr_ ? 0 : g.nr, (int)(q / g.np), (int)(q % g.np));
+    fid = F_UR;
+  } else if (t < 2 * nr_ + 2 * nt_) {
+    const long u = t - 2 * nr_, q = u % nt_;
+    idx = idx_t(g, (int)(q / g.np), u < nt_ ? 0 : g.nt, (int)(q % g.np));
+    fid = F_UT;
+  } else if (t < 2 * nr_ + 2 * nt_ + 2 * nf_) {
+    const long u = t - 2 * nr_ - 2 * nt_, q = u % nf_;
+    idx = idx_f(g, (int)(q / g.nt), (int)(q % g.nt), u < nf_ ? 0 : g.np);
+    fid = F_UF;
+  } else {
+    return;
+  }
+  const double v = fsel(src, fid)[idx];
+  if (d0.p) fsel(d0, fid)[idx] = v;
+  if (d1.p) fsel(d1, fid)[idx] = v;
+  if (d2.p) fsel(d2, fid)[idx] = v;
+}
+
+void launch_bnd_copy(const Geo &g, const Fields &src, const Fields &d0, const Fields &d1,
+                     const Fields &d2, hipStream_t st) {
+  const long n = 2L * g.nt * g.np + 2L * g.nr * g.np + (g.periodic ? 0 : 2L * g.nr * g.nt);
+  hipLaunchKernelGGL(k_bnd_copy, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, g, src, d0, d1, d2);
 }
 
 } // namespace dsw

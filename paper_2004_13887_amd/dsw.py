@@ -25,7 +25,7 @@ _NAMES = {DSW_EINVAL: "DSW_EINVAL", DSW_ENOMEM: "DSW_ENOMEM", DSW_EHIP: "DSW_EHI
 SYMBOLS = ("dsw_init_grid", "dsw_free_grid", "dsw_layout", "dsw_residual", "dsw_line_solve_r",
            "dsw_line_solve_theta", "dsw_line_solve_phi", "dsw_split_step", "dsw_set_timing",
            "dsw_read_timing", "dsw_get_status", "dsw_last_error")
-TIMING_KINDS = ("residual", "sweep_r", "sweep_theta", "sweep_phi_update", "state_copy")
+TIMING_KINDS = ("residual", "sweep_r", "sweep_theta", "sweep_phi_update", "boundary_copy")
 
 
 class DswError(RuntimeError):
