@@ -34,7 +34,13 @@
  * periodic (cyclic) lines by bordered elimination of the last block.
  *
  * Discrete conventions (the paper says only "standard central differences on
- * the MAC stencil"): see the tables in the design doc of this repository.
+ * the MAC stencil"): compact flux-form divergence at centres; face gradients
+ * of centre scalars; centre-averaged velocities for advection of centre
+ * scalars and 4-point averages for the transverse advecting velocity at a
+ * face; conservative 3-point second differences with metric factors at the
+ * half points; face 1/rho from the mean of the two centre densities; velocity
+ * gradient at centres with compact diagonal and 4-point-averaged off-diagonal
+ * entries; grad-div at a face from the two adjacent centre divergences.
  * Build: gcc -O2 -fopenmp -ffp-contract=off (no contraction, no fast-math).
  */
 #include <math.h>
