@@ -137,6 +137,63 @@ int dsw_set_timing(dsw_grid *grid, int32_t enable);
 int dsw_read_timing(dsw_grid *grid, void *stream, double ms[DSW_TIMING_KINDS],
                     int64_t launches[DSW_TIMING_KINDS]);
 
+/* Launch shapes of a grid's kernels (the tunable parameters; they change
+ * speed, and for the phi sweep the order of rounding, never the method):
+ *   residual_block        threads per workgroup of the residual (64, 128, 256)
+ *   sweep_block_r/_theta  lines per workgroup of the r / theta sweeps
+ *                         (64, 128, 256; one thread per line)
+ *   phi_rows_per_thread   phi sweep: 2 or 4 = partitioned solver, one
+ *                         workgroup per line, that many rows per thread,
+ *                         separators by cyclic reduction in LDS; 0 = one
+ *                         thread per line.  Lines the partitioned solver
+ *                         cannot take (more than 256 chunks, or a cyclic line
+ *                         whose chunk count is not a power of two) fall back
+ *                         to one thread per line.
+ * Default {64, 128, 128, 4}.  dsw_set_config returns DSW_EINVAL for other
+ * values. */
+typedef struct {
+  int32_t residual_block, sweep_block_r, sweep_block_theta, phi_rows_per_thread;
+} dsw_config;
+int dsw_set_config(dsw_grid *grid, const dsw_config *cfg);
+int dsw_get_config(const dsw_grid *grid, dsw_config *cfg);
+
+/* Ensembles: n independent grids (uneven sizes allowed) stepped together.
+ * Each member is a full grid handle with its own workspace; a step of the
+ * ensemble computes exactly what dsw_split_step computes for every member
+ * (paper section 2.2, eqs. (spl1)-(spl3) iterated K times), with one launch
+ * per pass covering all members (workgroups mapped to members by a table of
+ * offsets) instead of one launch per member and pass, and the whole step
+ * captured once in a HIP graph and replayed.
+ *
+ * dsw_ensemble_create: descs and mats are arrays of n (n >= 1).
+ * dsw_ensemble_member: borrowed handle of member m (valid until the ensemble
+ *   is freed; do not free it); use it for dsw_layout or single-grid calls.
+ * dsw_ensemble_step: Un, Unp1 and tau are arrays of n; member m steps
+ *   Un[m] -> Unp1[m] with tau[m] (same rules as dsw_split_step).  The first
+ *   call with a given set of pointers, steps and K builds and captures the
+ *   graph (a few ms); later calls replay it.  At most 8 such graphs are
+ *   kept (the oldest is dropped, after a device synchronisation).
+ * dsw_ensemble_tune: an autotuner.  It runs the batched step directly (no
+ *   graph) under candidate launch shapes, `reps` timed steps each, times every
+ *   pass with HIP events, and keeps for each pass the fastest shape.  The
+ *   result becomes the configuration of the ensemble and of every member
+ *   (so that per-member dsw_split_step calls compute the same numbers) and
+ *   is stored in *best if best is non-NULL.  Unp1 is overwritten.
+ *   Synchronises the stream.
+ * dsw_ensemble_get_status: dsw_get_status over all members (first error). */
+typedef struct dsw_ensemble dsw_ensemble;
+int dsw_ensemble_create(const dsw_grid_desc *descs, const dsw_material *mats, int32_t n,
+                        dsw_ensemble **out);
+int dsw_ensemble_free(dsw_ensemble *ens);
+int dsw_ensemble_member(dsw_ensemble *ens, int32_t m, dsw_grid **grid);
+int dsw_ensemble_step(dsw_ensemble *ens, const dsw_fields *Un, dsw_fields *Unp1, const double *tau,
+                      int32_t K, void *stream);
+int dsw_ensemble_tune(dsw_ensemble *ens, const dsw_fields *Un, dsw_fields *Unp1, const double *tau,
+                      int32_t K, int32_t reps, void *stream, dsw_config *best);
+int dsw_ensemble_set_config(dsw_ensemble *ens, const dsw_config *cfg);
+int dsw_ensemble_get_config(const dsw_ensemble *ens, dsw_config *cfg);
+int dsw_ensemble_get_status(dsw_ensemble *ens, void *stream);
+
 /* Synchronise the stream, read and clear the device status word.  Returns
  * DSW_OK, DSW_ENONPHYS or DSW_ESINGULAR (or DSW_EHIP). */
 int dsw_get_status(dsw_grid *grid, void *stream);

@@ -2,6 +2,7 @@
 // descriptor validation, metric tables, workspace and the orchestration of
 // one split time step (paper section 2.2: K iterations of residual + three
 // sweeps on one HIP stream; eqs. (spl1)-(spl3)).
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -19,6 +20,7 @@ struct dsw_grid {
   dsw_material mat;
   Geo geo;
   Mat m;
+  Cfg cfg{64, {128, 128}, 4}; // launch shapes
   double *tables = nullptr; // rc | rf | sc | cc | sf | cf
   Fields ub{}, ub2{}, r{}, x1{}, x2{}; // ub, ub2: midpoint states of consecutive iterations
   double *fields_mem = nullptr;
@@ -264,6 +266,133 @@ extern "C" int dsw_residual(dsw_grid *G, const dsw_fields *Un, const dsw_fields 
   return check_launch("residual kernel");
 }
 
+// ------------------------------------------------------------- passes --
+
+static SrcOne src1(const Fields &f) {
+  SrcOne u;
+  u.a[F_P] = f.p; u.a[F_UR] = f.ur; u.a[F_UT] = f.ut; u.a[F_UF] = f.uf; u.a[F_T] = f.T;
+  return u;
+}
+
+static Diff diff(const Fields &n, const Fields &k) {
+  Diff d;
+  const double *nn[5] = {n.p, n.ur, n.ut, n.uf, n.T}, *kk[5] = {k.p, k.ur, k.ut, k.uf, k.T};
+  for (int q = 0; q < 5; q++) { d.n[q] = nn[q]; d.k[q] = kk[q]; }
+  d.same = (n.p == k.p) ? 1 : 0;
+  return d;
+}
+
+static PassArgs base_args(const dsw_grid *G) {
+  PassArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.g = G->geo;
+  a.m = G->m;
+  a.scb = G->sc.blk;
+  a.scs = G->sc.sca;
+  a.status = G->status;
+  return a;
+}
+
+// one pass of a plan: kernel kind, timing kind, arguments
+struct Pass {
+  int kind, tk;
+  PassArgs a;
+};
+
+static Pass sweep_pass(const dsw_grid *G, int d, const Fields &ubar, double tau, const Fields &rhs,
+                       const Out &o) {
+  Pass p;
+  p.kind = d == 0 ? PK_SW0 : d == 1 ? PK_SW1 : phi_kind(G->geo, G->cfg);
+  p.tk = 1 + d;
+  p.a = base_args(G);
+  p.a.u = src1(ubar);
+  p.a.tau = 0.5 * tau;
+  p.a.rhs = rhs;
+  p.a.o = o;
+  return p;
+}
+
+// the passes of one split step, in stream order (paper section 2.2: K
+// iterations of eqs. (spl1)-(spl3) after the residual)
+static void plan_step(const dsw_grid *G, const Fields &un, const Fields &uk, double tau, int K,
+                      std::vector<Pass> &out) {
+  const Fields none{};
+  {
+    // Dirichlet data of U^{n+1} and of both midpoint buffers = those of U^n
+    Pass p{PK_BND, 4, base_args(G)};
+    p.a.src = un; p.a.d0 = uk; p.a.d1 = G->ub; p.a.d2 = G->ub2;
+    out.push_back(p);
+  }
+  const Fields ubuf[2] = {G->ub, G->ub2};
+  for (int it = 0; it < K; it++) {
+    // midpoint state of this iteration: U^n itself at the first one, else the
+    // one written by the previous iteration's phi sweep
+    const Fields ubar = it == 0 ? un : ubuf[(it - 1) % 2];
+    Pass r{PK_RES, 0, base_args(G)};
+    r.a.u = src1(ubar);
+    r.a.d = diff(un, it == 0 ? un : uk);
+    r.a.tau = tau;
+    r.a.R = G->r;
+    out.push_back(r);
+    Out o1{}, o2{}, o3{};
+    o1.x = G->x1; o1.mode = 0;
+    o2.x = G->x2; o2.mode = 0;
+    o3.x = uk; o3.base = it == 0 ? un : uk; o3.un = un;
+    o3.ub = it < K - 1 ? ubuf[it % 2] : none;
+    o3.mode = 1;
+    out.push_back(sweep_pass(G, 0, ubar, tau, G->r, o1));
+    out.push_back(sweep_pass(G, 1, ubar, tau, G->x1, o2));
+    out.push_back(sweep_pass(G, 2, ubar, tau, G->x2, o3));
+  }
+}
+
+static unsigned kind_threads(int kind, const Geo &g, const Cfg &c) {
+  switch (kind) {
+  case PK_RES: return (unsigned)c.res_bs;
+  case PK_SW0: return (unsigned)c.sweep_bs[0];
+  case PK_SW1: return (unsigned)c.sweep_bs[1];
+  case PK_SW2_PART: return phi_part_threads(g, c.phi_pm);
+  default: return 128u; // boundary copy, thread-per-line phi
+  }
+}
+
+static unsigned cdiv(unsigned long a, unsigned b) { return (unsigned)((a + b - 1) / b); }
+
+static unsigned kind_blocks(int kind, const Geo &g, unsigned threads) {
+  switch (kind) {
+  case PK_BND: return cdiv(bnd_points(g), threads);
+  case PK_RES: return cdiv((unsigned long)g.npf, threads) * (unsigned)(g.nt + 1) * (unsigned)(g.nr + 1);
+  case PK_SW0: return cdiv(sweep_lines(g, 0), threads);
+  case PK_SW1: return cdiv(sweep_lines(g, 1), threads);
+  case PK_SW2_LINE: return cdiv(sweep_lines(g, 2), threads);
+  default: return (unsigned)g.nr * (unsigned)g.nt; // PK_SW2_PART
+  }
+}
+
+static size_t kind_lds(int kind, const Geo &g, const Cfg &c) {
+  return kind == PK_SW2_PART ? phi_part_lds(g, c.phi_pm) : 0;
+}
+
+static void launch_kind(int kind, const Cfg &c, const PassArgs &a, const Batch &b, unsigned blocks,
+                        unsigned threads, size_t lds, hipStream_t st) {
+  switch (kind) {
+  case PK_BND: launch_bnd_pass(a, b, blocks, threads, st); break;
+  case PK_RES: launch_residual_pass(a, b, blocks, threads, st); break;
+  case PK_SW0: launch_sweep_pass(0, a, b, blocks, threads, st); break;
+  case PK_SW1: launch_sweep_pass(1, a, b, blocks, threads, st); break;
+  case PK_SW2_LINE: launch_sweep_pass(2, a, b, blocks, threads, st); break;
+  default: launch_phi_pass(c.phi_pm, a, b, blocks, threads, lds, st); break;
+  }
+}
+
+// one pass on one grid, arguments by value
+static void launch_single(const dsw_grid *G, const Pass &p, hipStream_t st) {
+  const unsigned th = kind_threads(p.kind, G->geo, G->cfg);
+  const Batch none{nullptr, nullptr, 0};
+  launch_kind(p.kind, G->cfg, p.a, none, kind_blocks(p.kind, G->geo, th), th,
+              kind_lds(p.kind, G->geo, G->cfg), st);
+}
+
 static int line_solve(int d, dsw_grid *G, const dsw_fields *Ubar, double tau, const dsw_fields *rhs,
                       dsw_fields *x, void *stream) {
   if (!G) return fail(DSW_EINVAL, "null handle");
@@ -276,7 +405,7 @@ static int line_solve(int d, dsw_grid *G, const dsw_fields *Ubar, double tau, co
   Out o{};
   o.x = F(x);
   o.mode = 0;
-  launch_sweep(d, G->geo, G->m, F(Ubar), tau, F(rhs), o, G->sc, G->status, (hipStream_t)stream);
+  launch_single(G, sweep_pass(G, d, F(Ubar), tau, F(rhs), o), (hipStream_t)stream);
   return check_launch("sweep kernel");
 }
 
@@ -293,9 +422,7 @@ extern "C" int dsw_line_solve_phi(dsw_grid *G, const dsw_fields *Ubar, double ta
   return line_solve(2, G, Ubar, tau, rhs, x, stream);
 }
 
-extern "C" int dsw_split_step(dsw_grid *G, const dsw_fields *Un, dsw_fields *Unp1, double tau,
-                              int32_t K, void *stream) {
-  if (!G) return fail(DSW_EINVAL, "null handle");
+static int check_step_args(const dsw_fields *Un, const dsw_fields *Unp1, double tau, int32_t K) {
   int rc;
   if ((rc = check_fields(Un, "Un")) || (rc = check_fields(Unp1, "Unp1"))) return rc;
   if (!(tau > 0.0)) return fail(DSW_EINVAL, "tau must be > 0");
@@ -303,30 +430,56 @@ extern "C" int dsw_split_step(dsw_grid *G, const dsw_fields *Un, dsw_fields *Unp
   if (Un->p == Unp1->p || Un->ur == Unp1->ur || Un->ut == Unp1->ut || Un->uf == Unp1->uf ||
       Un->T == Unp1->T)
     return fail(DSW_EINVAL, "Unp1 must not alias Un");
+  return DSW_OK;
+}
+
+extern "C" int dsw_split_step(dsw_grid *G, const dsw_fields *Un, dsw_fields *Unp1, double tau,
+                              int32_t K, void *stream) {
+  if (!G) return fail(DSW_EINVAL, "null handle");
+  const int rc = check_step_args(Un, Unp1, tau, K);
+  if (rc) return rc;
   hipStream_t st = (hipStream_t)stream;
-  const Fields un = F(Un), uk = F(Unp1);
-  const Fields none{};
-  // Dirichlet data of U^{n+1} and of both midpoint buffers = those of U^n
-  timed(G, 4, st, [&] { launch_bnd_copy(G->geo, un, uk, G->ub, G->ub2, st); });
-  const Fields ubuf[2] = {G->ub, G->ub2};
-  for (int it = 0; it < K; it++) {
-    // midpoint state of this iteration: U^n itself at the first one, else the
-    // one written by the previous iteration's phi sweep
-    const Fields ubar = it == 0 ? un : ubuf[(it - 1) % 2];
-    timed(G, 0, st, [&] {
-      launch_residual_given_mid(G->geo, G->m, un, it == 0 ? un : uk, ubar, tau, G->r, G->status, st);
-    });
-    Out o1{}, o2{}, o3{};
-    o1.x = G->x1; o1.mode = 0;
-    o2.x = G->x2; o2.mode = 0;
-    o3.x = uk; o3.base = it == 0 ? un : uk; o3.un = un;
-    o3.ub = it < K - 1 ? ubuf[it % 2] : none;
-    o3.mode = 1;
-    timed(G, 1, st, [&] { launch_sweep(0, G->geo, G->m, ubar, tau, G->r, o1, G->sc, G->status, st); });
-    timed(G, 2, st, [&] { launch_sweep(1, G->geo, G->m, ubar, tau, G->x1, o2, G->sc, G->status, st); });
-    timed(G, 3, st, [&] { launch_sweep(2, G->geo, G->m, ubar, tau, G->x2, o3, G->sc, G->status, st); });
-  }
+  std::vector<Pass> plan;
+  plan_step(G, F(Un), F(Unp1), tau, K, plan);
+  for (const Pass &p : plan) timed(G, p.tk, st, [&] { launch_single(G, p, st); });
   return check_launch("split step kernels");
+}
+
+static int check_cfg(const dsw_config *c) {
+  if (!c) return fail(DSW_EINVAL, "null config");
+  auto bs_ok = [](int v) { return v == 64 || v == 128 || v == 256; };
+  if (!bs_ok(c->residual_block) || !bs_ok(c->sweep_block_r) || !bs_ok(c->sweep_block_theta))
+    return fail(DSW_EINVAL, "block sizes must be 64, 128 or 256");
+  if (c->phi_rows_per_thread != 0 && c->phi_rows_per_thread != 2 && c->phi_rows_per_thread != 4)
+    return fail(DSW_EINVAL, "phi_rows_per_thread must be 0, 2 or 4");
+  return DSW_OK;
+}
+
+static Cfg to_cfg(const dsw_config *c) {
+  return Cfg{c->residual_block, {c->sweep_block_r, c->sweep_block_theta}, c->phi_rows_per_thread};
+}
+
+static dsw_config from_cfg(const Cfg &c) {
+  dsw_config o;
+  o.residual_block = c.res_bs;
+  o.sweep_block_r = c.sweep_bs[0];
+  o.sweep_block_theta = c.sweep_bs[1];
+  o.phi_rows_per_thread = c.phi_pm;
+  return o;
+}
+
+extern "C" int dsw_set_config(dsw_grid *G, const dsw_config *cfg) {
+  if (!G) return fail(DSW_EINVAL, "null handle");
+  const int rc = check_cfg(cfg);
+  if (rc) return rc;
+  G->cfg = to_cfg(cfg);
+  return DSW_OK;
+}
+
+extern "C" int dsw_get_config(const dsw_grid *G, dsw_config *cfg) {
+  if (!G || !cfg) return fail(DSW_EINVAL, "null argument");
+  *cfg = from_cfg(G->cfg);
+  return DSW_OK;
 }
 
 extern "C" int dsw_set_timing(dsw_grid *G, int32_t enable) {
@@ -360,5 +513,319 @@ extern "C" int dsw_get_status(dsw_grid *G, void *stream) {
   HIPCHK(hipMemset(G->status, 0, sizeof(h)));
   if (h[ST_NONPHYS]) return fail(DSW_ENONPHYS, "non-positive temperature or pressure met");
   if (h[ST_SINGULAR]) return fail(DSW_ESINGULAR, "zero pivot in a line solve");
+  return DSW_OK;
+}
+
+// ------------------------------------------------------------- ensembles --
+
+struct dsw_ensemble {
+  std::vector<dsw_grid *> mem;
+  Cfg cfg{64, {128, 128}, 4};
+  hipStream_t cap = nullptr; // capture stream
+  // one launch of a batched plan
+  struct Group {
+    int kind, tk;
+    unsigned blocks, threads;
+    size_t lds;
+    size_t tab_off, woff_off; // byte offsets into the plan's device buffer
+    int n;
+  };
+  struct Plan {
+    std::vector<Group> groups;
+    char *dev = nullptr;
+  };
+  struct Entry {
+    std::vector<uint64_t> key;
+    Plan plan;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    uint64_t used = 0;
+  };
+  std::vector<Entry> cache;
+  uint64_t tick = 0;
+};
+
+static void free_plan(dsw_ensemble::Plan &p) {
+  if (p.dev) (void)hipFree(p.dev);
+  p.dev = nullptr;
+  p.groups.clear();
+}
+
+static void drop_entry(dsw_ensemble::Entry &e) {
+  if (e.exec) (void)hipGraphExecDestroy(e.exec);
+  if (e.graph) (void)hipGraphDestroy(e.graph);
+  e.exec = nullptr;
+  e.graph = nullptr;
+  free_plan(e.plan);
+}
+
+extern "C" int dsw_ensemble_create(const dsw_grid_desc *descs, const dsw_material *mats, int32_t n,
+                                   dsw_ensemble **out) {
+  if (!out) return fail(DSW_EINVAL, "null output handle");
+  *out = nullptr;
+  if (!descs || !mats || n < 1) return fail(DSW_EINVAL, "need n >= 1 descriptors and materials");
+  dsw_ensemble *E = new dsw_ensemble();
+  for (int m = 0; m < n; m++) {
+    dsw_grid *G = nullptr;
+    const int rc = dsw_init_grid(&descs[m], &mats[m], &G);
+    if (rc) {
+      const std::string msg = "member " + std::to_string(m) + ": " + g_err;
+      dsw_ensemble_free(E);
+      return fail(rc, msg);
+    }
+    E->mem.push_back(G);
+  }
+  if (hipStreamCreateWithFlags(&E->cap, hipStreamNonBlocking) != hipSuccess) {
+    dsw_ensemble_free(E);
+    return fail(DSW_EHIP, "capture stream");
+  }
+  *out = E;
+  return DSW_OK;
+}
+
+extern "C" int dsw_ensemble_free(dsw_ensemble *E) {
+  if (!E) return DSW_OK;
+  (void)hipDeviceSynchronize();
+  for (auto &e : E->cache) drop_entry(e);
+  if (E->cap) (void)hipStreamDestroy(E->cap);
+  for (dsw_grid *G : E->mem) dsw_free_grid(G);
+  delete E;
+  return DSW_OK;
+}
+
+extern "C" int dsw_ensemble_member(dsw_ensemble *E, int32_t m, dsw_grid **grid) {
+  if (!E || !grid) return fail(DSW_EINVAL, "null argument");
+  if (m < 0 || m >= (int)E->mem.size()) return fail(DSW_EINVAL, "member index out of range");
+  *grid = E->mem[m];
+  return DSW_OK;
+}
+
+static int check_ens_args(dsw_ensemble *E, const dsw_fields *Un, dsw_fields *Unp1, const double *tau,
+                          int32_t K) {
+  if (!E || !Un || !Unp1 || !tau) return fail(DSW_EINVAL, "null argument");
+  for (size_t m = 0; m < E->mem.size(); m++) {
+    const int rc = check_step_args(&Un[m], &Unp1[m], tau[m], K);
+    if (rc) return fail(rc, "member " + std::to_string(m) + ": " + g_err);
+  }
+  for (size_t m = 0; m < E->mem.size(); m++) // outputs of different members must be distinct
+    for (size_t q = 0; q < E->mem.size(); q++)
+      if (q != m && (Unp1[m].p == Unp1[q].p || Unp1[m].p == Un[q].p))
+        return fail(DSW_EINVAL, "member " + std::to_string(m) + ": Unp1 aliases another member's state");
+  return DSW_OK;
+}
+
+// Batched plan of one ensemble step: pass q of every member's plan goes into
+// one launch (two for the phi pass when members differ in solver kind).
+static int build_plan(dsw_ensemble *E, const Cfg &cfg, const dsw_fields *Un, dsw_fields *Unp1,
+                      const double *tau, int K, dsw_ensemble::Plan &plan) {
+  const int n = (int)E->mem.size();
+  std::vector<std::vector<Pass>> per(n);
+  for (int m = 0; m < n; m++) {
+    dsw_grid *G = E->mem[m];
+    const Cfg keep = G->cfg;
+    G->cfg = cfg;
+    plan_step(G, F(&Un[m]), F(&Unp1[m]), tau[m], K, per[m]);
+    G->cfg = keep;
+  }
+  const size_t npass = per[0].size();
+  std::vector<char> host;
+  auto append = [&](const void *src, size_t bytes) {
+    size_t off = (host.size() + 255) & ~size_t(255);
+    host.resize(off + bytes);
+    std::memcpy(host.data() + off, src, bytes);
+    return off;
+  };
+  for (size_t q = 0; q < npass; q++) {
+    const int kinds[2] = {per[0][q].kind == PK_SW2_PART || per[0][q].kind == PK_SW2_LINE ? PK_SW2_PART
+                                                                                         : per[0][q].kind,
+                          PK_SW2_LINE};
+    const int nk = (kinds[0] == PK_SW2_PART) ? 2 : 1;
+    for (int v = 0; v < nk; v++) {
+      const int kind = kinds[v];
+      std::vector<int> who;
+      for (int m = 0; m < n; m++)
+        if (per[m][q].kind == kind) who.push_back(m);
+      if (who.empty()) continue;
+      unsigned th = 0;
+      size_t lds = 0;
+      for (int m : who) {
+        th = std::max(th, kind_threads(kind, E->mem[m]->geo, cfg));
+        lds = std::max(lds, kind_lds(kind, E->mem[m]->geo, cfg));
+      }
+      std::vector<PassArgs> tab;
+      std::vector<unsigned> woff(1, 0u);
+      unsigned long total = 0;
+      for (int m : who) {
+        tab.push_back(per[m][q].a);
+        total += kind_blocks(kind, E->mem[m]->geo, th);
+        if (total > 0x7fffffffUL) return fail(DSW_EINVAL, "ensemble too large for one launch");
+        woff.push_back((unsigned)total);
+      }
+      dsw_ensemble::Group gr;
+      gr.kind = kind;
+      gr.tk = per[0][q].tk;
+      gr.blocks = (unsigned)total;
+      gr.threads = th;
+      gr.lds = lds;
+      gr.n = (int)who.size();
+      gr.tab_off = append(tab.data(), tab.size() * sizeof(PassArgs));
+      gr.woff_off = append(woff.data(), woff.size() * sizeof(unsigned));
+      plan.groups.push_back(gr);
+    }
+  }
+  if (hipMalloc(&plan.dev, host.size()) != hipSuccess) {
+    plan.dev = nullptr;
+    return fail(DSW_ENOMEM, "ensemble launch tables");
+  }
+  HIPCHK(hipMemcpy(plan.dev, host.data(), host.size(), hipMemcpyHostToDevice));
+  return DSW_OK;
+}
+
+// enqueue a batched plan; ev (optional) receives one event pair per group
+static void enqueue_plan(const dsw_ensemble::Plan &plan, const Cfg &cfg, hipStream_t st,
+                         std::vector<std::pair<hipEvent_t, hipEvent_t>> *ev) {
+  PassArgs dummy;
+  std::memset(&dummy, 0, sizeof(dummy));
+  for (size_t q = 0; q < plan.groups.size(); q++) {
+    const auto &gr = plan.groups[q];
+    const Batch b{(const PassArgs *)(plan.dev + gr.tab_off), (const unsigned *)(plan.dev + gr.woff_off),
+                  gr.n};
+    if (ev) (void)hipEventRecord((*ev)[q].first, st);
+    launch_kind(gr.kind, cfg, dummy, b, gr.blocks, gr.threads, gr.lds, st);
+    if (ev) (void)hipEventRecord((*ev)[q].second, st);
+  }
+}
+
+static std::vector<uint64_t> plan_key(const dsw_ensemble *E, const Cfg &cfg, const dsw_fields *Un,
+                                      const dsw_fields *Unp1, const double *tau, int K) {
+  std::vector<uint64_t> k;
+  k.push_back((uint64_t)K);
+  k.push_back((uint64_t)cfg.res_bs | ((uint64_t)cfg.sweep_bs[0] << 16) |
+              ((uint64_t)cfg.sweep_bs[1] << 32) | ((uint64_t)cfg.phi_pm << 48));
+  for (size_t m = 0; m < E->mem.size(); m++) {
+    const double *pu[10] = {Un[m].p, Un[m].ur, Un[m].ut, Un[m].uf, Un[m].T,
+                            Unp1[m].p, Unp1[m].ur, Unp1[m].ut, Unp1[m].uf, Unp1[m].T};
+    for (int q = 0; q < 10; q++) k.push_back((uint64_t)(uintptr_t)pu[q]);
+    uint64_t tb;
+    std::memcpy(&tb, &tau[m], sizeof(tb));
+    k.push_back(tb);
+  }
+  return k;
+}
+
+extern "C" int dsw_ensemble_step(dsw_ensemble *E, const dsw_fields *Un, dsw_fields *Unp1,
+                                 const double *tau, int32_t K, void *stream) {
+  int rc = check_ens_args(E, Un, Unp1, tau, K);
+  if (rc) return rc;
+  hipStream_t st = (hipStream_t)stream;
+  const std::vector<uint64_t> key = plan_key(E, E->cfg, Un, Unp1, tau, K);
+  dsw_ensemble::Entry *hit = nullptr;
+  for (auto &e : E->cache)
+    if (e.exec && e.key == key) hit = &e;
+  if (!hit) {
+    if (E->cache.size() >= 8) { // drop the least recently used graph
+      size_t old = 0;
+      for (size_t q = 1; q < E->cache.size(); q++)
+        if (E->cache[q].used < E->cache[old].used) old = q;
+      HIPCHK(hipDeviceSynchronize());
+      drop_entry(E->cache[old]);
+      E->cache.erase(E->cache.begin() + old);
+    }
+    dsw_ensemble::Entry e;
+    e.key = key;
+    if ((rc = build_plan(E, E->cfg, Un, Unp1, tau, K, e.plan))) return rc;
+    HIPCHK(hipStreamBeginCapture(E->cap, hipStreamCaptureModeThreadLocal));
+    enqueue_plan(e.plan, E->cfg, E->cap, nullptr);
+    const hipError_t ce = hipStreamEndCapture(E->cap, &e.graph);
+    if (ce != hipSuccess) {
+      drop_entry(e);
+      return fail(DSW_EHIP, std::string("graph capture: ") + hipGetErrorString(ce));
+    }
+    const hipError_t ie = hipGraphInstantiate(&e.exec, e.graph, nullptr, nullptr, 0);
+    if (ie != hipSuccess) {
+      drop_entry(e);
+      return fail(DSW_EHIP, std::string("graph instantiate: ") + hipGetErrorString(ie));
+    }
+    E->cache.push_back(e);
+    hit = &E->cache.back();
+  }
+  hit->used = ++E->tick;
+  HIPCHK(hipGraphLaunch(hit->exec, st));
+  return DSW_OK;
+}
+
+extern "C" int dsw_ensemble_set_config(dsw_ensemble *E, const dsw_config *cfg) {
+  if (!E) return fail(DSW_EINVAL, "null handle");
+  const int rc = check_cfg(cfg);
+  if (rc) return rc;
+  E->cfg = to_cfg(cfg);
+  for (dsw_grid *G : E->mem) G->cfg = E->cfg;
+  return DSW_OK;
+}
+
+extern "C" int dsw_ensemble_get_config(const dsw_ensemble *E, dsw_config *cfg) {
+  if (!E || !cfg) return fail(DSW_EINVAL, "null argument");
+  *cfg = from_cfg(E->cfg);
+  return DSW_OK;
+}
+
+extern "C" int dsw_ensemble_tune(dsw_ensemble *E, const dsw_fields *Un, dsw_fields *Unp1,
+                                 const double *tau, int32_t K, int32_t reps, void *stream,
+                                 dsw_config *best) {
+  int rc = check_ens_args(E, Un, Unp1, tau, K);
+  if (rc) return rc;
+  if (reps < 1) return fail(DSW_EINVAL, "reps must be >= 1");
+  hipStream_t st = (hipStream_t)stream;
+  // candidate v sets every tunable to its v-th value; passes are timed
+  // separately, so each pass keeps its own best value
+  const int bsz[3] = {64, 128, 256}, pms[3] = {4, 2, 0};
+  double tbest[4] = {1e300, 1e300, 1e300, 1e300};
+  Cfg out = E->cfg;
+  for (int v = 0; v < 3; v++) {
+    const Cfg c{bsz[v], {bsz[v], bsz[v]}, pms[v]};
+    dsw_ensemble::Plan plan;
+    if ((rc = build_plan(E, c, Un, Unp1, tau, K, plan))) return rc;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev(plan.groups.size());
+    for (auto &e : ev) {
+      HIPCHK(hipEventCreate(&e.first));
+      HIPCHK(hipEventCreate(&e.second));
+    }
+    double t[4] = {0, 0, 0, 0};
+    enqueue_plan(plan, c, st, nullptr); // warm-up
+    for (int r = 0; r < reps; r++) {
+      enqueue_plan(plan, c, st, &ev);
+      HIPCHK(hipStreamSynchronize(st));
+      for (size_t q = 0; q < plan.groups.size(); q++) {
+        const int tk = plan.groups[q].tk;
+        if (tk < 0 || tk > 3) continue;
+        float ms = 0.0f;
+        HIPCHK(hipEventElapsedTime(&ms, ev[q].first, ev[q].second));
+        t[tk] += ms;
+      }
+    }
+    for (auto &e : ev) { (void)hipEventDestroy(e.first); (void)hipEventDestroy(e.second); }
+    free_plan(plan);
+    if (t[0] < tbest[0]) { tbest[0] = t[0]; out.res_bs = c.res_bs; }
+    if (t[1] < tbest[1]) { tbest[1] = t[1]; out.sweep_bs[0] = c.sweep_bs[0]; }
+    if (t[2] < tbest[2]) { tbest[2] = t[2]; out.sweep_bs[1] = c.sweep_bs[1]; }
+    if (t[3] < tbest[3]) { tbest[3] = t[3]; out.phi_pm = c.phi_pm; }
+  }
+  rc = check_launch("ensemble tuning kernels");
+  if (rc) return rc;
+  E->cfg = out;
+  for (dsw_grid *G : E->mem) G->cfg = out;
+  if (best) *best = from_cfg(out);
+  return DSW_OK;
+}
+
+extern "C" int dsw_ensemble_get_status(dsw_ensemble *E, void *stream) {
+  if (!E) return fail(DSW_EINVAL, "null handle");
+  int first = DSW_OK;
+  std::string msg;
+  for (size_t m = 0; m < E->mem.size(); m++) {
+    const int rc = dsw_get_status(E->mem[m], stream);
+    if (rc && first == DSW_OK) { first = rc; msg = "member " + std::to_string(m) + ": " + g_err; }
+  }
+  if (first) return fail(first, msg);
   return DSW_OK;
 }

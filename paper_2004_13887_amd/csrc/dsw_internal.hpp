@@ -24,6 +24,13 @@ struct Out {
   int mode;
 };
 
+// -(Uk - Un) at a point; zero when the two states are the same array
+struct Diff {
+  const double *k[5], *n[5];
+  int same;
+  __device__ __forceinline__ double at(int f, long x) const { return same ? 0.0 : k[f][x] - n[f][x]; }
+};
+
 // workspace of the line solvers: intermediates of the forward elimination
 struct Scratch {
   double *blk;   // block lines
@@ -32,30 +39,80 @@ struct Scratch {
   long sca_len;
 };
 
+// Everything one pass (one kernel) needs for one grid.  Fields a pass does
+// not use are left zero.
+struct PassArgs {
+  Geo g;
+  Mat m;
+  SrcOne u;          // midpoint state: residual operand / sweep coefficients
+  Diff d;            // residual: -(Uk - Un)
+  double tau;        // residual: tau; sweeps: tau/2
+  Fields rhs;        // sweeps: right-hand side
+  Fields R;          // residual: output
+  Out o;             // sweeps: destination
+  double *scb, *scs; // sweeps: scratch of block and scalar lines
+  int *status;
+  Fields src, d0, d1, d2; // boundary-face copy: src -> d0, d1, d2
+};
+
+// One launch over several grids.  Workgroup w belongs to member m with
+// woff[m] <= w < woff[m+1] (woff has n+1 entries, woff[0] = 0); tab[m] is
+// that member's PassArgs.  tab == nullptr: a single grid, passed by value.
+struct Batch {
+  const PassArgs *tab;
+  const unsigned *woff;
+  int n;
+};
+
+// Launch shapes (the tunable parameters).
+struct Cfg {
+  int res_bs;      // residual: threads per workgroup along phi (64, 128, 256)
+  int sweep_bs[2]; // r and theta sweeps: lines per workgroup (64, 128, 256)
+  int phi_pm;      // phi sweep: 0 = one thread per line, 2 or 4 = partitioned
+                   // with that many rows per thread
+};
+
+enum PassKind { PK_BND = 0, PK_RES = 1, PK_SW0 = 2, PK_SW1 = 3, PK_SW2_LINE = 4, PK_SW2_PART = 5 };
+
+// kernel launchers of the passes: by value for one grid (b.tab == nullptr), or
+// over a batch (blocks = sum over the members, threads and lds = maxima)
+void launch_residual_pass(const PassArgs &a, const Batch &b, unsigned blocks, unsigned threads,
+                          hipStream_t st);
+void launch_sweep_pass(int d, const PassArgs &a, const Batch &b, unsigned blocks, unsigned threads,
+                       hipStream_t st);
+void launch_phi_pass(int pm, const PassArgs &a, const Batch &b, unsigned blocks, unsigned threads,
+                     size_t lds, hipStream_t st);
+void launch_bnd_pass(const PassArgs &a, const Batch &b, unsigned blocks, unsigned threads,
+                     hipStream_t st);
+unsigned sweep_lines(const Geo &g, int d);   // lines of all families of sweep d
+unsigned bnd_points(const Geo &g);           // boundary-normal faces
+unsigned phi_part_threads(const Geo &g, int pm);
+size_t phi_part_lds(const Geo &g, int pm);
+
+// public residual: forms the midpoint on the fly from Un and Uk and writes it
 void launch_residual(const Geo &g, const Mat &m, const Fields &Un, const Fields &Uk, double tau,
                      const Fields &R, const Fields &Ub, int *status, hipStream_t st);
 
-// d = 0 (r), 1 (theta), 2 (phi).  If upd is non-null (phi sweep of a split
-// step), the solution is added to upd instead of being stored in x.
-void launch_sweep(int d, const Geo &g, const Mat &m, const Fields &Ub, double tau,
-                  const Fields &rhs, const Out &o, const Scratch &sc, int *status, hipStream_t st);
-
-// residual with the midpoint state already resident (split-step internal);
-// Uk may be the same arrays as Un (first iteration: no difference term)
-void launch_residual_given_mid(const Geo &g, const Mat &m, const Fields &Un, const Fields &Uk,
-                               const Fields &Ub, double tau, const Fields &R, int *status,
-                               hipStream_t st);
-
-// copy the boundary-normal faces of src into dst (skipped where dst.p is null)
-void launch_bnd_copy(const Geo &g, const Fields &src, const Fields &d0, const Fields &d1,
-                     const Fields &d2, hipStream_t st);
-
-// partitioned phi solver (one workgroup per line slot), when the line fits
-bool phi_part_supported(const Geo &g);
-void launch_phi_part(const Geo &g, const Mat &m, const Fields &Ub, double tau, const Fields &rhs,
-                     const Out &o, int *status, hipStream_t st);
+// partitioned phi solver: whether a grid's phi lines fit it
+bool phi_part_supported(const Geo &g, int pm);
 
 // doubles of scratch needed by the sweeps of a grid
 void sweep_scratch_size(const Geo &g, long *blk, long *sca);
+
+// the kind of the phi pass of a grid under a configuration
+inline int phi_kind(const Geo &g, const Cfg &c) {
+  return (c.phi_pm > 0 && phi_part_supported(g, c.phi_pm)) ? PK_SW2_PART : PK_SW2_LINE;
+}
+
+// member lookup of a batched launch (binary search over the offsets)
+__device__ __forceinline__ int batch_member(const Batch &b, unsigned w) {
+  int lo = 0, hi = b.n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (b.woff[mid] <= w) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
 
 } // namespace dsw

@@ -18,9 +18,9 @@
 
 namespace dsw {
 
-constexpr int PM = 4;        // rows per thread
-constexpr int PT_MAX = 256;  // chunks per line (so lines up to 1024 cells)
+constexpr int PT_MAX = 256;  // chunks per line (lines up to PM * 256 cells)
 
+template <int PM>
 __host__ __device__ inline int part_chunks(int n) { return (n + PM - 1) / PM; }
 
 // ---------------------------------------------------------- 3x3 helpers --
@@ -129,9 +129,10 @@ __device__ void pcr_scalar(int t, int T, int cyc, double &A, double &B, double &
 }
 
 // ------------------------------------------------------------ block line --
+template <int PM>
 __device__ void part_block_line(const Geo &g, const Mat &m, const SrcOne &u, const Fields &rhs,
                                 const Out &o, int i, int j, double hs, double *lds, int *status) {
-  const int N = g.np, T = part_chunks(N), cyc = g.periodic;
+  const int N = g.np, T = part_chunks<PM>(N), cyc = g.periodic;
   const int t = threadIdx.x;
   const bool act = t < T;
   const int a0 = t * PM;
@@ -281,10 +282,10 @@ __device__ void part_block_line(const Geo &g, const Mat &m, const SrcOne &u, con
 }
 
 // ----------------------------------------------------------- scalar line --
-template <int FAM>
+template <int PM, int FAM>
 __device__ void part_scalar_line(const Geo &g, const Mat &m, const SrcOne &u, const Fields &rhs,
                                  const Out &o, int a, int b, double hs, double *lds, int *status) {
-  const int N = g.np, T = part_chunks(N), cyc = g.periodic;
+  const int N = g.np, T = part_chunks<PM>(N), cyc = g.periodic;
   const int t = threadIdx.x;
   const bool act = t < T;
   const int a0 = t * PM;
@@ -363,12 +364,15 @@ __device__ void part_scalar_line(const Geo &g, const Mat &m, const SrcOne &u, co
 }
 
 // one workgroup per (i, j): block line (i, j), u_r line on r-face i (i >= 1),
-// u_theta line on theta-face j (j >= 1)
-__global__ void __launch_bounds__(256) k_phi_part(Geo g, Mat m, SrcOne u, double hs, Fields rhs,
-                                                  Out o, int *status) {
-  extern __shared__ double lds[];
-  const int j = blockIdx.x, i = blockIdx.y;
+// u_theta line on theta-face j (j >= 1).  Flat grid of nr * nt workgroups per
+// grid; one grid or a batch of grids.  The workgroup may be wider than the
+// chunk count: threads past it only join the barriers.
+template <int PM>
+__device__ __forceinline__ void phi_body(const PassArgs &a, unsigned w, double *lds) {
+  const Geo &g = a.g;
+  const int j = (int)(w % g.nt), i = (int)(w / g.nt);
   const int t = threadIdx.x;
+  const Out &o = a.o;
   if (o.mode == 0) { // boundary-normal faces of x that no phi line owns
     const Fields &x = o.x;
     for (int k = t; k < g.np; k += blockDim.x) {
@@ -379,30 +383,53 @@ __global__ void __launch_bounds__(256) k_phi_part(Geo g, Mat m, SrcOne u, double
     }
     if (!g.periodic && t == 0) x.uf[idx_f(g, i, j, 0)] = 0.0;
   }
-  part_block_line(g, m, u, rhs, o, i, j, hs, lds, status);
-  if (i >= 1) part_scalar_line<0>(g, m, u, rhs, o, i, j, hs, lds, status);
-  if (j >= 1) part_scalar_line<1>(g, m, u, rhs, o, i, j, hs, lds, status);
+  part_block_line<PM>(g, a.m, a.u, a.rhs, o, i, j, a.tau, lds, a.status);
+  if (i >= 1) part_scalar_line<PM, 0>(g, a.m, a.u, a.rhs, o, i, j, a.tau, lds, a.status);
+  if (j >= 1) part_scalar_line<PM, 1>(g, a.m, a.u, a.rhs, o, i, j, a.tau, lds, a.status);
 }
 
-bool phi_part_supported(const Geo &g) {
-  const int T = part_chunks(g.np);
+template <int PM, bool B>
+__global__ void __launch_bounds__(256) k_phi_part(PassArgs a, Batch bt) {
+  extern __shared__ double lds[];
+  if constexpr (B) {
+    const int mb = batch_member(bt, blockIdx.x);
+    phi_body<PM>(bt.tab[mb], blockIdx.x - bt.woff[mb], lds);
+  } else {
+    phi_body<PM>(a, blockIdx.x, lds);
+  }
+}
+
+bool phi_part_supported(const Geo &g, int pm) {
+  if (pm != 2 && pm != 4) return false;
+  const int T = (g.np + pm - 1) / pm;
   if (T > PT_MAX) return false;
   if (g.periodic) { // cyclic reduction needs a power-of-two number of equal chunks
-    if (g.np % PM != 0) return false;
+    if (g.np % pm != 0) return false;
     if (T & (T - 1)) return false;
   }
   return true;
 }
 
-void launch_phi_part(const Geo &g, const Mat &m, const Fields &Ub, double tau, const Fields &rhs,
-                     const Out &o, int *status, hipStream_t st) {
-  SrcOne u;
-  u.a[F_P] = Ub.p; u.a[F_UR] = Ub.ur; u.a[F_UT] = Ub.ut; u.a[F_UF] = Ub.uf; u.a[F_T] = Ub.T;
-  const int T = part_chunks(g.np);
-  const int bs = ((T + 63) / 64) * 64;
-  const size_t lds = sizeof(double) * 33 * T;
-  dim3 grid(g.nt, g.nr);
-  hipLaunchKernelGGL(k_phi_part, grid, dim3(bs), lds, st, g, m, u, 0.5 * tau, rhs, o, status);
+unsigned phi_part_threads(const Geo &g, int pm) {
+  const int T = (g.np + pm - 1) / pm;
+  return (unsigned)(((T + 63) / 64) * 64);
+}
+
+size_t phi_part_lds(const Geo &g, int pm) {
+  const int T = (g.np + pm - 1) / pm;
+  return sizeof(double) * 33 * (size_t)T;
+}
+
+void launch_phi_pass(int pm, const PassArgs &a, const Batch &b, unsigned blocks, unsigned threads,
+                     size_t lds, hipStream_t st) {
+  const dim3 gr(blocks), bl(threads);
+  if (b.tab) {
+    if (pm == 2) hipLaunchKernelGGL((k_phi_part<2, true>), gr, bl, lds, st, a, b);
+    else hipLaunchKernelGGL((k_phi_part<4, true>), gr, bl, lds, st, a, b);
+  } else {
+    if (pm == 2) hipLaunchKernelGGL((k_phi_part<2, false>), gr, bl, lds, st, a, b);
+    else hipLaunchKernelGGL((k_phi_part<4, false>), gr, bl, lds, st, a, b);
+  }
 }
 
 } // namespace dsw

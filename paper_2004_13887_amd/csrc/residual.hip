@@ -129,19 +129,11 @@ __device__ double F_uf(const Geo &g, const Mat &m, const S &s, int i, int j, int
   return N - nu * vis - nu / 3.0 * gd;
 }
 
-// -(Uk - Un) at a point; zero when the two states are the same array
-struct Diff {
-  const double *k[5], *n[5];
-  int same;
-  __device__ __forceinline__ double at(int f, long x) const { return same ? 0.0 : k[f][x] - n[f][x]; }
-};
-
+// residual at the centre (i,j,k) and the three faces with the same indices
 template <class S, bool WRITE_UB>
-__global__ void __launch_bounds__(256) k_residual(Geo g, Mat m, S s, Diff dU, double tau, Fields R,
-                                                  Fields Ub, int *status) {
-  const int k = blockIdx.x * blockDim.x + threadIdx.x;
-  const int j = blockIdx.y;
-  const int i = blockIdx.z;
+__device__ __forceinline__ void residual_point(const Geo &g, const Mat &m, const S &s, const Diff &dU,
+                                               double tau, const Fields &R, const Fields &Ub,
+                                               int *status, int i, int j, int k) {
   if (k >= g.npf) return;
   const bool kc = k < g.np;
   if (i < g.nr && j < g.nt && kc) { // cell centre
@@ -172,6 +164,34 @@ __global__ void __launch_bounds__(256) k_residual(Geo g, Mat m, S s, Diff dU, do
   }
 }
 
+// public form: midpoint formed from Un and Uk and written out; 3-D grid
+__global__ void __launch_bounds__(256) k_residual_mid(Geo g, Mat m, SrcMid s, Diff dU, double tau,
+                                                      Fields R, Fields Ub, int *status) {
+  residual_point<SrcMid, true>(g, m, s, dU, tau, R, Ub, status, blockIdx.z, blockIdx.y,
+                               blockIdx.x * blockDim.x + threadIdx.x);
+}
+
+// split-step form: the midpoint is resident; flat grid of workgroups over
+// (phi block, theta index, r index).  B: a batch of grids, each workgroup
+// reads its grid's arguments from the batch table; else one grid by value.
+__device__ __forceinline__ void residual_body(const PassArgs &a, unsigned w) {
+  const unsigned nkb = (a.g.npf + blockDim.x - 1) / blockDim.x;
+  const unsigned kb = w % nkb, rest = w / nkb;
+  const int j = (int)(rest % (a.g.nt + 1)), i = (int)(rest / (a.g.nt + 1));
+  residual_point<SrcOne, false>(a.g, a.m, a.u, a.d, a.tau, a.R, Fields{}, a.status, i, j,
+                                (int)(kb * blockDim.x + threadIdx.x));
+}
+
+template <bool B>
+__global__ void __launch_bounds__(256) k_residual(PassArgs a, Batch bt) {
+  if constexpr (B) {
+    const int mb = batch_member(bt, blockIdx.x);
+    residual_body(bt.tab[mb], blockIdx.x - bt.woff[mb]);
+  } else {
+    residual_body(a, blockIdx.x);
+  }
+}
+
 static void set5(const double **dst, const Fields &f) {
   dst[F_P] = f.p; dst[F_UR] = f.ur; dst[F_UT] = f.ut; dst[F_UF] = f.uf; dst[F_T] = f.T;
 }
@@ -187,22 +207,13 @@ void launch_residual(const Geo &g, const Mat &m, const Fields &Un, const Fields 
   d.same = 0;
   dim3 block(64, 1, 1);
   dim3 grid((g.npf + 63) / 64, g.nt + 1, g.nr + 1);
-  hipLaunchKernelGGL((k_residual<SrcMid, true>), grid, block, 0, st, g, m, s, d, tau, R, Ub, status);
+  hipLaunchKernelGGL(k_residual_mid, grid, block, 0, st, g, m, s, d, tau, R, Ub, status);
 }
 
-void launch_residual_given_mid(const Geo &g, const Mat &m, const Fields &Un, const Fields &Uk,
-                               const Fields &Ub, double tau, const Fields &R, int *status,
-                               hipStream_t st) {
-  SrcOne s;
-  set5(s.a, Ub);
-  Diff d;
-  set5(d.n, Un);
-  set5(d.k, Uk);
-  d.same = (Un.p == Uk.p) ? 1 : 0;
-  dim3 block(64, 1, 1);
-  dim3 grid((g.npf + 63) / 64, g.nt + 1, g.nr + 1);
-  hipLaunchKernelGGL((k_residual<SrcOne, false>), grid, block, 0, st, g, m, s, d, tau, R, Fields{},
-                     status);
+void launch_residual_pass(const PassArgs &a, const Batch &b, unsigned blocks, unsigned threads,
+                          hipStream_t st) {
+  if (b.tab) hipLaunchKernelGGL(k_residual<true>, dim3(blocks), dim3(threads), 0, st, a, b);
+  else hipLaunchKernelGGL(k_residual<false>, dim3(blocks), dim3(threads), 0, st, a, b);
 }
 
 } // namespace dsw

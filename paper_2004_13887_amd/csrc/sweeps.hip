@@ -270,39 +270,54 @@ __device__ void solve_scalar_line(const Geo &g, const Mat &m, const SrcOne &u, c
 
 // ----------------------------------------------------------------- kernel --
 
+// one thread per line: the block lines first, then the two scalar families;
+// one grid or a batch of grids (flat grid of workgroups)
 template <int D>
-__global__ void __launch_bounds__(128) k_sweep(Geo g, Mat m, SrcOne u, double hs, Fields rhs,
-                                               Out o, double *scb, double *scs, int *status) {
+__device__ __forceinline__ void sweep_body(const PassArgs &a, unsigned w) {
+  const Geo &g = a.g;
   const Families F = families(g, D);
-  const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long t = (long)w * blockDim.x + threadIdx.x;
   const int nkf = g.periodic ? g.np : g.np - 1, kf0 = g.periodic ? 0 : 1;
+  const double hs = a.tau;
   if (t < F.nb) {
-    int a, b;
-    if (D == 0) { a = (int)(t / g.np); b = (int)(t % g.np); }
-    else if (D == 1) { a = (int)(t / g.np); b = (int)(t % g.np); }
-    else { a = (int)(t / g.nt); b = (int)(t % g.nt); }
-    if (o.mode == 0) zero_bnd<D>(g, o.x, a, b);
-    if (F.cyclic) solve_block_cyclic<D>(g, m, u, rhs, o, scb, F.nb, t, a, b, F.n, hs, status);
-    else solve_block_line<D>(g, m, u, rhs, o, scb, F.nb, t, a, b, F.n, hs, status);
+    int p, q;
+    if (D == 0) { p = (int)(t / g.np); q = (int)(t % g.np); }
+    else if (D == 1) { p = (int)(t / g.np); q = (int)(t % g.np); }
+    else { p = (int)(t / g.nt); q = (int)(t % g.nt); }
+    if (a.o.mode == 0) zero_bnd<D>(g, a.o.x, p, q);
+    if (F.cyclic) solve_block_cyclic<D>(g, a.m, a.u, a.rhs, a.o, a.scb, F.nb, t, p, q, F.n, hs, a.status);
+    else solve_block_line<D>(g, a.m, a.u, a.rhs, a.o, a.scb, F.nb, t, p, q, F.n, hs, a.status);
     return;
   }
   long t2 = t - F.nb;
   const long ns = (long)F.na + F.nbb;
   if (t2 < F.na) {
-    int a, b;
-    if (D == 0) { a = 1 + (int)(t2 / g.np); b = (int)(t2 % g.np); }
-    else if (D == 1) { a = 1 + (int)(t2 / g.np); b = (int)(t2 % g.np); }
-    else { a = 1 + (int)(t2 / g.nt); b = (int)(t2 % g.nt); }
-    solve_scalar_line<D, 0>(g, m, u, rhs, o, scs, ns, t2, a, b, F.n, F.cyclic, hs, status);
+    int p, q;
+    if (D == 0) { p = 1 + (int)(t2 / g.np); q = (int)(t2 % g.np); }
+    else if (D == 1) { p = 1 + (int)(t2 / g.np); q = (int)(t2 % g.np); }
+    else { p = 1 + (int)(t2 / g.nt); q = (int)(t2 % g.nt); }
+    solve_scalar_line<D, 0>(g, a.m, a.u, a.rhs, a.o, a.scs, ns, t2, p, q, F.n, F.cyclic, hs, a.status);
     return;
   }
   t2 -= F.na;
   if (t2 < F.nbb) {
-    int a, b;
-    if (D == 0) { a = (int)(t2 / nkf); b = kf0 + (int)(t2 % nkf); }
-    else if (D == 1) { a = (int)(t2 / nkf); b = kf0 + (int)(t2 % nkf); }
-    else { a = (int)(t2 / (g.nt - 1)); b = 1 + (int)(t2 % (g.nt - 1)); }
-    solve_scalar_line<D, 1>(g, m, u, rhs, o, scs, ns, F.na + t2, a, b, F.n, F.cyclic, hs, status);
+    int p, q;
+    if (D == 0) { p = (int)(t2 / nkf); q = kf0 + (int)(t2 % nkf); }
+    else if (D == 1) { p = (int)(t2 / nkf); q = kf0 + (int)(t2 % nkf); }
+    else { p = (int)(t2 / (g.nt - 1)); q = 1 + (int)(t2 % (g.nt - 1)); }
+    solve_scalar_line<D, 1>(g, a.m, a.u, a.rhs, a.o, a.scs, ns, F.na + t2, p, q, F.n, F.cyclic, hs,
+                            a.status);
+  }
+}
+
+// B: a batch of grids (arguments from the batch table), else one grid
+template <int D, bool B>
+__global__ void __launch_bounds__(256) k_sweep(PassArgs a, Batch bt) {
+  if constexpr (B) {
+    const int mb = batch_member(bt, blockIdx.x);
+    sweep_body<D>(bt.tab[mb], blockIdx.x - bt.woff[mb]);
+  } else {
+    sweep_body<D>(a, blockIdx.x);
   }
 }
 
@@ -319,26 +334,30 @@ void sweep_scratch_size(const Geo &g, long *blk, long *sca) {
   *sca = s;
 }
 
-void launch_sweep(int d, const Geo &g, const Mat &m, const Fields &Ub, double tau,
-                  const Fields &rhs, const Out &o, const Scratch &sc, int *status,
-                  hipStream_t st) {
-  SrcOne u;
-  u.a[F_P] = Ub.p; u.a[F_UR] = Ub.ur; u.a[F_UT] = Ub.ut; u.a[F_UF] = Ub.uf; u.a[F_T] = Ub.T;
+unsigned sweep_lines(const Geo &g, int d) {
   const Families F = families(g, d);
-  const long nt = (long)F.nb + F.na + F.nbb;
-  const int bs = 128;
-  dim3 grid((unsigned)((nt + bs - 1) / bs));
-  const double hs = 0.5 * tau;
-  if (d == 0) hipLaunchKernelGGL(k_sweep<0>, grid, dim3(bs), 0, st, g, m, u, hs, rhs, o, sc.blk, sc.sca, status);
-  else if (d == 1) hipLaunchKernelGGL(k_sweep<1>, grid, dim3(bs), 0, st, g, m, u, hs, rhs, o, sc.blk, sc.sca, status);
-  else if (phi_part_supported(g)) launch_phi_part(g, m, Ub, tau, rhs, o, status, st);
-  else hipLaunchKernelGGL(k_sweep<2>, grid, dim3(bs), 0, st, g, m, u, hs, rhs, o, sc.blk, sc.sca, status);
+  return (unsigned)((long)F.nb + F.na + F.nbb);
+}
+
+void launch_sweep_pass(int d, const PassArgs &a, const Batch &b, unsigned blocks, unsigned threads,
+                       hipStream_t st) {
+  const dim3 gr(blocks), bl(threads);
+  if (b.tab) {
+    if (d == 0) hipLaunchKernelGGL((k_sweep<0, true>), gr, bl, 0, st, a, b);
+    else if (d == 1) hipLaunchKernelGGL((k_sweep<1, true>), gr, bl, 0, st, a, b);
+    else hipLaunchKernelGGL((k_sweep<2, true>), gr, bl, 0, st, a, b);
+  } else {
+    if (d == 0) hipLaunchKernelGGL((k_sweep<0, false>), gr, bl, 0, st, a, b);
+    else if (d == 1) hipLaunchKernelGGL((k_sweep<1, false>), gr, bl, 0, st, a, b);
+    else hipLaunchKernelGGL((k_sweep<2, false>), gr, bl, 0, st, a, b);
+  }
 }
 
 // boundary-normal faces: u_r on r = r1, r2; u_theta on the theta boundaries;
 // u_phi on the phi walls (sector only)
-__global__ void k_bnd_copy(Geo g, Fields src, Fields d0, Fields d1, Fields d2) {
-  const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void bnd_body(const PassArgs &a, unsigned w) {
+  const Geo &g = a.g;
+  const long t = (long)w * blockDim.x + threadIdx.x;
   const long nr_ = (long)g.nt * g.np, nt_ = (long)g.nr * g.np, nf_ = g.periodic ? 0 : (long)g.nr * g.nt;
   long idx;
   int fid;
@@ -357,16 +376,30 @@ __global__ void k_bnd_copy(Geo g, Fields src, Fields d0, Fields d1, Fields d2) {
   } else {
     return;
   }
-  const double v = fsel(src, fid)[idx];
-  if (d0.p) fsel(d0, fid)[idx] = v;
-  if (d1.p) fsel(d1, fid)[idx] = v;
-  if (d2.p) fsel(d2, fid)[idx] = v;
+  const double v = fsel(a.src, fid)[idx];
+  if (a.d0.p) fsel(a.d0, fid)[idx] = v;
+  if (a.d1.p) fsel(a.d1, fid)[idx] = v;
+  if (a.d2.p) fsel(a.d2, fid)[idx] = v;
 }
 
-void launch_bnd_copy(const Geo &g, const Fields &src, const Fields &d0, const Fields &d1,
-                     const Fields &d2, hipStream_t st) {
-  const long n = 2L * g.nt * g.np + 2L * g.nr * g.np + (g.periodic ? 0 : 2L * g.nr * g.nt);
-  hipLaunchKernelGGL(k_bnd_copy, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, g, src, d0, d1, d2);
+template <bool B>
+__global__ void __launch_bounds__(256) k_bnd_copy(PassArgs a, Batch bt) {
+  if constexpr (B) {
+    const int mb = batch_member(bt, blockIdx.x);
+    bnd_body(bt.tab[mb], blockIdx.x - bt.woff[mb]);
+  } else {
+    bnd_body(a, blockIdx.x);
+  }
+}
+
+unsigned bnd_points(const Geo &g) {
+  return (unsigned)(2L * g.nt * g.np + 2L * g.nr * g.np + (g.periodic ? 0 : 2L * g.nr * g.nt));
+}
+
+void launch_bnd_pass(const PassArgs &a, const Batch &b, unsigned blocks, unsigned threads,
+                     hipStream_t st) {
+  if (b.tab) hipLaunchKernelGGL(k_bnd_copy<true>, dim3(blocks), dim3(threads), 0, st, a, b);
+  else hipLaunchKernelGGL(k_bnd_copy<false>, dim3(blocks), dim3(threads), 0, st, a, b);
 }
 
 } // namespace dsw

@@ -24,7 +24,10 @@ _NAMES = {DSW_EINVAL: "DSW_EINVAL", DSW_ENOMEM: "DSW_ENOMEM", DSW_EHIP: "DSW_EHI
 # every extern "C" symbol the header declares
 SYMBOLS = ("dsw_init_grid", "dsw_free_grid", "dsw_layout", "dsw_residual", "dsw_line_solve_r",
            "dsw_line_solve_theta", "dsw_line_solve_phi", "dsw_split_step", "dsw_set_timing",
-           "dsw_read_timing", "dsw_get_status", "dsw_last_error")
+           "dsw_read_timing", "dsw_get_status", "dsw_set_config", "dsw_get_config",
+           "dsw_ensemble_create", "dsw_ensemble_free", "dsw_ensemble_member", "dsw_ensemble_step",
+           "dsw_ensemble_tune", "dsw_ensemble_set_config", "dsw_ensemble_get_config",
+           "dsw_ensemble_get_status", "dsw_last_error")
 TIMING_KINDS = ("residual", "sweep_r", "sweep_theta", "sweep_phi_update", "boundary_copy")
 
 
@@ -47,6 +50,15 @@ class Material(C.Structure):
 
 class Fields(C.Structure):
     _fields_ = [(n, C.c_void_p) for n in FIELDS]
+
+
+class Config(C.Structure):
+    _fields_ = [("residual_block", C.c_int32), ("sweep_block_r", C.c_int32),
+                ("sweep_block_theta", C.c_int32), ("phi_rows_per_thread", C.c_int32)]
+
+    def astuple(self):
+        return (self.residual_block, self.sweep_block_r, self.sweep_block_theta,
+                self.phi_rows_per_thread)
 
 
 class LayoutInfo(C.Structure):
@@ -78,6 +90,18 @@ def lib():
         L.dsw_get_status.argtypes = [P, P]
         L.dsw_set_timing.argtypes = [P, I]
         L.dsw_read_timing.argtypes = [P, P, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
+        CP = C.POINTER(Config)
+        L.dsw_set_config.argtypes = [P, CP]
+        L.dsw_get_config.argtypes = [P, CP]
+        L.dsw_ensemble_create.argtypes = [C.POINTER(GridDesc), C.POINTER(Material), I,
+                                          C.POINTER(C.c_void_p)]
+        L.dsw_ensemble_free.argtypes = [P]
+        L.dsw_ensemble_member.argtypes = [P, I, C.POINTER(C.c_void_p)]
+        L.dsw_ensemble_step.argtypes = [P, FP, FP, C.POINTER(C.c_double), I, P]
+        L.dsw_ensemble_tune.argtypes = [P, FP, FP, C.POINTER(C.c_double), I, I, P, CP]
+        L.dsw_ensemble_set_config.argtypes = [P, CP]
+        L.dsw_ensemble_get_config.argtypes = [P, CP]
+        L.dsw_ensemble_get_status.argtypes = [P, P]
         L.dsw_last_error.restype = C.c_char_p
         for n in SYMBOLS[:-1]:
             getattr(L, n).restype = C.c_int
@@ -109,22 +133,25 @@ def _stream(stream):
 class Grid:
     """Handle of dsw_init_grid; methods are the C-ABI calls of the same names."""
 
-    def __init__(self, nr, nt, np_, r1, r2, t1, t2, p1, p2, periodic, material):
+    def __init__(self, nr, nt, np_, r1, r2, t1, t2, p1, p2, periodic, material, _borrowed=None):
         self.desc = GridDesc(int(nr), int(nt), int(np_), 1 if periodic else 0, float(r1), float(r2),
                              float(t1), float(t2), float(p1), float(p2))
         self.mat = Material(*(float(x) for x in material))
+        if _borrowed is not None:  # member handle owned by an Ensemble
+            self._h, self._owned, self._owner = _borrowed[0], False, _borrowed[1]
+            return
         h = C.c_void_p()
         _check(lib().dsw_init_grid(C.byref(self.desc), C.byref(self.mat), C.byref(h)))
-        self._h = h
+        self._h, self._owned = h, True
 
     @classmethod
     def from_spec(cls, spec, material):
         return cls(*spec.args(), material.astuple())
 
     def free_grid(self):
-        if getattr(self, "_h", None):
+        if getattr(self, "_h", None) and getattr(self, "_owned", False):
             lib().dsw_free_grid(self._h)
-            self._h = None
+        self._h = None
 
     __del__ = free_grid
 
@@ -172,6 +199,81 @@ class Grid:
     def get_status(self, stream=None):
         """DSW_OK, or raises DswError(DSW_ENONPHYS / DSW_ESINGULAR)."""
         _check(lib().dsw_get_status(self._h, _stream(stream)))
+        return DSW_OK
+
+    def set_config(self, residual_block=64, sweep_block_r=128, sweep_block_theta=128,
+                   phi_rows_per_thread=4):
+        c = Config(residual_block, sweep_block_r, sweep_block_theta, phi_rows_per_thread)
+        _check(lib().dsw_set_config(self._h, C.byref(c)))
+
+    def get_config(self):
+        c = Config()
+        _check(lib().dsw_get_config(self._h, C.byref(c)))
+        return c.astuple()
+
+
+def _field_array(states):
+    arr = (Fields * len(states))()
+    for q, d in enumerate(states):
+        arr[q] = _fields(d)
+    return arr
+
+
+class Ensemble:
+    """Handle of dsw_ensemble_create: n grids stepped by batched launches
+    replayed from one HIP graph."""
+
+    def __init__(self, specs, materials):
+        n = len(specs)
+        descs = (GridDesc * n)()
+        mats = (Material * n)()
+        for q, (g, m) in enumerate(zip(specs, materials)):
+            nr, nt, np_, r1, r2, t1, t2, p1, p2, periodic = g.args()
+            descs[q] = GridDesc(nr, nt, np_, 1 if periodic else 0, r1, r2, t1, t2, p1, p2)
+            mats[q] = Material(*m.astuple())
+        h = C.c_void_p()
+        _check(lib().dsw_ensemble_create(descs, mats, n, C.byref(h)))
+        self._h = h
+        self.n = n
+        self.members = []
+        for q, (g, m) in enumerate(zip(specs, materials)):
+            gh = C.c_void_p()
+            _check(lib().dsw_ensemble_member(self._h, q, C.byref(gh)))
+            self.members.append(Grid(*g.args(), m.astuple(), _borrowed=(gh, self)))
+
+    def ensemble_free(self):
+        if getattr(self, "_h", None):
+            for g in self.members:
+                g._h = None
+            lib().dsw_ensemble_free(self._h)
+            self._h = None
+
+    __del__ = ensemble_free
+
+    def ensemble_step(self, Un, Unp1, tau, K, stream=None):
+        taus = (C.c_double * self.n)(*[float(t) for t in tau])
+        _check(lib().dsw_ensemble_step(self._h, _field_array(Un), _field_array(Unp1), taus, int(K),
+                                       _stream(stream)))
+
+    def ensemble_tune(self, Un, Unp1, tau, K, reps=2, stream=None):
+        taus = (C.c_double * self.n)(*[float(t) for t in tau])
+        c = Config()
+        _check(lib().dsw_ensemble_tune(self._h, _field_array(Un), _field_array(Unp1), taus, int(K),
+                                       int(reps), _stream(stream), C.byref(c)))
+        return c.astuple()
+
+    def set_config(self, residual_block=64, sweep_block_r=128, sweep_block_theta=128,
+                   phi_rows_per_thread=4):
+        c = Config(residual_block, sweep_block_r, sweep_block_theta, phi_rows_per_thread)
+        _check(lib().dsw_ensemble_set_config(self._h, C.byref(c)))
+
+    def get_config(self):
+        c = Config()
+        _check(lib().dsw_ensemble_get_config(self._h, C.byref(c)))
+        return c.astuple()
+
+    def get_status(self, stream=None):
+        _check(lib().dsw_ensemble_get_status(self._h, _stream(stream)))
         return DSW_OK
 
 
