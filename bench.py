@@ -1,6 +1,7 @@
 """Benchmark: split time steps of the full-sphere global workload on one GPU.
 
-    python bench.py [--gpus 1] [--steps 10] [--warmup 2] [--no-cpu]
+    python bench.py [--gpus 1] [--steps 10] [--warmup 2] [--no-cpu] [--config R,SR,ST,PM]
+    python bench.py --ensemble [--members 64] [--steps 3] [--warmup 1]
 
 Workload: 512 (phi, periodic) x 256 (theta, poles) x 128 (r) cells over a
 10 km shell, FP64, K = 3 nonlinear iterations per split step, Mach 1e-4,
@@ -8,6 +9,12 @@ seeded synthetic initial data (hydrostatic isothermal atmosphere, Gaussian
 potential-temperature bubble, seeded velocity noise).  A "step" is one call of
 dsw_split_step (K x (residual + three line sweeps)); inputs are resident in
 HBM before the timed region.  Prints one JSON line.
+
+--ensemble measures the 64-member ensemble of uneven regional grids instead:
+the autotuner picks the launch shapes, then the batched step (one launch per
+pass over all members, replayed from one HIP graph) is timed against the same
+step done as one dsw_split_step call per member on one stream, from the same
+initial states, and the two final states are compared.
 """
 import argparse
 import hashlib
@@ -106,11 +113,18 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--calib", action="store_true",
                     help="also run a plain 1 GiB device copy (to scale hardware byte counters)")
+    ap.add_argument("--config", default=None,
+                    help="launch shapes residual_block,sweep_block_r,sweep_block_theta,phi_rows_per_thread")
+    ap.add_argument("--ensemble", action="store_true", help="measure the batched ensemble instead")
+    ap.add_argument("--members", type=int, default=64)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the multi-GPU path is "
               "not part of this build", file=sys.stderr)
         sys.exit(2)
+
+    if args.ensemble:
+        return bench_ensemble(args)
 
     import torch
     from paper_2004_13887_amd import dsw
@@ -120,6 +134,8 @@ def main():
     log(f"[bench] generating {w.name}: {w.grid.np}x{w.grid.nt}x{w.grid.nr} cells")
     U0, tau = I.initial_state(w)
     grid = dsw.Grid.from_spec(w.grid, w.material)
+    if args.config:
+        grid.set_config(*(int(x) for x in args.config.split(",")))
     bufs = [dsw.to_device(U0), grid.empty()]
     counts = [v.numel() for v in bufs[0].values()]
     stream = torch.cuda.current_stream()
@@ -191,7 +207,9 @@ def main():
         "data": "synthetic",
         "config": {"workload": "global: 512 (phi, periodic) x 256 (theta) x 128 (r) full sphere, "
                                "10 km shell, K=3, Mach 1e-4, seeded bubble + noise",
-                   "cells": cells, "K": w.K, "tau_s": tau},
+                   "cells": cells, "K": w.K, "tau_s": tau,
+                   "launch_config": dict(zip(("residual_block", "sweep_block_r", "sweep_block_theta",
+                                              "phi_rows_per_thread"), grid.get_config()))},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": PEAK_HBM / 1e9,
                      "unit": "GB/s", "frac": achieved / (PEAK_HBM / 1e9),
                      "traffic": traffic, "bytes_per_launch": kstats[dom]["bytes_per_launch"],
@@ -203,6 +221,102 @@ def main():
     if not args.no_cpu:
         log("[bench] timing the CPU oracle on a bounded sample")
         out["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(out), flush=True)
+
+
+def bench_ensemble(args):
+    import torch
+    from paper_2004_13887_amd import dsw
+    from paper_2004_13887_amd import inputs as I
+
+    ws = I.ensemble_members(n=args.members)
+    cells = sum(w.grid.ncells for w in ws)
+    K = ws[0].K
+    log(f"[ensemble] {len(ws)} members, {cells} cells; generating inputs")
+    t0 = time.perf_counter()
+    E = dsw.Ensemble([w.grid for w in ws], [w.material for w in ws])
+    U0, taus = [], []
+    for w in ws:
+        u, tau = I.initial_state(w)
+        U0.append(dsw.to_device(u))
+        taus.append(tau)
+        del u
+    A = [g.empty() for g in E.members]
+    B = [g.empty() for g in E.members]
+    keep = [g.empty() for g in E.members]
+    log(f"[ensemble] inputs resident after {time.perf_counter() - t0:.1f} s; tuning")
+    stream = torch.cuda.current_stream()
+
+    def reset():
+        for a, u in zip(A, U0):
+            for k in a:
+                a[k].copy_(u[k])
+
+    reset()
+    cfg = E.ensemble_tune(A, B, taus, K, reps=1, stream=stream)
+    log(f"[ensemble] tuned launch shapes {cfg}")
+
+    def run(step_fn, n0, n):
+        for q in range(n0, n0 + n):
+            src, dst = (A, B) if q % 2 == 0 else (B, A)
+            step_fn(src, dst)
+
+    def batched(src, dst):
+        E.ensemble_step(src, dst, taus, K, stream)
+
+    def per_member(src, dst):
+        for m, g in enumerate(E.members):
+            g.split_step(src[m], dst[m], taus[m], K, stream)
+
+    times = {}
+    for name, fn in (("batched_graph", batched), ("per_member", per_member)):
+        reset()
+        run(fn, 0, args.warmup)
+        torch.cuda.synchronize()
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record(stream)
+        run(fn, args.warmup, args.steps)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        times[name] = ev0.elapsed_time(ev1) / args.steps
+        log(f"[ensemble] {name}: {times[name]:.2f} ms per step")
+        final = A if (args.warmup + args.steps) % 2 == 0 else B
+        if name == "batched_graph":
+            for kk, f in zip(keep, final):
+                for k in kk:
+                    kk[k].copy_(f[k])
+    E.get_status()
+    final = A if (args.warmup + args.steps) % 2 == 0 else B
+    diff = 0.0
+    for kk, f in zip(keep, final):
+        for k in kk:
+            n = float(torch.linalg.vector_norm(f[k]))
+            d = float(torch.linalg.vector_norm(kk[k] - f[k]))
+            diff = max(diff, d / n if n > 0 else d)
+    ms = times["batched_graph"]
+    out = {
+        "metric": "grid-point updates/s per ensemble split step (FP64)",
+        "value": cells / (ms * 1e-3),
+        "unit": "grid-point updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"ensemble: {len(ws)} regional members, sizes U{{64..256}} per "
+                               "direction, 100 m horizontal, K=3, seeded", "members": len(ws),
+                   "cells": cells, "K": K,
+                   "launch_config": dict(zip(("residual_block", "sweep_block_r", "sweep_block_theta",
+                                              "phi_rows_per_thread"), cfg))},
+        "per_member": {"value": cells / (times["per_member"] * 1e-3),
+                       "ms_per_step": times["per_member"]},
+        "speedup_vs_per_member": times["per_member"] / ms,
+        "max_rel_l2_vs_per_member": diff,
+    }
     print(json.dumps(out), flush=True)
 
 

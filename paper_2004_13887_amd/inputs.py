@@ -231,18 +231,26 @@ def initial_state(w: Workload):
     sh = g.shapes()
     pcol = hydrostatic_pressure(g, mat)
     p = np.broadcast_to(pcol[:, None, None], sh["p"]).copy()
-    # bubble: chord distance from the centre, 2 km above r1
-    rc, tc, pc = np.meshgrid(c["rc"], c["tc"], c["pc"], indexing="ij")
+    # bubble: chord distance from the centre, 2 km above r1 (separable in
+    # r, theta, phi: trigonometry on the 1-D coordinates, then broadcast)
     rb = g.r1 + w.bubble_height
     xb = rb * np.sin(w.bubble_theta) * np.cos(w.bubble_phi)
     yb = rb * np.sin(w.bubble_theta) * np.sin(w.bubble_phi)
     zb = rb * np.cos(w.bubble_theta)
-    x = rc * np.sin(tc) * np.cos(pc) - xb
-    y = rc * np.sin(tc) * np.sin(pc) - yb
-    z = rc * np.cos(tc) - zb
+    r3 = c["rc"][:, None, None]
+    st, ct = np.sin(c["tc"])[None, :, None], np.cos(c["tc"])[None, :, None]
+    sp, cp = np.sin(c["pc"])[None, None, :], np.cos(c["pc"])[None, None, :]
+    x = r3 * st * cp - xb
+    y = r3 * st * sp - yb
+    z = r3 * ct - zb
     L2 = (x * x + y * y + z * z) / (w.bubble_radius ** 2)
-    dtheta = w.amplitude * np.exp(-L2)
-    T = T0 + dtheta * (p / P00) ** (mat.R / mat.cp)
+    del x, y, z
+    # exp(-L2) is exactly 0 in FP64 beyond L2 = 746: evaluate it only nearer
+    near = L2 < 750.0
+    dtheta = np.zeros(sh["p"])
+    dtheta[near] = w.amplitude * np.exp(-L2[near])
+    exner = ((pcol / P00) ** (mat.R / mat.cp))[:, None, None]
+    T = T0 + dtheta * exner
     c0 = math.sqrt(mat.gamma * mat.R * T0)
     scale = w.mach * c0
     ur = scale * rng.uniform(-1.0, 1.0, sh["ur"])
