@@ -137,6 +137,48 @@ int dsw_set_timing(dsw_grid *grid, int32_t enable);
 int dsw_read_timing(dsw_grid *grid, void *stream, double ms[DSW_TIMING_KINDS],
                     int64_t launches[DSW_TIMING_KINDS]);
 
+/* Adjoint (reverse mode) of dsw_split_step.  The split step is a map
+ * Phi: U^n -> U^{n+1} (paper eqs. (spl1)-(spl3), K iterations); its Jacobian
+ * J is taken exactly as the discrete map is written, every iteration's
+ * midpoint linearisation and line matrices included (a discrete, not a
+ * continuous, adjoint).
+ *
+ * dsw_adjoint_step: lam_n = J(U^n)^T lam_np1 over every array entry (the
+ *   boundary-normal faces included: their entries of U^{n+1} are copies of
+ *   those of U^n).  Un is the checkpoint of the step; the forward step is
+ *   recomputed from it, keeping each iteration's midpoint and line-solve
+ *   outputs in a workspace of 4K+7 states that the handle allocates on the
+ *   first call (and grows for a larger K).  lam_n must not alias Un or
+ *   lam_np1.  tau, K: those of the forward step.
+ *
+ * The pieces, exported for tests and for custom reverse passes:
+ * dsw_line_solve_T_{r,theta,phi}: x = (I + tau/2 D_d(Ubar))^{-T} rhs, the
+ *   transposed line systems (block, scalar; cyclic on a periodic grid), same
+ *   conventions as dsw_line_solve_*.
+ * dsw_line_vjp_{r,theta,phi}: acc += (d[(I + tau/2 D_d(Ubar)) X]/dUbar)^T mu,
+ *   the transposed derivative of the line operator applied to a fixed X,
+ *   with respect to the state it is linearised at.
+ * dsw_residual_vjp: acc += (d[-tau F_h(Ubar)]/dUbar)^T mu, mu taken at the
+ *   unknowns (the rows of the boundary-normal faces are constant).
+ * The _vjp calls accumulate with FP64 atomic adds: acc must be initialised
+ * by the caller, and the last bits of the sums may vary from run to run. */
+int dsw_adjoint_step(dsw_grid *grid, const dsw_fields *Un, double tau, int32_t K,
+                     const dsw_fields *lam_np1, dsw_fields *lam_n, void *stream);
+int dsw_line_solve_T_r(dsw_grid *grid, const dsw_fields *Ubar, double tau, const dsw_fields *rhs,
+                       dsw_fields *x, void *stream);
+int dsw_line_solve_T_theta(dsw_grid *grid, const dsw_fields *Ubar, double tau,
+                           const dsw_fields *rhs, dsw_fields *x, void *stream);
+int dsw_line_solve_T_phi(dsw_grid *grid, const dsw_fields *Ubar, double tau, const dsw_fields *rhs,
+                         dsw_fields *x, void *stream);
+int dsw_line_vjp_r(dsw_grid *grid, const dsw_fields *Ubar, double tau, const dsw_fields *X,
+                   const dsw_fields *mu, dsw_fields *acc, void *stream);
+int dsw_line_vjp_theta(dsw_grid *grid, const dsw_fields *Ubar, double tau, const dsw_fields *X,
+                       const dsw_fields *mu, dsw_fields *acc, void *stream);
+int dsw_line_vjp_phi(dsw_grid *grid, const dsw_fields *Ubar, double tau, const dsw_fields *X,
+                     const dsw_fields *mu, dsw_fields *acc, void *stream);
+int dsw_residual_vjp(dsw_grid *grid, const dsw_fields *Ubar, double tau, const dsw_fields *mu,
+                     dsw_fields *acc, void *stream);
+
 /* Launch shapes of a grid's kernels (the tunable parameters; they change
  * speed, and for the phi sweep the order of rounding, never the method):
  *   residual_block        threads per workgroup of the residual (64, 128, 256)

@@ -27,21 +27,28 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "dsw_oracle.c")
 _LIB = os.path.join(_HERE, "libdsw_oracle.so")
+_LIB_CS = os.path.join(_HERE, "libdsw_oracle_cs.so")  # complex-step build
 
 MASK_R, MASK_T, MASK_F, MASK_M, MASK_ALL = 1, 2, 4, 8, 15
 FIELDS = ("p", "ur", "ut", "uf", "T")
 FID = {"p": 0, "ur": 1, "ut": 2, "uf": 3, "T": 4}
 
 
-def build(force: bool = False) -> str:
-    """Compile the oracle with gcc (no FMA contraction, no fast-math)."""
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-        tmp = _LIB + ".tmp"
+def _build_one(out, defs, force):
+    if force or not os.path.exists(out) or os.path.getmtime(out) < os.path.getmtime(_SRC):
+        tmp = out + ".tmp"
         cmd = ["gcc", "-O2", "-std=gnu11", "-fopenmp", "-ffp-contract=off", "-fno-fast-math",
-               "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"]
+               "-fPIC", "-shared"] + defs + ["-o", tmp, _SRC, "-lm"]
         subprocess.check_call(cmd)
-        os.replace(tmp, _LIB)
-    return _LIB
+        os.replace(tmp, out)
+    return out
+
+
+def build(force: bool = False) -> str:
+    """Compile the oracle with gcc (no FMA contraction, no fast-math): the FP64
+    library and its complex-step twin (same source, complex state type)."""
+    _build_one(_LIB_CS, ["-DORC_COMPLEX_STEP"], force)
+    return _build_one(_LIB, [], force)
 
 
 class _Mat(C.Structure):
@@ -61,35 +68,50 @@ class _Wall(C.Structure):
 
 
 _lib = None
+_lib_cs = None
+
+
+def _load(path):
+    L_ = C.CDLL(path)
+    P, D, I, L = C.c_void_p, C.c_double, C.c_int, C.c_long
+    L_.orc_grid_new.restype = P
+    L_.orc_grid_new.argtypes = [I, I, I, D, D, D, D, D, D, I]
+    L_.orc_grid_free.argtypes = [P]
+    FP = C.POINTER(_Fields)
+    MP = C.POINTER(_Mat)
+    WP = C.POINTER(_Wall)
+    L_.orc_apply.argtypes = [P, MP, FP, WP, FP, WP, I, FP]
+    L_.orc_residual.argtypes = [P, MP, FP, FP, WP, FP, D, FP, FP]
+    L_.orc_line_solve.argtypes = [P, MP, FP, WP, D, I, FP, FP]
+    L_.orc_line_matvec.argtypes = [P, MP, FP, WP, D, I, FP, FP]
+    L_.orc_line_blocks.argtypes = [P, MP, FP, WP, D, I, I, I, I, C.c_void_p, C.c_void_p,
+                                     C.c_void_p, C.c_void_p, C.c_void_p]
+    L_.orc_split_step.argtypes = [P, MP, FP, FP, D, I, WP, FP, FP]
+    L_.orc_residual_at.argtypes = [P, MP, FP, FP, FP, WP, D, L, C.c_void_p, C.c_void_p,
+                                     C.c_void_p]
+    L_.orc_line_solve_some.argtypes = [P, MP, FP, WP, D, I, L, C.c_void_p, C.c_void_p,
+                                         C.c_void_p, FP, FP]
+    L_.orc_block_solve.argtypes = [I, I, I, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
+    for f in ("orc_block_solve", "orc_apply", "orc_residual", "orc_line_solve", "orc_line_matvec",
+              "orc_line_blocks", "orc_split_step", "orc_residual_at", "orc_line_solve_some"):
+        getattr(L_, f).restype = I
+    return L_
 
 
 def lib():
     global _lib
     if _lib is None:
-        _lib = C.CDLL(build())
-        P, D, I, L = C.c_void_p, C.c_double, C.c_int, C.c_long
-        _lib.orc_grid_new.restype = P
-        _lib.orc_grid_new.argtypes = [I, I, I, D, D, D, D, D, D, I]
-        _lib.orc_grid_free.argtypes = [P]
-        FP = C.POINTER(_Fields)
-        MP = C.POINTER(_Mat)
-        WP = C.POINTER(_Wall)
-        _lib.orc_apply.argtypes = [P, MP, FP, WP, FP, WP, I, FP]
-        _lib.orc_residual.argtypes = [P, MP, FP, FP, WP, FP, D, FP, FP]
-        _lib.orc_line_solve.argtypes = [P, MP, FP, WP, D, I, FP, FP]
-        _lib.orc_line_matvec.argtypes = [P, MP, FP, WP, D, I, FP, FP]
-        _lib.orc_line_blocks.argtypes = [P, MP, FP, WP, D, I, I, I, I, C.c_void_p, C.c_void_p,
-                                         C.c_void_p, C.c_void_p, C.c_void_p]
-        _lib.orc_split_step.argtypes = [P, MP, FP, FP, D, I, WP, FP, FP]
-        _lib.orc_residual_at.argtypes = [P, MP, FP, FP, FP, WP, D, L, C.c_void_p, C.c_void_p,
-                                         C.c_void_p]
-        _lib.orc_line_solve_some.argtypes = [P, MP, FP, WP, D, I, L, C.c_void_p, C.c_void_p,
-                                             C.c_void_p, FP, FP]
-        _lib.orc_block_solve.argtypes = [I, I, I, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
-        for f in ("orc_block_solve", "orc_apply", "orc_residual", "orc_line_solve", "orc_line_matvec",
-                  "orc_line_blocks", "orc_split_step", "orc_residual_at", "orc_line_solve_some"):
-            getattr(_lib, f).restype = I
+        _lib = _load(build())
     return _lib
+
+
+def lib_cs():
+    """the complex-step build (state type double complex)"""
+    global _lib_cs
+    if _lib_cs is None:
+        build()
+        _lib_cs = _load(_LIB_CS)
+    return _lib_cs
 
 
 @dataclass(frozen=True)
@@ -297,3 +319,82 @@ def block_solve(L, D, U, b, cyclic=False):
     if rc != 0:
         raise ArithmeticError("zero pivot")
     return x
+
+
+# ---------------------------------------------------------- complex step --
+#
+# The complex-step build evaluates the same oracle on complex states.  At
+# U + i h V with h = 1e-30 every output equals its real value plus i h times
+# its directional derivative along V, with no subtraction of nearby values,
+# so Im(.)/h is the Jacobian-vector product exact to rounding.  A grid handle
+# of the FP64 build serves both builds (the grid struct holds only FP64
+# geometry).
+
+CS_H = 1e-30
+
+
+def _cfields(g: Grid, d, keep):
+    sh = g.shapes()
+    f = _Fields()
+    for n in FIELDS:
+        a = d[n]
+        if a.dtype != np.complex128 or not a.flags.c_contiguous or a.shape != sh[n]:
+            raise ValueError(f"field {n}: need C-contiguous complex128 of shape {sh[n]}")
+        keep.append(a)
+        setattr(f, n, a.ctypes.data_as(C.POINTER(C.c_double)))
+    return C.byref(f)
+
+
+def _czeros(g: Grid):
+    return {k: np.zeros(s, dtype=np.complex128) for k, s in g.shapes().items()}
+
+
+def _probe(U, V, h):
+    return {k: np.ascontiguousarray(np.asarray(U[k], dtype=np.float64)
+                                    + 1j * h * np.asarray(V[k], dtype=np.float64))
+            for k in FIELDS}
+
+
+def _split(Z, h):
+    return ({k: np.ascontiguousarray(v.real) for k, v in Z.items()},
+            {k: np.ascontiguousarray(v.imag / h) for k, v in Z.items()})
+
+
+def jvp_residual(g: Grid, mat: Material, Ubar, V, tau, h=CS_H):
+    """(R, dR) for Un = Uk = Ubar + e V at e = 0: R = -tau F_h(Ubar) and
+    dR = -tau J_F(Ubar) V (complex step)."""
+    keep = []
+    Z = _probe(Ubar, V, h)
+    R, Ub = _czeros(g), _czeros(g)
+    m = mat.c()
+    rc = lib_cs().orc_residual(g._h, C.byref(m), _cfields(g, Z, keep), _cfields(g, Z, keep), None,
+                               None, float(tau), _cfields(g, R, keep), _cfields(g, Ub, keep))
+    assert rc == 0
+    return _split(R, h)
+
+
+def jvp_line_matvec(g: Grid, mat: Material, Ubar, V, tau, d, X, h=CS_H):
+    """(y, dy): y = (I + tau/2 D_d(Ubar)) X and its derivative along Ubar -> V."""
+    keep = []
+    Z = _probe(Ubar, V, h)
+    Xc = _probe(X, {k: np.zeros_like(X[k]) for k in FIELDS}, h)
+    y = _czeros(g)
+    m = mat.c()
+    rc = lib_cs().orc_line_matvec(g._h, C.byref(m), _cfields(g, Z, keep), None, float(tau), int(d),
+                                  _cfields(g, Xc, keep), _cfields(g, y, keep))
+    assert rc == 0
+    return _split(y, h)
+
+
+def jvp_split_step(g: Grid, mat: Material, Un, V, tau, K, h=CS_H):
+    """(U^{n+1}, dU^{n+1}): one split step from Un + e V and its derivative
+    at e = 0 (complex step)."""
+    keep = []
+    Z = _probe(Un, V, h)
+    out = _czeros(g)
+    m = mat.c()
+    rc = lib_cs().orc_split_step(g._h, C.byref(m), _cfields(g, Z, keep), _cfields(g, out, keep),
+                                 float(tau), int(K), None, None, None)
+    if rc != 0:
+        raise ArithmeticError("zero pivot in a line solve")
+    return _split(out, h)

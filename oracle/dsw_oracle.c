@@ -48,10 +48,25 @@
 #include <stdlib.h>
 #include <string.h>
 
+/* Scalar type of the state.  The default build is FP64.  Built with
+ * -DORC_COMPLEX_STEP the same code runs on complex numbers: evaluated at
+ * U + i h V with a tiny h, every output's imaginary part divided by h is its
+ * directional derivative along V, exact to rounding (complex-step
+ * differentiation; no difference of nearby values is formed).  The tests use
+ * it to pin the GPU adjoint.  Geometry and material constants stay FP64. */
+#ifdef ORC_COMPLEX_STEP
+#include <complex.h>
+typedef double _Complex real;
+#define RMAG(x) fabs(creal(x))
+#else
+typedef double real;
+#define RMAG(x) fabs(x)
+#endif
+
 /* ---------------------------------------------------------------- types -- */
 
 typedef struct { double cp, cv, pi_inf, mu, prandtl, omega, g_r; } orc_mat;
-typedef struct { double *p, *ur, *ut, *uf, *T; } orc_fields;
+typedef struct { real *p, *ur, *ut, *uf, *T; } orc_fields;
 
 /* Tangential wall velocities used for ghost values (2g - interior).  NULL
  * entries (or a NULL struct) mean g = 0.  Shapes:
@@ -62,9 +77,9 @@ typedef struct { double *p, *ur, *ut, *uf, *T; } orc_fields;
  *   uf_r1, uf_r2 : [nt][npf]     u_phi on the r walls
  *   uf_t1, uf_t2 : [nr][npf]     u_phi on the theta walls                     */
 typedef struct {
-  const double *ur_t1, *ur_t2, *ur_p1, *ur_p2;
-  const double *ut_r1, *ut_r2, *ut_p1, *ut_p2;
-  const double *uf_r1, *uf_r2, *uf_t1, *uf_t2;
+  const real *ur_t1, *ur_t2, *ur_p1, *ur_p2;
+  const real *ut_r1, *ut_r2, *ut_p1, *ut_p2;
+  const real *uf_r1, *uf_r2, *uf_t1, *uf_t2;
 } orc_wall;
 
 typedef struct {
@@ -137,13 +152,13 @@ void orc_grid_free(orc_grid *g) {
 /* An operand is either five arrays (with optional wall data for ghosts) or a
  * single unit entry (used to probe the line matrices; homogeneous ghosts). */
 typedef struct {
-  const double *a[5];
+  const real *a[5];
   const orc_wall *w;
   int ufid;  /* >= 0: unit operand */
   long uidx;
 } opnd;
 
-static inline double rd(const opnd *v, int fid, long idx) {
+static inline real rd(const opnd *v, int fid, long idx) {
   if (v->ufid >= 0) return (fid == v->ufid && idx == v->uidx) ? 1.0 : 0.0;
   return v->a[fid][idx];
 }
@@ -158,7 +173,7 @@ static inline int kwrap(const orc_grid *g, int k) {
 static inline int clampi(int x, int lo, int hi) { return x < lo ? lo : (x > hi ? hi : x); }
 
 /* p, T at centres: zero-Neumann (copy) ghosts at every non-periodic boundary. */
-static double cval(const orc_grid *g, const opnd *v, int fid, int i, int j, int k) {
+static real cval(const orc_grid *g, const opnd *v, int fid, int i, int j, int k) {
   i = clampi(i, 0, g->nr - 1);
   j = clampi(j, 0, g->nt - 1);
   k = g->periodic ? kwrap(g, k) : clampi(k, 0, g->np - 1);
@@ -167,35 +182,35 @@ static double cval(const orc_grid *g, const opnd *v, int fid, int i, int j, int 
 
 /* u_r at r-face f (0..nr, never a ghost in r).  Tangential to theta and phi
  * boundaries: wall ghost 2g - u; pole ghost +u (symmetry). */
-static double urv(const orc_grid *g, const opnd *v, int f, int j, int k) {
+static real urv(const orc_grid *g, const opnd *v, int f, int j, int k) {
   if (k < 0 || k >= g->np) {
     if (g->periodic) k = kwrap(g, k);
     else {
       int kin = k < 0 ? 0 : g->np - 1;
       long gi = (long)f * g->nt + clampi(j, 0, g->nt - 1);
-      double gw = k < 0 ? WV(v->w, ur_p1, gi) : WV(v->w, ur_p2, gi);
+      real gw = k < 0 ? WV(v->w, ur_p1, gi) : WV(v->w, ur_p2, gi);
       return 2.0 * gw - urv(g, v, f, j, kin);
     }
   }
   if (j < 0) {
-    double in = rd(v, FR, IR(g, f, 0, k));
+    real in = rd(v, FR, IR(g, f, 0, k));
     return g->pole_lo ? in : 2.0 * WV(v->w, ur_t1, (long)f * g->np + k) - in;
   }
   if (j >= g->nt) {
-    double in = rd(v, FR, IR(g, f, g->nt - 1, k));
+    real in = rd(v, FR, IR(g, f, g->nt - 1, k));
     return g->pole_hi ? in : 2.0 * WV(v->w, ur_t2, (long)f * g->np + k) - in;
   }
   return rd(v, FR, IR(g, f, j, k));
 }
 
 /* u_theta at theta-face f (0..nt).  Tangential to r and phi boundaries. */
-static double utv(const orc_grid *g, const opnd *v, int i, int f, int k) {
+static real utv(const orc_grid *g, const opnd *v, int i, int f, int k) {
   if (k < 0 || k >= g->np) {
     if (g->periodic) k = kwrap(g, k);
     else {
       int kin = k < 0 ? 0 : g->np - 1;
       long gi = (long)clampi(i, 0, g->nr - 1) * (g->nt + 1) + f;
-      double gw = k < 0 ? WV(v->w, ut_p1, gi) : WV(v->w, ut_p2, gi);
+      real gw = k < 0 ? WV(v->w, ut_p1, gi) : WV(v->w, ut_p2, gi);
       return 2.0 * gw - utv(g, v, i, f, kin);
     }
   }
@@ -207,14 +222,14 @@ static double utv(const orc_grid *g, const opnd *v, int i, int f, int k) {
 
 /* u_phi at phi-face f (0..npf-1; wraps when periodic).  Tangential to r and
  * theta boundaries; at a pole the ghost is -u. */
-static double ufv(const orc_grid *g, const opnd *v, int i, int j, int f) {
+static real ufv(const orc_grid *g, const opnd *v, int i, int j, int f) {
   if (g->periodic) f = kwrap(g, f);
   if (j < 0 || j >= g->nt) {
     int jin = j < 0 ? 0 : g->nt - 1;
-    double in = ufv(g, v, i, jin, f);
+    real in = ufv(g, v, i, jin, f);
     if ((j < 0 && g->pole_lo) || (j >= g->nt && g->pole_hi)) return -in;
     long gi = (long)clampi(i, 0, g->nr - 1) * g->npf + f;
-    double gw = j < 0 ? WV(v->w, uf_t1, gi) : WV(v->w, uf_t2, gi);
+    real gw = j < 0 ? WV(v->w, uf_t1, gi) : WV(v->w, uf_t2, gi);
     return 2.0 * gw - in;
   }
   if (i < 0) return 2.0 * WV(v->w, uf_r1, (long)j * g->npf + f) - rd(v, FF, IF(g, 0, j, f));
@@ -225,37 +240,37 @@ static double ufv(const orc_grid *g, const opnd *v, int i, int j, int f) {
 
 /* velocity components averaged to the centre of cell (i,j,k) (may be a ghost
  * cell in the directions tangential to the component) */
-static double urc(const orc_grid *g, const opnd *v, int i, int j, int k) {
+static real urc(const orc_grid *g, const opnd *v, int i, int j, int k) {
   return 0.5 * (urv(g, v, i, j, k) + urv(g, v, i + 1, j, k));
 }
-static double utc(const orc_grid *g, const opnd *v, int i, int j, int k) {
+static real utc(const orc_grid *g, const opnd *v, int i, int j, int k) {
   return 0.5 * (utv(g, v, i, j, k) + utv(g, v, i, j + 1, k));
 }
-static double ufc(const orc_grid *g, const opnd *v, int i, int j, int k) {
+static real ufc(const orc_grid *g, const opnd *v, int i, int j, int k) {
   return 0.5 * (ufv(g, v, i, j, k) + ufv(g, v, i, j, k + 1));
 }
 
 /* ------------------------------------------------ coefficients (from u) -- */
 
-static double rho_c(const orc_grid *g, const orc_mat *m, const opnd *u, int i, int j, int k) {
-  double P = cval(g, u, FP, i, j, k) + m->pi_inf;
-  double T = cval(g, u, FTT, i, j, k);
+static real rho_c(const orc_grid *g, const orc_mat *m, const opnd *u, int i, int j, int k) {
+  real P = cval(g, u, FP, i, j, k) + m->pi_inf;
+  real T = cval(g, u, FTT, i, j, k);
   return P / ((m->cp - m->cv) * T); /* c_v (gamma-1) = c_p - c_v */
 }
 
 /* Velocity gradient G = grad u (physical spherical components) at a centre. */
 typedef struct {
-  double urc, utc, ufc, P, T, chi;
-  double Grr, Gtt, Gff, Srt, Srf, Stf, tr;
+  real urc, utc, ufc, P, T, chi;
+  real Grr, Gtt, Gff, Srt, Srf, Stf, tr;
 } ccoef;
 
 static void ccoef_at(const orc_grid *g, const orc_mat *m, const opnd *u, int i, int j, int k,
                      ccoef *c) {
-  double r = g->rc[i], s = g->sc[j], ct = g->cc[j] / g->sc[j];
-  double gam = m->cp / m->cv;
-  double r0 = urv(g, u, i, j, k), r1 = urv(g, u, i + 1, j, k);
-  double t0 = utv(g, u, i, j, k), t1 = utv(g, u, i, j + 1, k);
-  double f0 = ufv(g, u, i, j, k), f1 = ufv(g, u, i, j, k + 1);
+  real r = g->rc[i], s = g->sc[j], ct = g->cc[j] / g->sc[j];
+  real gam = m->cp / m->cv;
+  real r0 = urv(g, u, i, j, k), r1 = urv(g, u, i + 1, j, k);
+  real t0 = utv(g, u, i, j, k), t1 = utv(g, u, i, j + 1, k);
+  real f0 = ufv(g, u, i, j, k), f1 = ufv(g, u, i, j, k + 1);
   c->urc = 0.5 * (r0 + r1);
   c->utc = 0.5 * (t0 + t1);
   c->ufc = 0.5 * (f0 + f1);
@@ -278,14 +293,14 @@ static void ccoef_at(const orc_grid *g, const orc_mat *m, const opnd *u, int i, 
 /* The operand's G(v) and div(v) at a centre, keeping only the parts whose
  * direction tag is in mask (paper Appendix B, operators A2, C2: the v_r terms
  * belong to r, the theta-derivative and v_theta terms to theta, ...). */
-typedef struct { double Grr, Gtt, Gff, Srt, Srf, Stf, div; } cgrad;
+typedef struct { real Grr, Gtt, Gff, Srt, Srf, Stf, div; } cgrad;
 
 static void cgrad_at(const orc_grid *g, const opnd *v, int i, int j, int k, int mask, cgrad *q) {
-  double r = g->rc[i], s = g->sc[j], ct = g->cc[j] / g->sc[j];
-  double r0 = urv(g, v, i, j, k), r1 = urv(g, v, i + 1, j, k);
-  double t0 = utv(g, v, i, j, k), t1 = utv(g, v, i, j + 1, k);
-  double f0 = ufv(g, v, i, j, k), f1 = ufv(g, v, i, j, k + 1);
-  double vrc = 0.5 * (r0 + r1), vtc = 0.5 * (t0 + t1), vfc = 0.5 * (f0 + f1);
+  real r = g->rc[i], s = g->sc[j], ct = g->cc[j] / g->sc[j];
+  real r0 = urv(g, v, i, j, k), r1 = urv(g, v, i + 1, j, k);
+  real t0 = utv(g, v, i, j, k), t1 = utv(g, v, i, j + 1, k);
+  real f0 = ufv(g, v, i, j, k), f1 = ufv(g, v, i, j, k + 1);
+  real vrc = 0.5 * (r0 + r1), vtc = 0.5 * (t0 + t1), vfc = 0.5 * (f0 + f1);
   memset(q, 0, sizeof(*q));
   if (mask & MR) {
     q->Grr = (r1 - r0) / g->dr;
@@ -316,15 +331,15 @@ static void cgrad_at(const orc_grid *g, const opnd *v, int i, int j, int k, int 
 }
 
 /* viscous dissipation grad(u) : sigma(v), bilinear, discrete */
-static double phi_h(const orc_mat *m, const ccoef *c, const cgrad *q) {
+static real phi_h(const orc_mat *m, const ccoef *c, const cgrad *q) {
   return m->mu * (2.0 * (c->Grr * q->Grr + c->Gtt * q->Gtt + c->Gff * q->Gff) + c->Srt * q->Srt +
                   c->Srf * q->Srf + c->Stf * q->Stf - (2.0 / 3.0) * c->tr * q->div);
 }
 
 /* u . grad f for a centre scalar, central differences over two cells */
-static double cadv(const orc_grid *g, const opnd *v, int fid, const ccoef *c, int i, int j,
+static real cadv(const orc_grid *g, const opnd *v, int fid, const ccoef *c, int i, int j,
                    int k, int mask) {
-  double r = g->rc[i], s = g->sc[j], a = 0.0;
+  real r = g->rc[i], s = g->sc[j], a = 0.0;
   if (mask & MR)
     a += c->urc * (cval(g, v, fid, i + 1, j, k) - cval(g, v, fid, i - 1, j, k)) / (2.0 * g->dr);
   if (mask & MT)
@@ -336,8 +351,8 @@ static double cadv(const orc_grid *g, const opnd *v, int fid, const ccoef *c, in
 }
 
 /* conservative scalar Laplacian of a centre field (zero-flux through walls) */
-static double clap(const orc_grid *g, const opnd *v, int fid, int i, int j, int k, int mask) {
-  double r = g->rc[i], s = g->sc[j], f0 = cval(g, v, fid, i, j, k), L = 0.0;
+static real clap(const orc_grid *g, const opnd *v, int fid, int i, int j, int k, int mask) {
+  real r = g->rc[i], s = g->sc[j], f0 = cval(g, v, fid, i, j, k), L = 0.0;
   if (mask & MR)
     L += (g->rf[i + 1] * g->rf[i + 1] * (cval(g, v, fid, i + 1, j, k) - f0) -
           g->rf[i] * g->rf[i] * (f0 - cval(g, v, fid, i - 1, j, k))) /
@@ -353,9 +368,9 @@ static double clap(const orc_grid *g, const opnd *v, int fid, int i, int j, int 
 }
 
 /* divergence of v at centre (i,j,k), split by direction */
-static void cdiv(const orc_grid *g, const opnd *v, int i, int j, int k, double *dr_, double *dt_,
-                 double *dp_) {
-  double r = g->rc[i], s = g->sc[j];
+static void cdiv(const orc_grid *g, const opnd *v, int i, int j, int k, real *dr_, real *dt_,
+                 real *dp_) {
+  real r = g->rc[i], s = g->sc[j];
   *dr_ = (g->rf[i + 1] * g->rf[i + 1] * urv(g, v, i + 1, j, k) -
           g->rf[i] * g->rf[i] * urv(g, v, i, j, k)) / (r * r * g->dr);
   *dt_ = (g->sf[j + 1] * utv(g, v, i, j + 1, k) - g->sf[j] * utv(g, v, i, j, k)) /
@@ -366,9 +381,9 @@ static void cdiv(const orc_grid *g, const opnd *v, int i, int j, int k, double *
 /* ------------------------------------------------------------- row forms -- */
 
 /* pressure equation (nonconservener) at a centre */
-static double row_p(const orc_grid *g, const orc_mat *m, const ccoef *c, const opnd *v, int i,
+static real row_p(const orc_grid *g, const orc_mat *m, const ccoef *c, const opnd *v, int i,
                     int j, int k, int mask) {
-  double gam = m->cp / m->cv, kap = m->mu * m->cp / m->prandtl;
+  real gam = m->cp / m->cv, kap = m->mu * m->cp / m->prandtl;
   cgrad q;
   cgrad_at(g, v, i, j, k, mask, &q);
   return cadv(g, v, FP, c, i, j, k, mask) + gam * c->P * q.div - (gam - 1.0) * phi_h(m, c, &q) -
@@ -376,9 +391,9 @@ static double row_p(const orc_grid *g, const orc_mat *m, const ccoef *c, const o
 }
 
 /* temperature equation (nonconservmass) at a centre */
-static double row_T(const orc_grid *g, const orc_mat *m, const ccoef *c, const opnd *v, int i,
+static real row_T(const orc_grid *g, const orc_mat *m, const ccoef *c, const opnd *v, int i,
                     int j, int k, int mask) {
-  double gam = m->cp / m->cv, kap = m->mu * m->cp / m->prandtl;
+  real gam = m->cp / m->cv, kap = m->mu * m->cp / m->prandtl;
   cgrad q;
   cgrad_at(g, v, i, j, k, mask, &q);
   return cadv(g, v, FTT, c, i, j, k, mask) + (gam - 1.0) * c->T * q.div - c->chi * phi_h(m, c, &q) -
@@ -387,7 +402,7 @@ static double row_T(const orc_grid *g, const orc_mat *m, const ccoef *c, const o
 
 /* coefficients at a face: density (mean of the two cells), the normal
  * velocity on the face and the two transverse components interpolated to it */
-typedef struct { double rho, un, ua, ub; } fcoef;
+typedef struct { real rho, un, ua, ub; } fcoef;
 
 static void fcoef_r(const orc_grid *g, const orc_mat *m, const opnd *u, int f, int j, int k,
                     fcoef *c) {
@@ -419,17 +434,17 @@ static void fcoef_f(const orc_grid *g, const orc_mat *m, const opnd *u, int i, i
 }
 
 /* radial momentum (nonconservmom, r component) at interior r-face (f,j,k) */
-static double row_ur(const orc_grid *g, const orc_mat *m, const fcoef *c, const opnd *v, int f,
+static real row_ur(const orc_grid *g, const orc_mat *m, const fcoef *c, const opnd *v, int f,
                      int j, int k, int mask) {
-  double rF = g->rf[f], s = g->sc[j], nu = m->mu / c->rho, N = 0.0, vis = 0.0, gd = 0.0;
-  double x0 = urv(g, v, f, j, k);
+  real rF = g->rf[f], s = g->sc[j], nu = m->mu / c->rho, N = 0.0, vis = 0.0, gd = 0.0;
+  real x0 = urv(g, v, f, j, k);
   if (mask & MR) {
     N += (cval(g, v, FP, f, j, k) - cval(g, v, FP, f - 1, j, k)) / (c->rho * g->dr);
     N += c->un * (urv(g, v, f + 1, j, k) - urv(g, v, f - 1, j, k)) / (2.0 * g->dr);
     vis += (g->rc[f] * g->rc[f] * (urv(g, v, f + 1, j, k) - x0) -
             g->rc[f - 1] * g->rc[f - 1] * (x0 - urv(g, v, f - 1, j, k))) /
            (rF * rF * g->dr * g->dr);
-    double a0, b0, c0, a1, b1, c1;
+    real a0, b0, c0, a1, b1, c1;
     cdiv(g, v, f - 1, j, k, &a0, &b0, &c0);
     cdiv(g, v, f, j, k, &a1, &b1, &c1);
     gd += (a1 - a0) / g->dr;
@@ -444,19 +459,19 @@ static double row_ur(const orc_grid *g, const orc_mat *m, const fcoef *c, const 
     vis += (urv(g, v, f, j, k + 1) - 2.0 * x0 + urv(g, v, f, j, k - 1)) / (rF * rF * s * s * g->dp * g->dp);
   }
   if (mask & MM) {
-    double va = 0.25 * (utv(g, v, f - 1, j, k) + utv(g, v, f - 1, j + 1, k) + utv(g, v, f, j, k) +
+    real va = 0.25 * (utv(g, v, f - 1, j, k) + utv(g, v, f - 1, j + 1, k) + utv(g, v, f, j, k) +
                         utv(g, v, f, j + 1, k));
-    double vb = 0.25 * (ufv(g, v, f - 1, j, k) + ufv(g, v, f - 1, j, k + 1) + ufv(g, v, f, j, k) +
+    real vb = 0.25 * (ufv(g, v, f - 1, j, k) + ufv(g, v, f - 1, j, k + 1) + ufv(g, v, f, j, k) +
                         ufv(g, v, f, j, k + 1));
     N += -(c->ua * va + c->ub * vb) / rF;
-    double dth = 0.5 *
+    real dth = 0.5 *
                  ((g->sf[j + 1] * utv(g, v, f - 1, j + 1, k) - g->sf[j] * utv(g, v, f - 1, j, k)) +
                   (g->sf[j + 1] * utv(g, v, f, j + 1, k) - g->sf[j] * utv(g, v, f, j, k))) / g->dt;
-    double dph = 0.5 *
+    real dph = 0.5 *
                  ((ufv(g, v, f - 1, j, k + 1) - ufv(g, v, f - 1, j, k)) +
                   (ufv(g, v, f, j, k + 1) - ufv(g, v, f, j, k))) / g->dp;
     vis += -2.0 * x0 / (rF * rF) - 2.0 / (rF * rF * s) * dth - 2.0 / (rF * rF * s) * dph;
-    double a0, b0, c0, a1, b1, c1;
+    real a0, b0, c0, a1, b1, c1;
     cdiv(g, v, f - 1, j, k, &a0, &b0, &c0);
     cdiv(g, v, f, j, k, &a1, &b1, &c1);
     gd += (b1 - b0) / g->dr + (c1 - c0) / g->dr;
@@ -466,18 +481,18 @@ static double row_ur(const orc_grid *g, const orc_mat *m, const fcoef *c, const 
 }
 
 /* colatitudinal momentum at interior theta-face (i,f,k) */
-static double row_ut(const orc_grid *g, const orc_mat *m, const fcoef *c, const opnd *v, int i,
+static real row_ut(const orc_grid *g, const orc_mat *m, const fcoef *c, const opnd *v, int i,
                      int f, int k, int mask) {
-  double r = g->rc[i], s = g->sf[f], ctF = g->cf[f] / g->sf[f];
-  double nu = m->mu / c->rho, N = 0.0, vis = 0.0, gd = 0.0;
+  real r = g->rc[i], s = g->sf[f], ctF = g->cf[f] / g->sf[f];
+  real nu = m->mu / c->rho, N = 0.0, vis = 0.0, gd = 0.0;
   int j0 = f - 1, j1 = f;
-  double x0 = utv(g, v, i, f, k);
+  real x0 = utv(g, v, i, f, k);
   if (mask & MT) {
     N += (cval(g, v, FP, i, j1, k) - cval(g, v, FP, i, j0, k)) / (c->rho * r * g->dt);
     N += c->un / r * (utv(g, v, i, f + 1, k) - utv(g, v, i, f - 1, k)) / (2.0 * g->dt);
     vis += (g->sc[j1] * (utv(g, v, i, f + 1, k) - x0) - g->sc[j0] * (x0 - utv(g, v, i, f - 1, k))) /
            (r * r * s * g->dt * g->dt);
-    double a0, b0, c0, a1, b1, c1;
+    real a0, b0, c0, a1, b1, c1;
     cdiv(g, v, i, j0, k, &a0, &b0, &c0);
     cdiv(g, v, i, j1, k, &a1, &b1, &c1);
     gd += (b1 - b0) / (r * g->dt);
@@ -493,19 +508,19 @@ static double row_ut(const orc_grid *g, const orc_mat *m, const fcoef *c, const 
     vis += (utv(g, v, i, f, k + 1) - 2.0 * x0 + utv(g, v, i, f, k - 1)) / (r * r * s * s * g->dp * g->dp);
   }
   if (mask & MM) {
-    double va = 0.25 * (urv(g, v, i, j0, k) + urv(g, v, i, j1, k) + urv(g, v, i + 1, j0, k) +
+    real va = 0.25 * (urv(g, v, i, j0, k) + urv(g, v, i, j1, k) + urv(g, v, i + 1, j0, k) +
                         urv(g, v, i + 1, j1, k));
-    double vb = 0.25 * (ufv(g, v, i, j0, k) + ufv(g, v, i, j0, k + 1) + ufv(g, v, i, j1, k) +
+    real vb = 0.25 * (ufv(g, v, i, j0, k) + ufv(g, v, i, j0, k + 1) + ufv(g, v, i, j1, k) +
                         ufv(g, v, i, j1, k + 1));
     N += (c->un * va - c->ub * vb * ctF) / r;
-    double dthr = 0.5 *
+    real dthr = 0.5 *
                   ((urv(g, v, i, j1, k) - urv(g, v, i, j0, k)) +
                    (urv(g, v, i + 1, j1, k) - urv(g, v, i + 1, j0, k))) / g->dt;
-    double dphf = 0.5 *
+    real dphf = 0.5 *
                   ((ufv(g, v, i, j0, k + 1) - ufv(g, v, i, j0, k)) +
                    (ufv(g, v, i, j1, k + 1) - ufv(g, v, i, j1, k))) / g->dp;
     vis += -x0 / (r * r * s * s) + 2.0 / (r * r) * dthr - 2.0 * ctF / (r * r * s) * dphf;
-    double a0, b0, c0, a1, b1, c1;
+    real a0, b0, c0, a1, b1, c1;
     cdiv(g, v, i, j0, k, &a0, &b0, &c0);
     cdiv(g, v, i, j1, k, &a1, &b1, &c1);
     gd += (a1 - a0) / (r * g->dt) + (c1 - c0) / (r * g->dt);
@@ -515,17 +530,17 @@ static double row_ut(const orc_grid *g, const orc_mat *m, const fcoef *c, const 
 }
 
 /* azimuthal momentum at interior phi-face (i,j,f) */
-static double row_uf(const orc_grid *g, const orc_mat *m, const fcoef *c, const opnd *v, int i,
+static real row_uf(const orc_grid *g, const orc_mat *m, const fcoef *c, const opnd *v, int i,
                      int j, int f, int mask) {
-  double r = g->rc[i], s = g->sc[j], ct = g->cc[j] / g->sc[j];
-  double nu = m->mu / c->rho, N = 0.0, vis = 0.0, gd = 0.0;
+  real r = g->rc[i], s = g->sc[j], ct = g->cc[j] / g->sc[j];
+  real nu = m->mu / c->rho, N = 0.0, vis = 0.0, gd = 0.0;
   int k0 = g->periodic ? kwrap(g, f - 1) : f - 1, k1 = g->periodic ? kwrap(g, f) : f;
-  double x0 = ufv(g, v, i, j, f);
+  real x0 = ufv(g, v, i, j, f);
   if (mask & MF) {
     N += (cval(g, v, FP, i, j, k1) - cval(g, v, FP, i, j, k0)) / (c->rho * r * s * g->dp);
     N += c->un / (r * s) * (ufv(g, v, i, j, f + 1) - ufv(g, v, i, j, f - 1)) / (2.0 * g->dp);
     vis += (ufv(g, v, i, j, f + 1) - 2.0 * x0 + ufv(g, v, i, j, f - 1)) / (r * r * s * s * g->dp * g->dp);
-    double a0, b0, c0, a1, b1, c1;
+    real a0, b0, c0, a1, b1, c1;
     cdiv(g, v, i, j, k0, &a0, &b0, &c0);
     cdiv(g, v, i, j, k1, &a1, &b1, &c1);
     gd += (c1 - c0) / (r * s * g->dp);
@@ -542,19 +557,19 @@ static double row_uf(const orc_grid *g, const orc_mat *m, const fcoef *c, const 
            (r * r * s * g->dt * g->dt);
   }
   if (mask & MM) {
-    double va = 0.25 * (urv(g, v, i, j, k0) + urv(g, v, i, j, k1) + urv(g, v, i + 1, j, k0) +
+    real va = 0.25 * (urv(g, v, i, j, k0) + urv(g, v, i, j, k1) + urv(g, v, i + 1, j, k0) +
                         urv(g, v, i + 1, j, k1));
-    double vb = 0.25 * (utv(g, v, i, j, k0) + utv(g, v, i, j, k1) + utv(g, v, i, j + 1, k0) +
+    real vb = 0.25 * (utv(g, v, i, j, k0) + utv(g, v, i, j, k1) + utv(g, v, i, j + 1, k0) +
                         utv(g, v, i, j + 1, k1));
     N += c->un * (va + vb * ct) / r;
-    double dphr = 0.5 *
+    real dphr = 0.5 *
                   ((urv(g, v, i, j, k1) - urv(g, v, i, j, k0)) +
                    (urv(g, v, i + 1, j, k1) - urv(g, v, i + 1, j, k0))) / g->dp;
-    double dpht = 0.5 *
+    real dpht = 0.5 *
                   ((utv(g, v, i, j, k1) - utv(g, v, i, j, k0)) +
                    (utv(g, v, i, j + 1, k1) - utv(g, v, i, j + 1, k0))) / g->dp;
     vis += -x0 / (r * r * s * s) + 2.0 / (r * r * s) * dphr + 2.0 * ct / (r * r * s) * dpht;
-    double a0, b0, c0, a1, b1, c1;
+    real a0, b0, c0, a1, b1, c1;
     cdiv(g, v, i, j, k0, &a0, &b0, &c0);
     cdiv(g, v, i, j, k1, &a1, &b1, &c1);
     gd += (a1 - a0) / (r * s * g->dp) + (b1 - b0) / (r * s * g->dp);
@@ -577,11 +592,11 @@ static opnd mk_opnd(const orc_fields *x, const orc_wall *w) {
 }
 
 static void zero_fields(const orc_grid *g, orc_fields *x) {
-  memset(x->p, 0, sizeof(double) * fsize(g, FP));
-  memset(x->ur, 0, sizeof(double) * fsize(g, FR));
-  memset(x->ut, 0, sizeof(double) * fsize(g, FT));
-  memset(x->uf, 0, sizeof(double) * fsize(g, FF));
-  memset(x->T, 0, sizeof(double) * fsize(g, FTT));
+  memset(x->p, 0, sizeof(real) * fsize(g, FP));
+  memset(x->ur, 0, sizeof(real) * fsize(g, FR));
+  memset(x->ut, 0, sizeof(real) * fsize(g, FT));
+  memset(x->uf, 0, sizeof(real) * fsize(g, FF));
+  memset(x->T, 0, sizeof(real) * fsize(g, FTT));
 }
 
 /* out = N(u; v) restricted to the terms in mask, at every unknown; boundary
@@ -634,21 +649,21 @@ int orc_apply(const orc_grid *g, const orc_mat *m, const orc_fields *uf_, const 
 int orc_residual(const orc_grid *g, const orc_mat *m, const orc_fields *Un, const orc_fields *Uk,
                  const orc_wall *wall, const orc_fields *src, double tau, orc_fields *R,
                  orc_fields *Ub) {
-  double *un[5] = {Un->p, Un->ur, Un->ut, Un->uf, Un->T};
-  double *uk[5] = {Uk->p, Uk->ur, Uk->ut, Uk->uf, Uk->T};
-  double *ub[5] = {Ub->p, Ub->ur, Ub->ut, Ub->uf, Ub->T};
-  double *rr[5] = {R->p, R->ur, R->ut, R->uf, R->T};
+  real *un[5] = {Un->p, Un->ur, Un->ut, Un->uf, Un->T};
+  real *uk[5] = {Uk->p, Uk->ur, Uk->ut, Uk->uf, Uk->T};
+  real *ub[5] = {Ub->p, Ub->ur, Ub->ut, Ub->uf, Ub->T};
+  real *rr[5] = {R->p, R->ur, R->ut, R->uf, R->T};
   for (int q = 0; q < 5; q++) {
     long n = fsize(g, q);
     for (long x = 0; x < n; x++) ub[q][x] = 0.5 * (uk[q][x] + un[q][x]);
   }
   orc_fields F;
-  F.p = malloc(sizeof(double) * fsize(g, FP)); F.ur = malloc(sizeof(double) * fsize(g, FR));
-  F.ut = malloc(sizeof(double) * fsize(g, FT)); F.uf = malloc(sizeof(double) * fsize(g, FF));
-  F.T = malloc(sizeof(double) * fsize(g, FTT));
+  F.p = malloc(sizeof(real) * fsize(g, FP)); F.ur = malloc(sizeof(real) * fsize(g, FR));
+  F.ut = malloc(sizeof(real) * fsize(g, FT)); F.uf = malloc(sizeof(real) * fsize(g, FF));
+  F.T = malloc(sizeof(real) * fsize(g, FTT));
   orc_apply(g, m, Ub, wall, Ub, wall, MALL, &F);
-  double *ff[5] = {F.p, F.ur, F.ut, F.uf, F.T};
-  const double *ss[5] = {0, 0, 0, 0, 0};
+  real *ff[5] = {F.p, F.ur, F.ut, F.uf, F.T};
+  const real *ss[5] = {0, 0, 0, 0, 0};
   if (src) { ss[0] = src->p; ss[1] = src->ur; ss[2] = src->ut; ss[3] = src->uf; ss[4] = src->T; }
   for (int q = 0; q < 5; q++) {
     long n = fsize(g, q);
@@ -660,7 +675,7 @@ int orc_residual(const orc_grid *g, const orc_mat *m, const orc_fields *Un, cons
       for (int k = 0; k < g->np; k++) {
         long x = IC(g, i, j, k);
         for (int q = 0; q < 5; q += 4) {
-          double fx = ff[q][x] - (ss[q] ? ss[q][x] : 0.0);
+          real fx = ff[q][x] - (ss[q] ? ss[q][x] : 0.0);
           rr[q][x] = -(uk[q][x] - un[q][x]) - tau * fx;
         }
       }
@@ -668,21 +683,21 @@ int orc_residual(const orc_grid *g, const orc_mat *m, const orc_fields *Un, cons
     for (int j = 0; j < g->nt; j++)
       for (int k = 0; k < g->np; k++) {
         long x = IR(g, f, j, k);
-        double fx = ff[FR][x] + m->g_r - (ss[FR] ? ss[FR][x] : 0.0);
+        real fx = ff[FR][x] + m->g_r - (ss[FR] ? ss[FR][x] : 0.0);
         rr[FR][x] = -(uk[FR][x] - un[FR][x]) - tau * fx;
       }
   for (int i = 0; i < g->nr; i++)
     for (int f = 1; f < g->nt; f++)
       for (int k = 0; k < g->np; k++) {
         long x = IT(g, i, f, k);
-        double fx = ff[FT][x] - (ss[FT] ? ss[FT][x] : 0.0);
+        real fx = ff[FT][x] - (ss[FT] ? ss[FT][x] : 0.0);
         rr[FT][x] = -(uk[FT][x] - un[FT][x]) - tau * fx;
       }
   for (int i = 0; i < g->nr; i++)
     for (int j = 0; j < g->nt; j++)
       for (int f = uf_lo(g); f <= uf_hi(g); f++) {
         long x = IF(g, i, j, f);
-        double fx = ff[FF][x] - (ss[FF] ? ss[FF][x] : 0.0);
+        real fx = ff[FF][x] - (ss[FF] ? ss[FF][x] : 0.0);
         rr[FF][x] = -(uk[FF][x] - un[FF][x]) - tau * fx;
       }
   free(F.p); free(F.ur); free(F.ut); free(F.uf); free(F.T);
@@ -693,25 +708,25 @@ int orc_residual(const orc_grid *g, const orc_mat *m, const orc_fields *Un, cons
 
 /* Solve A X = B, A bs x bs, B bs x nc (row-major), Gaussian elimination with
  * partial pivoting.  Result overwrites B.  Returns -1 on a zero pivot. */
-static int small_solve(int bs, double *A, int nc, double *B) {
+static int small_solve(int bs, real *A, int nc, real *B) {
   for (int c = 0; c < bs; c++) {
     int piv = c;
     for (int r = c + 1; r < bs; r++)
-      if (fabs(A[r * bs + c]) > fabs(A[piv * bs + c])) piv = r;
+      if (RMAG(A[r * bs + c]) > RMAG(A[piv * bs + c])) piv = r;
     if (A[piv * bs + c] == 0.0) return -1;
     if (piv != c) {
-      for (int q = 0; q < bs; q++) { double t = A[c * bs + q]; A[c * bs + q] = A[piv * bs + q]; A[piv * bs + q] = t; }
-      for (int q = 0; q < nc; q++) { double t = B[c * nc + q]; B[c * nc + q] = B[piv * nc + q]; B[piv * nc + q] = t; }
+      for (int q = 0; q < bs; q++) { real t = A[c * bs + q]; A[c * bs + q] = A[piv * bs + q]; A[piv * bs + q] = t; }
+      for (int q = 0; q < nc; q++) { real t = B[c * nc + q]; B[c * nc + q] = B[piv * nc + q]; B[piv * nc + q] = t; }
     }
     for (int r = c + 1; r < bs; r++) {
-      double l = A[r * bs + c] / A[c * bs + c];
+      real l = A[r * bs + c] / A[c * bs + c];
       for (int q = c; q < bs; q++) A[r * bs + q] -= l * A[c * bs + q];
       for (int q = 0; q < nc; q++) B[r * nc + q] -= l * B[c * nc + q];
     }
   }
   for (int c = bs - 1; c >= 0; c--)
     for (int q = 0; q < nc; q++) {
-      double s = B[c * nc + q];
+      real s = B[c * nc + q];
       for (int t = c + 1; t < bs; t++) s -= A[c * bs + t] * B[t * nc + q];
       B[c * nc + q] = s / A[c * bs + c];
     }
@@ -721,29 +736,29 @@ static int small_solve(int bs, double *A, int nc, double *B) {
 /* Block Thomas for rows 0..n-1: L[i] x[i-1] + D[i] x[i] + U[i] x[i+1] = b[i]
  * (L[0], U[n-1] ignored), bs x bs blocks, nc right-hand-side columns.
  * b (n x bs x nc) is overwritten by the solution.  work: n*bs*bs doubles. */
-static int block_thomas(int n, int bs, const double *L, const double *D, const double *U,
-                        int nc, double *b, double *C) {
-  double A[9], T[9 * 8], tmp[3 * 8];
+static int block_thomas(int n, int bs, const real *L, const real *D, const real *U,
+                        int nc, real *b, real *C) {
+  real A[9], T[9 * 8], tmp[3 * 8];
   int bb = bs * bs, bn = bs * nc, w = bs + nc;
   for (int i = 0; i < n; i++) {
-    memcpy(A, D + (long)i * bb, sizeof(double) * bb);
-    double *bi = b + (long)i * bn;
+    memcpy(A, D + (long)i * bb, sizeof(real) * bb);
+    real *bi = b + (long)i * bn;
     if (i > 0) {
-      const double *Li = L + (long)i * bb, *Cp = C + (long)(i - 1) * bb, *yp = b + (long)(i - 1) * bn;
+      const real *Li = L + (long)i * bb, *Cp = C + (long)(i - 1) * bb, *yp = b + (long)(i - 1) * bn;
       for (int r = 0; r < bs; r++)
         for (int c = 0; c < bs; c++) {
-          double s = 0.0;
+          real s = 0.0;
           for (int t = 0; t < bs; t++) s += Li[r * bs + t] * Cp[t * bs + c];
           A[r * bs + c] -= s;
         }
       for (int r = 0; r < bs; r++)
         for (int c = 0; c < nc; c++) {
-          double s = 0.0;
+          real s = 0.0;
           for (int t = 0; t < bs; t++) s += Li[r * bs + t] * yp[t * nc + c];
           tmp[r * nc + c] = bi[r * nc + c] - s;
         }
     } else {
-      memcpy(tmp, bi, sizeof(double) * bn);
+      memcpy(tmp, bi, sizeof(real) * bn);
     }
     for (int r = 0; r < bs; r++) {
       for (int c = 0; c < bs; c++) T[r * w + c] = (i < n - 1) ? U[(long)i * bb + r * bs + c] : 0.0;
@@ -756,11 +771,11 @@ static int block_thomas(int n, int bs, const double *L, const double *D, const d
     }
   }
   for (int i = n - 2; i >= 0; i--) {
-    double *xi = b + (long)i * bn, *xn = b + (long)(i + 1) * bn;
-    const double *Ci = C + (long)i * bb;
+    real *xi = b + (long)i * bn, *xn = b + (long)(i + 1) * bn;
+    const real *Ci = C + (long)i * bb;
     for (int r = 0; r < bs; r++)
       for (int c = 0; c < nc; c++) {
-        double s = 0.0;
+        real s = 0.0;
         for (int t = 0; t < bs; t++) s += Ci[r * bs + t] * xn[t * nc + c];
         xi[r * nc + c] -= s;
       }
@@ -772,15 +787,15 @@ static int block_thomas(int n, int bs, const double *L, const double *D, const d
  * x[0] through U[n-1].  Bordered elimination of the last block: for rows
  * 0..n-2 solve A'[y | Z] = [b | E] (E: L[0] in row 0, U[n-2] in row n-2),
  * then x[n-1] from row n-1, then x = y - Z x[n-1].  b (n x bs) overwritten. */
-static int block_cyclic(int n, int bs, const double *L, const double *D, const double *U,
-                        double *b) {
+static int block_cyclic(int n, int bs, const real *L, const real *D, const real *U,
+                        real *b) {
   int bb = bs * bs, nc = 1 + bs, m = n - 1;
-  double *L2 = calloc((size_t)m * bb, sizeof(double)), *U2 = calloc((size_t)m * bb, sizeof(double));
-  double *B2 = calloc((size_t)m * bs * nc, sizeof(double)), *C = calloc((size_t)m * bb, sizeof(double));
-  memcpy(L2, L, sizeof(double) * m * bb);
-  memcpy(U2, U, sizeof(double) * m * bb);
-  memset(L2, 0, sizeof(double) * bb);                      /* row 0 L -> border */
-  memset(U2 + (long)(m - 1) * bb, 0, sizeof(double) * bb); /* row n-2 U -> border */
+  real *L2 = calloc((size_t)m * bb, sizeof(real)), *U2 = calloc((size_t)m * bb, sizeof(real));
+  real *B2 = calloc((size_t)m * bs * nc, sizeof(real)), *C = calloc((size_t)m * bb, sizeof(real));
+  memcpy(L2, L, sizeof(real) * m * bb);
+  memcpy(U2, U, sizeof(real) * m * bb);
+  memset(L2, 0, sizeof(real) * bb);                      /* row 0 L -> border */
+  memset(U2 + (long)(m - 1) * bb, 0, sizeof(real) * bb); /* row n-2 U -> border */
   for (int i = 0; i < m; i++)
     for (int r = 0; r < bs; r++) B2[(long)i * bs * nc + r * nc] = b[(long)i * bs + r];
   for (int r = 0; r < bs; r++)
@@ -790,15 +805,15 @@ static int block_cyclic(int n, int bs, const double *L, const double *D, const d
     }
   int rc = block_thomas(m, bs, L2, D, U2, nc, B2, C);
   if (!rc) {
-    double A[9], rhs[3];
-    const double *Ln = L + (long)(n - 1) * bb, *Dn = D + (long)(n - 1) * bb, *Un = U + (long)(n - 1) * bb;
-    const double *Yl = B2 + (long)(m - 1) * bs * nc, *Y0 = B2;
+    real A[9], rhs[3];
+    const real *Ln = L + (long)(n - 1) * bb, *Dn = D + (long)(n - 1) * bb, *Un = U + (long)(n - 1) * bb;
+    const real *Yl = B2 + (long)(m - 1) * bs * nc, *Y0 = B2;
     for (int r = 0; r < bs; r++) {
-      double s = b[(long)(n - 1) * bs + r];
+      real s = b[(long)(n - 1) * bs + r];
       for (int t = 0; t < bs; t++) s -= Ln[r * bs + t] * Yl[t * nc] + Un[r * bs + t] * Y0[t * nc];
       rhs[r] = s;
       for (int c = 0; c < bs; c++) {
-        double a = Dn[r * bs + c];
+        real a = Dn[r * bs + c];
         for (int t = 0; t < bs; t++) a -= Ln[r * bs + t] * Yl[t * nc + 1 + c] + Un[r * bs + t] * Y0[t * nc + 1 + c];
         A[r * bs + c] = a;
       }
@@ -808,7 +823,7 @@ static int block_cyclic(int n, int bs, const double *L, const double *D, const d
       for (int r = 0; r < bs; r++) b[(long)(n - 1) * bs + r] = rhs[r];
       for (int i = 0; i < m; i++)
         for (int r = 0; r < bs; r++) {
-          double s = B2[(long)i * bs * nc + r * nc];
+          real s = B2[(long)i * bs * nc + r * nc];
           for (int c = 0; c < bs; c++) s -= B2[(long)i * bs * nc + r * nc + 1 + c] * rhs[c];
           b[(long)i * bs + r] = s;
         }
@@ -872,7 +887,7 @@ static int dmask(int d) { return d == 0 ? MR : (d == 1 ? MT : MF); }
 
 /* Evaluate the row of block s, component q (0 p-row, 1 T-row, 2 w-row) of
  * N_d(u; v). */
-static double block_row(const orc_grid *g, const orc_mat *m, const opnd *u, const opnd *v,
+static real block_row(const orc_grid *g, const orc_mat *m, const opnd *u, const opnd *v,
                         const line_t *L, int s, int q, const ccoef *cc, const fcoef *fc) {
   int mask = dmask(L->d);
   int i, j, k;
@@ -896,11 +911,11 @@ static void block_fcoef(const orc_grid *g, const orc_mat *m, const opnd *u, cons
 /* Assemble (I + tau/2 N_d(Ubar; .)) on a block line by probing with unit
  * operands.  Lb, Db, Ub: n x 9 each. */
 static void assemble_block(const orc_grid *g, const orc_mat *m, const opnd *u, const line_t *L,
-                           double tau, double *Lb, double *Db, double *Ub) {
+                           double tau, real *Lb, real *Db, real *Ub) {
   int n = L->n;
-  memset(Lb, 0, sizeof(double) * 9 * n);
-  memset(Db, 0, sizeof(double) * 9 * n);
-  memset(Ub, 0, sizeof(double) * 9 * n);
+  memset(Lb, 0, sizeof(real) * 9 * n);
+  memset(Db, 0, sizeof(real) * 9 * n);
+  memset(Ub, 0, sizeof(real) * 9 * n);
   for (int s = 0; s < n; s++) {
     ccoef cc;
     fcoef fc;
@@ -913,7 +928,7 @@ static void assemble_block(const orc_grid *g, const orc_mat *m, const opnd *u, c
       int s2 = s + off;
       if (!L->cyclic && (s2 < 0 || s2 >= n)) continue;
       int s2w = L->cyclic ? ((s2 % n) + n) % n : s2;
-      double *blk = off < 0 ? Lb : (off == 0 ? Db : Ub);
+      real *blk = off < 0 ? Lb : (off == 0 ? Db : Ub);
       for (int q2 = 0; q2 < 3; q2++) {
         opnd e;
         memset(&e, 0, sizeof(e));
@@ -921,7 +936,7 @@ static void assemble_block(const orc_grid *g, const orc_mat *m, const opnd *u, c
         if (!block_unknown(g, L, s2w, q2, &e.ufid, &e.uidx)) continue;
         for (int q = 0; q < 3; q++) {
           if (q == 2 && !w_is_unknown) continue;
-          double val = block_row(g, m, u, &e, L, s, q, &cc, &fc);
+          real val = block_row(g, m, u, &e, L, s, q, &cc, &fc);
           blk[(long)s * 9 + q * 3 + q2] += 0.5 * tau * val;
         }
       }
@@ -938,7 +953,7 @@ static void assemble_block(const orc_grid *g, const orc_mat *m, const opnd *u, c
 }
 
 /* scalar line: the component tcomp at position s */
-static double scalar_row(const orc_grid *g, const orc_mat *m, const opnd *v, const line_t *L,
+static real scalar_row(const orc_grid *g, const orc_mat *m, const opnd *v, const line_t *L,
                          int s, const fcoef *fc) {
   int mask = dmask(L->d);
   int i, j, k; /* position of the face in (i,j,k) face-index space */
@@ -962,12 +977,12 @@ static void scalar_fcoef(const orc_grid *g, const orc_mat *m, const opnd *u, con
 }
 
 static void assemble_scalar(const orc_grid *g, const orc_mat *m, const opnd *u, const line_t *L,
-                            double tau, double *a, double *bd, double *c) {
+                            double tau, real *a, real *bd, real *c) {
   int n = L->n;
   for (int s = 0; s < n; s++) {
     fcoef fc;
     scalar_fcoef(g, m, u, L, s, &fc);
-    double co[3] = {0, 0, 0};
+    real co[3] = {0, 0, 0};
     for (int off = -1; off <= 1; off++) {
       int s2 = s + off;
       if (!L->cyclic && (s2 < 0 || s2 >= n)) continue;
@@ -1017,10 +1032,10 @@ static long enum_lines(const orc_grid *g, int d, line_t *out) {
 
 /* ------------------------------------------------------------ line solve -- */
 
-static const double *fld(const orc_fields *x, int fid) {
+static const real *fld(const orc_fields *x, int fid) {
   return fid == FP ? x->p : fid == FR ? x->ur : fid == FT ? x->ut : fid == FF ? x->uf : x->T;
 }
-static double *fldw(orc_fields *x, int fid) {
+static real *fldw(orc_fields *x, int fid) {
   return fid == FP ? x->p : fid == FR ? x->ur : fid == FT ? x->ut : fid == FF ? x->uf : x->T;
 }
 
@@ -1037,9 +1052,9 @@ int orc_line_solve(const orc_grid *g, const orc_mat *m, const orc_fields *Ub, co
   int n = dir_len(g, d), err = 0;
 #pragma omp parallel reduction(| : err)
   {
-    double *Lb = malloc(sizeof(double) * 9 * n), *Db = malloc(sizeof(double) * 9 * n);
-    double *Ubk = malloc(sizeof(double) * 9 * n), *bv = malloc(sizeof(double) * 3 * n);
-    double *C = malloc(sizeof(double) * 9 * n);
+    real *Lb = malloc(sizeof(real) * 9 * n), *Db = malloc(sizeof(real) * 9 * n);
+    real *Ubk = malloc(sizeof(real) * 9 * n), *bv = malloc(sizeof(real) * 3 * n);
+    real *C = malloc(sizeof(real) * 9 * n);
 #pragma omp for schedule(static)
     for (long l = 0; l < nl; l++) {
       const line_t *L = &lines[l];
@@ -1058,7 +1073,7 @@ int orc_line_solve(const orc_grid *g, const orc_mat *m, const orc_fields *Ub, co
             if (block_unknown(g, L, s, q, &fid, &idx)) fldw(x, fid)[idx] = bv[s * 3 + q];
           }
       } else {
-        double *a = Lb, *bd = Db, *c = Ubk;
+        real *a = Lb, *bd = Db, *c = Ubk;
         assemble_scalar(g, m, &u, L, tau, a, bd, c);
         for (int s = 0; s < n; s++) bv[s] = fld(rhs, L->tcomp)[line_idx(g, L, L->tcomp, s)];
         int rc = L->cyclic ? block_cyclic(n, 1, a, bd, c, bv) : block_thomas(n, 1, a, bd, c, 1, bv, C);
@@ -1084,8 +1099,8 @@ int orc_line_matvec(const orc_grid *g, const orc_mat *m, const orc_fields *Ub, c
   int n = dir_len(g, d);
 #pragma omp parallel
   {
-    double *Lb = malloc(sizeof(double) * 9 * n), *Db = malloc(sizeof(double) * 9 * n);
-    double *Ubk = malloc(sizeof(double) * 9 * n), *xv = malloc(sizeof(double) * 3 * n);
+    real *Lb = malloc(sizeof(real) * 9 * n), *Db = malloc(sizeof(real) * 9 * n);
+    real *Ubk = malloc(sizeof(real) * 9 * n), *xv = malloc(sizeof(real) * 3 * n);
 #pragma omp for schedule(static)
     for (long l = 0; l < nl; l++) {
       const line_t *L = &lines[l];
@@ -1103,12 +1118,12 @@ int orc_line_matvec(const orc_grid *g, const orc_mat *m, const orc_fields *Ub, c
       }
       for (int s = 0; s < n; s++) {
         for (int q = 0; q < bs; q++) {
-          double acc = 0.0;
+          real acc = 0.0;
           for (int off = -1; off <= 1; off++) {
             int s2 = s + off;
             if (!L->cyclic && (s2 < 0 || s2 >= n)) continue;
             s2 = ((s2 % n) + n) % n;
-            const double *blk = off < 0 ? Lb : (off == 0 ? Db : Ubk);
+            const real *blk = off < 0 ? Lb : (off == 0 ? Db : Ubk);
             for (int q2 = 0; q2 < bs; q2++) acc += blk[(long)s * bs * bs + q * bs + q2] * xv[s2 * bs + q2];
           }
           if (bs == 3) {
@@ -1130,7 +1145,7 @@ int orc_line_matvec(const orc_grid *g, const orc_mat *m, const orc_fields *Ub, c
  * else the scalar family's field id; (a, b) the line's transverse coords.
  * L/D/U: n*bs*bs; idx: n*bs flat indices (-1 for a boundary face), fid: n*bs. */
 int orc_line_blocks(const orc_grid *g, const orc_mat *m, const orc_fields *Ub, const orc_wall *wall,
-                    double tau, int d, int kind, int a, int b, double *Lo, double *Do, double *Uo,
+                    double tau, int d, int kind, int a, int b, real *Lo, real *Do, real *Uo,
                     long *idx, int *fid) {
   line_t L;
   L.d = d; L.n = dir_len(g, d); L.cyclic = (d == 2 && g->periodic); L.last_is_bnd = !L.cyclic;
@@ -1154,9 +1169,9 @@ int orc_line_blocks(const orc_grid *g, const orc_mat *m, const orc_fields *Ub, c
 /* ----------------------------------------------------------- split step -- */
 
 static void alloc_fields(const orc_grid *g, orc_fields *x) {
-  x->p = calloc(fsize(g, FP), sizeof(double)); x->ur = calloc(fsize(g, FR), sizeof(double));
-  x->ut = calloc(fsize(g, FT), sizeof(double)); x->uf = calloc(fsize(g, FF), sizeof(double));
-  x->T = calloc(fsize(g, FTT), sizeof(double));
+  x->p = calloc(fsize(g, FP), sizeof(real)); x->ur = calloc(fsize(g, FR), sizeof(real));
+  x->ut = calloc(fsize(g, FT), sizeof(real)); x->uf = calloc(fsize(g, FF), sizeof(real));
+  x->T = calloc(fsize(g, FTT), sizeof(real));
 }
 static void free_fields(orc_fields *x) { free(x->p); free(x->ur); free(x->ut); free(x->uf); free(x->T); }
 
@@ -1190,10 +1205,10 @@ int orc_split_step(const orc_grid *g, const orc_mat *m, const orc_fields *Un, or
   orc_fields Uk, R, Ub, X1, X2, X3;
   alloc_fields(g, &Uk); alloc_fields(g, &R); alloc_fields(g, &Ub);
   alloc_fields(g, &X1); alloc_fields(g, &X2); alloc_fields(g, &X3);
-  const double *un[5] = {Un->p, Un->ur, Un->ut, Un->uf, Un->T};
-  double *uk[5] = {Uk.p, Uk.ur, Uk.ut, Uk.uf, Uk.T};
-  double *x3[5] = {X3.p, X3.ur, X3.ut, X3.uf, X3.T};
-  for (int q = 0; q < 5; q++) memcpy(uk[q], un[q], sizeof(double) * fsize(g, q));
+  const real *un[5] = {Un->p, Un->ur, Un->ut, Un->uf, Un->T};
+  real *uk[5] = {Uk.p, Uk.ur, Uk.ut, Uk.uf, Uk.T};
+  real *x3[5] = {X3.p, X3.ur, X3.ut, X3.uf, X3.T};
+  for (int q = 0; q < 5; q++) memcpy(uk[q], un[q], sizeof(real) * fsize(g, q));
   if (bnd) copy_bnd_faces(g, bnd, &Uk);
   int rc = 0;
   for (int it = 0; it < K && !rc; it++) {
@@ -1206,8 +1221,8 @@ int orc_split_step(const orc_grid *g, const orc_mat *m, const orc_fields *Un, or
       for (long x = 0; x < n; x++) uk[q][x] += x3[q][x];
     }
   }
-  double *out[5] = {Unp1->p, Unp1->ur, Unp1->ut, Unp1->uf, Unp1->T};
-  for (int q = 0; q < 5; q++) memcpy(out[q], uk[q], sizeof(double) * fsize(g, q));
+  real *out[5] = {Unp1->p, Unp1->ur, Unp1->ut, Unp1->uf, Unp1->T};
+  for (int q = 0; q < 5; q++) memcpy(out[q], uk[q], sizeof(real) * fsize(g, q));
   free_fields(&Uk); free_fields(&R); free_fields(&Ub);
   free_fields(&X1); free_fields(&X2); free_fields(&X3);
   return rc ? -1 : 0;
@@ -1218,15 +1233,15 @@ int orc_split_step(const orc_grid *g, const orc_mat *m, const orc_fields *Un, or
  * already hold the midpoint state (ghost data wall).  out: R at each point. */
 int orc_residual_at(const orc_grid *g, const orc_mat *m, const orc_fields *Un, const orc_fields *Uk,
                     const orc_fields *Ub, const orc_wall *wall, double tau, long npts,
-                    const int *fids, const long *idx, double *out) {
+                    const int *fids, const long *idx, real *out) {
   opnd u = mk_opnd(Ub, wall);
-  const double *un[5] = {Un->p, Un->ur, Un->ut, Un->uf, Un->T};
-  const double *uk[5] = {Uk->p, Uk->ur, Uk->ut, Uk->uf, Uk->T};
+  const real *un[5] = {Un->p, Un->ur, Un->ut, Un->uf, Un->T};
+  const real *uk[5] = {Uk->p, Uk->ur, Uk->ut, Uk->uf, Uk->T};
 #pragma omp parallel for schedule(static)
   for (long s = 0; s < npts; s++) {
     int fid = fids[s];
     long x = idx[s];
-    double F = 0.0;
+    real F = 0.0;
     int unknown = 1;
     if (fid == FP || fid == FTT) {
       int k = (int)(x % g->np), j = (int)((x / g->np) % g->nt), i = (int)(x / ((long)g->np * g->nt));
@@ -1261,9 +1276,9 @@ int orc_line_solve_some(const orc_grid *g, const orc_mat *m, const orc_fields *U
   int n = dir_len(g, d), err = 0;
 #pragma omp parallel reduction(| : err)
   {
-    double *Lb = malloc(sizeof(double) * 9 * n), *Db = malloc(sizeof(double) * 9 * n);
-    double *Ubk = malloc(sizeof(double) * 9 * n), *bv = malloc(sizeof(double) * 3 * n);
-    double *C = malloc(sizeof(double) * 9 * n);
+    real *Lb = malloc(sizeof(real) * 9 * n), *Db = malloc(sizeof(real) * 9 * n);
+    real *Ubk = malloc(sizeof(real) * 9 * n), *bv = malloc(sizeof(real) * 3 * n);
+    real *C = malloc(sizeof(real) * 9 * n);
 #pragma omp for schedule(static)
     for (long l = 0; l < nl; l++) {
       line_t L;
@@ -1298,10 +1313,10 @@ int orc_line_solve_some(const orc_grid *g, const orc_mat *m, const orc_fields *U
 
 /* Solve one (cyclic or not) block-tridiagonal system given its blocks
  * (for dense-LU tests of the line solvers).  b (n x bs) is overwritten. */
-int orc_block_solve(int n, int bs, int cyclic, const double *L, const double *D, const double *U,
-                    double *b) {
+int orc_block_solve(int n, int bs, int cyclic, const real *L, const real *D, const real *U,
+                    real *b) {
   if (cyclic) return block_cyclic(n, bs, L, D, U, b);
-  double *C = malloc(sizeof(double) * (size_t)n * bs * bs);
+  real *C = malloc(sizeof(real) * (size_t)n * bs * bs);
   int rc = block_thomas(n, bs, L, D, U, 1, b, C);
   free(C);
   return rc;

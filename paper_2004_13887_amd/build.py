@@ -5,7 +5,7 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-SRC = [os.path.join(HERE, "csrc", f) for f in ("residual.hip", "sweeps.hip", "phi_part.hip", "api.hip")]
+SRC = [os.path.join(HERE, "csrc", f) for f in ("residual.hip", "sweeps.hip", "phi_part.hip", "adjoint.hip", "api.hip")]
 LIB = os.path.join(HERE, "libdsw.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

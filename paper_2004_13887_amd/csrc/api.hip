@@ -26,6 +26,8 @@ struct dsw_grid {
   double *fields_mem = nullptr;
   Scratch sc{};
   double *scratch_mem = nullptr;
+  double *adj_mem = nullptr; // adjoint workspace, allocated on first use
+  int adj_K = 0;
   int *status = nullptr;
   long count[5];
   int device = 0;
@@ -217,6 +219,7 @@ extern "C" int dsw_free_grid(dsw_grid *G) {
   if (G->tables) (void)hipFree(G->tables);
   if (G->fields_mem) (void)hipFree(G->fields_mem);
   if (G->scratch_mem) (void)hipFree(G->scratch_mem);
+  if (G->adj_mem) (void)hipFree(G->adj_mem);
   if (G->status) (void)hipFree(G->status);
   delete G;
   return DSW_OK;
@@ -514,6 +517,169 @@ extern "C" int dsw_get_status(dsw_grid *G, void *stream) {
   if (h[ST_NONPHYS]) return fail(DSW_ENONPHYS, "non-positive temperature or pressure met");
   if (h[ST_SINGULAR]) return fail(DSW_ESINGULAR, "zero pivot in a line solve");
   return DSW_OK;
+}
+
+// --------------------------------------------------------------- adjoint --
+
+static int line_solve_T(int d, dsw_grid *G, const dsw_fields *Ubar, double tau, const dsw_fields *rhs,
+                        dsw_fields *x, void *stream) {
+  if (!G) return fail(DSW_EINVAL, "null handle");
+  int rc;
+  if ((rc = check_fields(Ubar, "Ubar")) || (rc = check_fields(rhs, "rhs")) || (rc = check_fields(x, "x")))
+    return rc;
+  if (!(tau > 0.0)) return fail(DSW_EINVAL, "tau must be > 0");
+  if (rhs->p == x->p || rhs->ur == x->ur || rhs->ut == x->ut || rhs->uf == x->uf || rhs->T == x->T)
+    return fail(DSW_EINVAL, "rhs and x must not alias");
+  Out o{};
+  o.x = F(x);
+  o.mode = 0;
+  Pass p = sweep_pass(G, d, F(Ubar), tau, F(rhs), o);
+  launch_sweep_T(d, p.a, cdiv(sweep_lines(G->geo, d), 128), 128, (hipStream_t)stream);
+  return check_launch("transposed sweep kernel");
+}
+
+extern "C" int dsw_line_solve_T_r(dsw_grid *G, const dsw_fields *Ubar, double tau,
+                                  const dsw_fields *rhs, dsw_fields *x, void *stream) {
+  return line_solve_T(0, G, Ubar, tau, rhs, x, stream);
+}
+extern "C" int dsw_line_solve_T_theta(dsw_grid *G, const dsw_fields *Ubar, double tau,
+                                      const dsw_fields *rhs, dsw_fields *x, void *stream) {
+  return line_solve_T(1, G, Ubar, tau, rhs, x, stream);
+}
+extern "C" int dsw_line_solve_T_phi(dsw_grid *G, const dsw_fields *Ubar, double tau,
+                                    const dsw_fields *rhs, dsw_fields *x, void *stream) {
+  return line_solve_T(2, G, Ubar, tau, rhs, x, stream);
+}
+
+static int line_vjp(int d, dsw_grid *G, const dsw_fields *Ubar, double tau, const dsw_fields *X,
+                    const dsw_fields *mu, dsw_fields *acc, void *stream) {
+  if (!G) return fail(DSW_EINVAL, "null handle");
+  int rc;
+  if ((rc = check_fields(Ubar, "Ubar")) || (rc = check_fields(X, "X")) || (rc = check_fields(mu, "mu")) ||
+      (rc = check_fields(acc, "acc")))
+    return rc;
+  if (!(tau > 0.0)) return fail(DSW_EINVAL, "tau must be > 0");
+  launch_line_vjp(d, G->geo, G->m, F(Ubar), tau, F(X), F(mu), F(acc), (hipStream_t)stream);
+  return check_launch("line vjp kernel");
+}
+
+extern "C" int dsw_line_vjp_r(dsw_grid *G, const dsw_fields *Ubar, double tau, const dsw_fields *X,
+                              const dsw_fields *mu, dsw_fields *acc, void *stream) {
+  return line_vjp(0, G, Ubar, tau, X, mu, acc, stream);
+}
+extern "C" int dsw_line_vjp_theta(dsw_grid *G, const dsw_fields *Ubar, double tau, const dsw_fields *X,
+                                  const dsw_fields *mu, dsw_fields *acc, void *stream) {
+  return line_vjp(1, G, Ubar, tau, X, mu, acc, stream);
+}
+extern "C" int dsw_line_vjp_phi(dsw_grid *G, const dsw_fields *Ubar, double tau, const dsw_fields *X,
+                                const dsw_fields *mu, dsw_fields *acc, void *stream) {
+  return line_vjp(2, G, Ubar, tau, X, mu, acc, stream);
+}
+
+extern "C" int dsw_residual_vjp(dsw_grid *G, const dsw_fields *Ubar, double tau, const dsw_fields *mu,
+                                dsw_fields *acc, void *stream) {
+  if (!G) return fail(DSW_EINVAL, "null handle");
+  int rc;
+  if ((rc = check_fields(Ubar, "Ubar")) || (rc = check_fields(mu, "mu")) || (rc = check_fields(acc, "acc")))
+    return rc;
+  if (!(tau > 0.0)) return fail(DSW_EINVAL, "tau must be > 0");
+  launch_residual_vjp(G->geo, G->m, F(Ubar), tau, F(mu), F(acc), (hipStream_t)stream);
+  return check_launch("residual vjp kernel");
+}
+
+// adjoint workspace: per iteration Ubar, X1, X2, X3; the running iterate; two
+// cotangents of the iterate; mu3, mu2, mu1; the cotangent of Ubar
+static int adj_workspace(dsw_grid *G, int K, std::vector<Fields> &ws) {
+  const long per = G->count[0] + G->count[1] + G->count[2] + G->count[3] + G->count[4];
+  const int nstates = 4 * K + 7;
+  if (G->adj_K < K) {
+    if (G->adj_mem) {
+      HIPCHK(hipDeviceSynchronize());
+      (void)hipFree(G->adj_mem);
+      G->adj_mem = nullptr;
+      G->adj_K = 0;
+    }
+    if (hipMalloc(&G->adj_mem, (size_t)nstates * per * sizeof(double)) != hipSuccess) {
+      G->adj_mem = nullptr;
+      return fail(DSW_ENOMEM, "adjoint workspace");
+    }
+    G->adj_K = K;
+  }
+  long off = 0;
+  ws.clear();
+  for (int q = 0; q < nstates; q++) ws.push_back(carve(G->adj_mem, G->count, &off));
+  return DSW_OK;
+}
+
+extern "C" int dsw_adjoint_step(dsw_grid *G, const dsw_fields *Un, double tau, int32_t K,
+                                const dsw_fields *lam_np1, dsw_fields *lam_n, void *stream) {
+  if (!G) return fail(DSW_EINVAL, "null handle");
+  int rc;
+  if ((rc = check_fields(Un, "Un")) || (rc = check_fields(lam_np1, "lam_np1")) ||
+      (rc = check_fields(lam_n, "lam_n")))
+    return rc;
+  if (!(tau > 0.0)) return fail(DSW_EINVAL, "tau must be > 0");
+  if (K < 1) return fail(DSW_EINVAL, "K must be >= 1");
+  if (lam_n->p == lam_np1->p || lam_n->p == Un->p) return fail(DSW_EINVAL, "lam_n must not alias the inputs");
+  std::vector<Fields> ws;
+  if ((rc = adj_workspace(G, K, ws))) return rc;
+  hipStream_t st = (hipStream_t)stream;
+  const Fields un = F(Un), none{};
+  const long *cnt = G->count;
+  auto UB = [&](int k) { return ws[4 * k + 0]; };
+  auto X1 = [&](int k) { return ws[4 * k + 1]; };
+  auto X2 = [&](int k) { return ws[4 * k + 2]; };
+  auto X3 = [&](int k) { return ws[4 * k + 3]; };
+  const Fields U = ws[4 * K], La = ws[4 * K + 1], Lb = ws[4 * K + 2];
+  const Fields M3 = ws[4 * K + 3], M2 = ws[4 * K + 4], M1 = ws[4 * K + 5], UBB = ws[4 * K + 6];
+  // forward recompute from the checkpoint, keeping every iteration's
+  // midpoint and line-solve outputs
+  launch_axpy3(cnt, 1.0, un, 0.0, none, 0.0, none, U, st);
+  for (int k = 0; k < K; k++) {
+    launch_axpy3(cnt, 0.5, U, 0.5, un, 0.0, none, UB(k), st);
+    Pass r{PK_RES, 0, base_args(G)};
+    r.a.u = src1(UB(k));
+    r.a.d = diff(un, k == 0 ? un : U);
+    r.a.tau = tau;
+    r.a.R = G->r;
+    launch_single(G, r, st);
+    Out o1{}, o2{}, o3{};
+    o1.x = X1(k); o2.x = X2(k); o3.x = X3(k);
+    launch_single(G, sweep_pass(G, 0, UB(k), tau, G->r, o1), st);
+    launch_single(G, sweep_pass(G, 1, UB(k), tau, X1(k), o2), st);
+    launch_single(G, sweep_pass(G, 2, UB(k), tau, X2(k), o3), st);
+    launch_axpy3(cnt, 1.0, U, 1.0, X3(k), 0.0, none, U, st);
+  }
+  // reverse sweep (reverse of every statement above, last iteration first)
+  launch_axpy3(cnt, 0.0, un, 0.0, none, 0.0, none, F(lam_n), st); // lam_n = 0
+  Fields L = F(lam_np1), Lnext = La;
+  for (int k = K - 1; k >= 0; k--) {
+    const Fields ubk = UB(k);
+    launch_axpy3(cnt, 0.0, un, 0.0, none, 0.0, none, UBB, st); // Ubar cotangent = 0
+    Out o{};
+    o.mode = 0;
+    o.x = M3;
+    Pass p3 = sweep_pass(G, 2, ubk, tau, L, o);
+    launch_sweep_T(2, p3.a, cdiv(sweep_lines(G->geo, 2), 128), 128, st);
+    launch_line_vjp(2, G->geo, G->m, ubk, tau, X3(k), M3, UBB, st);
+    o.x = M2;
+    Pass p2 = sweep_pass(G, 1, ubk, tau, M3, o);
+    launch_sweep_T(1, p2.a, cdiv(sweep_lines(G->geo, 1), 128), 128, st);
+    launch_line_vjp(1, G->geo, G->m, ubk, tau, X2(k), M2, UBB, st);
+    o.x = M1;
+    Pass p1 = sweep_pass(G, 0, ubk, tau, M2, o);
+    launch_sweep_T(0, p1.a, cdiv(sweep_lines(G->geo, 0), 128), 128, st);
+    launch_line_vjp(0, G->geo, G->m, ubk, tau, X1(k), M1, UBB, st);
+    // the line operators enter as -(dM/dUbar)^T mu: UBB holds +(...) so far
+    launch_axpy3(cnt, -1.0, UBB, 0.0, none, 0.0, none, UBB, st);
+    launch_residual_vjp(G->geo, G->m, ubk, tau, M1, UBB, st);
+    launch_adj_mix(G->geo, cnt, L, M1, UBB, Lnext, F(lam_n), st);
+    L = Lnext;
+    Lnext = (Lnext.p == La.p) ? Lb : La;
+  }
+  // U^{n+1,0} = U^n
+  launch_axpy3(cnt, 1.0, F(lam_n), 1.0, L, 0.0, none, F(lam_n), st);
+  return check_launch("adjoint step kernels");
 }
 
 // ------------------------------------------------------------- ensembles --

@@ -89,6 +89,19 @@ unsigned bnd_points(const Geo &g);           // boundary-normal faces
 unsigned phi_part_threads(const Geo &g, int pm);
 size_t phi_part_lds(const Geo &g, int pm);
 
+// adjoint pieces: transposed line solves (one thread per line), the
+// transposed Jacobians of the residual and of the line operators (both
+// accumulate into acc), and elementwise helpers
+void launch_sweep_T(int d, const PassArgs &a, unsigned blocks, unsigned threads, hipStream_t st);
+void launch_residual_vjp(const Geo &g, const Mat &m, const Fields &Ub, double tau, const Fields &mu,
+                         const Fields &acc, hipStream_t st);
+void launch_line_vjp(int d, const Geo &g, const Mat &m, const Fields &Ub, double tau, const Fields &X,
+                     const Fields &mu, const Fields &acc, hipStream_t st);
+void launch_axpy3(const long *cnt, double a, const Fields &x, double b, const Fields &y, double c,
+                  const Fields &z, const Fields &out, hipStream_t st);
+void launch_adj_mix(const Geo &g, const long *cnt, const Fields &L, const Fields &mu1, const Fields &ubb,
+                    const Fields &Lnew, const Fields &lam, hipStream_t st);
+
 // public residual: forms the midpoint on the fly from Un and Uk and writes it
 void launch_residual(const Geo &g, const Mat &m, const Fields &Un, const Fields &Uk, double tau,
                      const Fields &R, const Fields &Ub, int *status, hipStream_t st);

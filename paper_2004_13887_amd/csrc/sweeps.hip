@@ -56,7 +56,67 @@ __device__ void zero_bnd(const Geo &g, const Fields &x, int a, int b) {
   }
 }
 
-template <int D>
+// Row s of the line system, or of its transpose (TR): the transposed row s
+// has lower block U_{s-1}^T, diagonal D_s^T and upper block L_{s+1}^T, and
+// the right-hand side read at row s's unknowns.
+__device__ __forceinline__ void tr3(const double *A, double *B) {
+#pragma unroll
+  for (int r = 0; r < 3; r++)
+#pragma unroll
+    for (int c = 0; c < 3; c++) B[c * 3 + r] = A[r * 3 + c];
+}
+
+template <int D, bool TR>
+__device__ __forceinline__ void get_brow(const Geo &g, const Mat &m, const SrcOne &u,
+                                         const Fields &rhs, int a, int b, int s, int n, int cyc,
+                                         double hs, BRow &R) {
+  block_row<D>(g, m, u, rhs, a, b, s, n, cyc, hs, R);
+  if (!TR) return;
+  double t9[9];
+  tr3(R.D, t9);
+#pragma unroll
+  for (int q = 0; q < 9; q++) R.D[q] = t9[q];
+  const bool has_m = cyc || s > 0, has_p = cyc || s < n - 1;
+  BRow Q;
+  if (has_m) {
+    block_row<D>(g, m, u, rhs, a, b, s > 0 ? s - 1 : n - 1, n, cyc, hs, Q);
+    tr3(Q.U, R.L);
+  } else {
+#pragma unroll
+    for (int q = 0; q < 9; q++) R.L[q] = 0.0;
+  }
+  if (has_p) {
+    block_row<D>(g, m, u, rhs, a, b, s < n - 1 ? s + 1 : 0, n, cyc, hs, Q);
+    tr3(Q.L, R.U);
+  } else {
+#pragma unroll
+    for (int q = 0; q < 9; q++) R.U[q] = 0.0;
+  }
+}
+
+template <int D, int FAM, bool TR>
+__device__ __forceinline__ void get_srow(const Geo &g, const Mat &m, const SrcOne &u,
+                                         const Fields &rhs, int a, int b, int s, int n, int cyc,
+                                         double hs, SRow &R, long &xi, double *&arr) {
+  scalar_row<D, FAM>(g, m, u, rhs, a, b, s, n, cyc, hs, R, xi, arr);
+  if (!TR) return;
+  SRow Q;
+  long xq;
+  double *aq;
+  double lo = 0.0, up = 0.0;
+  if (cyc || s > 0) {
+    scalar_row<D, FAM>(g, m, u, rhs, a, b, s > 0 ? s - 1 : n - 1, n, cyc, hs, Q, xq, aq);
+    lo = Q.c;
+  }
+  if (cyc || s < n - 1) {
+    scalar_row<D, FAM>(g, m, u, rhs, a, b, s < n - 1 ? s + 1 : 0, n, cyc, hs, Q, xq, aq);
+    up = Q.a;
+  }
+  R.a = lo;
+  R.c = up;
+}
+
+template <int D, bool TR>
 __device__ void solve_block_line(const Geo &g, const Mat &m, const SrcOne &u, const Fields &rhs,
                                  const Out &o, double *sc, long nl, long line, int a, int b,
                                  int n, double hs, int *status) {
@@ -65,7 +125,7 @@ __device__ void solve_block_line(const Geo &g, const Mat &m, const SrcOne &u, co
   BRow R;
   double C[9], y[3], Ap[9], Ai[9], t9[9], t3[3];
   for (int s = 0; s < n; s++) {
-    block_row<D>(g, m, u, rhs, a, b, s, n, 0, hs, R);
+    get_brow<D, TR>(g, m, u, rhs, a, b, s, n, 0, hs, R);
     if (s == 0) {
 #pragma unroll
       for (int q = 0; q < 9; q++) Ap[q] = R.D[q];
@@ -106,7 +166,7 @@ __device__ void solve_block_line(const Geo &g, const Mat &m, const SrcOne &u, co
 }
 
 // cyclic block line: bordered elimination of the last block
-template <int D>
+template <int D, bool TR>
 __device__ void solve_block_cyclic(const Geo &g, const Mat &m, const SrcOne &u, const Fields &rhs,
                                    const Out &o, double *sc, long nl, long line, int a, int b,
                                    int n, double hs, int *status) {
@@ -115,7 +175,7 @@ __device__ void solve_block_cyclic(const Geo &g, const Mat &m, const SrcOne &u, 
   BRow R;
   double C[9], y[3], Z[9], Ap[9], Ai[9], t9[9], t3[3], E[9];
   for (int s = 0; s < n - 1; s++) {
-    block_row<D>(g, m, u, rhs, a, b, s, n, 1, hs, R);
+    get_brow<D, TR>(g, m, u, rhs, a, b, s, n, 1, hs, R);
 #pragma unroll
     for (int q = 0; q < 9; q++) E[q] = 0.0;
     if (s == 0) {
@@ -166,7 +226,7 @@ __device__ void solve_block_cyclic(const Geo &g, const Mat &m, const SrcOne &u, 
     for (int q = 0; q < 9; q++) { Z[q] = SC(s, 12 + q) - t9[q]; SC(s, 12 + q) = Z[q]; }
   }
   // last row: (D - L Z_{n-2} - U Z_0) x = b - L y_{n-2} - U y_0
-  block_row<D>(g, m, u, rhs, a, b, n - 1, n, 1, hs, R);
+  get_brow<D, TR>(g, m, u, rhs, a, b, n - 1, n, 1, hs, R);
   double LZ[9], UZ[9], Ly[3], Uy[3], xl[3];
   mm3(R.L, Zl, LZ);
   mm3(R.U, Z, UZ);
@@ -198,7 +258,7 @@ __device__ __forceinline__ long scalar_index(const Geo &g, int a, int b, int s) 
   return FAM == 0 ? idx_r(g, a, b, s) : idx_t(g, a, b, s);
 }
 
-template <int D, int FAM>
+template <int D, int FAM, bool TR>
 __device__ void solve_scalar_line(const Geo &g, const Mat &m, const SrcOne &u, const Fields &rhs,
                                   const Out &o, double *sc, long nl, long line, int a, int b,
                                   int n, int cyc, double hs, int *status) {
@@ -214,7 +274,7 @@ __device__ void solve_scalar_line(const Geo &g, const Mat &m, const SrcOne &u, c
 #define SC(s, q) sc[((long)(s) * 2 + (q)) * nl + line]
     double cpv = 0.0, yv = 0.0;
     for (int s = 0; s < n; s++) {
-      scalar_row<D, FAM>(g, m, u, rhs, a, b, s, n, 0, hs, R, xi, arr);
+      get_srow<D, FAM, TR>(g, m, u, rhs, a, b, s, n, 0, hs, R, xi, arr);
       const double den = R.b - R.a * cpv;
       if (!(den != 0.0)) status[ST_SINGULAR] = 1;
       const double id = 1.0 / den;
@@ -235,7 +295,7 @@ __device__ void solve_scalar_line(const Geo &g, const Mat &m, const SrcOne &u, c
     // bordered elimination of the last unknown
     double cpv = 0.0, yv = 0.0, zv = 0.0;
     for (int s = 0; s < n - 1; s++) {
-      scalar_row<D, FAM>(g, m, u, rhs, a, b, s, n, 1, hs, R, xi, arr);
+      get_srow<D, FAM, TR>(g, m, u, rhs, a, b, s, n, 1, hs, R, xi, arr);
       double e = 0.0, c = R.c, den;
       if (s == 0) { e = R.a; den = R.b; }
       else { den = R.b - R.a * cpv; e = -R.a * zv; }
@@ -254,7 +314,7 @@ __device__ void solve_scalar_line(const Geo &g, const Mat &m, const SrcOne &u, c
       zv = SC(s, 2) - cs * zv;
       SC(s, 1) = yv; SC(s, 2) = zv;
     }
-    scalar_row<D, FAM>(g, m, u, rhs, a, b, n - 1, n, 1, hs, R, xi, arr);
+    get_srow<D, FAM, TR>(g, m, u, rhs, a, b, n - 1, n, 1, hs, R, xi, arr);
     const double den = R.b - R.a * zl - R.c * zv;
     if (!(den != 0.0)) status[ST_SINGULAR] = 1;
     const double xl = (R.r - R.a * yl - R.c * yv) / den;
@@ -272,7 +332,7 @@ __device__ void solve_scalar_line(const Geo &g, const Mat &m, const SrcOne &u, c
 
 // one thread per line: the block lines first, then the two scalar families;
 // one grid or a batch of grids (flat grid of workgroups)
-template <int D>
+template <int D, bool TR>
 __device__ __forceinline__ void sweep_body(const PassArgs &a, unsigned w) {
   const Geo &g = a.g;
   const Families F = families(g, D);
@@ -285,8 +345,8 @@ __device__ __forceinline__ void sweep_body(const PassArgs &a, unsigned w) {
     else if (D == 1) { p = (int)(t / g.np); q = (int)(t % g.np); }
     else { p = (int)(t / g.nt); q = (int)(t % g.nt); }
     if (a.o.mode == 0) zero_bnd<D>(g, a.o.x, p, q);
-    if (F.cyclic) solve_block_cyclic<D>(g, a.m, a.u, a.rhs, a.o, a.scb, F.nb, t, p, q, F.n, hs, a.status);
-    else solve_block_line<D>(g, a.m, a.u, a.rhs, a.o, a.scb, F.nb, t, p, q, F.n, hs, a.status);
+    if (F.cyclic) solve_block_cyclic<D, TR>(g, a.m, a.u, a.rhs, a.o, a.scb, F.nb, t, p, q, F.n, hs, a.status);
+    else solve_block_line<D, TR>(g, a.m, a.u, a.rhs, a.o, a.scb, F.nb, t, p, q, F.n, hs, a.status);
     return;
   }
   long t2 = t - F.nb;
@@ -296,7 +356,7 @@ __device__ __forceinline__ void sweep_body(const PassArgs &a, unsigned w) {
     if (D == 0) { p = 1 + (int)(t2 / g.np); q = (int)(t2 % g.np); }
     else if (D == 1) { p = 1 + (int)(t2 / g.np); q = (int)(t2 % g.np); }
     else { p = 1 + (int)(t2 / g.nt); q = (int)(t2 % g.nt); }
-    solve_scalar_line<D, 0>(g, a.m, a.u, a.rhs, a.o, a.scs, ns, t2, p, q, F.n, F.cyclic, hs, a.status);
+    solve_scalar_line<D, 0, TR>(g, a.m, a.u, a.rhs, a.o, a.scs, ns, t2, p, q, F.n, F.cyclic, hs, a.status);
     return;
   }
   t2 -= F.na;
@@ -305,7 +365,7 @@ __device__ __forceinline__ void sweep_body(const PassArgs &a, unsigned w) {
     if (D == 0) { p = (int)(t2 / nkf); q = kf0 + (int)(t2 % nkf); }
     else if (D == 1) { p = (int)(t2 / nkf); q = kf0 + (int)(t2 % nkf); }
     else { p = (int)(t2 / (g.nt - 1)); q = 1 + (int)(t2 % (g.nt - 1)); }
-    solve_scalar_line<D, 1>(g, a.m, a.u, a.rhs, a.o, a.scs, ns, F.na + t2, p, q, F.n, F.cyclic, hs,
+    solve_scalar_line<D, 1, TR>(g, a.m, a.u, a.rhs, a.o, a.scs, ns, F.na + t2, p, q, F.n, F.cyclic, hs,
                             a.status);
   }
 }
@@ -315,10 +375,23 @@ template <int D, bool B>
 __global__ void __launch_bounds__(256) k_sweep(PassArgs a, Batch bt) {
   if constexpr (B) {
     const int mb = batch_member(bt, blockIdx.x);
-    sweep_body<D>(bt.tab[mb], blockIdx.x - bt.woff[mb]);
+    sweep_body<D, false>(bt.tab[mb], blockIdx.x - bt.woff[mb]);
   } else {
-    sweep_body<D>(a, blockIdx.x);
+    sweep_body<D, false>(a, blockIdx.x);
   }
+}
+
+// transposed systems (adjoint): (I + tau/2 D_d(Ubar))^T x = rhs, one grid
+template <int D>
+__global__ void __launch_bounds__(256) k_sweep_T(PassArgs a) {
+  sweep_body<D, true>(a, blockIdx.x);
+}
+
+void launch_sweep_T(int d, const PassArgs &a, unsigned blocks, unsigned threads, hipStream_t st) {
+  const dim3 gr(blocks), bl(threads);
+  if (d == 0) hipLaunchKernelGGL(k_sweep_T<0>, gr, bl, 0, st, a);
+  else if (d == 1) hipLaunchKernelGGL(k_sweep_T<1>, gr, bl, 0, st, a);
+  else hipLaunchKernelGGL(k_sweep_T<2>, gr, bl, 0, st, a);
 }
 
 void sweep_scratch_size(const Geo &g, long *blk, long *sca) {

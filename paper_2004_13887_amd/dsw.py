@@ -27,7 +27,9 @@ SYMBOLS = ("dsw_init_grid", "dsw_free_grid", "dsw_layout", "dsw_residual", "dsw_
            "dsw_read_timing", "dsw_get_status", "dsw_set_config", "dsw_get_config",
            "dsw_ensemble_create", "dsw_ensemble_free", "dsw_ensemble_member", "dsw_ensemble_step",
            "dsw_ensemble_tune", "dsw_ensemble_set_config", "dsw_ensemble_get_config",
-           "dsw_ensemble_get_status", "dsw_last_error")
+           "dsw_ensemble_get_status", "dsw_adjoint_step", "dsw_line_solve_T_r",
+           "dsw_line_solve_T_theta", "dsw_line_solve_T_phi", "dsw_line_vjp_r", "dsw_line_vjp_theta",
+           "dsw_line_vjp_phi", "dsw_residual_vjp", "dsw_last_error")
 TIMING_KINDS = ("residual", "sweep_r", "sweep_theta", "sweep_phi_update", "boundary_copy")
 
 
@@ -102,6 +104,12 @@ def lib():
         L.dsw_ensemble_set_config.argtypes = [P, CP]
         L.dsw_ensemble_get_config.argtypes = [P, CP]
         L.dsw_ensemble_get_status.argtypes = [P, P]
+        L.dsw_adjoint_step.argtypes = [P, FP, D, I, FP, FP, P]
+        for n in ("dsw_line_solve_T_r", "dsw_line_solve_T_theta", "dsw_line_solve_T_phi"):
+            getattr(L, n).argtypes = [P, FP, D, FP, FP, P]
+        for n in ("dsw_line_vjp_r", "dsw_line_vjp_theta", "dsw_line_vjp_phi"):
+            getattr(L, n).argtypes = [P, FP, D, FP, FP, FP, P]
+        L.dsw_residual_vjp.argtypes = [P, FP, D, FP, FP, P]
         L.dsw_last_error.restype = C.c_char_p
         for n in SYMBOLS[:-1]:
             getattr(L, n).restype = C.c_int
@@ -181,6 +189,25 @@ class Grid:
 
     def line_solve(self, d, Ubar, tau, rhs, x, stream=None):
         (self.line_solve_r, self.line_solve_theta, self.line_solve_phi)[d](Ubar, tau, rhs, x, stream)
+
+    def adjoint_step(self, Un, tau, K, lam_np1, lam_n, stream=None):
+        _check(lib().dsw_adjoint_step(self._h, C.byref(_fields(Un)), float(tau), int(K),
+                                      C.byref(_fields(lam_np1)), C.byref(_fields(lam_n)),
+                                      _stream(stream)))
+
+    def line_solve_T(self, d, Ubar, tau, rhs, x, stream=None):
+        fn = ("dsw_line_solve_T_r", "dsw_line_solve_T_theta", "dsw_line_solve_T_phi")[d]
+        _check(getattr(lib(), fn)(self._h, C.byref(_fields(Ubar)), float(tau), C.byref(_fields(rhs)),
+                                  C.byref(_fields(x)), _stream(stream)))
+
+    def line_vjp(self, d, Ubar, tau, X, mu, acc, stream=None):
+        fn = ("dsw_line_vjp_r", "dsw_line_vjp_theta", "dsw_line_vjp_phi")[d]
+        _check(getattr(lib(), fn)(self._h, C.byref(_fields(Ubar)), float(tau), C.byref(_fields(X)),
+                                  C.byref(_fields(mu)), C.byref(_fields(acc)), _stream(stream)))
+
+    def residual_vjp(self, Ubar, tau, mu, acc, stream=None):
+        _check(lib().dsw_residual_vjp(self._h, C.byref(_fields(Ubar)), float(tau),
+                                      C.byref(_fields(mu)), C.byref(_fields(acc)), _stream(stream)))
 
     def split_step(self, Un, Unp1, tau, K, stream=None):
         _check(lib().dsw_split_step(self._h, C.byref(_fields(Un)), C.byref(_fields(Unp1)),
@@ -275,6 +302,39 @@ class Ensemble:
     def get_status(self, stream=None):
         _check(lib().dsw_ensemble_get_status(self._h, _stream(stream)))
         return DSW_OK
+
+
+class SplitStep(torch.autograd.Function):
+    """U^{n+1} = split_step(U^n) as a differentiable function of the five
+    fields (in the order p, ur, ut, uf, T).  The forward keeps U^n as the
+    checkpoint; the backward calls dsw_adjoint_step, which recomputes the
+    step from it."""
+
+    @staticmethod
+    def forward(ctx, grid, tau, K, p, ur, ut, uf, T):
+        Un = {"p": p.detach().contiguous(), "ur": ur.detach().contiguous(),
+              "ut": ut.detach().contiguous(), "uf": uf.detach().contiguous(),
+              "T": T.detach().contiguous()}
+        out = grid.empty(device=p.device)
+        grid.split_step(Un, out, tau, K)
+        ctx.grid, ctx.tau, ctx.K = grid, tau, K
+        ctx.save_for_backward(*(Un[k] for k in FIELDS))
+        return tuple(out[k] for k in FIELDS)
+
+    @staticmethod
+    def backward(ctx, *grads):
+        Un = dict(zip(FIELDS, ctx.saved_tensors))
+        lam = {k: (g if g is not None else torch.zeros_like(Un[k])).contiguous()
+               for k, g in zip(FIELDS, grads)}
+        out = ctx.grid.empty(device=Un["p"].device)
+        ctx.grid.adjoint_step(Un, ctx.tau, ctx.K, lam, out)
+        return (None, None, None) + tuple(out[k] for k in FIELDS)
+
+
+def split_step_fn(grid, U, tau, K):
+    """differentiable split step on a dict of fields"""
+    outs = SplitStep.apply(grid, tau, K, *(U[k] for k in FIELDS))
+    return dict(zip(FIELDS, outs))
 
 
 def to_device(fields, device="cuda"):

@@ -14,7 +14,7 @@ LIB = os.path.join(ROOT, "paper_2004_13887_amd", "libdsw.so")
 def declared():
     src = open(HEADER).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"\b(dsw_[a-z_0-9]+)\s*\(", src)))
+    return sorted(set(re.findall(r"\b(dsw_[A-Za-z_0-9]+)\s*\(", src)))
 
 
 def test_header_declares_the_boundary():

@@ -1,0 +1,161 @@
+"""GPU adjoint of the split step against the complex-step oracle.
+
+The complex-step oracle gives exact Jacobian-vector products J v of the
+oracle's own step (pinned in test_oracle_adjoint.py); the GPU adjoint gives
+J^T lam.  Every piece is checked by the identity <J^T lam, v> = <lam, J v> on
+random lam and v, and on tiny grids the whole transposed Jacobian is built
+column by column and compared entry by entry.  Bar: 1e-10 relative."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from gpu_common import small_cases
+from paper_2004_13887_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-10
+FIELDS = ("p", "ur", "ut", "uf", "T")
+SCALE = {"p": 1.0, "ur": 1e-2, "ut": 1e-2, "uf": 1e-2, "T": 1e-2}
+CASES = small_cases()
+NAMES = ["parity", "sector-ragged", "sphere-ragged", "sphere-chunks16", "sector-min", "sphere-min"]
+
+
+@pytest.fixture(scope="module")
+def dsw():
+    from paper_2004_13887_amd import dsw as D
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    D.lib()
+    return D
+
+
+def direction(spec, seed):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return {k: SCALE[k] * rng.uniform(-1.0, 1.0, s) for k, s in spec.shapes().items()}
+
+
+def cotangent(spec, seed):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return {k: rng.uniform(-1.0, 1.0, s) / SCALE[k] for k, s in spec.shapes().items()}
+
+
+def dot(a, b):
+    return float(sum(np.dot(np.ravel(a[k]), np.ravel(b[k])) for k in FIELDS))
+
+
+def check_dot(tag, lhs, rhs):
+    e = abs(lhs - rhs) / max(abs(lhs), abs(rhs), 1e-300)
+    print(f"{tag}: <J^T lam, v> = {lhs:.15e}  <lam, J v> = {rhs:.15e}  rel {e:.2e}", flush=True)
+    assert e <= TOL
+
+
+def _setup(name, dsw):
+    w = CASES[name]
+    U0, tau = I.initial_state(w)
+    og = oracle.Grid(*w.grid.args())
+    om = oracle.Material(*w.material.astuple())
+    gg = dsw.Grid.from_spec(w.grid, w.material)
+    return w, U0, tau, og, om, gg
+
+
+@pytest.mark.parametrize("d", [0, 1, 2])
+@pytest.mark.parametrize("name", NAMES)
+def test_transposed_line_solve(name, d, dsw):
+    print(f"[line_solve_T d={d}] {name}", flush=True)
+    w, U0, tau, og, om, gg = _setup(name, dsw)
+    b = I.random_fields(w.grid, 21 + d)
+    y = cotangent(w.grid, 31 + d)
+    xb = oracle.line_solve(og, om, U0, tau, d, b)
+    xT = gg.empty()
+    gg.line_solve_T(d, dsw.to_device(U0), tau, dsw.to_device(y), xT)
+    torch.cuda.synchronize()
+    gg.get_status()
+    check_dot(f"{name} M_{d}^-T", dot(dsw.to_host(xT), b), dot(y, xb))
+
+
+@pytest.mark.parametrize("d", [0, 1, 2])
+@pytest.mark.parametrize("name", NAMES)
+def test_line_operator_vjp(name, d, dsw):
+    print(f"[line_vjp d={d}] {name}", flush=True)
+    w, U0, tau, og, om, gg = _setup(name, dsw)
+    X = I.random_fields(w.grid, 41 + d, scale=1e-3)
+    mu = cotangent(w.grid, 51 + d)
+    V = direction(w.grid, 61 + d)
+    _, dy = oracle.jvp_line_matvec(og, om, U0, V, tau, d, X)
+    acc = gg.empty()
+    gg.line_vjp(d, dsw.to_device(U0), tau, dsw.to_device(X), dsw.to_device(mu), acc)
+    torch.cuda.synchronize()
+    gg.get_status()
+    check_dot(f"{name} dM_{d}", dot(dsw.to_host(acc), V), dot(mu, dy))
+
+
+@pytest.mark.parametrize("name", NAMES)
+def test_residual_vjp(name, dsw):
+    print(f"[residual_vjp] {name}", flush=True)
+    w, U0, tau, og, om, gg = _setup(name, dsw)
+    mu = cotangent(w.grid, 71)
+    V = direction(w.grid, 72)
+    _, dR = oracle.jvp_residual(og, om, U0, V, tau)
+    acc = gg.empty()
+    gg.residual_vjp(dsw.to_device(U0), tau, dsw.to_device(mu), acc)
+    torch.cuda.synchronize()
+    gg.get_status()
+    check_dot(f"{name} dR", dot(dsw.to_host(acc), V), dot(mu, dR))
+
+
+@pytest.mark.parametrize("name", NAMES)
+def test_adjoint_step_dot_product(name, dsw):
+    print(f"[adjoint_step] {name}", flush=True)
+    w, U0, tau, og, om, gg = _setup(name, dsw)
+    lam = cotangent(w.grid, 81)
+    V = direction(w.grid, 82)
+    _, dU1 = oracle.jvp_split_step(og, om, U0, V, tau, w.K)
+    out = gg.empty()
+    gg.adjoint_step(dsw.to_device(U0), tau, w.K, dsw.to_device(lam), out)
+    torch.cuda.synchronize()
+    gg.get_status()
+    check_dot(f"{name} J^T (K={w.K})", dot(dsw.to_host(out), V), dot(lam, dU1))
+
+
+@pytest.mark.parametrize("name", ["sector-min", "sphere-min"])
+def test_adjoint_step_dense_tiny(name, dsw):
+    """the whole transposed Jacobian on a 3x3x3 grid, entry by entry"""
+    print(f"[adjoint dense] {name}", flush=True)
+    w, U0, tau, og, om, gg = _setup(name, dsw)
+    shapes = w.grid.shapes()
+    sizes = [int(np.prod(shapes[k])) for k in FIELDS]
+    n = sum(sizes)
+    J = np.zeros((n, n))
+    col = 0
+    for q, k in enumerate(FIELDS):
+        for e in range(sizes[q]):
+            V = {kk: np.zeros(shapes[kk]) for kk in FIELDS}
+            V[k].reshape(-1)[e] = 1.0
+            _, d = oracle.jvp_split_step(og, om, U0, V, tau, w.K)
+            J[:, col] = np.concatenate([d[kk].ravel() for kk in FIELDS])
+            col += 1
+    lam = cotangent(w.grid, 91)
+    ref = J.T @ np.concatenate([lam[k].ravel() for k in FIELDS])
+    out = gg.empty()
+    gg.adjoint_step(dsw.to_device(U0), tau, w.K, dsw.to_device(lam), out)
+    torch.cuda.synchronize()
+    got = np.concatenate([dsw.to_host(out)[k].ravel() for k in FIELDS])
+    e = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+    print(f"{name}: {n} unknowns, rel L2 of J^T lam = {e:.2e}", flush=True)
+    assert e <= TOL
+
+
+def test_autograd_function(dsw):
+    """torch.autograd through SplitStep: the gradient of <w, U^{n+1}> is the
+    adjoint step applied to w"""
+    w, U0, tau, og, om, gg = _setup("sphere-ragged", dsw)
+    Ud = {k: v.clone().requires_grad_(True) for k, v in dsw.to_device(U0).items()}
+    wt = cotangent(w.grid, 101)
+    U1 = dsw.split_step_fn(gg, Ud, tau, w.K)
+    loss = sum((U1[k] * torch.as_tensor(wt[k], device="cuda")).sum() for k in FIELDS)
+    loss.backward()
+    V = direction(w.grid, 102)
+    _, dU1 = oracle.jvp_split_step(og, om, U0, V, tau, w.K)
+    grad = {k: Ud[k].grad.cpu().numpy() for k in FIELDS}
+    check_dot("autograd", dot(grad, V), dot(wt, dU1))
