@@ -117,6 +117,8 @@ def main():
                     help="launch shapes residual_block,sweep_block_r,sweep_block_theta,phi_rows_per_thread")
     ap.add_argument("--ensemble", action="store_true", help="measure the batched ensemble instead")
     ap.add_argument("--members", type=int, default=64)
+    ap.add_argument("--adjoint", action="store_true",
+                    help="measure the adjoint step against the forward step instead")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the multi-GPU path is "
@@ -125,6 +127,8 @@ def main():
 
     if args.ensemble:
         return bench_ensemble(args)
+    if args.adjoint:
+        return bench_adjoint(args)
 
     import torch
     from paper_2004_13887_amd import dsw
@@ -222,6 +226,66 @@ def main():
         log("[bench] timing the CPU oracle on a bounded sample")
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out), flush=True)
+
+
+def bench_adjoint(args):
+    """adjoint workload (64 x 128 x 256 sector, 100 m, Mach 1e-2, K = 3): time
+    of dsw_adjoint_step (forward recompute from the checkpoint included)
+    against dsw_split_step"""
+    import numpy as np
+    import torch
+    from paper_2004_13887_amd import dsw
+    from paper_2004_13887_amd import inputs as I
+
+    w = I.WORKLOADS["adjoint"]
+    U0, tau = I.initial_state(w)
+    grid = dsw.Grid.from_spec(w.grid, w.material)
+    if args.config:
+        grid.set_config(*(int(x) for x in args.config.split(",")))
+    A, B = dsw.to_device(U0), grid.empty()
+    rng = np.random.Generator(np.random.PCG64(7))
+    lam = {k: torch.as_tensor(rng.uniform(-1.0, 1.0, v.shape), device="cuda") for k, v in U0.items()}
+    out = grid.empty()
+    stream = torch.cuda.current_stream()
+    times = {}
+    for name in ("forward", "adjoint"):
+        def one(n):
+            if name == "forward":
+                src, dst = (A, B) if n % 2 == 0 else (B, A)
+                grid.split_step(src, dst, tau, w.K, stream)
+            else:
+                grid.adjoint_step(A, tau, w.K, lam, out, stream)
+        for n in range(args.warmup):
+            one(n)
+        torch.cuda.synchronize()
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record(stream)
+        for n in range(args.steps):
+            one(args.warmup + n)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        times[name] = ev0.elapsed_time(ev1) / args.steps
+        log(f"[adjoint] {name}: {times[name]:.3f} ms per step")
+    grid.get_status()
+    out_line = {
+        "metric": "adjoint step time / forward step time",
+        "value": times["adjoint"] / times["forward"],
+        "unit": "ratio",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": times["adjoint"],
+        "forward_ms_per_step": times["forward"],
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "adjoint: 256 (phi) x 128 (theta) x 64 (r) sector, 100 m horizontal, "
+                               "K=3, Mach 1e-2, seeded bubble + noise", "cells": w.grid.ncells,
+                   "K": w.K},
+    }
+    print(json.dumps(out_line), flush=True)
 
 
 def bench_ensemble(args):

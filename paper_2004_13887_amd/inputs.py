@@ -287,3 +287,34 @@ def random_fields(g: GridSpec, seed: int, base=None, scale=1.0):
         out["uf"][:, :, 0] = 0.0
         out["uf"][:, :, -1] = 0.0
     return out
+
+
+# ------------------------------------------------- adjoint-check workload --
+
+def adjoint_box_weights(w: Workload, half_width=2.5e3, r_lo=1.0e3, r_hi=3.0e3):
+    """Cell volumes of the cells whose centre lies in the box of the adjoint
+    check (zero elsewhere), shape (nr, nt, np): horizontally within
+    +-half_width of the bubble centre, measured as arc length at r1, and
+    radially in [r1 + r_lo, r1 + r_hi].  Exact spherical cell volumes
+    (r^3/3) dcos(theta) dphi."""
+    g = w.grid
+    c = coords(g)
+    vol_r = (c["rf"][1:] ** 3 - c["rf"][:-1] ** 3) / 3.0
+    vol_t = np.cos(c["tf"][:-1]) - np.cos(c["tf"][1:])
+    vol = vol_r[:, None, None] * vol_t[None, :, None] * c["dp"]
+    in_r = (c["rc"] >= g.r1 + r_lo) & (c["rc"] <= g.r1 + r_hi)
+    in_t = np.abs(c["tc"] - w.bubble_theta) * g.r1 <= half_width
+    in_p = np.abs(c["pc"] - w.bubble_phi) * g.r1 <= half_width
+    mask = in_r[:, None, None] & in_t[None, :, None] & in_p[None, None, :]
+    return np.where(mask, vol, 0.0)
+
+
+def exner(p, mat: MaterialSpec):
+    """(p / p00)^(R / c_p): potential temperature Theta = T / exner(p)"""
+    return (p / P00) ** (mat.R / mat.cp)
+
+
+def adjoint_directions(shape, n=32):
+    """seeded perturbation directions of Theta0 (K per cell), N(0, 1)"""
+    return [np.random.Generator(np.random.PCG64([SEED_BASE + 5, 1000 + j])).standard_normal(shape)
+            for j in range(n)]
