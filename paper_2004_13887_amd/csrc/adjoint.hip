@@ -165,10 +165,8 @@ __device__ void centre_rev(const Geo &g, const Mat &m, const S &s, int i, int j,
 // pressure and temperature rows at a centre (F_p_T of residual.hip);
 // wp, wT: adjoints of F_p and F_T
 template <class S>
-__device__ void F_p_T_rev(const Geo &g, const Mat &m, const S &s, int i, int j, int k, double wp,
-                          double wT, const Fields &A) {
-  Cent c;
-  centre(g, m, s, i, j, k, c);
+__device__ void F_p_T_rev_cb(const Geo &g, const Mat &m, const S &s, int i, int j, int k, const Cent &c,
+                             double wp, double wT, Cent &cb, const Fields &A) {
   const double ir = g.irc[i], is = g.isc[j], ir2 = ir * ir;
   const double hr = 0.5 * g.idr, ht = 0.5 * ir * g.idt, hp = 0.5 * ir * is * g.idp;
   const double pim = gC(g, s, F_P, i - 1, j, k), pip = gC(g, s, F_P, i + 1, j, k);
@@ -185,12 +183,11 @@ __device__ void F_p_T_rev(const Geo &g, const Mat &m, const S &s, int i, int j, 
   const double phi = m.mu * (2.0 * (c.Grr * c.Grr + c.Gtt * c.Gtt + c.Gff * c.Gff) + c.Srt * c.Srt +
                              c.Srf * c.Srf + c.Stf * c.Stf - (2.0 / 3.0) * c.tr * c.div);
   const double g1 = m.gam - 1.0;
-  Cent cb{};
-  cb.P = m.gam * c.div * wp;
-  cb.div = m.gam * c.P * wp + g1 * c.T * wT;
-  cb.T = g1 * c.div * wT;
+  cb.P += m.gam * c.div * wp;
+  cb.div += m.gam * c.P * wp + g1 * c.T * wT;
+  cb.T += g1 * c.div * wT;
   const double phib = -g1 * wp - c.chi * wT;
-  cb.chi = -(phi + m.kap * lap) * wT;
+  cb.chi += -(phi + m.kap * lap) * wT;
   const double lapb = -g1 * m.kap * wp - c.chi * m.kap * wT;
   cb.Grr += 4.0 * m.mu * c.Grr * phib;
   cb.Gtt += 4.0 * m.mu * c.Gtt * phib;
@@ -223,134 +220,177 @@ __device__ void F_p_T_rev(const Geo &g, const Mat &m, const S &s, int i, int j, 
   sC(g, A, F_P, i, j - 1, k, -c.ut * ht * wp);
   sC(g, A, F_P, i, j, k + 1, c.uf * hp * wp);
   sC(g, A, F_P, i, j, k - 1, -c.uf * hp * wp);
+}
+
+template <class S>
+__device__ void F_p_T_rev(const Geo &g, const Mat &m, const S &s, int i, int j, int k, double wp,
+                          double wT, const Fields &A) {
+  Cent c, cb{};
+  centre(g, m, s, i, j, k, c);
+  F_p_T_rev_cb(g, m, s, i, j, k, c, wp, wT, cb, A);
   centre_rev(g, m, s, i, j, k, c, cb, A);
 }
+
+// The three momentum rows reversed.  Contributions that land on the same
+// load are summed before the one atomic add of that load.  Extra inputs
+// (from the two scalar line rows through the same face, which read the same
+// face density and the same transverse averages): rfx, the adjoint of the
+// face density rho_f = (rho_a + rho_b)/2; uax, ubx, of the two transverse
+// averages ua, ub.
 
 // radial momentum row at interior r-face (f, j, k) (F_ur of residual.hip)
 template <class S>
 __device__ void F_ur_rev(const Geo &g, const Mat &m, const S &s, int f, int j, int k, double w,
-                         const Fields &A) {
+                         const Fields &A, double rfx = 0.0, double uax = 0.0, double ubx = 0.0) {
   const double irF = g.irf[f], is = g.isc[j], irF2 = irF * irF;
-  const double irho = 1.0 / (0.5 * (rho_at(g, m, s, f - 1, j, k) + rho_at(g, m, s, f, j, k)));
+  const double Pa = gC(g, s, F_P, f, j, k) + m.pinf, Ta = gC(g, s, F_T, f, j, k);
+  const double Pb_ = gC(g, s, F_P, f - 1, j, k) + m.pinf, Tb_ = gC(g, s, F_T, f - 1, j, k);
+  const double rho_a = Pa / (m.Rg * Ta), rho_b = Pb_ / (m.Rg * Tb_);
+  const double irho = 1.0 / (0.5 * (rho_b + rho_a));
   const double nu = m.mu * irho;
   const double un = gR(g, s, f, j, k);
-  const double ua = 0.25 * (gT(g, s, f - 1, j, k) + gT(g, s, f - 1, j + 1, k) + gT(g, s, f, j, k) +
-                            gT(g, s, f, j + 1, k));
-  const double ub = 0.25 * (gF(g, s, f - 1, j, k) + gF(g, s, f - 1, j, k + 1) + gF(g, s, f, j, k) +
-                            gF(g, s, f, j, k + 1));
+  const double T00 = gT(g, s, f - 1, j, k), T01 = gT(g, s, f - 1, j + 1, k);
+  const double T10 = gT(g, s, f, j, k), T11 = gT(g, s, f, j + 1, k);
+  const double F00 = gF(g, s, f - 1, j, k), F01 = gF(g, s, f - 1, j, k + 1);
+  const double F10 = gF(g, s, f, j, k), F11 = gF(g, s, f, j, k + 1);
+  const double ua = 0.25 * (T00 + T01 + T10 + T11);
+  const double ub = 0.25 * (F00 + F01 + F10 + F11);
   const double xp = gR(g, s, f + 1, j, k), xm = gR(g, s, f - 1, j, k);
   const double yp = gR(g, s, f, j + 1, k), ym = gR(g, s, f, j - 1, k);
   const double zp = gR(g, s, f, j, k + 1), zm = gR(g, s, f, j, k - 1);
-  const double pa = gC(g, s, F_P, f, j, k), pb = gC(g, s, F_P, f - 1, j, k);
+  const double pa = Pa - m.pinf, pb = Pb_ - m.pinf;
   const double Cr = irF2 * g.idr * g.idr, Ct = irF2 * is * g.idt * g.idt, Cp = irF2 * is * is * g.idp * g.idp;
   const double ra2 = g.rc[f] * g.rc[f], rb2 = g.rc[f - 1] * g.rc[f - 1];
   double vis = (ra2 * (xp - un) - rb2 * (un - xm)) * Cr + (g.sf[j + 1] * (yp - un) - g.sf[j] * (un - ym)) * Ct +
                (zp - 2.0 * un + zm) * Cp;
-  const double dth = 0.5 *
-                     ((g.sf[j + 1] * gT(g, s, f - 1, j + 1, k) - g.sf[j] * gT(g, s, f - 1, j, k)) +
-                      (g.sf[j + 1] * gT(g, s, f, j + 1, k) - g.sf[j] * gT(g, s, f, j, k))) * g.idt;
-  const double dph = 0.5 *
-                     ((gF(g, s, f - 1, j, k + 1) - gF(g, s, f - 1, j, k)) +
-                      (gF(g, s, f, j, k + 1) - gF(g, s, f, j, k))) * g.idp;
+  const double dth = 0.5 * ((g.sf[j + 1] * T01 - g.sf[j] * T00) + (g.sf[j + 1] * T11 - g.sf[j] * T10)) * g.idt;
+  const double dph = 0.5 * ((F01 - F00) + (F11 - F10)) * g.idp;
   vis += -2.0 * un * irF2 - 2.0 * irF2 * is * dth - 2.0 * irF2 * is * dph;
   const double gd = (divc(g, s, f, j, k) - divc(g, s, f - 1, j, k)) * g.idr;
   // reverse of F = N - nu vis - nu/3 gd + g_r
   const double Nb = w, visb = -nu * w, gdb = -nu / 3.0 * w, nub = -(vis + gd / 3.0) * w;
-  double ubb = -2.0 * m.omega * g.sc[j] * Nb, uab = 0.0, unb = 0.0;
-  divc_rev(g, A, f, j, k, g.idr * gdb);
-  divc_rev(g, A, f - 1, j, k, -g.idr * gdb);
+  double uab = uax, ubb = ubx - 2.0 * m.omega * g.sc[j] * Nb, unb = 0.0;
+  double aT00 = 0.0, aT01 = 0.0, aT10 = 0.0, aT11 = 0.0, aF00 = 0.0, aF01 = 0.0, aF10 = 0.0, aF11 = 0.0;
+  double aRf = 0.0, aRfp = 0.0, aRfm = 0.0;
+  {  // divergences at cells f (+) and f - 1 (-)
+    const double a1 = g.idr * gdb, a0 = -g.idr * gdb;
+    const double ir1 = g.irc[f], ir0 = g.irc[f - 1];
+    const double c1r = ir1 * ir1 * g.idr * a1, c1t = ir1 * is * g.idt * a1, c1p = ir1 * is * g.idp * a1;
+    const double c0r = ir0 * ir0 * g.idr * a0, c0t = ir0 * is * g.idt * a0, c0p = ir0 * is * g.idp * a0;
+    aRfp += g.rf[f + 1] * g.rf[f + 1] * c1r;
+    aRf += -g.rf[f] * g.rf[f] * c1r + g.rf[f] * g.rf[f] * c0r;
+    aRfm += -g.rf[f - 1] * g.rf[f - 1] * c0r;
+    aT11 += g.sf[j + 1] * c1t; aT10 -= g.sf[j] * c1t;
+    aT01 += g.sf[j + 1] * c0t; aT00 -= g.sf[j] * c0t;
+    aF11 += c1p; aF10 -= c1p;
+    aF01 += c0p; aF00 -= c0p;
+  }
   unb += -2.0 * irF2 * visb;
   const double dthb = -2.0 * irF2 * is * visb, dphb = -2.0 * irF2 * is * visb;
-  sF(g, A, f - 1, j, k + 1, 0.5 * g.idp * dphb);
-  sF(g, A, f - 1, j, k, -0.5 * g.idp * dphb);
-  sF(g, A, f, j, k + 1, 0.5 * g.idp * dphb);
-  sF(g, A, f, j, k, -0.5 * g.idp * dphb);
-  sT(g, A, f - 1, j + 1, k, 0.5 * g.idt * g.sf[j + 1] * dthb);
-  sT(g, A, f - 1, j, k, -0.5 * g.idt * g.sf[j] * dthb);
-  sT(g, A, f, j + 1, k, 0.5 * g.idt * g.sf[j + 1] * dthb);
-  sT(g, A, f, j, k, -0.5 * g.idt * g.sf[j] * dthb);
+  aF01 += 0.5 * g.idp * dphb; aF00 -= 0.5 * g.idp * dphb;
+  aF11 += 0.5 * g.idp * dphb; aF10 -= 0.5 * g.idp * dphb;
+  aT01 += 0.5 * g.idt * g.sf[j + 1] * dthb; aT00 -= 0.5 * g.idt * g.sf[j] * dthb;
+  aT11 += 0.5 * g.idt * g.sf[j + 1] * dthb; aT10 -= 0.5 * g.idt * g.sf[j] * dthb;
   double xpb = ra2 * Cr * visb, xmb = rb2 * Cr * visb;
   double ypb = g.sf[j + 1] * Ct * visb, ymb = g.sf[j] * Ct * visb;
   double zpb = Cp * visb, zmb = Cp * visb;
   unb -= ((ra2 + rb2) * Cr + (g.sf[j + 1] + g.sf[j]) * Ct + 2.0 * Cp) * visb;
-  // N
   const double hr = 0.5 * g.idr, ht = 0.5 * irF * g.idt, hp = 0.5 * irF * is * g.idp;
   double irhob = (pa - pb) * g.idr * Nb;
-  sC(g, A, F_P, f, j, k, irho * g.idr * Nb);
-  sC(g, A, F_P, f - 1, j, k, -irho * g.idr * Nb);
+  double aPa = irho * g.idr * Nb, aPb = -irho * g.idr * Nb;
   unb += (xp - xm) * hr * Nb; xpb += un * hr * Nb; xmb -= un * hr * Nb;
   uab += (yp - ym) * ht * Nb; ypb += ua * ht * Nb; ymb -= ua * ht * Nb;
   ubb += (zp - zm) * hp * Nb; zpb += ub * hp * Nb; zmb -= ub * hp * Nb;
   uab += -2.0 * ua * irF * Nb;
   ubb += -2.0 * ub * irF * Nb;
   irhob += m.mu * nub;
-  const double rhob = -0.5 * irho * irho * irhob;
-  rho_rev(g, m, s, A, f - 1, j, k, rhob);
-  rho_rev(g, m, s, A, f, j, k, rhob);
-  sR(g, A, f, j, k, unb);
-  sR(g, A, f + 1, j, k, xpb);
-  sR(g, A, f - 1, j, k, xmb);
+  const double rhob = 0.5 * (rfx - irho * irho * irhob); // each of the two cells
+  aPa += rhob / (m.Rg * Ta);
+  aPb += rhob / (m.Rg * Tb_);
+  const double aTa = -rhob * rho_a / Ta, aTb = -rhob * rho_b / Tb_;
+  aT00 += 0.25 * uab; aT01 += 0.25 * uab; aT10 += 0.25 * uab; aT11 += 0.25 * uab;
+  aF00 += 0.25 * ubb; aF01 += 0.25 * ubb; aF10 += 0.25 * ubb; aF11 += 0.25 * ubb;
+  sR(g, A, f, j, k, unb + aRf);
+  sR(g, A, f + 1, j, k, xpb + aRfp);
+  sR(g, A, f - 1, j, k, xmb + aRfm);
   sR(g, A, f, j + 1, k, ypb);
   sR(g, A, f, j - 1, k, ymb);
   sR(g, A, f, j, k + 1, zpb);
   sR(g, A, f, j, k - 1, zmb);
-  sT(g, A, f - 1, j, k, 0.25 * uab);
-  sT(g, A, f - 1, j + 1, k, 0.25 * uab);
-  sT(g, A, f, j, k, 0.25 * uab);
-  sT(g, A, f, j + 1, k, 0.25 * uab);
-  sF(g, A, f - 1, j, k, 0.25 * ubb);
-  sF(g, A, f - 1, j, k + 1, 0.25 * ubb);
-  sF(g, A, f, j, k, 0.25 * ubb);
-  sF(g, A, f, j, k + 1, 0.25 * ubb);
+  sT(g, A, f - 1, j, k, aT00);
+  sT(g, A, f - 1, j + 1, k, aT01);
+  sT(g, A, f, j, k, aT10);
+  sT(g, A, f, j + 1, k, aT11);
+  sF(g, A, f - 1, j, k, aF00);
+  sF(g, A, f - 1, j, k + 1, aF01);
+  sF(g, A, f, j, k, aF10);
+  sF(g, A, f, j, k + 1, aF11);
+  sC(g, A, F_P, f, j, k, aPa);
+  sC(g, A, F_P, f - 1, j, k, aPb);
+  sC(g, A, F_T, f, j, k, aTa);
+  sC(g, A, F_T, f - 1, j, k, aTb);
 }
 
 // colatitudinal momentum row at interior theta-face (i, f, k) (F_ut)
 template <class S>
 __device__ void F_ut_rev(const Geo &g, const Mat &m, const S &s, int i, int f, int k, double w,
-                         const Fields &A) {
+                         const Fields &A, double rfx = 0.0, double uax = 0.0, double ubx = 0.0) {
   const double ir = g.irc[i], isF = g.isf[f], ctF = g.ctf[f], ir2 = ir * ir;
   const int j0 = f - 1, j1 = f;
-  const double irho = 1.0 / (0.5 * (rho_at(g, m, s, i, j0, k) + rho_at(g, m, s, i, j1, k)));
+  const double P1 = gC(g, s, F_P, i, j1, k) + m.pinf, T1 = gC(g, s, F_T, i, j1, k);
+  const double P0 = gC(g, s, F_P, i, j0, k) + m.pinf, T0 = gC(g, s, F_T, i, j0, k);
+  const double rho1 = P1 / (m.Rg * T1), rho0 = P0 / (m.Rg * T0);
+  const double irho = 1.0 / (0.5 * (rho0 + rho1));
   const double nu = m.mu * irho;
   const double un = gT(g, s, i, f, k);
-  const double ua = 0.25 * (gR(g, s, i, j0, k) + gR(g, s, i, j1, k) + gR(g, s, i + 1, j0, k) +
-                            gR(g, s, i + 1, j1, k));
-  const double ub = 0.25 * (gF(g, s, i, j0, k) + gF(g, s, i, j0, k + 1) + gF(g, s, i, j1, k) +
-                            gF(g, s, i, j1, k + 1));
+  const double R00 = gR(g, s, i, j0, k), R01 = gR(g, s, i, j1, k);
+  const double R10 = gR(g, s, i + 1, j0, k), R11 = gR(g, s, i + 1, j1, k);
+  const double F00 = gF(g, s, i, j0, k), F01 = gF(g, s, i, j0, k + 1);
+  const double F10 = gF(g, s, i, j1, k), F11 = gF(g, s, i, j1, k + 1);
+  const double ua = 0.25 * (R00 + R01 + R10 + R11);
+  const double ub = 0.25 * (F00 + F01 + F10 + F11);
   const double xp = gT(g, s, i + 1, f, k), xm = gT(g, s, i - 1, f, k);
   const double yp = gT(g, s, i, f + 1, k), ym = gT(g, s, i, f - 1, k);
   const double zp = gT(g, s, i, f, k + 1), zm = gT(g, s, i, f, k - 1);
-  const double p1 = gC(g, s, F_P, i, j1, k), p0 = gC(g, s, F_P, i, j0, k);
+  const double p1 = P1 - m.pinf, p0 = P0 - m.pinf;
   const double Cr = ir2 * g.idr * g.idr, Ct = ir2 * isF * g.idt * g.idt, Cp = ir2 * isF * isF * g.idp * g.idp;
   const double rp2 = g.rf[i + 1] * g.rf[i + 1], rm2 = g.rf[i] * g.rf[i];
   double vis = (rp2 * (xp - un) - rm2 * (un - xm)) * Cr + (g.sc[j1] * (yp - un) - g.sc[j0] * (un - ym)) * Ct +
                (zp - 2.0 * un + zm) * Cp;
-  const double dthr = 0.5 * ((gR(g, s, i, j1, k) - gR(g, s, i, j0, k)) + (gR(g, s, i + 1, j1, k) - gR(g, s, i + 1, j0, k))) * g.idt;
-  const double dphf = 0.5 * ((gF(g, s, i, j0, k + 1) - gF(g, s, i, j0, k)) + (gF(g, s, i, j1, k + 1) - gF(g, s, i, j1, k))) * g.idp;
+  const double dthr = 0.5 * ((R01 - R00) + (R11 - R10)) * g.idt;
+  const double dphf = 0.5 * ((F01 - F00) + (F11 - F10)) * g.idp;
   vis += -un * ir2 * isF * isF + 2.0 * ir2 * dthr - 2.0 * ctF * ir2 * isF * dphf;
   const double gd = (divc(g, s, i, j1, k) - divc(g, s, i, j0, k)) * (ir * g.idt);
   const double Nb = w, visb = -nu * w, gdb = -nu / 3.0 * w, nub = -(vis + gd / 3.0) * w;
-  double ubb = -2.0 * m.omega * g.cf[f] * Nb, uab = 0.0, unb = 0.0;
-  divc_rev(g, A, i, j1, k, ir * g.idt * gdb);
-  divc_rev(g, A, i, j0, k, -ir * g.idt * gdb);
+  double uab = uax, ubb = ubx - 2.0 * m.omega * g.cf[f] * Nb, unb = 0.0;
+  double aR00 = 0.0, aR01 = 0.0, aR10 = 0.0, aR11 = 0.0, aF00 = 0.0, aF01 = 0.0, aF10 = 0.0, aF11 = 0.0;
+  double aTf = 0.0, aTfp = 0.0, aTfm = 0.0;
+  {  // divergences at cells (i, j1) (+) and (i, j0) (-)
+    const double a1 = ir * g.idt * gdb, a0 = -ir * g.idt * gdb;
+    const double is1 = g.isc[j1], is0 = g.isc[j0];
+    const double c1r = ir * ir * g.idr * a1, c1t = ir * is1 * g.idt * a1, c1p = ir * is1 * g.idp * a1;
+    const double c0r = ir * ir * g.idr * a0, c0t = ir * is0 * g.idt * a0, c0p = ir * is0 * g.idp * a0;
+    aR11 += g.rf[i + 1] * g.rf[i + 1] * c1r; aR01 -= g.rf[i] * g.rf[i] * c1r;
+    aR10 += g.rf[i + 1] * g.rf[i + 1] * c0r; aR00 -= g.rf[i] * g.rf[i] * c0r;
+    aTfp += g.sf[j1 + 1] * c1t;
+    aTf += -g.sf[j1] * c1t + g.sf[j0 + 1] * c0t;
+    aTfm += -g.sf[j0] * c0t;
+    aF11 += c1p; aF10 -= c1p;
+    aF01 += c0p; aF00 -= c0p;
+  }
   unb += -ir2 * isF * isF * visb;
   const double dthrb = 2.0 * ir2 * visb, dphfb = -2.0 * ctF * ir2 * isF * visb;
-  sR(g, A, i, j1, k, 0.5 * g.idt * dthrb);
-  sR(g, A, i, j0, k, -0.5 * g.idt * dthrb);
-  sR(g, A, i + 1, j1, k, 0.5 * g.idt * dthrb);
-  sR(g, A, i + 1, j0, k, -0.5 * g.idt * dthrb);
-  sF(g, A, i, j0, k + 1, 0.5 * g.idp * dphfb);
-  sF(g, A, i, j0, k, -0.5 * g.idp * dphfb);
-  sF(g, A, i, j1, k + 1, 0.5 * g.idp * dphfb);
-  sF(g, A, i, j1, k, -0.5 * g.idp * dphfb);
+  aR01 += 0.5 * g.idt * dthrb; aR00 -= 0.5 * g.idt * dthrb;
+  aR11 += 0.5 * g.idt * dthrb; aR10 -= 0.5 * g.idt * dthrb;
+  aF01 += 0.5 * g.idp * dphfb; aF00 -= 0.5 * g.idp * dphfb;
+  aF11 += 0.5 * g.idp * dphfb; aF10 -= 0.5 * g.idp * dphfb;
   double xpb = rp2 * Cr * visb, xmb = rm2 * Cr * visb;
   double ypb = g.sc[j1] * Ct * visb, ymb = g.sc[j0] * Ct * visb;
   double zpb = Cp * visb, zmb = Cp * visb;
   unb -= ((rp2 + rm2) * Cr + (g.sc[j1] + g.sc[j0]) * Ct + 2.0 * Cp) * visb;
   const double hr = 0.5 * g.idr, ht = 0.5 * ir * g.idt, hp = 0.5 * ir * isF * g.idp;
   double irhob = (p1 - p0) * ir * g.idt * Nb;
-  sC(g, A, F_P, i, j1, k, irho * ir * g.idt * Nb);
-  sC(g, A, F_P, i, j0, k, -irho * ir * g.idt * Nb);
+  double aP1 = irho * ir * g.idt * Nb, aP0 = -irho * ir * g.idt * Nb;
   uab += (xp - xm) * hr * Nb; xpb += ua * hr * Nb; xmb -= ua * hr * Nb;
   unb += (yp - ym) * ht * Nb; ypb += un * ht * Nb; ymb -= un * ht * Nb;
   ubb += (zp - zm) * hp * Nb; zpb += ub * hp * Nb; zmb -= ub * hp * Nb;
@@ -358,73 +398,92 @@ __device__ void F_ut_rev(const Geo &g, const Mat &m, const S &s, int i, int f, i
   uab += un * ir * Nb;
   ubb += -2.0 * ub * ctF * ir * Nb;
   irhob += m.mu * nub;
-  const double rhob = -0.5 * irho * irho * irhob;
-  rho_rev(g, m, s, A, i, j0, k, rhob);
-  rho_rev(g, m, s, A, i, j1, k, rhob);
-  sT(g, A, i, f, k, unb);
+  const double rhob = 0.5 * (rfx - irho * irho * irhob);
+  aP1 += rhob / (m.Rg * T1);
+  aP0 += rhob / (m.Rg * T0);
+  const double aT1 = -rhob * rho1 / T1, aT0 = -rhob * rho0 / T0;
+  aR00 += 0.25 * uab; aR01 += 0.25 * uab; aR10 += 0.25 * uab; aR11 += 0.25 * uab;
+  aF00 += 0.25 * ubb; aF01 += 0.25 * ubb; aF10 += 0.25 * ubb; aF11 += 0.25 * ubb;
+  sT(g, A, i, f, k, unb + aTf);
   sT(g, A, i + 1, f, k, xpb);
   sT(g, A, i - 1, f, k, xmb);
-  sT(g, A, i, f + 1, k, ypb);
-  sT(g, A, i, f - 1, k, ymb);
+  sT(g, A, i, f + 1, k, ypb + aTfp);
+  sT(g, A, i, f - 1, k, ymb + aTfm);
   sT(g, A, i, f, k + 1, zpb);
   sT(g, A, i, f, k - 1, zmb);
-  sR(g, A, i, j0, k, 0.25 * uab);
-  sR(g, A, i, j1, k, 0.25 * uab);
-  sR(g, A, i + 1, j0, k, 0.25 * uab);
-  sR(g, A, i + 1, j1, k, 0.25 * uab);
-  sF(g, A, i, j0, k, 0.25 * ubb);
-  sF(g, A, i, j0, k + 1, 0.25 * ubb);
-  sF(g, A, i, j1, k, 0.25 * ubb);
-  sF(g, A, i, j1, k + 1, 0.25 * ubb);
+  sR(g, A, i, j0, k, aR00);
+  sR(g, A, i, j1, k, aR01);
+  sR(g, A, i + 1, j0, k, aR10);
+  sR(g, A, i + 1, j1, k, aR11);
+  sF(g, A, i, j0, k, aF00);
+  sF(g, A, i, j0, k + 1, aF01);
+  sF(g, A, i, j1, k, aF10);
+  sF(g, A, i, j1, k + 1, aF11);
+  sC(g, A, F_P, i, j1, k, aP1);
+  sC(g, A, F_P, i, j0, k, aP0);
+  sC(g, A, F_T, i, j1, k, aT1);
+  sC(g, A, F_T, i, j0, k, aT0);
 }
 
 // azimuthal momentum row at phi-face (i, j, f) (F_uf)
 template <class S>
 __device__ void F_uf_rev(const Geo &g, const Mat &m, const S &s, int i, int j, int f, double w,
-                         const Fields &A) {
+                         const Fields &A, double rfx = 0.0, double uax = 0.0, double ubx = 0.0) {
   const double ir = g.irc[i], is = g.isc[j], ct = g.ctc[j], ir2 = ir * ir;
   const int k0 = g.periodic ? wrapk(g, f - 1) : f - 1, k1 = g.periodic ? wrapk(g, f) : f;
-  const double irho = 1.0 / (0.5 * (rho_at(g, m, s, i, j, k0) + rho_at(g, m, s, i, j, k1)));
+  const double P1 = gC(g, s, F_P, i, j, k1) + m.pinf, T1 = gC(g, s, F_T, i, j, k1);
+  const double P0 = gC(g, s, F_P, i, j, k0) + m.pinf, T0 = gC(g, s, F_T, i, j, k0);
+  const double rho1 = P1 / (m.Rg * T1), rho0 = P0 / (m.Rg * T0);
+  const double irho = 1.0 / (0.5 * (rho0 + rho1));
   const double nu = m.mu * irho;
   const double un = gF(g, s, i, j, f);
-  const double ua = 0.25 * (gR(g, s, i, j, k0) + gR(g, s, i, j, k1) + gR(g, s, i + 1, j, k0) +
-                            gR(g, s, i + 1, j, k1));
-  const double ub = 0.25 * (gT(g, s, i, j, k0) + gT(g, s, i, j, k1) + gT(g, s, i, j + 1, k0) +
-                            gT(g, s, i, j + 1, k1));
+  const double R00 = gR(g, s, i, j, k0), R01 = gR(g, s, i, j, k1);
+  const double R10 = gR(g, s, i + 1, j, k0), R11 = gR(g, s, i + 1, j, k1);
+  const double T00 = gT(g, s, i, j, k0), T01 = gT(g, s, i, j, k1);
+  const double T10 = gT(g, s, i, j + 1, k0), T11 = gT(g, s, i, j + 1, k1);
+  const double ua = 0.25 * (R00 + R01 + R10 + R11);
+  const double ub = 0.25 * (T00 + T01 + T10 + T11);
   const double xp = gF(g, s, i + 1, j, f), xm = gF(g, s, i - 1, j, f);
   const double yp = gF(g, s, i, j + 1, f), ym = gF(g, s, i, j - 1, f);
   const double zp = gF(g, s, i, j, f + 1), zm = gF(g, s, i, j, f - 1);
-  const double p1 = gC(g, s, F_P, i, j, k1), p0 = gC(g, s, F_P, i, j, k0);
+  const double p1 = P1 - m.pinf, p0 = P0 - m.pinf;
   const double Cr = ir2 * g.idr * g.idr, Ct = ir2 * is * g.idt * g.idt, Cp = ir2 * is * is * g.idp * g.idp;
   const double rp2 = g.rf[i + 1] * g.rf[i + 1], rm2 = g.rf[i] * g.rf[i];
   double vis = (rp2 * (xp - un) - rm2 * (un - xm)) * Cr + (g.sf[j + 1] * (yp - un) - g.sf[j] * (un - ym)) * Ct +
                (zp - 2.0 * un + zm) * Cp;
-  const double dphr = 0.5 * ((gR(g, s, i, j, k1) - gR(g, s, i, j, k0)) + (gR(g, s, i + 1, j, k1) - gR(g, s, i + 1, j, k0))) * g.idp;
-  const double dpht = 0.5 * ((gT(g, s, i, j, k1) - gT(g, s, i, j, k0)) + (gT(g, s, i, j + 1, k1) - gT(g, s, i, j + 1, k0))) * g.idp;
+  const double dphr = 0.5 * ((R01 - R00) + (R11 - R10)) * g.idp;
+  const double dpht = 0.5 * ((T01 - T00) + (T11 - T10)) * g.idp;
   vis += -un * ir2 * is * is + 2.0 * ir2 * is * dphr + 2.0 * ct * ir2 * is * dpht;
   const double gd = (divc(g, s, i, j, k1) - divc(g, s, i, j, k0)) * (ir * is * g.idp);
   const double Nb = w, visb = -nu * w, gdb = -nu / 3.0 * w, nub = -(vis + gd / 3.0) * w;
-  double ubb = 2.0 * m.omega * g.cc[j] * Nb, uab = 2.0 * m.omega * g.sc[j] * Nb, unb = 0.0;
-  divc_rev(g, A, i, j, k1, ir * is * g.idp * gdb);
-  divc_rev(g, A, i, j, k0, -ir * is * g.idp * gdb);
+  double ubb = ubx + 2.0 * m.omega * g.cc[j] * Nb, uab = uax + 2.0 * m.omega * g.sc[j] * Nb, unb = 0.0;
+  double aR00 = 0.0, aR01 = 0.0, aR10 = 0.0, aR11 = 0.0, aT00 = 0.0, aT01 = 0.0, aT10 = 0.0, aT11 = 0.0;
+  double aFf = 0.0, aFfp = 0.0, aFfm = 0.0;
+  {  // divergences at cells (i, j, k1) (+) and (i, j, k0) (-); their phi
+     // faces k1 + 1 = f + 1, k1 = f, k0 + 1 = f, k0 = f - 1 (wrapped alike)
+    const double a1 = ir * is * g.idp * gdb, a0 = -ir * is * g.idp * gdb;
+    const double cr = ir * ir * g.idr, irs = ir * is;
+    aR11 += g.rf[i + 1] * g.rf[i + 1] * cr * a1; aR01 -= g.rf[i] * g.rf[i] * cr * a1;
+    aR10 += g.rf[i + 1] * g.rf[i + 1] * cr * a0; aR00 -= g.rf[i] * g.rf[i] * cr * a0;
+    aT11 += g.sf[j + 1] * irs * g.idt * a1; aT01 -= g.sf[j] * irs * g.idt * a1;
+    aT10 += g.sf[j + 1] * irs * g.idt * a0; aT00 -= g.sf[j] * irs * g.idt * a0;
+    aFfp += irs * g.idp * a1;
+    aFf += -irs * g.idp * a1 + irs * g.idp * a0;
+    aFfm += -irs * g.idp * a0;
+  }
   unb += -ir2 * is * is * visb;
   const double dphrb = 2.0 * ir2 * is * visb, dphtb = 2.0 * ct * ir2 * is * visb;
-  sR(g, A, i, j, k1, 0.5 * g.idp * dphrb);
-  sR(g, A, i, j, k0, -0.5 * g.idp * dphrb);
-  sR(g, A, i + 1, j, k1, 0.5 * g.idp * dphrb);
-  sR(g, A, i + 1, j, k0, -0.5 * g.idp * dphrb);
-  sT(g, A, i, j, k1, 0.5 * g.idp * dphtb);
-  sT(g, A, i, j, k0, -0.5 * g.idp * dphtb);
-  sT(g, A, i, j + 1, k1, 0.5 * g.idp * dphtb);
-  sT(g, A, i, j + 1, k0, -0.5 * g.idp * dphtb);
+  aR01 += 0.5 * g.idp * dphrb; aR00 -= 0.5 * g.idp * dphrb;
+  aR11 += 0.5 * g.idp * dphrb; aR10 -= 0.5 * g.idp * dphrb;
+  aT01 += 0.5 * g.idp * dphtb; aT00 -= 0.5 * g.idp * dphtb;
+  aT11 += 0.5 * g.idp * dphtb; aT10 -= 0.5 * g.idp * dphtb;
   double xpb = rp2 * Cr * visb, xmb = rm2 * Cr * visb;
   double ypb = g.sf[j + 1] * Ct * visb, ymb = g.sf[j] * Ct * visb;
   double zpb = Cp * visb, zmb = Cp * visb;
   unb -= ((rp2 + rm2) * Cr + (g.sf[j + 1] + g.sf[j]) * Ct + 2.0 * Cp) * visb;
   const double hr = 0.5 * g.idr, ht = 0.5 * ir * g.idt, hp = 0.5 * ir * is * g.idp;
   double irhob = (p1 - p0) * ir * is * g.idp * Nb;
-  sC(g, A, F_P, i, j, k1, irho * ir * is * g.idp * Nb);
-  sC(g, A, F_P, i, j, k0, -irho * ir * is * g.idp * Nb);
+  double aP1 = irho * ir * is * g.idp * Nb, aP0 = -irho * ir * is * g.idp * Nb;
   uab += (xp - xm) * hr * Nb; xpb += ua * hr * Nb; xmb -= ua * hr * Nb;
   ubb += (yp - ym) * ht * Nb; ypb += ub * ht * Nb; ymb -= ub * ht * Nb;
   unb += (zp - zm) * hp * Nb; zpb += un * hp * Nb; zmb -= un * hp * Nb;
@@ -432,40 +491,52 @@ __device__ void F_uf_rev(const Geo &g, const Mat &m, const S &s, int i, int j, i
   uab += un * ir * Nb;
   ubb += un * ct * ir * Nb;
   irhob += m.mu * nub;
-  const double rhob = -0.5 * irho * irho * irhob;
-  rho_rev(g, m, s, A, i, j, k0, rhob);
-  rho_rev(g, m, s, A, i, j, k1, rhob);
-  sF(g, A, i, j, f, unb);
+  const double rhob = 0.5 * (rfx - irho * irho * irhob);
+  aP1 += rhob / (m.Rg * T1);
+  aP0 += rhob / (m.Rg * T0);
+  const double aT1 = -rhob * rho1 / T1, aT0 = -rhob * rho0 / T0;
+  aR00 += 0.25 * uab; aR01 += 0.25 * uab; aR10 += 0.25 * uab; aR11 += 0.25 * uab;
+  aT00 += 0.25 * ubb; aT01 += 0.25 * ubb; aT10 += 0.25 * ubb; aT11 += 0.25 * ubb;
+  sF(g, A, i, j, f, unb + aFf);
   sF(g, A, i + 1, j, f, xpb);
   sF(g, A, i - 1, j, f, xmb);
   sF(g, A, i, j + 1, f, ypb);
   sF(g, A, i, j - 1, f, ymb);
-  sF(g, A, i, j, f + 1, zpb);
-  sF(g, A, i, j, f - 1, zmb);
-  sR(g, A, i, j, k0, 0.25 * uab);
-  sR(g, A, i, j, k1, 0.25 * uab);
-  sR(g, A, i + 1, j, k0, 0.25 * uab);
-  sR(g, A, i + 1, j, k1, 0.25 * uab);
-  sT(g, A, i, j, k0, 0.25 * ubb);
-  sT(g, A, i, j, k1, 0.25 * ubb);
-  sT(g, A, i, j + 1, k0, 0.25 * ubb);
-  sT(g, A, i, j + 1, k1, 0.25 * ubb);
+  sF(g, A, i, j, f + 1, zpb + aFfp);
+  sF(g, A, i, j, f - 1, zmb + aFfm);
+  sR(g, A, i, j, k0, aR00);
+  sR(g, A, i, j, k1, aR01);
+  sR(g, A, i + 1, j, k0, aR10);
+  sR(g, A, i + 1, j, k1, aR11);
+  sT(g, A, i, j, k0, aT00);
+  sT(g, A, i, j, k1, aT01);
+  sT(g, A, i, j + 1, k0, aT10);
+  sT(g, A, i, j + 1, k1, aT11);
+  sC(g, A, F_P, i, j, k1, aP1);
+  sC(g, A, F_P, i, j, k0, aP0);
+  sC(g, A, F_T, i, j, k1, aT1);
+  sC(g, A, F_T, i, j, k0, aT0);
 }
 
 // acc += (d(-tau F_h(Ubar))/dUbar)^T mu over every unknown row (the rows of the
-// boundary-normal faces are constant); index space as k_residual
+// boundary-normal faces are constant); index space as k_residual.  One
+// launch per kind of row (PART 0: p and T at centres, 1: r faces, 2: theta
+// faces, 3: phi faces), which keeps each kernel's registers in bounds.
+template <int PART>
 __global__ void __launch_bounds__(256) k_residual_vjp(Geo g, Mat m, SrcOne u, double tau, Fields mu,
                                                       Fields A) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x, j = blockIdx.y, i = blockIdx.z;
   if (k >= g.npf) return;
   const bool kc = k < g.np;
-  if (i < g.nr && j < g.nt && kc) {
+  if (PART == 0 && i < g.nr && j < g.nt && kc) {
     const long x = idx_c(g, i, j, k);
     F_p_T_rev(g, m, u, i, j, k, -tau * mu.p[x], -tau * mu.T[x], A);
   }
-  if (j < g.nt && kc && i >= 1 && i < g.nr) F_ur_rev(g, m, u, i, j, k, -tau * mu.ur[idx_r(g, i, j, k)], A);
-  if (i < g.nr && kc && j >= 1 && j < g.nt) F_ut_rev(g, m, u, i, j, k, -tau * mu.ut[idx_t(g, i, j, k)], A);
-  if (i < g.nr && j < g.nt && (g.periodic || (k >= 1 && k < g.np)))
+  if (PART == 1 && j < g.nt && kc && i >= 1 && i < g.nr)
+    F_ur_rev(g, m, u, i, j, k, -tau * mu.ur[idx_r(g, i, j, k)], A);
+  if (PART == 2 && i < g.nr && kc && j >= 1 && j < g.nt)
+    F_ut_rev(g, m, u, i, j, k, -tau * mu.ut[idx_t(g, i, j, k)], A);
+  if (PART == 3 && i < g.nr && j < g.nt && (g.periodic || (k >= 1 && k < g.np)))
     F_uf_rev(g, m, u, i, j, k, -tau * mu.uf[idx_f(g, i, j, k)], A);
 }
 
@@ -473,8 +544,11 @@ void launch_residual_vjp(const Geo &g, const Mat &m, const Fields &Ub, double ta
                          const Fields &acc_, hipStream_t st) {
   SrcOne u;
   u.a[F_P] = Ub.p; u.a[F_UR] = Ub.ur; u.a[F_UT] = Ub.ut; u.a[F_UF] = Ub.uf; u.a[F_T] = Ub.T;
-  dim3 grid((g.npf + 63) / 64, g.nt + 1, g.nr + 1);
-  hipLaunchKernelGGL(k_residual_vjp, grid, dim3(64), 0, st, g, m, u, tau, mu, acc_);
+  const dim3 grid((g.npf + 63) / 64, g.nt + 1, g.nr + 1), block(64);
+  hipLaunchKernelGGL(k_residual_vjp<0>, grid, block, 0, st, g, m, u, tau, mu, acc_);
+  hipLaunchKernelGGL(k_residual_vjp<1>, grid, block, 0, st, g, m, u, tau, mu, acc_);
+  hipLaunchKernelGGL(k_residual_vjp<2>, grid, block, 0, st, g, m, u, tau, mu, acc_);
+  hipLaunchKernelGGL(k_residual_vjp<3>, grid, block, 0, st, g, m, u, tau, mu, acc_);
 }
 
 // ------------------------------------------------- line rows, reversed --
@@ -482,15 +556,13 @@ void launch_residual_vjp(const Geo &g, const Mat &m, const Fields &Ub, double ta
 // Reverse of block_row<D> (rows.hpp) for the coefficient entries: EL, ED, EU
 // are the adjoints of the final (scaled) L, D, U blocks of row s.
 template <int D>
-__device__ void block_row_rev(const Geo &g, const Mat &m, const SrcOne &u, int a, int b, int s, int n,
-                              int cyc, double hs, const double *EL, const double *ED, const double *EU,
-                              const Fields &A) {
+__device__ void block_row_rev_cb(const Geo &g, const Mat &m, const SrcOne &u, int a, int b, int s, int n,
+                                 int cyc, double hs, const double *EL, const double *ED, const double *EU,
+                                 const Cent &c, Cent &cb, const Fields &A) {
   int i, j, k;
   if (D == 0) { i = s; j = a; k = b; }
   else if (D == 1) { i = a; j = s; k = b; }
   else { i = a; j = b; k = s; }
-  Cent c;
-  centre(g, m, u, i, j, k, c);
   const double ir = g.irc[i], is = g.isc[j], ir2 = ir * ir;
   double hadv, dp_, dm_, lp, lm;
   if (D == 0) {
@@ -550,29 +622,27 @@ __device__ void block_row_rev(const Geo &g, const Mat &m, const SrcOne &u, int a
   double Tb = g1 * (dm_ * L[5] + dp_ * Dg[5]);
   const double amb = -g1 * L[2] - c.chi * L[5], apb = -g1 * Dg[2] - c.chi * Dg[5];
   chib += -(am * L[5] + ap * Dg[5]);
-  Cent cb{};
-  cb.P = Pb;
-  cb.T = Tb;
-  cb.chi = chib;
+  cb.P += Pb;
+  cb.T += Tb;
+  cb.chi += chib;
   const double ggb = m.mu * (apb + amb);
-  cb.tr = -(2.0 / 3.0) * m.mu * (dp_ * apb + dm_ * amb);
+  cb.tr += -(2.0 / 3.0) * m.mu * (dp_ * apb + dm_ * amb);
   if (D == 0) {
-    cb.ur = hadv * advb;
-    cb.Grr = 2.0 * m.mu * g.idr * (apb - amb);
-    cb.Gtt = ir * ggb;
-    cb.Gff = ir * ggb;
+    cb.ur += hadv * advb;
+    cb.Grr += 2.0 * m.mu * g.idr * (apb - amb);
+    cb.Gtt += ir * ggb;
+    cb.Gff += ir * ggb;
   } else if (D == 1) {
-    cb.ut = hadv * advb;
-    cb.Gtt = 2.0 * m.mu * ir * g.idt * (apb - amb);
-    cb.Gff = g.ctc[j] * ir * ggb;
-    cb.Srt = -0.5 * ir * ggb;
+    cb.ut += hadv * advb;
+    cb.Gtt += 2.0 * m.mu * ir * g.idt * (apb - amb);
+    cb.Gff += g.ctc[j] * ir * ggb;
+    cb.Srt += -0.5 * ir * ggb;
   } else {
-    cb.uf = hadv * advb;
-    cb.Gff = 2.0 * m.mu * dp_ * (apb - amb);
-    cb.Srf = -0.5 * ir * ggb;
-    cb.Stf = -0.5 * g.ctc[j] * ir * ggb;
+    cb.uf += hadv * advb;
+    cb.Gff += 2.0 * m.mu * dp_ * (apb - amb);
+    cb.Srf += -0.5 * ir * ggb;
+    cb.Stf += -0.5 * g.ctc[j] * ir * ggb;
   }
-  centre_rev(g, m, u, i, j, k, c, cb, A);
   if (!w_unknown) return;
   // w row: gp = irho * G, cp / c0 / cm linear in un and nu = mu irho
   const double U8 = (!cyc && s == n - 2) ? 0.0 : U[8];
@@ -624,15 +694,31 @@ __device__ void block_row_rev(const Geo &g, const Mat &m, const SrcOne &u, int a
   acc(up, unb);
 }
 
+template <int D>
+__device__ void block_row_rev(const Geo &g, const Mat &m, const SrcOne &u, int a, int b, int s, int n,
+                              int cyc, double hs, const double *EL, const double *ED, const double *EU,
+                              const Fields &A) {
+  int i, j, k;
+  if (D == 0) { i = s; j = a; k = b; }
+  else if (D == 1) { i = a; j = s; k = b; }
+  else { i = a; j = b; k = s; }
+  Cent c, cb{};
+  centre(g, m, u, i, j, k, c);
+  block_row_rev_cb<D>(g, m, u, a, b, s, n, cyc, hs, EL, ED, EU, c, cb, A);
+  centre_rev(g, m, u, i, j, k, c, cb, A);
+}
+
 // Reverse of scalar_row<D, FAM> for its entries: ea, eb, ec are the adjoints
 // of the final a, b, c of row s.
+// The reverse is returned as rfb, the adjoint of the face density
+// rho_f = (rho_c0 + rho_c1)/2, and uab, that of the transverse average
+// (scalar_row_parts); scalar_row_rev also scatters them into A.
 template <int D, int FAM>
-__device__ void scalar_row_rev(const Geo &g, const Mat &m, const SrcOne &u, int a, int b, int s, int n,
-                               int cyc, double hs, double ea, double eb, double ec, const Fields &A) {
+__device__ void scalar_row_parts(const Geo &g, const Mat &m, const SrcOne &u, int a, int b, int s, int n,
+                                 int cyc, double hs, double ea, double eb, double ec, double &rfb,
+                                 double &uab, int *cells, long *ix, double *&base, const Fields &A) {
   double h, qa, qb, qc, sglo = -1.0, sghi = -1.0;
   int ci0, cj0, ck0, ci1, cj1, ck1; // the two cells of the face density
-  long ix[4];                        // the four loads of the transverse average
-  double *base;
   if (D == 0) {
     const int i = s;
     const double ir = g.irc[i], r2d2 = ir * ir * g.idr * g.idr;
@@ -699,12 +785,22 @@ __device__ void scalar_row_rev(const Geo &g, const Mat &m, const SrcOne &u, int 
   const double cab = first ? hs * sglo * eb : hs * ea;
   const double cbb = hs * eb;
   const double ccb = last ? hs * sghi * eb : hs * ec;
-  const double uab = h * (ccb - cab);
+  uab = h * (ccb - cab);
   const double nub = -qa * cab + qb * cbb - qc * ccb;
   const double rho = 0.5 * (rho_at(g, m, u, ci0, cj0, ck0) + rho_at(g, m, u, ci1, cj1, ck1));
-  const double rhob = -m.mu / (rho * rho) * nub;
-  rho_rev(g, m, u, A, ci0, cj0, ck0, 0.5 * rhob);
-  rho_rev(g, m, u, A, ci1, cj1, ck1, 0.5 * rhob);
+  rfb = -m.mu / (rho * rho) * nub;
+  cells[0] = ci0; cells[1] = cj0; cells[2] = ck0; cells[3] = ci1; cells[4] = cj1; cells[5] = ck1;
+}
+
+template <int D, int FAM>
+__device__ void scalar_row_rev(const Geo &g, const Mat &m, const SrcOne &u, int a, int b, int s, int n,
+                               int cyc, double hs, double ea, double eb, double ec, const Fields &A) {
+  double rfb, uab, *base;
+  int c[6];
+  long ix[4];
+  scalar_row_parts<D, FAM>(g, m, u, a, b, s, n, cyc, hs, ea, eb, ec, rfb, uab, c, ix, base, A);
+  rho_rev(g, m, u, A, c[0], c[1], c[2], 0.5 * rfb);
+  rho_rev(g, m, u, A, c[3], c[4], c[5], 0.5 * rfb);
 #pragma unroll
   for (int q = 0; q < 4; q++) acc(base + ix[q], 0.25 * uab);
 }
@@ -743,8 +839,9 @@ __device__ __forceinline__ double load1(const Geo &g, const Fields &X, int a, in
 }
 
 // acc += (d(M_d(Ubar) X)/dUbar)^T mu: one thread per row of every line of
-// direction D (rows s outer, lines inner, so that lanes read neighbouring
-// phi positions)
+// direction D, numbered so that neighbouring lanes touch neighbouring phi
+// positions (r and theta lines: rows outer, lines inner; phi lines: lines
+// outer, rows inner)
 template <int D>
 __global__ void __launch_bounds__(256) k_line_vjp(Geo g, Mat m, SrcOne u, double hs, Fields X,
                                                   Fields mu, Fields A) {
@@ -754,8 +851,8 @@ __global__ void __launch_bounds__(256) k_line_vjp(Geo g, Mat m, SrcOne u, double
   const int nkf = g.periodic ? g.np : g.np - 1, kf0 = g.periodic ? 0 : 1;
   const long nbr = (long)F.nb * n, nar = (long)F.na * n, nbbr = (long)F.nbb * n;
   if (t < nbr) {
-    const long line = t % F.nb;
-    const int s = (int)(t / F.nb);
+    const long line = D == 2 ? t / n : t % F.nb;
+    const int s = D == 2 ? (int)(t % n) : (int)(t / F.nb);
     int p, q;
     if (D == 2) { p = (int)(line / g.nt); q = (int)(line % g.nt); }
     else { p = (int)(line / g.np); q = (int)(line % g.np); }
@@ -777,8 +874,8 @@ __global__ void __launch_bounds__(256) k_line_vjp(Geo g, Mat m, SrcOne u, double
   }
   long t2 = t - nbr;
   if (t2 < nar) {
-    const long line = t2 % F.na;
-    const int s = (int)(t2 / F.na);
+    const long line = D == 2 ? t2 / n : t2 % F.na;
+    const int s = D == 2 ? (int)(t2 % n) : (int)(t2 / F.na);
     int p, q;
     if (D == 2) { p = 1 + (int)(line / g.nt); q = (int)(line % g.nt); }
     else { p = 1 + (int)(line / g.np); q = (int)(line % g.np); }
@@ -789,8 +886,8 @@ __global__ void __launch_bounds__(256) k_line_vjp(Geo g, Mat m, SrcOne u, double
   }
   t2 -= nar;
   if (t2 < nbbr) {
-    const long line = t2 % F.nbb;
-    const int s = (int)(t2 / F.nbb);
+    const long line = D == 2 ? t2 / n : t2 % F.nbb;
+    const int s = D == 2 ? (int)(t2 % n) : (int)(t2 / F.nbb);
     int p, q;
     if (D == 2) { p = (int)(line / (g.nt - 1)); q = 1 + (int)(line % (g.nt - 1)); }
     else { p = (int)(line / nkf); q = kf0 + (int)(line % nkf); }
@@ -811,6 +908,112 @@ void launch_line_vjp(int d, const Geo &g, const Mat &m, const Fields &Ub, double
   if (d == 0) hipLaunchKernelGGL(k_line_vjp<0>, grid, block, 0, st, g, m, u, hs, X, mu, acc_);
   else if (d == 1) hipLaunchKernelGGL(k_line_vjp<1>, grid, block, 0, st, g, m, u, hs, X, mu, acc_);
   else hipLaunchKernelGGL(k_line_vjp<2>, grid, block, 0, st, g, m, u, hs, X, mu, acc_);
+}
+
+// ------------------------------------------ fused reverse of one iteration --
+
+// For dsw_adjoint_step: acc += (d(-tau F_h)/dUbar)^T mu[0]
+//                              - sum_d (d(M_d(Ubar) X[d])/dUbar)^T mu[d]
+// (d = 0 r, 1 theta, 2 phi).  PART 0: every cell, with the p and T rows and
+// the three block rows through the cell sharing one evaluation of the centre
+// coefficients and one reverse of it; PART 1, 2, 3: the r, theta, phi faces,
+// each with its momentum row and the two scalar rows through it.
+struct AdjIn {
+  Fields X[3], mu[3];
+};
+
+template <int D>
+__device__ __forceinline__ void cell_block_row(const Geo &g, const Mat &m, const SrcOne &u, double hs,
+                                               const AdjIn &in, int i, int j, int k, const Cent &c,
+                                               Cent &cb, const Fields &A) {
+  int a, b, s, n;
+  if (D == 0) { a = j; b = k; s = i; n = g.nr; }
+  else if (D == 1) { a = i; b = k; s = j; n = g.nt; }
+  else { a = i; b = j; s = k; n = g.np; }
+  const int cyc = (D == 2 && g.periodic) ? 1 : 0;
+  double mv[3], xm[3], x0[3], xp[3], EL[9], ED[9], EU[9];
+  load3<D>(g, in.mu[D], a, b, s, n, cyc, mv);
+  load3<D>(g, in.X[D], a, b, s - 1, n, cyc, xm);
+  load3<D>(g, in.X[D], a, b, s, n, cyc, x0);
+  load3<D>(g, in.X[D], a, b, s + 1, n, cyc, xp);
+#pragma unroll
+  for (int r = 0; r < 3; r++)
+#pragma unroll
+    for (int q = 0; q < 3; q++) {
+      EL[r * 3 + q] = -mv[r] * xm[q];
+      ED[r * 3 + q] = -mv[r] * x0[q];
+      EU[r * 3 + q] = -mv[r] * xp[q];
+    }
+  block_row_rev_cb<D>(g, m, u, a, b, s, n, cyc, hs, EL, ED, EU, c, cb, A);
+}
+
+// the scalar row of family FAM in direction D through a face: adds the
+// adjoints of the face density and of the transverse average it reads to
+// rfb, uab (the momentum row of the face reads the same ones)
+template <int D, int FAM>
+__device__ __forceinline__ void face_scalar_row(const Geo &g, const Mat &m, const SrcOne &u, double hs,
+                                                const AdjIn &in, int a, int b, int s, double &rfb,
+                                                double &uab, const Fields &A) {
+  const int n = D == 0 ? g.nr : (D == 1 ? g.nt : g.np);
+  const int cyc = (D == 2 && g.periodic) ? 1 : 0;
+  const double mv = load1<D, FAM>(g, in.mu[D], a, b, s, n, cyc);
+  double r, ua, *base;
+  int c[6];
+  long ix[4];
+  scalar_row_parts<D, FAM>(g, m, u, a, b, s, n, cyc, hs, -mv * load1<D, FAM>(g, in.X[D], a, b, s - 1, n, cyc),
+                           -mv * load1<D, FAM>(g, in.X[D], a, b, s, n, cyc),
+                           -mv * load1<D, FAM>(g, in.X[D], a, b, s + 1, n, cyc), r, ua, c, ix, base, A);
+  rfb += r;
+  uab += ua;
+}
+
+template <int PART>
+__global__ void __launch_bounds__(256) k_adj_local(Geo g, Mat m, SrcOne u, double tau, AdjIn in,
+                                                   Fields A) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x, j = blockIdx.y, i = blockIdx.z;
+  if (k >= g.npf) return;
+  const bool kc = k < g.np;
+  const double hs = 0.5 * tau;
+  const Fields &mu1 = in.mu[0];
+  if (PART == 0 && i < g.nr && j < g.nt && kc) {
+    Cent c, cb{};
+    centre(g, m, u, i, j, k, c);
+    const long x = idx_c(g, i, j, k);
+    F_p_T_rev_cb(g, m, u, i, j, k, c, -tau * mu1.p[x], -tau * mu1.T[x], cb, A);
+    cell_block_row<0>(g, m, u, hs, in, i, j, k, c, cb, A);
+    cell_block_row<1>(g, m, u, hs, in, i, j, k, c, cb, A);
+    cell_block_row<2>(g, m, u, hs, in, i, j, k, c, cb, A);
+    centre_rev(g, m, u, i, j, k, c, cb, A);
+  }
+  double rfb = 0.0, uab = 0.0, ubb = 0.0;
+  if (PART == 1 && j < g.nt && kc && i >= 1 && i < g.nr) {
+    face_scalar_row<1, 0>(g, m, u, hs, in, i, k, j, rfb, uab, A); // u_r along theta: reads ua (u_theta)
+    face_scalar_row<2, 0>(g, m, u, hs, in, i, j, k, rfb, ubb, A); // u_r along phi: reads ub (u_phi)
+    F_ur_rev(g, m, u, i, j, k, -tau * mu1.ur[idx_r(g, i, j, k)], A, rfb, uab, ubb);
+  }
+  if (PART == 2 && i < g.nr && kc && j >= 1 && j < g.nt) {
+    face_scalar_row<0, 0>(g, m, u, hs, in, j, k, i, rfb, uab, A); // u_theta along r: ua (u_r)
+    face_scalar_row<2, 1>(g, m, u, hs, in, i, j, k, rfb, ubb, A); // u_theta along phi: ub (u_phi)
+    F_ut_rev(g, m, u, i, j, k, -tau * mu1.ut[idx_t(g, i, j, k)], A, rfb, uab, ubb);
+  }
+  if (PART == 3 && i < g.nr && j < g.nt && (g.periodic || (k >= 1 && k < g.np))) {
+    face_scalar_row<0, 1>(g, m, u, hs, in, j, k, i, rfb, uab, A); // u_phi along r: ua (u_r)
+    face_scalar_row<1, 1>(g, m, u, hs, in, i, k, j, rfb, ubb, A); // u_phi along theta: ub (u_theta)
+    F_uf_rev(g, m, u, i, j, k, -tau * mu1.uf[idx_f(g, i, j, k)], A, rfb, uab, ubb);
+  }
+}
+
+void launch_adj_local(const Geo &g, const Mat &m, const Fields &Ub, double tau, const Fields *X,
+                      const Fields *mu, const Fields &acc_, hipStream_t st) {
+  SrcOne u;
+  u.a[F_P] = Ub.p; u.a[F_UR] = Ub.ur; u.a[F_UT] = Ub.ut; u.a[F_UF] = Ub.uf; u.a[F_T] = Ub.T;
+  AdjIn in;
+  for (int d = 0; d < 3; d++) { in.X[d] = X[d]; in.mu[d] = mu[d]; }
+  const dim3 grid((g.npf + 63) / 64, g.nt + 1, g.nr + 1), block(64);
+  hipLaunchKernelGGL(k_adj_local<0>, grid, block, 0, st, g, m, u, tau, in, acc_);
+  hipLaunchKernelGGL(k_adj_local<1>, grid, block, 0, st, g, m, u, tau, in, acc_);
+  hipLaunchKernelGGL(k_adj_local<2>, grid, block, 0, st, g, m, u, tau, in, acc_);
+  hipLaunchKernelGGL(k_adj_local<3>, grid, block, 0, st, g, m, u, tau, in, acc_);
 }
 
 // --------------------------------------------------- elementwise helpers --

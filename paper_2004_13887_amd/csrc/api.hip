@@ -521,6 +521,17 @@ extern "C" int dsw_get_status(dsw_grid *G, void *stream) {
 
 // --------------------------------------------------------------- adjoint --
 
+// transposed line solve of direction d on one grid: phi lines by the
+// partitioned solver when the configuration and the line allow it
+static void launch_T(const dsw_grid *G, int d, const Pass &p, hipStream_t st) {
+  if (d == 2 && p.kind == PK_SW2_PART) {
+    launch_phi_T(G->cfg.phi_pm, p.a, (unsigned)G->geo.nr * (unsigned)G->geo.nt,
+                 phi_part_threads(G->geo, G->cfg.phi_pm), phi_part_lds(G->geo, G->cfg.phi_pm), st);
+  } else {
+    launch_sweep_T(d, p.a, cdiv(sweep_lines(G->geo, d), 128), 128, st);
+  }
+}
+
 static int line_solve_T(int d, dsw_grid *G, const dsw_fields *Ubar, double tau, const dsw_fields *rhs,
                         dsw_fields *x, void *stream) {
   if (!G) return fail(DSW_EINVAL, "null handle");
@@ -533,8 +544,7 @@ static int line_solve_T(int d, dsw_grid *G, const dsw_fields *Ubar, double tau, 
   Out o{};
   o.x = F(x);
   o.mode = 0;
-  Pass p = sweep_pass(G, d, F(Ubar), tau, F(rhs), o);
-  launch_sweep_T(d, p.a, cdiv(sweep_lines(G->geo, d), 128), 128, (hipStream_t)stream);
+  launch_T(G, d, sweep_pass(G, d, F(Ubar), tau, F(rhs), o), (hipStream_t)stream);
   return check_launch("transposed sweep kernel");
 }
 
@@ -659,20 +669,13 @@ extern "C" int dsw_adjoint_step(dsw_grid *G, const dsw_fields *Un, double tau, i
     Out o{};
     o.mode = 0;
     o.x = M3;
-    Pass p3 = sweep_pass(G, 2, ubk, tau, L, o);
-    launch_sweep_T(2, p3.a, cdiv(sweep_lines(G->geo, 2), 128), 128, st);
-    launch_line_vjp(2, G->geo, G->m, ubk, tau, X3(k), M3, UBB, st);
+    launch_T(G, 2, sweep_pass(G, 2, ubk, tau, L, o), st);
     o.x = M2;
-    Pass p2 = sweep_pass(G, 1, ubk, tau, M3, o);
-    launch_sweep_T(1, p2.a, cdiv(sweep_lines(G->geo, 1), 128), 128, st);
-    launch_line_vjp(1, G->geo, G->m, ubk, tau, X2(k), M2, UBB, st);
+    launch_T(G, 1, sweep_pass(G, 1, ubk, tau, M3, o), st);
     o.x = M1;
-    Pass p1 = sweep_pass(G, 0, ubk, tau, M2, o);
-    launch_sweep_T(0, p1.a, cdiv(sweep_lines(G->geo, 0), 128), 128, st);
-    launch_line_vjp(0, G->geo, G->m, ubk, tau, X1(k), M1, UBB, st);
-    // the line operators enter as -(dM/dUbar)^T mu: UBB holds +(...) so far
-    launch_axpy3(cnt, -1.0, UBB, 0.0, none, 0.0, none, UBB, st);
-    launch_residual_vjp(G->geo, G->m, ubk, tau, M1, UBB, st);
+    launch_T(G, 0, sweep_pass(G, 0, ubk, tau, M2, o), st);
+    const Fields xs[3] = {X1(k), X2(k), X3(k)}, mus[3] = {M1, M2, M3};
+    launch_adj_local(G->geo, G->m, ubk, tau, xs, mus, UBB, st);
     launch_adj_mix(G->geo, cnt, L, M1, UBB, Lnext, F(lam_n), st);
     L = Lnext;
     Lnext = (Lnext.p == La.p) ? Lb : La;

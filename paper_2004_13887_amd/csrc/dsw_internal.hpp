@@ -93,10 +93,16 @@ size_t phi_part_lds(const Geo &g, int pm);
 // transposed Jacobians of the residual and of the line operators (both
 // accumulate into acc), and elementwise helpers
 void launch_sweep_T(int d, const PassArgs &a, unsigned blocks, unsigned threads, hipStream_t st);
+void launch_phi_T(int pm, const PassArgs &a, unsigned blocks, unsigned threads, size_t lds,
+                  hipStream_t st);
 void launch_residual_vjp(const Geo &g, const Mat &m, const Fields &Ub, double tau, const Fields &mu,
                          const Fields &acc, hipStream_t st);
 void launch_line_vjp(int d, const Geo &g, const Mat &m, const Fields &Ub, double tau, const Fields &X,
                      const Fields &mu, const Fields &acc, hipStream_t st);
+// one reverse iteration's local functions at once (cells, then r, theta, phi
+// faces): acc += (d(-tau F_h)/dUbar)^T mu[0] - sum_d (d(M_d X[d])/dUbar)^T mu[d]
+void launch_adj_local(const Geo &g, const Mat &m, const Fields &Ub, double tau, const Fields *X,
+                      const Fields *mu, const Fields &acc, hipStream_t st);
 void launch_axpy3(const long *cnt, double a, const Fields &x, double b, const Fields &y, double c,
                   const Fields &z, const Fields &out, hipStream_t st);
 void launch_adj_mix(const Geo &g, const long *cnt, const Fields &L, const Fields &mu1, const Fields &ubb,

@@ -129,7 +129,7 @@ __device__ void pcr_scalar(int t, int T, int cyc, double &A, double &B, double &
 }
 
 // ------------------------------------------------------------ block line --
-template <int PM>
+template <int PM, bool TR>
 __device__ void part_block_line(const Geo &g, const Mat &m, const SrcOne &u, const Fields &rhs,
                                 const Out &o, int i, int j, double hs, double *lds, int *status) {
   const int N = g.np, T = part_chunks<PM>(N), cyc = g.periodic;
@@ -143,7 +143,7 @@ __device__ void part_block_line(const Geo &g, const Mat &m, const SrcOne &u, con
 #pragma unroll
   for (int q = 0; q < PM - 1; q++) {
     if (q < len - 1) {
-      block_row<2>(g, m, u, rhs, i, j, a0 + q, N, cyc, hs, R);
+      get_brow<2, TR>(g, m, u, rhs, i, j, a0 + q, N, cyc, hs, R);
       double Dp[9], rr[3], Lx[9], Ai[9];
       if (q == 0) {
 #pragma unroll
@@ -168,7 +168,7 @@ __device__ void part_block_line(const Geo &g, const Mat &m, const SrcOne &u, con
   }
   // separator row (last row of the chunk)
   BRow S;
-  if (act) block_row<2>(g, m, u, rhs, i, j, a0 + len - 1, N, cyc, hs, S);
+  if (act) get_brow<2, TR>(g, m, u, rhs, i, j, a0 + len - 1, N, cyc, hs, S);
   // backward sweep: (Y, E, C) -> (g, V, W), x_q = g_q + V_q x_left + W_q x_sep
 #pragma unroll
   for (int q = PM - 2; q >= 0; q--) {
@@ -282,7 +282,7 @@ __device__ void part_block_line(const Geo &g, const Mat &m, const SrcOne &u, con
 }
 
 // ----------------------------------------------------------- scalar line --
-template <int PM, int FAM>
+template <int PM, int FAM, bool TR>
 __device__ void part_scalar_line(const Geo &g, const Mat &m, const SrcOne &u, const Fields &rhs,
                                  const Out &o, int a, int b, double hs, double *lds, int *status) {
   const int N = g.np, T = part_chunks<PM>(N), cyc = g.periodic;
@@ -298,7 +298,7 @@ __device__ void part_scalar_line(const Geo &g, const Mat &m, const SrcOne &u, co
 #pragma unroll
   for (int q = 0; q < PM - 1; q++) {
     if (q < len - 1) {
-      scalar_row<2, FAM>(g, m, u, rhs, a, b, a0 + q, N, cyc, hs, R, xi, arr);
+      get_srow<2, FAM, TR>(g, m, u, rhs, a, b, a0 + q, N, cyc, hs, R, xi, arr);
       double dp = R.b, rr = R.r, lx = R.a;
       if (q > 0) { dp -= R.a * Cm[q - 1]; rr -= R.a * Ym[q - 1]; lx = -R.a * Em[q - 1]; }
       if (!(dp != 0.0)) status[ST_SINGULAR] = 1;
@@ -309,7 +309,7 @@ __device__ void part_scalar_line(const Geo &g, const Mat &m, const SrcOne &u, co
     }
   }
   SRow S{0, 1, 0, 0};
-  if (act) scalar_row<2, FAM>(g, m, u, rhs, a, b, a0 + len - 1, N, cyc, hs, S, xi, arr);
+  if (act) get_srow<2, FAM, TR>(g, m, u, rhs, a, b, a0 + len - 1, N, cyc, hs, S, xi, arr);
 #pragma unroll
   for (int q = PM - 2; q >= 0; q--) {
     if (q == len - 2) { Em[q] = -Em[q]; Cm[q] = -Cm[q]; }
@@ -367,7 +367,7 @@ __device__ void part_scalar_line(const Geo &g, const Mat &m, const SrcOne &u, co
 // u_theta line on theta-face j (j >= 1).  Flat grid of nr * nt workgroups per
 // grid; one grid or a batch of grids.  The workgroup may be wider than the
 // chunk count: threads past it only join the barriers.
-template <int PM>
+template <int PM, bool TR>
 __device__ __forceinline__ void phi_body(const PassArgs &a, unsigned w, double *lds) {
   const Geo &g = a.g;
   const int j = (int)(w % g.nt), i = (int)(w / g.nt);
@@ -383,9 +383,9 @@ __device__ __forceinline__ void phi_body(const PassArgs &a, unsigned w, double *
     }
     if (!g.periodic && t == 0) x.uf[idx_f(g, i, j, 0)] = 0.0;
   }
-  part_block_line<PM>(g, a.m, a.u, a.rhs, o, i, j, a.tau, lds, a.status);
-  if (i >= 1) part_scalar_line<PM, 0>(g, a.m, a.u, a.rhs, o, i, j, a.tau, lds, a.status);
-  if (j >= 1) part_scalar_line<PM, 1>(g, a.m, a.u, a.rhs, o, i, j, a.tau, lds, a.status);
+  part_block_line<PM, TR>(g, a.m, a.u, a.rhs, o, i, j, a.tau, lds, a.status);
+  if (i >= 1) part_scalar_line<PM, 0, TR>(g, a.m, a.u, a.rhs, o, i, j, a.tau, lds, a.status);
+  if (j >= 1) part_scalar_line<PM, 1, TR>(g, a.m, a.u, a.rhs, o, i, j, a.tau, lds, a.status);
 }
 
 template <int PM, bool B>
@@ -393,10 +393,24 @@ __global__ void __launch_bounds__(256) k_phi_part(PassArgs a, Batch bt) {
   extern __shared__ double lds[];
   if constexpr (B) {
     const int mb = batch_member(bt, blockIdx.x);
-    phi_body<PM>(bt.tab[mb], blockIdx.x - bt.woff[mb], lds);
+    phi_body<PM, false>(bt.tab[mb], blockIdx.x - bt.woff[mb], lds);
   } else {
-    phi_body<PM>(a, blockIdx.x, lds);
+    phi_body<PM, false>(a, blockIdx.x, lds);
   }
+}
+
+// transposed systems (adjoint), one grid: every row of the transposed line
+// is assembled from three rows of the line (see get_brow)
+template <int PM>
+__global__ void __launch_bounds__(256) k_phi_part_T(PassArgs a) {
+  extern __shared__ double lds[];
+  phi_body<PM, true>(a, blockIdx.x, lds);
+}
+
+void launch_phi_T(int pm, const PassArgs &a, unsigned blocks, unsigned threads, size_t lds,
+                  hipStream_t st) {
+  if (pm == 2) hipLaunchKernelGGL(k_phi_part_T<2>, dim3(blocks), dim3(threads), lds, st, a);
+  else hipLaunchKernelGGL(k_phi_part_T<4>, dim3(blocks), dim3(threads), lds, st, a);
 }
 
 bool phi_part_supported(const Geo &g, int pm) {

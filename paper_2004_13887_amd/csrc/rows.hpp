@@ -284,6 +284,66 @@ __device__ void scalar_row(const Geo &g, const Mat &m, const SrcOne &u, const Fi
 }
 
 
+// Row s of the line system, or of its transpose (TR): the transposed row s
+// has lower block U_{s-1}^T, diagonal D_s^T and upper block L_{s+1}^T, and
+// the right-hand side read at row s's unknowns.
+__device__ __forceinline__ void tr3(const double *A, double *B) {
+#pragma unroll
+  for (int r = 0; r < 3; r++)
+#pragma unroll
+    for (int c = 0; c < 3; c++) B[c * 3 + r] = A[r * 3 + c];
+}
+
+template <int D, bool TR>
+__device__ __forceinline__ void get_brow(const Geo &g, const Mat &m, const SrcOne &u,
+                                         const Fields &rhs, int a, int b, int s, int n, int cyc,
+                                         double hs, BRow &R) {
+  block_row<D>(g, m, u, rhs, a, b, s, n, cyc, hs, R);
+  if (!TR) return;
+  double t9[9];
+  tr3(R.D, t9);
+#pragma unroll
+  for (int q = 0; q < 9; q++) R.D[q] = t9[q];
+  const bool has_m = cyc || s > 0, has_p = cyc || s < n - 1;
+  BRow Q;
+  if (has_m) {
+    block_row<D>(g, m, u, rhs, a, b, s > 0 ? s - 1 : n - 1, n, cyc, hs, Q);
+    tr3(Q.U, R.L);
+  } else {
+#pragma unroll
+    for (int q = 0; q < 9; q++) R.L[q] = 0.0;
+  }
+  if (has_p) {
+    block_row<D>(g, m, u, rhs, a, b, s < n - 1 ? s + 1 : 0, n, cyc, hs, Q);
+    tr3(Q.L, R.U);
+  } else {
+#pragma unroll
+    for (int q = 0; q < 9; q++) R.U[q] = 0.0;
+  }
+}
+
+template <int D, int FAM, bool TR>
+__device__ __forceinline__ void get_srow(const Geo &g, const Mat &m, const SrcOne &u,
+                                         const Fields &rhs, int a, int b, int s, int n, int cyc,
+                                         double hs, SRow &R, long &xi, double *&arr) {
+  scalar_row<D, FAM>(g, m, u, rhs, a, b, s, n, cyc, hs, R, xi, arr);
+  if (!TR) return;
+  SRow Q;
+  long xq;
+  double *aq;
+  double lo = 0.0, up = 0.0;
+  if (cyc || s > 0) {
+    scalar_row<D, FAM>(g, m, u, rhs, a, b, s > 0 ? s - 1 : n - 1, n, cyc, hs, Q, xq, aq);
+    lo = Q.c;
+  }
+  if (cyc || s < n - 1) {
+    scalar_row<D, FAM>(g, m, u, rhs, a, b, s < n - 1 ? s + 1 : 0, n, cyc, hs, Q, xq, aq);
+    up = Q.a;
+  }
+  R.a = lo;
+  R.c = up;
+}
+
 __device__ __forceinline__ double *fsel(const Fields &f, int fid) {
   return fid == F_P ? f.p : fid == F_UR ? f.ur : fid == F_UT ? f.ut : fid == F_UF ? f.uf : f.T;
 }

@@ -56,66 +56,6 @@ __device__ void zero_bnd(const Geo &g, const Fields &x, int a, int b) {
   }
 }
 
-// Row s of the line system, or of its transpose (TR): the transposed row s
-// has lower block U_{s-1}^T, diagonal D_s^T and upper block L_{s+1}^T, and
-// the right-hand side read at row s's unknowns.
-__device__ __forceinline__ void tr3(const double *A, double *B) {
-#pragma unroll
-  for (int r = 0; r < 3; r++)
-#pragma unroll
-    for (int c = 0; c < 3; c++) B[c * 3 + r] = A[r * 3 + c];
-}
-
-template <int D, bool TR>
-__device__ __forceinline__ void get_brow(const Geo &g, const Mat &m, const SrcOne &u,
-                                         const Fields &rhs, int a, int b, int s, int n, int cyc,
-                                         double hs, BRow &R) {
-  block_row<D>(g, m, u, rhs, a, b, s, n, cyc, hs, R);
-  if (!TR) return;
-  double t9[9];
-  tr3(R.D, t9);
-#pragma unroll
-  for (int q = 0; q < 9; q++) R.D[q] = t9[q];
-  const bool has_m = cyc || s > 0, has_p = cyc || s < n - 1;
-  BRow Q;
-  if (has_m) {
-    block_row<D>(g, m, u, rhs, a, b, s > 0 ? s - 1 : n - 1, n, cyc, hs, Q);
-    tr3(Q.U, R.L);
-  } else {
-#pragma unroll
-    for (int q = 0; q < 9; q++) R.L[q] = 0.0;
-  }
-  if (has_p) {
-    block_row<D>(g, m, u, rhs, a, b, s < n - 1 ? s + 1 : 0, n, cyc, hs, Q);
-    tr3(Q.L, R.U);
-  } else {
-#pragma unroll
-    for (int q = 0; q < 9; q++) R.U[q] = 0.0;
-  }
-}
-
-template <int D, int FAM, bool TR>
-__device__ __forceinline__ void get_srow(const Geo &g, const Mat &m, const SrcOne &u,
-                                         const Fields &rhs, int a, int b, int s, int n, int cyc,
-                                         double hs, SRow &R, long &xi, double *&arr) {
-  scalar_row<D, FAM>(g, m, u, rhs, a, b, s, n, cyc, hs, R, xi, arr);
-  if (!TR) return;
-  SRow Q;
-  long xq;
-  double *aq;
-  double lo = 0.0, up = 0.0;
-  if (cyc || s > 0) {
-    scalar_row<D, FAM>(g, m, u, rhs, a, b, s > 0 ? s - 1 : n - 1, n, cyc, hs, Q, xq, aq);
-    lo = Q.c;
-  }
-  if (cyc || s < n - 1) {
-    scalar_row<D, FAM>(g, m, u, rhs, a, b, s < n - 1 ? s + 1 : 0, n, cyc, hs, Q, xq, aq);
-    up = Q.a;
-  }
-  R.a = lo;
-  R.c = up;
-}
-
 template <int D, bool TR>
 __device__ void solve_block_line(const Geo &g, const Mat &m, const SrcOne &u, const Fields &rhs,
                                  const Out &o, double *sc, long nl, long line, int a, int b,
@@ -161,6 +101,66 @@ __device__ void solve_block_line(const Geo &g, const Mat &m, const SrcOne &u, co
 #pragma unroll
     for (int q = 0; q < 3; q++) xn[q] = SC(s, 9 + q) - cx[q];
     block_store<D>(g, o, a, b, s, xn);
+  }
+#undef SC
+}
+
+// Transposed non-cyclic block line, M^T x = y, from the block LU factors of
+// M that the forward recurrence builds (M = L U: L has the pivots
+// Ap_s = D_s - A_s C'_{s-1} on its diagonal and the lower blocks A_s below it,
+// U is unit upper with C'_s = Ap_s^{-1} C_s): first U^T z = y,
+// z_s = y_s - C'_{s-1}^T z_{s-1}, alongside the factorisation; then L^T x = z,
+// x_s = Ap_s^{-T} (z_s - A_{s+1}^T x_{s+1}).  Each row is assembled once.
+// scratch [s][q][line], q < 21: Ap^{-1} (9), A (9), z (3)
+template <int D>
+__device__ void solve_block_line_T(const Geo &g, const Mat &m, const SrcOne &u, const Fields &rhs,
+                                   const Out &o, double *sc, long nl, long line, int a, int b, int n,
+                                   double hs, int *status) {
+#define SC(s, q) sc[((long)(s) * 21 + (q)) * nl + line]
+  BRow R;
+  double C[9], z[3], Ap[9], Ai[9], t9[9], t3[3];
+  for (int s = 0; s < n; s++) {
+    block_row<D>(g, m, u, rhs, a, b, s, n, 0, hs, R);
+    if (s == 0) {
+#pragma unroll
+      for (int q = 0; q < 9; q++) Ap[q] = R.D[q];
+#pragma unroll
+      for (int q = 0; q < 3; q++) z[q] = R.b[q];
+    } else {
+      mm3(R.L, C, t9);
+#pragma unroll
+      for (int q = 0; q < 9; q++) Ap[q] = R.D[q] - t9[q];
+#pragma unroll
+      for (int q = 0; q < 3; q++) t3[q] = R.b[q] - (C[q] * z[0] + C[3 + q] * z[1] + C[6 + q] * z[2]);
+#pragma unroll
+      for (int q = 0; q < 3; q++) z[q] = t3[q];
+    }
+    inv3(Ap, Ai, status);
+    mm3(Ai, R.U, C);
+    if (s < n - 1) {
+#pragma unroll
+      for (int q = 0; q < 9; q++) { SC(s, q) = Ai[q]; SC(s, 9 + q) = R.L[q]; }
+#pragma unroll
+      for (int q = 0; q < 3; q++) SC(s, 18 + q) = z[q];
+    }
+  }
+  // x_{n-1} = Ap_{n-1}^{-T} z_{n-1}
+  double x[3], An[9];
+#pragma unroll
+  for (int q = 0; q < 3; q++) x[q] = Ai[q] * z[0] + Ai[3 + q] * z[1] + Ai[6 + q] * z[2];
+#pragma unroll
+  for (int q = 0; q < 9; q++) An[q] = R.L[q];
+  block_store<D>(g, o, a, b, n - 1, x);
+  for (int s = n - 2; s >= 0; s--) {
+    double w[3];
+#pragma unroll
+    for (int q = 0; q < 3; q++)
+      w[q] = SC(s, 18 + q) - (An[q] * x[0] + An[3 + q] * x[1] + An[6 + q] * x[2]);
+#pragma unroll
+    for (int q = 0; q < 9; q++) { Ai[q] = SC(s, q); An[q] = SC(s, 9 + q); }
+#pragma unroll
+    for (int q = 0; q < 3; q++) x[q] = Ai[q] * w[0] + Ai[3 + q] * w[1] + Ai[6 + q] * w[2];
+    block_store<D>(g, o, a, b, s, x);
   }
 #undef SC
 }
@@ -270,7 +270,30 @@ __device__ void solve_scalar_line(const Geo &g, const Mat &m, const SrcOne &u, c
   SRow R;
   long xi;
   double *arr;
-  if (!cyc) {
+  if (!cyc && TR) {
+    // transposed, from the LU factors of the forward recurrence:
+    // z_s = y_s - c'_{s-1} z_{s-1}; x_s = (z_s - a_{s+1} x_{s+1}) / den_s
+#define SC(s, q) sc[((long)(s) * 3 + (q)) * nl + line]
+    double cpv = 0.0, zv = 0.0, av = 0.0, id = 1.0;
+    for (int s = 0; s < n; s++) {
+      scalar_row<D, FAM>(g, m, u, rhs, a, b, s, n, 0, hs, R, xi, arr);
+      const double den = R.b - R.a * cpv;
+      if (!(den != 0.0)) status[ST_SINGULAR] = 1;
+      id = 1.0 / den;
+      zv = R.r - cpv * zv;
+      cpv = R.c * id;
+      av = R.a;
+      if (s < n - 1) { SC(s, 0) = id; SC(s, 1) = R.a; SC(s, 2) = zv; }
+    }
+    double xv = id * zv;
+    put(o, ofid, xi, xv);
+    for (int s = n - 2; s >= 0; s--) {
+      xv = SC(s, 0) * (SC(s, 2) - av * xv);
+      av = SC(s, 1);
+      put(o, ofid, scalar_index<D, FAM>(g, a, b, s), xv);
+    }
+#undef SC
+  } else if (!cyc) {
 #define SC(s, q) sc[((long)(s) * 2 + (q)) * nl + line]
     double cpv = 0.0, yv = 0.0;
     for (int s = 0; s < n; s++) {
@@ -346,7 +369,8 @@ __device__ __forceinline__ void sweep_body(const PassArgs &a, unsigned w) {
     else { p = (int)(t / g.nt); q = (int)(t % g.nt); }
     if (a.o.mode == 0) zero_bnd<D>(g, a.o.x, p, q);
     if (F.cyclic) solve_block_cyclic<D, TR>(g, a.m, a.u, a.rhs, a.o, a.scb, F.nb, t, p, q, F.n, hs, a.status);
-    else solve_block_line<D, TR>(g, a.m, a.u, a.rhs, a.o, a.scb, F.nb, t, p, q, F.n, hs, a.status);
+    else if (TR) solve_block_line_T<D>(g, a.m, a.u, a.rhs, a.o, a.scb, F.nb, t, p, q, F.n, hs, a.status);
+    else solve_block_line<D, false>(g, a.m, a.u, a.rhs, a.o, a.scb, F.nb, t, p, q, F.n, hs, a.status);
     return;
   }
   long t2 = t - F.nb;
@@ -398,7 +422,7 @@ void sweep_scratch_size(const Geo &g, long *blk, long *sca) {
   long b = 0, s = 0;
   for (int d = 0; d < 3; d++) {
     const Families F = families(g, d);
-    const long per = F.cyclic ? 21 : 12, pers = F.cyclic ? 3 : 2;
+    const long per = 21, pers = 3; // transposed and cyclic solvers need the most
     b = b > per * F.n * (long)F.nb ? b : per * F.n * (long)F.nb;
     const long ss = pers * F.n * ((long)F.na + F.nbb);
     s = s > ss ? s : ss;

@@ -118,6 +118,24 @@ def test_adjoint_step_dot_product(name, dsw):
     check_dot(f"{name} J^T (K={w.K})", dot(dsw.to_host(out), V), dot(lam, dU1))
 
 
+@pytest.mark.parametrize("phi", [0, 2])
+@pytest.mark.parametrize("name", ["sector-ragged", "sphere-chunks16", "sphere-chunks2"])
+def test_adjoint_step_other_phi_solvers(name, phi, dsw):
+    """the adjoint with the phi lines solved one thread per line (0) or
+    partitioned with 2 rows per thread"""
+    print(f"[adjoint_step phi={phi}] {name}", flush=True)
+    w, U0, tau, og, om, gg = _setup(name, dsw)
+    gg.set_config(64, 128, 128, phi)
+    lam = cotangent(w.grid, 83)
+    V = direction(w.grid, 84)
+    _, dU1 = oracle.jvp_split_step(og, om, U0, V, tau, w.K)
+    out = gg.empty()
+    gg.adjoint_step(dsw.to_device(U0), tau, w.K, dsw.to_device(lam), out)
+    torch.cuda.synchronize()
+    gg.get_status()
+    check_dot(f"{name} J^T phi={phi}", dot(dsw.to_host(out), V), dot(lam, dU1))
+
+
 @pytest.mark.parametrize("name", ["sector-min", "sphere-min"])
 def test_adjoint_step_dense_tiny(name, dsw):
     """the whole transposed Jacobian on a 3x3x3 grid, entry by entry"""
