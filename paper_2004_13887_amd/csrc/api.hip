@@ -331,12 +331,14 @@ static void plan_step(const dsw_grid *G, const Fields &un, const Fields &uk, dou
     // midpoint state of this iteration: U^n itself at the first one, else the
     // one written by the previous iteration's phi sweep
     const Fields ubar = it == 0 ? un : ubuf[(it - 1) % 2];
-    Pass r{PK_RES, 0, base_args(G)};
+    Pass r{PK_RES_IN, 0, base_args(G)};
     r.a.u = src1(ubar);
     r.a.d = diff(un, it == 0 ? un : uk);
     r.a.tau = tau;
     r.a.R = G->r;
-    out.push_back(r);
+    out.push_back(r);  // interior workgroups
+    r.kind = PK_RES;
+    out.push_back(r);  // the rest
     Out o1{}, o2{}, o3{};
     o1.x = G->x1; o1.mode = 0;
     o2.x = G->x2; o2.mode = 0;
@@ -351,7 +353,8 @@ static void plan_step(const dsw_grid *G, const Fields &un, const Fields &uk, dou
 
 static unsigned kind_threads(int kind, const Geo &g, const Cfg &c) {
   switch (kind) {
-  case PK_RES: return (unsigned)c.res_bs;
+  case PK_RES:
+  case PK_RES_IN: return (unsigned)c.res_bs;
   case PK_SW0: return (unsigned)c.sweep_bs[0];
   case PK_SW1: return (unsigned)c.sweep_bs[1];
   case PK_SW2_PART: return phi_part_threads(g, c.phi_pm);
@@ -365,6 +368,7 @@ static unsigned kind_blocks(int kind, const Geo &g, unsigned threads) {
   switch (kind) {
   case PK_BND: return cdiv(bnd_points(g), threads);
   case PK_RES: return cdiv((unsigned long)g.npf, threads) * (unsigned)(g.nt + 1) * (unsigned)(g.nr + 1);
+  case PK_RES_IN: return residual_interior_blocks(g, (int)threads);
   case PK_SW0: return cdiv(sweep_lines(g, 0), threads);
   case PK_SW1: return cdiv(sweep_lines(g, 1), threads);
   case PK_SW2_LINE: return cdiv(sweep_lines(g, 2), threads);
@@ -381,6 +385,7 @@ static void launch_kind(int kind, const Cfg &c, const PassArgs &a, const Batch &
   switch (kind) {
   case PK_BND: launch_bnd_pass(a, b, blocks, threads, st); break;
   case PK_RES: launch_residual_pass(a, b, blocks, threads, st); break;
+  case PK_RES_IN: launch_residual_in_pass(a, b, blocks, threads, st); break;
   case PK_SW0: launch_sweep_pass(0, a, b, blocks, threads, st); break;
   case PK_SW1: launch_sweep_pass(1, a, b, blocks, threads, st); break;
   case PK_SW2_LINE: launch_sweep_pass(2, a, b, blocks, threads, st); break;
@@ -391,9 +396,10 @@ static void launch_kind(int kind, const Cfg &c, const PassArgs &a, const Batch &
 // one pass on one grid, arguments by value
 static void launch_single(const dsw_grid *G, const Pass &p, hipStream_t st) {
   const unsigned th = kind_threads(p.kind, G->geo, G->cfg);
+  const unsigned nb = kind_blocks(p.kind, G->geo, th);
+  if (nb == 0) return;  // e.g. no interior workgroups on a tiny grid
   const Batch none{nullptr, nullptr, 0};
-  launch_kind(p.kind, G->cfg, p.a, none, kind_blocks(p.kind, G->geo, th), th,
-              kind_lds(p.kind, G->geo, G->cfg), st);
+  launch_kind(p.kind, G->cfg, p.a, none, nb, th, kind_lds(p.kind, G->geo, G->cfg), st);
 }
 
 static int line_solve(int d, dsw_grid *G, const dsw_fields *Ubar, double tau, const dsw_fields *rhs,
@@ -444,7 +450,17 @@ extern "C" int dsw_split_step(dsw_grid *G, const dsw_fields *Un, dsw_fields *Unp
   hipStream_t st = (hipStream_t)stream;
   std::vector<Pass> plan;
   plan_step(G, F(Un), F(Unp1), tau, K, plan);
-  for (const Pass &p : plan) timed(G, p.tk, st, [&] { launch_single(G, p, st); });
+  // consecutive launches of one kind (the two residual launches) are timed together
+  for (size_t q = 0; q < plan.size();) {
+    size_t e = q + 1;
+    while (e < plan.size() && plan[e].tk == plan[q].tk && plan[e].kind != plan[q].kind &&
+           (plan[q].kind == PK_RES_IN))
+      e++;
+    timed(G, plan[q].tk, st, [&] {
+      for (size_t r = q; r < e; r++) launch_single(G, plan[r], st);
+    });
+    q = e;
+  }
   return check_launch("split step kernels");
 }
 
@@ -647,11 +663,13 @@ extern "C" int dsw_adjoint_step(dsw_grid *G, const dsw_fields *Un, double tau, i
   launch_axpy3(cnt, 1.0, un, 0.0, none, 0.0, none, U, st);
   for (int k = 0; k < K; k++) {
     launch_axpy3(cnt, 0.5, U, 0.5, un, 0.0, none, UB(k), st);
-    Pass r{PK_RES, 0, base_args(G)};
+    Pass r{PK_RES_IN, 0, base_args(G)};
     r.a.u = src1(UB(k));
     r.a.d = diff(un, k == 0 ? un : U);
     r.a.tau = tau;
     r.a.R = G->r;
+    launch_single(G, r, st);
+    r.kind = PK_RES;
     launch_single(G, r, st);
     Out o1{}, o2{}, o3{};
     o1.x = X1(k); o2.x = X2(k); o3.x = X3(k);
@@ -833,6 +851,7 @@ static int build_plan(dsw_ensemble *E, const Cfg &cfg, const dsw_fields *Un, dsw
       dsw_ensemble::Group gr;
       gr.kind = kind;
       gr.tk = per[0][q].tk;
+      if (total == 0) continue;  // nothing to launch (e.g. no interior workgroups)
       gr.blocks = (unsigned)total;
       gr.threads = th;
       gr.lds = lds;

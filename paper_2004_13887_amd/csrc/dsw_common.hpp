@@ -50,19 +50,29 @@ __device__ __forceinline__ int wrapk(const Geo &g, int k) {
 }
 __device__ __forceinline__ int clampi(int x, int lo, int hi) { return x < lo ? lo : (x > hi ? hi : x); }
 
-// State sources: a single array set, or the midpoint of two.
-struct SrcOne {
+// State sources: a single array set, or the midpoint of two.  INTERIOR: the
+// caller guarantees that every neighbour a stencil reads lies inside the
+// arrays in r and theta, and in phi too unless phi is periodic (then phi
+// indices are wrapped without branches); the other ghost rules and the
+// 64-bit index arithmetic are skipped.
+template <bool I>
+struct SrcOneT {
   const double *a[5];
+  static constexpr bool INTERIOR = I;
   __device__ __forceinline__ double ld(int f, long x) const { return a[f][x]; }
 };
+using SrcOne = SrcOneT<false>;
+using SrcIn = SrcOneT<true>;
 struct SrcMid {
   const double *n[5], *k[5];
+  static constexpr bool INTERIOR = false;
   __device__ __forceinline__ double ld(int f, long x) const { return 0.5 * (k[f][x] + n[f][x]); }
 };
 
 // p or T at a (possibly ghost) centre
 template <class S>
 __device__ __forceinline__ double gC(const Geo &g, const S &s, int fid, int i, int j, int k) {
+  if constexpr (S::INTERIOR) return s.ld(fid, (i * g.nt + j) * g.np + wrapk(g, k));
   i = clampi(i, 0, g.nr - 1);
   j = clampi(j, 0, g.nt - 1);
   k = g.periodic ? wrapk(g, k) : clampi(k, 0, g.np - 1);
@@ -71,6 +81,7 @@ __device__ __forceinline__ double gC(const Geo &g, const S &s, int fid, int i, i
 // u_r at r-face f (0..nr), ghosts across theta and phi boundaries
 template <class S>
 __device__ __forceinline__ double gR(const Geo &g, const S &s, int f, int j, int k) {
+  if constexpr (S::INTERIOR) return s.ld(F_UR, (f * g.nt + j) * g.np + wrapk(g, k));
   double sg = 1.0;
   if (k < 0 || k >= g.np) {
     if (g.periodic) k = wrapk(g, k);
@@ -83,6 +94,7 @@ __device__ __forceinline__ double gR(const Geo &g, const S &s, int f, int j, int
 // u_theta at theta-face f (0..nt), ghosts across r and phi boundaries
 template <class S>
 __device__ __forceinline__ double gT(const Geo &g, const S &s, int i, int f, int k) {
+  if constexpr (S::INTERIOR) return s.ld(F_UT, (i * (g.nt + 1) + f) * g.np + wrapk(g, k));
   double sg = 1.0;
   if (k < 0 || k >= g.np) {
     if (g.periodic) k = wrapk(g, k);
@@ -95,6 +107,7 @@ __device__ __forceinline__ double gT(const Geo &g, const S &s, int i, int f, int
 // u_phi at phi-face f, ghosts across r and theta boundaries (poles included)
 template <class S>
 __device__ __forceinline__ double gF(const Geo &g, const S &s, int i, int j, int f) {
+  if constexpr (S::INTERIOR) return s.ld(F_UF, (i * g.nt + j) * g.npf + (g.periodic ? wrapk(g, f) : f));
   double sg = 1.0;
   if (g.periodic) f = wrapk(g, f);
   if (j < 0) { sg = -sg; j = 0; }

@@ -8,6 +8,19 @@
 
 namespace dsw {
 
+// Occupancy targets (waves per SIMD) of the hot kernels: the compiler then
+// keeps their registers within 512 / target.  0 leaves the choice to it.
+#ifndef DSW_WAVES_RES
+#define DSW_WAVES_RES 0
+#endif
+#ifndef DSW_WAVES_SWEEP
+#define DSW_WAVES_SWEEP 0
+#endif
+#ifndef DSW_WAVES_PHI
+#define DSW_WAVES_PHI 0
+#endif
+#define DSW_OCC(w) __attribute__((amdgpu_waves_per_eu((w) > 0 ? (w) : 1)))
+
 // device status words, each set by plain stores of 1 (no atomics)
 enum { ST_NONPHYS = 0, ST_SINGULAR = 1, ST_WORDS = 2 };
 
@@ -72,12 +85,16 @@ struct Cfg {
                    // with that many rows per thread
 };
 
-enum PassKind { PK_BND = 0, PK_RES = 1, PK_SW0 = 2, PK_SW1 = 3, PK_SW2_LINE = 4, PK_SW2_PART = 5 };
+enum PassKind { PK_BND = 0, PK_RES = 1, PK_SW0 = 2, PK_SW1 = 3, PK_SW2_LINE = 4, PK_SW2_PART = 5,
+                PK_RES_IN = 6 };
 
 // kernel launchers of the passes: by value for one grid (b.tab == nullptr), or
 // over a batch (blocks = sum over the members, threads and lds = maxima)
 void launch_residual_pass(const PassArgs &a, const Batch &b, unsigned blocks, unsigned threads,
                           hipStream_t st);
+void launch_residual_in_pass(const PassArgs &a, const Batch &b, unsigned blocks, unsigned threads,
+                             hipStream_t st);
+unsigned residual_interior_blocks(const Geo &g, int bs); // workgroups of the interior launch
 void launch_sweep_pass(int d, const PassArgs &a, const Batch &b, unsigned blocks, unsigned threads,
                        hipStream_t st);
 void launch_phi_pass(int pm, const PassArgs &a, const Batch &b, unsigned blocks, unsigned threads,

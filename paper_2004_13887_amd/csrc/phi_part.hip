@@ -389,7 +389,7 @@ __device__ __forceinline__ void phi_body(const PassArgs &a, unsigned w, double *
 }
 
 template <int PM, bool B>
-__global__ void __launch_bounds__(256) k_phi_part(PassArgs a, Batch bt) {
+__global__ void __launch_bounds__(256) DSW_OCC(DSW_WAVES_PHI) k_phi_part(PassArgs a, Batch bt) {
   extern __shared__ double lds[];
   if constexpr (B) {
     const int mb = batch_member(bt, blockIdx.x);

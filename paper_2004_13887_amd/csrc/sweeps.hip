@@ -396,7 +396,7 @@ __device__ __forceinline__ void sweep_body(const PassArgs &a, unsigned w) {
 
 // B: a batch of grids (arguments from the batch table), else one grid
 template <int D, bool B>
-__global__ void __launch_bounds__(256) k_sweep(PassArgs a, Batch bt) {
+__global__ void __launch_bounds__(256) DSW_OCC(DSW_WAVES_SWEEP) k_sweep(PassArgs a, Batch bt) {
   if constexpr (B) {
     const int mb = batch_member(bt, blockIdx.x);
     sweep_body<D, false>(bt.tab[mb], blockIdx.x - bt.woff[mb]);
