@@ -12,6 +12,7 @@
 #include "../../include/dsw.h"
 #include "dsw_common.hpp"
 #include "dsw_internal.hpp"
+#include "rows.hpp"
 
 using namespace dsw;
 
@@ -305,7 +306,11 @@ struct Pass {
 static Pass sweep_pass(const dsw_grid *G, int d, const Fields &ubar, double tau, const Fields &rhs,
                        const Out &o) {
   Pass p;
-  p.kind = d == 0 ? PK_SW0 : d == 1 ? PK_SW1 : phi_kind(G->geo, G->cfg);
+  if (d == 2) p.kind = phi_kind(G->geo, G->cfg);
+  else {
+    const bool tw = families(G->geo, d).nb < TWIST_LINES;
+    p.kind = d == 0 ? (tw ? PK_SW0T : PK_SW0) : (tw ? PK_SW1T : PK_SW1);
+  }
   p.tk = 1 + d;
   p.a = base_args(G);
   p.a.u = src1(ubar);
@@ -355,8 +360,10 @@ static unsigned kind_threads(int kind, const Geo &g, const Cfg &c) {
   switch (kind) {
   case PK_RES:
   case PK_RES_IN: return (unsigned)c.res_bs;
-  case PK_SW0: return (unsigned)c.sweep_bs[0];
-  case PK_SW1: return (unsigned)c.sweep_bs[1];
+  case PK_SW0:
+  case PK_SW0T: return (unsigned)c.sweep_bs[0];
+  case PK_SW1:
+  case PK_SW1T: return (unsigned)c.sweep_bs[1];
   case PK_SW2_PART: return phi_part_threads(g, c.phi_pm);
   default: return 128u; // boundary copy, thread-per-line phi
   }
@@ -371,6 +378,8 @@ static unsigned kind_blocks(int kind, const Geo &g, unsigned threads) {
   case PK_RES_IN: return residual_interior_blocks(g, (int)threads);
   case PK_SW0: return cdiv(sweep_lines(g, 0), threads);
   case PK_SW1: return cdiv(sweep_lines(g, 1), threads);
+  case PK_SW0T: return sweep2_blocks(g, 0, threads);
+  case PK_SW1T: return sweep2_blocks(g, 1, threads);
   case PK_SW2_LINE: return cdiv(sweep_lines(g, 2), threads);
   default: return (unsigned)g.nr * (unsigned)g.nt; // PK_SW2_PART
   }
@@ -388,6 +397,8 @@ static void launch_kind(int kind, const Cfg &c, const PassArgs &a, const Batch &
   case PK_RES_IN: launch_residual_in_pass(a, b, blocks, threads, st); break;
   case PK_SW0: launch_sweep_pass(0, a, b, blocks, threads, st); break;
   case PK_SW1: launch_sweep_pass(1, a, b, blocks, threads, st); break;
+  case PK_SW0T: launch_sweep2_pass(0, a, b, blocks, threads, st); break;
+  case PK_SW1T: launch_sweep2_pass(1, a, b, blocks, threads, st); break;
   case PK_SW2_LINE: launch_sweep_pass(2, a, b, blocks, threads, st); break;
   default: launch_phi_pass(c.phi_pm, a, b, blocks, threads, lds, st); break;
   }
@@ -823,16 +834,13 @@ static int build_plan(dsw_ensemble *E, const Cfg &cfg, const dsw_fields *Un, dsw
     return off;
   };
   for (size_t q = 0; q < npass; q++) {
-    const int kinds[2] = {per[0][q].kind == PK_SW2_PART || per[0][q].kind == PK_SW2_LINE ? PK_SW2_PART
-                                                                                         : per[0][q].kind,
-                          PK_SW2_LINE};
-    const int nk = (kinds[0] == PK_SW2_PART) ? 2 : 1;
-    for (int v = 0; v < nk; v++) {
-      const int kind = kinds[v];
+    std::vector<int> kinds;  // distinct kinds of pass q over the members, in order
+    for (int m = 0; m < n; m++)
+      if (std::find(kinds.begin(), kinds.end(), per[m][q].kind) == kinds.end()) kinds.push_back(per[m][q].kind);
+    for (const int kind : kinds) {
       std::vector<int> who;
       for (int m = 0; m < n; m++)
         if (per[m][q].kind == kind) who.push_back(m);
-      if (who.empty()) continue;
       unsigned th = 0;
       size_t lds = 0;
       for (int m : who) {

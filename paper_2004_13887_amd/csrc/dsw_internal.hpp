@@ -86,7 +86,12 @@ struct Cfg {
 };
 
 enum PassKind { PK_BND = 0, PK_RES = 1, PK_SW0 = 2, PK_SW1 = 3, PK_SW2_LINE = 4, PK_SW2_PART = 5,
-                PK_RES_IN = 6 };
+                PK_RES_IN = 6, PK_SW0T = 7, PK_SW1T = 8 };
+
+// r and theta sweeps take two threads per block line (twisted factorisation)
+// when one thread per line would give the GPU fewer than two waves of block
+// lines per SIMD
+constexpr long TWIST_LINES = 131072;
 
 // kernel launchers of the passes: by value for one grid (b.tab == nullptr), or
 // over a batch (blocks = sum over the members, threads and lds = maxima)
@@ -102,6 +107,10 @@ void launch_phi_pass(int pm, const PassArgs &a, const Batch &b, unsigned blocks,
 void launch_bnd_pass(const PassArgs &a, const Batch &b, unsigned blocks, unsigned threads,
                      hipStream_t st);
 unsigned sweep_lines(const Geo &g, int d);   // lines of all families of sweep d
+// r and theta sweeps with two threads per block line (twisted factorisation)
+void launch_sweep2_pass(int d, const PassArgs &a, const Batch &b, unsigned blocks, unsigned threads,
+                        hipStream_t st);
+unsigned sweep2_blocks(const Geo &g, int d, unsigned bs);
 unsigned bnd_points(const Geo &g);           // boundary-normal faces
 unsigned phi_part_threads(const Geo &g, int pm);
 size_t phi_part_lds(const Geo &g, int pm);

@@ -418,6 +418,210 @@ void launch_sweep_T(int d, const PassArgs &a, unsigned blocks, unsigned threads,
   else hipLaunchKernelGGL(k_sweep_T<2>, gr, bl, 0, st, a);
 }
 
+// ------------------------------------------------ two-ended block lines --
+
+// Twisted block factorisation of a non-cyclic block line by two threads: the
+// top thread eliminates rows 0 .. m-1 downwards (C'_s = Ap_s^{-1} U_s,
+// y_s = Ap_s^{-1}(b_s - L_s y_{s-1}), Ap_s = D_s - L_s C'_{s-1}), the bottom
+// thread rows n-1 .. m+1 upwards (E'_s = Bp_s^{-1} L_s,
+// z_s = Bp_s^{-1}(b_s - U_s z_{s+1}), Bp_s = D_s - U_s E'_{s+1}); the top
+// thread then solves the middle row
+//   (D_m - L_m C'_{m-1} - U_m E'_{m+1}) x_m = b_m - L_m y_{m-1} - U_m z_{m+1}
+// and each substitutes back over its half (x_s = y_s - C'_s x_{s+1} above,
+// x_s = z_s - E'_s x_{s-1} below).  Same arithmetic and scratch as one thread
+// per line, twice the threads.  Lane l of the top half and lane l of the
+// bottom half of a workgroup share a line; the middle data pass through LDS.
+template <int D>
+__device__ void twisted_block_line(const Geo &g, const Mat &m, const SrcOne &u, const Fields &rhs,
+                                   const Out &o, double *sc, long nl, long line, bool act, bool top,
+                                   int a, int b, int n, double hs, double *lds, int lane, int *status) {
+#define SC(s, q) sc[((long)(s) * 12 + (q)) * nl + line]
+  const int mid = n / 2;
+  BRow R;
+  double C[9], y[3], Ap[9], Ai[9], t9[9], t3[3];
+  double *my = lds + (long)lane * 15;  // E'_{m+1} (9), z_{m+1} (3), x_m (3)
+  if (act) {
+    if (top) {
+      for (int s = 0; s < mid; s++) {
+        block_row<D>(g, m, u, rhs, a, b, s, n, 0, hs, R);
+        if (s == 0) {
+#pragma unroll
+          for (int q = 0; q < 9; q++) Ap[q] = R.D[q];
+#pragma unroll
+          for (int q = 0; q < 3; q++) t3[q] = R.b[q];
+        } else {
+          mm3(R.L, C, t9);
+#pragma unroll
+          for (int q = 0; q < 9; q++) Ap[q] = R.D[q] - t9[q];
+          double ly[3];
+          mv3(R.L, y, ly);
+#pragma unroll
+          for (int q = 0; q < 3; q++) t3[q] = R.b[q] - ly[q];
+        }
+        inv3(Ap, Ai, status);
+        mm3(Ai, R.U, C);
+        mv3(Ai, t3, y);
+#pragma unroll
+        for (int q = 0; q < 9; q++) SC(s, q) = C[q];
+#pragma unroll
+        for (int q = 0; q < 3; q++) SC(s, 9 + q) = y[q];
+      }
+    } else {
+      for (int s = n - 1; s > mid; s--) {
+        block_row<D>(g, m, u, rhs, a, b, s, n, 0, hs, R);
+        if (s == n - 1) {
+#pragma unroll
+          for (int q = 0; q < 9; q++) Ap[q] = R.D[q];
+#pragma unroll
+          for (int q = 0; q < 3; q++) t3[q] = R.b[q];
+        } else {
+          mm3(R.U, C, t9);
+#pragma unroll
+          for (int q = 0; q < 9; q++) Ap[q] = R.D[q] - t9[q];
+          double uz[3];
+          mv3(R.U, y, uz);
+#pragma unroll
+          for (int q = 0; q < 3; q++) t3[q] = R.b[q] - uz[q];
+        }
+        inv3(Ap, Ai, status);
+        mm3(Ai, R.L, C);  // E'_s
+        mv3(Ai, t3, y);   // z_s
+#pragma unroll
+        for (int q = 0; q < 9; q++) SC(s, q) = C[q];
+#pragma unroll
+        for (int q = 0; q < 3; q++) SC(s, 9 + q) = y[q];
+      }
+#pragma unroll
+      for (int q = 0; q < 9; q++) my[q] = C[q];
+#pragma unroll
+      for (int q = 0; q < 3; q++) my[9 + q] = y[q];
+    }
+  }
+  __syncthreads();
+  if (act && top) {  // middle row
+    block_row<D>(g, m, u, rhs, a, b, mid, n, 0, hs, R);
+    double Ub[9], t9b[9], uz[3], ly[3];
+    mm3(R.U, my, Ub);  // U_m E'_{m+1}
+    mv3(R.U, my + 9, uz);
+    if (mid > 0) {
+      mm3(R.L, C, t9b);
+      mv3(R.L, y, ly);
+    } else {
+#pragma unroll
+      for (int q = 0; q < 9; q++) t9b[q] = 0.0;
+#pragma unroll
+      for (int q = 0; q < 3; q++) ly[q] = 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < 9; q++) Ap[q] = R.D[q] - t9b[q] - Ub[q];
+#pragma unroll
+    for (int q = 0; q < 3; q++) t3[q] = R.b[q] - ly[q] - uz[q];
+    inv3(Ap, Ai, status);
+    double xm[3];
+    mv3(Ai, t3, xm);
+    block_store<D>(g, o, a, b, mid, xm);
+#pragma unroll
+    for (int q = 0; q < 3; q++) my[12 + q] = xm[q];
+  }
+  __syncthreads();
+  if (!act) return;
+  double x[3] = {my[12], my[13], my[14]};
+  if (top) {
+    for (int s = mid - 1; s >= 0; s--) {
+#pragma unroll
+      for (int q = 0; q < 9; q++) C[q] = SC(s, q);
+      double cx[3];
+      mv3(C, x, cx);
+#pragma unroll
+      for (int q = 0; q < 3; q++) x[q] = SC(s, 9 + q) - cx[q];
+      block_store<D>(g, o, a, b, s, x);
+    }
+  } else {
+    for (int s = mid + 1; s < n; s++) {
+#pragma unroll
+      for (int q = 0; q < 9; q++) C[q] = SC(s, q);
+      double ex[3];
+      mv3(C, x, ex);
+#pragma unroll
+      for (int q = 0; q < 3; q++) x[q] = SC(s, 9 + q) - ex[q];
+      block_store<D>(g, o, a, b, s, x);
+    }
+  }
+#undef SC
+}
+
+// r and theta sweeps: workgroups [0, nbw) take the block lines, two threads
+// per line (blockDim/2 lines per workgroup), the rest one scalar line per
+// thread
+__host__ __device__ inline unsigned twisted_block_wgs(const Geo &g, int d, unsigned bs) {
+  const Families F = families(g, d);
+  const unsigned lpw = bs / 2;
+  return (unsigned)((F.nb + lpw - 1) / lpw);
+}
+
+template <int D>
+__device__ __forceinline__ void sweep2_body(const PassArgs &a, unsigned w, double *lds) {
+  const Geo &g = a.g;
+  const Families F = families(g, D);
+  const double hs = a.tau;
+  const unsigned nbw = twisted_block_wgs(g, D, blockDim.x);
+  if (w < nbw) {
+    const unsigned lpw = blockDim.x / 2;
+    const unsigned lane = threadIdx.x % lpw;
+    const bool top = threadIdx.x < lpw;
+    const long line = (long)w * lpw + lane;
+    const bool act = line < F.nb;
+    int p = 0, q = 0;
+    if (act) { p = (int)(line / g.np); q = (int)(line % g.np); }
+    if (act && top && a.o.mode == 0) zero_bnd<D>(g, a.o.x, p, q);
+    twisted_block_line<D>(g, a.m, a.u, a.rhs, a.o, a.scb, F.nb, line, act, top, p, q, F.n, hs, lds,
+                          (int)lane, a.status);
+    return;
+  }
+  const long t2 = (long)(w - nbw) * blockDim.x + threadIdx.x;
+  const long ns = (long)F.na + F.nbb;
+  const int nkf = g.periodic ? g.np : g.np - 1, kf0 = g.periodic ? 0 : 1;
+  if (t2 < F.na) {
+    const int p = 1 + (int)(t2 / g.np), q = (int)(t2 % g.np);
+    solve_scalar_line<D, 0, false>(g, a.m, a.u, a.rhs, a.o, a.scs, ns, t2, p, q, F.n, 0, hs, a.status);
+    return;
+  }
+  const long t3 = t2 - F.na;
+  if (t3 < F.nbb) {
+    const int p = (int)(t3 / nkf), q = kf0 + (int)(t3 % nkf);
+    solve_scalar_line<D, 1, false>(g, a.m, a.u, a.rhs, a.o, a.scs, ns, F.na + t3, p, q, F.n, 0, hs, a.status);
+  }
+}
+
+template <int D, bool B>
+__global__ void __launch_bounds__(256) DSW_OCC(DSW_WAVES_SWEEP) k_sweep2(PassArgs a, Batch bt) {
+  __shared__ double lds[128 * 15];
+  if constexpr (B) {
+    const int mb = batch_member(bt, blockIdx.x);
+    sweep2_body<D>(bt.tab[mb], blockIdx.x - bt.woff[mb], lds);
+  } else {
+    sweep2_body<D>(a, blockIdx.x, lds);
+  }
+}
+
+unsigned sweep2_blocks(const Geo &g, int d, unsigned bs) {
+  const Families F = families(g, d);
+  const long ns = (long)F.na + F.nbb;
+  return twisted_block_wgs(g, d, bs) + (unsigned)((ns + bs - 1) / bs);
+}
+
+void launch_sweep2_pass(int d, const PassArgs &a, const Batch &b, unsigned blocks, unsigned threads,
+                        hipStream_t st) {
+  const dim3 gr(blocks), bl(threads);
+  if (b.tab) {
+    if (d == 0) hipLaunchKernelGGL((k_sweep2<0, true>), gr, bl, 0, st, a, b);
+    else hipLaunchKernelGGL((k_sweep2<1, true>), gr, bl, 0, st, a, b);
+  } else {
+    if (d == 0) hipLaunchKernelGGL((k_sweep2<0, false>), gr, bl, 0, st, a, b);
+    else hipLaunchKernelGGL((k_sweep2<1, false>), gr, bl, 0, st, a, b);
+  }
+}
+
 void sweep_scratch_size(const Geo &g, long *blk, long *sca) {
   long b = 0, s = 0;
   for (int d = 0; d < 3; d++) {
