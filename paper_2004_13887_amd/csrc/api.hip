@@ -336,7 +336,7 @@ static void plan_step(const dsw_grid *G, const Fields &un, const Fields &uk, dou
     // midpoint state of this iteration: U^n itself at the first one, else the
     // one written by the previous iteration's phi sweep
     const Fields ubar = it == 0 ? un : ubuf[(it - 1) % 2];
-    Pass r{PK_RES_IN, 0, base_args(G)};
+    Pass r{G->geo.periodic ? PK_RES_INP : PK_RES_IN, 0, base_args(G)};
     r.a.u = src1(ubar);
     r.a.d = diff(un, it == 0 ? un : uk);
     r.a.tau = tau;
@@ -359,7 +359,8 @@ static void plan_step(const dsw_grid *G, const Fields &un, const Fields &uk, dou
 static unsigned kind_threads(int kind, const Geo &g, const Cfg &c) {
   switch (kind) {
   case PK_RES:
-  case PK_RES_IN: return (unsigned)c.res_bs;
+  case PK_RES_IN:
+  case PK_RES_INP: return (unsigned)c.res_bs;
   case PK_SW0:
   case PK_SW0T: return (unsigned)c.sweep_bs[0];
   case PK_SW1:
@@ -375,7 +376,8 @@ static unsigned kind_blocks(int kind, const Geo &g, unsigned threads) {
   switch (kind) {
   case PK_BND: return cdiv(bnd_points(g), threads);
   case PK_RES: return cdiv((unsigned long)g.npf, threads) * (unsigned)(g.nt + 1) * (unsigned)(g.nr + 1);
-  case PK_RES_IN: return residual_interior_blocks(g, (int)threads);
+  case PK_RES_IN:
+  case PK_RES_INP: return residual_interior_blocks(g, (int)threads);
   case PK_SW0: return cdiv(sweep_lines(g, 0), threads);
   case PK_SW1: return cdiv(sweep_lines(g, 1), threads);
   case PK_SW0T: return sweep2_blocks(g, 0, threads);
@@ -394,7 +396,8 @@ static void launch_kind(int kind, const Cfg &c, const PassArgs &a, const Batch &
   switch (kind) {
   case PK_BND: launch_bnd_pass(a, b, blocks, threads, st); break;
   case PK_RES: launch_residual_pass(a, b, blocks, threads, st); break;
-  case PK_RES_IN: launch_residual_in_pass(a, b, blocks, threads, st); break;
+  case PK_RES_IN: launch_residual_in_pass(false, a, b, blocks, threads, st); break;
+  case PK_RES_INP: launch_residual_in_pass(true, a, b, blocks, threads, st); break;
   case PK_SW0: launch_sweep_pass(0, a, b, blocks, threads, st); break;
   case PK_SW1: launch_sweep_pass(1, a, b, blocks, threads, st); break;
   case PK_SW0T: launch_sweep2_pass(0, a, b, blocks, threads, st); break;
@@ -465,7 +468,7 @@ extern "C" int dsw_split_step(dsw_grid *G, const dsw_fields *Un, dsw_fields *Unp
   for (size_t q = 0; q < plan.size();) {
     size_t e = q + 1;
     while (e < plan.size() && plan[e].tk == plan[q].tk && plan[e].kind != plan[q].kind &&
-           (plan[q].kind == PK_RES_IN))
+           (plan[q].kind == PK_RES_IN || plan[q].kind == PK_RES_INP))
       e++;
     timed(G, plan[q].tk, st, [&] {
       for (size_t r = q; r < e; r++) launch_single(G, plan[r], st);
@@ -674,7 +677,7 @@ extern "C" int dsw_adjoint_step(dsw_grid *G, const dsw_fields *Un, double tau, i
   launch_axpy3(cnt, 1.0, un, 0.0, none, 0.0, none, U, st);
   for (int k = 0; k < K; k++) {
     launch_axpy3(cnt, 0.5, U, 0.5, un, 0.0, none, UB(k), st);
-    Pass r{PK_RES_IN, 0, base_args(G)};
+    Pass r{G->geo.periodic ? PK_RES_INP : PK_RES_IN, 0, base_args(G)};
     r.a.u = src1(UB(k));
     r.a.d = diff(un, k == 0 ? un : U);
     r.a.tau = tau;
@@ -838,9 +841,18 @@ static int build_plan(dsw_ensemble *E, const Cfg &cfg, const dsw_fields *Un, dsw
     for (int m = 0; m < n; m++)
       if (std::find(kinds.begin(), kinds.end(), per[m][q].kind) == kinds.end()) kinds.push_back(per[m][q].kind);
     for (const int kind : kinds) {
+      // one launch per (kind, workgroup width): members whose phi lines need
+      // narrower workgroups do not pay for the widest one
+      std::vector<unsigned> widths;
+      for (int m = 0; m < n; m++) {
+        if (per[m][q].kind != kind) continue;
+        const unsigned w0 = kind_threads(kind, E->mem[m]->geo, cfg);
+        if (std::find(widths.begin(), widths.end(), w0) == widths.end()) widths.push_back(w0);
+      }
+      for (const unsigned width : widths) {
       std::vector<int> who;
       for (int m = 0; m < n; m++)
-        if (per[m][q].kind == kind) who.push_back(m);
+        if (per[m][q].kind == kind && kind_threads(kind, E->mem[m]->geo, cfg) == width) who.push_back(m);
       unsigned th = 0;
       size_t lds = 0;
       for (int m : who) {
@@ -867,6 +879,7 @@ static int build_plan(dsw_ensemble *E, const Cfg &cfg, const dsw_fields *Un, dsw
       gr.tab_off = append(tab.data(), tab.size() * sizeof(PassArgs));
       gr.woff_off = append(woff.data(), woff.size() * sizeof(unsigned));
       plan.groups.push_back(gr);
+      }
     }
   }
   if (hipMalloc(&plan.dev, host.size()) != hipSuccess) {

@@ -52,27 +52,33 @@ __device__ __forceinline__ int clampi(int x, int lo, int hi) { return x < lo ? l
 
 // State sources: a single array set, or the midpoint of two.  INTERIOR: the
 // caller guarantees that every neighbour a stencil reads lies inside the
-// arrays in r and theta, and in phi too unless phi is periodic (then phi
-// indices are wrapped without branches); the other ghost rules and the
-// 64-bit index arithmetic are skipped.
-template <bool I>
+// arrays in r and theta; the ghost rules in phi (wrap when periodic, else the
+// zero-gradient copy for p, T and the no-slip sign for u_r, u_theta) are
+// applied without branches, and indices are 32-bit.
+template <bool I, bool P = false>
 struct SrcOneT {
   const double *a[5];
   static constexpr bool INTERIOR = I;
+  static constexpr bool PERIODIC = P; // interior sources: phi periodic (known at compile time)
   __device__ __forceinline__ double ld(int f, long x) const { return a[f][x]; }
 };
 using SrcOne = SrcOneT<false>;
-using SrcIn = SrcOneT<true>;
+using SrcInN = SrcOneT<true, false>; // interior, phi bounded by walls
+using SrcInP = SrcOneT<true, true>;  // interior, phi periodic
 struct SrcMid {
   const double *n[5], *k[5];
   static constexpr bool INTERIOR = false;
+  static constexpr bool PERIODIC = false;
   __device__ __forceinline__ double ld(int f, long x) const { return 0.5 * (k[f][x] + n[f][x]); }
 };
 
 // p or T at a (possibly ghost) centre
 template <class S>
 __device__ __forceinline__ double gC(const Geo &g, const S &s, int fid, int i, int j, int k) {
-  if constexpr (S::INTERIOR) return s.ld(fid, (i * g.nt + j) * g.np + wrapk(g, k));
+  if constexpr (S::INTERIOR) {
+    const int kk = S::PERIODIC ? wrapk(g, k) : clampi(k, 0, g.np - 1);
+    return s.ld(fid, (i * g.nt + j) * g.np + kk);
+  }
   i = clampi(i, 0, g.nr - 1);
   j = clampi(j, 0, g.nt - 1);
   k = g.periodic ? wrapk(g, k) : clampi(k, 0, g.np - 1);
@@ -81,7 +87,12 @@ __device__ __forceinline__ double gC(const Geo &g, const S &s, int fid, int i, i
 // u_r at r-face f (0..nr), ghosts across theta and phi boundaries
 template <class S>
 __device__ __forceinline__ double gR(const Geo &g, const S &s, int f, int j, int k) {
-  if constexpr (S::INTERIOR) return s.ld(F_UR, (f * g.nt + j) * g.np + wrapk(g, k));
+  if constexpr (S::INTERIOR) {
+    if constexpr (S::PERIODIC) return s.ld(F_UR, (f * g.nt + j) * g.np + wrapk(g, k));
+    const int kk = clampi(k, 0, g.np - 1);
+    const double v = s.ld(F_UR, (f * g.nt + j) * g.np + kk);
+    return kk == k ? v : -v;
+  }
   double sg = 1.0;
   if (k < 0 || k >= g.np) {
     if (g.periodic) k = wrapk(g, k);
@@ -94,7 +105,12 @@ __device__ __forceinline__ double gR(const Geo &g, const S &s, int f, int j, int
 // u_theta at theta-face f (0..nt), ghosts across r and phi boundaries
 template <class S>
 __device__ __forceinline__ double gT(const Geo &g, const S &s, int i, int f, int k) {
-  if constexpr (S::INTERIOR) return s.ld(F_UT, (i * (g.nt + 1) + f) * g.np + wrapk(g, k));
+  if constexpr (S::INTERIOR) {
+    if constexpr (S::PERIODIC) return s.ld(F_UT, (i * (g.nt + 1) + f) * g.np + wrapk(g, k));
+    const int kk = clampi(k, 0, g.np - 1);
+    const double v = s.ld(F_UT, (i * (g.nt + 1) + f) * g.np + kk);
+    return kk == k ? v : -v;
+  }
   double sg = 1.0;
   if (k < 0 || k >= g.np) {
     if (g.periodic) k = wrapk(g, k);
@@ -107,7 +123,7 @@ __device__ __forceinline__ double gT(const Geo &g, const S &s, int i, int f, int
 // u_phi at phi-face f, ghosts across r and theta boundaries (poles included)
 template <class S>
 __device__ __forceinline__ double gF(const Geo &g, const S &s, int i, int j, int f) {
-  if constexpr (S::INTERIOR) return s.ld(F_UF, (i * g.nt + j) * g.npf + (g.periodic ? wrapk(g, f) : f));
+  if constexpr (S::INTERIOR) return s.ld(F_UF, (i * g.nt + j) * g.npf + (S::PERIODIC ? wrapk(g, f) : f));
   double sg = 1.0;
   if (g.periodic) f = wrapk(g, f);
   if (j < 0) { sg = -sg; j = 0; }

@@ -86,7 +86,7 @@ struct Cfg {
 };
 
 enum PassKind { PK_BND = 0, PK_RES = 1, PK_SW0 = 2, PK_SW1 = 3, PK_SW2_LINE = 4, PK_SW2_PART = 5,
-                PK_RES_IN = 6, PK_SW0T = 7, PK_SW1T = 8 };
+                PK_RES_IN = 6, PK_SW0T = 7, PK_SW1T = 8, PK_RES_INP = 9 };
 
 // r and theta sweeps take two threads per block line (twisted factorisation)
 // when one thread per line would give the GPU fewer than two waves of block
@@ -97,8 +97,8 @@ constexpr long TWIST_LINES = 131072;
 // over a batch (blocks = sum over the members, threads and lds = maxima)
 void launch_residual_pass(const PassArgs &a, const Batch &b, unsigned blocks, unsigned threads,
                           hipStream_t st);
-void launch_residual_in_pass(const PassArgs &a, const Batch &b, unsigned blocks, unsigned threads,
-                             hipStream_t st);
+void launch_residual_in_pass(bool periodic, const PassArgs &a, const Batch &b, unsigned blocks,
+                             unsigned threads, hipStream_t st);
 unsigned residual_interior_blocks(const Geo &g, int bs); // workgroups of the interior launch
 void launch_sweep_pass(int d, const PassArgs &a, const Batch &b, unsigned blocks, unsigned threads,
                        hipStream_t st);

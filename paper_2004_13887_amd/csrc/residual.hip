@@ -176,23 +176,17 @@ __global__ void __launch_bounds__(256) k_residual_mid(Geo g, Mat m, SrcMid s, Di
 // reads its grid's arguments from the batch table; else one grid by value.
 // The split-step residual runs as two launches.  The interior launch covers
 // the workgroups whose points and all their stencil neighbours lie inside the
-// arrays in r and theta (1 <= i <= nr-2, 1 <= j <= nt-2) and, on a sector, in
-// phi (a phi block away from both ends); periodic phi indices wrap without
-// branches.  It has no other ghost rules and uses 32-bit indices, which
-// roughly halves its registers.  The general launch covers the whole index
-// space and leaves those workgroups at once.
+// arrays in r and theta (1 <= i <= nr-2, 1 <= j <= nt-2), every phi block;
+// its accessors apply the phi ghost rules without branches and use 32-bit
+// indices, which roughly halves its registers.  The general launch covers
+// the whole index space and leaves those workgroups at once.
 __host__ __device__ inline bool res_interior_ok(const Geo &g) {
   return (long)(g.nr + 1) * (g.nt + 1) * g.npf < 0x7fffffffL;
 }
-// phi blocks of the interior launch: [kb_lo, kb_lo + nk)
-__host__ __device__ inline int res_kb_lo(const Geo &g) { return g.periodic ? 0 : 1; }
-__host__ __device__ inline int res_nk(const Geo &g, int bs) {
-  return g.periodic ? (g.npf + bs - 1) / bs : (g.np - 1 - bs) / bs;
-}
+__host__ __device__ inline int res_nk(const Geo &g, int bs) { return (g.npf + bs - 1) / bs; }
 __host__ __device__ inline unsigned res_interior_blocks(const Geo &g, int bs) {
-  const int nk = res_nk(g, bs);
-  if (!res_interior_ok(g) || g.nr < 3 || g.nt < 3 || nk < 1) return 0;
-  return (unsigned)nk * (unsigned)(g.nt - 2) * (unsigned)(g.nr - 2);
+  if (!res_interior_ok(g) || g.nr < 3 || g.nt < 3) return 0;
+  return (unsigned)res_nk(g, bs) * (unsigned)(g.nt - 2) * (unsigned)(g.nr - 2);
 }
 
 __device__ __forceinline__ void residual_body(const PassArgs &a, unsigned w) {
@@ -201,25 +195,25 @@ __device__ __forceinline__ void residual_body(const PassArgs &a, unsigned w) {
   const unsigned kb = w % nkb, rest = w / nkb;
   const int j = (int)(rest % (g.nt + 1)), i = (int)(rest / (g.nt + 1));
   const int bs = (int)blockDim.x;
-  const int kl = res_kb_lo(g);
   const bool interior = res_interior_blocks(g, bs) > 0 && i >= 1 && i <= g.nr - 2 && j >= 1 &&
-                        j <= g.nt - 2 && (int)kb >= kl && (int)kb < kl + res_nk(g, bs);
+                        j <= g.nt - 2;
   if (interior) return;  // done by the interior launch
   residual_point<SrcOne, false>(g, a.m, a.u, a.d, a.tau, a.R, Fields{}, a.status, i, j,
                                 (int)(kb * blockDim.x + threadIdx.x));
 }
 
+template <class SI>
 __device__ __forceinline__ void residual_body_in(const PassArgs &a, unsigned w) {
   const Geo &g = a.g;
   const int bs = (int)blockDim.x;
   const unsigned nkin = (unsigned)res_nk(g, bs);
-  const unsigned kb = (unsigned)res_kb_lo(g) + w % nkin, rest = w / nkin;
+  const unsigned kb = w % nkin, rest = w / nkin;
   const int j = 1 + (int)(rest % (unsigned)(g.nt - 2)), i = 1 + (int)(rest / (unsigned)(g.nt - 2));
-  SrcIn s;
+  SI s;
 #pragma unroll
   for (int q = 0; q < 5; q++) s.a[q] = a.u.a[q];
-  residual_point<SrcIn, false>(g, a.m, s, a.d, a.tau, a.R, Fields{}, a.status, i, j,
-                               (int)(kb * blockDim.x + threadIdx.x));
+  residual_point<SI, false>(g, a.m, s, a.d, a.tau, a.R, Fields{}, a.status, i, j,
+                            (int)(kb * blockDim.x + threadIdx.x));
 }
 
 template <bool B>
@@ -232,13 +226,16 @@ __global__ void __launch_bounds__(256) DSW_OCC(DSW_WAVES_RES) k_residual(PassArg
   }
 }
 
-template <bool B>
+// P: the grids of the launch are periodic in phi (full sphere)
+template <bool B, bool P>
 __global__ void __launch_bounds__(256) k_residual_in(PassArgs a, Batch bt) {
+  using SI = SrcOneT<true, P>;
   if constexpr (B) {
     const int mb = batch_member(bt, blockIdx.x);
-    residual_body_in(bt.tab[mb], blockIdx.x - bt.woff[mb]);
+    const PassArgs am = bt.tab[mb];  // loaded once, before any store
+    residual_body_in<SI>(am, blockIdx.x - bt.woff[mb]);
   } else {
-    residual_body_in(a, blockIdx.x);
+    residual_body_in<SI>(a, blockIdx.x);
   }
 }
 
@@ -268,10 +265,16 @@ void launch_residual_pass(const PassArgs &a, const Batch &b, unsigned blocks, un
   else hipLaunchKernelGGL(k_residual<false>, dim3(blocks), dim3(threads), 0, st, a, b);
 }
 
-void launch_residual_in_pass(const PassArgs &a, const Batch &b, unsigned blocks, unsigned threads,
-                             hipStream_t st) {
-  if (b.tab) hipLaunchKernelGGL(k_residual_in<true>, dim3(blocks), dim3(threads), 0, st, a, b);
-  else hipLaunchKernelGGL(k_residual_in<false>, dim3(blocks), dim3(threads), 0, st, a, b);
+void launch_residual_in_pass(bool periodic, const PassArgs &a, const Batch &b, unsigned blocks,
+                             unsigned threads, hipStream_t st) {
+  const dim3 gr(blocks), bl(threads);
+  if (periodic) {
+    if (b.tab) hipLaunchKernelGGL((k_residual_in<true, true>), gr, bl, 0, st, a, b);
+    else hipLaunchKernelGGL((k_residual_in<false, true>), gr, bl, 0, st, a, b);
+  } else {
+    if (b.tab) hipLaunchKernelGGL((k_residual_in<true, false>), gr, bl, 0, st, a, b);
+    else hipLaunchKernelGGL((k_residual_in<false, false>), gr, bl, 0, st, a, b);
+  }
 }
 
 } // namespace dsw
