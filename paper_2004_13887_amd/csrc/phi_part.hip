@@ -258,6 +258,7 @@ __device__ void part_block_line(const Geo &g, const Mat &m, const SrcOne &u, con
     for (int z = 0; z < 3; z++) sX[t * 3 + z] = xs[z];
   }
   __syncthreads();
+  double val[PM][3];
   if (act) {
     double xl[3] = {0, 0, 0};
     if (t > 0 || cyc) {
@@ -268,15 +269,28 @@ __device__ void part_block_line(const Geo &g, const Mat &m, const SrcOne &u, con
 #pragma unroll
     for (int q = 0; q < PM - 1; q++) {
       if (q < len - 1) {
-        double v[3], t3[3];
-        mv3(Em[q], xl, v);
+        double t3[3];
+        mv3(Em[q], xl, val[q]);
         mv3(Cm[q], xs, t3);
 #pragma unroll
-        for (int z = 0; z < 3; z++) v[z] += Ym[q][z] + t3[z];
-        block_store<2>(g, o, i, j, a0 + q, v);
+        for (int z = 0; z < 3; z++) val[q][z] += Ym[q][z] + t3[z];
       }
     }
-    block_store<2>(g, o, i, j, a0 + len - 1, xs);
+  }
+  __syncthreads(); // every thread has read the separators: the LDS is free
+  // stage the solution in LDS and store it row-contiguously (whole lines
+  // per store instruction instead of a 4-row stride across lanes)
+  double *sP = lds, *sT_ = lds + N, *sWv = lds + 2 * N;
+  if (act) {
+#pragma unroll
+    for (int q = 0; q < PM - 1; q++)
+      if (q < len - 1) { sP[a0 + q] = val[q][0]; sT_[a0 + q] = val[q][1]; sWv[a0 + q] = val[q][2]; }
+    sP[a0 + len - 1] = xs[0]; sT_[a0 + len - 1] = xs[1]; sWv[a0 + len - 1] = xs[2];
+  }
+  __syncthreads();
+  for (int r = t; r < N; r += blockDim.x) {
+    const double v[3] = {sP[r], sT_[r], sWv[r]};
+    block_store<2>(g, o, i, j, r, v);
   }
   __syncthreads();
 }
@@ -348,18 +362,24 @@ __device__ void part_scalar_line(const Geo &g, const Mat &m, const SrcOne &u, co
   double *sX = lds + 4 * T;
   if (act) sX[t] = xs;
   __syncthreads();
+  double val[PM];
   if (act) {
     double xl = 0.0;
     if (t > 0 || cyc) xl = sX[t > 0 ? t - 1 : T - 1];
 #pragma unroll
-    for (int q = 0; q < PM - 1; q++) {
-      if (q < len - 1) {
-        const double v = Ym[q] + Em[q] * xl + Cm[q] * xs;
-        put(o, ofid, FAM == 0 ? idx_r(g, a, b, a0 + q) : idx_t(g, a, b, a0 + q), v);
-      }
-    }
-    put(o, ofid, FAM == 0 ? idx_r(g, a, b, a0 + len - 1) : idx_t(g, a, b, a0 + len - 1), xs);
+    for (int q = 0; q < PM - 1; q++)
+      if (q < len - 1) val[q] = Ym[q] + Em[q] * xl + Cm[q] * xs;
   }
+  __syncthreads(); // the LDS is free: stage the line, store it contiguously
+  if (act) {
+#pragma unroll
+    for (int q = 0; q < PM - 1; q++)
+      if (q < len - 1) lds[a0 + q] = val[q];
+    lds[a0 + len - 1] = xs;
+  }
+  __syncthreads();
+  for (int r = t; r < N; r += blockDim.x)
+    put(o, ofid, FAM == 0 ? idx_r(g, a, b, r) : idx_t(g, a, b, r), lds[r]);
   __syncthreads();
 }
 
