@@ -121,8 +121,8 @@ def main():
                     help="measure the adjoint step against the forward step instead")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the multi-GPU path is "
-              "not part of this build", file=sys.stderr)
+        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the library runs one "
+              "grid or ensemble per GPU and has no multi-GPU path", file=sys.stderr)
         sys.exit(2)
 
     if args.ensemble:

@@ -19,64 +19,87 @@
 
 namespace dsw {
 
-__device__ __forceinline__ void acc(double *p, double v) { unsafeAtomicAdd(p, v); }
+#ifndef DSW_ADJ_JT
+#define DSW_ADJ_JT 4   // theta rows per workgroup of the column-tiled reverse
+#endif
+#ifndef DSW_ADJ_SEG
+#define DSW_ADJ_SEG 8  // r planes per workgroup of the column-tiled reverse
+#endif
+
+// Scatter targets.  add(g, fid, i, j, k, v) adds v to array fid at its own
+// index triple (cells: centre (i, j, k); r faces: (face, j, k); theta faces:
+// (i, face, k); phi faces: (i, j, face)), ghost-mapped except for the
+// periodic phi wrap: on a periodic grid k may be -1 or np, and add wraps it.
+// GAcc: FP64 atomics straight into the global arrays.
+struct GAcc {
+  Fields A;
+  __device__ __forceinline__ void add(const Geo &g, int fid, int i, int j, int k, double v) const {
+    if (g.periodic) k = wrapk(g, k);
+    double *p;
+    if (fid == F_P) p = A.p + idx_c(g, i, j, k);
+    else if (fid == F_T) p = A.T + idx_c(g, i, j, k);
+    else if (fid == F_UR) p = A.ur + idx_r(g, i, j, k);
+    else if (fid == F_UT) p = A.ut + idx_t(g, i, j, k);
+    else p = A.uf + idx_f(g, i, j, k);
+    unsafeAtomicAdd(p, v);
+  }
+};
 
 // ----------------------------------------------- reverse of the ghost loads --
 
-__device__ __forceinline__ void sC(const Geo &g, const Fields &A, int fid, int i, int j, int k,
-                                   double v) {
+template <class Acc>
+__device__ __forceinline__ void sC(const Geo &g, const Acc &A, int fid, int i, int j, int k, double v) {
   i = clampi(i, 0, g.nr - 1);
   j = clampi(j, 0, g.nt - 1);
-  k = g.periodic ? wrapk(g, k) : clampi(k, 0, g.np - 1);
-  acc((fid == F_P ? A.p : A.T) + idx_c(g, i, j, k), v);
+  if (!g.periodic) k = clampi(k, 0, g.np - 1);
+  A.add(g, fid, i, j, k, v);
 }
-__device__ __forceinline__ void sR(const Geo &g, const Fields &A, int f, int j, int k, double v) {
+template <class Acc>
+__device__ __forceinline__ void sR(const Geo &g, const Acc &A, int f, int j, int k, double v) {
   double sg = 1.0;
-  if (k < 0 || k >= g.np) {
-    if (g.periodic) k = wrapk(g, k);
-    else { sg = -sg; k = k < 0 ? 0 : g.np - 1; }
-  }
+  if (!g.periodic && (k < 0 || k >= g.np)) { sg = -sg; k = k < 0 ? 0 : g.np - 1; }
   if (j < 0) { if (!g.pole_lo) sg = -sg; j = 0; }
   else if (j >= g.nt) { if (!g.pole_hi) sg = -sg; j = g.nt - 1; }
-  acc(A.ur + idx_r(g, f, j, k), sg * v);
+  A.add(g, F_UR, f, j, k, sg * v);
 }
-__device__ __forceinline__ void sT(const Geo &g, const Fields &A, int i, int f, int k, double v) {
+template <class Acc>
+__device__ __forceinline__ void sT(const Geo &g, const Acc &A, int i, int f, int k, double v) {
   double sg = 1.0;
-  if (k < 0 || k >= g.np) {
-    if (g.periodic) k = wrapk(g, k);
-    else { sg = -sg; k = k < 0 ? 0 : g.np - 1; }
-  }
+  if (!g.periodic && (k < 0 || k >= g.np)) { sg = -sg; k = k < 0 ? 0 : g.np - 1; }
   if (i < 0) { sg = -sg; i = 0; }
   else if (i >= g.nr) { sg = -sg; i = g.nr - 1; }
-  acc(A.ut + idx_t(g, i, f, k), sg * v);
+  A.add(g, F_UT, i, f, k, sg * v);
 }
-__device__ __forceinline__ void sF(const Geo &g, const Fields &A, int i, int j, int f, double v) {
+template <class Acc>
+__device__ __forceinline__ void sF(const Geo &g, const Acc &A, int i, int j, int f, double v) {
   double sg = 1.0;
-  if (g.periodic) f = wrapk(g, f);
   if (j < 0) { sg = -sg; j = 0; }
   else if (j >= g.nt) { sg = -sg; j = g.nt - 1; }
   if (i < 0) { sg = -sg; i = 0; }
   else if (i >= g.nr) { sg = -sg; i = g.nr - 1; }
-  acc(A.uf + idx_f(g, i, j, f), sg * v);
+  A.add(g, F_UF, i, j, f, sg * v);
 }
 
 // centre averages (avgR / avgT / avgF of dsw_common.hpp), reversed
-__device__ __forceinline__ void avgR_rev(const Geo &g, const Fields &A, int i, int j, int k, double a) {
+template <class Acc>
+__device__ __forceinline__ void avgR_rev(const Geo &g, const Acc &A, int i, int j, int k, double a) {
   sR(g, A, i, j, k, 0.5 * a);
   sR(g, A, i + 1, j, k, 0.5 * a);
 }
-__device__ __forceinline__ void avgT_rev(const Geo &g, const Fields &A, int i, int j, int k, double a) {
+template <class Acc>
+__device__ __forceinline__ void avgT_rev(const Geo &g, const Acc &A, int i, int j, int k, double a) {
   sT(g, A, i, j, k, 0.5 * a);
   sT(g, A, i, j + 1, k, 0.5 * a);
 }
-__device__ __forceinline__ void avgF_rev(const Geo &g, const Fields &A, int i, int j, int k, double a) {
+template <class Acc>
+__device__ __forceinline__ void avgF_rev(const Geo &g, const Acc &A, int i, int j, int k, double a) {
   sF(g, A, i, j, k, 0.5 * a);
   sF(g, A, i, j, k + 1, 0.5 * a);
 }
 
 // rho = (p + pi_inf) / (R T) at a (ghost-mapped) centre, reversed
-template <class S>
-__device__ __forceinline__ void rho_rev(const Geo &g, const Mat &m, const S &s, const Fields &A, int i,
+template <class S, class Acc>
+__device__ __forceinline__ void rho_rev(const Geo &g, const Mat &m, const S &s, const Acc &A, int i,
                                         int j, int k, double rb) {
   const double P = gC(g, s, F_P, i, j, k) + m.pinf, T = gC(g, s, F_T, i, j, k);
   const double iRT = 1.0 / (m.Rg * T);
@@ -85,7 +108,8 @@ __device__ __forceinline__ void rho_rev(const Geo &g, const Mat &m, const S &s, 
 }
 
 // divc (compact divergence at a centre), reversed
-__device__ __forceinline__ void divc_rev(const Geo &g, const Fields &A, int i, int j, int k, double a) {
+template <class Acc>
+__device__ __forceinline__ void divc_rev(const Geo &g, const Acc &A, int i, int j, int k, double a) {
   const double ir = g.irc[i], irs = ir * g.isc[j];
   const double cr = ir * ir * g.idr * a, ct = irs * g.idt * a, cp = irs * g.idp * a;
   sR(g, A, i + 1, j, k, g.rf[i + 1] * g.rf[i + 1] * cr);
@@ -97,9 +121,9 @@ __device__ __forceinline__ void divc_rev(const Geo &g, const Fields &A, int i, i
 }
 
 // centre() reversed: cb holds the adjoints of the Cent fields, c the values
-template <class S>
+template <class S, class Acc>
 __device__ void centre_rev(const Geo &g, const Mat &m, const S &s, int i, int j, int k, const Cent &c,
-                           const Cent &cb, const Fields &A) {
+                           const Cent &cb, const Acc &A) {
   const double ir = g.irc[i], is = g.isc[j], ct = g.ctc[j], irs = ir * is;
   const double Grr = cb.Grr + cb.tr, Gtt = cb.Gtt + cb.tr, Gff = cb.Gff + cb.tr;
   double ur = cb.ur, ut = cb.ut, uf = cb.uf;
@@ -164,9 +188,9 @@ __device__ void centre_rev(const Geo &g, const Mat &m, const S &s, int i, int j,
 
 // pressure and temperature rows at a centre (F_p_T of residual.hip);
 // wp, wT: adjoints of F_p and F_T
-template <class S>
+template <class S, class Acc>
 __device__ void F_p_T_rev_cb(const Geo &g, const Mat &m, const S &s, int i, int j, int k, const Cent &c,
-                             double wp, double wT, Cent &cb, const Fields &A) {
+                             double wp, double wT, Cent &cb, const Acc &A) {
   const double ir = g.irc[i], is = g.isc[j], ir2 = ir * ir;
   const double hr = 0.5 * g.idr, ht = 0.5 * ir * g.idt, hp = 0.5 * ir * is * g.idp;
   const double pim = gC(g, s, F_P, i - 1, j, k), pip = gC(g, s, F_P, i + 1, j, k);
@@ -222,9 +246,9 @@ __device__ void F_p_T_rev_cb(const Geo &g, const Mat &m, const S &s, int i, int 
   sC(g, A, F_P, i, j, k - 1, -c.uf * hp * wp);
 }
 
-template <class S>
+template <class S, class Acc>
 __device__ void F_p_T_rev(const Geo &g, const Mat &m, const S &s, int i, int j, int k, double wp,
-                          double wT, const Fields &A) {
+                          double wT, const Acc &A) {
   Cent c, cb{};
   centre(g, m, s, i, j, k, c);
   F_p_T_rev_cb(g, m, s, i, j, k, c, wp, wT, cb, A);
@@ -239,9 +263,9 @@ __device__ void F_p_T_rev(const Geo &g, const Mat &m, const S &s, int i, int j, 
 // averages ua, ub.
 
 // radial momentum row at interior r-face (f, j, k) (F_ur of residual.hip)
-template <class S>
+template <class S, class Acc>
 __device__ void F_ur_rev(const Geo &g, const Mat &m, const S &s, int f, int j, int k, double w,
-                         const Fields &A, double rfx = 0.0, double uax = 0.0, double ubx = 0.0) {
+                         const Acc &A, double rfx = 0.0, double uax = 0.0, double ubx = 0.0) {
   const double irF = g.irf[f], is = g.isc[j], irF2 = irF * irF;
   const double Pa = gC(g, s, F_P, f, j, k) + m.pinf, Ta = gC(g, s, F_T, f, j, k);
   const double Pb_ = gC(g, s, F_P, f - 1, j, k) + m.pinf, Tb_ = gC(g, s, F_T, f - 1, j, k);
@@ -332,9 +356,9 @@ __device__ void F_ur_rev(const Geo &g, const Mat &m, const S &s, int f, int j, i
 }
 
 // colatitudinal momentum row at interior theta-face (i, f, k) (F_ut)
-template <class S>
+template <class S, class Acc>
 __device__ void F_ut_rev(const Geo &g, const Mat &m, const S &s, int i, int f, int k, double w,
-                         const Fields &A, double rfx = 0.0, double uax = 0.0, double ubx = 0.0) {
+                         const Acc &A, double rfx = 0.0, double uax = 0.0, double ubx = 0.0) {
   const double ir = g.irc[i], isF = g.isf[f], ctF = g.ctf[f], ir2 = ir * ir;
   const int j0 = f - 1, j1 = f;
   const double P1 = gC(g, s, F_P, i, j1, k) + m.pinf, T1 = gC(g, s, F_T, i, j1, k);
@@ -426,9 +450,9 @@ __device__ void F_ut_rev(const Geo &g, const Mat &m, const S &s, int i, int f, i
 }
 
 // azimuthal momentum row at phi-face (i, j, f) (F_uf)
-template <class S>
+template <class S, class Acc>
 __device__ void F_uf_rev(const Geo &g, const Mat &m, const S &s, int i, int j, int f, double w,
-                         const Fields &A, double rfx = 0.0, double uax = 0.0, double ubx = 0.0) {
+                         const Acc &A, double rfx = 0.0, double uax = 0.0, double ubx = 0.0) {
   const double ir = g.irc[i], is = g.isc[j], ct = g.ctc[j], ir2 = ir * ir;
   const int k0 = g.periodic ? wrapk(g, f - 1) : f - 1, k1 = g.periodic ? wrapk(g, f) : f;
   const double P1 = gC(g, s, F_P, i, j, k1) + m.pinf, T1 = gC(g, s, F_T, i, j, k1);
@@ -504,18 +528,19 @@ __device__ void F_uf_rev(const Geo &g, const Mat &m, const S &s, int i, int j, i
   sF(g, A, i, j - 1, f, ymb);
   sF(g, A, i, j, f + 1, zpb + aFfp);
   sF(g, A, i, j, f - 1, zmb + aFfm);
-  sR(g, A, i, j, k0, aR00);
-  sR(g, A, i, j, k1, aR01);
-  sR(g, A, i + 1, j, k0, aR10);
-  sR(g, A, i + 1, j, k1, aR11);
-  sT(g, A, i, j, k0, aT00);
-  sT(g, A, i, j, k1, aT01);
-  sT(g, A, i, j + 1, k0, aT10);
-  sT(g, A, i, j + 1, k1, aT11);
-  sC(g, A, F_P, i, j, k1, aP1);
-  sC(g, A, F_P, i, j, k0, aP0);
-  sC(g, A, F_T, i, j, k1, aT1);
-  sC(g, A, F_T, i, j, k0, aT0);
+  // scatter with the unwrapped cell indices f - 1, f
+  sR(g, A, i, j, f - 1, aR00);
+  sR(g, A, i, j, f, aR01);
+  sR(g, A, i + 1, j, f - 1, aR10);
+  sR(g, A, i + 1, j, f, aR11);
+  sT(g, A, i, j, f - 1, aT00);
+  sT(g, A, i, j, f, aT01);
+  sT(g, A, i, j + 1, f - 1, aT10);
+  sT(g, A, i, j + 1, f, aT11);
+  sC(g, A, F_P, i, j, f, aP1);
+  sC(g, A, F_P, i, j, f - 1, aP0);
+  sC(g, A, F_T, i, j, f, aT1);
+  sC(g, A, F_T, i, j, f - 1, aT0);
 }
 
 // acc += (d(-tau F_h(Ubar))/dUbar)^T mu over every unknown row (the rows of the
@@ -528,16 +553,17 @@ __global__ void __launch_bounds__(256) k_residual_vjp(Geo g, Mat m, SrcOne u, do
   const int k = blockIdx.x * blockDim.x + threadIdx.x, j = blockIdx.y, i = blockIdx.z;
   if (k >= g.npf) return;
   const bool kc = k < g.np;
+  const GAcc ga{A};
   if (PART == 0 && i < g.nr && j < g.nt && kc) {
     const long x = idx_c(g, i, j, k);
-    F_p_T_rev(g, m, u, i, j, k, -tau * mu.p[x], -tau * mu.T[x], A);
+    F_p_T_rev(g, m, u, i, j, k, -tau * mu.p[x], -tau * mu.T[x], ga);
   }
   if (PART == 1 && j < g.nt && kc && i >= 1 && i < g.nr)
-    F_ur_rev(g, m, u, i, j, k, -tau * mu.ur[idx_r(g, i, j, k)], A);
+    F_ur_rev(g, m, u, i, j, k, -tau * mu.ur[idx_r(g, i, j, k)], ga);
   if (PART == 2 && i < g.nr && kc && j >= 1 && j < g.nt)
-    F_ut_rev(g, m, u, i, j, k, -tau * mu.ut[idx_t(g, i, j, k)], A);
+    F_ut_rev(g, m, u, i, j, k, -tau * mu.ut[idx_t(g, i, j, k)], ga);
   if (PART == 3 && i < g.nr && j < g.nt && (g.periodic || (k >= 1 && k < g.np)))
-    F_uf_rev(g, m, u, i, j, k, -tau * mu.uf[idx_f(g, i, j, k)], A);
+    F_uf_rev(g, m, u, i, j, k, -tau * mu.uf[idx_f(g, i, j, k)], ga);
 }
 
 void launch_residual_vjp(const Geo &g, const Mat &m, const Fields &Ub, double tau, const Fields &mu,
@@ -555,10 +581,10 @@ void launch_residual_vjp(const Geo &g, const Mat &m, const Fields &Ub, double ta
 
 // Reverse of block_row<D> (rows.hpp) for the coefficient entries: EL, ED, EU
 // are the adjoints of the final (scaled) L, D, U blocks of row s.
-template <int D>
+template <int D, class Acc>
 __device__ void block_row_rev_cb(const Geo &g, const Mat &m, const SrcOne &u, int a, int b, int s, int n,
                                  int cyc, double hs, const double *EL, const double *ED, const double *EU,
-                                 const Cent &c, Cent &cb, const Fields &A) {
+                                 const Cent &c, Cent &cb, const Acc &A) {
   int i, j, k;
   if (D == 0) { i = s; j = a; k = b; }
   else if (D == 1) { i = a; j = s; k = b; }
@@ -648,7 +674,7 @@ __device__ void block_row_rev_cb(const Geo &g, const Mat &m, const SrcOne &u, in
   const double U8 = (!cyc && s == n - 2) ? 0.0 : U[8];
   double G, hc, ap_, a0_, am_;
   int i1 = i, j1 = j, k1 = k;
-  double *up;
+  int wf, wi = i, wj = j, wk = k; // the row's face unknown w
   if (D == 0) {
     const int f = i + 1;
     const double irF2 = g.irf[f] * g.irf[f], d2 = g.idr * g.idr, rF2 = g.rf[f] * g.rf[f];
@@ -660,7 +686,7 @@ __device__ void block_row_rev_cb(const Geo &g, const Mat &m, const SrcOne &u, in
     a0_ = (rb2 + ra2) * irF2 * d2 + rF2 * (irb2 + ira2) * d2 / 3.0;
     am_ = -ra2 * irF2 * d2 - g.rf[i] * g.rf[i] * ira2 * d2 / 3.0;
     i1 = i + 1;
-    up = A.ur + idx_r(g, f, j, k);
+    wf = F_UR; wi = f;
   } else if (D == 1) {
     const int f = j + 1;
     const double sF_ = g.sf[f], isF = g.isf[f], r2d2 = ir2 * g.idt * g.idt;
@@ -671,9 +697,8 @@ __device__ void block_row_rev_cb(const Geo &g, const Mat &m, const SrcOne &u, in
     a0_ = (sb + sa) * r2d2 * isF + sF_ * (isb + isa) * r2d2 / 3.0;
     am_ = -sa * r2d2 * isF - g.sf[j] * r2d2 * isa / 3.0;
     j1 = j + 1;
-    up = A.ut + idx_t(g, i, f, k);
+    wf = F_UT; wj = f;
   } else {
-    const int f = g.periodic ? wrapk(g, k + 1) : k + 1;
     const double q2 = ir2 * is * is * g.idp * g.idp;
     G = ir * is * g.idp;
     hc = 0.5 * ir * is * g.idp;
@@ -681,7 +706,7 @@ __device__ void block_row_rev_cb(const Geo &g, const Mat &m, const SrcOne &u, in
     a0_ = 8.0 * q2 / 3.0;
     am_ = -4.0 * q2 / 3.0;
     k1 = k + 1;
-    up = A.uf + idx_f(g, i, j, f);
+    wf = F_UF; wk = k + 1; // unwrapped
   }
   const double irho = 1.0 / (0.5 * (rho_at(g, m, u, i, j, k) + rho_at(g, m, u, i1, j1, k1)));
   double irhob = G * (U[6] - Dg[6]);
@@ -691,13 +716,13 @@ __device__ void block_row_rev_cb(const Geo &g, const Mat &m, const SrcOne &u, in
   const double rhob = -0.5 * irho * irho * irhob;
   rho_rev(g, m, u, A, i, j, k, rhob);
   rho_rev(g, m, u, A, i1, j1, k1, rhob);
-  acc(up, unb);
+  A.add(g, wf, wi, wj, wk, unb);
 }
 
-template <int D>
+template <int D, class Acc>
 __device__ void block_row_rev(const Geo &g, const Mat &m, const SrcOne &u, int a, int b, int s, int n,
                               int cyc, double hs, const double *EL, const double *ED, const double *EU,
-                              const Fields &A) {
+                              const Acc &A) {
   int i, j, k;
   if (D == 0) { i = s; j = a; k = b; }
   else if (D == 1) { i = a; j = s; k = b; }
@@ -716,7 +741,7 @@ __device__ void block_row_rev(const Geo &g, const Mat &m, const SrcOne &u, int a
 template <int D, int FAM>
 __device__ void scalar_row_parts(const Geo &g, const Mat &m, const SrcOne &u, int a, int b, int s, int n,
                                  int cyc, double hs, double ea, double eb, double ec, double &rfb,
-                                 double &uab, int *cells, long *ix, double *&base, const Fields &A) {
+                                 double &uab, int *cells, long *ix, int &bfid) {
   double h, qa, qb, qc, sglo = -1.0, sghi = -1.0;
   int ci0, cj0, ck0, ci1, cj1, ck1; // the two cells of the face density
   if (D == 0) {
@@ -724,7 +749,7 @@ __device__ void scalar_row_parts(const Geo &g, const Mat &m, const SrcOne &u, in
     const double ir = g.irc[i], r2d2 = ir * ir * g.idr * g.idr;
     const double fp = g.rf[i + 1] * g.rf[i + 1], fm = g.rf[i] * g.rf[i];
     h = 0.5 * g.idr; qa = fm * r2d2; qb = (fp + fm) * r2d2; qc = fp * r2d2;
-    base = A.ur;
+    bfid = F_UR;
     if (FAM == 0) {
       const int jf = a, k = b;
       ix[0] = idx_r(g, i, jf - 1, k); ix[1] = idx_r(g, i, jf, k);
@@ -741,7 +766,7 @@ __device__ void scalar_row_parts(const Geo &g, const Mat &m, const SrcOne &u, in
     const int j = s;
     const double is = g.isc[j];
     double irr;
-    base = A.ut;
+    bfid = F_UT;
     if (FAM == 0) {
       const int fr = a, k = b;
       irr = g.irf[fr];
@@ -764,7 +789,7 @@ __device__ void scalar_row_parts(const Geo &g, const Mat &m, const SrcOne &u, in
     const int k = s;
     const int kp = g.periodic ? wrapk(g, k + 1) : k + 1;
     double irr, iss;
-    base = A.uf;
+    bfid = F_UF;
     if (FAM == 0) {
       const int fr = a, j = b;
       irr = g.irf[fr]; iss = g.isc[j];
@@ -794,15 +819,16 @@ __device__ void scalar_row_parts(const Geo &g, const Mat &m, const SrcOne &u, in
 
 template <int D, int FAM>
 __device__ void scalar_row_rev(const Geo &g, const Mat &m, const SrcOne &u, int a, int b, int s, int n,
-                               int cyc, double hs, double ea, double eb, double ec, const Fields &A) {
-  double rfb, uab, *base;
-  int c[6];
+                               int cyc, double hs, double ea, double eb, double ec, const GAcc &A) {
+  double rfb, uab;
+  int c[6], bfid;
   long ix[4];
-  scalar_row_parts<D, FAM>(g, m, u, a, b, s, n, cyc, hs, ea, eb, ec, rfb, uab, c, ix, base, A);
+  scalar_row_parts<D, FAM>(g, m, u, a, b, s, n, cyc, hs, ea, eb, ec, rfb, uab, c, ix, bfid);
   rho_rev(g, m, u, A, c[0], c[1], c[2], 0.5 * rfb);
   rho_rev(g, m, u, A, c[3], c[4], c[5], 0.5 * rfb);
+  double *base = fsel(A.A, bfid);
 #pragma unroll
-  for (int q = 0; q < 4; q++) acc(base + ix[q], 0.25 * uab);
+  for (int q = 0; q < 4; q++) unsafeAtomicAdd(base + ix[q], 0.25 * uab);
 }
 
 // the three unknowns (p, T, w) of block s of a line, 0 outside a non-cyclic
@@ -844,7 +870,8 @@ __device__ __forceinline__ double load1(const Geo &g, const Fields &X, int a, in
 // outer, rows inner)
 template <int D>
 __global__ void __launch_bounds__(256) k_line_vjp(Geo g, Mat m, SrcOne u, double hs, Fields X,
-                                                  Fields mu, Fields A) {
+                                                  Fields mu, Fields Aout) {
+  const GAcc A{Aout};
   const Families F = families(g, D);
   const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
   const int n = F.n, cyc = F.cyclic;
@@ -922,10 +949,10 @@ struct AdjIn {
   Fields X[3], mu[3];
 };
 
-template <int D>
+template <int D, class Acc>
 __device__ __forceinline__ void cell_block_row(const Geo &g, const Mat &m, const SrcOne &u, double hs,
                                                const AdjIn &in, int i, int j, int k, const Cent &c,
-                                               Cent &cb, const Fields &A) {
+                                               Cent &cb, const Acc &A) {
   int a, b, s, n;
   if (D == 0) { a = j; b = k; s = i; n = g.nr; }
   else if (D == 1) { a = i; b = k; s = j; n = g.nt; }
@@ -953,28 +980,28 @@ __device__ __forceinline__ void cell_block_row(const Geo &g, const Mat &m, const
 template <int D, int FAM>
 __device__ __forceinline__ void face_scalar_row(const Geo &g, const Mat &m, const SrcOne &u, double hs,
                                                 const AdjIn &in, int a, int b, int s, double &rfb,
-                                                double &uab, const Fields &A) {
+                                                double &uab) {
   const int n = D == 0 ? g.nr : (D == 1 ? g.nt : g.np);
   const int cyc = (D == 2 && g.periodic) ? 1 : 0;
   const double mv = load1<D, FAM>(g, in.mu[D], a, b, s, n, cyc);
-  double r, ua, *base;
-  int c[6];
+  double r, ua;
+  int c[6], bfid;
   long ix[4];
   scalar_row_parts<D, FAM>(g, m, u, a, b, s, n, cyc, hs, -mv * load1<D, FAM>(g, in.X[D], a, b, s - 1, n, cyc),
                            -mv * load1<D, FAM>(g, in.X[D], a, b, s, n, cyc),
-                           -mv * load1<D, FAM>(g, in.X[D], a, b, s + 1, n, cyc), r, ua, c, ix, base, A);
+                           -mv * load1<D, FAM>(g, in.X[D], a, b, s + 1, n, cyc), r, ua, c, ix, bfid);
   rfb += r;
   uab += ua;
 }
 
-template <int PART>
-__global__ void __launch_bounds__(256) k_adj_local(Geo g, Mat m, SrcOne u, double tau, AdjIn in,
-                                                   Fields A) {
-  const int k = blockIdx.x * blockDim.x + threadIdx.x, j = blockIdx.y, i = blockIdx.z;
-  if (k >= g.npf) return;
-  const bool kc = k < g.np;
+// the reverse at one index (i, j, k) of the rows of one kind (PART 0: the
+// cell, 1: r-face i, 2: theta-face j, 3: phi-face k), when that row exists
+template <int PART, class Acc>
+__device__ __forceinline__ void adj_point(const Geo &g, const Mat &m, const SrcOne &u, double tau,
+                                          const AdjIn &in, int i, int j, int k, const Acc &A) {
   const double hs = 0.5 * tau;
   const Fields &mu1 = in.mu[0];
+  const bool kc = k < g.np;
   if (PART == 0 && i < g.nr && j < g.nt && kc) {
     Cent c, cb{};
     centre(g, m, u, i, j, k, c);
@@ -987,20 +1014,145 @@ __global__ void __launch_bounds__(256) k_adj_local(Geo g, Mat m, SrcOne u, doubl
   }
   double rfb = 0.0, uab = 0.0, ubb = 0.0;
   if (PART == 1 && j < g.nt && kc && i >= 1 && i < g.nr) {
-    face_scalar_row<1, 0>(g, m, u, hs, in, i, k, j, rfb, uab, A); // u_r along theta: reads ua (u_theta)
-    face_scalar_row<2, 0>(g, m, u, hs, in, i, j, k, rfb, ubb, A); // u_r along phi: reads ub (u_phi)
+    face_scalar_row<1, 0>(g, m, u, hs, in, i, k, j, rfb, uab); // u_r along theta: reads ua (u_theta)
+    face_scalar_row<2, 0>(g, m, u, hs, in, i, j, k, rfb, ubb); // u_r along phi: reads ub (u_phi)
     F_ur_rev(g, m, u, i, j, k, -tau * mu1.ur[idx_r(g, i, j, k)], A, rfb, uab, ubb);
   }
   if (PART == 2 && i < g.nr && kc && j >= 1 && j < g.nt) {
-    face_scalar_row<0, 0>(g, m, u, hs, in, j, k, i, rfb, uab, A); // u_theta along r: ua (u_r)
-    face_scalar_row<2, 1>(g, m, u, hs, in, i, j, k, rfb, ubb, A); // u_theta along phi: ub (u_phi)
+    face_scalar_row<0, 0>(g, m, u, hs, in, j, k, i, rfb, uab); // u_theta along r: ua (u_r)
+    face_scalar_row<2, 1>(g, m, u, hs, in, i, j, k, rfb, ubb); // u_theta along phi: ub (u_phi)
     F_ut_rev(g, m, u, i, j, k, -tau * mu1.ut[idx_t(g, i, j, k)], A, rfb, uab, ubb);
   }
   if (PART == 3 && i < g.nr && j < g.nt && (g.periodic || (k >= 1 && k < g.np))) {
-    face_scalar_row<0, 1>(g, m, u, hs, in, j, k, i, rfb, uab, A); // u_phi along r: ua (u_r)
-    face_scalar_row<1, 1>(g, m, u, hs, in, i, k, j, rfb, ubb, A); // u_phi along theta: ub (u_theta)
+    face_scalar_row<0, 1>(g, m, u, hs, in, j, k, i, rfb, uab); // u_phi along r: ua (u_r)
+    face_scalar_row<1, 1>(g, m, u, hs, in, i, k, j, rfb, ubb); // u_phi along theta: ub (u_theta)
     F_uf_rev(g, m, u, i, j, k, -tau * mu1.uf[idx_f(g, i, j, k)], A, rfb, uab, ubb);
   }
+}
+
+// The cell rows in four pieces, each with its own evaluation of the centre
+// coefficients and its own reverse of them (centre_rev is linear in the
+// adjoints, so the pieces add up to the fused form): P = 0 the p and T rows,
+// P = 1, 2, 3 the block rows of the r, theta, phi lines.  Fewer values live at
+// once than in the fused form.
+template <int P, class Acc>
+__device__ __forceinline__ void adj_cell_piece(const Geo &g, const Mat &m, const SrcOne &u, double tau,
+                                               const AdjIn &in, int i, int j, int k, const Acc &A) {
+  if (!(i < g.nr && j < g.nt && k < g.np)) return;
+  const double hs = 0.5 * tau;
+  Cent c, cb{};
+  centre(g, m, u, i, j, k, c);
+  if constexpr (P == 0) {
+    const long x = idx_c(g, i, j, k);
+    F_p_T_rev_cb(g, m, u, i, j, k, c, -tau * in.mu[0].p[x], -tau * in.mu[0].T[x], cb, A);
+  } else {
+    cell_block_row<P - 1>(g, m, u, hs, in, i, j, k, c, cb, A);
+  }
+  centre_rev(g, m, u, i, j, k, c, cb, A);
+}
+
+// One thread per index, FP64 atomics straight into the global arrays.
+template <int PART>
+__global__ void __launch_bounds__(256) k_adj_local(Geo g, Mat m, SrcOne u, double tau, AdjIn in,
+                                                   Fields A) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x, j = blockIdx.y, i = blockIdx.z;
+  if (k >= g.npf) return;
+  adj_point<PART>(g, m, u, tau, in, i, j, k, GAcc{A});
+}
+
+// Column-tiled variant: a workgroup owns 64 (phi) x JT (theta) indices and
+// walks a segment of r planes, doing all four kinds of rows at each plane.
+// Every scatter target lies within one index of the source in each direction
+// (in its own array's index space), so the adds go into an LDS window of
+// three r planes x (JT + 2) x 66 per field (phi indices unwrapped, so a
+// periodic neighbour across phi = 0 stays in the window); after plane i is
+// done, plane i - 1 can receive nothing more from this workgroup and is added
+// to the global arrays (one atomic per non-zero window entry) and cleared for
+// plane i + 2.  Global atomics drop from ~100 per cell to ~10.
+constexpr int ACOL_K = 64;
+constexpr int ACOL_W = ACOL_K + 2;
+
+template <int JT>
+struct TileAcc {
+  Fields A;
+  double *lds;         // [5 fields][3 slots][JT + 2][ACOL_W]
+  int i0, j0, k0;      // current plane, first theta row and phi column of the tile
+  int sl0, sl1, sl2;   // LDS slots of planes i0 - 1, i0, i0 + 1
+  __device__ __forceinline__ void add(const Geo &, int fid, int i, int j, int k, double v) const {
+    // in the window by construction; the clamps only keep LDS addresses in
+    // bounds
+    const int di = min(max(i - i0 + 1, 0), 2), jj = min(max(j - j0 + 1, 0), JT + 1);
+    const int kk = min(max(k - k0 + 1, 0), ACOL_W - 1);
+    const int sl = di == 0 ? sl0 : (di == 1 ? sl1 : sl2);
+    __hip_atomic_fetch_add(&lds[((fid * 3 + sl) * (JT + 2) + jj) * ACOL_W + kk], v, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_WORKGROUP);
+  }
+};
+
+// add LDS slot sl (plane p) to the global arrays and clear it
+template <int JT>
+__device__ __forceinline__ void acol_flush(const Geo &g, const Fields &A, double *lds, int sl, int p, int j0,
+                                           int k0, int tid, int nth) {
+  constexpr int PER = (JT + 2) * ACOL_W;
+  for (int e = tid; e < 5 * PER; e += nth) {
+    const int fid = e / PER, r = e - fid * PER, jj = r / ACOL_W, kk = r - jj * ACOL_W;
+    double *q = &lds[(fid * 3 + sl) * PER + r];
+    const double v = *q;
+    *q = 0.0;
+    if (v == 0.0) continue;
+    const int j = j0 - 1 + jj;
+    int k = k0 - 1 + kk;
+    if (g.periodic) k = wrapk(g, k);
+    const int ni = fid == F_UR ? g.nr + 1 : g.nr, nj = fid == F_UT ? g.nt + 1 : g.nt;
+    const int nk = fid == F_UF ? g.npf : g.np;
+    if (p >= 0 && p < ni && j >= 0 && j < nj && k >= 0 && k < nk) GAcc{A}.add(g, fid, p, j, k, v);
+  }
+}
+
+template <int JT>
+__global__ void __launch_bounds__(64 * JT) k_adj_col(Geo g, Mat m, SrcOne u, double tau, AdjIn in,
+                                                     Fields A, int seg) {
+  __shared__ double lds[5 * 3 * (JT + 2) * ACOL_W];
+  const int tid = threadIdx.y * ACOL_K + threadIdx.x, nth = ACOL_K * JT;
+  const int k0 = blockIdx.x * ACOL_K, j0 = blockIdx.y * JT;
+  // one wave per theta row (blockDim.x is the wave size): j is wave-uniform
+  const int k = k0 + threadIdx.x, j = __builtin_amdgcn_readfirstlane(j0 + (int)threadIdx.y);
+  const int ib = blockIdx.z * seg, ie = min(g.nr, ib + seg);
+  for (int e = tid; e < 5 * 3 * (JT + 2) * ACOL_W; e += nth) lds[e] = 0.0;
+  __syncthreads();
+  // plane p lives in slot (p - ib + 1) % 3
+  TileAcc<JT> ta{A, lds, 0, j0, k0, 0, 0, 0};
+  const bool on = j < g.nt && k < g.np;
+#pragma nounroll
+  for (int i = ib; i < ie; i++) {
+    ta.i0 = i;
+    ta.sl0 = (i - ib) % 3;
+    ta.sl1 = (i - ib + 1) % 3;
+    ta.sl2 = (i - ib + 2) % 3;
+    if (on) {
+      // the indices pass through an empty asm before each piece, so that
+      // nothing derived from them is hoisted out of the loop or shared
+      // between pieces (either keeps hundreds of registers live)
+      int jv, kv;
+#define DSW_ACOL_PIECE(CALL)                  \
+      jv = j; kv = k;                         \
+      asm volatile("" : "+s"(jv), "+v"(kv));  \
+      CALL;
+      DSW_ACOL_PIECE((adj_cell_piece<0>(g, m, u, tau, in, i, jv, kv, ta)))
+      DSW_ACOL_PIECE((adj_cell_piece<1>(g, m, u, tau, in, i, jv, kv, ta)))
+      DSW_ACOL_PIECE((adj_cell_piece<2>(g, m, u, tau, in, i, jv, kv, ta)))
+      DSW_ACOL_PIECE((adj_cell_piece<3>(g, m, u, tau, in, i, jv, kv, ta)))
+      DSW_ACOL_PIECE((adj_point<1>(g, m, u, tau, in, i, jv, kv, ta)))
+      DSW_ACOL_PIECE((adj_point<2>(g, m, u, tau, in, i, jv, kv, ta)))
+      DSW_ACOL_PIECE((adj_point<3>(g, m, u, tau, in, i, jv, kv, ta)))
+#undef DSW_ACOL_PIECE
+    }
+    __syncthreads();
+    if (i - 1 >= 0) acol_flush<JT>(g, A, lds, (i - ib) % 3, i - 1, j0, k0, tid, nth);
+    __syncthreads();
+  }
+  acol_flush<JT>(g, A, lds, (ie - ib) % 3, ie - 1, j0, k0, tid, nth);
+  if (ie <= g.nr) acol_flush<JT>(g, A, lds, (ie - ib + 1) % 3, ie, j0, k0, tid, nth);
 }
 
 void launch_adj_local(const Geo &g, const Mat &m, const Fields &Ub, double tau, const Fields *X,
@@ -1009,11 +1161,19 @@ void launch_adj_local(const Geo &g, const Mat &m, const Fields &Ub, double tau, 
   u.a[F_P] = Ub.p; u.a[F_UR] = Ub.ur; u.a[F_UT] = Ub.ut; u.a[F_UF] = Ub.uf; u.a[F_T] = Ub.T;
   AdjIn in;
   for (int d = 0; d < 3; d++) { in.X[d] = X[d]; in.mu[d] = mu[d]; }
+#ifndef DSW_ADJ_ATOMIC
+  constexpr int JT = DSW_ADJ_JT;
+  const int seg = DSW_ADJ_SEG;
+  const dim3 grid((g.np + ACOL_K - 1) / ACOL_K, (g.nt + JT - 1) / JT, (g.nr + seg - 1) / seg),
+      block(ACOL_K, JT);
+  hipLaunchKernelGGL(k_adj_col<JT>, grid, block, 0, st, g, m, u, tau, in, acc_, seg);
+#else
   const dim3 grid((g.npf + 63) / 64, g.nt + 1, g.nr + 1), block(64);
   hipLaunchKernelGGL(k_adj_local<0>, grid, block, 0, st, g, m, u, tau, in, acc_);
   hipLaunchKernelGGL(k_adj_local<1>, grid, block, 0, st, g, m, u, tau, in, acc_);
   hipLaunchKernelGGL(k_adj_local<2>, grid, block, 0, st, g, m, u, tau, in, acc_);
   hipLaunchKernelGGL(k_adj_local<3>, grid, block, 0, st, g, m, u, tau, in, acc_);
+#endif
 }
 
 // --------------------------------------------------- elementwise helpers --
