@@ -557,6 +557,9 @@ static void launch_T(const dsw_grid *G, int d, const Pass &p, hipStream_t st) {
   if (d == 2 && p.kind == PK_SW2_PART) {
     launch_phi_T(G->cfg.phi_pm, p.a, (unsigned)G->geo.nr * (unsigned)G->geo.nt,
                  phi_part_threads(G->geo, G->cfg.phi_pm), phi_part_lds(G->geo, G->cfg.phi_pm), st);
+  } else if (d < 2 && families(G->geo, d).nb < TWIST_LINES) {
+    const unsigned bs = (unsigned)G->cfg.sweep_bs[d];
+    launch_sweep2_T(d, p.a, sweep2_blocks(G->geo, d, bs), bs, st);
   } else {
     launch_sweep_T(d, p.a, cdiv(sweep_lines(G->geo, d), 128), 128, st);
   }

@@ -119,6 +119,7 @@ size_t phi_part_lds(const Geo &g, int pm);
 // transposed Jacobians of the residual and of the line operators (both
 // accumulate into acc), and elementwise helpers
 void launch_sweep_T(int d, const PassArgs &a, unsigned blocks, unsigned threads, hipStream_t st);
+void launch_sweep2_T(int d, const PassArgs &a, unsigned blocks, unsigned threads, hipStream_t st);
 void launch_phi_T(int pm, const PassArgs &a, unsigned blocks, unsigned threads, size_t lds,
                   hipStream_t st);
 void launch_residual_vjp(const Geo &g, const Mat &m, const Fields &Ub, double tau, const Fields &mu,

@@ -139,11 +139,14 @@ __device__ void part_block_line(const Geo &g, const Mat &m, const SrcOne &u, con
   const int len = act ? min(PM, N - a0) : 0;
   double Cm[PM - 1][9], Em[PM - 1][9], Ym[PM - 1][3];
   BRow R;
+  TrWalk<2> tw; // transposed rows: each row of the line assembled once
+  if (TR && act) tw.init(g, m, u, rhs, i, j, a0, N, cyc, hs);
   // 1. forward elimination over interior rows with the left spike
 #pragma unroll
   for (int q = 0; q < PM - 1; q++) {
     if (q < len - 1) {
-      get_brow<2, TR>(g, m, u, rhs, i, j, a0 + q, N, cyc, hs, R);
+      if constexpr (TR) tw.next(g, m, u, rhs, i, j, N, cyc, hs, R);
+      else block_row<2>(g, m, u, rhs, i, j, a0 + q, N, cyc, hs, R);
       double Dp[9], rr[3], Lx[9], Ai[9];
       if (q == 0) {
 #pragma unroll
@@ -168,7 +171,10 @@ __device__ void part_block_line(const Geo &g, const Mat &m, const SrcOne &u, con
   }
   // separator row (last row of the chunk)
   BRow S;
-  if (act) get_brow<2, TR>(g, m, u, rhs, i, j, a0 + len - 1, N, cyc, hs, S);
+  if (act) {
+    if constexpr (TR) tw.next(g, m, u, rhs, i, j, N, cyc, hs, S);
+    else block_row<2>(g, m, u, rhs, i, j, a0 + len - 1, N, cyc, hs, S);
+  }
   // backward sweep: (Y, E, C) -> (g, V, W), x_q = g_q + V_q x_left + W_q x_sep
 #pragma unroll
   for (int q = PM - 2; q >= 0; q--) {

@@ -322,6 +322,57 @@ __device__ __forceinline__ void get_brow(const Geo &g, const Mat &m, const SrcOn
   }
 }
 
+// The rows of the transposed line in increasing order s0, s0 + 1, ...,
+// assembling each row of the line once: the walker keeps U_{s-1}, D_s, U_s
+// and b_s, and next() assembles row s + 1 for L_{s+1}.
+template <int D>
+struct TrWalk {
+  double Up[9], Dc[9], Uc[9], bc[3];
+  int s;
+  __device__ __forceinline__ void init(const Geo &g, const Mat &m, const SrcOne &u, const Fields &rhs,
+                                       int a, int b, int s0, int n, int cyc, double hs) {
+    BRow R;
+    if (cyc || s0 > 0) {
+      block_row<D>(g, m, u, rhs, a, b, s0 > 0 ? s0 - 1 : n - 1, n, cyc, hs, R);
+#pragma unroll
+      for (int q = 0; q < 9; q++) Up[q] = R.U[q];
+    } else {
+#pragma unroll
+      for (int q = 0; q < 9; q++) Up[q] = 0.0;
+    }
+    block_row<D>(g, m, u, rhs, a, b, s0, n, cyc, hs, R);
+#pragma unroll
+    for (int q = 0; q < 9; q++) { Dc[q] = R.D[q]; Uc[q] = R.U[q]; }
+#pragma unroll
+    for (int q = 0; q < 3; q++) bc[q] = R.b[q];
+    s = s0;
+  }
+  // transposed row s into T, then advance to s + 1
+  __device__ __forceinline__ void next(const Geo &g, const Mat &m, const SrcOne &u, const Fields &rhs,
+                                       int a, int b, int n, int cyc, double hs, BRow &T) {
+    BRow R;
+    const bool has_p = cyc || s < n - 1;
+    if (has_p) {
+      block_row<D>(g, m, u, rhs, a, b, s < n - 1 ? s + 1 : 0, n, cyc, hs, R);
+    } else {
+#pragma unroll
+      for (int q = 0; q < 9; q++) { R.L[q] = 0.0; R.D[q] = 0.0; R.U[q] = 0.0; }
+#pragma unroll
+      for (int q = 0; q < 3; q++) R.b[q] = 0.0;
+    }
+    tr3(Up, T.L);
+    tr3(Dc, T.D);
+    tr3(R.L, T.U);
+#pragma unroll
+    for (int q = 0; q < 3; q++) T.b[q] = bc[q];
+#pragma unroll
+    for (int q = 0; q < 9; q++) { Up[q] = Uc[q]; Dc[q] = R.D[q]; Uc[q] = R.U[q]; }
+#pragma unroll
+    for (int q = 0; q < 3; q++) bc[q] = R.b[q];
+    s++;
+  }
+};
+
 template <int D, int FAM, bool TR>
 __device__ __forceinline__ void get_srow(const Geo &g, const Mat &m, const SrcOne &u,
                                          const Fields &rhs, int a, int b, int s, int n, int cyc,

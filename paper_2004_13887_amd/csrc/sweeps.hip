@@ -550,6 +550,157 @@ __device__ void twisted_block_line(const Geo &g, const Mat &m, const SrcOne &u, 
 #undef SC
 }
 
+// The same two-ended elimination for the transposed line M^T x = b (adjoint).
+// Row s of M^T is (U_{s-1}^T, D_s^T, L_{s+1}^T) with the right-hand side read
+// at row s's unknowns.  Each thread keeps a window of the rows of M around
+// the row it is at, so every row of M is assembled once per thread (plus one
+// row for the middle), not three times.  Lines have n >= 3, so 1 <= m < n - 1.
+template <int D>
+__device__ void twisted_block_line_T(const Geo &g, const Mat &m, const SrcOne &u, const Fields &rhs,
+                                     const Out &o, double *sc, long nl, long line, bool act, bool top,
+                                     int a, int b, int n, double hs, double *lds, int lane, int *status) {
+#define SC(s, q) sc[((long)(s) * 12 + (q)) * nl + line]
+  const int mid = n / 2;
+  BRow R;
+  double C[9], y[3], Ap[9], Ai[9], t9[9], t3[3], Lt[9], Dt[9], Ut[9];
+  double Wa[9], Wd[9], Wb[9], wb[3]; // window (see each half)
+  double *my = lds + (long)lane * 15;
+#pragma unroll
+  for (int q = 0; q < 9; q++) C[q] = 0.0;
+#pragma unroll
+  for (int q = 0; q < 3; q++) y[q] = 0.0;
+  if (act) {
+    if (top) {
+      // window: Wa = U_{s-1}, Wd = D_s, Wb = U_s, wb = b_s
+      block_row<D>(g, m, u, rhs, a, b, 0, n, 0, hs, R);
+#pragma unroll
+      for (int q = 0; q < 9; q++) { Wa[q] = 0.0; Wd[q] = R.D[q]; Wb[q] = R.U[q]; }
+#pragma unroll
+      for (int q = 0; q < 3; q++) wb[q] = R.b[q];
+      for (int s = 0; s < mid; s++) {
+        block_row<D>(g, m, u, rhs, a, b, s + 1, n, 0, hs, R);
+        tr3(Wa, Lt);
+        tr3(Wd, Dt);
+        tr3(R.L, Ut);
+        if (s == 0) {
+#pragma unroll
+          for (int q = 0; q < 9; q++) Ap[q] = Dt[q];
+#pragma unroll
+          for (int q = 0; q < 3; q++) t3[q] = wb[q];
+        } else {
+          mm3(Lt, C, t9);
+#pragma unroll
+          for (int q = 0; q < 9; q++) Ap[q] = Dt[q] - t9[q];
+          double ly[3];
+          mv3(Lt, y, ly);
+#pragma unroll
+          for (int q = 0; q < 3; q++) t3[q] = wb[q] - ly[q];
+        }
+        inv3(Ap, Ai, status);
+        mm3(Ai, Ut, C);
+        mv3(Ai, t3, y);
+#pragma unroll
+        for (int q = 0; q < 9; q++) SC(s, q) = C[q];
+#pragma unroll
+        for (int q = 0; q < 3; q++) SC(s, 9 + q) = y[q];
+#pragma unroll
+        for (int q = 0; q < 9; q++) { Wa[q] = Wb[q]; Wd[q] = R.D[q]; Wb[q] = R.U[q]; }
+#pragma unroll
+        for (int q = 0; q < 3; q++) wb[q] = R.b[q];
+      }
+    } else {
+      // window: Wa = L_{s+1}, Wd = D_s, Wb = L_s, wb = b_s
+      block_row<D>(g, m, u, rhs, a, b, n - 1, n, 0, hs, R);
+#pragma unroll
+      for (int q = 0; q < 9; q++) { Wa[q] = 0.0; Wd[q] = R.D[q]; Wb[q] = R.L[q]; }
+#pragma unroll
+      for (int q = 0; q < 3; q++) wb[q] = R.b[q];
+      for (int s = n - 1; s > mid; s--) {
+        block_row<D>(g, m, u, rhs, a, b, s - 1, n, 0, hs, R);
+        tr3(R.U, Lt);
+        tr3(Wd, Dt);
+        tr3(Wa, Ut);
+        if (s == n - 1) {
+#pragma unroll
+          for (int q = 0; q < 9; q++) Ap[q] = Dt[q];
+#pragma unroll
+          for (int q = 0; q < 3; q++) t3[q] = wb[q];
+        } else {
+          mm3(Ut, C, t9);
+#pragma unroll
+          for (int q = 0; q < 9; q++) Ap[q] = Dt[q] - t9[q];
+          double uz[3];
+          mv3(Ut, y, uz);
+#pragma unroll
+          for (int q = 0; q < 3; q++) t3[q] = wb[q] - uz[q];
+        }
+        inv3(Ap, Ai, status);
+        mm3(Ai, Lt, C);  // E'_s
+        mv3(Ai, t3, y);  // z_s
+#pragma unroll
+        for (int q = 0; q < 9; q++) SC(s, q) = C[q];
+#pragma unroll
+        for (int q = 0; q < 3; q++) SC(s, 9 + q) = y[q];
+#pragma unroll
+        for (int q = 0; q < 9; q++) { Wa[q] = Wb[q]; Wd[q] = R.D[q]; Wb[q] = R.L[q]; }
+#pragma unroll
+        for (int q = 0; q < 3; q++) wb[q] = R.b[q];
+      }
+#pragma unroll
+      for (int q = 0; q < 9; q++) my[q] = C[q];
+#pragma unroll
+      for (int q = 0; q < 3; q++) my[9 + q] = y[q];
+    }
+  }
+  __syncthreads();
+  if (act && top) {  // middle row: the top window now holds U_{m-1}, D_m, U_m, b_m
+    block_row<D>(g, m, u, rhs, a, b, mid + 1, n, 0, hs, R);
+    tr3(Wa, Lt);
+    tr3(Wd, Dt);
+    tr3(R.L, Ut);
+    double Ub[9], t9b[9], uz[3], ly[3];
+    mm3(Ut, my, Ub);
+    mv3(Ut, my + 9, uz);
+    mm3(Lt, C, t9b);
+    mv3(Lt, y, ly);
+#pragma unroll
+    for (int q = 0; q < 9; q++) Ap[q] = Dt[q] - t9b[q] - Ub[q];
+#pragma unroll
+    for (int q = 0; q < 3; q++) t3[q] = wb[q] - ly[q] - uz[q];
+    inv3(Ap, Ai, status);
+    double xm[3];
+    mv3(Ai, t3, xm);
+    block_store<D>(g, o, a, b, mid, xm);
+#pragma unroll
+    for (int q = 0; q < 3; q++) my[12 + q] = xm[q];
+  }
+  __syncthreads();
+  if (!act) return;
+  double x[3] = {my[12], my[13], my[14]};
+  if (top) {
+    for (int s = mid - 1; s >= 0; s--) {
+#pragma unroll
+      for (int q = 0; q < 9; q++) C[q] = SC(s, q);
+      double cx[3];
+      mv3(C, x, cx);
+#pragma unroll
+      for (int q = 0; q < 3; q++) x[q] = SC(s, 9 + q) - cx[q];
+      block_store<D>(g, o, a, b, s, x);
+    }
+  } else {
+    for (int s = mid + 1; s < n; s++) {
+#pragma unroll
+      for (int q = 0; q < 9; q++) C[q] = SC(s, q);
+      double ex[3];
+      mv3(C, x, ex);
+#pragma unroll
+      for (int q = 0; q < 3; q++) x[q] = SC(s, 9 + q) - ex[q];
+      block_store<D>(g, o, a, b, s, x);
+    }
+  }
+#undef SC
+}
+
 // r and theta sweeps: workgroups [0, nbw) take the block lines, two threads
 // per line (blockDim/2 lines per workgroup), the rest one scalar line per
 // thread
@@ -559,7 +710,7 @@ __host__ __device__ inline unsigned twisted_block_wgs(const Geo &g, int d, unsig
   return (unsigned)((F.nb + lpw - 1) / lpw);
 }
 
-template <int D>
+template <int D, bool TR = false>
 __device__ __forceinline__ void sweep2_body(const PassArgs &a, unsigned w, double *lds) {
   const Geo &g = a.g;
   const Families F = families(g, D);
@@ -574,8 +725,12 @@ __device__ __forceinline__ void sweep2_body(const PassArgs &a, unsigned w, doubl
     int p = 0, q = 0;
     if (act) { p = (int)(line / g.np); q = (int)(line % g.np); }
     if (act && top && a.o.mode == 0) zero_bnd<D>(g, a.o.x, p, q);
-    twisted_block_line<D>(g, a.m, a.u, a.rhs, a.o, a.scb, F.nb, line, act, top, p, q, F.n, hs, lds,
-                          (int)lane, a.status);
+    if constexpr (TR)
+      twisted_block_line_T<D>(g, a.m, a.u, a.rhs, a.o, a.scb, F.nb, line, act, top, p, q, F.n, hs, lds,
+                              (int)lane, a.status);
+    else
+      twisted_block_line<D>(g, a.m, a.u, a.rhs, a.o, a.scb, F.nb, line, act, top, p, q, F.n, hs, lds,
+                            (int)lane, a.status);
     return;
   }
   const long t2 = (long)(w - nbw) * blockDim.x + threadIdx.x;
@@ -583,13 +738,13 @@ __device__ __forceinline__ void sweep2_body(const PassArgs &a, unsigned w, doubl
   const int nkf = g.periodic ? g.np : g.np - 1, kf0 = g.periodic ? 0 : 1;
   if (t2 < F.na) {
     const int p = 1 + (int)(t2 / g.np), q = (int)(t2 % g.np);
-    solve_scalar_line<D, 0, false>(g, a.m, a.u, a.rhs, a.o, a.scs, ns, t2, p, q, F.n, 0, hs, a.status);
+    solve_scalar_line<D, 0, TR>(g, a.m, a.u, a.rhs, a.o, a.scs, ns, t2, p, q, F.n, 0, hs, a.status);
     return;
   }
   const long t3 = t2 - F.na;
   if (t3 < F.nbb) {
     const int p = (int)(t3 / nkf), q = kf0 + (int)(t3 % nkf);
-    solve_scalar_line<D, 1, false>(g, a.m, a.u, a.rhs, a.o, a.scs, ns, F.na + t3, p, q, F.n, 0, hs, a.status);
+    solve_scalar_line<D, 1, TR>(g, a.m, a.u, a.rhs, a.o, a.scs, ns, F.na + t3, p, q, F.n, 0, hs, a.status);
   }
 }
 
@@ -602,6 +757,18 @@ __global__ void __launch_bounds__(256) DSW_OCC(DSW_WAVES_SWEEP) k_sweep2(PassArg
   } else {
     sweep2_body<D>(a, blockIdx.x, lds);
   }
+}
+
+// transposed systems (adjoint), one grid
+template <int D>
+__global__ void __launch_bounds__(256) k_sweep2T(PassArgs a) {
+  __shared__ double lds[128 * 15];
+  sweep2_body<D, true>(a, blockIdx.x, lds);
+}
+
+void launch_sweep2_T(int d, const PassArgs &a, unsigned blocks, unsigned threads, hipStream_t st) {
+  if (d == 0) hipLaunchKernelGGL(k_sweep2T<0>, dim3(blocks), dim3(threads), 0, st, a);
+  else hipLaunchKernelGGL(k_sweep2T<1>, dim3(blocks), dim3(threads), 0, st, a);
 }
 
 unsigned sweep2_blocks(const Geo &g, int d, unsigned bs) {
