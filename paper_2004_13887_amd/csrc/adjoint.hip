@@ -1179,7 +1179,7 @@ void launch_adj_local(const Geo &g, const Mat &m, const Fields &Ub, double tau, 
 // --------------------------------------------------- elementwise helpers --
 
 // out = a*x + b*y + c*z over the five arrays (n doubles each, given per
-// field); y or z may be null
+// field); y or z may be null; x is not read when a = 0
 __global__ void __launch_bounds__(256) k_axpy3(long n0, long n1, long n2, long n3, long n4, double a,
                                                Fields x, double b, Fields y, double c, Fields z, Fields out) {
   long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1187,7 +1187,7 @@ __global__ void __launch_bounds__(256) k_axpy3(long n0, long n1, long n2, long n
   int f = 0;
   while (f < 5 && t >= ns[f]) { t -= ns[f]; f++; }
   if (f >= 5) return;
-  double v = a * fsel(x, f)[t];
+  double v = a != 0.0 ? a * fsel(x, f)[t] : 0.0;
   if (y.p) v += b * fsel(y, f)[t];
   if (z.p) v += c * fsel(z, f)[t];
   fsel(out, f)[t] = v;
@@ -1202,9 +1202,13 @@ void launch_axpy3(const long *cnt, double a, const Fields &x, double b, const Fi
 
 // One reverse iteration's bookkeeping (boundary-normal faces of every
 // iterate are copies of those of U^n):
-//   Lnew = (bnd ? 0 : L) - mu1 + ub/2,   lam_n += (bnd ? L : 0) + mu1 + ub/2
+//   Lnew = (bnd ? 0 : L) - mu1 + ub/2,   lam_n += (bnd ? L : 0) + mu1 + ub/2,
+// and ub = 0 for the next iteration's accumulation.  fold (the first
+// iteration, whose U^{n+1,0} is U^n): lam_n += Lnew as well, i.e.
+// lam_n += L + ub, and Lnew is not written.
 __global__ void __launch_bounds__(256) k_adj_mix(Geo g, long n0, long n1, long n2, long n3, long n4,
-                                                 Fields L, Fields mu1, Fields ubb, Fields Lnew, Fields lam) {
+                                                 Fields L, Fields mu1, Fields ubb, Fields Lnew, Fields lam,
+                                                 int fold) {
   long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
   const long ns[5] = {n0, n1, n2, n3, n4};
   int f = 0;
@@ -1214,16 +1218,22 @@ __global__ void __launch_bounds__(256) k_adj_mix(Geo g, long n0, long n1, long n
   if (f == F_UR) { const long fr = t / ((long)g.nt * g.np); bnd = fr == 0 || fr == g.nr; }
   else if (f == F_UT) { const long ft = (t / g.np) % (g.nt + 1); bnd = ft == 0 || ft == g.nt; }
   else if (f == F_UF && !g.periodic) { const long ff = t % g.npf; bnd = ff == 0 || ff == g.np; }
-  const double l = fsel(L, f)[t], m1 = fsel(mu1, f)[t], hb = 0.5 * fsel(ubb, f)[t];
+  const double l = fsel(L, f)[t], ub = fsel(ubb, f)[t];
+  fsel(ubb, f)[t] = 0.0;
+  if (fold) {
+    fsel(lam, f)[t] += l + ub;
+    return;
+  }
+  const double m1 = fsel(mu1, f)[t], hb = 0.5 * ub;
   fsel(Lnew, f)[t] = (bnd ? 0.0 : l) - m1 + hb;
   fsel(lam, f)[t] += (bnd ? l : 0.0) + m1 + hb;
 }
 
 void launch_adj_mix(const Geo &g, const long *cnt, const Fields &L, const Fields &mu1, const Fields &ubb,
-                    const Fields &Lnew, const Fields &lam, hipStream_t st) {
+                    const Fields &Lnew, const Fields &lam, bool fold, hipStream_t st) {
   const long tot = cnt[0] + cnt[1] + cnt[2] + cnt[3] + cnt[4];
   hipLaunchKernelGGL(k_adj_mix, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, g, cnt[0], cnt[1],
-                     cnt[2], cnt[3], cnt[4], L, mu1, ubb, Lnew, lam);
+                     cnt[2], cnt[3], cnt[4], L, mu1, ubb, Lnew, lam, fold ? 1 : 0);
 }
 
 } // namespace dsw

@@ -676,12 +676,28 @@ extern "C" int dsw_adjoint_step(dsw_grid *G, const dsw_fields *Un, double tau, i
   const Fields U = ws[4 * K], La = ws[4 * K + 1], Lb = ws[4 * K + 2];
   const Fields M3 = ws[4 * K + 3], M2 = ws[4 * K + 4], M1 = ws[4 * K + 5], UBB = ws[4 * K + 6];
   // forward recompute from the checkpoint, keeping every iteration's
-  // midpoint and line-solve outputs
-  launch_axpy3(cnt, 1.0, un, 0.0, none, 0.0, none, U, st);
+  // midpoint and line-solve outputs.  The midpoint of the first iteration is
+  // U^n itself; the phi sweep updates U in place and writes the next
+  // midpoint and its own solution X3.  Boundary-normal faces of U and of the
+  // midpoints are those of U^n (the sweeps leave them alone); those of X3 are
+  // never read.
+  auto UBk = [&](int k) { return k == 0 ? un : UB(k); };
+  {
+    std::vector<Fields> dst{U};
+    for (int k = 1; k < K; k++) dst.push_back(UB(k));
+    for (size_t q = 0; q < dst.size(); q += 3) {
+      Pass p{PK_BND, 4, base_args(G)};
+      p.a.src = un;
+      p.a.d0 = dst[q];
+      p.a.d1 = q + 1 < dst.size() ? dst[q + 1] : none;
+      p.a.d2 = q + 2 < dst.size() ? dst[q + 2] : none;
+      launch_single(G, p, st);
+    }
+  }
   for (int k = 0; k < K; k++) {
-    launch_axpy3(cnt, 0.5, U, 0.5, un, 0.0, none, UB(k), st);
+    const Fields ubk = UBk(k);
     Pass r{G->geo.periodic ? PK_RES_INP : PK_RES_IN, 0, base_args(G)};
-    r.a.u = src1(UB(k));
+    r.a.u = src1(ubk);
     r.a.d = diff(un, k == 0 ? un : U);
     r.a.tau = tau;
     r.a.R = G->r;
@@ -689,18 +705,23 @@ extern "C" int dsw_adjoint_step(dsw_grid *G, const dsw_fields *Un, double tau, i
     r.kind = PK_RES;
     launch_single(G, r, st);
     Out o1{}, o2{}, o3{};
-    o1.x = X1(k); o2.x = X2(k); o3.x = X3(k);
-    launch_single(G, sweep_pass(G, 0, UB(k), tau, G->r, o1), st);
-    launch_single(G, sweep_pass(G, 1, UB(k), tau, X1(k), o2), st);
-    launch_single(G, sweep_pass(G, 2, UB(k), tau, X2(k), o3), st);
-    launch_axpy3(cnt, 1.0, U, 1.0, X3(k), 0.0, none, U, st);
+    o1.x = X1(k); o2.x = X2(k);
+    o3.mode = 1;
+    o3.x = U;
+    o3.base = k == 0 ? un : U;
+    o3.un = un;
+    o3.ub = k < K - 1 ? UB(k + 1) : none;
+    o3.raw = X3(k);
+    launch_single(G, sweep_pass(G, 0, ubk, tau, G->r, o1), st);
+    launch_single(G, sweep_pass(G, 1, ubk, tau, X1(k), o2), st);
+    launch_single(G, sweep_pass(G, 2, ubk, tau, X2(k), o3), st);
   }
   // reverse sweep (reverse of every statement above, last iteration first)
   launch_axpy3(cnt, 0.0, un, 0.0, none, 0.0, none, F(lam_n), st); // lam_n = 0
+  launch_axpy3(cnt, 0.0, un, 0.0, none, 0.0, none, UBB, st);      // Ubar cotangent = 0
   Fields L = F(lam_np1), Lnext = La;
   for (int k = K - 1; k >= 0; k--) {
-    const Fields ubk = UB(k);
-    launch_axpy3(cnt, 0.0, un, 0.0, none, 0.0, none, UBB, st); // Ubar cotangent = 0
+    const Fields ubk = UBk(k);
     Out o{};
     o.mode = 0;
     o.x = M3;
@@ -711,12 +732,12 @@ extern "C" int dsw_adjoint_step(dsw_grid *G, const dsw_fields *Un, double tau, i
     launch_T(G, 0, sweep_pass(G, 0, ubk, tau, M2, o), st);
     const Fields xs[3] = {X1(k), X2(k), X3(k)}, mus[3] = {M1, M2, M3};
     launch_adj_local(G->geo, G->m, ubk, tau, xs, mus, UBB, st);
-    launch_adj_mix(G->geo, cnt, L, M1, UBB, Lnext, F(lam_n), st);
+    // also clears UBB; at k = 0 it adds the cotangent of U^{n+1,0} = U^n
+    // to lam_n as well
+    launch_adj_mix(G->geo, cnt, L, M1, UBB, Lnext, F(lam_n), k == 0, st);
     L = Lnext;
     Lnext = (Lnext.p == La.p) ? Lb : La;
   }
-  // U^{n+1,0} = U^n
-  launch_axpy3(cnt, 1.0, F(lam_n), 1.0, L, 0.0, none, F(lam_n), st);
   return check_launch("adjoint step kernels");
 }
 

@@ -31,9 +31,9 @@ struct Fields {
 // Destination of a sweep.  mode 0: x = solution (boundary-normal faces of x
 // are zeroed).  mode 1: x = base + solution at every unknown (x may alias
 // base); when ub.p is set, also ub = (x + un)/2 there (the midpoint state of
-// the next iteration).
+// the next iteration); when raw.p is set, also raw = solution there.
 struct Out {
-  Fields x, base, ub, un;
+  Fields x, base, ub, un, raw;
   int mode;
 };
 
@@ -133,7 +133,7 @@ void launch_adj_local(const Geo &g, const Mat &m, const Fields &Ub, double tau, 
 void launch_axpy3(const long *cnt, double a, const Fields &x, double b, const Fields &y, double c,
                   const Fields &z, const Fields &out, hipStream_t st);
 void launch_adj_mix(const Geo &g, const long *cnt, const Fields &L, const Fields &mu1, const Fields &ubb,
-                    const Fields &Lnew, const Fields &lam, hipStream_t st);
+                    const Fields &Lnew, const Fields &lam, bool fold, hipStream_t st);
 
 // public residual: forms the midpoint on the fly from Un and Uk and writes it
 void launch_residual(const Geo &g, const Mat &m, const Fields &Un, const Fields &Uk, double tau,

@@ -315,10 +315,13 @@ __device__ void part_scalar_line(const Geo &g, const Mat &m, const SrcOne &u, co
   SRow R;
   long xi;
   double *arr;
+  TrWalkS<2, FAM> tw; // transposed rows: each row of the line assembled once
+  if (TR && act) tw.init(g, m, u, rhs, a, b, a0, N, cyc, hs);
 #pragma unroll
   for (int q = 0; q < PM - 1; q++) {
     if (q < len - 1) {
-      get_srow<2, FAM, TR>(g, m, u, rhs, a, b, a0 + q, N, cyc, hs, R, xi, arr);
+      if constexpr (TR) tw.next(g, m, u, rhs, a, b, N, cyc, hs, R);
+      else scalar_row<2, FAM>(g, m, u, rhs, a, b, a0 + q, N, cyc, hs, R, xi, arr);
       double dp = R.b, rr = R.r, lx = R.a;
       if (q > 0) { dp -= R.a * Cm[q - 1]; rr -= R.a * Ym[q - 1]; lx = -R.a * Em[q - 1]; }
       if (!(dp != 0.0)) status[ST_SINGULAR] = 1;
@@ -329,7 +332,10 @@ __device__ void part_scalar_line(const Geo &g, const Mat &m, const SrcOne &u, co
     }
   }
   SRow S{0, 1, 0, 0};
-  if (act) get_srow<2, FAM, TR>(g, m, u, rhs, a, b, a0 + len - 1, N, cyc, hs, S, xi, arr);
+  if (act) {
+    if constexpr (TR) tw.next(g, m, u, rhs, a, b, N, cyc, hs, S);
+    else scalar_row<2, FAM>(g, m, u, rhs, a, b, a0 + len - 1, N, cyc, hs, S, xi, arr);
+  }
 #pragma unroll
   for (int q = PM - 2; q >= 0; q--) {
     if (q == len - 2) { Em[q] = -Em[q]; Cm[q] = -Cm[q]; }
@@ -425,8 +431,8 @@ __global__ void __launch_bounds__(256) DSW_OCC(DSW_WAVES_PHI) k_phi_part(PassArg
   }
 }
 
-// transposed systems (adjoint), one grid: every row of the transposed line
-// is assembled from three rows of the line (see get_brow)
+// transposed systems (adjoint), one grid: each chunk walks the rows of the
+// line once and forms the transposed rows from them (TrWalk, TrWalkS)
 template <int PM>
 __global__ void __launch_bounds__(256) k_phi_part_T(PassArgs a) {
   extern __shared__ double lds[];

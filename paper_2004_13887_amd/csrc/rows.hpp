@@ -395,6 +395,38 @@ __device__ __forceinline__ void get_srow(const Geo &g, const Mat &m, const SrcOn
   R.c = up;
 }
 
+// The scalar counterpart of TrWalk: transposed row s is (c_{s-1}, b_s,
+// a_{s+1}) with the right-hand side r_s.
+template <int D, int FAM>
+struct TrWalkS {
+  double cp, bc, cc, rc;
+  int s;
+  __device__ __forceinline__ void init(const Geo &g, const Mat &m, const SrcOne &u, const Fields &rhs,
+                                       int a, int b, int s0, int n, int cyc, double hs) {
+    SRow Q;
+    long xq;
+    double *aq;
+    cp = 0.0;
+    if (cyc || s0 > 0) {
+      scalar_row<D, FAM>(g, m, u, rhs, a, b, s0 > 0 ? s0 - 1 : n - 1, n, cyc, hs, Q, xq, aq);
+      cp = Q.c;
+    }
+    scalar_row<D, FAM>(g, m, u, rhs, a, b, s0, n, cyc, hs, Q, xq, aq);
+    bc = Q.b; cc = Q.c; rc = Q.r;
+    s = s0;
+  }
+  __device__ __forceinline__ void next(const Geo &g, const Mat &m, const SrcOne &u, const Fields &rhs,
+                                       int a, int b, int n, int cyc, double hs, SRow &T) {
+    SRow Q{0.0, 0.0, 0.0, 0.0};
+    long xq;
+    double *aq;
+    if (cyc || s < n - 1) scalar_row<D, FAM>(g, m, u, rhs, a, b, s < n - 1 ? s + 1 : 0, n, cyc, hs, Q, xq, aq);
+    T.a = cp; T.b = bc; T.c = Q.a; T.r = rc;
+    cp = cc; bc = Q.b; cc = Q.c; rc = Q.r;
+    s++;
+  }
+};
+
 __device__ __forceinline__ double *fsel(const Fields &f, int fid) {
   return fid == F_P ? f.p : fid == F_UR ? f.ur : fid == F_UT ? f.ut : fid == F_UF ? f.uf : f.T;
 }
@@ -409,6 +441,7 @@ __device__ __forceinline__ void put(const Out &o, int fid, long idx, double v) {
   const double nv = fsel(o.base, fid)[idx] + v;
   fsel(o.x, fid)[idx] = nv;
   if (o.ub.p) fsel(o.ub, fid)[idx] = 0.5 * (nv + fsel(o.un, fid)[idx]);
+  if (o.raw.p) fsel(o.raw, fid)[idx] = v;
 }
 
 template <int D>
