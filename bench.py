@@ -319,6 +319,10 @@ def bench_ensemble(args):
     reset()
     cfg = E.ensemble_tune(A, B, taus, K, reps=1, stream=stream)
     log(f"[ensemble] tuned launch shapes {cfg}")
+    # the per-member calls take the same launch shapes, so that both paths
+    # run the same arithmetic (the phi solver's partition depends on them)
+    for g in E.members:
+        g.set_config(*cfg)
 
     def run(step_fn, n0, n):
         for q in range(n0, n0 + n):
