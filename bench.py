@@ -10,6 +10,10 @@ potential-temperature bubble, seeded velocity noise).  A "step" is one call of
 dsw_split_step (K x (residual + three line sweeps)); inputs are resident in
 HBM before the timed region.  Prints one JSON line.
 
+--sweeps measures the line solves alone and the split step's passes on the
+1024 x 512 x 64 sector; --adjoint the adjoint step against the forward step
+on the 256 x 128 x 64 sector.
+
 --ensemble measures the 64-member ensemble of uneven regional grids instead:
 the autotuner picks the launch shapes, then the batched step (one launch per
 pass over all members, replayed from one HIP graph) is timed against the same
@@ -119,6 +123,8 @@ def main():
     ap.add_argument("--members", type=int, default=64)
     ap.add_argument("--adjoint", action="store_true",
                     help="measure the adjoint step against the forward step instead")
+    ap.add_argument("--sweeps", action="store_true",
+                    help="measure the line solves and the split step's passes on the sweeps workload")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the library runs one "
@@ -129,6 +135,8 @@ def main():
         return bench_ensemble(args)
     if args.adjoint:
         return bench_adjoint(args)
+    if args.sweeps:
+        return bench_sweeps(args)
 
     import torch
     from paper_2004_13887_amd import dsw
@@ -286,6 +294,90 @@ def bench_adjoint(args):
                    "K": w.K},
     }
     print(json.dumps(out_line), flush=True)
+
+
+def bench_sweeps(args):
+    """sweeps workload (1024 x 512 x 64 sector, 100 m, Mach 1e-6, K = 3): GB/s
+    of each pass of the split step (HIP events around every launch) and of
+    the three exported line solves alone, dsw_line_solve_{r,theta,phi} on
+    (Ubar = U^n, rhs = the first residual); algorithmic bytes: 3 states per
+    line solve (reads Ubar and rhs, writes x)"""
+    import torch
+    from paper_2004_13887_amd import dsw
+    from paper_2004_13887_amd import inputs as I
+
+    w = I.WORKLOADS["sweeps"]
+    log(f"[sweeps] generating {w.name}: {w.grid.np}x{w.grid.nt}x{w.grid.nr} cells")
+    U0, tau = I.initial_state(w)
+    grid = dsw.Grid.from_spec(w.grid, w.material)
+    if args.config:
+        grid.set_config(*(int(x) for x in args.config.split(",")))
+    A, B = dsw.to_device(U0), grid.empty()
+    counts = [v.numel() for v in A.values()]
+    S = 8 * sum(counts)
+    stream = torch.cuda.current_stream()
+    # split-step passes
+    for n in range(args.warmup):
+        grid.split_step(A if n % 2 == 0 else B, B if n % 2 == 0 else A, tau, w.K, stream)
+    torch.cuda.synchronize()
+    grid.set_timing(True)
+    grid.read_timing(stream)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    for n in range(args.steps):
+        q = args.warmup + n
+        grid.split_step(A if q % 2 == 0 else B, B if q % 2 == 0 else A, tau, w.K, stream)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    per_kernel = grid.read_timing(stream)
+    grid.set_timing(False)
+    step_ms = ev0.elapsed_time(ev1) / args.steps
+    alg = algorithmic_bytes(counts, w.K)
+    passes = {}
+    for k, (ms, n) in per_kernel.items():
+        if n and alg[k]:
+            avg = ms / n * 1e-3
+            per_launch = alg[k] * args.steps / n
+            passes[k] = {"avg_ms": avg * 1e3, "GBps": per_launch / avg / 1e9}
+            log(f"[sweeps] split-step {k:17s} avg {avg * 1e3:7.3f} ms, {per_launch / avg / 1e9:7.1f} GB/s")
+    # the exported line solves alone
+    R, Ub, X = grid.empty(), grid.empty(), grid.empty()
+    grid.residual(A, A, tau, R, Ub, stream)
+    solves = {}
+    for d, name in enumerate(("r", "theta", "phi")):
+        for _ in range(args.warmup):
+            grid.line_solve(d, Ub, tau, R, X, stream)
+        torch.cuda.synchronize()
+        ev0.record(stream)
+        for _ in range(args.steps):
+            grid.line_solve(d, Ub, tau, R, X, stream)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        ms = ev0.elapsed_time(ev1) / args.steps
+        solves[name] = {"avg_ms": ms, "GBps": 3 * S / (ms * 1e-3) / 1e9}
+        log(f"[sweeps] dsw_line_solve_{name:5s} {ms:7.3f} ms, {3 * S / (ms * 1e-3) / 1e9:7.1f} GB/s")
+    grid.get_status()
+    model_bytes = 8 * (55 + 70 * (w.K - 1)) * w.grid.ncells
+    out = {
+        "metric": "GB/s per line solve (FP64, algorithmic bytes)",
+        "value": min(v["GBps"] for v in solves.values()),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": step_ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "sweeps: 1024 (phi) x 512 (theta) x 64 (r) sector, 100 m horizontal, K=3, "
+                               "Mach 1e-6, seeded bubble + noise", "cells": w.grid.ncells, "K": w.K},
+        "line_solves": solves,
+        "split_step_passes": passes,
+        "split_step_model_GBps": model_bytes / (step_ms * 1e-3) / 1e9,
+    }
+    print(json.dumps(out), flush=True)
 
 
 def bench_ensemble(args):

@@ -921,7 +921,7 @@ static void enqueue_plan(const dsw_ensemble::Plan &plan, const Cfg &cfg, hipStre
   std::memset(&dummy, 0, sizeof(dummy));
   for (size_t q = 0; q < plan.groups.size(); q++) {
     const auto &gr = plan.groups[q];
-    const Batch b{(const PassArgs *)(plan.dev + gr.tab_off), (const unsigned *)(plan.dev + gr.woff_off),
+    const Batch b{(CPassArgs *)(plan.dev + gr.tab_off), (const unsigned *)(plan.dev + gr.woff_off),
                   gr.n};
     if (ev) (void)hipEventRecord((*ev)[q].first, st);
     launch_kind(gr.kind, cfg, dummy, b, gr.blocks, gr.threads, gr.lds, st);

@@ -71,11 +71,25 @@ struct PassArgs {
 // One launch over several grids.  Workgroup w belongs to member m with
 // woff[m] <= w < woff[m+1] (woff has n+1 entries, woff[0] = 0); tab[m] is
 // that member's PassArgs.  tab == nullptr: a single grid, passed by value.
+// In device code the table is seen through the constant address space: the
+// kernels never write it, and so its loads stay scalar (a generic pointer
+// would turn every use of a member's arguments into a vector load, reloaded
+// after every store).
+#if defined(__HIP_DEVICE_COMPILE__)
+typedef const __attribute__((address_space(4))) PassArgs CPassArgs;
+#else
+typedef const PassArgs CPassArgs;
+#endif
 struct Batch {
-  const PassArgs *tab;
+  CPassArgs *tab;
   const unsigned *woff;
   int n;
 };
+
+// member m's arguments, as a reference the pass bodies take
+__device__ __forceinline__ const PassArgs &batch_args(const Batch &b, int m) {
+  return (const PassArgs &)b.tab[m];
+}
 
 // Launch shapes (the tunable parameters).
 struct Cfg {
@@ -88,10 +102,10 @@ struct Cfg {
 enum PassKind { PK_BND = 0, PK_RES = 1, PK_SW0 = 2, PK_SW1 = 3, PK_SW2_LINE = 4, PK_SW2_PART = 5,
                 PK_RES_IN = 6, PK_SW0T = 7, PK_SW1T = 8, PK_RES_INP = 9 };
 
-// r and theta sweeps take two threads per block line (twisted factorisation)
-// when one thread per line would give the GPU fewer than two waves of block
-// lines per SIMD
-constexpr long TWIST_LINES = 131072;
+// r and theta sweeps take two threads per line (two-ended elimination) on
+// grids with fewer block lines than this; measured faster than one thread
+// per line on every grid tried (2^12 .. 2^17 block lines of 64 .. 256 rows)
+constexpr long TWIST_LINES = 1L << 24;
 
 // kernel launchers of the passes: by value for one grid (b.tab == nullptr), or
 // over a batch (blocks = sum over the members, threads and lds = maxima)

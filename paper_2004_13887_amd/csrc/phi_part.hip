@@ -425,7 +425,7 @@ __global__ void __launch_bounds__(256) DSW_OCC(DSW_WAVES_PHI) k_phi_part(PassArg
   extern __shared__ double lds[];
   if constexpr (B) {
     const int mb = batch_member(bt, blockIdx.x);
-    phi_body<PM, false>(bt.tab[mb], blockIdx.x - bt.woff[mb], lds);
+    phi_body<PM, false>(batch_args(bt, mb), blockIdx.x - bt.woff[mb], lds);
   } else {
     phi_body<PM, false>(a, blockIdx.x, lds);
   }

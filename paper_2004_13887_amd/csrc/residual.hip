@@ -220,7 +220,7 @@ template <bool B>
 __global__ void __launch_bounds__(256) DSW_OCC(DSW_WAVES_RES) k_residual(PassArgs a, Batch bt) {
   if constexpr (B) {
     const int mb = batch_member(bt, blockIdx.x);
-    residual_body(bt.tab[mb], blockIdx.x - bt.woff[mb]);
+    residual_body(batch_args(bt, mb), blockIdx.x - bt.woff[mb]);
   } else {
     residual_body(a, blockIdx.x);
   }
@@ -232,7 +232,7 @@ __global__ void __launch_bounds__(256) k_residual_in(PassArgs a, Batch bt) {
   using SI = SrcOneT<true, P>;
   if constexpr (B) {
     const int mb = batch_member(bt, blockIdx.x);
-    const PassArgs am = bt.tab[mb];  // loaded once, before any store
+    const PassArgs am = batch_args(bt, mb);  // loaded once, before any store
     residual_body_in<SI>(am, blockIdx.x - bt.woff[mb]);
   } else {
     residual_body_in<SI>(a, blockIdx.x);

@@ -399,7 +399,7 @@ template <int D, bool B>
 __global__ void __launch_bounds__(256) DSW_OCC(DSW_WAVES_SWEEP) k_sweep(PassArgs a, Batch bt) {
   if constexpr (B) {
     const int mb = batch_member(bt, blockIdx.x);
-    sweep_body<D, false>(bt.tab[mb], blockIdx.x - bt.woff[mb]);
+    sweep_body<D, false>(batch_args(bt, mb), blockIdx.x - bt.woff[mb]);
   } else {
     sweep_body<D, false>(a, blockIdx.x);
   }
@@ -701,6 +701,164 @@ __device__ void twisted_block_line_T(const Geo &g, const Mat &m, const SrcOne &u
 #undef SC
 }
 
+// Two-ended elimination of a non-cyclic scalar line by two threads, as for
+// the block lines: the top thread runs the Thomas recurrence down rows
+// 0 .. m-1 (c'_s, y_s), the bottom thread up rows n-1 .. m+1
+// (e'_s = a_s / den_s, z_s = (r_s - c_s z_{s+1}) / den_s,
+// den_s = b_s - c_s e'_{s+1}); the top thread solves the middle row
+//   (b_m - a_m c'_{m-1} - c_m e'_{m+1}) x_m = r_m - a_m y_{m-1} - c_m z_{m+1}
+// and both substitute back over their halves.  LDS per lane: e'_{m+1},
+// z_{m+1}, x_m.
+template <int D, int FAM>
+__device__ void twisted_scalar_line(const Geo &g, const Mat &m, const SrcOne &u, const Fields &rhs,
+                                    const Out &o, double *sc, long nl, long line, bool act, bool top,
+                                    int a, int b, int n, double hs, double *lds, int lane, int *status) {
+#define SC(s, q) sc[((long)(s) * 2 + (q)) * nl + line]
+  int ofid;
+  if (D == 0) ofid = FAM == 0 ? F_UT : F_UF;
+  else ofid = FAM == 0 ? F_UR : F_UF;
+  const int mid = n / 2;
+  double *my = lds + (long)lane * 15;
+  SRow R;
+  long xi;
+  double *arr;
+  double cv = 0.0, yv = 0.0;
+  if (act) {
+    if (top) {
+      for (int s = 0; s < mid; s++) {
+        scalar_row<D, FAM>(g, m, u, rhs, a, b, s, n, 0, hs, R, xi, arr);
+        const double den = R.b - R.a * cv;
+        if (!(den != 0.0)) status[ST_SINGULAR] = 1;
+        const double id = 1.0 / den;
+        yv = (R.r - R.a * yv) * id;
+        cv = R.c * id;
+        SC(s, 0) = cv;
+        SC(s, 1) = yv;
+      }
+    } else {
+      for (int s = n - 1; s > mid; s--) {
+        scalar_row<D, FAM>(g, m, u, rhs, a, b, s, n, 0, hs, R, xi, arr);
+        const double den = R.b - R.c * cv;
+        if (!(den != 0.0)) status[ST_SINGULAR] = 1;
+        const double id = 1.0 / den;
+        yv = (R.r - R.c * yv) * id;
+        cv = R.a * id;
+        SC(s, 0) = cv;
+        SC(s, 1) = yv;
+      }
+      my[0] = cv;
+      my[1] = yv;
+    }
+  }
+  __syncthreads();
+  if (act && top) { // middle row
+    scalar_row<D, FAM>(g, m, u, rhs, a, b, mid, n, 0, hs, R, xi, arr);
+    const double den = R.b - R.a * cv - R.c * my[0];
+    if (!(den != 0.0)) status[ST_SINGULAR] = 1;
+    const double xm = (R.r - R.a * yv - R.c * my[1]) / den;
+    put(o, ofid, xi, xm);
+    my[2] = xm;
+  }
+  __syncthreads();
+  if (!act) return;
+  double x = my[2];
+  if (top) {
+    for (int s = mid - 1; s >= 0; s--) {
+      x = SC(s, 1) - SC(s, 0) * x;
+      put(o, ofid, scalar_index<D, FAM>(g, a, b, s), x);
+    }
+  } else {
+    for (int s = mid + 1; s < n; s++) {
+      x = SC(s, 1) - SC(s, 0) * x;
+      put(o, ofid, scalar_index<D, FAM>(g, a, b, s), x);
+    }
+  }
+#undef SC
+}
+
+// The same for the transposed scalar line: row s of M^T is
+// (c_{s-1}, b_s, a_{s+1}) with the right-hand side r_s.  Each thread keeps a
+// window of the rows of M around its position (top: c_{s-1}, b_s, c_s, r_s;
+// bottom: a_{s+1}, b_s, a_s, r_s), so every row is assembled once.
+template <int D, int FAM>
+__device__ void twisted_scalar_line_T(const Geo &g, const Mat &m, const SrcOne &u, const Fields &rhs,
+                                      const Out &o, double *sc, long nl, long line, bool act, bool top,
+                                      int a, int b, int n, double hs, double *lds, int lane, int *status) {
+#define SC(s, q) sc[((long)(s) * 2 + (q)) * nl + line]
+  int ofid;
+  if (D == 0) ofid = FAM == 0 ? F_UT : F_UF;
+  else ofid = FAM == 0 ? F_UR : F_UF;
+  const int mid = n / 2;
+  double *my = lds + (long)lane * 15;
+  SRow R;
+  long xi;
+  double *arr;
+  double cv = 0.0, yv = 0.0;
+  double w0 = 0.0, wb = 0.0, w1 = 0.0, wr = 0.0; // window
+  if (act) {
+    if (top) {
+      // w0 = c_{s-1}, wb = b_s, w1 = c_s, wr = r_s
+      scalar_row<D, FAM>(g, m, u, rhs, a, b, 0, n, 0, hs, R, xi, arr);
+      wb = R.b; w1 = R.c; wr = R.r;
+      for (int s = 0; s < mid; s++) {
+        scalar_row<D, FAM>(g, m, u, rhs, a, b, s + 1, n, 0, hs, R, xi, arr);
+        const double at = w0, bt = wb, ct = R.a, rt = wr; // transposed row s
+        const double den = bt - at * cv;
+        if (!(den != 0.0)) status[ST_SINGULAR] = 1;
+        const double id = 1.0 / den;
+        yv = (rt - at * yv) * id;
+        cv = ct * id;
+        SC(s, 0) = cv;
+        SC(s, 1) = yv;
+        w0 = w1; wb = R.b; w1 = R.c; wr = R.r;
+      }
+    } else {
+      // w0 = a_{s+1}, wb = b_s, w1 = a_s, wr = r_s
+      scalar_row<D, FAM>(g, m, u, rhs, a, b, n - 1, n, 0, hs, R, xi, arr);
+      wb = R.b; w1 = R.a; wr = R.r;
+      for (int s = n - 1; s > mid; s--) {
+        scalar_row<D, FAM>(g, m, u, rhs, a, b, s - 1, n, 0, hs, R, xi, arr);
+        const double at = R.c, bt = wb, ct = w0, rt = wr; // transposed row s
+        const double den = bt - ct * cv;
+        if (!(den != 0.0)) status[ST_SINGULAR] = 1;
+        const double id = 1.0 / den;
+        yv = (rt - ct * yv) * id;
+        cv = at * id;
+        SC(s, 0) = cv;
+        SC(s, 1) = yv;
+        w0 = w1; wb = R.b; w1 = R.a; wr = R.r;
+      }
+      my[0] = cv;
+      my[1] = yv;
+    }
+  }
+  __syncthreads();
+  if (act && top) { // middle row (c_{m-1}, b_m, a_{m+1}): the top window holds c_{m-1}, b_m, r_m
+    scalar_row<D, FAM>(g, m, u, rhs, a, b, mid + 1, n, 0, hs, R, xi, arr);
+    const double at = w0, bt = wb, ct = R.a, rt = wr;
+    const double den = bt - at * cv - ct * my[0];
+    if (!(den != 0.0)) status[ST_SINGULAR] = 1;
+    const double xm = (rt - at * yv - ct * my[1]) / den;
+    put(o, ofid, scalar_index<D, FAM>(g, a, b, mid), xm);
+    my[2] = xm;
+  }
+  __syncthreads();
+  if (!act) return;
+  double x = my[2];
+  if (top) {
+    for (int s = mid - 1; s >= 0; s--) {
+      x = SC(s, 1) - SC(s, 0) * x;
+      put(o, ofid, scalar_index<D, FAM>(g, a, b, s), x);
+    }
+  } else {
+    for (int s = mid + 1; s < n; s++) {
+      x = SC(s, 1) - SC(s, 0) * x;
+      put(o, ofid, scalar_index<D, FAM>(g, a, b, s), x);
+    }
+  }
+#undef SC
+}
+
 // r and theta sweeps: workgroups [0, nbw) take the block lines, two threads
 // per line (blockDim/2 lines per workgroup), the rest one scalar line per
 // thread
@@ -733,18 +891,37 @@ __device__ __forceinline__ void sweep2_body(const PassArgs &a, unsigned w, doubl
                             (int)lane, a.status);
     return;
   }
-  const long t2 = (long)(w - nbw) * blockDim.x + threadIdx.x;
+  // scalar lines two-ended too: blockDim/2 lines per workgroup, each
+  // workgroup within one family (so its barriers are uniform)
   const long ns = (long)F.na + F.nbb;
   const int nkf = g.periodic ? g.np : g.np - 1, kf0 = g.periodic ? 0 : 1;
-  if (t2 < F.na) {
-    const int p = 1 + (int)(t2 / g.np), q = (int)(t2 % g.np);
-    solve_scalar_line<D, 0, TR>(g, a.m, a.u, a.rhs, a.o, a.scs, ns, t2, p, q, F.n, 0, hs, a.status);
-    return;
-  }
-  const long t3 = t2 - F.na;
-  if (t3 < F.nbb) {
-    const int p = (int)(t3 / nkf), q = kf0 + (int)(t3 % nkf);
-    solve_scalar_line<D, 1, TR>(g, a.m, a.u, a.rhs, a.o, a.scs, ns, F.na + t3, p, q, F.n, 0, hs, a.status);
+  const unsigned lpw = blockDim.x / 2;
+  const unsigned lane = threadIdx.x % lpw;
+  const bool top = threadIdx.x < lpw;
+  const unsigned nwa = (unsigned)((F.na + lpw - 1) / lpw);
+  const unsigned w2 = w - nbw;
+  if (w2 < nwa) {
+    const long line = (long)w2 * lpw + lane;
+    const bool act = line < F.na;
+    int p = 1, q = 0;
+    if (act) { p = 1 + (int)(line / g.np); q = (int)(line % g.np); }
+    if constexpr (TR)
+      twisted_scalar_line_T<D, 0>(g, a.m, a.u, a.rhs, a.o, a.scs, ns, line, act, top, p, q, F.n, hs, lds,
+                                  (int)lane, a.status);
+    else
+      twisted_scalar_line<D, 0>(g, a.m, a.u, a.rhs, a.o, a.scs, ns, line, act, top, p, q, F.n, hs, lds,
+                                (int)lane, a.status);
+  } else {
+    const long l3 = (long)(w2 - nwa) * lpw + lane;
+    const bool act = l3 < F.nbb;
+    int p = 0, q = kf0;
+    if (act) { p = (int)(l3 / nkf); q = kf0 + (int)(l3 % nkf); }
+    if constexpr (TR)
+      twisted_scalar_line_T<D, 1>(g, a.m, a.u, a.rhs, a.o, a.scs, ns, F.na + l3, act, top, p, q, F.n, hs, lds,
+                                  (int)lane, a.status);
+    else
+      twisted_scalar_line<D, 1>(g, a.m, a.u, a.rhs, a.o, a.scs, ns, F.na + l3, act, top, p, q, F.n, hs, lds,
+                                (int)lane, a.status);
   }
 }
 
@@ -753,7 +930,7 @@ __global__ void __launch_bounds__(256) DSW_OCC(DSW_WAVES_SWEEP) k_sweep2(PassArg
   __shared__ double lds[128 * 15];
   if constexpr (B) {
     const int mb = batch_member(bt, blockIdx.x);
-    sweep2_body<D>(bt.tab[mb], blockIdx.x - bt.woff[mb], lds);
+    sweep2_body<D>(batch_args(bt, mb), blockIdx.x - bt.woff[mb], lds);
   } else {
     sweep2_body<D>(a, blockIdx.x, lds);
   }
@@ -771,10 +948,12 @@ void launch_sweep2_T(int d, const PassArgs &a, unsigned blocks, unsigned threads
   else hipLaunchKernelGGL(k_sweep2T<1>, dim3(blocks), dim3(threads), 0, st, a);
 }
 
+// workgroups of a two-ended r or theta sweep: the block lines, then the
+// scalar lines of each family, two threads per line
 unsigned sweep2_blocks(const Geo &g, int d, unsigned bs) {
   const Families F = families(g, d);
-  const long ns = (long)F.na + F.nbb;
-  return twisted_block_wgs(g, d, bs) + (unsigned)((ns + bs - 1) / bs);
+  const long lpw = bs / 2;
+  return twisted_block_wgs(g, d, bs) + (unsigned)((F.na + lpw - 1) / lpw) + (unsigned)((F.nbb + lpw - 1) / lpw);
 }
 
 void launch_sweep2_pass(int d, const PassArgs &a, const Batch &b, unsigned blocks, unsigned threads,
@@ -854,7 +1033,7 @@ template <bool B>
 __global__ void __launch_bounds__(256) k_bnd_copy(PassArgs a, Batch bt) {
   if constexpr (B) {
     const int mb = batch_member(bt, blockIdx.x);
-    bnd_body(bt.tab[mb], blockIdx.x - bt.woff[mb]);
+    bnd_body(batch_args(bt, mb), blockIdx.x - bt.woff[mb]);
   } else {
     bnd_body(a, blockIdx.x);
   }
