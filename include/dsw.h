@@ -191,7 +191,7 @@ int dsw_residual_vjp(dsw_grid *grid, const dsw_fields *Ubar, double tau, const d
  *                         cannot take (more than 256 chunks, or a cyclic line
  *                         whose chunk count is not a power of two) fall back
  *                         to one thread per line.
- * Default {64, 128, 128, 4}.  dsw_set_config returns DSW_EINVAL for other
+ * Default {64, 256, 256, 4}.  dsw_set_config returns DSW_EINVAL for other
  * values. */
 typedef struct {
   int32_t residual_block, sweep_block_r, sweep_block_theta, phi_rows_per_thread;

@@ -21,7 +21,7 @@ struct dsw_grid {
   dsw_material mat;
   Geo geo;
   Mat m;
-  Cfg cfg{64, {128, 128}, 4}; // launch shapes
+  Cfg cfg{64, {256, 256}, 4}; // launch shapes
   double *tables = nullptr; // rc | rf | sc | cc | sf | cf
   Fields ub{}, ub2{}, r{}, x1{}, x2{}; // ub, ub2: midpoint states of consecutive iterations
   double *fields_mem = nullptr;
@@ -745,7 +745,7 @@ extern "C" int dsw_adjoint_step(dsw_grid *G, const dsw_fields *Un, double tau, i
 
 struct dsw_ensemble {
   std::vector<dsw_grid *> mem;
-  Cfg cfg{64, {128, 128}, 4};
+  Cfg cfg{64, {256, 256}, 4};
   hipStream_t cap = nullptr; // capture stream
   // one launch of a batched plan
   struct Group {

@@ -228,7 +228,7 @@ class Grid:
         _check(lib().dsw_get_status(self._h, _stream(stream)))
         return DSW_OK
 
-    def set_config(self, residual_block=64, sweep_block_r=128, sweep_block_theta=128,
+    def set_config(self, residual_block=64, sweep_block_r=256, sweep_block_theta=256,
                    phi_rows_per_thread=4):
         c = Config(residual_block, sweep_block_r, sweep_block_theta, phi_rows_per_thread)
         _check(lib().dsw_set_config(self._h, C.byref(c)))
@@ -289,7 +289,7 @@ class Ensemble:
                                        int(reps), _stream(stream), C.byref(c)))
         return c.astuple()
 
-    def set_config(self, residual_block=64, sweep_block_r=128, sweep_block_theta=128,
+    def set_config(self, residual_block=64, sweep_block_r=256, sweep_block_theta=256,
                    phi_rows_per_thread=4):
         c = Config(residual_block, sweep_block_r, sweep_block_theta, phi_rows_per_thread)
         _check(lib().dsw_ensemble_set_config(self._h, C.byref(c)))

@@ -171,7 +171,7 @@ def test_bad_config_rejected(dsw):
         g.set_config(96, 128, 128, 4)
     with pytest.raises(dsw.DswError):
         g.set_config(64, 128, 128, 3)
-    assert g.get_config() == (64, 128, 128, 4)
+    assert g.get_config() == (64, 256, 256, 4)
 
 
 def test_autotuner_then_bitwise_member_equality(dsw):
