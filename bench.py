@@ -409,8 +409,13 @@ def bench_ensemble(args):
                 a[k].copy_(u[k])
 
     reset()
-    cfg = E.ensemble_tune(A, B, taus, K, reps=1, stream=stream)
-    log(f"[ensemble] tuned launch shapes {cfg}")
+    if args.config:
+        cfg = tuple(int(x) for x in args.config.split(","))
+        E.set_config(*cfg)
+        log(f"[ensemble] launch shapes {cfg} (given)")
+    else:
+        cfg = E.ensemble_tune(A, B, taus, K, reps=1, stream=stream)
+        log(f"[ensemble] tuned launch shapes {cfg}")
     # the per-member calls take the same launch shapes, so that both paths
     # run the same arithmetic (the phi solver's partition depends on them)
     for g in E.members:

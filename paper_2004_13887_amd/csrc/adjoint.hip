@@ -122,7 +122,7 @@ __device__ __forceinline__ void divc_rev(const Geo &g, const Acc &A, int i, int 
 
 // centre() reversed: cb holds the adjoints of the Cent fields, c the values
 template <class S, class Acc>
-__device__ void centre_rev(const Geo &g, const Mat &m, const S &s, int i, int j, int k, const Cent &c,
+__device__ __forceinline__ void centre_rev(const Geo &g, const Mat &m, const S &s, int i, int j, int k, const Cent &c,
                            const Cent &cb, const Acc &A) {
   const double ir = g.irc[i], is = g.isc[j], ct = g.ctc[j], irs = ir * is;
   const double Grr = cb.Grr + cb.tr, Gtt = cb.Gtt + cb.tr, Gff = cb.Gff + cb.tr;
@@ -189,7 +189,7 @@ __device__ void centre_rev(const Geo &g, const Mat &m, const S &s, int i, int j,
 // pressure and temperature rows at a centre (F_p_T of residual.hip);
 // wp, wT: adjoints of F_p and F_T
 template <class S, class Acc>
-__device__ void F_p_T_rev_cb(const Geo &g, const Mat &m, const S &s, int i, int j, int k, const Cent &c,
+__device__ __forceinline__ void F_p_T_rev_cb(const Geo &g, const Mat &m, const S &s, int i, int j, int k, const Cent &c,
                              double wp, double wT, Cent &cb, const Acc &A) {
   const double ir = g.irc[i], is = g.isc[j], ir2 = ir * ir;
   const double hr = 0.5 * g.idr, ht = 0.5 * ir * g.idt, hp = 0.5 * ir * is * g.idp;
@@ -247,7 +247,7 @@ __device__ void F_p_T_rev_cb(const Geo &g, const Mat &m, const S &s, int i, int 
 }
 
 template <class S, class Acc>
-__device__ void F_p_T_rev(const Geo &g, const Mat &m, const S &s, int i, int j, int k, double wp,
+__device__ __forceinline__ void F_p_T_rev(const Geo &g, const Mat &m, const S &s, int i, int j, int k, double wp,
                           double wT, const Acc &A) {
   Cent c, cb{};
   centre(g, m, s, i, j, k, c);
@@ -264,7 +264,7 @@ __device__ void F_p_T_rev(const Geo &g, const Mat &m, const S &s, int i, int j, 
 
 // radial momentum row at interior r-face (f, j, k) (F_ur of residual.hip)
 template <class S, class Acc>
-__device__ void F_ur_rev(const Geo &g, const Mat &m, const S &s, int f, int j, int k, double w,
+__device__ __forceinline__ void F_ur_rev(const Geo &g, const Mat &m, const S &s, int f, int j, int k, double w,
                          const Acc &A, double rfx = 0.0, double uax = 0.0, double ubx = 0.0) {
   const double irF = g.irf[f], is = g.isc[j], irF2 = irF * irF;
   const double Pa = gC(g, s, F_P, f, j, k) + m.pinf, Ta = gC(g, s, F_T, f, j, k);
@@ -357,7 +357,7 @@ __device__ void F_ur_rev(const Geo &g, const Mat &m, const S &s, int f, int j, i
 
 // colatitudinal momentum row at interior theta-face (i, f, k) (F_ut)
 template <class S, class Acc>
-__device__ void F_ut_rev(const Geo &g, const Mat &m, const S &s, int i, int f, int k, double w,
+__device__ __forceinline__ void F_ut_rev(const Geo &g, const Mat &m, const S &s, int i, int f, int k, double w,
                          const Acc &A, double rfx = 0.0, double uax = 0.0, double ubx = 0.0) {
   const double ir = g.irc[i], isF = g.isf[f], ctF = g.ctf[f], ir2 = ir * ir;
   const int j0 = f - 1, j1 = f;
@@ -451,7 +451,7 @@ __device__ void F_ut_rev(const Geo &g, const Mat &m, const S &s, int i, int f, i
 
 // azimuthal momentum row at phi-face (i, j, f) (F_uf)
 template <class S, class Acc>
-__device__ void F_uf_rev(const Geo &g, const Mat &m, const S &s, int i, int j, int f, double w,
+__device__ __forceinline__ void F_uf_rev(const Geo &g, const Mat &m, const S &s, int i, int j, int f, double w,
                          const Acc &A, double rfx = 0.0, double uax = 0.0, double ubx = 0.0) {
   const double ir = g.irc[i], is = g.isc[j], ct = g.ctc[j], ir2 = ir * ir;
   const int k0 = g.periodic ? wrapk(g, f - 1) : f - 1, k1 = g.periodic ? wrapk(g, f) : f;
@@ -582,7 +582,7 @@ void launch_residual_vjp(const Geo &g, const Mat &m, const Fields &Ub, double ta
 // Reverse of block_row<D> (rows.hpp) for the coefficient entries: EL, ED, EU
 // are the adjoints of the final (scaled) L, D, U blocks of row s.
 template <int D, class Acc>
-__device__ void block_row_rev_cb(const Geo &g, const Mat &m, const SrcOne &u, int a, int b, int s, int n,
+__device__ __forceinline__ void block_row_rev_cb(const Geo &g, const Mat &m, const SrcOne &u, int a, int b, int s, int n,
                                  int cyc, double hs, const double *EL, const double *ED, const double *EU,
                                  const Cent &c, Cent &cb, const Acc &A) {
   int i, j, k;
@@ -720,7 +720,7 @@ __device__ void block_row_rev_cb(const Geo &g, const Mat &m, const SrcOne &u, in
 }
 
 template <int D, class Acc>
-__device__ void block_row_rev(const Geo &g, const Mat &m, const SrcOne &u, int a, int b, int s, int n,
+__device__ __forceinline__ void block_row_rev(const Geo &g, const Mat &m, const SrcOne &u, int a, int b, int s, int n,
                               int cyc, double hs, const double *EL, const double *ED, const double *EU,
                               const Acc &A) {
   int i, j, k;
@@ -739,7 +739,7 @@ __device__ void block_row_rev(const Geo &g, const Mat &m, const SrcOne &u, int a
 // rho_f = (rho_c0 + rho_c1)/2, and uab, that of the transverse average
 // (scalar_row_parts); scalar_row_rev also scatters them into A.
 template <int D, int FAM>
-__device__ void scalar_row_parts(const Geo &g, const Mat &m, const SrcOne &u, int a, int b, int s, int n,
+__device__ __forceinline__ void scalar_row_parts(const Geo &g, const Mat &m, const SrcOne &u, int a, int b, int s, int n,
                                  int cyc, double hs, double ea, double eb, double ec, double &rfb,
                                  double &uab, int *cells, long *ix, int &bfid) {
   double h, qa, qb, qc, sglo = -1.0, sghi = -1.0;
@@ -818,7 +818,7 @@ __device__ void scalar_row_parts(const Geo &g, const Mat &m, const SrcOne &u, in
 }
 
 template <int D, int FAM>
-__device__ void scalar_row_rev(const Geo &g, const Mat &m, const SrcOne &u, int a, int b, int s, int n,
+__device__ __forceinline__ void scalar_row_rev(const Geo &g, const Mat &m, const SrcOne &u, int a, int b, int s, int n,
                                int cyc, double hs, double ea, double eb, double ec, const GAcc &A) {
   double rfb, uab;
   int c[6], bfid;

@@ -33,7 +33,7 @@ __device__ __forceinline__ void mm3s(const double *A, const double *B, double *C
 // ------------------------------------------------------- block: PCR step --
 // Solve the T separator rows A x_{t-1} + B x_t + C x_{t+1} = r (t < T) held
 // in registers of threads t < T; LDS holds T x 33 doubles.  Returns x_t.
-__device__ void pcr_block(int t, int T, int cyc, double *A, double *B, double *C, double *r,
+__device__ __forceinline__ void pcr_block(int t, int T, int cyc, double *A, double *B, double *C, double *r,
                           double *lds, double *x, int *status) {
   double *sA = lds, *sC = lds + 9 * T, *sR = lds + 18 * T, *sBi = lds + 21 * T;
   const bool act = t < T;
@@ -93,7 +93,7 @@ __device__ void pcr_block(int t, int T, int cyc, double *A, double *B, double *C
   }
 }
 
-__device__ void pcr_scalar(int t, int T, int cyc, double &A, double &B, double &C, double &r,
+__device__ __forceinline__ void pcr_scalar(int t, int T, int cyc, double &A, double &B, double &C, double &r,
                            double *lds, double &x, int *status) {
   double *sA = lds, *sC = lds + T, *sR = lds + 2 * T, *sB = lds + 3 * T;
   const bool act = t < T;
@@ -130,7 +130,7 @@ __device__ void pcr_scalar(int t, int T, int cyc, double &A, double &B, double &
 
 // ------------------------------------------------------------ block line --
 template <int PM, bool TR>
-__device__ void part_block_line(const Geo &g, const Mat &m, const SrcOne &u, const Fields &rhs,
+__device__ __forceinline__ void part_block_line(const Geo &g, const Mat &m, const SrcOne &u, const Fields &rhs,
                                 const Out &o, int i, int j, double hs, double *lds, int *status) {
   const int N = g.np, T = part_chunks<PM>(N), cyc = g.periodic;
   const int t = threadIdx.x;
@@ -303,7 +303,7 @@ __device__ void part_block_line(const Geo &g, const Mat &m, const SrcOne &u, con
 
 // ----------------------------------------------------------- scalar line --
 template <int PM, int FAM, bool TR>
-__device__ void part_scalar_line(const Geo &g, const Mat &m, const SrcOne &u, const Fields &rhs,
+__device__ __forceinline__ void part_scalar_line(const Geo &g, const Mat &m, const SrcOne &u, const Fields &rhs,
                                  const Out &o, int a, int b, double hs, double *lds, int *status) {
   const int N = g.np, T = part_chunks<PM>(N), cyc = g.periodic;
   const int t = threadIdx.x;
@@ -398,14 +398,19 @@ __device__ void part_scalar_line(const Geo &g, const Mat &m, const SrcOne &u, co
 // one workgroup per (i, j): block line (i, j), u_r line on r-face i (i >= 1),
 // u_theta line on theta-face j (j >= 1).  Flat grid of nr * nt workgroups per
 // grid; one grid or a batch of grids.  The workgroup may be wider than the
-// chunk count: threads past it only join the barriers.
-template <int PM, bool TR>
+// chunk count: threads past it only join the barriers.  PART 0: the block
+// line; 1: the two scalar lines; 2: all three.  On large launches the
+// forward sweep runs parts 0 and 1 as two launches: the scalar lines need far
+// fewer registers (about 55 against 256) and on their own run at a much
+// higher occupancy; on small ones the second launch costs more than that
+// gains.
+template <int PM, bool TR, int PART = 2>
 __device__ __forceinline__ void phi_body(const PassArgs &a, unsigned w, double *lds) {
   const Geo &g = a.g;
   const int j = (int)(w % g.nt), i = (int)(w / g.nt);
   const int t = threadIdx.x;
   const Out &o = a.o;
-  if (o.mode == 0) { // boundary-normal faces of x that no phi line owns
+  if (PART != 1 && o.mode == 0) { // boundary-normal faces of x that no phi line owns
     const Fields &x = o.x;
     for (int k = t; k < g.np; k += blockDim.x) {
       if (i == 0) x.ur[idx_r(g, 0, j, k)] = 0.0;
@@ -415,19 +420,21 @@ __device__ __forceinline__ void phi_body(const PassArgs &a, unsigned w, double *
     }
     if (!g.periodic && t == 0) x.uf[idx_f(g, i, j, 0)] = 0.0;
   }
-  part_block_line<PM, TR>(g, a.m, a.u, a.rhs, o, i, j, a.tau, lds, a.status);
-  if (i >= 1) part_scalar_line<PM, 0, TR>(g, a.m, a.u, a.rhs, o, i, j, a.tau, lds, a.status);
-  if (j >= 1) part_scalar_line<PM, 1, TR>(g, a.m, a.u, a.rhs, o, i, j, a.tau, lds, a.status);
+  if (PART != 1) part_block_line<PM, TR>(g, a.m, a.u, a.rhs, o, i, j, a.tau, lds, a.status);
+  if (PART != 0) {
+    if (i >= 1) part_scalar_line<PM, 0, TR>(g, a.m, a.u, a.rhs, o, i, j, a.tau, lds, a.status);
+    if (j >= 1) part_scalar_line<PM, 1, TR>(g, a.m, a.u, a.rhs, o, i, j, a.tau, lds, a.status);
+  }
 }
 
-template <int PM, bool B>
+template <int PM, bool B, int PART>
 __global__ void __launch_bounds__(256) DSW_OCC(DSW_WAVES_PHI) k_phi_part(PassArgs a, Batch bt) {
   extern __shared__ double lds[];
   if constexpr (B) {
     const int mb = batch_member(bt, blockIdx.x);
-    phi_body<PM, false>(batch_args(bt, mb), blockIdx.x - bt.woff[mb], lds);
+    phi_body<PM, false, PART>(batch_args(bt, mb), blockIdx.x - bt.woff[mb], lds);
   } else {
-    phi_body<PM, false>(a, blockIdx.x, lds);
+    phi_body<PM, false, PART>(a, blockIdx.x, lds);
   }
 }
 
@@ -466,15 +473,44 @@ size_t phi_part_lds(const Geo &g, int pm) {
   return sizeof(double) * 33 * (size_t)T;
 }
 
+// From this many line slots on, the block and the scalar lines run as two
+// launches (measured: 1.99 -> 1.93 ms on 32768 slots of 512 cells, 0.27 ->
+// 0.31 ms on 8192 slots of 256 cells).
+constexpr unsigned PHI_SPLIT_SLOTS = 16384;
+
+// the block lines, then the scalar lines (their LDS: the exchange and
+// reduction arrays, 5 doubles per chunk, or the staged line, PM per chunk),
+// or all in one launch
 void launch_phi_pass(int pm, const PassArgs &a, const Batch &b, unsigned blocks, unsigned threads,
                      size_t lds, hipStream_t st) {
   const dim3 gr(blocks), bl(threads);
+  const size_t lds_s = sizeof(double) * (size_t)(pm > 5 ? pm : 5) * threads;
+  if (blocks < PHI_SPLIT_SLOTS) {
+    if (b.tab) {
+      if (pm == 2) hipLaunchKernelGGL((k_phi_part<2, true, 2>), gr, bl, lds, st, a, b);
+      else hipLaunchKernelGGL((k_phi_part<4, true, 2>), gr, bl, lds, st, a, b);
+    } else {
+      if (pm == 2) hipLaunchKernelGGL((k_phi_part<2, false, 2>), gr, bl, lds, st, a, b);
+      else hipLaunchKernelGGL((k_phi_part<4, false, 2>), gr, bl, lds, st, a, b);
+    }
+    return;
+  }
   if (b.tab) {
-    if (pm == 2) hipLaunchKernelGGL((k_phi_part<2, true>), gr, bl, lds, st, a, b);
-    else hipLaunchKernelGGL((k_phi_part<4, true>), gr, bl, lds, st, a, b);
+    if (pm == 2) {
+      hipLaunchKernelGGL((k_phi_part<2, true, 0>), gr, bl, lds, st, a, b);
+      hipLaunchKernelGGL((k_phi_part<2, true, 1>), gr, bl, lds_s, st, a, b);
+    } else {
+      hipLaunchKernelGGL((k_phi_part<4, true, 0>), gr, bl, lds, st, a, b);
+      hipLaunchKernelGGL((k_phi_part<4, true, 1>), gr, bl, lds_s, st, a, b);
+    }
   } else {
-    if (pm == 2) hipLaunchKernelGGL((k_phi_part<2, false>), gr, bl, lds, st, a, b);
-    else hipLaunchKernelGGL((k_phi_part<4, false>), gr, bl, lds, st, a, b);
+    if (pm == 2) {
+      hipLaunchKernelGGL((k_phi_part<2, false, 0>), gr, bl, lds, st, a, b);
+      hipLaunchKernelGGL((k_phi_part<2, false, 1>), gr, bl, lds_s, st, a, b);
+    } else {
+      hipLaunchKernelGGL((k_phi_part<4, false, 0>), gr, bl, lds, st, a, b);
+      hipLaunchKernelGGL((k_phi_part<4, false, 1>), gr, bl, lds_s, st, a, b);
+    }
   }
 }
 

@@ -19,7 +19,7 @@
 namespace dsw {
 
 template <class S>
-__device__ double F_p_T(const Geo &g, const Mat &m, const S &s, int i, int j, int k, double *FT) {
+__device__ __forceinline__ double F_p_T(const Geo &g, const Mat &m, const S &s, int i, int j, int k, double *FT) {
   Cent c;
   centre(g, m, s, i, j, k, c);
   const double ir = g.irc[i], is = g.isc[j];
@@ -43,7 +43,7 @@ __device__ double F_p_T(const Geo &g, const Mat &m, const S &s, int i, int j, in
 }
 
 template <class S>
-__device__ double F_ur(const Geo &g, const Mat &m, const S &s, int f, int j, int k) {
+__device__ __forceinline__ double F_ur(const Geo &g, const Mat &m, const S &s, int f, int j, int k) {
   const double irF = g.irf[f], is = g.isc[j], irF2 = irF * irF;
   const double irho = 1.0 / (0.5 * (rho_at(g, m, s, f - 1, j, k) + rho_at(g, m, s, f, j, k)));
   const double nu = m.mu * irho;
@@ -74,7 +74,7 @@ __device__ double F_ur(const Geo &g, const Mat &m, const S &s, int f, int j, int
 }
 
 template <class S>
-__device__ double F_ut(const Geo &g, const Mat &m, const S &s, int i, int f, int k) {
+__device__ __forceinline__ double F_ut(const Geo &g, const Mat &m, const S &s, int i, int f, int k) {
   const double ir = g.irc[i], isF = g.isf[f], ctF = g.ctf[f], ir2 = ir * ir;
   const int j0 = f - 1, j1 = f;
   const double irho = 1.0 / (0.5 * (rho_at(g, m, s, i, j0, k) + rho_at(g, m, s, i, j1, k)));
@@ -102,7 +102,7 @@ __device__ double F_ut(const Geo &g, const Mat &m, const S &s, int i, int f, int
 }
 
 template <class S>
-__device__ double F_uf(const Geo &g, const Mat &m, const S &s, int i, int j, int f) {
+__device__ __forceinline__ double F_uf(const Geo &g, const Mat &m, const S &s, int i, int j, int f) {
   const double ir = g.irc[i], is = g.isc[j], ct = g.ctc[j], ir2 = ir * ir;
   const int k0 = g.periodic ? wrapk(g, f - 1) : f - 1, k1 = g.periodic ? wrapk(g, f) : f;
   const double irho = 1.0 / (0.5 * (rho_at(g, m, s, i, j, k0) + rho_at(g, m, s, i, j, k1)));

@@ -25,7 +25,7 @@ namespace dsw {
 // zero the boundary-normal faces of x that no line of this sweep writes:
 // every block line owns a short piece of them
 template <int D>
-__device__ void zero_bnd(const Geo &g, const Fields &x, int a, int b) {
+__device__ __forceinline__ void zero_bnd(const Geo &g, const Fields &x, int a, int b) {
   if (D == 0) { // line (j,k): ur faces 0 (nr written as last block); ut faces 0/nt; uf faces 0/np
     const int j = a, k = b;
     x.ur[idx_r(g, 0, j, k)] = 0.0;
@@ -57,7 +57,7 @@ __device__ void zero_bnd(const Geo &g, const Fields &x, int a, int b) {
 }
 
 template <int D, bool TR>
-__device__ void solve_block_line(const Geo &g, const Mat &m, const SrcOne &u, const Fields &rhs,
+__device__ __forceinline__ void solve_block_line(const Geo &g, const Mat &m, const SrcOne &u, const Fields &rhs,
                                  const Out &o, double *sc, long nl, long line, int a, int b,
                                  int n, double hs, int *status) {
   // scratch: [s][q][line], q < 12: C (9), y (3)
@@ -113,7 +113,7 @@ __device__ void solve_block_line(const Geo &g, const Mat &m, const SrcOne &u, co
 // x_s = Ap_s^{-T} (z_s - A_{s+1}^T x_{s+1}).  Each row is assembled once.
 // scratch [s][q][line], q < 21: Ap^{-1} (9), A (9), z (3)
 template <int D>
-__device__ void solve_block_line_T(const Geo &g, const Mat &m, const SrcOne &u, const Fields &rhs,
+__device__ __forceinline__ void solve_block_line_T(const Geo &g, const Mat &m, const SrcOne &u, const Fields &rhs,
                                    const Out &o, double *sc, long nl, long line, int a, int b, int n,
                                    double hs, int *status) {
 #define SC(s, q) sc[((long)(s) * 21 + (q)) * nl + line]
@@ -167,7 +167,7 @@ __device__ void solve_block_line_T(const Geo &g, const Mat &m, const SrcOne &u, 
 
 // cyclic block line: bordered elimination of the last block
 template <int D, bool TR>
-__device__ void solve_block_cyclic(const Geo &g, const Mat &m, const SrcOne &u, const Fields &rhs,
+__device__ __forceinline__ void solve_block_cyclic(const Geo &g, const Mat &m, const SrcOne &u, const Fields &rhs,
                                    const Out &o, double *sc, long nl, long line, int a, int b,
                                    int n, double hs, int *status) {
   // scratch: [s][q][line], q < 21: C (9), y (3), Z (9)
@@ -259,7 +259,7 @@ __device__ __forceinline__ long scalar_index(const Geo &g, int a, int b, int s) 
 }
 
 template <int D, int FAM, bool TR>
-__device__ void solve_scalar_line(const Geo &g, const Mat &m, const SrcOne &u, const Fields &rhs,
+__device__ __forceinline__ void solve_scalar_line(const Geo &g, const Mat &m, const SrcOne &u, const Fields &rhs,
                                   const Out &o, double *sc, long nl, long line, int a, int b,
                                   int n, int cyc, double hs, int *status) {
   // output field of this family
@@ -432,7 +432,7 @@ void launch_sweep_T(int d, const PassArgs &a, unsigned blocks, unsigned threads,
 // per line, twice the threads.  Lane l of the top half and lane l of the
 // bottom half of a workgroup share a line; the middle data pass through LDS.
 template <int D>
-__device__ void twisted_block_line(const Geo &g, const Mat &m, const SrcOne &u, const Fields &rhs,
+__device__ __forceinline__ void twisted_block_line(const Geo &g, const Mat &m, const SrcOne &u, const Fields &rhs,
                                    const Out &o, double *sc, long nl, long line, bool act, bool top,
                                    int a, int b, int n, double hs, double *lds, int lane, int *status) {
 #define SC(s, q) sc[((long)(s) * 12 + (q)) * nl + line]
@@ -556,7 +556,7 @@ __device__ void twisted_block_line(const Geo &g, const Mat &m, const SrcOne &u, 
 // the row it is at, so every row of M is assembled once per thread (plus one
 // row for the middle), not three times.  Lines have n >= 3, so 1 <= m < n - 1.
 template <int D>
-__device__ void twisted_block_line_T(const Geo &g, const Mat &m, const SrcOne &u, const Fields &rhs,
+__device__ __forceinline__ void twisted_block_line_T(const Geo &g, const Mat &m, const SrcOne &u, const Fields &rhs,
                                      const Out &o, double *sc, long nl, long line, bool act, bool top,
                                      int a, int b, int n, double hs, double *lds, int lane, int *status) {
 #define SC(s, q) sc[((long)(s) * 12 + (q)) * nl + line]
@@ -710,7 +710,7 @@ __device__ void twisted_block_line_T(const Geo &g, const Mat &m, const SrcOne &u
 // and both substitute back over their halves.  LDS per lane: e'_{m+1},
 // z_{m+1}, x_m.
 template <int D, int FAM>
-__device__ void twisted_scalar_line(const Geo &g, const Mat &m, const SrcOne &u, const Fields &rhs,
+__device__ __forceinline__ void twisted_scalar_line(const Geo &g, const Mat &m, const SrcOne &u, const Fields &rhs,
                                     const Out &o, double *sc, long nl, long line, bool act, bool top,
                                     int a, int b, int n, double hs, double *lds, int lane, int *status) {
 #define SC(s, q) sc[((long)(s) * 2 + (q)) * nl + line]
@@ -781,7 +781,7 @@ __device__ void twisted_scalar_line(const Geo &g, const Mat &m, const SrcOne &u,
 // window of the rows of M around its position (top: c_{s-1}, b_s, c_s, r_s;
 // bottom: a_{s+1}, b_s, a_s, r_s), so every row is assembled once.
 template <int D, int FAM>
-__device__ void twisted_scalar_line_T(const Geo &g, const Mat &m, const SrcOne &u, const Fields &rhs,
+__device__ __forceinline__ void twisted_scalar_line_T(const Geo &g, const Mat &m, const SrcOne &u, const Fields &rhs,
                                       const Out &o, double *sc, long nl, long line, bool act, bool top,
                                       int a, int b, int n, double hs, double *lds, int lane, int *status) {
 #define SC(s, q) sc[((long)(s) * 2 + (q)) * nl + line]
