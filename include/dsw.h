@@ -190,7 +190,9 @@ int dsw_residual_vjp(dsw_grid *grid, const dsw_fields *Ubar, double tau, const d
  *                         thread per line.  Lines the partitioned solver
  *                         cannot take (more than 256 chunks, or a cyclic line
  *                         whose chunk count is not a power of two) fall back
- *                         to one thread per line.
+ *                         to one thread per line.  The transposed phi
+ *                         solves of the adjoint take two rows per thread
+ *                         wherever the line allows it.
  * Default {64, 256, 256, 4}.  dsw_set_config returns DSW_EINVAL for other
  * values. */
 typedef struct {

@@ -555,8 +555,12 @@ extern "C" int dsw_get_status(dsw_grid *G, void *stream) {
 // partitioned solver when the configuration and the line allow it
 static void launch_T(const dsw_grid *G, int d, const Pass &p, hipStream_t st) {
   if (d == 2 && p.kind == PK_SW2_PART) {
-    launch_phi_T(G->cfg.phi_pm, p.a, (unsigned)G->geo.nr * (unsigned)G->geo.nt,
-                 phi_part_threads(G->geo, G->cfg.phi_pm), phi_part_lds(G->geo, G->cfg.phi_pm), st);
+    // two rows per chunk where the line allows it: twice the chunks in
+    // flight for the same line (measured faster than four on the transposed
+    // systems, whose row windows hold more registers)
+    const int pm = phi_part_supported(G->geo, 2) ? 2 : G->cfg.phi_pm;
+    launch_phi_T(pm, p.a, (unsigned)G->geo.nr * (unsigned)G->geo.nt, phi_part_threads(G->geo, pm),
+                 phi_part_lds(G->geo, pm), st);
   } else if (d < 2 && families(G->geo, d).nb < TWIST_LINES) {
     const unsigned bs = (unsigned)G->cfg.sweep_bs[d];
     launch_sweep2_T(d, p.a, sweep2_blocks(G->geo, d, bs), bs, st);

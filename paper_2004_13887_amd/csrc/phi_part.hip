@@ -440,16 +440,24 @@ __global__ void __launch_bounds__(256) DSW_OCC(DSW_WAVES_PHI) k_phi_part(PassArg
 
 // transposed systems (adjoint), one grid: each chunk walks the rows of the
 // line once and forms the transposed rows from them (TrWalk, TrWalkS)
-template <int PM>
+template <int PM, int PART>
 __global__ void __launch_bounds__(256) k_phi_part_T(PassArgs a) {
   extern __shared__ double lds[];
-  phi_body<PM, true>(a, blockIdx.x, lds);
+  phi_body<PM, true, PART>(a, blockIdx.x, lds);
 }
 
+// block lines, then scalar lines, as two launches: the scalar launch holds a
+// fraction of the block launch's registers and runs at higher occupancy
 void launch_phi_T(int pm, const PassArgs &a, unsigned blocks, unsigned threads, size_t lds,
                   hipStream_t st) {
-  if (pm == 2) hipLaunchKernelGGL(k_phi_part_T<2>, dim3(blocks), dim3(threads), lds, st, a);
-  else hipLaunchKernelGGL(k_phi_part_T<4>, dim3(blocks), dim3(threads), lds, st, a);
+  const size_t lds_s = sizeof(double) * (size_t)(pm > 5 ? pm : 5) * threads;
+  if (pm == 2) {
+    hipLaunchKernelGGL((k_phi_part_T<2, 0>), dim3(blocks), dim3(threads), lds, st, a);
+    hipLaunchKernelGGL((k_phi_part_T<2, 1>), dim3(blocks), dim3(threads), lds_s, st, a);
+  } else {
+    hipLaunchKernelGGL((k_phi_part_T<4, 0>), dim3(blocks), dim3(threads), lds, st, a);
+    hipLaunchKernelGGL((k_phi_part_T<4, 1>), dim3(blocks), dim3(threads), lds_s, st, a);
+  }
 }
 
 bool phi_part_supported(const Geo &g, int pm) {
