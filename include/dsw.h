@@ -125,6 +125,42 @@ int dsw_line_solve_phi(dsw_grid *grid, const dsw_fields *Ubar, double tau, const
 int dsw_split_step(dsw_grid *grid, const dsw_fields *Un, dsw_fields *Unp1, double tau, int32_t K,
                    void *stream);
 
+/* Tangential velocities on the non-periodic walls, at the time the ghost
+ * values are wanted (for a split step: the midpoint of the old and the new
+ * time level).  Device arrays, C order; a null entry is a zero wall velocity.
+ * A ghost value across a wall is 2 g - u of the interior neighbour (the
+ * no-slip rule of the velocity boundary condition, paper section 2.1, with
+ * the wall moving).  Pole boundaries ignore them (symmetry ghosts).
+ *   ur_t1, ur_t2 [n_r+1][n_phi]      u_r on the theta = theta1 / theta2 walls
+ *   ur_p1, ur_p2 [n_r+1][n_theta]    u_r on the phi = phi1 / phi2 walls
+ *   ut_r1, ut_r2 [n_theta+1][n_phi]  u_theta on the r = r1 / r2 walls
+ *   ut_p1, ut_p2 [n_r][n_theta+1]    u_theta on the phi walls
+ *   uf_r1, uf_r2 [n_theta][npf]      u_phi on the r walls
+ *   uf_t1, uf_t2 [n_r][npf]          u_phi on the theta walls
+ * (npf = n_phi + 1 on a sector, n_phi when periodic). */
+typedef struct {
+  const double *ur_t1, *ur_t2, *ur_p1, *ur_p2;
+  const double *ut_r1, *ut_r2, *ut_p1, *ut_p2;
+  const double *uf_r1, *uf_r2, *uf_t1, *uf_t2;
+} dsw_wall;
+
+/* dsw_split_step with forcing, for manufactured solutions (paper section 3.1,
+ * eq. (man_sol)) and moving or time-dependent walls:
+ *   src  (may be NULL, as may each of its arrays) a source S added to the
+ *        right-hand side of the system, taken at the midpoint time: every
+ *        iteration's residual is -(U^k - U^n) - tau (F_h(Ubar) - S);
+ *   wall (may be NULL) wall velocities for the ghost values of Ubar;
+ *   bnd  (may be NULL) fields whose boundary-normal faces (ur, ut, uf; p and
+ *        T are not read) hold the Dirichlet data of the new time level:
+ *        U^{n+1,k} takes them for every k and Ubar their mean with those of
+ *        Un.  NULL: those of Un.
+ * The rest as dsw_split_step.  Runs the residual over every point and needs
+ * phi lines that the partitioned solver takes (any sector of up to 1024 phi
+ * cells; on a full sphere a power-of-two chunk count), else DSW_EINVAL. */
+int dsw_split_step_forced(dsw_grid *grid, const dsw_fields *Un, dsw_fields *Unp1, double tau,
+                          int32_t K, const dsw_fields *src, const dsw_wall *wall,
+                          const dsw_fields *bnd, void *stream);
+
 /* Optional per-kernel timing of dsw_split_step.  While enabled, every kernel
  * the step enqueues is bracketed by a pair of HIP events recorded on the same
  * stream.  dsw_read_timing synchronises that stream, stores in ms[kind] the

@@ -478,6 +478,81 @@ extern "C" int dsw_split_step(dsw_grid *G, const dsw_fields *Un, dsw_fields *Unp
   return check_launch("split step kernels");
 }
 
+static Wall to_wall(const dsw_wall *w) {
+  Wall o{};
+  if (!w) return o;
+  o.ur_t1 = w->ur_t1; o.ur_t2 = w->ur_t2; o.ur_p1 = w->ur_p1; o.ur_p2 = w->ur_p2;
+  o.ut_r1 = w->ut_r1; o.ut_r2 = w->ut_r2; o.ut_p1 = w->ut_p1; o.ut_p2 = w->ut_p2;
+  o.uf_r1 = w->uf_r1; o.uf_r2 = w->uf_r2; o.uf_t1 = w->uf_t1; o.uf_t2 = w->uf_t2;
+  return o;
+}
+
+extern "C" int dsw_split_step_forced(dsw_grid *G, const dsw_fields *Un, dsw_fields *Unp1, double tau,
+                                     int32_t K, const dsw_fields *src, const dsw_wall *wall,
+                                     const dsw_fields *bnd, void *stream) {
+  if (!G) return fail(DSW_EINVAL, "null handle");
+  int rc = check_step_args(Un, Unp1, tau, K);
+  if (rc) return rc;
+  if (bnd && (!bnd->ur || !bnd->ut || !bnd->uf)) return fail(DSW_EINVAL, "bnd needs ur, ut and uf");
+  const Geo &g = G->geo;
+  int pm = G->cfg.phi_pm;
+  if (!(pm > 0 && phi_part_supported(g, pm))) pm = phi_part_supported(g, 4) ? 4 : (phi_part_supported(g, 2) ? 2 : 0);
+  if (!pm) return fail(DSW_EINVAL, "forced step: the phi lines do not fit the partitioned solver");
+  if (families(g, 0).nb >= TWIST_LINES || families(g, 1).nb >= TWIST_LINES)
+    return fail(DSW_EINVAL, "forced step: too many r or theta lines");
+  hipStream_t st = (hipStream_t)stream;
+  const Fields un = F(Un), uk = F(Unp1), none{};
+  const Wall w = to_wall(wall);
+  // U^{n+1,0} in Unp1: U^n with the new Dirichlet data on its
+  // boundary-normal faces.  Every phi sweep updates it in place: the sweep
+  // also rewrites the last phi face of a sector line as base + 0, which must
+  // then hold the new data, not U^n's.  Midpoint of the first iteration in
+  // ub2: U^n with the mean Dirichlet data; ub's boundary faces alike.
+  const double *unf[5] = {un.p, un.ur, un.ut, un.uf, un.T};
+  double *u0[5] = {G->ub2.p, G->ub2.ur, G->ub2.ut, G->ub2.uf, G->ub2.T};
+  double *u1[5] = {uk.p, uk.ur, uk.ut, uk.uf, uk.T};
+  for (int q = 0; q < 5; q++) {
+    HIPCHK(hipMemcpyAsync(u0[q], unf[q], sizeof(double) * (size_t)G->count[q], hipMemcpyDeviceToDevice, st));
+    HIPCHK(hipMemcpyAsync(u1[q], unf[q], sizeof(double) * (size_t)G->count[q], hipMemcpyDeviceToDevice, st));
+  }
+  {
+    PassArgs a = base_args(G);
+    a.src = un;
+    a.rhs = bnd ? F(bnd) : none;
+    a.d0 = uk; a.d1 = G->ub; a.d2 = G->ub2;
+    launch_bnd_forced(a, cdiv(bnd_points(g), 128), 128, st);
+  }
+  const Fields ubuf[2] = {G->ub, G->ub2};
+  const unsigned rbs = (unsigned)G->cfg.res_bs;
+  for (int it = 0; it < K; it++) {
+    const Fields ubar = it == 0 ? G->ub2 : ubuf[(it - 1) % 2];
+    PassArgs r = base_args(G);
+    r.u = src1(ubar);
+    r.d = diff(un, it == 0 ? un : uk);
+    r.tau = tau;
+    r.R = G->r;
+    r.wall = w;
+    if (src) r.fsrc = F(src);
+    launch_residual_forced(r, cdiv((unsigned long)g.npf, rbs) * (unsigned)(g.nt + 1) * (unsigned)(g.nr + 1), rbs, st);
+    Out o1{}, o2{}, o3{};
+    o1.x = G->x1; o1.mode = 0;
+    o2.x = G->x2; o2.mode = 0;
+    o3.x = uk; o3.base = uk; o3.un = un;
+    o3.ub = it < K - 1 ? ubuf[it % 2] : none;
+    o3.mode = 1;
+    for (int d = 0; d < 2; d++) {
+      Pass p = sweep_pass(G, d, ubar, tau, d == 0 ? G->r : G->x1, d == 0 ? o1 : o2);
+      p.a.wall = w;
+      const unsigned bs = (unsigned)G->cfg.sweep_bs[d];
+      launch_sweep2_forced(d, p.a, sweep2_blocks(g, d, bs), bs, st);
+    }
+    Pass p = sweep_pass(G, 2, ubar, tau, G->x2, o3);
+    p.a.wall = w;
+    launch_phi_forced(pm, p.a, (unsigned)g.nr * (unsigned)g.nt, phi_part_threads(g, pm), phi_part_lds(g, pm), st);
+  }
+  return check_launch("forced split step kernels");
+}
+
 static int check_cfg(const dsw_config *c) {
   if (!c) return fail(DSW_EINVAL, "null config");
   auto bs_ok = [](int v) { return v == 64 || v == 128 || v == 256; };

@@ -60,6 +60,7 @@ struct SrcOneT {
   const double *a[5];
   static constexpr bool INTERIOR = I;
   static constexpr bool PERIODIC = P; // interior sources: phi periodic (known at compile time)
+  static constexpr bool WALL = false;  // tangential wall velocities are zero
   __device__ __forceinline__ double ld(int f, long x) const { return a[f][x]; }
 };
 using SrcOne = SrcOneT<false>;
@@ -69,8 +70,81 @@ struct SrcMid {
   const double *n[5], *k[5];
   static constexpr bool INTERIOR = false;
   static constexpr bool PERIODIC = false;
+  static constexpr bool WALL = false;
   __device__ __forceinline__ double ld(int f, long x) const { return 0.5 * (k[f][x] + n[f][x]); }
 };
+
+// Tangential velocities on the non-periodic walls (device arrays; a null
+// entry is a zero wall velocity).  A ghost value across a wall is 2 g - u of
+// the interior neighbour.  Shapes:
+//   ur_t1, ur_t2 [nr+1][np]   u_r on the theta walls   ur_p1, ur_p2 [nr+1][nt]   on the phi walls
+//   ut_r1, ut_r2 [nt+1][np]   u_theta on the r walls   ut_p1, ut_p2 [nr][nt+1]   on the phi walls
+//   uf_r1, uf_r2 [nt][npf]    u_phi on the r walls     uf_t1, uf_t2 [nr][npf]    on the theta walls
+struct Wall {
+  const double *ur_t1, *ur_t2, *ur_p1, *ur_p2;
+  const double *ut_r1, *ut_r2, *ut_p1, *ut_p2;
+  const double *uf_r1, *uf_r2, *uf_t1, *uf_t2;
+};
+__device__ __forceinline__ double wallv(const double *w, long x) { return w ? w[x] : 0.0; }
+
+// A forced source: the state with wall velocities, plus a source term that
+// the residual adds to -F_h (paper section 3.1, manufactured solutions)
+struct SrcW {
+  const double *a[5];
+  Wall w;
+  const double *f[5]; // source at the midpoint time; null: none
+  static constexpr bool INTERIOR = false;
+  static constexpr bool PERIODIC = false;
+  static constexpr bool WALL = true;
+  __device__ __forceinline__ double ld(int fid, long x) const { return a[fid][x]; }
+};
+
+// Velocity ghosts of a forced source: across a wall 2 g - u (g the wall's
+// tangential velocity), the phi wall first, then the theta or r wall; across
+// a pole the symmetry ghosts of the plain rules.
+__device__ __forceinline__ double gR_wall(const Geo &g, const SrcW &s, int f, int j, int k) {
+  double sg = 1.0, add = 0.0;
+  if (k < 0 || k >= g.np) {
+    if (g.periodic) k = wrapk(g, k);
+    else {
+      add = 2.0 * wallv(k < 0 ? s.w.ur_p1 : s.w.ur_p2, (long)f * g.nt + clampi(j, 0, g.nt - 1));
+      sg = -sg; k = k < 0 ? 0 : g.np - 1;
+    }
+  }
+  if (j < 0) {
+    if (!g.pole_lo) { add += sg * 2.0 * wallv(s.w.ur_t1, (long)f * g.np + k); sg = -sg; }
+    j = 0;
+  } else if (j >= g.nt) {
+    if (!g.pole_hi) { add += sg * 2.0 * wallv(s.w.ur_t2, (long)f * g.np + k); sg = -sg; }
+    j = g.nt - 1;
+  }
+  return add + sg * s.ld(F_UR, idx_r(g, f, j, k));
+}
+__device__ __forceinline__ double gT_wall(const Geo &g, const SrcW &s, int i, int f, int k) {
+  double sg = 1.0, add = 0.0;
+  if (k < 0 || k >= g.np) {
+    if (g.periodic) k = wrapk(g, k);
+    else {
+      add = 2.0 * wallv(k < 0 ? s.w.ut_p1 : s.w.ut_p2, (long)clampi(i, 0, g.nr - 1) * (g.nt + 1) + f);
+      sg = -sg; k = k < 0 ? 0 : g.np - 1;
+    }
+  }
+  if (i < 0) { add += sg * 2.0 * wallv(s.w.ut_r1, (long)f * g.np + k); sg = -sg; i = 0; }
+  else if (i >= g.nr) { add += sg * 2.0 * wallv(s.w.ut_r2, (long)f * g.np + k); sg = -sg; i = g.nr - 1; }
+  return add + sg * s.ld(F_UT, idx_t(g, i, f, k));
+}
+__device__ __forceinline__ double gF_wall(const Geo &g, const SrcW &s, int i, int j, int f) {
+  double sg = 1.0, add = 0.0;
+  if (g.periodic) f = wrapk(g, f);
+  if (j < 0 || j >= g.nt) {
+    const bool pole = j < 0 ? g.pole_lo : g.pole_hi;
+    if (!pole) add = 2.0 * wallv(j < 0 ? s.w.uf_t1 : s.w.uf_t2, (long)clampi(i, 0, g.nr - 1) * g.npf + f);
+    sg = -sg; j = j < 0 ? 0 : g.nt - 1;
+  }
+  if (i < 0) { add += sg * 2.0 * wallv(s.w.uf_r1, (long)j * g.npf + f); sg = -sg; i = 0; }
+  else if (i >= g.nr) { add += sg * 2.0 * wallv(s.w.uf_r2, (long)j * g.npf + f); sg = -sg; i = g.nr - 1; }
+  return add + sg * s.ld(F_UF, idx_f(g, i, j, f));
+}
 
 // p or T at a (possibly ghost) centre
 template <class S>
@@ -93,6 +167,7 @@ __device__ __forceinline__ double gR(const Geo &g, const S &s, int f, int j, int
     const double v = s.ld(F_UR, (f * g.nt + j) * g.np + kk);
     return kk == k ? v : -v;
   }
+  if constexpr (S::WALL) return gR_wall(g, s, f, j, k);
   double sg = 1.0;
   if (k < 0 || k >= g.np) {
     if (g.periodic) k = wrapk(g, k);
@@ -111,6 +186,7 @@ __device__ __forceinline__ double gT(const Geo &g, const S &s, int i, int f, int
     const double v = s.ld(F_UT, (i * (g.nt + 1) + f) * g.np + kk);
     return kk == k ? v : -v;
   }
+  if constexpr (S::WALL) return gT_wall(g, s, i, f, k);
   double sg = 1.0;
   if (k < 0 || k >= g.np) {
     if (g.periodic) k = wrapk(g, k);
@@ -124,6 +200,7 @@ __device__ __forceinline__ double gT(const Geo &g, const S &s, int i, int f, int
 template <class S>
 __device__ __forceinline__ double gF(const Geo &g, const S &s, int i, int j, int f) {
   if constexpr (S::INTERIOR) return s.ld(F_UF, (i * g.nt + j) * g.npf + (S::PERIODIC ? wrapk(g, f) : f));
+  if constexpr (S::WALL) return gF_wall(g, s, i, j, f);
   double sg = 1.0;
   if (g.periodic) f = wrapk(g, f);
   if (j < 0) { sg = -sg; j = 0; }

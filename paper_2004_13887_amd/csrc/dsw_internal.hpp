@@ -66,6 +66,27 @@ struct PassArgs {
   double *scb, *scs; // sweeps: scratch of block and scalar lines
   int *status;
   Fields src, d0, d1, d2; // boundary-face copy: src -> d0, d1, d2
+  Wall wall;              // forced passes: tangential wall velocities
+  Fields fsrc;            // forced residual: source term (null entries: none)
+};
+
+// The state source of a pass: the plain midpoint (zero wall velocities), or
+// for a forced pass the midpoint with the wall velocities and the source.
+template <bool W>
+struct SrcSel {
+  __device__ static __forceinline__ const SrcOne &get(const PassArgs &a) { return a.u; }
+};
+template <>
+struct SrcSel<true> {
+  __device__ static __forceinline__ SrcW get(const PassArgs &a) {
+    SrcW s;
+#pragma unroll
+    for (int q = 0; q < 5; q++) s.a[q] = a.u.a[q];
+    s.w = a.wall;
+    s.f[F_P] = a.fsrc.p; s.f[F_UR] = a.fsrc.ur; s.f[F_UT] = a.fsrc.ut; s.f[F_UF] = a.fsrc.uf;
+    s.f[F_T] = a.fsrc.T;
+    return s;
+  }
 };
 
 // One launch over several grids.  Workgroup w belongs to member m with
@@ -101,6 +122,15 @@ struct Cfg {
 
 enum PassKind { PK_BND = 0, PK_RES = 1, PK_SW0 = 2, PK_SW1 = 3, PK_SW2_LINE = 4, PK_SW2_PART = 5,
                 PK_RES_IN = 6, PK_SW0T = 7, PK_SW1T = 8, PK_RES_INP = 9 };
+
+// forced split step (source term, wall velocities, Dirichlet data at the new
+// time level): one grid, the general residual over every point, the
+// two-ended r and theta sweeps and the partitioned phi solver
+void launch_bnd_forced(const PassArgs &a, unsigned blocks, unsigned threads, hipStream_t st);
+void launch_residual_forced(const PassArgs &a, unsigned blocks, unsigned threads, hipStream_t st);
+void launch_sweep2_forced(int d, const PassArgs &a, unsigned blocks, unsigned threads, hipStream_t st);
+void launch_phi_forced(int pm, const PassArgs &a, unsigned blocks, unsigned threads, size_t lds,
+                       hipStream_t st);
 
 // r and theta sweeps take two threads per line (two-ended elimination) on
 // grids with fewer block lines than this; measured faster than one thread

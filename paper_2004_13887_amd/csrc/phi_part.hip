@@ -129,8 +129,8 @@ __device__ __forceinline__ void pcr_scalar(int t, int T, int cyc, double &A, dou
 }
 
 // ------------------------------------------------------------ block line --
-template <int PM, bool TR>
-__device__ __forceinline__ void part_block_line(const Geo &g, const Mat &m, const SrcOne &u, const Fields &rhs,
+template <int PM, bool TR, class US>
+__device__ __forceinline__ void part_block_line(const Geo &g, const Mat &m, const US &u, const Fields &rhs,
                                 const Out &o, int i, int j, double hs, double *lds, int *status) {
   const int N = g.np, T = part_chunks<PM>(N), cyc = g.periodic;
   const int t = threadIdx.x;
@@ -140,7 +140,9 @@ __device__ __forceinline__ void part_block_line(const Geo &g, const Mat &m, cons
   double Cm[PM - 1][9], Em[PM - 1][9], Ym[PM - 1][3];
   BRow R;
   TrWalk<2> tw; // transposed rows: each row of the line assembled once
-  if (TR && act) tw.init(g, m, u, rhs, i, j, a0, N, cyc, hs);
+  if constexpr (TR) {
+    if (act) tw.init(g, m, u, rhs, i, j, a0, N, cyc, hs);
+  }
   // 1. forward elimination over interior rows with the left spike
 #pragma unroll
   for (int q = 0; q < PM - 1; q++) {
@@ -302,8 +304,8 @@ __device__ __forceinline__ void part_block_line(const Geo &g, const Mat &m, cons
 }
 
 // ----------------------------------------------------------- scalar line --
-template <int PM, int FAM, bool TR>
-__device__ __forceinline__ void part_scalar_line(const Geo &g, const Mat &m, const SrcOne &u, const Fields &rhs,
+template <int PM, int FAM, bool TR, class US>
+__device__ __forceinline__ void part_scalar_line(const Geo &g, const Mat &m, const US &u, const Fields &rhs,
                                  const Out &o, int a, int b, double hs, double *lds, int *status) {
   const int N = g.np, T = part_chunks<PM>(N), cyc = g.periodic;
   const int t = threadIdx.x;
@@ -316,7 +318,9 @@ __device__ __forceinline__ void part_scalar_line(const Geo &g, const Mat &m, con
   long xi;
   double *arr;
   TrWalkS<2, FAM> tw; // transposed rows: each row of the line assembled once
-  if (TR && act) tw.init(g, m, u, rhs, a, b, a0, N, cyc, hs);
+  if constexpr (TR) {
+    if (act) tw.init(g, m, u, rhs, a, b, a0, N, cyc, hs);
+  }
 #pragma unroll
   for (int q = 0; q < PM - 1; q++) {
     if (q < len - 1) {
@@ -404,9 +408,10 @@ __device__ __forceinline__ void part_scalar_line(const Geo &g, const Mat &m, con
 // fewer registers (about 55 against 256) and on their own run at a much
 // higher occupancy; on small ones the second launch costs more than that
 // gains.
-template <int PM, bool TR, int PART = 2>
+template <int PM, bool TR, int PART = 2, bool W = false>
 __device__ __forceinline__ void phi_body(const PassArgs &a, unsigned w, double *lds) {
   const Geo &g = a.g;
+  decltype(auto) u = SrcSel<W>::get(a); // W: forced pass (wall velocities)
   const int j = (int)(w % g.nt), i = (int)(w / g.nt);
   const int t = threadIdx.x;
   const Out &o = a.o;
@@ -420,10 +425,10 @@ __device__ __forceinline__ void phi_body(const PassArgs &a, unsigned w, double *
     }
     if (!g.periodic && t == 0) x.uf[idx_f(g, i, j, 0)] = 0.0;
   }
-  if (PART != 1) part_block_line<PM, TR>(g, a.m, a.u, a.rhs, o, i, j, a.tau, lds, a.status);
+  if (PART != 1) part_block_line<PM, TR>(g, a.m, u, a.rhs, o, i, j, a.tau, lds, a.status);
   if (PART != 0) {
-    if (i >= 1) part_scalar_line<PM, 0, TR>(g, a.m, a.u, a.rhs, o, i, j, a.tau, lds, a.status);
-    if (j >= 1) part_scalar_line<PM, 1, TR>(g, a.m, a.u, a.rhs, o, i, j, a.tau, lds, a.status);
+    if (i >= 1) part_scalar_line<PM, 0, TR>(g, a.m, u, a.rhs, o, i, j, a.tau, lds, a.status);
+    if (j >= 1) part_scalar_line<PM, 1, TR>(g, a.m, u, a.rhs, o, i, j, a.tau, lds, a.status);
   }
 }
 
@@ -436,6 +441,19 @@ __global__ void __launch_bounds__(256) DSW_OCC(DSW_WAVES_PHI) k_phi_part(PassArg
   } else {
     phi_body<PM, false, PART>(a, blockIdx.x, lds);
   }
+}
+
+// forced split step, one grid, all three lines of a slot in one launch
+template <int PM>
+__global__ void __launch_bounds__(256) DSW_OCC(DSW_WAVES_PHI) k_phi_partF(PassArgs a) {
+  extern __shared__ double lds[];
+  phi_body<PM, false, 2, true>(a, blockIdx.x, lds);
+}
+
+void launch_phi_forced(int pm, const PassArgs &a, unsigned blocks, unsigned threads, size_t lds,
+                       hipStream_t st) {
+  if (pm == 2) hipLaunchKernelGGL(k_phi_partF<2>, dim3(blocks), dim3(threads), lds, st, a);
+  else hipLaunchKernelGGL(k_phi_partF<4>, dim3(blocks), dim3(threads), lds, st, a);
 }
 
 // transposed systems (adjoint), one grid: each chunk walks the rows of the

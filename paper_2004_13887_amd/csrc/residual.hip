@@ -13,6 +13,8 @@
 //   * inside a split step the midpoint is already resident (written by the
 //     previous iteration's last sweep, or U^n itself at the first iteration),
 //     so every neighbour read is a single load.
+#include <type_traits>
+
 #include "dsw_common.hpp"
 #include "dsw_internal.hpp"
 
@@ -129,6 +131,14 @@ __device__ __forceinline__ double F_uf(const Geo &g, const Mat &m, const S &s, i
   return N - nu * vis - nu / 3.0 * gd;
 }
 
+// F_h at an unknown, less the source term of a forced state (manufactured
+// solutions: the residual takes -(F_h - S))
+template <class S>
+__device__ __forceinline__ double forced(const S &s, int fid, long x, double F) {
+  if constexpr (S::WALL) return s.f[fid] ? F - s.f[fid][x] : F;
+  else return F;
+}
+
 // residual at the centre (i,j,k) and the three faces with the same indices
 template <class S, bool WRITE_UB>
 __device__ __forceinline__ void residual_point(const Geo &g, const Mat &m, const S &s, const Diff &dU,
@@ -143,24 +153,24 @@ __device__ __forceinline__ void residual_point(const Geo &g, const Mat &m, const
     if (!(ubT > 0.0) || !(ubp + m.pinf > 0.0)) status[ST_NONPHYS] = 1; // plain vector store
     double FT;
     const double Fp = F_p_T(g, m, s, i, j, k, &FT);
-    R.p[x] = -dU.at(F_P, x) - tau * Fp;
-    R.T[x] = -dU.at(F_T, x) - tau * FT;
+    R.p[x] = -dU.at(F_P, x) - tau * forced(s, F_P, x, Fp);
+    R.T[x] = -dU.at(F_T, x) - tau * forced(s, F_T, x, FT);
   }
   if (j < g.nt && kc) { // r face i
     const long x = idx_r(g, i, j, k);
     if (WRITE_UB) Ub.ur[x] = s.ld(F_UR, x);
-    R.ur[x] = (i >= 1 && i < g.nr) ? -dU.at(F_UR, x) - tau * F_ur(g, m, s, i, j, k) : 0.0;
+    R.ur[x] = (i >= 1 && i < g.nr) ? -dU.at(F_UR, x) - tau * forced(s, F_UR, x, F_ur(g, m, s, i, j, k)) : 0.0;
   }
   if (i < g.nr && kc) { // theta face j
     const long x = idx_t(g, i, j, k);
     if (WRITE_UB) Ub.ut[x] = s.ld(F_UT, x);
-    R.ut[x] = (j >= 1 && j < g.nt) ? -dU.at(F_UT, x) - tau * F_ut(g, m, s, i, j, k) : 0.0;
+    R.ut[x] = (j >= 1 && j < g.nt) ? -dU.at(F_UT, x) - tau * forced(s, F_UT, x, F_ut(g, m, s, i, j, k)) : 0.0;
   }
   if (i < g.nr && j < g.nt) { // phi face k
     const long x = idx_f(g, i, j, k);
     if (WRITE_UB) Ub.uf[x] = s.ld(F_UF, x);
     const bool interior = g.periodic || (k >= 1 && k < g.np);
-    R.uf[x] = interior ? -dU.at(F_UF, x) - tau * F_uf(g, m, s, i, j, k) : 0.0;
+    R.uf[x] = interior ? -dU.at(F_UF, x) - tau * forced(s, F_UF, x, F_uf(g, m, s, i, j, k)) : 0.0;
   }
 }
 
@@ -189,6 +199,9 @@ __host__ __device__ inline unsigned res_interior_blocks(const Geo &g, int bs) {
   return (unsigned)res_nk(g, bs) * (unsigned)(g.nt - 2) * (unsigned)(g.nr - 2);
 }
 
+// W: a forced pass (wall velocities and source term; no interior launch, so
+// this one covers every point)
+template <bool W = false>
 __device__ __forceinline__ void residual_body(const PassArgs &a, unsigned w) {
   const Geo &g = a.g;
   const unsigned nkb = (g.npf + blockDim.x - 1) / blockDim.x;
@@ -197,9 +210,10 @@ __device__ __forceinline__ void residual_body(const PassArgs &a, unsigned w) {
   const int bs = (int)blockDim.x;
   const bool interior = res_interior_blocks(g, bs) > 0 && i >= 1 && i <= g.nr - 2 && j >= 1 &&
                         j <= g.nt - 2;
-  if (interior) return;  // done by the interior launch
-  residual_point<SrcOne, false>(g, a.m, a.u, a.d, a.tau, a.R, Fields{}, a.status, i, j,
-                                (int)(kb * blockDim.x + threadIdx.x));
+  if (!W && interior) return;  // done by the interior launch
+  decltype(auto) s = SrcSel<W>::get(a);
+  residual_point<std::decay_t<decltype(s)>, false>(g, a.m, s, a.d, a.tau, a.R, Fields{}, a.status, i, j,
+                                                   (int)(kb * blockDim.x + threadIdx.x));
 }
 
 template <class SI>
@@ -224,6 +238,13 @@ __global__ void __launch_bounds__(256) DSW_OCC(DSW_WAVES_RES) k_residual(PassArg
   } else {
     residual_body(a, blockIdx.x);
   }
+}
+
+// forced split step: one grid, every point
+__global__ void __launch_bounds__(256) k_residual_forced(PassArgs a) { residual_body<true>(a, blockIdx.x); }
+
+void launch_residual_forced(const PassArgs &a, unsigned blocks, unsigned threads, hipStream_t st) {
+  hipLaunchKernelGGL(k_residual_forced, dim3(blocks), dim3(threads), 0, st, a);
 }
 
 // P: the grids of the launch are periodic in phi (full sphere)

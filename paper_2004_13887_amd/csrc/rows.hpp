@@ -65,8 +65,8 @@ __host__ __device__ inline Families families(const Geo &g, int d) {
 
 // Assemble block row s of (I + tau/2 D_d) on block line (a, b).  hs = tau/2.
 // Unknown order within a block: p, T, w.
-template <int D>
-__device__ __forceinline__ void block_row(const Geo &g, const Mat &m, const SrcOne &u, const Fields &rhs, int a,
+template <int D, class S>
+__device__ __forceinline__ void block_row(const Geo &g, const Mat &m, const S &u, const Fields &rhs, int a,
                           int b, int s, int n, int cyc, double hs, BRow &R) {
   int i, j, k;
   if (D == 0) { i = s; j = a; k = b; }
@@ -196,8 +196,8 @@ struct SRow {
 // Scalar line of family FAM (0: A, 1: B) in direction D, transverse coords
 // (a, b); row s.  Ghost folding at non-cyclic ends: walls -1, poles (u_r
 // along theta) +1.
-template <int D, int FAM>
-__device__ __forceinline__ void scalar_row(const Geo &g, const Mat &m, const SrcOne &u, const Fields &rhs, int a,
+template <int D, int FAM, class S>
+__device__ __forceinline__ void scalar_row(const Geo &g, const Mat &m, const S &u, const Fields &rhs, int a,
                            int b, int s, int n, int cyc, double hs, SRow &R, long &xi,
                            double *&arr) {
   double ca, cb, cc_, sglo = -1.0, sghi = -1.0;

@@ -431,8 +431,8 @@ void launch_sweep_T(int d, const PassArgs &a, unsigned blocks, unsigned threads,
 // x_s = z_s - E'_s x_{s-1} below).  Same arithmetic and scratch as one thread
 // per line, twice the threads.  Lane l of the top half and lane l of the
 // bottom half of a workgroup share a line; the middle data pass through LDS.
-template <int D>
-__device__ __forceinline__ void twisted_block_line(const Geo &g, const Mat &m, const SrcOne &u, const Fields &rhs,
+template <int D, class S>
+__device__ __forceinline__ void twisted_block_line(const Geo &g, const Mat &m, const S &u, const Fields &rhs,
                                    const Out &o, double *sc, long nl, long line, bool act, bool top,
                                    int a, int b, int n, double hs, double *lds, int lane, int *status) {
 #define SC(s, q) sc[((long)(s) * 12 + (q)) * nl + line]
@@ -709,8 +709,8 @@ __device__ __forceinline__ void twisted_block_line_T(const Geo &g, const Mat &m,
 //   (b_m - a_m c'_{m-1} - c_m e'_{m+1}) x_m = r_m - a_m y_{m-1} - c_m z_{m+1}
 // and both substitute back over their halves.  LDS per lane: e'_{m+1},
 // z_{m+1}, x_m.
-template <int D, int FAM>
-__device__ __forceinline__ void twisted_scalar_line(const Geo &g, const Mat &m, const SrcOne &u, const Fields &rhs,
+template <int D, int FAM, class S>
+__device__ __forceinline__ void twisted_scalar_line(const Geo &g, const Mat &m, const S &u, const Fields &rhs,
                                     const Out &o, double *sc, long nl, long line, bool act, bool top,
                                     int a, int b, int n, double hs, double *lds, int lane, int *status) {
 #define SC(s, q) sc[((long)(s) * 2 + (q)) * nl + line]
@@ -868,9 +868,11 @@ __host__ __device__ inline unsigned twisted_block_wgs(const Geo &g, int d, unsig
   return (unsigned)((F.nb + lpw - 1) / lpw);
 }
 
-template <int D, bool TR = false>
+// W: a forced pass (the coefficients see the wall velocities)
+template <int D, bool TR = false, bool W = false>
 __device__ __forceinline__ void sweep2_body(const PassArgs &a, unsigned w, double *lds) {
   const Geo &g = a.g;
+  decltype(auto) u = SrcSel<W>::get(a);
   const Families F = families(g, D);
   const double hs = a.tau;
   const unsigned nbw = twisted_block_wgs(g, D, blockDim.x);
@@ -887,7 +889,7 @@ __device__ __forceinline__ void sweep2_body(const PassArgs &a, unsigned w, doubl
       twisted_block_line_T<D>(g, a.m, a.u, a.rhs, a.o, a.scb, F.nb, line, act, top, p, q, F.n, hs, lds,
                               (int)lane, a.status);
     else
-      twisted_block_line<D>(g, a.m, a.u, a.rhs, a.o, a.scb, F.nb, line, act, top, p, q, F.n, hs, lds,
+      twisted_block_line<D>(g, a.m, u, a.rhs, a.o, a.scb, F.nb, line, act, top, p, q, F.n, hs, lds,
                             (int)lane, a.status);
     return;
   }
@@ -909,7 +911,7 @@ __device__ __forceinline__ void sweep2_body(const PassArgs &a, unsigned w, doubl
       twisted_scalar_line_T<D, 0>(g, a.m, a.u, a.rhs, a.o, a.scs, ns, line, act, top, p, q, F.n, hs, lds,
                                   (int)lane, a.status);
     else
-      twisted_scalar_line<D, 0>(g, a.m, a.u, a.rhs, a.o, a.scs, ns, line, act, top, p, q, F.n, hs, lds,
+      twisted_scalar_line<D, 0>(g, a.m, u, a.rhs, a.o, a.scs, ns, line, act, top, p, q, F.n, hs, lds,
                                 (int)lane, a.status);
   } else {
     const long l3 = (long)(w2 - nwa) * lpw + lane;
@@ -920,7 +922,7 @@ __device__ __forceinline__ void sweep2_body(const PassArgs &a, unsigned w, doubl
       twisted_scalar_line_T<D, 1>(g, a.m, a.u, a.rhs, a.o, a.scs, ns, F.na + l3, act, top, p, q, F.n, hs, lds,
                                   (int)lane, a.status);
     else
-      twisted_scalar_line<D, 1>(g, a.m, a.u, a.rhs, a.o, a.scs, ns, F.na + l3, act, top, p, q, F.n, hs, lds,
+      twisted_scalar_line<D, 1>(g, a.m, u, a.rhs, a.o, a.scs, ns, F.na + l3, act, top, p, q, F.n, hs, lds,
                                 (int)lane, a.status);
   }
 }
@@ -934,6 +936,18 @@ __global__ void __launch_bounds__(256) DSW_OCC(DSW_WAVES_SWEEP) k_sweep2(PassArg
   } else {
     sweep2_body<D>(a, blockIdx.x, lds);
   }
+}
+
+// forced split step, one grid
+template <int D>
+__global__ void __launch_bounds__(256) DSW_OCC(DSW_WAVES_SWEEP) k_sweep2F(PassArgs a) {
+  __shared__ double lds[128 * 15];
+  sweep2_body<D, false, true>(a, blockIdx.x, lds);
+}
+
+void launch_sweep2_forced(int d, const PassArgs &a, unsigned blocks, unsigned threads, hipStream_t st) {
+  if (d == 0) hipLaunchKernelGGL(k_sweep2F<0>, dim3(blocks), dim3(threads), 0, st, a);
+  else hipLaunchKernelGGL(k_sweep2F<1>, dim3(blocks), dim3(threads), 0, st, a);
 }
 
 // transposed systems (adjoint), one grid
@@ -1001,7 +1015,10 @@ void launch_sweep_pass(int d, const PassArgs &a, const Batch &b, unsigned blocks
 }
 
 // boundary-normal faces: u_r on r = r1, r2; u_theta on the theta boundaries;
-// u_phi on the phi walls (sector only)
+// u_phi on the phi walls (sector only).  FORCED: d0 takes the Dirichlet data
+// of the new time level (rhs; src's own when rhs is unset), d1 and d2 the
+// midpoint of src's and those
+template <bool FORCED = false>
 __device__ __forceinline__ void bnd_body(const PassArgs &a, unsigned w) {
   const Geo &g = a.g;
   const long t = (long)w * blockDim.x + threadIdx.x;
@@ -1024,9 +1041,22 @@ __device__ __forceinline__ void bnd_body(const PassArgs &a, unsigned w) {
     return;
   }
   const double v = fsel(a.src, fid)[idx];
+  if constexpr (FORCED) {
+    const double vb = a.rhs.ur ? fsel(a.rhs, fid)[idx] : v, mid = 0.5 * (vb + v);
+    fsel(a.d0, fid)[idx] = vb;
+    fsel(a.d1, fid)[idx] = mid;
+    fsel(a.d2, fid)[idx] = mid;
+    return;
+  }
   if (a.d0.p) fsel(a.d0, fid)[idx] = v;
   if (a.d1.p) fsel(a.d1, fid)[idx] = v;
   if (a.d2.p) fsel(a.d2, fid)[idx] = v;
+}
+
+__global__ void __launch_bounds__(256) k_bnd_forced(PassArgs a) { bnd_body<true>(a, blockIdx.x); }
+
+void launch_bnd_forced(const PassArgs &a, unsigned blocks, unsigned threads, hipStream_t st) {
+  hipLaunchKernelGGL(k_bnd_forced, dim3(blocks), dim3(threads), 0, st, a);
 }
 
 template <bool B>

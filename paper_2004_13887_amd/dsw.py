@@ -29,7 +29,7 @@ SYMBOLS = ("dsw_init_grid", "dsw_free_grid", "dsw_layout", "dsw_residual", "dsw_
            "dsw_ensemble_tune", "dsw_ensemble_set_config", "dsw_ensemble_get_config",
            "dsw_ensemble_get_status", "dsw_adjoint_step", "dsw_line_solve_T_r",
            "dsw_line_solve_T_theta", "dsw_line_solve_T_phi", "dsw_line_vjp_r", "dsw_line_vjp_theta",
-           "dsw_line_vjp_phi", "dsw_residual_vjp", "dsw_last_error")
+           "dsw_line_vjp_phi", "dsw_residual_vjp", "dsw_split_step_forced", "dsw_last_error")
 TIMING_KINDS = ("residual", "sweep_r", "sweep_theta", "sweep_phi_update", "boundary_copy")
 
 
@@ -52,6 +52,14 @@ class Material(C.Structure):
 
 class Fields(C.Structure):
     _fields_ = [(n, C.c_void_p) for n in FIELDS]
+
+
+WALLS = ("ur_t1", "ur_t2", "ur_p1", "ur_p2", "ut_r1", "ut_r2", "ut_p1", "ut_p2",
+         "uf_r1", "uf_r2", "uf_t1", "uf_t2")
+
+
+class Wall(C.Structure):
+    _fields_ = [(n, C.c_void_p) for n in WALLS]
 
 
 class Config(C.Structure):
@@ -110,6 +118,7 @@ def lib():
         for n in ("dsw_line_vjp_r", "dsw_line_vjp_theta", "dsw_line_vjp_phi"):
             getattr(L, n).argtypes = [P, FP, D, FP, FP, FP, P]
         L.dsw_residual_vjp.argtypes = [P, FP, D, FP, FP, P]
+        L.dsw_split_step_forced.argtypes = [P, FP, FP, D, I, FP, C.POINTER(Wall), FP, P]
         L.dsw_last_error.restype = C.c_char_p
         for n in SYMBOLS[:-1]:
             getattr(L, n).restype = C.c_int
@@ -212,6 +221,41 @@ class Grid:
     def split_step(self, Un, Unp1, tau, K, stream=None):
         _check(lib().dsw_split_step(self._h, C.byref(_fields(Un)), C.byref(_fields(Unp1)),
                                     float(tau), int(K), _stream(stream)))
+
+    def split_step_forced(self, Un, Unp1, tau, K, src=None, wall=None, bnd=None, stream=None):
+        """dsw_split_step_forced: src (dict of five device arrays, a missing
+        one is zero), wall (dict of the WALLS arrays, a missing one is zero),
+        bnd (dict whose ur, ut, uf boundary-normal faces hold the new
+        Dirichlet data)."""
+        w = Wall()
+        if wall is not None:
+            for n in WALLS:
+                t = wall.get(n)
+                if t is not None:
+                    if not (t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
+                        raise ValueError(f"wall {n}: need a contiguous float64 device tensor")
+                    setattr(w, n, t.data_ptr())
+        fs = None
+        if src is not None:
+            fs = Fields()
+            for n in FIELDS:
+                t = src.get(n)
+                if t is not None:
+                    if not (t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
+                        raise ValueError(f"src {n}: need a contiguous float64 device tensor")
+                    setattr(fs, n, t.data_ptr())
+        fb = None
+        if bnd is not None:
+            fb = Fields()
+            for n in ("ur", "ut", "uf"):
+                t = bnd[n]
+                if not (t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
+                    raise ValueError(f"bnd {n}: need a contiguous float64 device tensor")
+                setattr(fb, n, t.data_ptr())
+        _check(lib().dsw_split_step_forced(
+            self._h, C.byref(_fields(Un)), C.byref(_fields(Unp1)), float(tau), int(K),
+            C.byref(fs) if fs is not None else None, C.byref(w) if wall is not None else None,
+            C.byref(fb) if fb is not None else None, _stream(stream)))
 
     def set_timing(self, enable=True):
         _check(lib().dsw_set_timing(self._h, 1 if enable else 0))

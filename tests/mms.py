@@ -173,6 +173,20 @@ class MMS:
         }
 
 
+def sources_interpolator(M, g, t0, t1, nodes=7):
+    """S(t) on [t0, t1] by polynomial interpolation of the exact sources at
+    Chebyshev nodes"""
+    k = np.arange(nodes)
+    ts = 0.5 * (t0 + t1) + 0.5 * (t1 - t0) * np.cos((2 * k + 1) * np.pi / (2 * nodes))
+    Ss = [M.sources(g, t) for t in ts]
+
+    def S(t):
+        w = np.array([np.prod([(t - ts[m]) / (ts[j] - ts[m]) for m in range(nodes) if m != j])
+                      for j in range(nodes)])
+        return {f: sum(w[j] * Ss[j][f] for j in range(nodes)) for f in Ss[0]}
+    return S
+
+
 def region_mask(g, key, frac=0.25):
     """points whose coordinates lie in the middle of the box (a fixed physical
     region, so that errors at different resolutions are comparable)"""

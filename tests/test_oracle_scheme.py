@@ -84,21 +84,8 @@ def test_converged_iteration_is_the_midpoint_scheme():
     assert np.max(np.abs(pack(spec, UK) - xn) / (np.abs(xn) + 1e-3)) < 1e-9
 
 
-def _sources_interpolator(M, g, t0, t1, nodes=7):
-    """S(t) by polynomial interpolation of exact sources at Chebyshev nodes"""
-    k = np.arange(nodes)
-    ts = 0.5 * (t0 + t1) + 0.5 * (t1 - t0) * np.cos((2 * k + 1) * np.pi / (2 * nodes))
-    Ss = [M.sources(g, t) for t in ts]
-
-    def S(t):
-        w = np.array([np.prod([(t - ts[m]) / (ts[j] - ts[m]) for m in range(nodes) if m != j])
-                      for j in range(nodes)])
-        return {f: sum(w[j] * Ss[j][f] for j in range(nodes)) for f in Ss[0]}
-    return S
-
-
 def run_mms(M, g, tau, nsteps, K, record=None):
-    S = _sources_interpolator(M, g, 0.0, tau * nsteps, nodes=3 if nsteps <= 10 else 7)
+    S = mms.sources_interpolator(M, g, 0.0, tau * nsteps, nodes=3 if nsteps <= 10 else 7)
     U = M.fields(g, 0.0)
     out = []
     for n in range(nsteps):
