@@ -12,7 +12,9 @@ HBM before the timed region.  Prints one JSON line.
 
 --sweeps measures the line solves alone and the split step's passes on the
 1024 x 512 x 64 sector; --adjoint the adjoint step against the forward step
-on the 256 x 128 x 64 sector.
+on the 256 x 128 x 64 sector; --forced the forced split step (source term,
+wall velocities, new Dirichlet data) against the plain one on the
+1024 x 512 x 64 sector.
 
 --ensemble measures the 64-member ensemble of uneven regional grids instead:
 the autotuner picks the launch shapes, then the batched step (one launch per
@@ -125,6 +127,8 @@ def main():
                     help="measure the adjoint step against the forward step instead")
     ap.add_argument("--sweeps", action="store_true",
                     help="measure the line solves and the split step's passes on the sweeps workload")
+    ap.add_argument("--forced", action="store_true",
+                    help="measure the forced split step against the plain one on the sweeps workload")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the library runs one "
@@ -135,6 +139,8 @@ def main():
         return bench_ensemble(args)
     if args.adjoint:
         return bench_adjoint(args)
+    if args.forced:
+        return bench_forced(args)
     if args.sweeps:
         return bench_sweeps(args)
 
@@ -376,6 +382,86 @@ def bench_sweeps(args):
         "line_solves": solves,
         "split_step_passes": passes,
         "split_step_model_GBps": model_bytes / (step_ms * 1e-3) / 1e9,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def bench_forced(args):
+    """sweeps workload (1024 x 512 x 64 sector: walls on every side), K = 3:
+    dsw_split_step_forced with a seeded source term, seeded wall velocities
+    on all twelve wall arrays and new Dirichlet data, against dsw_split_step
+    on the same grid; ms per step and grid-point updates/s of each"""
+    import numpy as np
+    import torch
+    from paper_2004_13887_amd import dsw
+    from paper_2004_13887_amd import inputs as I
+
+    w = I.WORKLOADS["sweeps"]
+    g = w.grid
+    log(f"[forced] generating {w.name}: {g.np}x{g.nt}x{g.nr} cells")
+    U0, tau = I.initial_state(w)
+    grid = dsw.Grid.from_spec(g, w.material)
+    if args.config:
+        grid.set_config(*(int(x) for x in args.config.split(",")))
+    rng = np.random.Generator(np.random.PCG64(200413899))
+    us = w.mach * 347.0
+    src = {"p": 1e-6 * np.mean(U0["p"]) / tau * rng.uniform(-1, 1, U0["p"].shape),
+           "ur": us / tau * rng.uniform(-1, 1, U0["ur"].shape),
+           "ut": us / tau * rng.uniform(-1, 1, U0["ut"].shape),
+           "uf": us / tau * rng.uniform(-1, 1, U0["uf"].shape),
+           "T": 1e-6 * np.mean(U0["T"]) / tau * rng.uniform(-1, 1, U0["T"].shape)}
+    shp = {"ur_t1": (g.nr + 1, g.np), "ur_t2": (g.nr + 1, g.np), "ur_p1": (g.nr + 1, g.nt),
+           "ur_p2": (g.nr + 1, g.nt), "ut_r1": (g.nt + 1, g.np), "ut_r2": (g.nt + 1, g.np),
+           "ut_p1": (g.nr, g.nt + 1), "ut_p2": (g.nr, g.nt + 1), "uf_r1": (g.nt, g.npf),
+           "uf_r2": (g.nt, g.npf), "uf_t1": (g.nr, g.npf), "uf_t2": (g.nr, g.npf)}
+    wall = {k: us * rng.uniform(-1, 1, s) for k, s in shp.items()}
+    bnd = {k: U0[k] + us * rng.uniform(-1, 1, U0[k].shape) for k in ("ur", "ut", "uf")}
+    dsrc, dwall, dbnd = dsw.to_device(src), dsw.to_device(wall), dsw.to_device(bnd)
+    del src, bnd
+    A, B = dsw.to_device(U0), grid.empty()
+    stream = torch.cuda.current_stream()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+    def run(forced):
+        X, Y = A, B
+        for n in range(args.warmup + args.steps):
+            if n == args.warmup:
+                torch.cuda.synchronize()
+                ev0.record(stream)
+            if forced:
+                grid.split_step_forced(X, Y, tau, w.K, src=dsrc, wall=dwall, bnd=dbnd, stream=stream)
+            else:
+                grid.split_step(X, Y, tau, w.K, stream)
+            X, Y = Y, X
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        grid.get_status()
+        return ev0.elapsed_time(ev1) / args.steps
+
+    U0d = dsw.to_device(U0)
+    plain_ms = run(False)
+    for k in A:
+        A[k].copy_(U0d[k])
+    forced_ms = run(True)
+    log(f"[forced] plain {plain_ms:.3f} ms, forced {forced_ms:.3f} ms per step")
+    out = {
+        "metric": "grid-point updates/s per forced split step (FP64)",
+        "value": g.ncells / (forced_ms * 1e-3),
+        "unit": "grid-point updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": forced_ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "forced: 1024 (phi) x 512 (theta) x 64 (r) sector, 100 m horizontal, K=3, "
+                               "Mach 1e-6, seeded source, wall velocities and Dirichlet data",
+                   "cells": g.ncells, "K": w.K},
+        "plain": {"ms_per_step": plain_ms, "value": g.ncells / (plain_ms * 1e-3)},
+        "forced_over_plain": forced_ms / plain_ms,
     }
     print(json.dumps(out), flush=True)
 

@@ -99,10 +99,24 @@ struct SrcW {
   __device__ __forceinline__ double ld(int fid, long x) const { return a[fid][x]; }
 };
 
+// A forced source for the interior residual launch (every r and theta
+// neighbour inside the arrays): ghosts only across phi walls (P: periodic)
+template <bool P>
+struct SrcInW {
+  const double *a[5];
+  Wall w;
+  const double *f[5];
+  static constexpr bool INTERIOR = true;
+  static constexpr bool PERIODIC = P;
+  static constexpr bool WALL = true;
+  __device__ __forceinline__ double ld(int fid, long x) const { return a[fid][x]; }
+};
+
 // Velocity ghosts of a forced source: across a wall 2 g - u (g the wall's
 // tangential velocity), the phi wall first, then the theta or r wall; across
 // a pole the symmetry ghosts of the plain rules.
-__device__ __forceinline__ double gR_wall(const Geo &g, const SrcW &s, int f, int j, int k) {
+template <class S>
+__device__ __forceinline__ double gR_wall(const Geo &g, const S &s, int f, int j, int k) {
   double sg = 1.0, add = 0.0;
   if (k < 0 || k >= g.np) {
     if (g.periodic) k = wrapk(g, k);
@@ -120,7 +134,8 @@ __device__ __forceinline__ double gR_wall(const Geo &g, const SrcW &s, int f, in
   }
   return add + sg * s.ld(F_UR, idx_r(g, f, j, k));
 }
-__device__ __forceinline__ double gT_wall(const Geo &g, const SrcW &s, int i, int f, int k) {
+template <class S>
+__device__ __forceinline__ double gT_wall(const Geo &g, const S &s, int i, int f, int k) {
   double sg = 1.0, add = 0.0;
   if (k < 0 || k >= g.np) {
     if (g.periodic) k = wrapk(g, k);
@@ -133,7 +148,8 @@ __device__ __forceinline__ double gT_wall(const Geo &g, const SrcW &s, int i, in
   else if (i >= g.nr) { add += sg * 2.0 * wallv(s.w.ut_r2, (long)f * g.np + k); sg = -sg; i = g.nr - 1; }
   return add + sg * s.ld(F_UT, idx_t(g, i, f, k));
 }
-__device__ __forceinline__ double gF_wall(const Geo &g, const SrcW &s, int i, int j, int f) {
+template <class S>
+__device__ __forceinline__ double gF_wall(const Geo &g, const S &s, int i, int j, int f) {
   double sg = 1.0, add = 0.0;
   if (g.periodic) f = wrapk(g, f);
   if (j < 0 || j >= g.nt) {
@@ -165,6 +181,7 @@ __device__ __forceinline__ double gR(const Geo &g, const S &s, int f, int j, int
     if constexpr (S::PERIODIC) return s.ld(F_UR, (f * g.nt + j) * g.np + wrapk(g, k));
     const int kk = clampi(k, 0, g.np - 1);
     const double v = s.ld(F_UR, (f * g.nt + j) * g.np + kk);
+    if constexpr (S::WALL) return kk == k ? v : 2.0 * wallv(k < 0 ? s.w.ur_p1 : s.w.ur_p2, (long)f * g.nt + j) - v;
     return kk == k ? v : -v;
   }
   if constexpr (S::WALL) return gR_wall(g, s, f, j, k);
@@ -184,6 +201,7 @@ __device__ __forceinline__ double gT(const Geo &g, const S &s, int i, int f, int
     if constexpr (S::PERIODIC) return s.ld(F_UT, (i * (g.nt + 1) + f) * g.np + wrapk(g, k));
     const int kk = clampi(k, 0, g.np - 1);
     const double v = s.ld(F_UT, (i * (g.nt + 1) + f) * g.np + kk);
+    if constexpr (S::WALL) return kk == k ? v : 2.0 * wallv(k < 0 ? s.w.ut_p1 : s.w.ut_p2, (long)i * (g.nt + 1) + f) - v;
     return kk == k ? v : -v;
   }
   if constexpr (S::WALL) return gT_wall(g, s, i, f, k);

@@ -443,17 +443,13 @@ __global__ void __launch_bounds__(256) DSW_OCC(DSW_WAVES_PHI) k_phi_part(PassArg
   }
 }
 
-// forced split step, one grid, all three lines of a slot in one launch
-template <int PM>
+// forced split step, one grid: as the plain sweep, all three lines of a slot
+// in one launch, or from PHI_SPLIT_SLOTS slots on the block lines and the
+// scalar lines as two
+template <int PM, int PART>
 __global__ void __launch_bounds__(256) DSW_OCC(DSW_WAVES_PHI) k_phi_partF(PassArgs a) {
   extern __shared__ double lds[];
-  phi_body<PM, false, 2, true>(a, blockIdx.x, lds);
-}
-
-void launch_phi_forced(int pm, const PassArgs &a, unsigned blocks, unsigned threads, size_t lds,
-                       hipStream_t st) {
-  if (pm == 2) hipLaunchKernelGGL(k_phi_partF<2>, dim3(blocks), dim3(threads), lds, st, a);
-  else hipLaunchKernelGGL(k_phi_partF<4>, dim3(blocks), dim3(threads), lds, st, a);
+  phi_body<PM, false, PART, true>(a, blockIdx.x, lds);
 }
 
 // transposed systems (adjoint), one grid: each chunk walks the rows of the
@@ -537,6 +533,22 @@ void launch_phi_pass(int pm, const PassArgs &a, const Batch &b, unsigned blocks,
       hipLaunchKernelGGL((k_phi_part<4, false, 0>), gr, bl, lds, st, a, b);
       hipLaunchKernelGGL((k_phi_part<4, false, 1>), gr, bl, lds_s, st, a, b);
     }
+  }
+}
+
+void launch_phi_forced(int pm, const PassArgs &a, unsigned blocks, unsigned threads, size_t lds,
+                       hipStream_t st) {
+  const dim3 gr(blocks), bl(threads);
+  const size_t lds_s = sizeof(double) * (size_t)(pm > 5 ? pm : 5) * threads;
+  if (blocks < PHI_SPLIT_SLOTS) {
+    if (pm == 2) hipLaunchKernelGGL((k_phi_partF<2, 2>), gr, bl, lds, st, a);
+    else hipLaunchKernelGGL((k_phi_partF<4, 2>), gr, bl, lds, st, a);
+  } else if (pm == 2) {
+    hipLaunchKernelGGL((k_phi_partF<2, 0>), gr, bl, lds, st, a);
+    hipLaunchKernelGGL((k_phi_partF<2, 1>), gr, bl, lds_s, st, a);
+  } else {
+    hipLaunchKernelGGL((k_phi_partF<4, 0>), gr, bl, lds, st, a);
+    hipLaunchKernelGGL((k_phi_partF<4, 1>), gr, bl, lds_s, st, a);
   }
 }
 

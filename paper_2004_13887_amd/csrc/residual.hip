@@ -199,8 +199,7 @@ __host__ __device__ inline unsigned res_interior_blocks(const Geo &g, int bs) {
   return (unsigned)res_nk(g, bs) * (unsigned)(g.nt - 2) * (unsigned)(g.nr - 2);
 }
 
-// W: a forced pass (wall velocities and source term; no interior launch, so
-// this one covers every point)
+// W: a forced pass (wall velocities and source term)
 template <bool W = false>
 __device__ __forceinline__ void residual_body(const PassArgs &a, unsigned w) {
   const Geo &g = a.g;
@@ -210,7 +209,7 @@ __device__ __forceinline__ void residual_body(const PassArgs &a, unsigned w) {
   const int bs = (int)blockDim.x;
   const bool interior = res_interior_blocks(g, bs) > 0 && i >= 1 && i <= g.nr - 2 && j >= 1 &&
                         j <= g.nt - 2;
-  if (!W && interior) return;  // done by the interior launch
+  if (interior) return;  // done by the interior launch
   decltype(auto) s = SrcSel<W>::get(a);
   residual_point<std::decay_t<decltype(s)>, false>(g, a.m, s, a.d, a.tau, a.R, Fields{}, a.status, i, j,
                                                    (int)(kb * blockDim.x + threadIdx.x));
@@ -226,6 +225,11 @@ __device__ __forceinline__ void residual_body_in(const PassArgs &a, unsigned w) 
   SI s;
 #pragma unroll
   for (int q = 0; q < 5; q++) s.a[q] = a.u.a[q];
+  if constexpr (SI::WALL) {
+    s.w = a.wall;
+    s.f[F_P] = a.fsrc.p; s.f[F_UR] = a.fsrc.ur; s.f[F_UT] = a.fsrc.ut; s.f[F_UF] = a.fsrc.uf;
+    s.f[F_T] = a.fsrc.T;
+  }
   residual_point<SI, false>(g, a.m, s, a.d, a.tau, a.R, Fields{}, a.status, i, j,
                             (int)(kb * blockDim.x + threadIdx.x));
 }
@@ -240,10 +244,20 @@ __global__ void __launch_bounds__(256) DSW_OCC(DSW_WAVES_RES) k_residual(PassArg
   }
 }
 
-// forced split step: one grid, every point
+// forced split step, one grid: the interior workgroups (P: periodic), then
+// the rest
+template <bool P>
+__global__ void __launch_bounds__(256) k_residual_in_forced(PassArgs a) {
+  residual_body_in<SrcInW<P>>(a, blockIdx.x);
+}
 __global__ void __launch_bounds__(256) k_residual_forced(PassArgs a) { residual_body<true>(a, blockIdx.x); }
 
 void launch_residual_forced(const PassArgs &a, unsigned blocks, unsigned threads, hipStream_t st) {
+  const unsigned nin = res_interior_blocks(a.g, (int)threads);
+  if (nin) {
+    if (a.g.periodic) hipLaunchKernelGGL(k_residual_in_forced<true>, dim3(nin), dim3(threads), 0, st, a);
+    else hipLaunchKernelGGL(k_residual_in_forced<false>, dim3(nin), dim3(threads), 0, st, a);
+  }
   hipLaunchKernelGGL(k_residual_forced, dim3(blocks), dim3(threads), 0, st, a);
 }
 
