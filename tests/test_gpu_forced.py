@@ -10,6 +10,8 @@ eq. (man_sol)):
   t = 1e-3, M0 = 1e-2 and 1e-4; at 1e-4 the pressure converges at second
   order in the central region, near-wall errors dominate the whole box on
   these grids);
+* the time convergence rate by inverse Richardson extrapolation (Tables 1
+  and 2: tau = 2e-3, 1e-3, 5e-4, M0 = 1e-2 and 1e-4);
 * the incompressible limit (Table 3: tau = 1e-3, grid diameter 0.12,
   max (p - p0)/p0 after 1, 50, 100 steps against the closed form
   (2 + sin 5t) gamma M0^2 and the printed values, over the cells off the
@@ -102,8 +104,9 @@ def _mms_grid(dsw, nr, nt, np_):
     return spec, gg, oracle.Grid(*spec.args())
 
 
-def _run_mms_gpu(dsw, gg, og, M, tau, nsteps, K, nodes, record=(), progress=None):
-    S = mms.sources_interpolator(M, og, 0.0, tau * nsteps, nodes=nodes)
+def _run_mms_gpu(dsw, gg, og, M, tau, nsteps, K, nodes, record=(), progress=None, S=None):
+    if S is None:
+        S = mms.sources_interpolator(M, og, 0.0, tau * nsteps, nodes=nodes)
     U = dsw.to_device(M.fields(og, 0.0))
     V = gg.empty()
     out = {}
@@ -221,6 +224,46 @@ def test_table3_incompressible_limit_gpu(mach, dsw):
         else:  # the printed values drift above the closed form too
             assert abs(dp - exact) < 0.04 * exact, (n, dp, exact)
             assert abs(dp - printed[n]) < 0.045 * printed[n], (n, dp, printed[n])
+
+
+@pytest.mark.parametrize("mach", [1e-2, 1e-4])
+def test_time_convergence_rate_gpu(mach, dsw):
+    """Tables 1-2 (inverse Richardson extrapolation): TCR(u, tau) =
+    log2(|u^tau - u^(tau/2)| / |u^(tau/2) - u^(tau/4)|) (l2 over the
+    unknowns) for tau = 2e-3, 1e-3, 5e-4, every field, K = 2, 8 x 16 x 48
+    cells, final time 0.064 (the paper states neither grid nor final time).
+    The paper's values scatter between 1.4 and 3.2 and are read as second
+    order.  Here the smallest tau gives about 2 for every field at
+    M0 = 1e-2 (asserted within [1.7, 2.4]); at M0 = 1e-4 the pressure and
+    temperature give about 2 and the velocities, whose tau^2 error constant
+    is small there, stay near 3 (asserted within [1.7, 3.5]); the larger
+    tau scatter as the paper's do (asserted within [1.0, 4.2])."""
+    M = mms.MMS(mach, I.MMS)
+    spec, gg, og = _mms_grid(dsw, 8, 16, 48)
+    tf = 0.064
+    S = mms.sources_interpolator(M, og, 0.0, tf, nodes=9)
+    sol = {}
+    for q in range(5):
+        tau = 2e-3 / 2 ** q
+        n = int(round(tf / tau))
+        print(f"[tcr M0={mach}] tau={tau:.3e}, {n} steps", flush=True)
+        sol[q], _ = _run_mms_gpu(dsw, gg, og, M, tau, n, 2, nodes=None, S=S)
+    for q in range(3):
+        tcr = {}
+        for k in KEYS:
+            m = mms.unknown_mask(og, k)
+            a = np.linalg.norm((sol[q][k] - sol[q + 1][k])[m])
+            b = np.linalg.norm((sol[q + 1][k] - sol[q + 2][k])[m])
+            tcr[k] = math.log2(a / b)
+        print(f"  tau={2e-3 / 2 ** q:.0e}: " + " ".join(f"{k}={v:.2f}" for k, v in tcr.items()), flush=True)
+        for k, v in tcr.items():
+            if q < 2:
+                lo, hi = 1.0, 4.2
+            elif mach >= 1e-2 or k in ("p", "T"):
+                lo, hi = 1.7, 2.4
+            else:
+                lo, hi = 1.7, 3.5
+            assert lo < v < hi, (q, k, v)
 
 
 def test_forced_step_rejects_bad_arguments(dsw):
