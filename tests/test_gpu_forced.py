@@ -98,6 +98,49 @@ def test_forced_step_parity_random(name, dsw):
     assert max(e.values()) <= 1e-13
 
 
+EDGE = [
+    # (case, K, which forcing inputs)
+    ("sector", 1, ("src", "wall", "bnd")),
+    ("sector-ragged", 2, ("src",)),
+    ("sector", 2, ("wall",)),
+    ("sector-ragged", 2, ("bnd",)),
+    ("sector-min", 3, ("src", "wall", "bnd")),
+    ("sphere-chunks2", 2, ("src", "wall", "bnd")),
+]
+EDGE_GRIDS = {"sector-min": I.sector(3, 3, 3, 0.01, 0.01), "sphere-chunks2": I.full_sphere(4, 5, 8)}
+
+
+@pytest.mark.parametrize("name,K,which", EDGE, ids=[f"{c}-K{k}-{'+'.join(w)}" for c, k, w in EDGE])
+def test_forced_step_parity_edges(name, K, which, dsw):
+    """K = 1, one forcing input at a time, the smallest grids"""
+    spec = CASES.get(name) or EDGE_GRIDS[name]
+    print(f"[forced edge] {name} K={K} {'+'.join(which)}", flush=True)
+    gg, og, om = _grid(dsw, spec, I.AIR)
+    U0, tau = random_state(spec, 311, mach=0.05)
+    src, wall, bnd = _forcing(spec, U0, 312)
+    kw_o = {"src": src, "wall": wall, "bnd": bnd}
+    kw_o = {k: v for k, v in kw_o.items() if k in which}
+    ref = oracle.split_step(og, om, U0, tau, K, **kw_o)
+    out = gg.empty()
+    gg.split_step_forced(dsw.to_device(U0), out, tau, K, **{k: dsw.to_device(v) for k, v in kw_o.items()})
+    torch.cuda.synchronize()
+    gg.get_status()
+    e = compare(f"{name} forced edge", dsw.to_host(out), ref, base=U0)
+    assert max(e[k] for k in KEYS) <= TOL
+
+
+def test_forced_step_needs_partitioned_phi_lines(dsw):
+    """a full sphere of 3 phi cells: no power-of-two chunk count, DSW_EINVAL
+    (the plain step takes such grids with one thread per line)"""
+    spec = I.full_sphere(3, 3, 3)
+    gg, _, _ = _grid(dsw, spec, I.AIR)
+    U0, tau = random_state(spec, 313)
+    out = gg.empty()
+    with pytest.raises(dsw.DswError) as ei:
+        gg.split_step_forced(dsw.to_device(U0), out, tau, 2)
+    assert ei.value.code == dsw.DSW_EINVAL
+
+
 def _mms_grid(dsw, nr, nt, np_):
     spec = I.GridSpec(nr, nt, np_, *mms.DOMAIN)
     gg = dsw.Grid.from_spec(spec, I.MMS)
