@@ -5,6 +5,9 @@ benchmark times, on sampled outputs the oracle computes one by one:
   boundary, at the poles and the periodic seam);
 * line solves r, theta, phi: sampled lines of every family (first, last,
   middle, random), each solved by the oracle from the same seeded inputs;
+* transposed line solves (the adjoint's): <M_d^-T y, b> = <y, M_d^-1 b> on
+  the whole grid, an identity at any size whose forward side is the solve
+  pinned above;
 * properties of the whole step that hold at any size: phi-shift equivariance
   on the full sphere (exercises the cyclic solves) and the discretely
   hydrostatic rest state.
@@ -18,7 +21,7 @@ from paper_2004_13887_amd import inputs as I
 
 pytestmark = pytest.mark.gpu
 TOL = 1e-11
-FULL = ["global", "sweeps"]
+FULL = ["global", "sweeps", "adjoint"]
 
 
 @pytest.fixture(scope="module")
@@ -137,6 +140,39 @@ def test_full_line_solve_sampled(name, d, dsw):
         print(f"{name} x{d}[{k}] sampled rel err = {e:.3e} ({m.sum()} values)", flush=True)
         worst = max(worst, e)
     assert worst <= TOL
+
+
+@pytest.mark.parametrize("d", [0, 1, 2])
+@pytest.mark.parametrize("name", ["global", "adjoint"])
+def test_full_transposed_line_solve_identity(name, d, dsw):
+    w, U0, tau, og, om, gg = setup(name, dsw)
+    rng = np.random.Generator(np.random.PCG64(51 + d))
+    b = {k: rng.uniform(-1.0, 1.0, s) for k, s in w.grid.shapes().items()}
+    y = {k: rng.uniform(-1.0, 1.0, s) for k, s in w.grid.shapes().items()}
+    for k, m in (("ur", (0, -1)), ("ut", (0, -1))):  # boundary-normal faces are not unknowns
+        for q in m:
+            if k == "ur":
+                b[k][q] = 0.0
+                y[k][q] = 0.0
+            else:
+                b[k][:, q] = 0.0
+                y[k][:, q] = 0.0
+    if not w.grid.periodic:
+        for q in (0, -1):
+            b["uf"][:, :, q] = 0.0
+            y["uf"][:, :, q] = 0.0
+    Ub = dsw.to_device(U0)
+    x, xT = gg.empty(), gg.empty()
+    gg.line_solve(d, Ub, tau, dsw.to_device(b), x)
+    gg.line_solve_T(d, Ub, tau, dsw.to_device(y), xT)
+    torch.cuda.synchronize()
+    gg.get_status()
+    xh, xTh = dsw.to_host(x), dsw.to_host(xT)
+    lhs = float(sum(np.dot(np.ravel(xTh[k]), np.ravel(b[k])) for k in b))
+    rhs = float(sum(np.dot(np.ravel(y[k]), np.ravel(xh[k])) for k in b))
+    e = abs(lhs - rhs) / max(abs(lhs), abs(rhs))
+    print(f"{name} d={d}: <M^-T y, b> = {lhs:.15e}, <y, M^-1 b> = {rhs:.15e}, rel {e:.2e}", flush=True)
+    assert e <= TOL
 
 
 def test_full_global_phi_shift_equivariance(dsw):
