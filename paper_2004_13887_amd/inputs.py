@@ -269,6 +269,75 @@ def initial_state(w: Workload):
     return fields, tau
 
 
+# ------------------------------------------------ rising thermal bubble --
+
+def thermal1_grid(nr=100, nt=200, np_=200) -> GridSpec:
+    """The paper's "Thermal 1" domain (section "Rising thermal bubble"):
+    r in [6371, 6381] km, theta in pi/2 +- 10/6371, phi in pi +- 10/6371
+    (20 km x 20 km x 10 km); 100 x 200 x 200 MAC cells by default."""
+    half = 10.0e3 / EARTH_R1
+    return GridSpec(nr, nt, np_, EARTH_R1, EARTH_R1 + SHELL_DEPTH, math.pi / 2 - half,
+                    math.pi / 2 + half, math.pi - half, math.pi + half, False)
+
+
+def exner_column(g: GridSpec, mat: MaterialSpec, theta0: float = T0):
+    """Discretely hydrostatic column at constant potential temperature
+    theta0: centre pressures p_i with T_i = theta0 (p_i / p00)^(R/c_p) and
+    p_i (1 + g dr / (2 R T_i)) = p_{i-1} (1 - g dr / (2 R T_{i-1})) (the u_r
+    equation at rest with the face density the mean of the two centres); the
+    first centre from the continuous profile pi = 1 - g z / (c_p theta0) half a
+    cell above r1, where p = p00.  Returns (p, T) of the column."""
+    dr = (g.r2 - g.r1) / g.nr
+    kap = mat.R / mat.cp
+    c = mat.g_r * dr / (2.0 * mat.R)
+    p = np.empty(g.nr)
+    T = np.empty(g.nr)
+    p[0] = P00 * (1.0 - mat.g_r * 0.5 * dr / (mat.cp * theta0)) ** (1.0 / kap)
+    T[0] = theta0 * (p[0] / P00) ** kap
+    for i in range(1, g.nr):
+        top = p[i - 1] * (1.0 - c / T[i - 1])
+        pi_ = top / (1.0 + c / T[i - 1])
+        for _ in range(50):  # fixed point in T_i (contraction factor ~ g dr / (R T))
+            Ti = theta0 * (pi_ / P00) ** kap
+            nxt = top / (1.0 + c / Ti)
+            if nxt == pi_:
+                break
+            pi_ = nxt
+        p[i] = pi_
+        T[i] = theta0 * (p[i] / P00) ** kap
+    return p, T
+
+
+def thermal1_state(g: GridSpec, mat: MaterialSpec = AIR, theta0: float = T0, amplitude: float = 2.0,
+                   radius: float = 2.0e3, height: float = 2.0e3, theta_c: float = math.pi / 2,
+                   phi_c: float = math.pi):
+    """Thermal 1 initial state: fluid at rest in the column of exner_column,
+    the potential temperature raised by 2 cos^2(pi L / 2) where L (the chord
+    distance to the centre, 2 km above r1, over R = 2 km) is <= 1, the
+    pressure unchanged (T = (theta0 + dTheta) (p / p00)^(R/c_p))."""
+    c = coords(g)
+    sh = g.shapes()
+    pcol, _ = exner_column(g, mat, theta0)
+    rb = g.r1 + height
+    xb = rb * math.sin(theta_c) * math.cos(phi_c)
+    yb = rb * math.sin(theta_c) * math.sin(phi_c)
+    zb = rb * math.cos(theta_c)
+    r3 = c["rc"][:, None, None]
+    st, ct = np.sin(c["tc"])[None, :, None], np.cos(c["tc"])[None, :, None]
+    sp, cp = np.sin(c["pc"])[None, None, :], np.cos(c["pc"])[None, None, :]
+    L = np.sqrt((r3 * st * cp - xb) ** 2 + (r3 * st * sp - yb) ** 2 + (r3 * ct - zb) ** 2) / radius
+    dth = np.where(L <= 1.0, amplitude * np.cos(0.5 * math.pi * L) ** 2, 0.0)
+    exner = ((pcol / P00) ** (mat.R / mat.cp))[:, None, None]
+    fields = {"p": np.broadcast_to(pcol[:, None, None], sh["p"]), "ur": np.zeros(sh["ur"]),
+              "ut": np.zeros(sh["ut"]), "uf": np.zeros(sh["uf"]), "T": (theta0 + dth) * exner}
+    return {k: np.ascontiguousarray(v, dtype=np.float64) for k, v in fields.items()}
+
+
+def potential_temperature_excess(g: GridSpec, U, mat: MaterialSpec = AIR, theta0: float = T0):
+    """Theta - theta0 at the cell centres, Theta = T / (p / p00)^(R/c_p)."""
+    return U["T"] / (U["p"] / P00) ** (mat.R / mat.cp) - theta0
+
+
 def random_fields(g: GridSpec, seed: int, base=None, scale=1.0):
     """Random perturbation fields (for line-solve tests): base + scale * U[-1,1]
     at every unknown, 0 on boundary-normal faces."""
