@@ -333,6 +333,35 @@ def thermal1_state(g: GridSpec, mat: MaterialSpec = AIR, theta0: float = T0, amp
     return {k: np.ascontiguousarray(v, dtype=np.float64) for k, v in fields.items()}
 
 
+def thermal2_grid(nr=200, nt=200, np_=200) -> GridSpec:
+    """The paper's "Thermal 2" domain (section "Rising thermal bubble"): a
+    1 km cube, theta in pi/2 +- 0.5/6371, phi in pi +- 0.5/6371, r from
+    6371 km up by 1 km (the printed radial interval is garbled; 1 km is the
+    span the cube and the bubble imply); 200^3 MAC cells by default."""
+    half = 0.5e3 / EARTH_R1
+    return GridSpec(nr, nt, np_, EARTH_R1, EARTH_R1 + 1.0e3, math.pi / 2 - half, math.pi / 2 + half,
+                    math.pi - half, math.pi + half, False)
+
+
+def thermal2_state(g: GridSpec, mat: MaterialSpec = AIR, theta0: float = T0):
+    """Thermal 2 initial state: as thermal1_state with the perturbation
+    (1 + cos(pi L)) / 4 K for L <= 1, R = 250 m, centred 260 m above r1."""
+    c = coords(g)
+    sh = g.shapes()
+    pcol, _ = exner_column(g, mat, theta0)
+    rb = g.r1 + 260.0
+    xb, yb, zb = -rb, 0.0, 0.0  # theta = pi/2, phi = pi
+    r3 = c["rc"][:, None, None]
+    st, ct = np.sin(c["tc"])[None, :, None], np.cos(c["tc"])[None, :, None]
+    sp, cp = np.sin(c["pc"])[None, None, :], np.cos(c["pc"])[None, None, :]
+    L = np.sqrt((r3 * st * cp - xb) ** 2 + (r3 * st * sp - yb) ** 2 + (r3 * ct - zb) ** 2) / 250.0
+    dth = np.where(L <= 1.0, 0.25 * (1.0 + np.cos(math.pi * L)), 0.0)
+    exner = ((pcol / P00) ** (mat.R / mat.cp))[:, None, None]
+    fields = {"p": np.broadcast_to(pcol[:, None, None], sh["p"]), "ur": np.zeros(sh["ur"]),
+              "ut": np.zeros(sh["ut"]), "uf": np.zeros(sh["uf"]), "T": (theta0 + dth) * exner}
+    return {k: np.ascontiguousarray(v, dtype=np.float64) for k, v in fields.items()}
+
+
 def potential_temperature_excess(g: GridSpec, U, mat: MaterialSpec = AIR, theta0: float = T0):
     """Theta - theta0 at the cell centres, Theta = T / (p / p00)^(R/c_p)."""
     return U["T"] / (U["p"] / P00) ** (mat.R / mat.cp) - theta0
