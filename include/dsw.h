@@ -35,8 +35,8 @@
  *
  * Return codes: DSW_OK (0) or a negative DSW_E* code; dsw_last_error() gives
  * a thread-local message.  Device-side conditions (a vanishing pivot, a
- * non-positive temperature or p + pi_inf) set a status word read by
- * dsw_get_status().
+ * non-positive temperature or p + pi_inf, a non-finite residual) set a
+ * status word read by dsw_get_status().
  */
 #ifndef DSW_H
 #define DSW_H
@@ -51,8 +51,10 @@ extern "C" {
 #define DSW_EINVAL (-1)    /* invalid argument or descriptor               */
 #define DSW_ENOMEM (-2)    /* device allocation failed                     */
 #define DSW_EHIP (-3)      /* a HIP runtime call failed                    */
-#define DSW_ENONPHYS (-4)  /* T <= 0 or p + pi_inf <= 0 met on the device  */
+#define DSW_ENONPHYS (-4)  /* finite T <= 0 or p + pi_inf <= 0 met         */
 #define DSW_ESINGULAR (-5) /* zero pivot in a line solve                   */
+#define DSW_EDIVERGED (-6) /* non-finite residual: the iteration diverged, or
+                              the state holds a NaN or an infinity          */
 
 /* Grid: n_r x n_theta x n_phi cells on [r1,r2] x [theta1,theta2] x [phi1,phi2]
  * (paper section 2.1, domain Omega).  Uniform spacing in r, theta and phi.
@@ -275,7 +277,9 @@ int dsw_ensemble_get_config(const dsw_ensemble *ens, dsw_config *cfg);
 int dsw_ensemble_get_status(dsw_ensemble *ens, void *stream);
 
 /* Synchronise the stream, read and clear the device status word.  Returns
- * DSW_OK, DSW_ENONPHYS or DSW_ESINGULAR (or DSW_EHIP). */
+ * DSW_OK, or the first of DSW_ENONPHYS, DSW_EDIVERGED, DSW_ESINGULAR that
+ * was met (or DSW_EHIP).  A non-finite residual ranks before a singular
+ * pivot: the line solves that follow it meet non-finite pivots too. */
 int dsw_get_status(dsw_grid *grid, void *stream);
 
 /* Thread-local description of the last error (never NULL). */

@@ -619,7 +619,10 @@ extern "C" int dsw_get_status(dsw_grid *G, void *stream) {
   int h[ST_WORDS];
   HIPCHK(hipMemcpy(h, G->status, sizeof(h), hipMemcpyDeviceToHost));
   HIPCHK(hipMemset(G->status, 0, sizeof(h)));
-  if (h[ST_NONPHYS]) return fail(DSW_ENONPHYS, "non-positive temperature or pressure met");
+  if (h[ST_NONPHYS]) return fail(DSW_ENONPHYS, "non-positive temperature or pressure met");  // the cause of what follows
+  // a non-finite residual comes first: the line solves that follow it see
+  // non-finite pivots as well
+  if (h[ST_DIVERGED]) return fail(DSW_EDIVERGED, "non-finite residual (diverged iteration or a NaN/Inf in the state)");
   if (h[ST_SINGULAR]) return fail(DSW_ESINGULAR, "zero pivot in a line solve");
   return DSW_OK;
 }

@@ -22,7 +22,7 @@ namespace dsw {
 #define DSW_OCC(w) __attribute__((amdgpu_waves_per_eu((w) > 0 ? (w) : 1)))
 
 // device status words, each set by plain stores of 1 (no atomics)
-enum { ST_NONPHYS = 0, ST_SINGULAR = 1, ST_WORDS = 2 };
+enum { ST_NONPHYS = 0, ST_SINGULAR = 1, ST_DIVERGED = 2, ST_WORDS = 3 };
 
 struct Fields {
   double *p, *ur, *ut, *uf, *T;

@@ -146,32 +146,45 @@ __device__ __forceinline__ void residual_point(const Geo &g, const Mat &m, const
                                                int *status, int i, int j, int k) {
   if (k >= g.npf) return;
   const bool kc = k < g.np;
+  double chk = 0.0; // the sum of this point's residuals: non-finite iff one of them is
   if (i < g.nr && j < g.nt && kc) { // cell centre
     const long x = idx_c(g, i, j, k);
     const double ubp = s.ld(F_P, x), ubT = s.ld(F_T, x);
     if (WRITE_UB) { Ub.p[x] = ubp; Ub.T[x] = ubT; }
-    if (!(ubT > 0.0) || !(ubp + m.pinf > 0.0)) status[ST_NONPHYS] = 1; // plain vector store
+    // finite and non-positive; a NaN or an infinity shows as a non-finite
+    // residual below
+    if (ubT <= 0.0 || ubp + m.pinf <= 0.0) status[ST_NONPHYS] = 1; // plain vector store
     double FT;
     const double Fp = F_p_T(g, m, s, i, j, k, &FT);
-    R.p[x] = -dU.at(F_P, x) - tau * forced(s, F_P, x, Fp);
-    R.T[x] = -dU.at(F_T, x) - tau * forced(s, F_T, x, FT);
+    const double rp = -dU.at(F_P, x) - tau * forced(s, F_P, x, Fp);
+    const double rT = -dU.at(F_T, x) - tau * forced(s, F_T, x, FT);
+    R.p[x] = rp;
+    R.T[x] = rT;
+    chk = rp + rT;
   }
   if (j < g.nt && kc) { // r face i
     const long x = idx_r(g, i, j, k);
     if (WRITE_UB) Ub.ur[x] = s.ld(F_UR, x);
-    R.ur[x] = (i >= 1 && i < g.nr) ? -dU.at(F_UR, x) - tau * forced(s, F_UR, x, F_ur(g, m, s, i, j, k)) : 0.0;
+    const double r = (i >= 1 && i < g.nr) ? -dU.at(F_UR, x) - tau * forced(s, F_UR, x, F_ur(g, m, s, i, j, k)) : 0.0;
+    R.ur[x] = r;
+    chk += r;
   }
   if (i < g.nr && kc) { // theta face j
     const long x = idx_t(g, i, j, k);
     if (WRITE_UB) Ub.ut[x] = s.ld(F_UT, x);
-    R.ut[x] = (j >= 1 && j < g.nt) ? -dU.at(F_UT, x) - tau * forced(s, F_UT, x, F_ut(g, m, s, i, j, k)) : 0.0;
+    const double r = (j >= 1 && j < g.nt) ? -dU.at(F_UT, x) - tau * forced(s, F_UT, x, F_ut(g, m, s, i, j, k)) : 0.0;
+    R.ut[x] = r;
+    chk += r;
   }
   if (i < g.nr && j < g.nt) { // phi face k
     const long x = idx_f(g, i, j, k);
     if (WRITE_UB) Ub.uf[x] = s.ld(F_UF, x);
     const bool interior = g.periodic || (k >= 1 && k < g.np);
-    R.uf[x] = interior ? -dU.at(F_UF, x) - tau * forced(s, F_UF, x, F_uf(g, m, s, i, j, k)) : 0.0;
+    const double r = interior ? -dU.at(F_UF, x) - tau * forced(s, F_UF, x, F_uf(g, m, s, i, j, k)) : 0.0;
+    R.uf[x] = r;
+    chk += r;
   }
+  if (!isfinite(chk)) status[ST_DIVERGED] = 1; // plain vector store
 }
 
 // public form: midpoint formed from Un and Uk and written out; 3-D grid

@@ -17,9 +17,10 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libdsw.so")
 FIELDS = ("p", "ur", "ut", "uf", "T")
 
-DSW_OK, DSW_EINVAL, DSW_ENOMEM, DSW_EHIP, DSW_ENONPHYS, DSW_ESINGULAR = 0, -1, -2, -3, -4, -5
+DSW_OK, DSW_EINVAL, DSW_ENOMEM, DSW_EHIP, DSW_ENONPHYS, DSW_ESINGULAR, DSW_EDIVERGED = (
+    0, -1, -2, -3, -4, -5, -6)
 _NAMES = {DSW_EINVAL: "DSW_EINVAL", DSW_ENOMEM: "DSW_ENOMEM", DSW_EHIP: "DSW_EHIP",
-          DSW_ENONPHYS: "DSW_ENONPHYS", DSW_ESINGULAR: "DSW_ESINGULAR"}
+          DSW_ENONPHYS: "DSW_ENONPHYS", DSW_ESINGULAR: "DSW_ESINGULAR", DSW_EDIVERGED: "DSW_EDIVERGED"}
 
 # every extern "C" symbol the header declares
 SYMBOLS = ("dsw_init_grid", "dsw_free_grid", "dsw_layout", "dsw_residual", "dsw_line_solve_r",
@@ -268,7 +269,7 @@ class Grid:
         return {k: (float(ms[q]), int(n[q])) for q, k in enumerate(TIMING_KINDS)}
 
     def get_status(self, stream=None):
-        """DSW_OK, or raises DswError(DSW_ENONPHYS / DSW_ESINGULAR)."""
+        """DSW_OK, or raises DswError(DSW_ENONPHYS / DSW_EDIVERGED / DSW_ESINGULAR)."""
         _check(lib().dsw_get_status(self._h, _stream(stream)))
         return DSW_OK
 
