@@ -100,20 +100,62 @@ def run_mms(M, g, tau, nsteps, K, record=None):
     return U, out
 
 
+def _cell_volumes(g):
+    c = g.coords()
+    r3 = ((c["rc"] + 0.5 * c["dr"]) ** 3 - (c["rc"] - 0.5 * c["dr"]) ** 3) / 3.0
+    ct = np.cos(c["tc"] - 0.5 * c["dt"]) - np.cos(c["tc"] + 0.5 * c["dt"])
+    return r3[:, None, None] * ct[None, :, None] * np.full((1, 1, g.np), c["dp"])
+
+
 def test_mms_second_order_in_space():
     """l2 error of every field after 10 steps of tau = 1e-4 (t = 1e-3),
-    K = 2, M0 = 1e-2; cells balanced to the solution's wavelengths"""
+    K = 2, M0 = 1e-2; cells balanced to the solution's wavelengths.  Also the
+    mass sum rho V: the non-conservative form does not keep it exactly (the
+    exact solution has rho = 1); its relative drift must be small and shrink
+    under refinement.  Observed: 2.5e-11, 8.5e-12, 4.2e-12 (order 1.5, then
+    1.0: the drift converges more slowly than the fields, near-wall cells
+    dominate it)."""
     M = mms.MMS(1e-2, I.MMS)
-    errs = []
+    R = I.MMS.R
+    errs, drift = [], []
     for N in (4, 8, 16):
         g = oracle.Grid(N, 2 * N, 6 * N, *mms.DOMAIN)
+        U0 = M.fields(g, 0.0)
         U, _ = run_mms(M, g, 1e-4, 10, 2)
         E = M.fields(g, 1e-3)
         errs.append({k: np.sqrt(np.mean((U[k] - E[k])[mms.unknown_mask(g, k)] ** 2)) for k in U})
+        V = _cell_volumes(g)
+        m0 = np.sum(U0["p"] / (R * U0["T"]) * V)
+        drift.append(abs(np.sum(U["p"] / (R * U["T"]) * V) - m0) / m0)
     for k in errs[0]:
         o1 = math.log2(errs[0][k] / errs[1][k])
         o2 = math.log2(errs[1][k] / errs[2][k])
         assert o1 > 1.8 and o2 > 1.9, (k, o1, o2)
+    print("mass drift", drift)
+    assert drift[0] < 1e-10 and drift[1] < 0.6 * drift[0] and drift[2] < 0.6 * drift[1]
+
+
+def test_mach_sweep_stable():
+    """Mach numbers 1e-2 ... 1e-6 (paper, after Table 3: stable for
+    M0 >= 1e-6, pressure variations O(M0^2)): two steps of tau = 1e-3 on
+    16 x 15 x 45 cells stay finite at every M0; max (p - p0)/p0 / M0^2 is
+    within 1.5 % of the closed form down to M0 = 1e-4.  Below, it grows
+    (about 3.6 at 1e-5 and 29 at 1e-6 after one step on this grid): the
+    pressure error no longer scales with M0^2, more than in the paper's
+    own values (3.2 and 3.9 after one step), and is recorded, not pinned."""
+    g = oracle.Grid(16, 15, 45, *mms.DOMAIN)
+    for mach in (1e-2, 1e-3, 1e-4, 1e-5, 1e-6):
+        M = mms.MMS(mach, I.MMS)
+        _, rec = run_mms(M, g, 1e-3, 2, 2, record={1, 2})
+        for n, U in rec:
+            assert all(np.isfinite(v).all() for v in U.values()), (mach, n)
+            dp = np.max(np.abs(U["p"] - mms.P0)) / mms.P0 / mach ** 2
+            exact = np.max(np.abs(M.fields(g, n * 1e-3)["p"] - mms.P0)) / mms.P0 / mach ** 2
+            print(f"M0={mach:.0e} n={n}: {dp:.4f} (closed form {exact:.4f})")
+            if mach >= 1e-4:
+                assert abs(dp - exact) < 0.015 * exact, (mach, n, dp, exact)
+            else:
+                assert dp < 100.0, (mach, n, dp)
 
 
 @pytest.mark.parametrize("mach", [1e-2, 1e-3])
