@@ -245,7 +245,8 @@ def main():
 def bench_adjoint(args):
     """adjoint workload (64 x 128 x 256 sector, 100 m, Mach 1e-2, K = 3): time
     of dsw_adjoint_step (forward recompute from the checkpoint included)
-    against dsw_split_step"""
+    against dsw_split_step; also the taped pair (dsw_split_step_taped, then
+    dsw_adjoint_step_taped without the recompute)"""
     import numpy as np
     import torch
     from paper_2004_13887_amd import dsw
@@ -261,14 +262,19 @@ def bench_adjoint(args):
     lam = {k: torch.as_tensor(rng.uniform(-1.0, 1.0, v.shape), device="cuda") for k, v in U0.items()}
     out = grid.empty()
     stream = torch.cuda.current_stream()
+    tape = grid.new_tape(w.K)
     times = {}
-    for name in ("forward", "adjoint"):
+    for name in ("forward", "adjoint", "forward_taped", "adjoint_taped"):
         def one(n):
             if name == "forward":
                 src, dst = (A, B) if n % 2 == 0 else (B, A)
                 grid.split_step(src, dst, tau, w.K, stream)
-            else:
+            elif name == "adjoint":
                 grid.adjoint_step(A, tau, w.K, lam, out, stream)
+            elif name == "forward_taped":
+                grid.split_step_taped(A, B, tau, w.K, tape, stream)
+            else:
+                grid.adjoint_step_taped(A, tau, w.K, tape, lam, out, stream)
         for n in range(args.warmup):
             one(n)
         torch.cuda.synchronize()
@@ -298,6 +304,9 @@ def bench_adjoint(args):
         "config": {"workload": "adjoint: 256 (phi) x 128 (theta) x 64 (r) sector, 100 m horizontal, "
                                "K=3, Mach 1e-2, seeded bubble + noise", "cells": w.grid.ncells,
                    "K": w.K},
+        "taped": {"forward_taped_ms": times["forward_taped"], "adjoint_taped_ms": times["adjoint_taped"],
+                  "adjoint_taped_over_forward": times["adjoint_taped"] / times["forward"],
+                  "tape_bytes": grid.tape_bytes(w.K)},
     }
     print(json.dumps(out_line), flush=True)
 

@@ -217,6 +217,25 @@ int dsw_line_vjp_phi(dsw_grid *grid, const dsw_fields *Ubar, double tau, const d
 int dsw_residual_vjp(dsw_grid *grid, const dsw_fields *Ubar, double tau, const dsw_fields *mu,
                      dsw_fields *acc, void *stream);
 
+/* The adjoint step without the forward recompute, for callers that keep a
+ * tape of the forward step (e.g. a backward pass right after the forward
+ * one).  The tape holds what the reverse of every iteration reads: the
+ * midpoint and the outputs X1, X2, X3 of the three line solves (4K
+ * five-field states; caller-owned device memory of dsw_tape_bytes bytes,
+ * 8-byte aligned, one tape per recorded step).
+ * dsw_tape_bytes: the size of the tape of a K-iteration step.
+ * dsw_split_step_taped: dsw_split_step (the same kernels and result) that
+ *   also fills the tape.
+ * dsw_adjoint_step_taped: dsw_adjoint_step from a tape filled by
+ *   dsw_split_step_taped with the same Un, tau and K (the tape is read only;
+ *   the result is that of dsw_adjoint_step up to the order of the atomic
+ *   sums). */
+int dsw_tape_bytes(const dsw_grid *grid, int32_t K, int64_t *bytes);
+int dsw_split_step_taped(dsw_grid *grid, const dsw_fields *Un, dsw_fields *Unp1, double tau, int32_t K,
+                         void *tape, void *stream);
+int dsw_adjoint_step_taped(dsw_grid *grid, const dsw_fields *Un, double tau, int32_t K,
+                           const void *tape, const dsw_fields *lam_np1, dsw_fields *lam_n, void *stream);
+
 /* Launch shapes of a grid's kernels (the tunable parameters; they change
  * speed, and for the phi sweep the order of rounding, never the method):
  *   residual_block        threads per workgroup of the residual (64, 128, 256)

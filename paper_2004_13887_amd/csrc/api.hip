@@ -713,11 +713,12 @@ extern "C" int dsw_residual_vjp(dsw_grid *G, const dsw_fields *Ubar, double tau,
 }
 
 // adjoint workspace: per iteration Ubar, X1, X2, X3; the running iterate; two
-// cotangents of the iterate; mu3, mu2, mu1; the cotangent of Ubar
+// cotangents of the iterate; mu3, mu2, mu1; the cotangent of Ubar (K = 0: the
+// last seven only, for a reverse from a tape)
 static int adj_workspace(dsw_grid *G, int K, std::vector<Fields> &ws) {
   const long per = G->count[0] + G->count[1] + G->count[2] + G->count[3] + G->count[4];
   const int nstates = 4 * K + 7;
-  if (G->adj_K < K) {
+  if (!G->adj_mem || G->adj_K < K) {
     if (G->adj_mem) {
       HIPCHK(hipDeviceSynchronize());
       (void)hipFree(G->adj_mem);
@@ -736,37 +737,38 @@ static int adj_workspace(dsw_grid *G, int K, std::vector<Fields> &ws) {
   return DSW_OK;
 }
 
-extern "C" int dsw_adjoint_step(dsw_grid *G, const dsw_fields *Un, double tau, int32_t K,
-                                const dsw_fields *lam_np1, dsw_fields *lam_n, void *stream) {
-  if (!G) return fail(DSW_EINVAL, "null handle");
-  int rc;
-  if ((rc = check_fields(Un, "Un")) || (rc = check_fields(lam_np1, "lam_np1")) ||
-      (rc = check_fields(lam_n, "lam_n")))
-    return rc;
-  if (!(tau > 0.0)) return fail(DSW_EINVAL, "tau must be > 0");
-  if (K < 1) return fail(DSW_EINVAL, "K must be >= 1");
-  if (lam_n->p == lam_np1->p || lam_n->p == Un->p) return fail(DSW_EINVAL, "lam_n must not alias the inputs");
-  std::vector<Fields> ws;
-  if ((rc = adj_workspace(G, K, ws))) return rc;
-  hipStream_t st = (hipStream_t)stream;
-  const Fields un = F(Un), none{};
-  const long *cnt = G->count;
-  auto UB = [&](int k) { return ws[4 * k + 0]; };
-  auto X1 = [&](int k) { return ws[4 * k + 1]; };
-  auto X2 = [&](int k) { return ws[4 * k + 2]; };
-  auto X3 = [&](int k) { return ws[4 * k + 3]; };
-  const Fields U = ws[4 * K], La = ws[4 * K + 1], Lb = ws[4 * K + 2];
-  const Fields M3 = ws[4 * K + 3], M2 = ws[4 * K + 4], M1 = ws[4 * K + 5], UBB = ws[4 * K + 6];
-  // forward recompute from the checkpoint, keeping every iteration's
-  // midpoint and line-solve outputs.  The midpoint of the first iteration is
-  // U^n itself; the phi sweep updates U in place and writes the next
-  // midpoint and its own solution X3.  Boundary-normal faces of U and of the
-  // midpoints are those of U^n (the sweeps leave them alone); those of X3 are
-  // never read.
-  auto UBk = [&](int k) { return k == 0 ? un : UB(k); };
+// The states one iteration of the reverse reads: the midpoint (U^n itself
+// at k = 0) and the three line-solve outputs, per iteration k.
+struct Tape {
+  std::vector<Fields> ub, x1, x2, x3;
+};
+
+// 4K states carved from one buffer: Ubar (the slot of k = 0 unused), X1, X2, X3
+static Tape carve_tape(double *base, const long *cnt, int K, const Fields &un) {
+  Tape t;
+  long off = 0;
+  for (int k = 0; k < K; k++) {
+    const Fields ub = carve(base, cnt, &off);
+    t.ub.push_back(k == 0 ? un : ub);
+    t.x1.push_back(carve(base, cnt, &off));
+    t.x2.push_back(carve(base, cnt, &off));
+    t.x3.push_back(carve(base, cnt, &off));
+  }
+  return t;
+}
+
+// The forward step from U^n into U (the running iterate, U^{n+1} at the
+// end), keeping every iteration's midpoint and line-solve outputs in the
+// tape.  The midpoint of the first iteration is U^n itself; the phi sweep
+// updates U in place and writes the next midpoint and its own solution X3.
+// Boundary-normal faces of U and of the midpoints are those of U^n (the
+// sweeps leave them alone); those of X3 are never read.
+static void adj_record(const dsw_grid *G, const Fields &un, double tau, int K, const Tape &t,
+                       const Fields &U, hipStream_t st) {
+  const Fields none{};
   {
     std::vector<Fields> dst{U};
-    for (int k = 1; k < K; k++) dst.push_back(UB(k));
+    for (int k = 1; k < K; k++) dst.push_back(t.ub[k]);
     for (size_t q = 0; q < dst.size(); q += 3) {
       Pass p{PK_BND, 4, base_args(G)};
       p.a.src = un;
@@ -777,7 +779,7 @@ extern "C" int dsw_adjoint_step(dsw_grid *G, const dsw_fields *Un, double tau, i
     }
   }
   for (int k = 0; k < K; k++) {
-    const Fields ubk = UBk(k);
+    const Fields ubk = t.ub[k];
     Pass r{G->geo.periodic ? PK_RES_INP : PK_RES_IN, 0, base_args(G)};
     r.a.u = src1(ubk);
     r.a.d = diff(un, k == 0 ? un : U);
@@ -787,23 +789,32 @@ extern "C" int dsw_adjoint_step(dsw_grid *G, const dsw_fields *Un, double tau, i
     r.kind = PK_RES;
     launch_single(G, r, st);
     Out o1{}, o2{}, o3{};
-    o1.x = X1(k); o2.x = X2(k);
+    o1.x = t.x1[k]; o2.x = t.x2[k];
     o3.mode = 1;
     o3.x = U;
     o3.base = k == 0 ? un : U;
     o3.un = un;
-    o3.ub = k < K - 1 ? UB(k + 1) : none;
-    o3.raw = X3(k);
+    o3.ub = k < K - 1 ? t.ub[k + 1] : none;
+    o3.raw = t.x3[k];
     launch_single(G, sweep_pass(G, 0, ubk, tau, G->r, o1), st);
-    launch_single(G, sweep_pass(G, 1, ubk, tau, X1(k), o2), st);
-    launch_single(G, sweep_pass(G, 2, ubk, tau, X2(k), o3), st);
+    launch_single(G, sweep_pass(G, 1, ubk, tau, t.x1[k], o2), st);
+    launch_single(G, sweep_pass(G, 2, ubk, tau, t.x2[k], o3), st);
   }
-  // reverse sweep (reverse of every statement above, last iteration first)
-  launch_axpy3(cnt, 0.0, un, 0.0, none, 0.0, none, F(lam_n), st); // lam_n = 0
-  launch_axpy3(cnt, 0.0, un, 0.0, none, 0.0, none, UBB, st);      // Ubar cotangent = 0
-  Fields L = F(lam_np1), Lnext = La;
+}
+
+// The reverse sweep (reverse of every statement of adj_record, last
+// iteration first).  sc: two cotangents of the iterate, mu3, mu2, mu1 and
+// the cotangent of Ubar.
+static void adj_reverse(const dsw_grid *G, const Fields &un, double tau, int K, const Tape &t,
+                        const Fields &lam_np1, const Fields &lam_n, const Fields *sc, hipStream_t st) {
+  const Fields none{};
+  const long *cnt = G->count;
+  const Fields La = sc[0], Lb = sc[1], M3 = sc[2], M2 = sc[3], M1 = sc[4], UBB = sc[5];
+  launch_axpy3(cnt, 0.0, un, 0.0, none, 0.0, none, lam_n, st); // lam_n = 0
+  launch_axpy3(cnt, 0.0, un, 0.0, none, 0.0, none, UBB, st);   // Ubar cotangent = 0
+  Fields L = lam_np1, Lnext = La;
   for (int k = K - 1; k >= 0; k--) {
-    const Fields ubk = UBk(k);
+    const Fields ubk = t.ub[k];
     Out o{};
     o.mode = 0;
     o.x = M3;
@@ -812,15 +823,78 @@ extern "C" int dsw_adjoint_step(dsw_grid *G, const dsw_fields *Un, double tau, i
     launch_T(G, 1, sweep_pass(G, 1, ubk, tau, M3, o), st);
     o.x = M1;
     launch_T(G, 0, sweep_pass(G, 0, ubk, tau, M2, o), st);
-    const Fields xs[3] = {X1(k), X2(k), X3(k)}, mus[3] = {M1, M2, M3};
+    const Fields xs[3] = {t.x1[k], t.x2[k], t.x3[k]}, mus[3] = {M1, M2, M3};
     launch_adj_local(G->geo, G->m, ubk, tau, xs, mus, UBB, st);
     // also clears UBB; at k = 0 it adds the cotangent of U^{n+1,0} = U^n
     // to lam_n as well
-    launch_adj_mix(G->geo, cnt, L, M1, UBB, Lnext, F(lam_n), k == 0, st);
+    launch_adj_mix(G->geo, cnt, L, M1, UBB, Lnext, lam_n, k == 0, st);
     L = Lnext;
     Lnext = (Lnext.p == La.p) ? Lb : La;
   }
+}
+
+static int check_adjoint_args(const dsw_grid *G, const dsw_fields *Un, double tau, int32_t K,
+                              const dsw_fields *lam_np1, const dsw_fields *lam_n) {
+  if (!G) return fail(DSW_EINVAL, "null handle");
+  int rc;
+  if ((rc = check_fields(Un, "Un")) || (rc = check_fields(lam_np1, "lam_np1")) ||
+      (rc = check_fields(lam_n, "lam_n")))
+    return rc;
+  if (!(tau > 0.0)) return fail(DSW_EINVAL, "tau must be > 0");
+  if (K < 1) return fail(DSW_EINVAL, "K must be >= 1");
+  if (lam_n->p == lam_np1->p || lam_n->p == Un->p) return fail(DSW_EINVAL, "lam_n must not alias the inputs");
+  return DSW_OK;
+}
+
+extern "C" int dsw_adjoint_step(dsw_grid *G, const dsw_fields *Un, double tau, int32_t K,
+                                const dsw_fields *lam_np1, dsw_fields *lam_n, void *stream) {
+  int rc;
+  if ((rc = check_adjoint_args(G, Un, tau, K, lam_np1, lam_n))) return rc;
+  std::vector<Fields> ws;
+  if ((rc = adj_workspace(G, K, ws))) return rc;
+  hipStream_t st = (hipStream_t)stream;
+  const Fields un = F(Un);
+  const Tape t = carve_tape(G->adj_mem, G->count, K, un);
+  // forward recompute from the checkpoint into the workspace's iterate
+  adj_record(G, un, tau, K, t, ws[4 * K], st);
+  adj_reverse(G, un, tau, K, t, F(lam_np1), F(lam_n), &ws[4 * K + 1], st);
   return check_launch("adjoint step kernels");
+}
+
+extern "C" int dsw_tape_bytes(const dsw_grid *G, int32_t K, int64_t *bytes) {
+  if (!G || !bytes) return fail(DSW_EINVAL, "null argument");
+  if (K < 1) return fail(DSW_EINVAL, "K must be >= 1");
+  const long per = G->count[0] + G->count[1] + G->count[2] + G->count[3] + G->count[4];
+  *bytes = (int64_t)4 * K * per * (int64_t)sizeof(double);
+  return DSW_OK;
+}
+
+extern "C" int dsw_split_step_taped(dsw_grid *G, const dsw_fields *Un, dsw_fields *Unp1, double tau,
+                                    int32_t K, void *tape, void *stream) {
+  if (!G) return fail(DSW_EINVAL, "null handle");
+  const int rc = check_step_args(Un, Unp1, tau, K);
+  if (rc) return rc;
+  if (!tape || ((uintptr_t)tape % sizeof(double)) != 0) return fail(DSW_EINVAL, "tape must be a non-null 8-byte aligned pointer");
+  hipStream_t st = (hipStream_t)stream;
+  const Fields un = F(Un);
+  const Tape t = carve_tape((double *)tape, G->count, K, un);
+  adj_record(G, un, tau, K, t, F(Unp1), st);
+  return check_launch("taped split step kernels");
+}
+
+extern "C" int dsw_adjoint_step_taped(dsw_grid *G, const dsw_fields *Un, double tau, int32_t K,
+                                      const void *tape, const dsw_fields *lam_np1, dsw_fields *lam_n,
+                                      void *stream) {
+  int rc;
+  if ((rc = check_adjoint_args(G, Un, tau, K, lam_np1, lam_n))) return rc;
+  if (!tape || ((uintptr_t)tape % sizeof(double)) != 0) return fail(DSW_EINVAL, "tape must be a non-null 8-byte aligned pointer");
+  std::vector<Fields> ws;
+  if ((rc = adj_workspace(G, 0, ws))) return rc;
+  hipStream_t st = (hipStream_t)stream;
+  const Fields un = F(Un);
+  const Tape t = carve_tape((double *)const_cast<void *>(tape), G->count, K, un);
+  adj_reverse(G, un, tau, K, t, F(lam_np1), F(lam_n), &ws[1], st);
+  return check_launch("taped adjoint step kernels");
 }
 
 // ------------------------------------------------------------- ensembles --

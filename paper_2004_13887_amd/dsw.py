@@ -30,7 +30,8 @@ SYMBOLS = ("dsw_init_grid", "dsw_free_grid", "dsw_layout", "dsw_residual", "dsw_
            "dsw_ensemble_tune", "dsw_ensemble_set_config", "dsw_ensemble_get_config",
            "dsw_ensemble_get_status", "dsw_adjoint_step", "dsw_line_solve_T_r",
            "dsw_line_solve_T_theta", "dsw_line_solve_T_phi", "dsw_line_vjp_r", "dsw_line_vjp_theta",
-           "dsw_line_vjp_phi", "dsw_residual_vjp", "dsw_split_step_forced", "dsw_last_error")
+           "dsw_line_vjp_phi", "dsw_residual_vjp", "dsw_split_step_forced", "dsw_tape_bytes", "dsw_split_step_taped",
+           "dsw_adjoint_step_taped", "dsw_last_error")
 TIMING_KINDS = ("residual", "sweep_r", "sweep_theta", "sweep_phi_update", "boundary_copy")
 
 
@@ -120,6 +121,9 @@ def lib():
             getattr(L, n).argtypes = [P, FP, D, FP, FP, FP, P]
         L.dsw_residual_vjp.argtypes = [P, FP, D, FP, FP, P]
         L.dsw_split_step_forced.argtypes = [P, FP, FP, D, I, FP, C.POINTER(Wall), FP, P]
+        L.dsw_tape_bytes.argtypes = [P, I, C.POINTER(C.c_int64)]
+        L.dsw_split_step_taped.argtypes = [P, FP, FP, D, I, P, P]
+        L.dsw_adjoint_step_taped.argtypes = [P, FP, D, I, P, FP, FP, P]
         L.dsw_last_error.restype = C.c_char_p
         for n in SYMBOLS[:-1]:
             getattr(L, n).restype = C.c_int
@@ -222,6 +226,25 @@ class Grid:
     def split_step(self, Un, Unp1, tau, K, stream=None):
         _check(lib().dsw_split_step(self._h, C.byref(_fields(Un)), C.byref(_fields(Unp1)),
                                     float(tau), int(K), _stream(stream)))
+
+    def tape_bytes(self, K):
+        n = C.c_int64()
+        _check(lib().dsw_tape_bytes(self._h, int(K), C.byref(n)))
+        return int(n.value)
+
+    def new_tape(self, K, device="cuda"):
+        """a device buffer for dsw_split_step_taped (8-byte aligned)"""
+        return torch.empty(self.tape_bytes(K) // 8, dtype=torch.float64, device=device)
+
+    def split_step_taped(self, Un, Unp1, tau, K, tape, stream=None):
+        _check(lib().dsw_split_step_taped(self._h, C.byref(_fields(Un)), C.byref(_fields(Unp1)),
+                                          float(tau), int(K), C.c_void_p(tape.data_ptr()),
+                                          _stream(stream)))
+
+    def adjoint_step_taped(self, Un, tau, K, tape, lam_np1, lam_n, stream=None):
+        _check(lib().dsw_adjoint_step_taped(self._h, C.byref(_fields(Un)), float(tau), int(K),
+                                            C.c_void_p(tape.data_ptr()), C.byref(_fields(lam_np1)),
+                                            C.byref(_fields(lam_n)), _stream(stream)))
 
     def split_step_forced(self, Un, Unp1, tau, K, src=None, wall=None, bnd=None, stream=None):
         """dsw_split_step_forced: src (dict of five device arrays, a missing
@@ -353,16 +376,23 @@ class SplitStep(torch.autograd.Function):
     """U^{n+1} = split_step(U^n) as a differentiable function of the five
     fields (in the order p, ur, ut, uf, T).  The forward keeps U^n as the
     checkpoint; the backward calls dsw_adjoint_step, which recomputes the
-    step from it."""
+    step from it.  With taped=True the forward also keeps a tape of the step
+    (dsw_split_step_taped; 4K states of device memory per step) and the
+    backward skips the recompute (dsw_adjoint_step_taped)."""
 
     @staticmethod
-    def forward(ctx, grid, tau, K, p, ur, ut, uf, T):
+    def forward(ctx, grid, tau, K, taped, p, ur, ut, uf, T):
         Un = {"p": p.detach().contiguous(), "ur": ur.detach().contiguous(),
               "ut": ut.detach().contiguous(), "uf": uf.detach().contiguous(),
               "T": T.detach().contiguous()}
         out = grid.empty(device=p.device)
-        grid.split_step(Un, out, tau, K)
-        ctx.grid, ctx.tau, ctx.K = grid, tau, K
+        tape = None
+        if taped:
+            tape = grid.new_tape(K, device=p.device)
+            grid.split_step_taped(Un, out, tau, K, tape)
+        else:
+            grid.split_step(Un, out, tau, K)
+        ctx.grid, ctx.tau, ctx.K, ctx.tape = grid, tau, K, tape
         ctx.save_for_backward(*(Un[k] for k in FIELDS))
         return tuple(out[k] for k in FIELDS)
 
@@ -372,13 +402,17 @@ class SplitStep(torch.autograd.Function):
         lam = {k: (g if g is not None else torch.zeros_like(Un[k])).contiguous()
                for k, g in zip(FIELDS, grads)}
         out = ctx.grid.empty(device=Un["p"].device)
-        ctx.grid.adjoint_step(Un, ctx.tau, ctx.K, lam, out)
-        return (None, None, None) + tuple(out[k] for k in FIELDS)
+        if ctx.tape is not None:
+            ctx.grid.adjoint_step_taped(Un, ctx.tau, ctx.K, ctx.tape, lam, out)
+            ctx.tape = None
+        else:
+            ctx.grid.adjoint_step(Un, ctx.tau, ctx.K, lam, out)
+        return (None, None, None, None) + tuple(out[k] for k in FIELDS)
 
 
-def split_step_fn(grid, U, tau, K):
+def split_step_fn(grid, U, tau, K, taped=False):
     """differentiable split step on a dict of fields"""
-    outs = SplitStep.apply(grid, tau, K, *(U[k] for k in FIELDS))
+    outs = SplitStep.apply(grid, tau, K, taped, *(U[k] for k in FIELDS))
     return dict(zip(FIELDS, outs))
 
 

@@ -177,3 +177,52 @@ def test_autograd_function(dsw):
     _, dU1 = oracle.jvp_split_step(og, om, U0, V, tau, w.K)
     grad = {k: Ud[k].grad.cpu().numpy() for k in FIELDS}
     check_dot("autograd", dot(grad, V), dot(wt, dU1))
+
+
+@pytest.mark.parametrize("name", ["parity", "sphere-ragged", "sector-min"])
+def test_taped_step_and_adjoint(name, dsw):
+    """dsw_split_step_taped computes what dsw_split_step computes (the same
+    kernels: bitwise) and fills the tape; dsw_adjoint_step_taped from it
+    gives the adjoint of dsw_adjoint_step (up to the order of the atomic
+    sums) and passes the oracle's dot-product check"""
+    print(f"[taped] {name}", flush=True)
+    w, U0, tau, og, om, gg = _setup(name, dsw)
+    per = sum(int(np.prod(s)) for s in w.grid.shapes().values())
+    assert gg.tape_bytes(w.K) == 4 * w.K * per * 8
+    Ud = dsw.to_device(U0)
+    plain, taped = gg.empty(), gg.empty()
+    tape = gg.new_tape(w.K)
+    gg.split_step(Ud, plain, tau, w.K)
+    gg.split_step_taped(Ud, taped, tau, w.K, tape)
+    lam = cotangent(w.grid, 111)
+    a1, a2 = gg.empty(), gg.empty()
+    gg.adjoint_step(Ud, tau, w.K, dsw.to_device(lam), a1)
+    gg.adjoint_step_taped(Ud, tau, w.K, tape, dsw.to_device(lam), a2)
+    torch.cuda.synchronize()
+    gg.get_status()
+    for k in FIELDS:
+        assert torch.equal(plain[k], taped[k]), k
+    h1, h2 = dsw.to_host(a1), dsw.to_host(a2)
+    e = max(np.linalg.norm(h1[k] - h2[k]) / max(np.linalg.norm(h1[k]), 1e-300) for k in FIELDS)
+    print(f"{name}: taped vs recomputed adjoint rel L2 {e:.2e}", flush=True)
+    assert e <= 1e-12
+    V = direction(w.grid, 112)
+    _, dU1 = oracle.jvp_split_step(og, om, U0, V, tau, w.K)
+    check_dot(f"{name} taped J^T", dot(h2, V), dot(lam, dU1))
+
+
+def test_autograd_taped(dsw):
+    """SplitStep with taped=True: the same gradient as with the recompute"""
+    w, U0, tau, og, om, gg = _setup("sphere-ragged", dsw)
+    wt = cotangent(w.grid, 121)
+    grads = []
+    for taped in (False, True):
+        Ud = {k: v.clone().requires_grad_(True) for k, v in dsw.to_device(U0).items()}
+        U1 = dsw.split_step_fn(gg, Ud, tau, w.K, taped=taped)
+        U2 = dsw.split_step_fn(gg, U1, tau, w.K, taped=taped)  # two steps: two tapes
+        loss = sum((U2[k] * torch.as_tensor(wt[k], device="cuda")).sum() for k in FIELDS)
+        loss.backward()
+        grads.append({k: Ud[k].grad.cpu().numpy() for k in FIELDS})
+    e = max(np.linalg.norm(grads[0][k] - grads[1][k]) / np.linalg.norm(grads[0][k]) for k in FIELDS)
+    print(f"autograd taped vs recomputed: rel L2 {e:.2e}", flush=True)
+    assert e <= 1e-12
