@@ -37,6 +37,7 @@ def _desc(**kw):
     {"t1": -0.1}, {"t2": GOOD.t1}, {"t2": math.pi + 0.1},
     {"p2": GOOD.p1},
     {"periodic": True},  # periodic needs phi2 - phi1 = 2 pi
+    {"nr": 2000, "nt": 2000, "np_": 1000},  # 4e9 cells: past the 32-bit line counts, refused before allocating
 ], ids=lambda b: ",".join(f"{k}={v}" for k, v in b.items()))
 def test_bad_descriptor(bad, dsw):
     a = _desc(**bad)
