@@ -408,11 +408,30 @@ __device__ __forceinline__ void part_scalar_line(const Geo &g, const Mat &m, con
 // fewer registers (about 55 against 256) and on their own run at a much
 // higher occupancy; on small ones the second launch costs more than that
 // gains.
-template <int PM, bool TR, int PART = 2, bool W = false>
+// MAP (forced passes): 0 every slot, w = i * nt + j; 1 the interior slots
+// (1 <= i <= nr - 2, 1 <= j <= nt - 2), whose rows read no ghost across an
+// r or theta boundary, with the interior source (phi walls only; P: periodic
+// phi); 2 the other slots, with the general source.
+template <int PM, bool TR, int PART = 2, bool W = false, int MAP = 0, bool P = false>
 __device__ __forceinline__ void phi_body(const PassArgs &a, unsigned w, double *lds) {
   const Geo &g = a.g;
-  decltype(auto) u = SrcSel<W>::get(a); // W: forced pass (wall velocities)
-  const int j = (int)(w % g.nt), i = (int)(w / g.nt);
+  int i, j;
+  if constexpr (MAP == 1) {
+    j = 1 + (int)(w % (unsigned)(g.nt - 2));
+    i = 1 + (int)(w / (unsigned)(g.nt - 2));
+  } else if constexpr (MAP == 2) {
+    if (w < 2u * (unsigned)g.nr) {
+      i = (int)(w >> 1);
+      j = (w & 1u) ? g.nt - 1 : 0;
+    } else {
+      const unsigned w2 = w - 2u * (unsigned)g.nr;
+      j = 1 + (int)(w2 >> 1);
+      i = (w2 & 1u) ? g.nr - 1 : 0;
+    }
+  } else {
+    j = (int)(w % g.nt);
+    i = (int)(w / g.nt);
+  }
   const int t = threadIdx.x;
   const Out &o = a.o;
   if (PART != 1 && o.mode == 0) { // boundary-normal faces of x that no phi line owns
@@ -425,10 +444,25 @@ __device__ __forceinline__ void phi_body(const PassArgs &a, unsigned w, double *
     }
     if (!g.periodic && t == 0) x.uf[idx_f(g, i, j, 0)] = 0.0;
   }
-  if (PART != 1) part_block_line<PM, TR>(g, a.m, u, a.rhs, o, i, j, a.tau, lds, a.status);
-  if (PART != 0) {
-    if (i >= 1) part_scalar_line<PM, 0, TR>(g, a.m, u, a.rhs, o, i, j, a.tau, lds, a.status);
-    if (j >= 1) part_scalar_line<PM, 1, TR>(g, a.m, u, a.rhs, o, i, j, a.tau, lds, a.status);
+  if constexpr (MAP == 1) {
+    SrcInW<P> u;
+#pragma unroll
+    for (int q = 0; q < 5; q++) u.a[q] = a.u.a[q];
+    u.w = a.wall;
+    u.f[F_P] = a.fsrc.p; u.f[F_UR] = a.fsrc.ur; u.f[F_UT] = a.fsrc.ut; u.f[F_UF] = a.fsrc.uf;
+    u.f[F_T] = a.fsrc.T;
+    if (PART != 1) part_block_line<PM, TR>(g, a.m, u, a.rhs, o, i, j, a.tau, lds, a.status);
+    if (PART != 0) {
+      part_scalar_line<PM, 0, TR>(g, a.m, u, a.rhs, o, i, j, a.tau, lds, a.status);
+      part_scalar_line<PM, 1, TR>(g, a.m, u, a.rhs, o, i, j, a.tau, lds, a.status);
+    }
+  } else {
+    decltype(auto) u = SrcSel<W>::get(a); // W: forced pass (wall velocities)
+    if (PART != 1) part_block_line<PM, TR>(g, a.m, u, a.rhs, o, i, j, a.tau, lds, a.status);
+    if (PART != 0) {
+      if (i >= 1) part_scalar_line<PM, 0, TR>(g, a.m, u, a.rhs, o, i, j, a.tau, lds, a.status);
+      if (j >= 1) part_scalar_line<PM, 1, TR>(g, a.m, u, a.rhs, o, i, j, a.tau, lds, a.status);
+    }
   }
 }
 
@@ -446,10 +480,10 @@ __global__ void __launch_bounds__(256) DSW_OCC(DSW_WAVES_PHI) k_phi_part(PassArg
 // forced split step, one grid: as the plain sweep, all three lines of a slot
 // in one launch, or from PHI_SPLIT_SLOTS slots on the block lines and the
 // scalar lines as two
-template <int PM, int PART>
+template <int PM, int PART, int MAP, bool P = false>
 __global__ void __launch_bounds__(256) DSW_OCC(DSW_WAVES_PHI) k_phi_partF(PassArgs a) {
   extern __shared__ double lds[];
-  phi_body<PM, false, PART, true>(a, blockIdx.x, lds);
+  phi_body<PM, false, PART, true, MAP, P>(a, blockIdx.x, lds);
 }
 
 // transposed systems (adjoint), one grid: each chunk walks the rows of the
@@ -536,19 +570,53 @@ void launch_phi_pass(int pm, const PassArgs &a, const Batch &b, unsigned blocks,
   }
 }
 
+// one launch of the forced phi pass over a slot set (MAP) and a part
+template <int PM, int MAP>
+static void launch_phi_forced_map(const PassArgs &a, unsigned blocks, unsigned threads, size_t lds,
+                                  size_t lds_s, bool split, hipStream_t st) {
+  if (!blocks) return;
+  const dim3 gr(blocks), bl(threads);
+  if constexpr (MAP == 1) {
+    if (a.g.periodic) {
+      if (!split) hipLaunchKernelGGL((k_phi_partF<PM, 2, MAP, true>), gr, bl, lds, st, a);
+      else {
+        hipLaunchKernelGGL((k_phi_partF<PM, 0, MAP, true>), gr, bl, lds, st, a);
+        hipLaunchKernelGGL((k_phi_partF<PM, 1, MAP, true>), gr, bl, lds_s, st, a);
+      }
+      return;
+    }
+  }
+  if (!split) {
+    hipLaunchKernelGGL((k_phi_partF<PM, 2, MAP>), gr, bl, lds, st, a);
+  } else {
+    hipLaunchKernelGGL((k_phi_partF<PM, 0, MAP>), gr, bl, lds, st, a);
+    hipLaunchKernelGGL((k_phi_partF<PM, 1, MAP>), gr, bl, lds_s, st, a);
+  }
+}
+
+// The interior slots with the interior source, the rest with the general
+// one (its ghost code across r and theta walls costs the block kernel a
+// wave per SIMD); every slot with the general one when 32-bit indices do
+// not reach.
 void launch_phi_forced(int pm, const PassArgs &a, unsigned blocks, unsigned threads, size_t lds,
                        hipStream_t st) {
-  const dim3 gr(blocks), bl(threads);
+  const Geo &g = a.g;
   const size_t lds_s = sizeof(double) * (size_t)(pm > 5 ? pm : 5) * threads;
-  if (blocks < PHI_SPLIT_SLOTS) {
-    if (pm == 2) hipLaunchKernelGGL((k_phi_partF<2, 2>), gr, bl, lds, st, a);
-    else hipLaunchKernelGGL((k_phi_partF<4, 2>), gr, bl, lds, st, a);
-  } else if (pm == 2) {
-    hipLaunchKernelGGL((k_phi_partF<2, 0>), gr, bl, lds, st, a);
-    hipLaunchKernelGGL((k_phi_partF<2, 1>), gr, bl, lds_s, st, a);
+  const bool split = blocks >= PHI_SPLIT_SLOTS;
+  const bool in32 = (long)(g.nr + 1) * (g.nt + 1) * g.npf < 0x7fffffffL;
+  if (!in32) {
+    if (pm == 2) launch_phi_forced_map<2, 0>(a, blocks, threads, lds, lds_s, split, st);
+    else launch_phi_forced_map<4, 0>(a, blocks, threads, lds, lds_s, split, st);
+    return;
+  }
+  const unsigned nin = (unsigned)(g.nr - 2) * (unsigned)(g.nt - 2);
+  const unsigned nbd = 2u * (unsigned)g.nr + 2u * (unsigned)(g.nt - 2);
+  if (pm == 2) {
+    launch_phi_forced_map<2, 1>(a, nin, threads, lds, lds_s, split, st);
+    launch_phi_forced_map<2, 2>(a, nbd, threads, lds, lds_s, split, st);
   } else {
-    hipLaunchKernelGGL((k_phi_partF<4, 0>), gr, bl, lds, st, a);
-    hipLaunchKernelGGL((k_phi_partF<4, 1>), gr, bl, lds_s, st, a);
+    launch_phi_forced_map<4, 1>(a, nin, threads, lds, lds_s, split, st);
+    launch_phi_forced_map<4, 2>(a, nbd, threads, lds, lds_s, split, st);
   }
 }
 
