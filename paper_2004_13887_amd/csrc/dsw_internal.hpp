@@ -194,6 +194,18 @@ inline int phi_kind(const Geo &g, const Cfg &c) {
   return (c.phi_pm > 0 && phi_part_supported(g, c.phi_pm)) ? PK_SW2_PART : PK_SW2_LINE;
 }
 
+// Workgroups go to the chip's 8 XCDs in turn (w mod 8), and each XCD has an
+// L2 of its own.  Renumbered by this bijection of [0, n), every XCD takes one
+// contiguous range of n work items, so that items next to each other, which
+// read each other's neighbour data, share an L2.  Used where that pays: the
+// scalar lines of the three sweeps (bandwidth-bound); the block lines and the
+// residual keep the round-robin order, which spreads every moment's accesses
+// over the whole grid and measured faster for them.
+__device__ __forceinline__ unsigned xcd_contiguous(unsigned w, unsigned n) {
+  const unsigned x = w & 7u, i = w >> 3, q = n >> 3, r = n & 7u;
+  return (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + i;
+}
+
 // member lookup of a batched launch (binary search over the offsets)
 __device__ __forceinline__ int batch_member(const Batch &b, unsigned w) {
   int lo = 0, hi = b.n - 1;

@@ -466,18 +466,10 @@ __device__ __forceinline__ void phi_body(const PassArgs &a, unsigned w, double *
   }
 }
 
-// Workgroups go to the chip's 8 XCDs in turn (w mod 8), and each XCD has an
-// L2 of its own.  The scalar lines of slot (i, j) read the cells of slots
-// (i - 1, j) and (i, j - 1) too; renumbered so that every XCD takes one
-// contiguous range of slots, the slots next to each other share an L2.
-// Measured on the global grid: the phi pass 1.93 -> 1.87 ms with the scalar
-// launch renumbered; renumbering the block launch as well, or the r and
-// theta sweeps, is slower.  A bijection of [0, n).
-__device__ __forceinline__ unsigned xcd_contiguous(unsigned w, unsigned n) {
-  const unsigned x = w & 7u, i = w >> 3, q = n >> 3, r = n & 7u;
-  return (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + i;
-}
-
+// The scalar lines of slot (i, j) read the cells of slots (i - 1, j) and
+// (i, j - 1) too: the scalar launch numbers its slots XCD-contiguously.
+// Measured on the global grid: the phi pass 1.93 -> 1.87 ms; renumbering the
+// block launch as well is slower.
 template <int PM, bool B, int PART>
 __global__ void __launch_bounds__(256) DSW_OCC(DSW_WAVES_PHI) k_phi_part(PassArgs a, Batch bt) {
   extern __shared__ double lds[];

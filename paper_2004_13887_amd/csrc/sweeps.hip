@@ -901,7 +901,11 @@ __device__ __forceinline__ void sweep2_body(const PassArgs &a, unsigned w, doubl
   const unsigned lane = threadIdx.x % lpw;
   const bool top = threadIdx.x < lpw;
   const unsigned nwa = (unsigned)((F.na + lpw - 1) / lpw);
-  const unsigned w2 = w - nbw;
+  // this grid's scalar workgroups, numbered XCD-contiguously (lines of
+  // neighbouring families share cells): r sweep 1.46 -> 1.42 ms on the
+  // global grid
+  const unsigned nws = nwa + (unsigned)((F.nbb + lpw - 1) / lpw);
+  const unsigned w2 = TR ? w - nbw : xcd_contiguous(w - nbw, nws);
   if (w2 < nwa) {
     const long line = (long)w2 * lpw + lane;
     const bool act = line < F.na;
