@@ -496,7 +496,8 @@ __global__ void __launch_bounds__(256) DSW_OCC(DSW_WAVES_PHI) k_phi_partF(PassAr
 template <int PM, int PART>
 __global__ void __launch_bounds__(256) k_phi_part_T(PassArgs a) {
   extern __shared__ double lds[];
-  phi_body<PM, true, PART>(a, blockIdx.x, lds);
+  // the scalar launch numbered XCD-contiguously, as in the forward sweep
+  phi_body<PM, true, PART>(a, PART == 1 ? xcd_contiguous(blockIdx.x, gridDim.x) : blockIdx.x, lds);
 }
 
 // block lines, then scalar lines, as two launches: the scalar launch holds a

@@ -903,9 +903,9 @@ __device__ __forceinline__ void sweep2_body(const PassArgs &a, unsigned w, doubl
   const unsigned nwa = (unsigned)((F.na + lpw - 1) / lpw);
   // this grid's scalar workgroups, numbered XCD-contiguously (lines of
   // neighbouring families share cells): r sweep 1.46 -> 1.42 ms on the
-  // global grid
+  // global grid; the transposed sweeps of the adjoint gain a little too
   const unsigned nws = nwa + (unsigned)((F.nbb + lpw - 1) / lpw);
-  const unsigned w2 = TR ? w - nbw : xcd_contiguous(w - nbw, nws);
+  const unsigned w2 = xcd_contiguous(w - nbw, nws);
   if (w2 < nwa) {
     const long line = (long)w2 * lpw + lane;
     const bool act = line < F.na;
