@@ -29,6 +29,11 @@ struct dsw_grid {
   double *scratch_mem = nullptr;
   double *adj_mem = nullptr; // adjoint workspace, allocated on first use
   int adj_K = 0;
+  // the adjoint's second stream (non-blocking, default priority), its
+  // fork/join events and the sweep scratch of the work it runs
+  hipStream_t side = nullptr;
+  hipEvent_t fork_ev = nullptr, join_ev = nullptr;
+  Scratch sc2{};
   int *status = nullptr;
   long count[5];
   int device = 0;
@@ -221,6 +226,9 @@ extern "C" int dsw_free_grid(dsw_grid *G) {
   if (G->fields_mem) (void)hipFree(G->fields_mem);
   if (G->scratch_mem) (void)hipFree(G->scratch_mem);
   if (G->adj_mem) (void)hipFree(G->adj_mem);
+  if (G->side) (void)hipStreamDestroy(G->side);
+  if (G->fork_ev) (void)hipEventDestroy(G->fork_ev);
+  if (G->join_ev) (void)hipEventDestroy(G->join_ev);
   if (G->status) (void)hipFree(G->status);
   delete G;
   return DSW_OK;
@@ -714,10 +722,12 @@ extern "C" int dsw_residual_vjp(dsw_grid *G, const dsw_fields *Ubar, double tau,
 
 // adjoint workspace: per iteration Ubar, X1, X2, X3; the running iterate; two
 // cotangents of the iterate; mu3, mu2, mu1; the cotangent of Ubar (K = 0: the
-// last seven only, for a reverse from a tape)
+// last seven only, for a reverse from a tape); after the states, the sweep
+// scratch of the second stream
 static int adj_workspace(dsw_grid *G, int K, std::vector<Fields> &ws) {
   const long per = G->count[0] + G->count[1] + G->count[2] + G->count[3] + G->count[4];
   const int nstates = 4 * K + 7;
+  const long extra = G->sc.blk_len + G->sc.sca_len;
   if (!G->adj_mem || G->adj_K < K) {
     if (G->adj_mem) {
       HIPCHK(hipDeviceSynchronize());
@@ -725,15 +735,34 @@ static int adj_workspace(dsw_grid *G, int K, std::vector<Fields> &ws) {
       G->adj_mem = nullptr;
       G->adj_K = 0;
     }
-    if (hipMalloc(&G->adj_mem, (size_t)nstates * per * sizeof(double)) != hipSuccess) {
+    if (hipMalloc(&G->adj_mem, ((size_t)nstates * per + extra) * sizeof(double)) != hipSuccess) {
       G->adj_mem = nullptr;
       return fail(DSW_ENOMEM, "adjoint workspace");
     }
     G->adj_K = K;
   }
+  // non-blocking: no implicit ordering against a caller's null stream
+  if (!G->side && hipStreamCreateWithFlags(&G->side, hipStreamNonBlocking) != hipSuccess) {
+    G->side = nullptr;
+    return fail(DSW_EHIP, "adjoint stream");
+  }
+  if (!G->fork_ev && hipEventCreateWithFlags(&G->fork_ev, hipEventDisableTiming) != hipSuccess) {
+    G->fork_ev = nullptr;
+    return fail(DSW_EHIP, "adjoint events");
+  }
+  if (!G->join_ev && hipEventCreateWithFlags(&G->join_ev, hipEventDisableTiming) != hipSuccess) {
+    G->join_ev = nullptr;
+    return fail(DSW_EHIP, "adjoint events");
+  }
   long off = 0;
   ws.clear();
   for (int q = 0; q < nstates; q++) ws.push_back(carve(G->adj_mem, G->count, &off));
+  // the states of the largest K allocated so far come first
+  double *s2 = G->adj_mem + (size_t)(4 * G->adj_K + 7) * per;
+  G->sc2.blk = s2;
+  G->sc2.sca = s2 + G->sc.blk_len;
+  G->sc2.blk_len = G->sc.blk_len;
+  G->sc2.sca_len = G->sc.sca_len;
   return DSW_OK;
 }
 
@@ -763,73 +792,110 @@ static Tape carve_tape(double *base, const long *cnt, int K, const Fields &un) {
 // updates U in place and writes the next midpoint and its own solution X3.
 // Boundary-normal faces of U and of the midpoints are those of U^n (the
 // sweeps leave them alone); those of X3 are never read.
+// adj_record_bnd: those faces; adj_record_iter: iteration k.
+static void adj_record_bnd(const dsw_grid *G, const Fields &un, int K, const Tape &t, const Fields &U,
+                           hipStream_t st) {
+  const Fields none{};
+  std::vector<Fields> dst{U};
+  for (int k = 1; k < K; k++) dst.push_back(t.ub[k]);
+  for (size_t q = 0; q < dst.size(); q += 3) {
+    Pass p{PK_BND, 4, base_args(G)};
+    p.a.src = un;
+    p.a.d0 = dst[q];
+    p.a.d1 = q + 1 < dst.size() ? dst[q + 1] : none;
+    p.a.d2 = q + 2 < dst.size() ? dst[q + 2] : none;
+    launch_single(G, p, st);
+  }
+}
+
+static void adj_record_iter(const dsw_grid *G, const Fields &un, double tau, int K, int k, const Tape &t,
+                            const Fields &U, hipStream_t st) {
+  const Fields none{};
+  const Fields ubk = t.ub[k];
+  Pass r{G->geo.periodic ? PK_RES_INP : PK_RES_IN, 0, base_args(G)};
+  r.a.u = src1(ubk);
+  r.a.d = diff(un, k == 0 ? un : U);
+  r.a.tau = tau;
+  r.a.R = G->r;
+  launch_single(G, r, st);
+  r.kind = PK_RES;
+  launch_single(G, r, st);
+  Out o1{}, o2{}, o3{};
+  o1.x = t.x1[k]; o2.x = t.x2[k];
+  o3.mode = 1;
+  o3.x = U;
+  o3.base = k == 0 ? un : U;
+  o3.un = un;
+  o3.ub = k < K - 1 ? t.ub[k + 1] : none;
+  o3.raw = t.x3[k];
+  launch_single(G, sweep_pass(G, 0, ubk, tau, G->r, o1), st);
+  launch_single(G, sweep_pass(G, 1, ubk, tau, t.x1[k], o2), st);
+  launch_single(G, sweep_pass(G, 2, ubk, tau, t.x2[k], o3), st);
+}
+
 static void adj_record(const dsw_grid *G, const Fields &un, double tau, int K, const Tape &t,
                        const Fields &U, hipStream_t st) {
-  const Fields none{};
-  {
-    std::vector<Fields> dst{U};
-    for (int k = 1; k < K; k++) dst.push_back(t.ub[k]);
-    for (size_t q = 0; q < dst.size(); q += 3) {
-      Pass p{PK_BND, 4, base_args(G)};
-      p.a.src = un;
-      p.a.d0 = dst[q];
-      p.a.d1 = q + 1 < dst.size() ? dst[q + 1] : none;
-      p.a.d2 = q + 2 < dst.size() ? dst[q + 2] : none;
-      launch_single(G, p, st);
-    }
-  }
-  for (int k = 0; k < K; k++) {
-    const Fields ubk = t.ub[k];
-    Pass r{G->geo.periodic ? PK_RES_INP : PK_RES_IN, 0, base_args(G)};
-    r.a.u = src1(ubk);
-    r.a.d = diff(un, k == 0 ? un : U);
-    r.a.tau = tau;
-    r.a.R = G->r;
-    launch_single(G, r, st);
-    r.kind = PK_RES;
-    launch_single(G, r, st);
-    Out o1{}, o2{}, o3{};
-    o1.x = t.x1[k]; o2.x = t.x2[k];
-    o3.mode = 1;
-    o3.x = U;
-    o3.base = k == 0 ? un : U;
-    o3.un = un;
-    o3.ub = k < K - 1 ? t.ub[k + 1] : none;
-    o3.raw = t.x3[k];
-    launch_single(G, sweep_pass(G, 0, ubk, tau, G->r, o1), st);
-    launch_single(G, sweep_pass(G, 1, ubk, tau, t.x1[k], o2), st);
-    launch_single(G, sweep_pass(G, 2, ubk, tau, t.x2[k], o3), st);
-  }
+  adj_record_bnd(G, un, K, t, U, st);
+  for (int k = 0; k < K; k++) adj_record_iter(G, un, tau, K, k, t, U, st);
 }
 
 // The reverse sweep (reverse of every statement of adj_record, last
 // iteration first).  sc: two cotangents of the iterate, mu3, mu2, mu1 and
-// the cotangent of Ubar.
+// the cotangent of Ubar.  Iteration k of it: the three transposed solves
+// (adj_reverse_solves: they read only the midpoint of iteration k and the
+// incoming cotangent L), then the reverse of the local rows and the mix
+// (adj_reverse_local: these read X1, X2, X3 of iteration k as well).
+struct Rev {
+  Fields La, Lb, M3, M2, M1, UBB;
+  Fields L, Lnext;
+};
+
+static Rev adj_reverse_init(const dsw_grid *G, const Fields &un, const Fields &lam_np1, const Fields &lam_n,
+                            const Fields *sc, hipStream_t st) {
+  const Fields none{};
+  Rev v{sc[0], sc[1], sc[2], sc[3], sc[4], sc[5], lam_np1, sc[0]};
+  launch_axpy3(G->count, 0.0, un, 0.0, none, 0.0, none, lam_n, st);  // lam_n = 0
+  launch_axpy3(G->count, 0.0, un, 0.0, none, 0.0, none, v.UBB, st);  // Ubar cotangent = 0
+  return v;
+}
+
+// scr: the sweep scratch the solves use (the grid's, or the second stream's)
+static void adj_reverse_solves(const dsw_grid *G, double tau, int k, const Tape &t, const Rev &v,
+                               const Scratch &scr, hipStream_t st) {
+  const Fields ubk = t.ub[k];
+  Out o{};
+  o.mode = 0;
+  auto pass = [&](int d, const Fields &rhs) {
+    Pass p = sweep_pass(G, d, ubk, tau, rhs, o);
+    p.a.scb = scr.blk;
+    p.a.scs = scr.sca;
+    return p;
+  };
+  o.x = v.M3;
+  launch_T(G, 2, pass(2, v.L), st);
+  o.x = v.M2;
+  launch_T(G, 1, pass(1, v.M3), st);
+  o.x = v.M1;
+  launch_T(G, 0, pass(0, v.M2), st);
+}
+
+static void adj_reverse_local(const dsw_grid *G, double tau, int k, const Tape &t, Rev &v,
+                              const Fields &lam_n, hipStream_t st) {
+  const Fields xs[3] = {t.x1[k], t.x2[k], t.x3[k]}, mus[3] = {v.M1, v.M2, v.M3};
+  launch_adj_local(G->geo, G->m, t.ub[k], tau, xs, mus, v.UBB, st);
+  // also clears UBB; at k = 0 it adds the cotangent of U^{n+1,0} = U^n
+  // to lam_n as well
+  launch_adj_mix(G->geo, G->count, v.L, v.M1, v.UBB, v.Lnext, lam_n, k == 0, st);
+  v.L = v.Lnext;
+  v.Lnext = (v.Lnext.p == v.La.p) ? v.Lb : v.La;
+}
+
 static void adj_reverse(const dsw_grid *G, const Fields &un, double tau, int K, const Tape &t,
                         const Fields &lam_np1, const Fields &lam_n, const Fields *sc, hipStream_t st) {
-  const Fields none{};
-  const long *cnt = G->count;
-  const Fields La = sc[0], Lb = sc[1], M3 = sc[2], M2 = sc[3], M1 = sc[4], UBB = sc[5];
-  launch_axpy3(cnt, 0.0, un, 0.0, none, 0.0, none, lam_n, st); // lam_n = 0
-  launch_axpy3(cnt, 0.0, un, 0.0, none, 0.0, none, UBB, st);   // Ubar cotangent = 0
-  Fields L = lam_np1, Lnext = La;
+  Rev v = adj_reverse_init(G, un, lam_np1, lam_n, sc, st);
   for (int k = K - 1; k >= 0; k--) {
-    const Fields ubk = t.ub[k];
-    Out o{};
-    o.mode = 0;
-    o.x = M3;
-    launch_T(G, 2, sweep_pass(G, 2, ubk, tau, L, o), st);
-    o.x = M2;
-    launch_T(G, 1, sweep_pass(G, 1, ubk, tau, M3, o), st);
-    o.x = M1;
-    launch_T(G, 0, sweep_pass(G, 0, ubk, tau, M2, o), st);
-    const Fields xs[3] = {t.x1[k], t.x2[k], t.x3[k]}, mus[3] = {M1, M2, M3};
-    launch_adj_local(G->geo, G->m, ubk, tau, xs, mus, UBB, st);
-    // also clears UBB; at k = 0 it adds the cotangent of U^{n+1,0} = U^n
-    // to lam_n as well
-    launch_adj_mix(G->geo, cnt, L, M1, UBB, Lnext, lam_n, k == 0, st);
-    L = Lnext;
-    Lnext = (Lnext.p == La.p) ? Lb : La;
+    adj_reverse_solves(G, tau, k, t, v, G->sc, st);
+    adj_reverse_local(G, tau, k, t, v, lam_n, st);
   }
 }
 
@@ -855,9 +921,27 @@ extern "C" int dsw_adjoint_step(dsw_grid *G, const dsw_fields *Un, double tau, i
   hipStream_t st = (hipStream_t)stream;
   const Fields un = F(Un);
   const Tape t = carve_tape(G->adj_mem, G->count, K, un);
-  // forward recompute from the checkpoint into the workspace's iterate
-  adj_record(G, un, tau, K, t, ws[4 * K], st);
-  adj_reverse(G, un, tau, K, t, F(lam_np1), F(lam_n), &ws[4 * K + 1], st);
+  const Fields U = ws[4 * K];
+  // forward recompute from the checkpoint into the workspace's iterate,
+  // up to the midpoint of the last iteration
+  adj_record_bnd(G, un, K, t, U, st);
+  for (int k = 0; k < K - 1; k++) adj_record_iter(G, un, tau, K, k, t, U, st);
+  // The last iteration's transposed solves read only its midpoint and
+  // lam_np1: they run on the second stream (with a sweep scratch of their
+  // own) while the forward finishes that iteration, whose X1, X2, X3 the
+  // rest of the reverse needs.  The two sides write disjoint buffers.
+  HIPCHK(hipEventRecord(G->fork_ev, st));
+  HIPCHK(hipStreamWaitEvent(G->side, G->fork_ev, 0));
+  Rev v = adj_reverse_init(G, un, F(lam_np1), F(lam_n), &ws[4 * K + 1], G->side);
+  adj_reverse_solves(G, tau, K - 1, t, v, G->sc2, G->side);
+  HIPCHK(hipEventRecord(G->join_ev, G->side));
+  adj_record_iter(G, un, tau, K, K - 1, t, U, st);
+  HIPCHK(hipStreamWaitEvent(st, G->join_ev, 0));
+  adj_reverse_local(G, tau, K - 1, t, v, F(lam_n), st);
+  for (int k = K - 2; k >= 0; k--) {
+    adj_reverse_solves(G, tau, k, t, v, G->sc, st);
+    adj_reverse_local(G, tau, k, t, v, F(lam_n), st);
+  }
   return check_launch("adjoint step kernels");
 }
 
