@@ -246,7 +246,9 @@ def bench_adjoint(args):
     """adjoint workload (64 x 128 x 256 sector, 100 m, Mach 1e-2, K = 3): time
     of dsw_adjoint_step (forward recompute from the checkpoint included)
     against dsw_split_step; also the taped pair (dsw_split_step_taped, then
-    dsw_adjoint_step_taped without the recompute)"""
+    dsw_adjoint_step_taped without the recompute) and the reverse pass
+    through the workload's 10 steps from per-step checkpoints
+    (dsw_adjoint_trajectory, every step's recompute included)"""
     import numpy as np
     import torch
     from paper_2004_13887_amd import dsw
@@ -286,6 +288,25 @@ def bench_adjoint(args):
         torch.cuda.synchronize()
         times[name] = ev0.elapsed_time(ev1) / args.steps
         log(f"[adjoint] {name}: {times[name]:.3f} ms per step")
+    # the adjoint workload's reverse pass: w.steps steps from per-step
+    # checkpoints (computed before the timed region), one call per pass
+    ck = [A]
+    for n in range(w.steps - 1):
+        nxt = grid.empty()
+        grid.split_step(ck[-1], nxt, tau, w.K, stream)
+        ck.append(nxt)
+    ntraj = max(1, args.steps // 5)
+    for n in range(max(1, args.warmup // 2)):
+        grid.adjoint_trajectory(ck, tau, w.K, lam, out, stream)
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    for n in range(ntraj):
+        grid.adjoint_trajectory(ck, tau, w.K, lam, out, stream)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    traj_ms = ev0.elapsed_time(ev1) / (ntraj * w.steps)
+    log(f"[adjoint] trajectory of {w.steps} steps: {traj_ms:.3f} ms per step ({ntraj} passes)")
     grid.get_status()
     out_line = {
         "metric": "adjoint step time / forward step time",
@@ -307,6 +328,8 @@ def bench_adjoint(args):
         "taped": {"forward_taped_ms": times["forward_taped"], "adjoint_taped_ms": times["adjoint_taped"],
                   "adjoint_taped_over_forward": times["adjoint_taped"] / times["forward"],
                   "tape_bytes": grid.tape_bytes(w.K)},
+        "trajectory": {"steps": w.steps, "passes": ntraj, "adjoint_ms_per_step": traj_ms,
+                       "adjoint_over_forward": traj_ms / times["forward"]},
     }
     print(json.dumps(out_line), flush=True)
 

@@ -236,6 +236,23 @@ int dsw_split_step_taped(dsw_grid *grid, const dsw_fields *Un, dsw_fields *Unp1,
 int dsw_adjoint_step_taped(dsw_grid *grid, const dsw_fields *Un, double tau, int32_t K,
                            const void *tape, const dsw_fields *lam_np1, dsw_fields *lam_n, void *stream);
 
+/* The adjoint of nsteps consecutive split steps (a trajectory U^0 -> U^N,
+ * N = nsteps, with a checkpoint of every step's starting state): lam_0 =
+ * J(U^0)^T ... J(U^{N-1})^T lam_end, i.e. dsw_adjoint_step applied from the
+ * last step back to the first, each step recomputed from its checkpoint.
+ * ckpts: host array of N field descriptors, ckpts[n] = U^n on the device
+ * (read only).  lam_end: the cotangent of U^N; lam_0: the result, which
+ * must alias neither lam_end nor a checkpoint.  The recompute of step n-1
+ * runs on a second stream of the handle while the reverse of step n runs on
+ * `stream` (the two read and write disjoint buffers); every piece of work is
+ * ordered before the call's later work on `stream`.  Workspace: 8K+9 states
+ * and a second sweep scratch, allocated by the handle on first use.  The
+ * result equals N chained dsw_adjoint_step calls up to the order of the
+ * atomic sums.  Errors: those of dsw_adjoint_step; DSW_EINVAL for
+ * nsteps < 1 or a null ckpts. */
+int dsw_adjoint_trajectory(dsw_grid *grid, const dsw_fields *ckpts, int32_t nsteps, double tau, int32_t K,
+                           const dsw_fields *lam_end, dsw_fields *lam_0, void *stream);
+
 /* Launch shapes of a grid's kernels (the tunable parameters; they change
  * speed, and for the phi sweep the order of rounding, never the method):
  *   residual_block        threads per workgroup of the residual (64, 128, 256)

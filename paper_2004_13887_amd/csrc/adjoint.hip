@@ -1205,10 +1205,11 @@ void launch_axpy3(const long *cnt, double a, const Fields &x, double b, const Fi
 //   Lnew = (bnd ? 0 : L) - mu1 + ub/2,   lam_n += (bnd ? L : 0) + mu1 + ub/2,
 // and ub = 0 for the next iteration's accumulation.  fold (the first
 // iteration, whose U^{n+1,0} is U^n): lam_n += Lnew as well, i.e.
-// lam_n += L + ub, and Lnew is not written.
+// lam_n += L + ub, and Lnew is not written.  first (the last iteration,
+// which the reverse takes first): lam_n is written, not accumulated.
 __global__ void __launch_bounds__(256) k_adj_mix(Geo g, long n0, long n1, long n2, long n3, long n4,
                                                  Fields L, Fields mu1, Fields ubb, Fields Lnew, Fields lam,
-                                                 int fold) {
+                                                 int fold, int first) {
   long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
   const long ns[5] = {n0, n1, n2, n3, n4};
   int f = 0;
@@ -1220,20 +1221,22 @@ __global__ void __launch_bounds__(256) k_adj_mix(Geo g, long n0, long n1, long n
   else if (f == F_UF && !g.periodic) { const long ff = t % g.npf; bnd = ff == 0 || ff == g.np; }
   const double l = fsel(L, f)[t], ub = fsel(ubb, f)[t];
   fsel(ubb, f)[t] = 0.0;
+  const double prev = first ? 0.0 : fsel(lam, f)[t];
   if (fold) {
-    fsel(lam, f)[t] += l + ub;
+    fsel(lam, f)[t] = prev + (l + ub);
     return;
   }
   const double m1 = fsel(mu1, f)[t], hb = 0.5 * ub;
   fsel(Lnew, f)[t] = (bnd ? 0.0 : l) - m1 + hb;
-  fsel(lam, f)[t] += (bnd ? l : 0.0) + m1 + hb;
+  fsel(lam, f)[t] = prev + ((bnd ? l : 0.0) + m1 + hb);
 }
 
 void launch_adj_mix(const Geo &g, const long *cnt, const Fields &L, const Fields &mu1, const Fields &ubb,
-                    const Fields &Lnew, const Fields &lam, bool fold, hipStream_t st) {
+                    const Fields &Lnew, const Fields &lam, bool fold, bool first, hipStream_t st) {
   const long tot = cnt[0] + cnt[1] + cnt[2] + cnt[3] + cnt[4];
   hipLaunchKernelGGL(k_adj_mix, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, g, cnt[0], cnt[1],
-                     cnt[2], cnt[3], cnt[4], L, mu1, ubb, Lnew, lam, fold ? 1 : 0);
+                     cnt[2], cnt[3], cnt[4], L, mu1, ubb, Lnew, lam, fold ? 1 : 0,
+                     first ? 1 : 0);
 }
 
 } // namespace dsw

@@ -28,7 +28,7 @@ struct dsw_grid {
   Scratch sc{};
   double *scratch_mem = nullptr;
   double *adj_mem = nullptr; // adjoint workspace, allocated on first use
-  int adj_K = 0;
+  int adj_states = 0;         // five-field states it holds
   // the adjoint's second stream (non-blocking, default priority), its
   // fork/join events and the sweep scratch of the work it runs
   hipStream_t side = nullptr;
@@ -720,26 +720,23 @@ extern "C" int dsw_residual_vjp(dsw_grid *G, const dsw_fields *Ubar, double tau,
   return check_launch("residual vjp kernel");
 }
 
-// adjoint workspace: per iteration Ubar, X1, X2, X3; the running iterate; two
-// cotangents of the iterate; mu3, mu2, mu1; the cotangent of Ubar (K = 0: the
-// last seven only, for a reverse from a tape); after the states, the sweep
-// scratch of the second stream
-static int adj_workspace(dsw_grid *G, int K, std::vector<Fields> &ws) {
+// adjoint workspace: nstates five-field states (their use is the caller's),
+// then the sweep scratch of the second stream
+static int adj_workspace(dsw_grid *G, int nstates, std::vector<Fields> &ws) {
   const long per = G->count[0] + G->count[1] + G->count[2] + G->count[3] + G->count[4];
-  const int nstates = 4 * K + 7;
   const long extra = G->sc.blk_len + G->sc.sca_len;
-  if (!G->adj_mem || G->adj_K < K) {
+  if (!G->adj_mem || G->adj_states < nstates) {
     if (G->adj_mem) {
       HIPCHK(hipDeviceSynchronize());
       (void)hipFree(G->adj_mem);
       G->adj_mem = nullptr;
-      G->adj_K = 0;
+      G->adj_states = 0;
     }
     if (hipMalloc(&G->adj_mem, ((size_t)nstates * per + extra) * sizeof(double)) != hipSuccess) {
       G->adj_mem = nullptr;
       return fail(DSW_ENOMEM, "adjoint workspace");
     }
-    G->adj_K = K;
+    G->adj_states = nstates;
   }
   // non-blocking: no implicit ordering against a caller's null stream
   if (!G->side && hipStreamCreateWithFlags(&G->side, hipStreamNonBlocking) != hipSuccess) {
@@ -757,8 +754,8 @@ static int adj_workspace(dsw_grid *G, int K, std::vector<Fields> &ws) {
   long off = 0;
   ws.clear();
   for (int q = 0; q < nstates; q++) ws.push_back(carve(G->adj_mem, G->count, &off));
-  // the states of the largest K allocated so far come first
-  double *s2 = G->adj_mem + (size_t)(4 * G->adj_K + 7) * per;
+  // the states of the largest workspace allocated so far come first
+  double *s2 = G->adj_mem + (size_t)G->adj_states * per;
   G->sc2.blk = s2;
   G->sc2.sca = s2 + G->sc.blk_len;
   G->sc2.blk_len = G->sc.blk_len;
@@ -771,6 +768,18 @@ static int adj_workspace(dsw_grid *G, int K, std::vector<Fields> &ws) {
 struct Tape {
   std::vector<Fields> ub, x1, x2, x3;
 };
+
+// a tape held in workspace states q0 .. q0 + 4K - 1, in carve_tape's order
+static Tape tape_from(const std::vector<Fields> &ws, int q0, int K, const Fields &un) {
+  Tape t;
+  for (int k = 0; k < K; k++) {
+    t.ub.push_back(k == 0 ? un : ws[q0 + 4 * k]);
+    t.x1.push_back(ws[q0 + 4 * k + 1]);
+    t.x2.push_back(ws[q0 + 4 * k + 2]);
+    t.x3.push_back(ws[q0 + 4 * k + 3]);
+  }
+  return t;
+}
 
 // 4K states carved from one buffer: Ubar (the slot of k = 0 unused), X1, X2, X3
 static Tape carve_tape(double *base, const long *cnt, int K, const Fields &un) {
@@ -808,8 +817,10 @@ static void adj_record_bnd(const dsw_grid *G, const Fields &un, int K, const Tap
   }
 }
 
+// scr: the sweep scratch of the line solves (the grid's, or the second
+// stream's)
 static void adj_record_iter(const dsw_grid *G, const Fields &un, double tau, int K, int k, const Tape &t,
-                            const Fields &U, hipStream_t st) {
+                            const Fields &U, const Scratch &scr, hipStream_t st) {
   const Fields none{};
   const Fields ubk = t.ub[k];
   Pass r{G->geo.periodic ? PK_RES_INP : PK_RES_IN, 0, base_args(G)};
@@ -828,15 +839,21 @@ static void adj_record_iter(const dsw_grid *G, const Fields &un, double tau, int
   o3.un = un;
   o3.ub = k < K - 1 ? t.ub[k + 1] : none;
   o3.raw = t.x3[k];
-  launch_single(G, sweep_pass(G, 0, ubk, tau, G->r, o1), st);
-  launch_single(G, sweep_pass(G, 1, ubk, tau, t.x1[k], o2), st);
-  launch_single(G, sweep_pass(G, 2, ubk, tau, t.x2[k], o3), st);
+  auto sw = [&](int d, const Fields &rhs, const Out &o) {
+    Pass p = sweep_pass(G, d, ubk, tau, rhs, o);
+    p.a.scb = scr.blk;
+    p.a.scs = scr.sca;
+    return p;
+  };
+  launch_single(G, sw(0, G->r, o1), st);
+  launch_single(G, sw(1, t.x1[k], o2), st);
+  launch_single(G, sw(2, t.x2[k], o3), st);
 }
 
 static void adj_record(const dsw_grid *G, const Fields &un, double tau, int K, const Tape &t,
-                       const Fields &U, hipStream_t st) {
+                       const Fields &U, const Scratch &scr, hipStream_t st) {
   adj_record_bnd(G, un, K, t, U, st);
-  for (int k = 0; k < K; k++) adj_record_iter(G, un, tau, K, k, t, U, st);
+  for (int k = 0; k < K; k++) adj_record_iter(G, un, tau, K, k, t, U, scr, st);
 }
 
 // The reverse sweep (reverse of every statement of adj_record, last
@@ -850,12 +867,14 @@ struct Rev {
   Fields L, Lnext;
 };
 
-static Rev adj_reverse_init(const dsw_grid *G, const Fields &un, const Fields &lam_np1, const Fields &lam_n,
-                            const Fields *sc, hipStream_t st) {
+// The mix of the last iteration (the first one reversed) writes lam_n; the
+// cotangent of Ubar accumulates from zero, and every mix leaves it zero:
+// zero_ubb clears it first (a call's first reverse).
+static Rev adj_reverse_init(const dsw_grid *G, const Fields &un, const Fields &lam_np1, const Fields *sc,
+                            bool zero_ubb, hipStream_t st) {
   const Fields none{};
   Rev v{sc[0], sc[1], sc[2], sc[3], sc[4], sc[5], lam_np1, sc[0]};
-  launch_axpy3(G->count, 0.0, un, 0.0, none, 0.0, none, lam_n, st);  // lam_n = 0
-  launch_axpy3(G->count, 0.0, un, 0.0, none, 0.0, none, v.UBB, st);  // Ubar cotangent = 0
+  if (zero_ubb) launch_axpy3(G->count, 0.0, un, 0.0, none, 0.0, none, v.UBB, st);
   return v;
 }
 
@@ -879,23 +898,24 @@ static void adj_reverse_solves(const dsw_grid *G, double tau, int k, const Tape 
   launch_T(G, 0, pass(0, v.M2), st);
 }
 
-static void adj_reverse_local(const dsw_grid *G, double tau, int k, const Tape &t, Rev &v,
+static void adj_reverse_local(const dsw_grid *G, double tau, int K, int k, const Tape &t, Rev &v,
                               const Fields &lam_n, hipStream_t st) {
   const Fields xs[3] = {t.x1[k], t.x2[k], t.x3[k]}, mus[3] = {v.M1, v.M2, v.M3};
   launch_adj_local(G->geo, G->m, t.ub[k], tau, xs, mus, v.UBB, st);
   // also clears UBB; at k = 0 it adds the cotangent of U^{n+1,0} = U^n
   // to lam_n as well
-  launch_adj_mix(G->geo, G->count, v.L, v.M1, v.UBB, v.Lnext, lam_n, k == 0, st);
+  launch_adj_mix(G->geo, G->count, v.L, v.M1, v.UBB, v.Lnext, lam_n, k == 0, k == K - 1, st);
   v.L = v.Lnext;
   v.Lnext = (v.Lnext.p == v.La.p) ? v.Lb : v.La;
 }
 
 static void adj_reverse(const dsw_grid *G, const Fields &un, double tau, int K, const Tape &t,
-                        const Fields &lam_np1, const Fields &lam_n, const Fields *sc, hipStream_t st) {
-  Rev v = adj_reverse_init(G, un, lam_np1, lam_n, sc, st);
+                        const Fields &lam_np1, const Fields &lam_n, const Fields *sc, bool zero_ubb,
+                        hipStream_t st) {
+  Rev v = adj_reverse_init(G, un, lam_np1, sc, zero_ubb, st);
   for (int k = K - 1; k >= 0; k--) {
     adj_reverse_solves(G, tau, k, t, v, G->sc, st);
-    adj_reverse_local(G, tau, k, t, v, lam_n, st);
+    adj_reverse_local(G, tau, K, k, t, v, lam_n, st);
   }
 }
 
@@ -916,31 +936,32 @@ extern "C" int dsw_adjoint_step(dsw_grid *G, const dsw_fields *Un, double tau, i
                                 const dsw_fields *lam_np1, dsw_fields *lam_n, void *stream) {
   int rc;
   if ((rc = check_adjoint_args(G, Un, tau, K, lam_np1, lam_n))) return rc;
+  // workspace: the tape (4K states), the running iterate, the reverse's six
   std::vector<Fields> ws;
-  if ((rc = adj_workspace(G, K, ws))) return rc;
+  if ((rc = adj_workspace(G, 4 * K + 7, ws))) return rc;
   hipStream_t st = (hipStream_t)stream;
   const Fields un = F(Un);
-  const Tape t = carve_tape(G->adj_mem, G->count, K, un);
+  const Tape t = tape_from(ws, 0, K, un);
   const Fields U = ws[4 * K];
   // forward recompute from the checkpoint into the workspace's iterate,
   // up to the midpoint of the last iteration
   adj_record_bnd(G, un, K, t, U, st);
-  for (int k = 0; k < K - 1; k++) adj_record_iter(G, un, tau, K, k, t, U, st);
+  for (int k = 0; k < K - 1; k++) adj_record_iter(G, un, tau, K, k, t, U, G->sc, st);
   // The last iteration's transposed solves read only its midpoint and
   // lam_np1: they run on the second stream (with a sweep scratch of their
   // own) while the forward finishes that iteration, whose X1, X2, X3 the
   // rest of the reverse needs.  The two sides write disjoint buffers.
   HIPCHK(hipEventRecord(G->fork_ev, st));
   HIPCHK(hipStreamWaitEvent(G->side, G->fork_ev, 0));
-  Rev v = adj_reverse_init(G, un, F(lam_np1), F(lam_n), &ws[4 * K + 1], G->side);
+  Rev v = adj_reverse_init(G, un, F(lam_np1), &ws[4 * K + 1], true, G->side);
   adj_reverse_solves(G, tau, K - 1, t, v, G->sc2, G->side);
   HIPCHK(hipEventRecord(G->join_ev, G->side));
-  adj_record_iter(G, un, tau, K, K - 1, t, U, st);
+  adj_record_iter(G, un, tau, K, K - 1, t, U, G->sc, st);
   HIPCHK(hipStreamWaitEvent(st, G->join_ev, 0));
-  adj_reverse_local(G, tau, K - 1, t, v, F(lam_n), st);
+  adj_reverse_local(G, tau, K, K - 1, t, v, F(lam_n), st);
   for (int k = K - 2; k >= 0; k--) {
     adj_reverse_solves(G, tau, k, t, v, G->sc, st);
-    adj_reverse_local(G, tau, k, t, v, F(lam_n), st);
+    adj_reverse_local(G, tau, K, k, t, v, F(lam_n), st);
   }
   return check_launch("adjoint step kernels");
 }
@@ -962,7 +983,7 @@ extern "C" int dsw_split_step_taped(dsw_grid *G, const dsw_fields *Un, dsw_field
   hipStream_t st = (hipStream_t)stream;
   const Fields un = F(Un);
   const Tape t = carve_tape((double *)tape, G->count, K, un);
-  adj_record(G, un, tau, K, t, F(Unp1), st);
+  adj_record(G, un, tau, K, t, F(Unp1), G->sc, st);
   return check_launch("taped split step kernels");
 }
 
@@ -973,12 +994,55 @@ extern "C" int dsw_adjoint_step_taped(dsw_grid *G, const dsw_fields *Un, double 
   if ((rc = check_adjoint_args(G, Un, tau, K, lam_np1, lam_n))) return rc;
   if (!tape || ((uintptr_t)tape % sizeof(double)) != 0) return fail(DSW_EINVAL, "tape must be a non-null 8-byte aligned pointer");
   std::vector<Fields> ws;
-  if ((rc = adj_workspace(G, 0, ws))) return rc;
+  if ((rc = adj_workspace(G, 6, ws))) return rc;
   hipStream_t st = (hipStream_t)stream;
   const Fields un = F(Un);
   const Tape t = carve_tape((double *)const_cast<void *>(tape), G->count, K, un);
-  adj_reverse(G, un, tau, K, t, F(lam_np1), F(lam_n), &ws[1], st);
+  adj_reverse(G, un, tau, K, t, F(lam_np1), F(lam_n), &ws[0], true, st);
   return check_launch("taped adjoint step kernels");
+}
+
+// The adjoint of nsteps consecutive split steps from their checkpoints.
+// Step n - 1 is recomputed into one of two tapes on the second stream (with
+// its own sweep scratch) while the reverse of step n runs from the other
+// tape on the caller's stream.  A tape is overwritten only after the
+// reverse that read it: the second stream waits for everything enqueued on
+// the caller's stream before each recompute.
+extern "C" int dsw_adjoint_trajectory(dsw_grid *G, const dsw_fields *ckpts, int32_t nsteps, double tau,
+                                      int32_t K, const dsw_fields *lam_end, dsw_fields *lam_0,
+                                      void *stream) {
+  if (!G) return fail(DSW_EINVAL, "null handle");
+  if (!ckpts || nsteps < 1) return fail(DSW_EINVAL, "need nsteps >= 1 checkpoints");
+  int rc;
+  if ((rc = check_adjoint_args(G, &ckpts[0], tau, K, lam_end, lam_0))) return rc;
+  for (int n = 0; n < nsteps; n++) {
+    if ((rc = check_fields(&ckpts[n], "checkpoint"))) return rc;
+    if (ckpts[n].p == lam_0->p) return fail(DSW_EINVAL, "lam_0 must not alias a checkpoint");
+  }
+  // workspace: two tapes, the running iterate, the reverse's six states,
+  // two cotangents of the step states
+  std::vector<Fields> ws;
+  if ((rc = adj_workspace(G, 8 * K + 9, ws))) return rc;
+  hipStream_t st = (hipStream_t)stream;
+  const Fields U = ws[8 * K];
+  const Fields *sc = &ws[8 * K + 1];
+  const Fields P[2] = {ws[8 * K + 7], ws[8 * K + 8]};
+  auto tape = [&](int n) { return tape_from(ws, (n & 1) ? 4 * K : 0, K, F(&ckpts[n])); };
+  adj_record(G, F(&ckpts[nsteps - 1]), tau, K, tape(nsteps - 1), U, G->sc, st);
+  Fields lin = F(lam_end);
+  for (int n = nsteps - 1; n >= 0; n--) {
+    if (n >= 1) {
+      HIPCHK(hipEventRecord(G->fork_ev, st));
+      HIPCHK(hipStreamWaitEvent(G->side, G->fork_ev, 0));
+      adj_record(G, F(&ckpts[n - 1]), tau, K, tape(n - 1), U, G->sc2, G->side);
+      HIPCHK(hipEventRecord(G->join_ev, G->side));
+    }
+    const Fields lout = n == 0 ? F(lam_0) : P[n & 1];
+    adj_reverse(G, F(&ckpts[n]), tau, K, tape(n), lin, lout, sc, n == nsteps - 1, st);
+    lin = lout;
+    if (n >= 1) HIPCHK(hipStreamWaitEvent(st, G->join_ev, 0));
+  }
+  return check_launch("adjoint trajectory kernels");
 }
 
 // ------------------------------------------------------------- ensembles --

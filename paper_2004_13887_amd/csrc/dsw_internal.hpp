@@ -177,7 +177,7 @@ void launch_adj_local(const Geo &g, const Mat &m, const Fields &Ub, double tau, 
 void launch_axpy3(const long *cnt, double a, const Fields &x, double b, const Fields &y, double c,
                   const Fields &z, const Fields &out, hipStream_t st);
 void launch_adj_mix(const Geo &g, const long *cnt, const Fields &L, const Fields &mu1, const Fields &ubb,
-                    const Fields &Lnew, const Fields &lam, bool fold, hipStream_t st);
+                    const Fields &Lnew, const Fields &lam, bool fold, bool first, hipStream_t st);
 
 // public residual: forms the midpoint on the fly from Un and Uk and writes it
 void launch_residual(const Geo &g, const Mat &m, const Fields &Un, const Fields &Uk, double tau,

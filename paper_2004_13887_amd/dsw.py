@@ -31,7 +31,7 @@ SYMBOLS = ("dsw_init_grid", "dsw_free_grid", "dsw_layout", "dsw_residual", "dsw_
            "dsw_ensemble_get_status", "dsw_adjoint_step", "dsw_line_solve_T_r",
            "dsw_line_solve_T_theta", "dsw_line_solve_T_phi", "dsw_line_vjp_r", "dsw_line_vjp_theta",
            "dsw_line_vjp_phi", "dsw_residual_vjp", "dsw_split_step_forced", "dsw_tape_bytes", "dsw_split_step_taped",
-           "dsw_adjoint_step_taped", "dsw_last_error")
+           "dsw_adjoint_step_taped", "dsw_adjoint_trajectory", "dsw_last_error")
 TIMING_KINDS = ("residual", "sweep_r", "sweep_theta", "sweep_phi_update", "boundary_copy")
 
 
@@ -124,6 +124,7 @@ def lib():
         L.dsw_tape_bytes.argtypes = [P, I, C.POINTER(C.c_int64)]
         L.dsw_split_step_taped.argtypes = [P, FP, FP, D, I, P, P]
         L.dsw_adjoint_step_taped.argtypes = [P, FP, D, I, P, FP, FP, P]
+        L.dsw_adjoint_trajectory.argtypes = [P, FP, I, D, I, FP, FP, P]
         L.dsw_last_error.restype = C.c_char_p
         for n in SYMBOLS[:-1]:
             getattr(L, n).restype = C.c_int
@@ -208,6 +209,14 @@ class Grid:
         _check(lib().dsw_adjoint_step(self._h, C.byref(_fields(Un)), float(tau), int(K),
                                       C.byref(_fields(lam_np1)), C.byref(_fields(lam_n)),
                                       _stream(stream)))
+
+    def adjoint_trajectory(self, ckpts, tau, K, lam_end, lam_0, stream=None):
+        """lam_0 = J(U^0)^T ... J(U^{N-1})^T lam_end over the N steps whose
+        starting states ckpts holds (a list of field dicts, U^0 first)."""
+        arr = (Fields * len(ckpts))(*[_fields(u) for u in ckpts])
+        _check(lib().dsw_adjoint_trajectory(self._h, arr, len(ckpts), float(tau), int(K),
+                                            C.byref(_fields(lam_end)), C.byref(_fields(lam_0)),
+                                            _stream(stream)))
 
     def line_solve_T(self, d, Ubar, tau, rhs, x, stream=None):
         fn = ("dsw_line_solve_T_r", "dsw_line_solve_T_theta", "dsw_line_solve_T_phi")[d]

@@ -226,3 +226,52 @@ def test_autograd_taped(dsw):
     e = max(np.linalg.norm(grads[0][k] - grads[1][k]) / np.linalg.norm(grads[0][k]) for k in FIELDS)
     print(f"autograd taped vs recomputed: rel L2 {e:.2e}", flush=True)
     assert e <= 1e-12
+
+
+@pytest.mark.parametrize("name,nsteps", [("parity", 3), ("sphere-ragged", 3), ("sector-min", 1)])
+def test_adjoint_trajectory(name, nsteps, dsw):
+    """dsw_adjoint_trajectory over N steps from per-step checkpoints: the
+    oracle's dot-product identity <lam_0, V> = <lam_end, J_{N-1} ... J_0 V>
+    (the checkpoints are the oracle's own states, the J V products its
+    complex-step JVPs), and N chained dsw_adjoint_step calls up to the order
+    of the atomic sums; a second call gives the same result"""
+    print(f"[trajectory] {name} N={nsteps}", flush=True)
+    w, U0, tau, og, om, gg = _setup(name, dsw)
+    V = direction(w.grid, 131)
+    states, dU = [U0], V
+    for _ in range(nsteps):
+        U1, dU = oracle.jvp_split_step(og, om, states[-1], dU, tau, w.K)
+        states.append(U1)
+    ck = [dsw.to_device(u) for u in states[:-1]]
+    lam = cotangent(w.grid, 132)
+    lam_d = dsw.to_device(lam)
+    t1, t2 = gg.empty(), gg.empty()
+    gg.adjoint_trajectory(ck, tau, w.K, lam_d, t1)
+    gg.adjoint_trajectory(ck, tau, w.K, lam_d, t2)
+    chained = lam_d
+    for n in range(nsteps - 1, -1, -1):
+        nxt = gg.empty()
+        gg.adjoint_step(ck[n], tau, w.K, chained, nxt)
+        chained = nxt
+    torch.cuda.synchronize()
+    gg.get_status()
+    h1, h2, hc = dsw.to_host(t1), dsw.to_host(t2), dsw.to_host(chained)
+    for other, tag in ((hc, "chained adjoint_step"), (h2, "second call")):
+        e = max(np.linalg.norm(h1[k] - other[k]) / max(np.linalg.norm(other[k]), 1e-300) for k in FIELDS)
+        print(f"{name}: trajectory vs {tag} rel L2 {e:.2e}", flush=True)
+        assert e <= 1e-12
+    check_dot(f"{name} trajectory J^T (N={nsteps}, K={w.K})", dot(h1, V), dot(lam, dU))
+
+
+def test_adjoint_trajectory_bad_args(dsw):
+    w, U0, tau, og, om, gg = _setup("sector-min", dsw)
+    ck = [dsw.to_device(U0)]
+    lam, out = dsw.to_device(cotangent(w.grid, 141)), gg.empty()
+    for tag, call in (("no checkpoints", lambda: gg.adjoint_trajectory([], tau, w.K, lam, out)),
+                      ("lam_0 is a checkpoint", lambda: gg.adjoint_trajectory(ck, tau, w.K, lam, ck[0])),
+                      ("K=0", lambda: gg.adjoint_trajectory(ck, tau, 0, lam, out)),
+                      ("lam_0 is lam_end", lambda: gg.adjoint_trajectory(ck, tau, w.K, lam, lam))):
+        with pytest.raises(dsw.DswError) as ei:
+            call()
+        assert ei.value.code == dsw.DSW_EINVAL, tag
+        print(f"{tag}: {ei.value}", flush=True)
