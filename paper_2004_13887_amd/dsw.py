@@ -165,6 +165,9 @@ class Grid:
             return
         h = C.c_void_p()
         _check(lib().dsw_init_grid(C.byref(self.desc), C.byref(self.mat), C.byref(h)))
+        # kept on the object: at interpreter exit the module's globals may be
+        # gone before the finaliser runs
+        self._free = lib().dsw_free_grid
         self._h, self._owned = h, True
 
     @classmethod
@@ -173,7 +176,7 @@ class Grid:
 
     def free_grid(self):
         if getattr(self, "_h", None) and getattr(self, "_owned", False):
-            lib().dsw_free_grid(self._h)
+            self._free(self._h)
         self._h = None
 
     __del__ = free_grid
@@ -337,6 +340,7 @@ class Ensemble:
             mats[q] = Material(*m.astuple())
         h = C.c_void_p()
         _check(lib().dsw_ensemble_create(descs, mats, n, C.byref(h)))
+        self._free = lib().dsw_ensemble_free  # as for Grid
         self._h = h
         self.n = n
         self.members = []
@@ -349,7 +353,7 @@ class Ensemble:
         if getattr(self, "_h", None):
             for g in self.members:
                 g._h = None
-            lib().dsw_ensemble_free(self._h)
+            self._free(self._h)
             self._h = None
 
     __del__ = ensemble_free
