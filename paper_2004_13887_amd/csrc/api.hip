@@ -1050,7 +1050,8 @@ extern "C" int dsw_adjoint_trajectory(dsw_grid *G, const dsw_fields *ckpts, int3
 struct dsw_ensemble {
   std::vector<dsw_grid *> mem;
   Cfg cfg{64, {256, 256}, 4};
-  hipStream_t cap = nullptr; // capture stream
+  hipStream_t cap = nullptr, cap2 = nullptr;  // capture streams of the two lanes
+  hipEvent_t fork = nullptr, stagger = nullptr, join = nullptr;
   // one launch of a batched plan
   struct Group {
     int kind, tk;
@@ -1065,7 +1066,7 @@ struct dsw_ensemble {
   };
   struct Entry {
     std::vector<uint64_t> key;
-    Plan plan;
+    Plan plan[2];  // the two lanes' plans (plan[1] empty with one member)
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     uint64_t used = 0;
@@ -1085,7 +1086,8 @@ static void drop_entry(dsw_ensemble::Entry &e) {
   if (e.graph) (void)hipGraphDestroy(e.graph);
   e.exec = nullptr;
   e.graph = nullptr;
-  free_plan(e.plan);
+  free_plan(e.plan[0]);
+  free_plan(e.plan[1]);
 }
 
 extern "C" int dsw_ensemble_create(const dsw_grid_desc *descs, const dsw_material *mats, int32_t n,
@@ -1104,9 +1106,13 @@ extern "C" int dsw_ensemble_create(const dsw_grid_desc *descs, const dsw_materia
     }
     E->mem.push_back(G);
   }
-  if (hipStreamCreateWithFlags(&E->cap, hipStreamNonBlocking) != hipSuccess) {
+  if (hipStreamCreateWithFlags(&E->cap, hipStreamNonBlocking) != hipSuccess ||
+      hipStreamCreateWithFlags(&E->cap2, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&E->fork, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&E->stagger, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&E->join, hipEventDisableTiming) != hipSuccess) {
     dsw_ensemble_free(E);
-    return fail(DSW_EHIP, "capture stream");
+    return fail(DSW_EHIP, "capture streams");
   }
   *out = E;
   return DSW_OK;
@@ -1117,6 +1123,10 @@ extern "C" int dsw_ensemble_free(dsw_ensemble *E) {
   (void)hipDeviceSynchronize();
   for (auto &e : E->cache) drop_entry(e);
   if (E->cap) (void)hipStreamDestroy(E->cap);
+  if (E->cap2) (void)hipStreamDestroy(E->cap2);
+  if (E->fork) (void)hipEventDestroy(E->fork);
+  if (E->stagger) (void)hipEventDestroy(E->stagger);
+  if (E->join) (void)hipEventDestroy(E->join);
   for (dsw_grid *G : E->mem) dsw_free_grid(G);
   delete E;
   return DSW_OK;
@@ -1143,17 +1153,22 @@ static int check_ens_args(dsw_ensemble *E, const dsw_fields *Un, dsw_fields *Unp
   return DSW_OK;
 }
 
-// Batched plan of one ensemble step: pass q of every member's plan goes into
-// one launch (two for the phi pass when members differ in solver kind).
+// Batched plan of one ensemble step over the members ids (all members when
+// empty): pass q of every member's plan goes into one launch (two for the
+// phi pass when members differ in solver kind).
 static int build_plan(dsw_ensemble *E, const Cfg &cfg, const dsw_fields *Un, dsw_fields *Unp1,
-                      const double *tau, int K, dsw_ensemble::Plan &plan) {
-  const int n = (int)E->mem.size();
+                      const double *tau, int K, dsw_ensemble::Plan &plan,
+                      std::vector<int> ids = std::vector<int>()) {
+  if (ids.empty())
+    for (int m = 0; m < (int)E->mem.size(); m++) ids.push_back(m);
+  const int n = (int)ids.size();
+  std::vector<dsw_grid *> mem(n);
   std::vector<std::vector<Pass>> per(n);
   for (int m = 0; m < n; m++) {
-    dsw_grid *G = E->mem[m];
+    dsw_grid *G = mem[m] = E->mem[ids[m]];
     const Cfg keep = G->cfg;
     G->cfg = cfg;
-    plan_step(G, F(&Un[m]), F(&Unp1[m]), tau[m], K, per[m]);
+    plan_step(G, F(&Un[ids[m]]), F(&Unp1[ids[m]]), tau[ids[m]], K, per[m]);
     G->cfg = keep;
   }
   const size_t npass = per[0].size();
@@ -1174,25 +1189,25 @@ static int build_plan(dsw_ensemble *E, const Cfg &cfg, const dsw_fields *Un, dsw
       std::vector<unsigned> widths;
       for (int m = 0; m < n; m++) {
         if (per[m][q].kind != kind) continue;
-        const unsigned w0 = kind_threads(kind, E->mem[m]->geo, cfg);
+        const unsigned w0 = kind_threads(kind, mem[m]->geo, cfg);
         if (std::find(widths.begin(), widths.end(), w0) == widths.end()) widths.push_back(w0);
       }
       for (const unsigned width : widths) {
       std::vector<int> who;
       for (int m = 0; m < n; m++)
-        if (per[m][q].kind == kind && kind_threads(kind, E->mem[m]->geo, cfg) == width) who.push_back(m);
+        if (per[m][q].kind == kind && kind_threads(kind, mem[m]->geo, cfg) == width) who.push_back(m);
       unsigned th = 0;
       size_t lds = 0;
       for (int m : who) {
-        th = std::max(th, kind_threads(kind, E->mem[m]->geo, cfg));
-        lds = std::max(lds, kind_lds(kind, E->mem[m]->geo, cfg));
+        th = std::max(th, kind_threads(kind, mem[m]->geo, cfg));
+        lds = std::max(lds, kind_lds(kind, mem[m]->geo, cfg));
       }
       std::vector<PassArgs> tab;
       std::vector<unsigned> woff(1, 0u);
       unsigned long total = 0;
       for (int m : who) {
         tab.push_back(per[m][q].a);
-        total += kind_blocks(kind, E->mem[m]->geo, th);
+        total += kind_blocks(kind, mem[m]->geo, th);
         if (total > 0x7fffffffUL) return fail(DSW_EINVAL, "ensemble too large for one launch");
         woff.push_back((unsigned)total);
       }
@@ -1218,12 +1233,14 @@ static int build_plan(dsw_ensemble *E, const Cfg &cfg, const dsw_fields *Un, dsw
   return DSW_OK;
 }
 
-// enqueue a batched plan; ev (optional) receives one event pair per group
+// enqueue groups [g0, g1) of a batched plan (g1 < 0: to the end); ev
+// (optional) receives one event pair per group
 static void enqueue_plan(const dsw_ensemble::Plan &plan, const Cfg &cfg, hipStream_t st,
-                         std::vector<std::pair<hipEvent_t, hipEvent_t>> *ev) {
+                         std::vector<std::pair<hipEvent_t, hipEvent_t>> *ev, size_t g0 = 0, long g1 = -1) {
   PassArgs dummy;
   std::memset(&dummy, 0, sizeof(dummy));
-  for (size_t q = 0; q < plan.groups.size(); q++) {
+  const size_t end = g1 < 0 ? plan.groups.size() : (size_t)g1;
+  for (size_t q = g0; q < end; q++) {
     const auto &gr = plan.groups[q];
     const Batch b{(CPassArgs *)(plan.dev + gr.tab_off), (const unsigned *)(plan.dev + gr.woff_off),
                   gr.n};
@@ -1270,9 +1287,48 @@ extern "C" int dsw_ensemble_step(dsw_ensemble *E, const dsw_fields *Un, dsw_fiel
     }
     dsw_ensemble::Entry e;
     e.key = key;
-    if ((rc = build_plan(E, E->cfg, Un, Unp1, tau, K, e.plan))) return rc;
+    // Two lanes of members, balanced by cells: the graph runs each lane's
+    // batched launches in order, the second lane starting when the first
+    // one's first residual launch has ended, so that one lane's residual
+    // (bound by load latency) runs beside the other's sweeps (bound by HBM).
+    // Members share no buffers: the lanes need no other ordering.
+    const int n = (int)E->mem.size();
+    std::vector<int> lane[2];
+    {
+      std::vector<int> order(n);
+      for (int m = 0; m < n; m++) order[m] = m;
+      std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+        return E->mem[x]->count[0] > E->mem[y]->count[0];
+      });
+      long load[2] = {0, 0};
+      for (int m : order) {
+        const int l = load[1] < load[0] ? 1 : 0;
+        lane[l].push_back(m);
+        load[l] += E->mem[m]->count[0];
+      }
+      for (auto &v : lane) std::sort(v.begin(), v.end());
+    }
+    if ((rc = build_plan(E, E->cfg, Un, Unp1, tau, K, e.plan[0], lane[0]))) return rc;
+    if (!lane[1].empty() && (rc = build_plan(E, E->cfg, Un, Unp1, tau, K, e.plan[1], lane[1]))) {
+      drop_entry(e);
+      return rc;
+    }
     HIPCHK(hipStreamBeginCapture(E->cap, hipStreamCaptureModeThreadLocal));
-    enqueue_plan(e.plan, E->cfg, E->cap, nullptr);
+    if (lane[1].empty()) {
+      enqueue_plan(e.plan[0], E->cfg, E->cap, nullptr);
+    } else {
+      size_t s0 = 0;  // lane 0's groups up to its first r sweep
+      while (s0 < e.plan[0].groups.size() && e.plan[0].groups[s0].tk != 1) s0++;
+      (void)hipEventRecord(E->fork, E->cap);
+      (void)hipStreamWaitEvent(E->cap2, E->fork, 0);
+      enqueue_plan(e.plan[0], E->cfg, E->cap, nullptr, 0, (long)s0);
+      (void)hipEventRecord(E->stagger, E->cap);
+      (void)hipStreamWaitEvent(E->cap2, E->stagger, 0);
+      enqueue_plan(e.plan[1], E->cfg, E->cap2, nullptr);
+      (void)hipEventRecord(E->join, E->cap2);
+      enqueue_plan(e.plan[0], E->cfg, E->cap, nullptr, s0);
+      (void)hipStreamWaitEvent(E->cap, E->join, 0);
+    }
     const hipError_t ce = hipStreamEndCapture(E->cap, &e.graph);
     if (ce != hipSuccess) {
       drop_entry(e);
