@@ -185,9 +185,13 @@ int dsw_read_timing(dsw_grid *grid, void *stream, double ms[DSW_TIMING_KINDS],
  *   boundary-normal faces included: their entries of U^{n+1} are copies of
  *   those of U^n).  Un is the checkpoint of the step; the forward step is
  *   recomputed from it, keeping each iteration's midpoint and line-solve
- *   outputs in a workspace of 4K+7 states that the handle allocates on the
- *   first call (and grows for a larger K).  lam_n must not alias Un or
- *   lam_np1.  tau, K: those of the forward step.
+ *   outputs in a workspace of 4K+7 states and a second sweep scratch that
+ *   the handle allocates on the first call (and grows for a larger K).  The
+ *   last iteration's transposed solves run on a second stream of the handle
+ *   (non-blocking, default priority) beside the recompute's last iteration;
+ *   the call orders that work before its later work on `stream`, so the
+ *   caller sees one stream.  lam_n must not alias Un or lam_np1.  tau, K:
+ *   those of the forward step.
  *
  * The pieces, exported for tests and for custom reverse passes:
  * dsw_line_solve_T_{r,theta,phi}: x = (I + tau/2 D_d(Ubar))^{-T} rhs, the
@@ -279,9 +283,12 @@ int dsw_get_config(const dsw_grid *grid, dsw_config *cfg);
  * Each member is a full grid handle with its own workspace; a step of the
  * ensemble computes exactly what dsw_split_step computes for every member
  * (paper section 2.2, eqs. (spl1)-(spl3) iterated K times), with one launch
- * per pass covering all members (workgroups mapped to members by a table of
- * offsets) instead of one launch per member and pass, and the whole step
- * captured once in a HIP graph and replayed.
+ * per pass covering all members of a lane (workgroups mapped to members by
+ * a table of offsets) instead of one launch per member and pass, and the
+ * whole step captured once in a HIP graph and replayed.  The graph holds two
+ * lanes of members (balanced by cells) as two chains of launches, the
+ * second starting after the first lane's first residual launch, so that
+ * their passes overlap; the graph runs on the caller's stream as one unit.
  *
  * dsw_ensemble_create: descs and mats are arrays of n (n >= 1).
  * dsw_ensemble_member: borrowed handle of member m (valid until the ensemble
