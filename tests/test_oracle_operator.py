@@ -147,16 +147,26 @@ def _reflect_phi(U):
             "uf": -U["uf"][:, :, ::-1].copy()}
 
 
+def _reflect_phi_periodic(U):
+    """phi -> 2 pi - phi on the full sphere: cell k -> np - 1 - k, and the
+    periodic phi face kf (np of them, face np being face 0) -> (np - kf) mod np,
+    i.e. the reversed face array rolled by one"""
+    return {"p": U["p"][:, :, ::-1].copy(), "T": U["T"][:, :, ::-1].copy(),
+            "ur": U["ur"][:, :, ::-1].copy(), "ut": U["ut"][:, :, ::-1].copy(),
+            "uf": -np.roll(U["uf"][:, :, ::-1], 1, axis=2).copy()}
+
+
 @pytest.mark.parametrize("which", ["sector", "sphere"])
 @pytest.mark.parametrize("refl", ["theta", "phi"])
 def test_mirror_symmetry(which, refl):
-    if which == "sphere" and refl == "phi":
-        pytest.skip("phi reflection of a periodic grid maps faces to shifted faces")
     spec = I.sector(5, 6, 8, 0.004, 0.005) if which == "sector" else I.full_sphere(5, 8, 8)
     g = grid_of(spec)
     from helpers import random_state
     U, tau = random_state(spec, 41, mach=0.05)
-    R = _reflect_theta if refl == "theta" else _reflect_phi
+    if refl == "theta":
+        R = _reflect_theta
+    else:
+        R = _reflect_phi_periodic if which == "sphere" else _reflect_phi
     RU = R(U)
     Us = {k: np.ascontiguousarray(0.5 * (U[k] + RU[k])) for k in U}
     U1 = oracle.split_step(g, AIR, Us, tau, 3)
