@@ -8,9 +8,9 @@ benchmark times, on sampled outputs the oracle computes one by one:
 * transposed line solves (the adjoint's): <M_d^-T y, b> = <y, M_d^-1 b> on
   the whole grid, an identity at any size whose forward side is the solve
   pinned above;
-* properties of the whole step that hold at any size: phi-shift equivariance
-  on the full sphere (exercises the cyclic solves) and the discretely
-  hydrostatic rest state.
+* properties of the whole step that hold at any size: phi-shift and
+  theta/phi mirror equivariance on the full sphere (the poles and the cyclic
+  solves) and the discretely hydrostatic rest state.
 """
 import numpy as np
 import pytest
@@ -191,6 +191,37 @@ def test_full_global_phi_shift_equivariance(dsw):
         d0 = float(torch.linalg.norm((ar - dUs[k]) - (b[k] - dUs[k])) /
                    max(float(torch.linalg.norm(b[k] - dUs[k])), 1e-300))
         print(f"global shift {k}: relL2 {e:.3e}, of the change {d0:.3e}", flush=True)
+        assert e <= 1e-13 and d0 <= 1e-9
+
+
+def _mirror(U, refl):
+    """theta -> pi - theta (cells j -> nt-1-j, theta faces jf -> nt-jf,
+    u_theta changes sign) or phi -> 2 pi - phi on the full sphere (cells
+    k -> np-1-k, periodic phi faces kf -> (np-kf) mod np, u_phi changes sign)"""
+    if refl == "theta":
+        return {k: (-1.0 if k == "ut" else 1.0) * torch.flip(v, dims=[1]).contiguous() for k, v in U.items()}
+    out = {k: torch.flip(v, dims=[2]).contiguous() for k, v in U.items() if k != "uf"}
+    out["uf"] = -torch.roll(torch.flip(U["uf"], dims=[2]), 1, dims=2).contiguous()
+    return out
+
+
+@pytest.mark.parametrize("refl", ["theta", "phi"])
+def test_full_global_mirror_equivariance(refl, dsw):
+    """the step commutes with the mirror maps of the full sphere (gravity
+    radial, no rotation): the poles and the cyclic phi solves at full size"""
+    w, U0, tau, og, om, gg = setup("global", dsw)
+    dU = dsw.to_device(U0)
+    dUm = _mirror(dU, refl)
+    a, b = gg.empty(), gg.empty()
+    gg.split_step(dU, a, tau, w.K)
+    gg.split_step(dUm, b, tau, w.K)
+    torch.cuda.synchronize()
+    gg.get_status()
+    am = _mirror(a, refl)
+    for k in a:
+        e = float(torch.linalg.norm(am[k] - b[k]) / torch.linalg.norm(b[k]))
+        d0 = float(torch.linalg.norm(am[k] - b[k]) / max(float(torch.linalg.norm(b[k] - dUm[k])), 1e-300))
+        print(f"global mirror {refl} {k}: relL2 {e:.3e}, of the change {d0:.3e}", flush=True)
         assert e <= 1e-13 and d0 <= 1e-9
 
 
