@@ -80,3 +80,43 @@ def test_adjoint_gradient_matches_finite_differences(dsw):
                   flush=True)
             assert best <= 1e-6
     print(f"[adjoint fd] worst over 32 directions: {worst:.2e}", flush=True)
+
+
+def test_trajectory_matches_autograd(dsw):
+    """dsw_adjoint_trajectory over the workload's ten checkpoints, started
+    from lam_N = dJ/dU^N, gives the gradient of J with respect to every field
+    of U^0 that the autograd function (one dsw_adjoint_step per step) gives,
+    up to the order of the atomic sums"""
+    w = I.WORKLOADS["adjoint"]
+    mat = w.material
+    U0, tau = I.initial_state(w)
+    grid = dsw.Grid.from_spec(w.grid, mat)
+    wts = torch.as_tensor(I.adjoint_box_weights(w), device="cuda")
+
+    def objective(U):
+        return (wts * (U["T"] / ((U["p"] / I.P00) ** (mat.R / mat.cp)))).sum()
+
+    leaf = {k: v.clone().requires_grad_(True) for k, v in dsw.to_device(U0).items()}
+    U = leaf
+    for _ in range(w.steps):
+        U = dsw.split_step_fn(grid, U, tau, w.K)
+    objective(U).backward()
+    ref = {k: leaf[k].grad.detach() for k in FIELDS}
+    ck = [dsw.to_device(U0)]
+    for _ in range(w.steps):
+        nxt = grid.empty()
+        grid.split_step(ck[-1], nxt, tau, w.K)
+        ck.append(nxt)
+    UN = {k: v.clone().requires_grad_(True) for k, v in ck[-1].items()}
+    objective(UN).backward()
+    lam_end = {k: (UN[k].grad.detach().contiguous() if UN[k].grad is not None else torch.zeros_like(UN[k]))
+               for k in FIELDS}
+    lam0 = grid.empty()
+    grid.adjoint_trajectory(ck[:-1], tau, w.K, lam_end, lam0)
+    torch.cuda.synchronize()
+    grid.get_status()
+    for k in FIELDS:
+        nr = float(torch.linalg.norm(ref[k]))
+        e = float(torch.linalg.norm(lam0[k] - ref[k])) / max(nr, 1e-300)
+        print(f"[trajectory] {k}: |grad| {nr:.3e}, rel L2 vs autograd {e:.2e}", flush=True)
+        assert e <= 1e-12 or nr == 0.0
