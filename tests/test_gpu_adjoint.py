@@ -275,3 +275,34 @@ def test_adjoint_trajectory_bad_args(dsw):
             call()
         assert ei.value.code == dsw.DSW_EINVAL, tag
         print(f"{tag}: {ei.value}", flush=True)
+
+
+def test_adjoint_on_a_caller_stream(dsw):
+    """dsw_adjoint_step and dsw_adjoint_trajectory on a stream of the
+    caller's: their second-stream work is ordered before the caller's next
+    work on that stream (a copy queued right after each call sees the whole
+    result)"""
+    w, U0, tau, og, om, gg = _setup("parity", dsw)
+    Ud = dsw.to_device(U0)
+    lam = dsw.to_device(cotangent(w.grid, 151))
+    nxt = gg.empty()
+    gg.split_step(Ud, nxt, tau, w.K)
+    ck = [Ud, nxt]
+    ref, tref = gg.empty(), gg.empty()
+    gg.adjoint_step(Ud, tau, w.K, lam, ref)
+    gg.adjoint_trajectory(ck, tau, w.K, lam, tref)
+    torch.cuda.synchronize()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        a, t = gg.empty(), gg.empty()
+        gg.adjoint_step(Ud, tau, w.K, lam, a, stream=s)
+        a_cp = {k: v.clone() for k, v in a.items()}
+        gg.adjoint_trajectory(ck, tau, w.K, lam, t, stream=s)
+        t_cp = {k: v.clone() for k, v in t.items()}
+    torch.cuda.synchronize()
+    gg.get_status()
+    for got, want, tag in ((a_cp, ref, "adjoint_step"), (t_cp, tref, "adjoint_trajectory")):
+        e = max(float(torch.linalg.norm(got[k] - want[k]) / torch.linalg.norm(want[k])) for k in FIELDS)
+        print(f"{tag} on a caller stream: rel L2 {e:.2e}", flush=True)
+        assert e <= 1e-12

@@ -228,3 +228,27 @@ def test_bad_ensemble_arguments(dsw):
         E.ensemble_step(dU0, [out[0], out[0]], taus, K)  # two members, one output
     with pytest.raises(dsw.DswError):
         E.ensemble_step(dU0, out, [taus[0], -1.0], K)
+
+
+def test_graph_on_a_caller_stream(dsw):
+    """the two-lane graph launched on a stream of the caller's: work queued on
+    that stream right after the launch (a copy of the outputs) sees the whole
+    step"""
+    ws = small_members()
+    E, U0, taus = _make(dsw, ws)
+    dU0 = [dsw.to_device(u) for u in U0]
+    ref = _per_member(E, dU0, taus)
+    torch.cuda.synchronize()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        out = [g.empty() for g in E.members]
+        for rep in range(2):  # capture, then a replay
+            E.ensemble_step(dU0, out, taus, K, stream=s)
+            cp = [{k: v.clone() for k, v in o.items()} for o in out]
+            for o in out:
+                for v in o.values():
+                    v.fill_(7.0)
+    torch.cuda.synchronize()
+    E.get_status()
+    _assert_same(cp, ref, "graph on a caller stream")
