@@ -867,6 +867,27 @@ struct Rev {
   Fields L, Lnext;
 };
 
+// Ordering between the caller's stream and the handle's second stream.  If
+// a join fails, the second stream is synchronised before the error returns,
+// so that no work of a failed call is left running beside the caller's.
+static int side_fork(dsw_grid *G, hipStream_t st) {
+  HIPCHK(hipEventRecord(G->fork_ev, st));
+  HIPCHK(hipStreamWaitEvent(G->side, G->fork_ev, 0));
+  return DSW_OK;
+}
+static int side_record(dsw_grid *G) {
+  const hipError_t e = hipEventRecord(G->join_ev, G->side);
+  if (e == hipSuccess) return DSW_OK;
+  (void)hipStreamSynchronize(G->side);
+  return fail(DSW_EHIP, std::string("second stream: ") + hipGetErrorString(e));
+}
+static int side_join(dsw_grid *G, hipStream_t st) {
+  const hipError_t e = hipStreamWaitEvent(st, G->join_ev, 0);
+  if (e == hipSuccess) return DSW_OK;
+  (void)hipStreamSynchronize(G->side);
+  return fail(DSW_EHIP, std::string("second stream: ") + hipGetErrorString(e));
+}
+
 // The mix of the last iteration (the first one reversed) writes lam_n; the
 // cotangent of Ubar accumulates from zero, and every mix leaves it zero:
 // zero_ubb clears it first (a call's first reverse).
@@ -951,13 +972,12 @@ extern "C" int dsw_adjoint_step(dsw_grid *G, const dsw_fields *Un, double tau, i
   // lam_np1: they run on the second stream (with a sweep scratch of their
   // own) while the forward finishes that iteration, whose X1, X2, X3 the
   // rest of the reverse needs.  The two sides write disjoint buffers.
-  HIPCHK(hipEventRecord(G->fork_ev, st));
-  HIPCHK(hipStreamWaitEvent(G->side, G->fork_ev, 0));
+  if ((rc = side_fork(G, st))) return rc;
   Rev v = adj_reverse_init(G, un, F(lam_np1), &ws[4 * K + 1], true, G->side);
   adj_reverse_solves(G, tau, K - 1, t, v, G->sc2, G->side);
-  HIPCHK(hipEventRecord(G->join_ev, G->side));
+  if ((rc = side_record(G))) return rc;
   adj_record_iter(G, un, tau, K, K - 1, t, U, G->sc, st);
-  HIPCHK(hipStreamWaitEvent(st, G->join_ev, 0));
+  if ((rc = side_join(G, st))) return rc;
   adj_reverse_local(G, tau, K, K - 1, t, v, F(lam_n), st);
   for (int k = K - 2; k >= 0; k--) {
     adj_reverse_solves(G, tau, k, t, v, G->sc, st);
@@ -1032,15 +1052,14 @@ extern "C" int dsw_adjoint_trajectory(dsw_grid *G, const dsw_fields *ckpts, int3
   Fields lin = F(lam_end);
   for (int n = nsteps - 1; n >= 0; n--) {
     if (n >= 1) {
-      HIPCHK(hipEventRecord(G->fork_ev, st));
-      HIPCHK(hipStreamWaitEvent(G->side, G->fork_ev, 0));
+      if ((rc = side_fork(G, st))) return rc;
       adj_record(G, F(&ckpts[n - 1]), tau, K, tape(n - 1), U, G->sc2, G->side);
-      HIPCHK(hipEventRecord(G->join_ev, G->side));
+      if ((rc = side_record(G))) return rc;
     }
     const Fields lout = n == 0 ? F(lam_0) : P[n & 1];
     adj_reverse(G, F(&ckpts[n]), tau, K, tape(n), lin, lout, sc, n == nsteps - 1, st);
     lin = lout;
-    if (n >= 1) HIPCHK(hipStreamWaitEvent(st, G->join_ev, 0));
+    if (n >= 1 && (rc = side_join(G, st))) return rc;
   }
   return check_launch("adjoint trajectory kernels");
 }
