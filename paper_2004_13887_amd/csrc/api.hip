@@ -818,9 +818,10 @@ static void adj_record_bnd(const dsw_grid *G, const Fields &un, int K, const Tap
 }
 
 // scr: the sweep scratch of the line solves (the grid's, or the second
-// stream's)
+// stream's).  keep_last false: the last iterate U^{n+1} is not needed (a
+// recompute for the reverse), so the last phi pass writes X3 alone.
 static void adj_record_iter(const dsw_grid *G, const Fields &un, double tau, int K, int k, const Tape &t,
-                            const Fields &U, const Scratch &scr, hipStream_t st) {
+                            const Fields &U, const Scratch &scr, hipStream_t st, bool keep_last = true) {
   const Fields none{};
   const Fields ubk = t.ub[k];
   Pass r{G->geo.periodic ? PK_RES_INP : PK_RES_IN, 0, base_args(G)};
@@ -833,12 +834,17 @@ static void adj_record_iter(const dsw_grid *G, const Fields &un, double tau, int
   launch_single(G, r, st);
   Out o1{}, o2{}, o3{};
   o1.x = t.x1[k]; o2.x = t.x2[k];
-  o3.mode = 1;
-  o3.x = U;
-  o3.base = k == 0 ? un : U;
-  o3.un = un;
-  o3.ub = k < K - 1 ? t.ub[k + 1] : none;
-  o3.raw = t.x3[k];
+  if (k == K - 1 && !keep_last) {
+    o3.mode = 0;
+    o3.x = t.x3[k];
+  } else {
+    o3.mode = 1;
+    o3.x = U;
+    o3.base = k == 0 ? un : U;
+    o3.un = un;
+    o3.ub = k < K - 1 ? t.ub[k + 1] : none;
+    o3.raw = t.x3[k];
+  }
   auto sw = [&](int d, const Fields &rhs, const Out &o) {
     Pass p = sweep_pass(G, d, ubk, tau, rhs, o);
     p.a.scb = scr.blk;
@@ -851,9 +857,9 @@ static void adj_record_iter(const dsw_grid *G, const Fields &un, double tau, int
 }
 
 static void adj_record(const dsw_grid *G, const Fields &un, double tau, int K, const Tape &t,
-                       const Fields &U, const Scratch &scr, hipStream_t st) {
+                       const Fields &U, const Scratch &scr, hipStream_t st, bool keep_last = true) {
   adj_record_bnd(G, un, K, t, U, st);
-  for (int k = 0; k < K; k++) adj_record_iter(G, un, tau, K, k, t, U, scr, st);
+  for (int k = 0; k < K; k++) adj_record_iter(G, un, tau, K, k, t, U, scr, st, keep_last);
 }
 
 // The reverse sweep (reverse of every statement of adj_record, last
@@ -953,6 +959,36 @@ static int check_adjoint_args(const dsw_grid *G, const dsw_fields *Un, double ta
   return DSW_OK;
 }
 
+// One adjoint step with its recompute from un (into the iterate U and the
+// tape t).  The last iteration's transposed solves read only its midpoint
+// and lam_in: they run on the second stream (with a sweep scratch of their
+// own) while the recompute finishes that iteration, whose X1, X2, X3 the
+// rest of the reverse needs.  The two sides write disjoint buffers.
+// then: called once the recompute has been enqueued and the solves joined,
+// before the rest of the reverse (the trajectory queues its next recompute
+// on the second stream there).
+template <class Then>
+static int adj_step_overlapped(dsw_grid *G, const Fields &un, double tau, int K, const Tape &t,
+                               const Fields &U, const Fields &lam_in, const Fields &lam_out,
+                               const Fields *sc, hipStream_t st, Then then) {
+  int rc;
+  adj_record_bnd(G, un, K, t, U, st);
+  for (int k = 0; k < K - 1; k++) adj_record_iter(G, un, tau, K, k, t, U, G->sc, st);
+  if ((rc = side_fork(G, st))) return rc;
+  Rev v = adj_reverse_init(G, un, lam_in, sc, true, G->side);
+  adj_reverse_solves(G, tau, K - 1, t, v, G->sc2, G->side);
+  if ((rc = side_record(G))) return rc;
+  adj_record_iter(G, un, tau, K, K - 1, t, U, G->sc, st, false);
+  if ((rc = side_join(G, st))) return rc;
+  if ((rc = then())) return rc;
+  adj_reverse_local(G, tau, K, K - 1, t, v, lam_out, st);
+  for (int k = K - 2; k >= 0; k--) {
+    adj_reverse_solves(G, tau, k, t, v, G->sc, st);
+    adj_reverse_local(G, tau, K, k, t, v, lam_out, st);
+  }
+  return DSW_OK;
+}
+
 extern "C" int dsw_adjoint_step(dsw_grid *G, const dsw_fields *Un, double tau, int32_t K,
                                 const dsw_fields *lam_np1, dsw_fields *lam_n, void *stream) {
   int rc;
@@ -963,26 +999,10 @@ extern "C" int dsw_adjoint_step(dsw_grid *G, const dsw_fields *Un, double tau, i
   hipStream_t st = (hipStream_t)stream;
   const Fields un = F(Un);
   const Tape t = tape_from(ws, 0, K, un);
-  const Fields U = ws[4 * K];
-  // forward recompute from the checkpoint into the workspace's iterate,
-  // up to the midpoint of the last iteration
-  adj_record_bnd(G, un, K, t, U, st);
-  for (int k = 0; k < K - 1; k++) adj_record_iter(G, un, tau, K, k, t, U, G->sc, st);
-  // The last iteration's transposed solves read only its midpoint and
-  // lam_np1: they run on the second stream (with a sweep scratch of their
-  // own) while the forward finishes that iteration, whose X1, X2, X3 the
-  // rest of the reverse needs.  The two sides write disjoint buffers.
-  if ((rc = side_fork(G, st))) return rc;
-  Rev v = adj_reverse_init(G, un, F(lam_np1), &ws[4 * K + 1], true, G->side);
-  adj_reverse_solves(G, tau, K - 1, t, v, G->sc2, G->side);
-  if ((rc = side_record(G))) return rc;
-  adj_record_iter(G, un, tau, K, K - 1, t, U, G->sc, st);
-  if ((rc = side_join(G, st))) return rc;
-  adj_reverse_local(G, tau, K, K - 1, t, v, F(lam_n), st);
-  for (int k = K - 2; k >= 0; k--) {
-    adj_reverse_solves(G, tau, k, t, v, G->sc, st);
-    adj_reverse_local(G, tau, K, k, t, v, F(lam_n), st);
-  }
+  // forward recompute from the checkpoint into the workspace's iterate
+  if ((rc = adj_step_overlapped(G, un, tau, K, t, ws[4 * K], F(lam_np1), F(lam_n), &ws[4 * K + 1], st,
+                                [] { return (int)DSW_OK; })))
+    return rc;
   return check_launch("adjoint step kernels");
 }
 
@@ -1027,7 +1047,9 @@ extern "C" int dsw_adjoint_step_taped(dsw_grid *G, const dsw_fields *Un, double 
 // its own sweep scratch) while the reverse of step n runs from the other
 // tape on the caller's stream.  A tape is overwritten only after the
 // reverse that read it: the second stream waits for everything enqueued on
-// the caller's stream before each recompute.
+// the caller's stream before each recompute.  The last step (the first one
+// reversed) runs as one overlapped adjoint step, whose recompute nothing
+// overlaps otherwise.
 extern "C" int dsw_adjoint_trajectory(dsw_grid *G, const dsw_fields *ckpts, int32_t nsteps, double tau,
                                       int32_t K, const dsw_fields *lam_end, dsw_fields *lam_0,
                                       void *stream) {
@@ -1048,16 +1070,25 @@ extern "C" int dsw_adjoint_trajectory(dsw_grid *G, const dsw_fields *ckpts, int3
   const Fields *sc = &ws[8 * K + 1];
   const Fields P[2] = {ws[8 * K + 7], ws[8 * K + 8]};
   auto tape = [&](int n) { return tape_from(ws, (n & 1) ? 4 * K : 0, K, F(&ckpts[n])); };
-  adj_record(G, F(&ckpts[nsteps - 1]), tau, K, tape(nsteps - 1), U, G->sc, st);
-  Fields lin = F(lam_end);
-  for (int n = nsteps - 1; n >= 0; n--) {
-    if (n >= 1) {
-      if ((rc = side_fork(G, st))) return rc;
-      adj_record(G, F(&ckpts[n - 1]), tau, K, tape(n - 1), U, G->sc2, G->side);
-      if ((rc = side_record(G))) return rc;
-    }
+  // the next recompute, on the second stream, once everything enqueued on
+  // the caller's stream so far is done
+  auto next_record = [&](int n) {
+    int r;
+    if ((r = side_fork(G, st))) return r;
+    adj_record(G, F(&ckpts[n]), tau, K, tape(n), U, G->sc2, G->side, false);
+    return side_record(G);
+  };
+  const int last = nsteps - 1;
+  Fields lin = last == 0 ? F(lam_0) : P[last & 1];
+  if ((rc = adj_step_overlapped(G, F(&ckpts[last]), tau, K, tape(last), U, F(lam_end), lin, sc, st,
+                                [&] { return last >= 1 ? next_record(last - 1) : (int)DSW_OK; })))
+    return rc;
+  if (last >= 1 && (rc = side_join(G, st))) return rc;
+  for (int n = last - 1; n >= 0; n--) {
+    if (n >= 1 && (rc = next_record(n - 1))) return rc;
     const Fields lout = n == 0 ? F(lam_0) : P[n & 1];
-    adj_reverse(G, F(&ckpts[n]), tau, K, tape(n), lin, lout, sc, n == nsteps - 1, st);
+    // the cotangent of Ubar is zero here: every reverse iteration's mix clears it
+    adj_reverse(G, F(&ckpts[n]), tau, K, tape(n), lin, lout, sc, false, st);
     lin = lout;
     if (n >= 1 && (rc = side_join(G, st))) return rc;
   }
