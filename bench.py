@@ -310,22 +310,24 @@ def bench_adjoint(args):
     log(f"[adjoint] trajectory of {w.steps} steps: {traj_ms:.3f} ms per step ({ntraj} passes)")
     grid.get_status()
     out_line = {
-        "metric": "adjoint step time / forward step time",
-        "value": times["adjoint"] / times["forward"],
+        "metric": "adjoint step time / forward step time (reverse pass through the workload's steps "
+                  "from per-step checkpoints, every step's forward recompute included)",
+        "value": traj_ms / times["forward"],
         "unit": "ratio",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": times["adjoint"],
+        "ms_per_step": traj_ms,
         "forward_ms_per_step": times["forward"],
+        "single_step": {"adjoint_ms": times["adjoint"], "adjoint_over_forward": times["adjoint"] / times["forward"]},
         "higher_is_better": False,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": "adjoint: 256 (phi) x 128 (theta) x 64 (r) sector, 100 m horizontal, "
-                               "K=3, Mach 1e-2, seeded bubble + noise", "cells": w.grid.ncells,
-                   "K": w.K},
+        "config": {"workload": f"adjoint: 256 (phi) x 128 (theta) x 64 (r) sector, 100 m horizontal, "
+                               f"K=3, Mach 1e-2, seeded bubble + noise, {w.steps} steps checkpointed",
+                   "cells": w.grid.ncells, "K": w.K},
         "taped": {"forward_taped_ms": times["forward_taped"], "adjoint_taped_ms": times["adjoint_taped"],
                   "adjoint_taped_over_forward": times["adjoint_taped"] / times["forward"],
                   "tape_bytes": grid.tape_bytes(w.K)},
