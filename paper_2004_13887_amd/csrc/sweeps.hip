@@ -424,6 +424,7 @@ void launch_sweep_T(int d, const PassArgs &a, unsigned blocks, unsigned threads,
 // two: the next row's loads issue while the current row is eliminated.  The
 // theta sweep runs at two waves per SIMD whatever its register count, so the
 // extra registers cost no occupancy (the r sweep's would: three waves to two).
+// Not for the forced sweep (wall-aware sources), which then spills.
 //
 // Twisted block factorisation of a non-cyclic block line by two threads: the
 // top thread eliminates rows 0 .. m-1 downwards (C'_s = Ap_s^{-1} U_s,
@@ -447,7 +448,7 @@ __device__ __forceinline__ void twisted_block_line(const Geo &g, const Mat &m, c
   double *my = lds + (long)lane * 15;  // E'_{m+1} (9), z_{m+1} (3), x_m (3)
   if (act) {
     if (top) {
-      #pragma unroll (D == 1 ? 2 : 1)
+      #pragma unroll (D == 1 && !S::WALL ? 2 : 1)
       for (int s = 0; s < mid; s++) {
         block_row<D>(g, m, u, rhs, a, b, s, n, 0, hs, R);
         if (s == 0) {
@@ -473,7 +474,7 @@ __device__ __forceinline__ void twisted_block_line(const Geo &g, const Mat &m, c
         for (int q = 0; q < 3; q++) SC(s, 9 + q) = y[q];
       }
     } else {
-      #pragma unroll (D == 1 ? 2 : 1)
+      #pragma unroll (D == 1 && !S::WALL ? 2 : 1)
       for (int s = n - 1; s > mid; s--) {
         block_row<D>(g, m, u, rhs, a, b, s, n, 0, hs, R);
         if (s == n - 1) {
@@ -534,7 +535,7 @@ __device__ __forceinline__ void twisted_block_line(const Geo &g, const Mat &m, c
   if (!act) return;
   double x[3] = {my[12], my[13], my[14]};
   if (top) {
-    #pragma unroll (D == 1 ? 2 : 1)
+    #pragma unroll (D == 1 && !S::WALL ? 2 : 1)
     for (int s = mid - 1; s >= 0; s--) {
 #pragma unroll
       for (int q = 0; q < 9; q++) C[q] = SC(s, q);
@@ -545,7 +546,7 @@ __device__ __forceinline__ void twisted_block_line(const Geo &g, const Mat &m, c
       block_store<D>(g, o, a, b, s, x);
     }
   } else {
-    #pragma unroll (D == 1 ? 2 : 1)
+    #pragma unroll (D == 1 && !S::WALL ? 2 : 1)
     for (int s = mid + 1; s < n; s++) {
 #pragma unroll
       for (int q = 0; q < 9; q++) C[q] = SC(s, q);
@@ -734,7 +735,7 @@ __device__ __forceinline__ void twisted_scalar_line(const Geo &g, const Mat &m, 
   double cv = 0.0, yv = 0.0;
   if (act) {
     if (top) {
-      #pragma unroll (D == 1 ? 2 : 1)
+      #pragma unroll (D == 1 && !S::WALL ? 2 : 1)
       for (int s = 0; s < mid; s++) {
         scalar_row<D, FAM>(g, m, u, rhs, a, b, s, n, 0, hs, R, xi, arr);
         const double den = R.b - R.a * cv;
@@ -746,7 +747,7 @@ __device__ __forceinline__ void twisted_scalar_line(const Geo &g, const Mat &m, 
         SC(s, 1) = yv;
       }
     } else {
-      #pragma unroll (D == 1 ? 2 : 1)
+      #pragma unroll (D == 1 && !S::WALL ? 2 : 1)
       for (int s = n - 1; s > mid; s--) {
         scalar_row<D, FAM>(g, m, u, rhs, a, b, s, n, 0, hs, R, xi, arr);
         const double den = R.b - R.c * cv;
@@ -774,13 +775,13 @@ __device__ __forceinline__ void twisted_scalar_line(const Geo &g, const Mat &m, 
   if (!act) return;
   double x = my[2];
   if (top) {
-    #pragma unroll (D == 1 ? 2 : 1)
+    #pragma unroll (D == 1 && !S::WALL ? 2 : 1)
     for (int s = mid - 1; s >= 0; s--) {
       x = SC(s, 1) - SC(s, 0) * x;
       put(o, ofid, scalar_index<D, FAM>(g, a, b, s), x);
     }
   } else {
-    #pragma unroll (D == 1 ? 2 : 1)
+    #pragma unroll (D == 1 && !S::WALL ? 2 : 1)
     for (int s = mid + 1; s < n; s++) {
       x = SC(s, 1) - SC(s, 0) * x;
       put(o, ofid, scalar_index<D, FAM>(g, a, b, s), x);
