@@ -127,6 +127,24 @@ int dsw_line_solve_phi(dsw_grid *grid, const dsw_fields *Ubar, double tau, const
 int dsw_split_step(dsw_grid *grid, const dsw_fields *Un, dsw_fields *Unp1, double tau, int32_t K,
                    void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * step as dsw_split_step, with the same results, that allocates nothing.  Its
+ * workspace (two midpoint states, the residual, the outputs of the r and
+ * theta sweeps, the sweep scratch) lives in one library-owned device array of
+ * DSW_NOALLOC_BYTES per GPU, which each GPU the library runs on holds until
+ * the process ends (its address is taken at dsw_init_grid).  A grid whose
+ * workspace exceeds it (about 5 x 8 x (cells + faces) + 8 x 27 x cells bytes;
+ * some 640 thousand cells fit) is refused with DSW_EINVAL and nothing is
+ * enqueued.  The handle's device must be current, else DSW_EINVAL.  All calls
+ * on one GPU share the array: calls that overlap in time on one GPU (two
+ * streams, two threads, two handles) race and give undefined results; calls
+ * ordered on one stream are safe.  Every part of the array a call reads it
+ * has first written, so no clearing is needed between calls. */
+#define DSW_NOALLOC_BYTES (256LL * 1024 * 1024)
+int dsw_split_step_noalloc(dsw_grid *grid, const dsw_fields *Un, dsw_fields *Unp1, double tau,
+                           int32_t K, void *stream);
+
 /* Tangential velocities on the non-periodic walls, at the time the ghost
  * values are wanted (for a split step: the midpoint of the old and the new
  * time level).  Device arrays, C order; a null entry is a zero wall velocity.

@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -82,6 +83,36 @@ static int fail(int code, const std::string &msg) {
 
 extern "C" const char *dsw_last_error(void) { return g_err.c_str(); }
 
+// ------------------------------------------- allocation-free workspace --
+
+// Workspace of dsw_split_step_noalloc: one file-scope device array of
+// DSW_NOALLOC_BYTES.  Every GPU the library runs on holds its own copy from
+// the library's first use on that GPU until the process ends.  In host code
+// the array's name is not a device address: each device's address comes from
+// hipGetSymbolAddress, taken once per device and kept in g_noalloc.
+static __device__ __align__(256) double scratch[DSW_NOALLOC_BYTES / sizeof(double)];
+
+static constexpr int NOALLOC_MAX_DEVICES = 64;
+static double *g_noalloc[NOALLOC_MAX_DEVICES];
+static std::mutex g_noalloc_mu;
+
+// device address of the array on device dev, which must be current; taken on
+// the first call for that device
+static int noalloc_base(int dev, double **out) {
+  if (dev < 0 || dev >= NOALLOC_MAX_DEVICES)
+    return fail(DSW_EINVAL, "device index beyond the allocation-free workspace table");
+  std::lock_guard<std::mutex> lk(g_noalloc_mu);
+  if (!g_noalloc[dev]) {
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(DSW_EHIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_noalloc[dev] = static_cast<double *>(p);
+  }
+  *out = g_noalloc[dev];
+  return DSW_OK;
+}
+
 static void counts(const dsw_grid_desc &d, long c[5]) {
   const long nr = d.n_r, nt = d.n_theta, np = d.n_phi, npf = d.periodic_phi ? np : np + 1;
   c[0] = nr * nt * np;
@@ -127,6 +158,14 @@ extern "C" int dsw_init_grid(const dsw_grid_desc *desc, const dsw_material *mat,
   G->desc = *desc;
   G->mat = *mat;
   HIPCHK(hipGetDevice(&G->device));
+  {
+    double *base = nullptr;  // the allocation-free workspace of this device
+    const int src = noalloc_base(G->device, &base);
+    if (src) {
+      delete G;
+      return src;
+    }
+  }
   const int nr = desc->n_r, nt = desc->n_theta, np = desc->n_phi;
   // metric tables (host, then device)
   const size_t nt1 = (size_t)nt + 1, nr1 = (size_t)nr + 1;
@@ -328,18 +367,36 @@ static Pass sweep_pass(const dsw_grid *G, int d, const Fields &ubar, double tau,
   return p;
 }
 
+// The workspace of one split step: the midpoint states of consecutive
+// iterations, the residual, the outputs of the r and theta sweeps, and the
+// sweep scratch.
+struct Work {
+  Fields ub, ub2, r, x1, x2;
+  Scratch sc;
+};
+
+static Work own_work(const dsw_grid *G) { return Work{G->ub, G->ub2, G->r, G->x1, G->x2, G->sc}; }
+
 // the passes of one split step, in stream order (paper section 2.2: K
-// iterations of eqs. (spl1)-(spl3) after the residual)
-static void plan_step(const dsw_grid *G, const Fields &un, const Fields &uk, double tau, int K,
-                      std::vector<Pass> &out) {
+// iterations of eqs. (spl1)-(spl3) after the residual), on workspace W;
+// emit(const Pass &) receives each pass in turn
+template <class Emit>
+static void plan_step(const dsw_grid *G, const Work &W, const Fields &un, const Fields &uk, double tau,
+                      int K, Emit emit) {
   const Fields none{};
   {
     // Dirichlet data of U^{n+1} and of both midpoint buffers = those of U^n
     Pass p{PK_BND, 4, base_args(G)};
-    p.a.src = un; p.a.d0 = uk; p.a.d1 = G->ub; p.a.d2 = G->ub2;
-    out.push_back(p);
+    p.a.src = un; p.a.d0 = uk; p.a.d1 = W.ub; p.a.d2 = W.ub2;
+    emit(p);
   }
-  const Fields ubuf[2] = {G->ub, G->ub2};
+  const Fields ubuf[2] = {W.ub, W.ub2};
+  auto sweep = [&](int d, const Fields &ubar, const Fields &rhs, const Out &o) {
+    Pass p = sweep_pass(G, d, ubar, tau, rhs, o);
+    p.a.scb = W.sc.blk;
+    p.a.scs = W.sc.sca;
+    emit(p);
+  };
   for (int it = 0; it < K; it++) {
     // midpoint state of this iteration: U^n itself at the first one, else the
     // one written by the previous iteration's phi sweep
@@ -348,19 +405,19 @@ static void plan_step(const dsw_grid *G, const Fields &un, const Fields &uk, dou
     r.a.u = src1(ubar);
     r.a.d = diff(un, it == 0 ? un : uk);
     r.a.tau = tau;
-    r.a.R = G->r;
-    out.push_back(r);  // interior workgroups
+    r.a.R = W.r;
+    emit(r);  // interior workgroups
     r.kind = PK_RES;
-    out.push_back(r);  // the rest
+    emit(r);  // the rest
     Out o1{}, o2{}, o3{};
-    o1.x = G->x1; o1.mode = 0;
-    o2.x = G->x2; o2.mode = 0;
+    o1.x = W.x1; o1.mode = 0;
+    o2.x = W.x2; o2.mode = 0;
     o3.x = uk; o3.base = it == 0 ? un : uk; o3.un = un;
     o3.ub = it < K - 1 ? ubuf[it % 2] : none;
     o3.mode = 1;
-    out.push_back(sweep_pass(G, 0, ubar, tau, G->r, o1));
-    out.push_back(sweep_pass(G, 1, ubar, tau, G->x1, o2));
-    out.push_back(sweep_pass(G, 2, ubar, tau, G->x2, o3));
+    sweep(0, ubar, W.r, o1);
+    sweep(1, ubar, W.x1, o2);
+    sweep(2, ubar, W.x2, o3);
   }
 }
 
@@ -471,7 +528,7 @@ extern "C" int dsw_split_step(dsw_grid *G, const dsw_fields *Un, dsw_fields *Unp
   if (rc) return rc;
   hipStream_t st = (hipStream_t)stream;
   std::vector<Pass> plan;
-  plan_step(G, F(Un), F(Unp1), tau, K, plan);
+  plan_step(G, own_work(G), F(Un), F(Unp1), tau, K, [&](const Pass &p) { plan.push_back(p); });
   // consecutive launches of one kind (the two residual launches) are timed together
   for (size_t q = 0; q < plan.size();) {
     size_t e = q + 1;
@@ -484,6 +541,49 @@ extern "C" int dsw_split_step(dsw_grid *G, const dsw_fields *Un, dsw_fields *Unp
     q = e;
   }
   return check_launch("split step kernels");
+}
+
+// the workspace of one split step carved from the allocation-free array
+static int noalloc_work(const dsw_grid *G, double *base, Work *W) {
+  const long per = G->count[0] + G->count[1] + G->count[2] + G->count[3] + G->count[4];
+  long sb, ss;
+  sweep_scratch_size(G->geo, &sb, &ss);
+  const long need = 5 * per + sb + ss;
+  if ((unsigned long long)need * sizeof(double) > (unsigned long long)DSW_NOALLOC_BYTES)
+    return fail(DSW_EINVAL, "allocation-free split step: the grid needs " +
+                                std::to_string((unsigned long long)need * sizeof(double)) +
+                                " bytes of workspace, more than DSW_NOALLOC_BYTES = " +
+                                std::to_string((unsigned long long)DSW_NOALLOC_BYTES));
+  long off = 0;
+  W->ub = carve(base, G->count, &off);
+  W->ub2 = carve(base, G->count, &off);
+  W->r = carve(base, G->count, &off);
+  W->x1 = carve(base, G->count, &off);
+  W->x2 = carve(base, G->count, &off);
+  W->sc.blk = base + off;
+  W->sc.sca = base + off + sb;
+  W->sc.blk_len = sb;
+  W->sc.sca_len = ss;
+  return DSW_OK;
+}
+
+extern "C" int dsw_split_step_noalloc(dsw_grid *G, const dsw_fields *Un, dsw_fields *Unp1, double tau,
+                                      int32_t K, void *stream) {
+  if (!G) return fail(DSW_EINVAL, "null handle");
+  int rc = check_step_args(Un, Unp1, tau, K);
+  if (rc) return rc;
+  int dev = -1;
+  HIPCHK(hipGetDevice(&dev));
+  if (dev != G->device) return fail(DSW_EINVAL, "allocation-free split step: the handle's device is not current");
+  double *base = nullptr;
+  if ((rc = noalloc_base(dev, &base))) return rc;
+  Work W;
+  if ((rc = noalloc_work(G, base, &W))) return rc;
+  // every buffer of W is written before it is read within the step, so no
+  // part of the array needs clearing; passes launch as they are planned
+  hipStream_t st = (hipStream_t)stream;
+  plan_step(G, W, F(Un), F(Unp1), tau, K, [&](const Pass &p) { launch_single(G, p, st); });
+  return check_launch("allocation-free split step kernels");
 }
 
 static Wall to_wall(const dsw_wall *w) {
@@ -1218,7 +1318,8 @@ static int build_plan(dsw_ensemble *E, const Cfg &cfg, const dsw_fields *Un, dsw
     dsw_grid *G = mem[m] = E->mem[ids[m]];
     const Cfg keep = G->cfg;
     G->cfg = cfg;
-    plan_step(G, F(&Un[ids[m]]), F(&Unp1[ids[m]]), tau[ids[m]], K, per[m]);
+    plan_step(G, own_work(G), F(&Un[ids[m]]), F(&Unp1[ids[m]]), tau[ids[m]], K,
+              [&](const Pass &p) { per[m].push_back(p); });
     G->cfg = keep;
   }
   const size_t npass = per[0].size();

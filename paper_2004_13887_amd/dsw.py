@@ -31,7 +31,8 @@ SYMBOLS = ("dsw_init_grid", "dsw_free_grid", "dsw_layout", "dsw_residual", "dsw_
            "dsw_ensemble_get_status", "dsw_adjoint_step", "dsw_line_solve_T_r",
            "dsw_line_solve_T_theta", "dsw_line_solve_T_phi", "dsw_line_vjp_r", "dsw_line_vjp_theta",
            "dsw_line_vjp_phi", "dsw_residual_vjp", "dsw_split_step_forced", "dsw_tape_bytes", "dsw_split_step_taped",
-           "dsw_adjoint_step_taped", "dsw_adjoint_trajectory", "dsw_last_error")
+           "dsw_adjoint_step_taped", "dsw_adjoint_trajectory", "dsw_split_step_noalloc",
+           "dsw_last_error")
 TIMING_KINDS = ("residual", "sweep_r", "sweep_theta", "sweep_phi_update", "boundary_copy")
 
 
@@ -99,6 +100,7 @@ def lib():
         for n in ("dsw_line_solve_r", "dsw_line_solve_theta", "dsw_line_solve_phi"):
             getattr(L, n).argtypes = [P, FP, D, FP, FP, P]
         L.dsw_split_step.argtypes = [P, FP, FP, D, I, P]
+        L.dsw_split_step_noalloc.argtypes = [P, FP, FP, D, I, P]
         L.dsw_get_status.argtypes = [P, P]
         L.dsw_set_timing.argtypes = [P, I]
         L.dsw_read_timing.argtypes = [P, P, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
@@ -238,6 +240,13 @@ class Grid:
     def split_step(self, Un, Unp1, tau, K, stream=None):
         _check(lib().dsw_split_step(self._h, C.byref(_fields(Un)), C.byref(_fields(Unp1)),
                                     float(tau), int(K), _stream(stream)))
+
+    def split_step_noalloc(self, Un, Unp1, tau, K, stream=None):
+        """dsw_split_step_noalloc: the same step on the library's static
+        workspace (no device allocation; grids up to DSW_NOALLOC_BYTES of
+        workspace)"""
+        _check(lib().dsw_split_step_noalloc(self._h, C.byref(_fields(Un)), C.byref(_fields(Unp1)),
+                                            float(tau), int(K), _stream(stream)))
 
     def tape_bytes(self, K):
         n = C.c_int64()
