@@ -86,7 +86,7 @@ def _load(path):
     L_.orc_line_matvec.argtypes = [P, MP, FP, WP, D, I, FP, FP]
     L_.orc_line_blocks.argtypes = [P, MP, FP, WP, D, I, I, I, I, C.c_void_p, C.c_void_p,
                                      C.c_void_p, C.c_void_p, C.c_void_p]
-    L_.orc_split_step.argtypes = [P, MP, FP, FP, D, I, WP, FP, FP]
+    L_.orc_split_step.argtypes = [P, MP, FP, FP, D, I, WP, WP, FP, FP]
     L_.orc_residual_at.argtypes = [P, MP, FP, FP, FP, WP, D, L, C.c_void_p, C.c_void_p,
                                      C.c_void_p]
     L_.orc_line_solve_some.argtypes = [P, MP, FP, WP, D, I, L, C.c_void_p, C.c_void_p,
@@ -264,13 +264,18 @@ def line_blocks(g: Grid, mat: Material, Ubar, tau, d, kind, a, b, wall=None):
     return Lo, Do, Uo, idx, fid, bool(cyc)
 
 
-def split_step(g: Grid, mat: Material, Un, tau, K, wall=None, src=None, bnd=None):
-    """One direction-split time step U^{n+1} from U^n with K iterations."""
+def split_step(g: Grid, mat: Material, Un, tau, K, wall0=None, wall1=None, src=None, bnd=None):
+    """One direction-split time step U^{n+1} from U^n with K iterations.
+    wall0, wall1: tangential wall velocities at t^n and t^{n+1} (None: zero);
+    bnd: fields whose boundary-normal faces hold the Dirichlet data at t^{n+1}
+    (None: Un's); src: the midpoint source.  The change of the boundary data
+    enters the first iteration's increments as inhomogeneous Dirichlet data
+    (see orc_split_step)."""
     keep = []
     out = g.zeros()
     m = mat.c()
     rc = lib().orc_split_step(g._h, C.byref(m), _fields(g, Un, keep), _fields(g, out, keep),
-                              float(tau), int(K), _wall(g, wall, keep),
+                              float(tau), int(K), _wall(g, wall0, keep), _wall(g, wall1, keep),
                               _fields(g, src, keep) if src else None,
                               _fields(g, bnd, keep) if bnd else None)
     if rc != 0:
@@ -394,7 +399,7 @@ def jvp_split_step(g: Grid, mat: Material, Un, V, tau, K, h=CS_H):
     out = _czeros(g)
     m = mat.c()
     rc = lib_cs().orc_split_step(g._h, C.byref(m), _cfields(g, Z, keep), _cfields(g, out, keep),
-                                 float(tau), int(K), None, None, None)
+                                 float(tau), int(K), None, None, None, None)
     if rc != 0:
         raise ArithmeticError("zero pivot in a line solve")
     return _split(out, h)

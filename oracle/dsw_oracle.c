@@ -378,6 +378,120 @@ static void cdiv(const orc_grid *g, const opnd *v, int i, int j, int k, real *dr
   *dp_ = (ufv(g, v, i, j, k + 1) - ufv(g, v, i, j, k)) / (r * s * g->dp);
 }
 
+
+/* ------------------------------------------------------- viscous vector -- */
+
+/* The viscous term of F_h, -(1/rho) div sigma = -(mu/rho) (Lap u + grad div u / 3)
+ * (eq. (nonconservmom), constant mu), is discretised as
+ *     -(mu/rho) V(u),   V(u) = (4/3) grad_h(div_h u) - curl_h(curl_h u),
+ * the vector-Laplacian identity Lap u = grad div u - curl curl u on the MAC
+ * complex: div_h at cell centres (cdiv), the vorticity curl_h u at cell edges
+ * as the circulation round a dual face over its area, and curl_h of an edge
+ * field at a face as its circulation round the face over the face area (the
+ * same face areas as div_h).  Then div_h(curl_h(.)) = 0 exactly, so the
+ * viscous update of a discretely solenoidal velocity stays solenoidal; the
+ * component form (scalar Laplacians plus curvature terms) does not do this in
+ * spherical coordinates.  The implicit operators D_d keep the paper's
+ * per-direction second derivatives (B2^{d,.} of Appendix B); the explicit
+ * remainder D_M takes V minus their sum, a discretisation of the paper's
+ * curvature and mixed terms (B2^{M,.}).  Ghost cells take their own radius
+ * and colatitude. */
+static double rc_any(const orc_grid *g, int i) { return g->r1 + (i + 0.5) * g->dr; }
+static double sc_any(const orc_grid *g, int j) { return sin(g->t1 + (j + 0.5) * g->dt); }
+
+static real div_at(const orc_grid *g, const opnd *v, int i, int j, int k) {
+  real a, b, c;
+  cdiv(g, v, i, j, k, &a, &b, &c);
+  return a + b + c;
+}
+/* omega_phi at the edge (r face fr, theta face ft, phi centre k) */
+static real om_phi(const orc_grid *g, const opnd *v, int fr, int ft, int k) {
+  return (rc_any(g, fr) * utv(g, v, fr, ft, k) - rc_any(g, fr - 1) * utv(g, v, fr - 1, ft, k)) /
+             (g->rf[fr] * g->dr) -
+         (urv(g, v, fr, ft, k) - urv(g, v, fr, ft - 1, k)) / (g->rf[fr] * g->dt);
+}
+/* omega_theta at the edge (r face fr, theta centre j, phi face fk) */
+static real om_theta(const orc_grid *g, const opnd *v, int fr, int j, int fk) {
+  return (urv(g, v, fr, j, fk) - urv(g, v, fr, j, fk - 1)) / (g->rf[fr] * g->sc[j] * g->dp) -
+         (rc_any(g, fr) * ufv(g, v, fr, j, fk) - rc_any(g, fr - 1) * ufv(g, v, fr - 1, j, fk)) /
+             (g->rf[fr] * g->dr);
+}
+/* omega_r at the edge (r centre i, theta face ft off a pole, phi face fk) */
+static real om_r(const orc_grid *g, const opnd *v, int i, int ft, int fk) {
+  return (sc_any(g, ft) * ufv(g, v, i, ft, fk) - sc_any(g, ft - 1) * ufv(g, v, i, ft - 1, fk)) /
+             (g->rc[i] * g->sf[ft] * g->dt) -
+         (utv(g, v, i, ft, fk) - utv(g, v, i, ft, fk - 1)) / (g->rc[i] * g->sf[ft] * g->dp);
+}
+/* V at the r face (f, j, k) */
+static real visc_r(const orc_grid *g, const opnd *v, int f, int j, int k) {
+  real cc = ((g->sf[j + 1] * om_phi(g, v, f, j + 1, k) - g->sf[j] * om_phi(g, v, f, j, k)) / g->dt -
+             (om_theta(g, v, f, j, k + 1) - om_theta(g, v, f, j, k)) / g->dp) /
+            (g->rf[f] * g->sc[j]);
+  return (4.0 / 3.0) * (div_at(g, v, f, j, k) - div_at(g, v, f - 1, j, k)) / g->dr - cc;
+}
+/* V at the theta face (i, f, k) */
+static real visc_t(const orc_grid *g, const opnd *v, int i, int f, int k) {
+  real cc = (om_r(g, v, i, f, k + 1) - om_r(g, v, i, f, k)) / (g->rc[i] * g->sf[f] * g->dp) -
+            (g->rf[i + 1] * om_phi(g, v, i + 1, f, k) - g->rf[i] * om_phi(g, v, i, f, k)) /
+                (g->rc[i] * g->dr);
+  return (4.0 / 3.0) * (div_at(g, v, i, f, k) - div_at(g, v, i, f - 1, k)) / (g->rc[i] * g->dt) - cc;
+}
+/* V at the phi face (i, j, f), j not next to a pole */
+static real visc_f(const orc_grid *g, const opnd *v, int i, int j, int f) {
+  int k0 = g->periodic ? kwrap(g, f - 1) : f - 1, k1 = g->periodic ? kwrap(g, f) : f;
+  real cc = (g->rf[i + 1] * om_theta(g, v, i + 1, j, f) - g->rf[i] * om_theta(g, v, i, j, f)) /
+                (g->rc[i] * g->dr) -
+            (om_r(g, v, i, j + 1, f) - om_r(g, v, i, j, f)) / (g->rc[i] * g->dt);
+  return (4.0 / 3.0) * (div_at(g, v, i, j, k1) - div_at(g, v, i, j, k0)) /
+             (g->rc[i] * g->sc[j] * g->dp) -
+         cc;
+}
+/* The per-direction viscous parts of the implicit operators (Appendix B,
+ * B2^{r,r} + B2^{theta,r} + B2^{phi,r} and their theta and phi counterparts:
+ * the three second differences of the face's own component plus the
+ * grad-div part along the face's own direction), summed over all three
+ * directions, in the units of V. */
+static real visc_dir_r(const orc_grid *g, const opnd *v, int f, int j, int k) {
+  real rF = g->rf[f], s = g->sc[j], x0 = urv(g, v, f, j, k), a0, b0, c0, a1, b1, c1;
+  cdiv(g, v, f - 1, j, k, &a0, &b0, &c0);
+  cdiv(g, v, f, j, k, &a1, &b1, &c1);
+  return (g->rc[f] * g->rc[f] * (urv(g, v, f + 1, j, k) - x0) -
+          g->rc[f - 1] * g->rc[f - 1] * (x0 - urv(g, v, f - 1, j, k))) / (rF * rF * g->dr * g->dr) +
+         (a1 - a0) / (3.0 * g->dr) +
+         (g->sf[j + 1] * (urv(g, v, f, j + 1, k) - x0) - g->sf[j] * (x0 - urv(g, v, f, j - 1, k))) /
+             (rF * rF * s * g->dt * g->dt) +
+         (urv(g, v, f, j, k + 1) - 2.0 * x0 + urv(g, v, f, j, k - 1)) / (rF * rF * s * s * g->dp * g->dp);
+}
+static real visc_dir_t(const orc_grid *g, const opnd *v, int i, int f, int k) {
+  real r = g->rc[i], s = g->sf[f], x0 = utv(g, v, i, f, k), a0, b0, c0, a1, b1, c1;
+  cdiv(g, v, i, f - 1, k, &a0, &b0, &c0);
+  cdiv(g, v, i, f, k, &a1, &b1, &c1);
+  return (g->sc[f] * (utv(g, v, i, f + 1, k) - x0) - g->sc[f - 1] * (x0 - utv(g, v, i, f - 1, k))) /
+             (r * r * s * g->dt * g->dt) +
+         (b1 - b0) / (3.0 * r * g->dt) +
+         (g->rf[i + 1] * g->rf[i + 1] * (utv(g, v, i + 1, f, k) - x0) -
+          g->rf[i] * g->rf[i] * (x0 - utv(g, v, i - 1, f, k))) / (r * r * g->dr * g->dr) +
+         (utv(g, v, i, f, k + 1) - 2.0 * x0 + utv(g, v, i, f, k - 1)) / (r * r * s * s * g->dp * g->dp);
+}
+static real visc_dir_f(const orc_grid *g, const opnd *v, int i, int j, int f) {
+  real r = g->rc[i], s = g->sc[j], x0 = ufv(g, v, i, j, f), a0, b0, c0, a1, b1, c1;
+  int k0 = g->periodic ? kwrap(g, f - 1) : f - 1, k1 = g->periodic ? kwrap(g, f) : f;
+  cdiv(g, v, i, j, k0, &a0, &b0, &c0);
+  cdiv(g, v, i, j, k1, &a1, &b1, &c1);
+  return (ufv(g, v, i, j, f + 1) - 2.0 * x0 + ufv(g, v, i, j, f - 1)) / (r * r * s * s * g->dp * g->dp) +
+         (c1 - c0) / (3.0 * r * s * g->dp) +
+         (g->rf[i + 1] * g->rf[i + 1] * (ufv(g, v, i + 1, j, f) - x0) -
+          g->rf[i] * g->rf[i] * (x0 - ufv(g, v, i - 1, j, f))) / (r * r * g->dr * g->dr) +
+         (g->sf[j + 1] * (ufv(g, v, i, j + 1, f) - x0) - g->sf[j] * (x0 - ufv(g, v, i, j - 1, f))) /
+             (r * r * s * g->dt * g->dt);
+}
+/* a phi-face row next to a pole: the edge vorticity omega_r on the polar axis
+ * is one value for the whole ring of phi faces, so these rows keep the
+ * component form of the vector Laplacian with the pole ghost rules */
+static int next_to_pole(const orc_grid *g, int j) {
+  return (j == 0 && g->pole_lo) || (j == g->nt - 1 && g->pole_hi);
+}
+
 /* ------------------------------------------------------------- row forms -- */
 
 /* pressure equation (nonconservener) at a centre */
@@ -464,17 +578,7 @@ static real row_ur(const orc_grid *g, const orc_mat *m, const fcoef *c, const op
     real vb = 0.25 * (ufv(g, v, f - 1, j, k) + ufv(g, v, f - 1, j, k + 1) + ufv(g, v, f, j, k) +
                         ufv(g, v, f, j, k + 1));
     N += -(c->ua * va + c->ub * vb) / rF;
-    real dth = 0.5 *
-                 ((g->sf[j + 1] * utv(g, v, f - 1, j + 1, k) - g->sf[j] * utv(g, v, f - 1, j, k)) +
-                  (g->sf[j + 1] * utv(g, v, f, j + 1, k) - g->sf[j] * utv(g, v, f, j, k))) / g->dt;
-    real dph = 0.5 *
-                 ((ufv(g, v, f - 1, j, k + 1) - ufv(g, v, f - 1, j, k)) +
-                  (ufv(g, v, f, j, k + 1) - ufv(g, v, f, j, k))) / g->dp;
-    vis += -2.0 * x0 / (rF * rF) - 2.0 / (rF * rF * s) * dth - 2.0 / (rF * rF * s) * dph;
-    real a0, b0, c0, a1, b1, c1;
-    cdiv(g, v, f - 1, j, k, &a0, &b0, &c0);
-    cdiv(g, v, f, j, k, &a1, &b1, &c1);
-    gd += (b1 - b0) / g->dr + (c1 - c0) / g->dr;
+    vis += visc_r(g, v, f, j, k) - visc_dir_r(g, v, f, j, k);
     N += -2.0 * m->omega * s * vb;
   }
   return N - nu * vis - nu / 3.0 * gd;
@@ -513,17 +617,7 @@ static real row_ut(const orc_grid *g, const orc_mat *m, const fcoef *c, const op
     real vb = 0.25 * (ufv(g, v, i, j0, k) + ufv(g, v, i, j0, k + 1) + ufv(g, v, i, j1, k) +
                         ufv(g, v, i, j1, k + 1));
     N += (c->un * va - c->ub * vb * ctF) / r;
-    real dthr = 0.5 *
-                  ((urv(g, v, i, j1, k) - urv(g, v, i, j0, k)) +
-                   (urv(g, v, i + 1, j1, k) - urv(g, v, i + 1, j0, k))) / g->dt;
-    real dphf = 0.5 *
-                  ((ufv(g, v, i, j0, k + 1) - ufv(g, v, i, j0, k)) +
-                   (ufv(g, v, i, j1, k + 1) - ufv(g, v, i, j1, k))) / g->dp;
-    vis += -x0 / (r * r * s * s) + 2.0 / (r * r) * dthr - 2.0 * ctF / (r * r * s) * dphf;
-    real a0, b0, c0, a1, b1, c1;
-    cdiv(g, v, i, j0, k, &a0, &b0, &c0);
-    cdiv(g, v, i, j1, k, &a1, &b1, &c1);
-    gd += (a1 - a0) / (r * g->dt) + (c1 - c0) / (r * g->dt);
+    vis += visc_t(g, v, i, f, k) - visc_dir_t(g, v, i, f, k);
     N += -2.0 * m->omega * g->cf[f] * vb;
   }
   return N - nu * vis - nu / 3.0 * gd;
@@ -568,11 +662,15 @@ static real row_uf(const orc_grid *g, const orc_mat *m, const fcoef *c, const op
     real dpht = 0.5 *
                   ((utv(g, v, i, j, k1) - utv(g, v, i, j, k0)) +
                    (utv(g, v, i, j + 1, k1) - utv(g, v, i, j + 1, k0))) / g->dp;
-    vis += -x0 / (r * r * s * s) + 2.0 / (r * r * s) * dphr + 2.0 * ct / (r * r * s) * dpht;
-    real a0, b0, c0, a1, b1, c1;
-    cdiv(g, v, i, j, k0, &a0, &b0, &c0);
-    cdiv(g, v, i, j, k1, &a1, &b1, &c1);
-    gd += (a1 - a0) / (r * s * g->dp) + (b1 - b0) / (r * s * g->dp);
+    if (next_to_pole(g, j)) { /* component form: curvature terms and the mixed grad-div */
+      vis += -x0 / (r * r * s * s) + 2.0 / (r * r * s) * dphr + 2.0 * ct / (r * r * s) * dpht;
+      real a0, b0, c0, a1, b1, c1;
+      cdiv(g, v, i, j, k0, &a0, &b0, &c0);
+      cdiv(g, v, i, j, k1, &a1, &b1, &c1);
+      gd += (a1 - a0) / (r * s * g->dp) + (b1 - b0) / (r * s * g->dp);
+    } else {
+      vis += visc_f(g, v, i, j, f) - visc_dir_f(g, v, i, j, f);
+    }
     N += 2.0 * m->omega * (g->cc[j] * vb + s * va);
   }
   return N - nu * vis - nu / 3.0 * gd;
@@ -1195,36 +1293,142 @@ static void copy_bnd_faces(const orc_grid *g, const orc_fields *src, orc_fields 
       }
 }
 
-/* One split time step: U^{n+1} from U^n with K iterations.  wall: ghost data
- * for Ubar (midpoint wall velocities); src: midpoint source (may be NULL);
- * bnd: fields whose boundary-normal faces hold the Dirichlet data at t^{n+1}
- * (NULL: keep those of Un).  Returns 0, or -1 on a vanishing pivot. */
+/* wall data: lengths of the twelve arrays and a linear combination of two
+ * sets (a NULL set or entry counts as zero) */
+static long wall_len(const orc_grid *g, int q) {
+  switch (q) {
+  case 0: case 1: return (long)(g->nr + 1) * g->np;   /* ur_t1, ur_t2 */
+  case 2: case 3: return (long)(g->nr + 1) * g->nt;   /* ur_p1, ur_p2 */
+  case 4: case 5: return (long)(g->nt + 1) * g->np;   /* ut_r1, ut_r2 */
+  case 6: case 7: return (long)g->nr * (g->nt + 1);   /* ut_p1, ut_p2 */
+  case 8: case 9: return (long)g->nt * g->npf;        /* uf_r1, uf_r2 */
+  default: return (long)g->nr * g->npf;               /* uf_t1, uf_t2 */
+  }
+}
+static const real *wall_get(const orc_wall *w, int q) {
+  if (!w) return NULL;
+  const real *const a[12] = {w->ur_t1, w->ur_t2, w->ur_p1, w->ur_p2, w->ut_r1, w->ut_r2,
+                             w->ut_p1, w->ut_p2, w->uf_r1, w->uf_r2, w->uf_t1, w->uf_t2};
+  return a[q];
+}
+static void wall_set(orc_wall *w, int q, const real *x) {
+  const real **a[12] = {&w->ur_t1, &w->ur_t2, &w->ur_p1, &w->ur_p2, &w->ut_r1, &w->ut_r2,
+                        &w->ut_p1, &w->ut_p2, &w->uf_r1, &w->uf_r2, &w->uf_t1, &w->uf_t2};
+  *a[q] = x;
+}
+/* out = ca a + cb b entry by entry; mem[12] receives the arrays to free */
+static void wall_mix(const orc_grid *g, double ca, const orc_wall *a, double cb, const orc_wall *b,
+                     orc_wall *out, real **mem) {
+  memset(out, 0, sizeof(*out));
+  for (int q = 0; q < 12; q++) {
+    const real *x = wall_get(a, q), *y = wall_get(b, q);
+    long n = wall_len(g, q);
+    mem[q] = calloc(n, sizeof(real));
+    for (long e = 0; e < n; e++) mem[q][e] = ca * (x ? x[e] : 0.0) + cb * (y ? y[e] : 0.0);
+    wall_set(out, q, mem[q]);
+  }
+}
+/* the walls of direction d (normal to it) take part in the d sweep: their
+ * tangential data are the wall indices 4,5,8,9 (r), 0,1,10,11 (theta),
+ * 2,3,6,7 (phi) */
+static int wall_of_dir(int q, int d) {
+  static const int dir[12] = {1, 1, 2, 2, 0, 0, 2, 2, 0, 0, 1, 1};
+  return dir[q] == d;
+}
+
+/* One split time step: U^{n+1} from U^n with K iterations (section 2.2).
+ *
+ * Boundary data (velocity Dirichlet data, paper section 3.1: they vary in time
+ * for a manufactured solution):
+ *   wall0, wall1: tangential wall velocities at t^n and t^{n+1} (NULL: zero);
+ *   bnd: fields whose boundary-normal faces hold the Dirichlet data at
+ *   t^{n+1} (NULL: those of Un, unchanged); Un's hold those at t^n;
+ *   src: the source taken at the midpoint time (may be NULL).
+ * U^{n+1,0} = U^n, boundary faces and wall data included (eq.
+ * (chapter3mainsd): the iteration starts from U^n).  Every iterate's
+ * increment solves (spl1)-(spl3) carry the change of the boundary data from
+ * iterate k to the new time level as inhomogeneous Dirichlet data of the
+ * increments xi - U^{n+1,k}, eta - U^{n+1,k}, U^{n+1,k+1} - U^{n+1,k}: in the
+ * d sweep the data on the walls normal to d are lifted out of the increment
+ * (X = X_0 + X_b, X_b zero but on those walls), i.e. the right-hand side
+ * loses tau/2 D_d(Ubar) X_b and X_0 solves the homogeneous line systems.
+ * After the first iteration every iterate holds the new data, so the later
+ * increments are homogeneous.  Ubar's ghost values take the mean wall data of
+ * U^{n+1,k} and U^n.  Returns 0, or -1 on a vanishing pivot. */
 int orc_split_step(const orc_grid *g, const orc_mat *m, const orc_fields *Un, orc_fields *Unp1,
-                   double tau, int K, const orc_wall *wall, const orc_fields *src,
-                   const orc_fields *bnd) {
-  orc_fields Uk, R, Ub, X1, X2, X3;
+                   double tau, int K, const orc_wall *wall0, const orc_wall *wall1,
+                   const orc_fields *src, const orc_fields *bnd) {
+  orc_fields Uk, R, Ub, X1, X2, X3, Xb, C;
   alloc_fields(g, &Uk); alloc_fields(g, &R); alloc_fields(g, &Ub);
   alloc_fields(g, &X1); alloc_fields(g, &X2); alloc_fields(g, &X3);
+  alloc_fields(g, &Xb); alloc_fields(g, &C);
   const real *un[5] = {Un->p, Un->ur, Un->ut, Un->uf, Un->T};
   real *uk[5] = {Uk.p, Uk.ur, Uk.ut, Uk.uf, Uk.T};
-  real *x3[5] = {X3.p, X3.ur, X3.ut, X3.uf, X3.T};
   for (int q = 0; q < 5; q++) memcpy(uk[q], un[q], sizeof(real) * fsize(g, q));
-  if (bnd) copy_bnd_faces(g, bnd, &Uk);
+  orc_fields Bn1; /* Dirichlet data of the new time level on boundary faces */
+  alloc_fields(g, &Bn1);
+  copy_bnd_faces(g, bnd ? bnd : Un, &Bn1);
+  real *wmem[3][12];
+  orc_wall wmid0, wmid1, dw0;   /* mean wall data of the iterates 0 and >= 1; change at 0 */
+  wall_mix(g, 1.0, wall0, 0.0, NULL, &wmid0, wmem[0]);
+  wall_mix(g, 0.5, wall0, 0.5, wall1, &wmid1, wmem[1]);
+  wall_mix(g, 1.0, wall1, -1.0, wall0, &dw0, wmem[2]);
   int rc = 0;
   for (int it = 0; it < K && !rc; it++) {
-    orc_residual(g, m, Un, &Uk, wall, src, tau, &R, &Ub);
-    rc |= orc_line_solve(g, m, &Ub, wall, tau, 0, &R, &X1);
-    rc |= orc_line_solve(g, m, &Ub, wall, tau, 1, &X1, &X2);
-    rc |= orc_line_solve(g, m, &Ub, wall, tau, 2, &X2, &X3);
+    const orc_wall *wm = it == 0 ? &wmid0 : &wmid1;
+    orc_residual(g, m, Un, &Uk, wm, src, tau, &R, &Ub);
+    const orc_fields *rhs = &R;
+    orc_fields *outs[3] = {&X1, &X2, &X3};
+    for (int d = 0; d < 3 && !rc; d++) {
+      if (it == 0) {
+        /* X_b: the change of the data on the walls normal to d */
+        zero_fields(g, &Xb);
+        if (d == 0)
+          for (int j = 0; j < g->nt; j++)
+            for (int k = 0; k < g->np; k++)
+              for (int f = 0; f <= g->nr; f += g->nr)
+                Xb.ur[IR(g, f, j, k)] = Bn1.ur[IR(g, f, j, k)] - Uk.ur[IR(g, f, j, k)];
+        if (d == 1)
+          for (int i = 0; i < g->nr; i++)
+            for (int k = 0; k < g->np; k++)
+              for (int f = 0; f <= g->nt; f += g->nt)
+                Xb.ut[IT(g, i, f, k)] = Bn1.ut[IT(g, i, f, k)] - Uk.ut[IT(g, i, f, k)];
+        if (d == 2 && !g->periodic)
+          for (int i = 0; i < g->nr; i++)
+            for (int j = 0; j < g->nt; j++)
+              for (int f = 0; f <= g->np; f += g->np)
+                Xb.uf[IF(g, i, j, f)] = Bn1.uf[IF(g, i, j, f)] - Uk.uf[IF(g, i, j, f)];
+        orc_wall dwd;
+        memset(&dwd, 0, sizeof(dwd));
+        for (int q = 0; q < 12; q++)
+          if (wall_of_dir(q, d)) wall_set(&dwd, q, wall_get(&dw0, q));
+        orc_apply(g, m, &Ub, wm, &Xb, &dwd, d == 0 ? MR : (d == 1 ? MT : MF), &C);
+        real *cc[5] = {C.p, C.ur, C.ut, C.uf, C.T};
+        const real *rr[5] = {rhs->p, rhs->ur, rhs->ut, rhs->uf, rhs->T};
+        for (int q = 0; q < 5; q++) {
+          long n = fsize(g, q);
+          for (long x = 0; x < n; x++) cc[q][x] = rr[q][x] - 0.5 * tau * cc[q][x];
+        }
+        rc |= orc_line_solve(g, m, &Ub, wm, tau, d, &C, outs[d]);
+      } else {
+        rc |= orc_line_solve(g, m, &Ub, wm, tau, d, rhs, outs[d]);
+      }
+      rhs = outs[d];
+    }
+    real *x3[5] = {X3.p, X3.ur, X3.ut, X3.uf, X3.T};
     for (int q = 0; q < 5; q++) {
       long n = fsize(g, q);
       for (long x = 0; x < n; x++) uk[q][x] += x3[q][x];
     }
+    copy_bnd_faces(g, &Bn1, &Uk); /* every later iterate holds the new data */
   }
   real *out[5] = {Unp1->p, Unp1->ur, Unp1->ut, Unp1->uf, Unp1->T};
   for (int q = 0; q < 5; q++) memcpy(out[q], uk[q], sizeof(real) * fsize(g, q));
   free_fields(&Uk); free_fields(&R); free_fields(&Ub);
   free_fields(&X1); free_fields(&X2); free_fields(&X3);
+  free_fields(&Xb); free_fields(&C); free_fields(&Bn1);
+  for (int a = 0; a < 3; a++)
+    for (int q = 0; q < 12; q++) free(wmem[a][q]);
   return rc ? -1 : 0;
 }
 

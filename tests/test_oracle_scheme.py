@@ -8,8 +8,9 @@
   against an independent dense Newton solve;
 * manufactured solution (eq. (man_sol)): second-order l2 convergence of every
   field at M0 = 1e-2 (paper, figure "conv");
-* incompressible limit (Table 3): max (p - p0)/p0 after 1, 50, 100 steps of
-  tau = 1e-3 reproduces the printed 3.2 / 3.6 / 4.0 x M0^2.
+* incompressible limit (Table 3): max (p - p0)/p0 over all cells after 1, 50,
+  100 steps of tau = 1e-3 reproduces the printed 3.2 / 3.6 / 4.0 x M0^2, and
+  stays O(M0^2) down to M0 = 1e-6.
 """
 import json
 import math
@@ -92,9 +93,8 @@ def run_mms(M, g, tau, nsteps, K, record=None):
         tn, tn1 = n * tau, (n + 1) * tau
         s0, s1 = S(tn), S(tn1)
         src = {k: np.ascontiguousarray(0.5 * (s0[k] + s1[k])) for k in s0}
-        w0, w1 = M.wall(g, tn), M.wall(g, tn1)
-        wall = {k: 0.5 * (w0[k] + w1[k]) for k in w0}
-        U = oracle.split_step(g, MAT_MMS, U, tau, K, wall=wall, src=src, bnd=M.fields(g, tn1))
+        U = oracle.split_step(g, MAT_MMS, U, tau, K, wall0=M.wall(g, tn), wall1=M.wall(g, tn1),
+                              src=src, bnd=M.fields(g, tn1))
         if record and (n + 1) in record:
             out.append((n + 1, U))
     return U, out
@@ -111,10 +111,10 @@ def test_mms_second_order_in_space():
     """l2 error of every field after 10 steps of tau = 1e-4 (t = 1e-3),
     K = 2, M0 = 1e-2; cells balanced to the solution's wavelengths.  Also the
     mass sum rho V: the non-conservative form does not keep it exactly (the
-    exact solution has rho = 1); its relative drift must be small and shrink
-    under refinement.  Observed: 2.5e-11, 8.5e-12, 4.2e-12 (order 1.5, then
-    1.0: the drift converges more slowly than the fields, near-wall cells
-    dominate it)."""
+    exact solution has rho = 1).  Its relative drift stays a few parts in
+    10^12 at every resolution (observed 1.3e-12, 1.6e-12, 1.1e-12, and the
+    same with tau refined with the grid): below the fields' truncation errors,
+    which converge at second order."""
     M = mms.MMS(1e-2, I.MMS)
     R = I.MMS.R
     errs, drift = [], []
@@ -132,17 +132,19 @@ def test_mms_second_order_in_space():
         o2 = math.log2(errs[1][k] / errs[2][k])
         assert o1 > 1.8 and o2 > 1.9, (k, o1, o2)
     print("mass drift", drift)
-    assert drift[0] < 1e-10 and drift[1] < 0.6 * drift[0] and drift[2] < 0.6 * drift[1]
+    assert max(drift) < 3e-12, drift
 
 
 def test_mach_sweep_stable():
     """Mach numbers 1e-2 ... 1e-6 (paper, after Table 3: stable for
-    M0 >= 1e-6, pressure variations O(M0^2)): two steps of tau = 1e-3 on
-    16 x 15 x 45 cells stay finite at every M0; max (p - p0)/p0 / M0^2 is
-    within 1.5 % of the closed form down to M0 = 1e-4.  Below, it grows
-    (about 3.6 at 1e-5 and 29 at 1e-6 after one step on this grid): the
-    pressure error no longer scales with M0^2, more than in the paper's
-    own values (3.2 and 3.9 after one step), and is recorded, not pinned."""
+    M0 >= 1e-6, pressure variations O(M0^2), no O(M0) acoustic pollution):
+    two steps of tau = 1e-3 on 16 x 15 x 45 cells stay finite at every M0;
+    max over all cells of (p - p0)/p0 / M0^2 is within 1.5 % of the closed
+    form down to M0 = 1e-4; at 1e-5 within 10 % above it (observed 3.21 and
+    3.36 against 3.19 and 3.20; the paper's own 1e-5 column lies up to 24 %
+    above the closed form); at 1e-6 O(M0^2) still, below 8 (observed 4.04
+    and 5.69; the paper's own 1e-6 column reads 3.9, 9.6 and 14 after 1, 50
+    and 100 steps on its finer grid)."""
     g = oracle.Grid(16, 15, 45, *mms.DOMAIN)
     for mach in (1e-2, 1e-3, 1e-4, 1e-5, 1e-6):
         M = mms.MMS(mach, I.MMS)
@@ -154,15 +156,19 @@ def test_mach_sweep_stable():
             print(f"M0={mach:.0e} n={n}: {dp:.4f} (closed form {exact:.4f})")
             if mach >= 1e-4:
                 assert abs(dp - exact) < 0.015 * exact, (mach, n, dp, exact)
+            elif mach >= 1e-5:
+                assert exact <= dp < 1.1 * exact, (mach, n, dp, exact)
             else:
-                assert dp < 100.0, (mach, n, dp)
+                assert exact <= dp < 8.0, (mach, n, dp)
 
 
 @pytest.mark.parametrize("mach", [1e-2, 1e-3])
 def test_table3_incompressible_limit(mach):
-    """Table 3: max relative pressure fluctuation after n steps, tau = 1e-3.
-    Odd cell counts put cell centres on the maxima of cos^2(4 theta) and
-    cos^2(4 phi); the printed values are 3.2, 3.6, 4.0 (x M0^2)."""
+    """Table 3: max over all cells of the relative pressure fluctuation after
+    n steps, tau = 1e-3.  Odd cell counts put cell centres on the maxima of
+    cos^2(4 theta) and cos^2(4 phi); the printed values are 3.2, 3.6, 4.0
+    (x M0^2).  This grid (diameter 0.30) is coarser than the paper's (0.12):
+    within 1.5 % of the closed form, and equal to the printed digits."""
     M = mms.MMS(mach, I.MMS)
     g = oracle.Grid(16, 15, 45, *mms.DOMAIN)
     _, rec = run_mms(M, g, 1e-3, 100, 2, record={1, 50, 100})
@@ -174,5 +180,6 @@ def test_table3_incompressible_limit(mach):
     for n, U in rec:
         dp = np.max(np.abs(U["p"] - mms.P0)) / mms.P0 / mach ** 2
         exact = np.max(np.abs(M.fields(g, n * 1e-3)["p"] - mms.P0)) / mms.P0 / mach ** 2
-        assert abs(dp - exact) < 0.01 * exact, (n, dp, exact)
+        print(f"M0={mach:.0e} n={n}: {dp:.4f} (closed form {exact:.4f}, printed {printed[n]})")
+        assert abs(dp - exact) < 0.015 * exact, (n, dp, exact)
         assert round(dp, 1) == printed[n], (n, dp)
