@@ -145,12 +145,11 @@ int dsw_split_step(dsw_grid *grid, const dsw_fields *Un, dsw_fields *Unp1, doubl
 int dsw_split_step_noalloc(dsw_grid *grid, const dsw_fields *Un, dsw_fields *Unp1, double tau,
                            int32_t K, void *stream);
 
-/* Tangential velocities on the non-periodic walls, at the time the ghost
- * values are wanted (for a split step: the midpoint of the old and the new
- * time level).  Device arrays, C order; a null entry is a zero wall velocity.
- * A ghost value across a wall is 2 g - u of the interior neighbour (the
- * no-slip rule of the velocity boundary condition, paper section 2.1, with
- * the wall moving).  Pole boundaries ignore them (symmetry ghosts).
+/* Tangential velocities on the non-periodic walls at one time level.  Device
+ * arrays, C order; a null entry is a zero wall velocity.  A ghost value
+ * across a wall is 2 g - u of the interior neighbour (the no-slip rule of the
+ * velocity boundary condition, paper section 2.1, with the wall moving).  Pole
+ * boundaries ignore them (symmetry ghosts).
  *   ur_t1, ur_t2 [n_r+1][n_phi]      u_r on the theta = theta1 / theta2 walls
  *   ur_p1, ur_p2 [n_r+1][n_theta]    u_r on the phi = phi1 / phi2 walls
  *   ut_r1, ut_r2 [n_theta+1][n_phi]  u_theta on the r = r1 / r2 walls
@@ -164,22 +163,28 @@ typedef struct {
   const double *uf_r1, *uf_r2, *uf_t1, *uf_t2;
 } dsw_wall;
 
-/* dsw_split_step with forcing, for manufactured solutions (paper section 3.1,
- * eq. (man_sol)) and moving or time-dependent walls:
- *   src  (may be NULL, as may each of its arrays) a source S added to the
- *        right-hand side of the system, taken at the midpoint time: every
- *        iteration's residual is -(U^k - U^n) - tau (F_h(Ubar) - S);
- *   wall (may be NULL) wall velocities for the ghost values of Ubar;
- *   bnd  (may be NULL) fields whose boundary-normal faces (ur, ut, uf; p and
- *        T are not read) hold the Dirichlet data of the new time level:
- *        U^{n+1,k} takes them for every k and Ubar their mean with those of
- *        Un.  NULL: those of Un.
+/* dsw_split_step with forcing and time-dependent velocity boundary data, for
+ * manufactured solutions (paper section 3.1, eq. (man_sol)) and moving walls:
+ *   src   (may be NULL, as may each of its arrays) a source S added to the
+ *         right-hand side of the system, taken at the midpoint time: every
+ *         iteration's residual is -(U^k - U^n) - tau (F_h(Ubar) - S);
+ *   wall0, wall1 (each may be NULL) tangential wall velocities at t^n and
+ *         t^{n+1};
+ *   bnd   (may be NULL) fields whose boundary-normal faces (ur, ut, uf; p and
+ *         T are not read) hold the Dirichlet data of t^{n+1}; Un's hold those
+ *         of t^n.  NULL: the data keep Un's.
+ * U^{n+1,0} = U^n, boundary data included (eq. (chapter3mainsd)).  The first
+ * iteration's increment solves (spl1)-(spl3) carry the change of the boundary
+ * data to t^{n+1} as inhomogeneous Dirichlet data of the increments (lifted
+ * into their right-hand sides); every later iterate holds the new data, its
+ * midpoint their mean with Un's, and its ghost values the mean wall velocity.
  * The rest as dsw_split_step.  Runs the residual over every point and needs
  * phi lines that the partitioned solver takes (any sector of up to 1024 phi
- * cells; on a full sphere a power-of-two chunk count), else DSW_EINVAL. */
+ * cells; on a full sphere a power-of-two chunk count), else DSW_EINVAL.  The
+ * first call on a handle allocates a small workspace for the wall data. */
 int dsw_split_step_forced(dsw_grid *grid, const dsw_fields *Un, dsw_fields *Unp1, double tau,
-                          int32_t K, const dsw_fields *src, const dsw_wall *wall,
-                          const dsw_fields *bnd, void *stream);
+                          int32_t K, const dsw_fields *src, const dsw_wall *wall0,
+                          const dsw_wall *wall1, const dsw_fields *bnd, void *stream);
 
 /* Optional per-kernel timing of dsw_split_step.  While enabled, every kernel
  * the step enqueues is bracketed by a pair of HIP events recorded on the same

@@ -1,29 +1,41 @@
-"""Build libdsw.so (HIP, gfx950) in-tree with hipcc."""
+"""Build libdsw.so (HIP, gfx950) in-tree with hipcc: every source compiled to
+its own object (in parallel), then linked."""
 import os
 import subprocess
 import sys
+from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 SRC = [os.path.join(HERE, "csrc", f) for f in ("residual.hip", "sweeps.hip", "phi_part.hip", "adjoint.hip", "api.hip")]
 LIB = os.path.join(HERE, "libdsw.so")
+OBJ = os.path.join(HERE, "_build")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 # -ffp-contract=on: multiply-adds are fused only within one source
 # expression, so that every kernel built from the same row code rounds the
 # same way (the batched ensemble kernels and the single-grid ones give
 # bitwise-equal states)
-FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared", "-ffp-contract=on",
+FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-ffp-contract=on",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-I", os.path.join(ROOT, "include"), "-Wall", "-Wno-unused-function"]
 
 
-def build(verbose=False):
-    """Compile every HIP source into libdsw.so (always recompiles)."""
-    tmp = LIB + ".tmp"
-    cmd = [HIPCC] + FLAGS + ["-o", tmp] + SRC
+def _run(cmd, verbose):
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)
+
+
+def build(verbose=False):
+    """Compile every HIP source into libdsw.so (always recompiles)."""
+    os.makedirs(OBJ, exist_ok=True)
+    objs = [os.path.join(OBJ, os.path.basename(s)[:-4] + ".o") for s in SRC]
+    with ThreadPoolExecutor(max_workers=len(SRC)) as ex:
+        futs = [ex.submit(_run, [HIPCC] + FLAGS + ["-c", s, "-o", o], verbose) for s, o in zip(SRC, objs)]
+        for f in futs:
+            f.result()
+    tmp = LIB + ".tmp"
+    _run([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs, verbose)
     os.replace(tmp, LIB)
     return LIB
 

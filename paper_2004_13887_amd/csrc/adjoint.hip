@@ -266,7 +266,7 @@ __device__ __forceinline__ void F_p_T_rev(const Geo &g, const Mat &m, const S &s
 template <class S, class Acc>
 __device__ __forceinline__ void F_ur_rev(const Geo &g, const Mat &m, const S &s, int f, int j, int k, double w,
                          const Acc &A, double rfx = 0.0, double uax = 0.0, double ubx = 0.0) {
-  const double irF = g.irf[f], is = g.isc[j], irF2 = irF * irF;
+  const double irF = g.irf[f], is = g.isc[j];
   const double Pa = gC(g, s, F_P, f, j, k) + m.pinf, Ta = gC(g, s, F_T, f, j, k);
   const double Pb_ = gC(g, s, F_P, f - 1, j, k) + m.pinf, Tb_ = gC(g, s, F_T, f - 1, j, k);
   const double rho_a = Pa / (m.Rg * Ta), rho_b = Pb_ / (m.Rg * Tb_);
@@ -283,16 +283,15 @@ __device__ __forceinline__ void F_ur_rev(const Geo &g, const Mat &m, const S &s,
   const double yp = gR(g, s, f, j + 1, k), ym = gR(g, s, f, j - 1, k);
   const double zp = gR(g, s, f, j, k + 1), zm = gR(g, s, f, j, k - 1);
   const double pa = Pa - m.pinf, pb = Pb_ - m.pinf;
-  const double Cr = irF2 * g.idr * g.idr, Ct = irF2 * is * g.idt * g.idt, Cp = irF2 * is * is * g.idp * g.idp;
-  const double ra2 = g.rc[f] * g.rc[f], rb2 = g.rc[f - 1] * g.rc[f - 1];
-  double vis = (ra2 * (xp - un) - rb2 * (un - xm)) * Cr + (g.sf[j + 1] * (yp - un) - g.sf[j] * (un - ym)) * Ct +
-               (zp - 2.0 * un + zm) * Cp;
-  const double dth = 0.5 * ((g.sf[j + 1] * T01 - g.sf[j] * T00) + (g.sf[j + 1] * T11 - g.sf[j] * T10)) * g.idt;
-  const double dph = 0.5 * ((F01 - F00) + (F11 - F10)) * g.idp;
-  vis += -2.0 * un * irF2 - 2.0 * irF2 * is * dth - 2.0 * irF2 * is * dph;
   const double gd = (divc(g, s, f, j, k) - divc(g, s, f - 1, j, k)) * g.idr;
-  // reverse of F = N - nu vis - nu/3 gd + g_r
-  const double Nb = w, visb = -nu * w, gdb = -nu / 3.0 * w, nub = -(vis + gd / 3.0) * w;
+  const double wp0 = (T10 - T00) * g.idr + 0.5 * (T10 + T00) * irF - (un - ym) * (irF * g.idt);
+  const double wp1 = (T11 - T01) * g.idr + 0.5 * (T11 + T01) * irF - (yp - un) * (irF * g.idt);
+  const double wt0 = (un - zm) * (irF * is * g.idp) - (F10 - F00) * g.idr - 0.5 * (F10 + F00) * irF;
+  const double wt1 = (zp - un) * (irF * is * g.idp) - (F11 - F01) * g.idr - 0.5 * (F11 + F01) * irF;
+  const double C = ((g.sf[j + 1] * wp1 - g.sf[j] * wp0) * g.idt - (wt1 - wt0) * g.idp) * (irF * is);
+  const double vis = gd - C;
+  // reverse of F = N - nu vis - nu/3 gd + g_r, vis = gd - C
+  const double Nb = w, visb = -nu * w, gdb = -nu / 3.0 * w + visb, nub = -(vis + gd / 3.0) * w;
   double uab = uax, ubb = ubx - 2.0 * m.omega * g.sc[j] * Nb, unb = 0.0;
   double aT00 = 0.0, aT01 = 0.0, aT10 = 0.0, aT11 = 0.0, aF00 = 0.0, aF01 = 0.0, aF10 = 0.0, aF11 = 0.0;
   double aRf = 0.0, aRfp = 0.0, aRfm = 0.0;
@@ -309,16 +308,21 @@ __device__ __forceinline__ void F_ur_rev(const Geo &g, const Mat &m, const S &s,
     aF11 += c1p; aF10 -= c1p;
     aF01 += c0p; aF00 -= c0p;
   }
-  unb += -2.0 * irF2 * visb;
-  const double dthb = -2.0 * irF2 * is * visb, dphb = -2.0 * irF2 * is * visb;
-  aF01 += 0.5 * g.idp * dphb; aF00 -= 0.5 * g.idp * dphb;
-  aF11 += 0.5 * g.idp * dphb; aF10 -= 0.5 * g.idp * dphb;
-  aT01 += 0.5 * g.idt * g.sf[j + 1] * dthb; aT00 -= 0.5 * g.idt * g.sf[j] * dthb;
-  aT11 += 0.5 * g.idt * g.sf[j + 1] * dthb; aT10 -= 0.5 * g.idt * g.sf[j] * dthb;
-  double xpb = ra2 * Cr * visb, xmb = rb2 * Cr * visb;
-  double ypb = g.sf[j + 1] * Ct * visb, ymb = g.sf[j] * Ct * visb;
-  double zpb = Cp * visb, zmb = Cp * visb;
-  unb -= ((ra2 + rb2) * Cr + (g.sf[j + 1] + g.sf[j]) * Ct + 2.0 * Cp) * visb;
+  double xpb = 0.0, xmb = 0.0, ypb, ymb, zpb, zmb;
+  {  // C = (curl omega)_r, reversed
+    const double q = -visb * (irF * is);
+    const double wp1b = g.sf[j + 1] * g.idt * q, wp0b = -g.sf[j] * g.idt * q;
+    const double wt1b = -g.idp * q, wt0b = g.idp * q;
+    const double c1 = g.idr + 0.5 * irF, c0 = -g.idr + 0.5 * irF;
+    aT10 += c1 * wp0b; aT00 += c0 * wp0b;
+    aT11 += c1 * wp1b; aT01 += c0 * wp1b;
+    aF10 -= c1 * wt0b; aF00 -= c0 * wt0b;
+    aF11 -= c1 * wt1b; aF01 -= c0 * wt1b;
+    const double ht_ = irF * g.idt, hp_ = irF * is * g.idp;
+    unb += ht_ * (wp1b - wp0b) + hp_ * (wt0b - wt1b);
+    ymb = ht_ * wp0b; ypb = -ht_ * wp1b;
+    zmb = -hp_ * wt0b; zpb = hp_ * wt1b;
+  }
   const double hr = 0.5 * g.idr, ht = 0.5 * irF * g.idt, hp = 0.5 * irF * is * g.idp;
   double irhob = (pa - pb) * g.idr * Nb;
   double aPa = irho * g.idr * Nb, aPb = -irho * g.idr * Nb;
@@ -359,7 +363,7 @@ __device__ __forceinline__ void F_ur_rev(const Geo &g, const Mat &m, const S &s,
 template <class S, class Acc>
 __device__ __forceinline__ void F_ut_rev(const Geo &g, const Mat &m, const S &s, int i, int f, int k, double w,
                          const Acc &A, double rfx = 0.0, double uax = 0.0, double ubx = 0.0) {
-  const double ir = g.irc[i], isF = g.isf[f], ctF = g.ctf[f], ir2 = ir * ir;
+  const double ir = g.irc[i], isF = g.isf[f], ctF = g.ctf[f];
   const int j0 = f - 1, j1 = f;
   const double P1 = gC(g, s, F_P, i, j1, k) + m.pinf, T1 = gC(g, s, F_T, i, j1, k);
   const double P0 = gC(g, s, F_P, i, j0, k) + m.pinf, T0 = gC(g, s, F_T, i, j0, k);
@@ -377,15 +381,15 @@ __device__ __forceinline__ void F_ut_rev(const Geo &g, const Mat &m, const S &s,
   const double yp = gT(g, s, i, f + 1, k), ym = gT(g, s, i, f - 1, k);
   const double zp = gT(g, s, i, f, k + 1), zm = gT(g, s, i, f, k - 1);
   const double p1 = P1 - m.pinf, p0 = P0 - m.pinf;
-  const double Cr = ir2 * g.idr * g.idr, Ct = ir2 * isF * g.idt * g.idt, Cp = ir2 * isF * isF * g.idp * g.idp;
-  const double rp2 = g.rf[i + 1] * g.rf[i + 1], rm2 = g.rf[i] * g.rf[i];
-  double vis = (rp2 * (xp - un) - rm2 * (un - xm)) * Cr + (g.sc[j1] * (yp - un) - g.sc[j0] * (un - ym)) * Ct +
-               (zp - 2.0 * un + zm) * Cp;
-  const double dthr = 0.5 * ((R01 - R00) + (R11 - R10)) * g.idt;
-  const double dphf = 0.5 * ((F01 - F00) + (F11 - F10)) * g.idp;
-  vis += -un * ir2 * isF * isF + 2.0 * ir2 * dthr - 2.0 * ctF * ir2 * isF * dphf;
   const double gd = (divc(g, s, i, j1, k) - divc(g, s, i, j0, k)) * (ir * g.idt);
-  const double Nb = w, visb = -nu * w, gdb = -nu / 3.0 * w, nub = -(vis + gd / 3.0) * w;
+  const double wr0 = ((g.sc[j1] * F10 - g.sc[j0] * F00) * g.idt - (un - zm) * g.idp) * (ir * isF);
+  const double wr1 = ((g.sc[j1] * F11 - g.sc[j0] * F01) * g.idt - (zp - un) * g.idp) * (ir * isF);
+  const double ira = g.irf[i], irb = g.irf[i + 1];
+  const double wp0 = (un - xm) * g.idr + 0.5 * (un + xm) * ira - (R01 - R00) * (ira * g.idt);
+  const double wp1 = (xp - un) * g.idr + 0.5 * (xp + un) * irb - (R11 - R10) * (irb * g.idt);
+  const double C = (wr1 - wr0) * (ir * isF * g.idp) - (g.rf[i + 1] * wp1 - g.rf[i] * wp0) * (ir * g.idr);
+  const double vis = gd - C;
+  const double Nb = w, visb = -nu * w, gdb = -nu / 3.0 * w + visb, nub = -(vis + gd / 3.0) * w;
   double uab = uax, ubb = ubx - 2.0 * m.omega * g.cf[f] * Nb, unb = 0.0;
   double aR00 = 0.0, aR01 = 0.0, aR10 = 0.0, aR11 = 0.0, aF00 = 0.0, aF01 = 0.0, aF10 = 0.0, aF11 = 0.0;
   double aTf = 0.0, aTfp = 0.0, aTfm = 0.0;
@@ -402,16 +406,21 @@ __device__ __forceinline__ void F_ut_rev(const Geo &g, const Mat &m, const S &s,
     aF11 += c1p; aF10 -= c1p;
     aF01 += c0p; aF00 -= c0p;
   }
-  unb += -ir2 * isF * isF * visb;
-  const double dthrb = 2.0 * ir2 * visb, dphfb = -2.0 * ctF * ir2 * isF * visb;
-  aR01 += 0.5 * g.idt * dthrb; aR00 -= 0.5 * g.idt * dthrb;
-  aR11 += 0.5 * g.idt * dthrb; aR10 -= 0.5 * g.idt * dthrb;
-  aF01 += 0.5 * g.idp * dphfb; aF00 -= 0.5 * g.idp * dphfb;
-  aF11 += 0.5 * g.idp * dphfb; aF10 -= 0.5 * g.idp * dphfb;
-  double xpb = rp2 * Cr * visb, xmb = rm2 * Cr * visb;
-  double ypb = g.sc[j1] * Ct * visb, ymb = g.sc[j0] * Ct * visb;
-  double zpb = Cp * visb, zmb = Cp * visb;
-  unb -= ((rp2 + rm2) * Cr + (g.sc[j1] + g.sc[j0]) * Ct + 2.0 * Cp) * visb;
+  double xpb, xmb, ypb = 0.0, ymb = 0.0, zpb, zmb;
+  {  // C = (curl omega)_theta, reversed
+    const double Cb = -visb;
+    const double wr1b = ir * isF * g.idp * Cb, wr0b = -wr1b;
+    const double wp1b = -g.rf[i + 1] * ir * g.idr * Cb, wp0b = g.rf[i] * ir * g.idr * Cb;
+    const double e = ir * isF;
+    aF10 += g.sc[j1] * g.idt * e * wr0b; aF00 -= g.sc[j0] * g.idt * e * wr0b;
+    aF11 += g.sc[j1] * g.idt * e * wr1b; aF01 -= g.sc[j0] * g.idt * e * wr1b;
+    unb += g.idp * e * (wr1b - wr0b);
+    zmb = g.idp * e * wr0b; zpb = -g.idp * e * wr1b;
+    unb += (g.idr + 0.5 * ira) * wp0b + (-g.idr + 0.5 * irb) * wp1b;
+    xmb = (-g.idr + 0.5 * ira) * wp0b; xpb = (g.idr + 0.5 * irb) * wp1b;
+    aR01 -= ira * g.idt * wp0b; aR00 += ira * g.idt * wp0b;
+    aR11 -= irb * g.idt * wp1b; aR10 += irb * g.idt * wp1b;
+  }
   const double hr = 0.5 * g.idr, ht = 0.5 * ir * g.idt, hp = 0.5 * ir * isF * g.idp;
   double irhob = (p1 - p0) * ir * g.idt * Nb;
   double aP1 = irho * ir * g.idt * Nb, aP0 = -irho * ir * g.idt * Nb;
@@ -471,17 +480,56 @@ __device__ __forceinline__ void F_uf_rev(const Geo &g, const Mat &m, const S &s,
   const double yp = gF(g, s, i, j + 1, f), ym = gF(g, s, i, j - 1, f);
   const double zp = gF(g, s, i, j, f + 1), zm = gF(g, s, i, j, f - 1);
   const double p1 = P1 - m.pinf, p0 = P0 - m.pinf;
-  const double Cr = ir2 * g.idr * g.idr, Ct = ir2 * is * g.idt * g.idt, Cp = ir2 * is * is * g.idp * g.idp;
-  const double rp2 = g.rf[i + 1] * g.rf[i + 1], rm2 = g.rf[i] * g.rf[i];
-  double vis = (rp2 * (xp - un) - rm2 * (un - xm)) * Cr + (g.sf[j + 1] * (yp - un) - g.sf[j] * (un - ym)) * Ct +
-               (zp - 2.0 * un + zm) * Cp;
-  const double dphr = 0.5 * ((R01 - R00) + (R11 - R10)) * g.idp;
-  const double dpht = 0.5 * ((T01 - T00) + (T11 - T10)) * g.idp;
-  vis += -un * ir2 * is * is + 2.0 * ir2 * is * dphr + 2.0 * ct * ir2 * is * dpht;
   const double gd = (divc(g, s, i, j, k1) - divc(g, s, i, j, k0)) * (ir * is * g.idp);
-  const double Nb = w, visb = -nu * w, gdb = -nu / 3.0 * w, nub = -(vis + gd / 3.0) * w;
-  double ubb = ubx + 2.0 * m.omega * g.cc[j] * Nb, uab = uax + 2.0 * m.omega * g.sc[j] * Nb, unb = 0.0;
+  const bool pole_row = !S::INTERIOR && ((j == 0 && g.pole_lo) || (j == g.nt - 1 && g.pole_hi));
+  double vis;
+  double xpb = 0.0, xmb = 0.0, ypb = 0.0, ymb = 0.0, zpb = 0.0, zmb = 0.0, unb = 0.0;
   double aR00 = 0.0, aR01 = 0.0, aR10 = 0.0, aR11 = 0.0, aT00 = 0.0, aT01 = 0.0, aT10 = 0.0, aT11 = 0.0;
+  const double visb = -nu * w;
+  if (pole_row) {
+    // next to a pole: component form (scalar Laplacians and curvature terms)
+    const double Cr = ir2 * g.idr * g.idr, Ct = ir2 * is * g.idt * g.idt, Cp = ir2 * is * is * g.idp * g.idp;
+    const double rp2 = g.rf[i + 1] * g.rf[i + 1], rm2 = g.rf[i] * g.rf[i];
+    vis = (rp2 * (xp - un) - rm2 * (un - xm)) * Cr + (g.sf[j + 1] * (yp - un) - g.sf[j] * (un - ym)) * Ct +
+          (zp - 2.0 * un + zm) * Cp;
+    const double dphr = 0.5 * ((R01 - R00) + (R11 - R10)) * g.idp;
+    const double dpht = 0.5 * ((T01 - T00) + (T11 - T10)) * g.idp;
+    vis += -un * ir2 * is * is + 2.0 * ir2 * is * dphr + 2.0 * ct * ir2 * is * dpht;
+    unb += -ir2 * is * is * visb;
+    const double dphrb = 2.0 * ir2 * is * visb, dphtb = 2.0 * ct * ir2 * is * visb;
+    aR01 += 0.5 * g.idp * dphrb; aR00 -= 0.5 * g.idp * dphrb;
+    aR11 += 0.5 * g.idp * dphrb; aR10 -= 0.5 * g.idp * dphrb;
+    aT01 += 0.5 * g.idp * dphtb; aT00 -= 0.5 * g.idp * dphtb;
+    aT11 += 0.5 * g.idp * dphtb; aT10 -= 0.5 * g.idp * dphtb;
+    xpb = rp2 * Cr * visb; xmb = rm2 * Cr * visb;
+    ypb = g.sf[j + 1] * Ct * visb; ymb = g.sf[j] * Ct * visb;
+    zpb = Cp * visb; zmb = Cp * visb;
+    unb -= ((rp2 + rm2) * Cr + (g.sf[j + 1] + g.sf[j]) * Ct + 2.0 * Cp) * visb;
+  } else {
+    const double ira = g.irf[i], irb = g.irf[i + 1];
+    const double wt0 = (R01 - R00) * (ira * is * g.idp) - (un - xm) * g.idr - 0.5 * (un + xm) * ira;
+    const double wt1 = (R11 - R10) * (irb * is * g.idp) - (xp - un) * g.idr - 0.5 * (xp + un) * irb;
+    const double wr0 = ((g.scx[j + 1] * un - g.scx[j] * ym) * g.idt - (T01 - T00) * g.idp) * (ir * g.isf[j]);
+    const double wr1 = ((g.scx[j + 2] * yp - g.scx[j + 1] * un) * g.idt - (T11 - T10) * g.idp) * (ir * g.isf[j + 1]);
+    const double C = (g.rf[i + 1] * wt1 - g.rf[i] * wt0) * (ir * g.idr) - (wr1 - wr0) * (ir * g.idt);
+    vis = gd - C;
+    // C = (curl omega)_phi, reversed
+    const double Cb = -visb;
+    const double wt1b = g.rf[i + 1] * ir * g.idr * Cb, wt0b = -g.rf[i] * ir * g.idr * Cb;
+    const double wr1b = -ir * g.idt * Cb, wr0b = -wr1b;
+    aR01 += ira * is * g.idp * wt0b; aR00 -= ira * is * g.idp * wt0b;
+    aR11 += irb * is * g.idp * wt1b; aR10 -= irb * is * g.idp * wt1b;
+    unb += (-g.idr - 0.5 * ira) * wt0b + (g.idr - 0.5 * irb) * wt1b;
+    xmb = (g.idr - 0.5 * ira) * wt0b; xpb = (-g.idr - 0.5 * irb) * wt1b;
+    const double e0 = ir * g.isf[j] * wr0b, e1 = ir * g.isf[j + 1] * wr1b;
+    unb += g.scx[j + 1] * g.idt * (e0 - e1);
+    ymb = -g.scx[j] * g.idt * e0; ypb = g.scx[j + 2] * g.idt * e1;
+    aT01 -= g.idp * e0; aT00 += g.idp * e0;
+    aT11 -= g.idp * e1; aT10 += g.idp * e1;
+  }
+  // reverse of F = N - nu vis - nu/3 gd, vis = gd - C off the poles
+  const double Nb = w, gdb = -nu / 3.0 * w + (pole_row ? 0.0 : visb), nub = -(vis + gd / 3.0) * w;
+  double ubb = ubx + 2.0 * m.omega * g.cc[j] * Nb, uab = uax + 2.0 * m.omega * g.sc[j] * Nb;
   double aFf = 0.0, aFfp = 0.0, aFfm = 0.0;
   {  // divergences at cells (i, j, k1) (+) and (i, j, k0) (-); their phi
      // faces k1 + 1 = f + 1, k1 = f, k0 + 1 = f, k0 = f - 1 (wrapped alike)
@@ -495,16 +543,6 @@ __device__ __forceinline__ void F_uf_rev(const Geo &g, const Mat &m, const S &s,
     aFf += -irs * g.idp * a1 + irs * g.idp * a0;
     aFfm += -irs * g.idp * a0;
   }
-  unb += -ir2 * is * is * visb;
-  const double dphrb = 2.0 * ir2 * is * visb, dphtb = 2.0 * ct * ir2 * is * visb;
-  aR01 += 0.5 * g.idp * dphrb; aR00 -= 0.5 * g.idp * dphrb;
-  aR11 += 0.5 * g.idp * dphrb; aR10 -= 0.5 * g.idp * dphrb;
-  aT01 += 0.5 * g.idp * dphtb; aT00 -= 0.5 * g.idp * dphtb;
-  aT11 += 0.5 * g.idp * dphtb; aT10 -= 0.5 * g.idp * dphtb;
-  double xpb = rp2 * Cr * visb, xmb = rm2 * Cr * visb;
-  double ypb = g.sf[j + 1] * Ct * visb, ymb = g.sf[j] * Ct * visb;
-  double zpb = Cp * visb, zmb = Cp * visb;
-  unb -= ((rp2 + rm2) * Cr + (g.sf[j + 1] + g.sf[j]) * Ct + 2.0 * Cp) * visb;
   const double hr = 0.5 * g.idr, ht = 0.5 * ir * g.idt, hp = 0.5 * ir * is * g.idp;
   double irhob = (p1 - p0) * ir * is * g.idp * Nb;
   double aP1 = irho * ir * is * g.idp * Nb, aP0 = -irho * ir * is * g.idp * Nb;

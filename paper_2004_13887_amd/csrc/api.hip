@@ -29,6 +29,7 @@ struct dsw_grid {
   Scratch sc{};
   double *scratch_mem = nullptr;
   double *adj_mem = nullptr; // adjoint workspace, allocated on first use
+  double *fwall_mem = nullptr; // forced step: mean and change of the wall data, on first use
   int adj_states = 0;         // five-field states it holds
   // the adjoint's second stream (non-blocking, default priority), its
   // fork/join events and the sweep scratch of the work it runs
@@ -169,10 +170,10 @@ extern "C" int dsw_init_grid(const dsw_grid_desc *desc, const dsw_material *mat,
   const int nr = desc->n_r, nt = desc->n_theta, np = desc->n_phi;
   // metric tables (host, then device)
   const size_t nt1 = (size_t)nt + 1, nr1 = (size_t)nr + 1;
-  std::vector<double> h(2 * (nr + nr1) + 4 * (nt + nt1));
+  std::vector<double> h(2 * (nr + nr1) + 4 * (nt + nt1) + (nt + 2));
   double *rc = h.data(), *rf = rc + nr, *sc = rf + nr1, *cc = sc + nt, *sf = cc + nt, *cf = sf + nt1;
   double *irc = cf + nt1, *irf = irc + nr, *isc = irf + nr1, *ctc = isc + nt, *isf = ctc + nt,
-         *ctf = isf + nt1;
+         *ctf = isf + nt1, *scx = ctf + nt1;
   const double dr = (desc->r2 - desc->r1) / nr, dt = (desc->theta2 - desc->theta1) / nt,
                dp = (desc->phi2 - desc->phi1) / np;
   for (int i = 0; i < nr; i++) rc[i] = desc->r1 + (i + 0.5) * dr;
@@ -187,6 +188,7 @@ extern "C" int dsw_init_grid(const dsw_grid_desc *desc, const dsw_material *mat,
     sf[f] = std::sin(th);
     cf[f] = std::cos(th);
   }
+  for (int j = -1; j <= nt; j++) scx[j + 1] = std::sin(desc->theta1 + (j + 0.5) * dt);
   const int pole_lo = desc->theta1 == 0.0, pole_hi = std::fabs(desc->theta2 - M_PI) <= 1e-12;
   if (pole_lo) { sf[0] = 0.0; cf[0] = 1.0; }
   if (pole_hi) { sf[nt] = 0.0; cf[nt] = -1.0; }
@@ -211,10 +213,11 @@ extern "C" int dsw_init_grid(const dsw_grid_desc *desc, const dsw_material *mat,
   double *t = G->tables;
   const long o_rf = nr, o_sc = o_rf + nr1, o_cc = o_sc + nt, o_sf = o_cc + nt, o_cf = o_sf + nt1,
              o_irc = o_cf + nt1, o_irf = o_irc + nr, o_isc = o_irf + nr1, o_ctc = o_isc + nt,
-             o_isf = o_ctc + nt, o_ctf = o_isf + nt1;
+             o_isf = o_ctc + nt, o_ctf = o_isf + nt1, o_scx = o_ctf + nt1;
   g.rc = t; g.rf = t + o_rf; g.sc = t + o_sc; g.cc = t + o_cc; g.sf = t + o_sf; g.cf = t + o_cf;
   g.irc = t + o_irc; g.irf = t + o_irf; g.isc = t + o_isc; g.ctc = t + o_ctc; g.isf = t + o_isf;
   g.ctf = t + o_ctf;
+  g.scx = t + o_scx;
   Mat &m = G->m;
   m.gam = mat->cp / mat->cv;
   m.Rg = mat->cp - mat->cv;
@@ -265,6 +268,7 @@ extern "C" int dsw_free_grid(dsw_grid *G) {
   if (G->fields_mem) (void)hipFree(G->fields_mem);
   if (G->scratch_mem) (void)hipFree(G->scratch_mem);
   if (G->adj_mem) (void)hipFree(G->adj_mem);
+  if (G->fwall_mem) (void)hipFree(G->fwall_mem);
   if (G->side) (void)hipStreamDestroy(G->side);
   if (G->fork_ev) (void)hipEventDestroy(G->fork_ev);
   if (G->join_ev) (void)hipEventDestroy(G->join_ev);
@@ -586,18 +590,32 @@ extern "C" int dsw_split_step_noalloc(dsw_grid *G, const dsw_fields *Un, dsw_fie
   return check_launch("allocation-free split step kernels");
 }
 
-static Wall to_wall(const dsw_wall *w) {
-  Wall o{};
-  if (!w) return o;
-  o.ur_t1 = w->ur_t1; o.ur_t2 = w->ur_t2; o.ur_p1 = w->ur_p1; o.ur_p2 = w->ur_p2;
-  o.ut_r1 = w->ut_r1; o.ut_r2 = w->ut_r2; o.ut_p1 = w->ut_p1; o.ut_p2 = w->ut_p2;
-  o.uf_r1 = w->uf_r1; o.uf_r2 = w->uf_r2; o.uf_t1 = w->uf_t1; o.uf_t2 = w->uf_t2;
+// lengths of the twelve wall arrays, in the order of dsw_wall
+static void wall_lens(const Geo &g, long len[12]) {
+  const long a = (long)(g.nr + 1) * g.np, b = (long)(g.nr + 1) * g.nt, c = (long)(g.nt + 1) * g.np,
+             d = (long)g.nr * (g.nt + 1), e = (long)g.nt * g.npf, f = (long)g.nr * g.npf;
+  const long l[12] = {a, a, b, b, c, c, d, d, e, e, f, f};
+  for (int q = 0; q < 12; q++) len[q] = l[q];
+}
+
+static const double *wall_ptr(const dsw_wall *w, int q) {
+  if (!w) return nullptr;
+  const double *const a[12] = {w->ur_t1, w->ur_t2, w->ur_p1, w->ur_p2, w->ut_r1, w->ut_r2,
+                               w->ut_p1, w->ut_p2, w->uf_r1, w->uf_r2, w->uf_t1, w->uf_t2};
+  return a[q];
+}
+
+static Wall wall_of(double *const p[12]) {
+  Wall o;
+  o.ur_t1 = p[0]; o.ur_t2 = p[1]; o.ur_p1 = p[2]; o.ur_p2 = p[3];
+  o.ut_r1 = p[4]; o.ut_r2 = p[5]; o.ut_p1 = p[6]; o.ut_p2 = p[7];
+  o.uf_r1 = p[8]; o.uf_r2 = p[9]; o.uf_t1 = p[10]; o.uf_t2 = p[11];
   return o;
 }
 
 extern "C" int dsw_split_step_forced(dsw_grid *G, const dsw_fields *Un, dsw_fields *Unp1, double tau,
-                                     int32_t K, const dsw_fields *src, const dsw_wall *wall,
-                                     const dsw_fields *bnd, void *stream) {
+                                     int32_t K, const dsw_fields *src, const dsw_wall *wall0,
+                                     const dsw_wall *wall1, const dsw_fields *bnd, void *stream) {
   if (!G) return fail(DSW_EINVAL, "null handle");
   int rc = check_step_args(Un, Unp1, tau, K);
   if (rc) return rc;
@@ -610,30 +628,41 @@ extern "C" int dsw_split_step_forced(dsw_grid *G, const dsw_fields *Un, dsw_fiel
     return fail(DSW_EINVAL, "forced step: too many r or theta lines");
   hipStream_t st = (hipStream_t)stream;
   const Fields un = F(Un), uk = F(Unp1), none{};
-  const Wall w = to_wall(wall);
-  // U^{n+1,0} in Unp1: U^n with the new Dirichlet data on its
-  // boundary-normal faces.  Every phi sweep updates it in place: the sweep
-  // also rewrites the last phi face of a sector line as base + 0, which must
-  // then hold the new data, not U^n's.  Midpoint of the first iteration in
-  // ub2: U^n with the mean Dirichlet data; ub's boundary faces alike.
-  const double *unf[5] = {un.p, un.ur, un.ut, un.uf, un.T};
-  double *u0[5] = {G->ub2.p, G->ub2.ur, G->ub2.ut, G->ub2.uf, G->ub2.T};
-  double *u1[5] = {uk.p, uk.ur, uk.ut, uk.uf, uk.T};
-  for (int q = 0; q < 5; q++) {
-    HIPCHK(hipMemcpyAsync(u0[q], unf[q], sizeof(double) * (size_t)G->count[q], hipMemcpyDeviceToDevice, st));
-    HIPCHK(hipMemcpyAsync(u1[q], unf[q], sizeof(double) * (size_t)G->count[q], hipMemcpyDeviceToDevice, st));
+  // wall data: w0 at t^n (the first iteration's), the mean of w0 and w1 (the
+  // later iterations'), and their change (the first iteration's lifted data)
+  long len[12], off[13];
+  wall_lens(g, len);
+  off[0] = 0;
+  for (int q = 0; q < 12; q++) off[q + 1] = off[q] + len[q];
+  if (!G->fwall_mem && hipMalloc(&G->fwall_mem, 2 * off[12] * sizeof(double)) != hipSuccess)
+    return fail(DSW_ENOMEM, "forced step: wall workspace");
+  WallMix wm;
+  for (int q = 0; q < 12; q++) {
+    wm.a[q] = wall_ptr(wall0, q);
+    wm.b[q] = wall_ptr(wall1, q);
+    wm.mid[q] = G->fwall_mem + off[q];
+    wm.dw[q] = G->fwall_mem + off[12] + off[q];
   }
+  for (int q = 0; q < 13; q++) wm.off[q] = off[q];
+  launch_wall_mix(wm, st);
+  Wall w0{};
   {
-    PassArgs a = base_args(G);
-    a.src = un;
-    a.rhs = bnd ? F(bnd) : none;
-    a.d0 = uk; a.d1 = G->ub; a.d2 = G->ub2;
-    launch_bnd_forced(a, cdiv(bnd_points(g), 128), 128, st);
+    double *p0[12];
+    for (int q = 0; q < 12; q++) p0[q] = const_cast<double *>(wall_ptr(wall0, q));
+    w0 = wall_of(p0);
   }
+  const Wall wmid = wall_of(wm.mid), dw = wall_of(wm.dw);
+  // U^{n+1,0} = U^n in Unp1, boundary faces included
+  const double *unf[5] = {un.p, un.ur, un.ut, un.uf, un.T};
+  double *u1[5] = {uk.p, uk.ur, uk.ut, uk.uf, uk.T};
+  for (int q = 0; q < 5; q++)
+    HIPCHK(hipMemcpyAsync(u1[q], unf[q], sizeof(double) * (size_t)G->count[q], hipMemcpyDeviceToDevice, st));
   const Fields ubuf[2] = {G->ub, G->ub2};
   const unsigned rbs = (unsigned)G->cfg.res_bs;
   for (int it = 0; it < K; it++) {
-    const Fields ubar = it == 0 ? G->ub2 : ubuf[(it - 1) % 2];
+    // the first iteration's midpoint is U^n itself (old data, wall w0)
+    const Fields ubar = it == 0 ? un : ubuf[(it - 1) % 2];
+    const Wall w = it == 0 ? w0 : wmid;
     PassArgs r = base_args(G);
     r.u = src1(ubar);
     r.d = diff(un, it == 0 ? un : uk);
@@ -648,15 +677,32 @@ extern "C" int dsw_split_step_forced(dsw_grid *G, const dsw_fields *Un, dsw_fiel
     o3.x = uk; o3.base = uk; o3.un = un;
     o3.ub = it < K - 1 ? ubuf[it % 2] : none;
     o3.mode = 1;
-    for (int d = 0; d < 2; d++) {
-      Pass p = sweep_pass(G, d, ubar, tau, d == 0 ? G->r : G->x1, d == 0 ? o1 : o2);
+    const Fields rhs_of[3] = {G->r, G->x1, G->x2};
+    for (int d = 0; d < 3; d++) {
+      Pass p = sweep_pass(G, d, ubar, tau, rhs_of[d], d == 0 ? o1 : (d == 1 ? o2 : o3));
       p.a.wall = w;
-      const unsigned bs = (unsigned)G->cfg.sweep_bs[d];
-      launch_sweep2_forced(d, p.a, sweep2_blocks(g, d, bs), bs, st);
+      if (it == 0) {  // the change of the boundary data, lifted out of the increment
+        PassArgs l = p.a;
+        l.src = un;
+        l.d0 = bnd ? F(bnd) : none;
+        launch_lift(d, l, dw, st);
+      }
+      if (d < 2) {
+        const unsigned bs = (unsigned)G->cfg.sweep_bs[d];
+        launch_sweep2_forced(d, p.a, sweep2_blocks(g, d, bs), bs, st);
+      } else {
+        launch_phi_forced(pm, p.a, (unsigned)g.nr * (unsigned)g.nt, phi_part_threads(g, pm), phi_part_lds(g, pm), st);
+      }
     }
-    Pass p = sweep_pass(G, 2, ubar, tau, G->x2, o3);
-    p.a.wall = w;
-    launch_phi_forced(pm, p.a, (unsigned)g.nr * (unsigned)g.nt, phi_part_threads(g, pm), phi_part_lds(g, pm), st);
+    if (it == 0) {
+      // from here on U^{n+1,k} holds the new Dirichlet data and the midpoint
+      // buffers their mean with U^n's
+      PassArgs a = base_args(G);
+      a.src = un;
+      a.rhs = bnd ? F(bnd) : none;
+      a.d0 = uk; a.d1 = G->ub; a.d2 = G->ub2;
+      launch_bnd_forced(a, cdiv(bnd_points(g), 128), 128, st);
+    }
   }
   return check_launch("forced split step kernels");
 }

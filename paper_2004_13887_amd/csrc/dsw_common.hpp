@@ -27,6 +27,7 @@ struct Geo {
   const double *irc, *irf; // 1/rc, 1/rf
   const double *isc, *ctc; // 1/sin, cot at centres
   const double *isf, *ctf; // 1/sin, cot at faces (0 at a pole face: never used there)
+  const double *scx;       // sin of theta at centres j = -1 .. nt (ghosts included), at scx[j + 1]
 };
 
 struct Mat {

@@ -129,6 +129,17 @@ enum PassKind { PK_BND = 0, PK_RES = 1, PK_SW0 = 2, PK_SW1 = 3, PK_SW2_LINE = 4,
 void launch_bnd_forced(const PassArgs &a, unsigned blocks, unsigned threads, hipStream_t st);
 void launch_residual_forced(const PassArgs &a, unsigned blocks, unsigned threads, hipStream_t st);
 void launch_sweep2_forced(int d, const PassArgs &a, unsigned blocks, unsigned threads, hipStream_t st);
+// first iteration of a forced step: rhs -= tau/2 D_d(Ubar) X_b for the change
+// X_b of the boundary data (a.d0 - a.src on the boundary-normal faces, dw on
+// the walls), in place on a.rhs
+void launch_lift(int d, const PassArgs &a, const Wall &dw, hipStream_t st);
+// mean and change of two sets of the twelve wall arrays
+struct WallMix {
+  const double *a[12], *b[12];
+  double *mid[12], *dw[12];
+  long off[13];  // prefix sums of the array lengths
+};
+void launch_wall_mix(const WallMix &w, hipStream_t st);
 void launch_phi_forced(int pm, const PassArgs &a, unsigned blocks, unsigned threads, size_t lds,
                        hipStream_t st);
 

@@ -3,8 +3,20 @@
 // F_h(V) = (D + D_M)(V) V + G is the full discrete operator of the
 // non-conservative system (nonconservmass)-(nonconservener) in spherical
 // components (Appendix B): advection with curvature terms, pressure gradient,
-// compressibility terms, vector Laplacian + grad-div viscosity, viscous
-// heating, heat conduction, Coriolis and gravity.
+// compressibility terms, viscosity, viscous heating, heat conduction,
+// Coriolis and gravity.
+//
+// Viscosity: -(mu/rho) (Lap u + grad div u / 3) = -(mu/rho) V with
+// V = (4/3) grad(div u) - curl(curl u) on the MAC complex: the divergence at
+// cell centres, the vorticity at cell edges (circulation round the dual face
+// over its area), its curl at a face (circulation round the face over the
+// face area).  Then div(curl) vanishes identically and a discretely
+// solenoidal velocity field keeps a solenoidal viscous update.  A radial
+// circulation r_a u_a - r_b u_b over centres r_a = r_f + dr/2, r_b = r_f - dr/2
+// is formed as r_f (u_a - u_b) + dr (u_a + u_b) / 2 (the same value, without
+// the cancellation of two products of size r).  The phi rows next to a pole
+// keep the component form (the edge vorticity on the polar axis is one value
+// for the whole ring).
 //
 // One thread per point of the extended index space (nr+1) x (nt+1) x npf; a
 // thread owns the centre (i,j,k) and the three faces with the same indices.
@@ -46,7 +58,7 @@ __device__ __forceinline__ double F_p_T(const Geo &g, const Mat &m, const S &s, 
 
 template <class S>
 __device__ __forceinline__ double F_ur(const Geo &g, const Mat &m, const S &s, int f, int j, int k) {
-  const double irF = g.irf[f], is = g.isc[j], irF2 = irF * irF;
+  const double irF = g.irf[f], is = g.isc[j];
   const double irho = 1.0 / (0.5 * (rho_at(g, m, s, f - 1, j, k) + rho_at(g, m, s, f, j, k)));
   const double nu = m.mu * irho;
   const double un = gR(g, s, f, j, k);
@@ -60,24 +72,26 @@ __device__ __forceinline__ double F_ur(const Geo &g, const Mat &m, const S &s, i
   double N = (gC(g, s, F_P, f, j, k) - gC(g, s, F_P, f - 1, j, k)) * (irho * g.idr);
   N += un * (xp - xm) * (0.5 * g.idr) + ua * (yp - ym) * (0.5 * irF * g.idt) +
        ub * (zp - zm) * (0.5 * irF * is * g.idp) - (ua * ua + ub * ub) * irF;
-  double vis = (g.rc[f] * g.rc[f] * (xp - un) - g.rc[f - 1] * g.rc[f - 1] * (un - xm)) * (irF2 * g.idr * g.idr) +
-               (g.sf[j + 1] * (yp - un) - g.sf[j] * (un - ym)) * (irF2 * is * g.idt * g.idt) +
-               (zp - 2.0 * un + zm) * (irF2 * is * is * g.idp * g.idp);
-  const double dth = 0.5 *
-                     ((g.sf[j + 1] * gT(g, s, f - 1, j + 1, k) - g.sf[j] * gT(g, s, f - 1, j, k)) +
-                      (g.sf[j + 1] * gT(g, s, f, j + 1, k) - g.sf[j] * gT(g, s, f, j, k))) * g.idt;
-  const double dph = 0.5 *
-                     ((gF(g, s, f - 1, j, k + 1) - gF(g, s, f - 1, j, k)) +
-                      (gF(g, s, f, j, k + 1) - gF(g, s, f, j, k))) * g.idp;
-  vis += -2.0 * un * irF2 - 2.0 * irF2 * is * dth - 2.0 * irF2 * is * dph;
   const double gd = (divc(g, s, f, j, k) - divc(g, s, f - 1, j, k)) * g.idr;
+  // vorticity: omega_phi at the edges (f, j) and (f, j + 1), omega_theta at
+  // the edges (f, k) and (f, k + 1); C = (curl omega)_r
+  const double T00 = gT(g, s, f - 1, j, k), T01 = gT(g, s, f - 1, j + 1, k);
+  const double T10 = gT(g, s, f, j, k), T11 = gT(g, s, f, j + 1, k);
+  const double F00 = gF(g, s, f - 1, j, k), F01 = gF(g, s, f - 1, j, k + 1);
+  const double F10 = gF(g, s, f, j, k), F11 = gF(g, s, f, j, k + 1);
+  const double wp0 = (T10 - T00) * g.idr + 0.5 * (T10 + T00) * irF - (un - ym) * (irF * g.idt);
+  const double wp1 = (T11 - T01) * g.idr + 0.5 * (T11 + T01) * irF - (yp - un) * (irF * g.idt);
+  const double wt0 = (un - zm) * (irF * is * g.idp) - (F10 - F00) * g.idr - 0.5 * (F10 + F00) * irF;
+  const double wt1 = (zp - un) * (irF * is * g.idp) - (F11 - F01) * g.idr - 0.5 * (F11 + F01) * irF;
+  const double C = ((g.sf[j + 1] * wp1 - g.sf[j] * wp0) * g.idt - (wt1 - wt0) * g.idp) * (irF * is);
+  const double vis = gd - C;  // nu (vis + gd / 3) = nu ((4/3) gd - C)
   N += -2.0 * m.omega * g.sc[j] * ub;
   return N - nu * vis - nu / 3.0 * gd + m.g_r;
 }
 
 template <class S>
 __device__ __forceinline__ double F_ut(const Geo &g, const Mat &m, const S &s, int i, int f, int k) {
-  const double ir = g.irc[i], isF = g.isf[f], ctF = g.ctf[f], ir2 = ir * ir;
+  const double ir = g.irc[i], isF = g.isf[f], ctF = g.ctf[f];
   const int j0 = f - 1, j1 = f;
   const double irho = 1.0 / (0.5 * (rho_at(g, m, s, i, j0, k) + rho_at(g, m, s, i, j1, k)));
   const double nu = m.mu * irho;
@@ -92,13 +106,20 @@ __device__ __forceinline__ double F_ut(const Geo &g, const Mat &m, const S &s, i
   double N = (gC(g, s, F_P, i, j1, k) - gC(g, s, F_P, i, j0, k)) * (irho * ir * g.idt);
   N += ua * (xp - xm) * (0.5 * g.idr) + un * (yp - ym) * (0.5 * ir * g.idt) +
        ub * (zp - zm) * (0.5 * ir * isF * g.idp) + (un * ua - ub * ub * ctF) * ir;
-  double vis = (g.rf[i + 1] * g.rf[i + 1] * (xp - un) - g.rf[i] * g.rf[i] * (un - xm)) * (ir2 * g.idr * g.idr) +
-               (g.sc[j1] * (yp - un) - g.sc[j0] * (un - ym)) * (ir2 * isF * g.idt * g.idt) +
-               (zp - 2.0 * un + zm) * (ir2 * isF * isF * g.idp * g.idp);
-  const double dthr = 0.5 * ((gR(g, s, i, j1, k) - gR(g, s, i, j0, k)) + (gR(g, s, i + 1, j1, k) - gR(g, s, i + 1, j0, k))) * g.idt;
-  const double dphf = 0.5 * ((gF(g, s, i, j0, k + 1) - gF(g, s, i, j0, k)) + (gF(g, s, i, j1, k + 1) - gF(g, s, i, j1, k))) * g.idp;
-  vis += -un * ir2 * isF * isF + 2.0 * ir2 * dthr - 2.0 * ctF * ir2 * isF * dphf;
   const double gd = (divc(g, s, i, j1, k) - divc(g, s, i, j0, k)) * (ir * g.idt);
+  // vorticity: omega_r at the edges (f, k) and (f, k + 1), omega_phi at the
+  // edges (i, f) and (i + 1, f); C = (curl omega)_theta
+  const double R00 = gR(g, s, i, j0, k), R01 = gR(g, s, i, j1, k);
+  const double R10 = gR(g, s, i + 1, j0, k), R11 = gR(g, s, i + 1, j1, k);
+  const double F00 = gF(g, s, i, j0, k), F01 = gF(g, s, i, j0, k + 1);
+  const double F10 = gF(g, s, i, j1, k), F11 = gF(g, s, i, j1, k + 1);
+  const double wr0 = ((g.sc[j1] * F10 - g.sc[j0] * F00) * g.idt - (un - zm) * g.idp) * (ir * isF);
+  const double wr1 = ((g.sc[j1] * F11 - g.sc[j0] * F01) * g.idt - (zp - un) * g.idp) * (ir * isF);
+  const double ira = g.irf[i], irb = g.irf[i + 1];
+  const double wp0 = (un - xm) * g.idr + 0.5 * (un + xm) * ira - (R01 - R00) * (ira * g.idt);
+  const double wp1 = (xp - un) * g.idr + 0.5 * (xp + un) * irb - (R11 - R10) * (irb * g.idt);
+  const double C = (wr1 - wr0) * (ir * isF * g.idp) - (g.rf[i + 1] * wp1 - g.rf[i] * wp0) * (ir * g.idr);
+  const double vis = gd - C;
   N += -2.0 * m.omega * g.cf[f] * ub;
   return N - nu * vis - nu / 3.0 * gd;
 }
@@ -120,13 +141,31 @@ __device__ __forceinline__ double F_uf(const Geo &g, const Mat &m, const S &s, i
   double N = (gC(g, s, F_P, i, j, k1) - gC(g, s, F_P, i, j, k0)) * (irho * ir * is * g.idp);
   N += ua * (xp - xm) * (0.5 * g.idr) + ub * (yp - ym) * (0.5 * ir * g.idt) +
        un * (zp - zm) * (0.5 * ir * is * g.idp) + un * (ua + ub * ct) * ir;
-  double vis = (g.rf[i + 1] * g.rf[i + 1] * (xp - un) - g.rf[i] * g.rf[i] * (un - xm)) * (ir2 * g.idr * g.idr) +
-               (g.sf[j + 1] * (yp - un) - g.sf[j] * (un - ym)) * (ir2 * is * g.idt * g.idt) +
-               (zp - 2.0 * un + zm) * (ir2 * is * is * g.idp * g.idp);
-  const double dphr = 0.5 * ((gR(g, s, i, j, k1) - gR(g, s, i, j, k0)) + (gR(g, s, i + 1, j, k1) - gR(g, s, i + 1, j, k0))) * g.idp;
-  const double dpht = 0.5 * ((gT(g, s, i, j, k1) - gT(g, s, i, j, k0)) + (gT(g, s, i, j + 1, k1) - gT(g, s, i, j + 1, k0))) * g.idp;
-  vis += -un * ir2 * is * is + 2.0 * ir2 * is * dphr + 2.0 * ct * ir2 * is * dpht;
   const double gd = (divc(g, s, i, j, k1) - divc(g, s, i, j, k0)) * (ir * is * g.idp);
+  const double R00 = gR(g, s, i, j, k0), R01 = gR(g, s, i, j, k1);
+  const double R10 = gR(g, s, i + 1, j, k0), R11 = gR(g, s, i + 1, j, k1);
+  const double T00 = gT(g, s, i, j, k0), T01 = gT(g, s, i, j, k1);
+  const double T10 = gT(g, s, i, j + 1, k0), T11 = gT(g, s, i, j + 1, k1);
+  double vis;
+  if (!S::INTERIOR && ((j == 0 && g.pole_lo) || (j == g.nt - 1 && g.pole_hi))) {
+    // next to a pole: component form, scalar Laplacians and curvature terms
+    vis = (g.rf[i + 1] * g.rf[i + 1] * (xp - un) - g.rf[i] * g.rf[i] * (un - xm)) * (ir2 * g.idr * g.idr) +
+          (g.sf[j + 1] * (yp - un) - g.sf[j] * (un - ym)) * (ir2 * is * g.idt * g.idt) +
+          (zp - 2.0 * un + zm) * (ir2 * is * is * g.idp * g.idp);
+    const double dphr = 0.5 * ((R01 - R00) + (R11 - R10)) * g.idp;
+    const double dpht = 0.5 * ((T01 - T00) + (T11 - T10)) * g.idp;
+    vis += -un * ir2 * is * is + 2.0 * ir2 * is * dphr + 2.0 * ct * ir2 * is * dpht;
+  } else {
+    // vorticity: omega_theta at the edges (i, f) and (i + 1, f), omega_r at
+    // the edges (j, f) and (j + 1, f); C = (curl omega)_phi
+    const double ira = g.irf[i], irb = g.irf[i + 1];
+    const double wt0 = (R01 - R00) * (ira * is * g.idp) - (un - xm) * g.idr - 0.5 * (un + xm) * ira;
+    const double wt1 = (R11 - R10) * (irb * is * g.idp) - (xp - un) * g.idr - 0.5 * (xp + un) * irb;
+    const double wr0 = ((g.scx[j + 1] * un - g.scx[j] * ym) * g.idt - (T01 - T00) * g.idp) * (ir * g.isf[j]);
+    const double wr1 = ((g.scx[j + 2] * yp - g.scx[j + 1] * un) * g.idt - (T11 - T10) * g.idp) * (ir * g.isf[j + 1]);
+    const double C = (g.rf[i + 1] * wt1 - g.rf[i] * wt0) * (ir * g.idr) - (wr1 - wr0) * (ir * g.idt);
+    vis = gd - C;
+  }
   N += 2.0 * m.omega * (g.cc[j] * ub + g.sc[j] * ua);
   return N - nu * vis - nu / 3.0 * gd;
 }

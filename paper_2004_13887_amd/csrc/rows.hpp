@@ -13,6 +13,16 @@ struct BRow {
   double L[9], D[9], U[9], b[3];
 };
 
+// The coupling of a line's end rows to values beyond its ends, scaled by
+// tau/2, as the line assembly drops or folds it for homogeneous increment
+// data: lo[0..2] the p, T and w rows of block 0 on the boundary face before
+// it; hi[0..1] the p and T rows of block n-1 on the boundary face that closes
+// the line, hiw the w row of block n-2 on that face; slo, shi the scalar rows
+// 0 and n-1 on their ghost values.  Filled only where a row asks for it.
+struct Edge {
+  double lo[3], hi[2], hiw, slo, shi;
+};
+
 __device__ __forceinline__ void inv3(const double *A, double *X, int *status) {
   const double c00 = A[4] * A[8] - A[5] * A[7];
   const double c01 = A[5] * A[6] - A[3] * A[8];
@@ -67,7 +77,7 @@ __host__ __device__ inline Families families(const Geo &g, int d) {
 // Unknown order within a block: p, T, w.
 template <int D, class S>
 __device__ __forceinline__ void block_row(const Geo &g, const Mat &m, const S &u, const Fields &rhs, int a,
-                          int b, int s, int n, int cyc, double hs, BRow &R) {
+                          int b, int s, int n, int cyc, double hs, BRow &R, Edge *e = nullptr) {
   int i, j, k;
   if (D == 0) { i = s; j = a; k = b; }
   else if (D == 1) { i = a; j = s; k = b; }
@@ -162,9 +172,12 @@ __device__ __forceinline__ void block_row(const Geo &g, const Mat &m, const S &u
     }
     R.D[6] = -gp; R.U[6] = gp;
     R.L[8] = cm; R.D[8] = c0; R.U[8] = cp;
+    if (e && !cyc && s == n - 2) e->hiw = hs * cp;
     if (!cyc && s == n - 2) R.U[8] = 0.0; // w_{s+1} is the boundary face
   }
+  if (e && !w_unknown) { e->hi[0] = hs * R.D[2]; e->hi[1] = hs * R.D[5]; }
   if (!w_unknown) { R.D[2] = 0.0; R.D[5] = 0.0; } // w_{n-1} is the boundary face
+  if (e && first) { e->lo[0] = hs * R.L[2]; e->lo[1] = hs * R.L[5]; e->lo[2] = hs * R.L[8]; }
   if (first) { // no row before the first one: the L block couples to nothing
 #pragma unroll
     for (int q = 0; q < 9; q++) R.L[q] = 0.0;
@@ -199,7 +212,7 @@ struct SRow {
 template <int D, int FAM, class S>
 __device__ __forceinline__ void scalar_row(const Geo &g, const Mat &m, const S &u, const Fields &rhs, int a,
                            int b, int s, int n, int cyc, double hs, SRow &R, long &xi,
-                           double *&arr) {
+                           double *&arr, Edge *e = nullptr) {
   double ca, cb, cc_, sglo = -1.0, sghi = -1.0;
   if (D == 0) {
     const int i = s;
@@ -275,6 +288,8 @@ __device__ __forceinline__ void scalar_row(const Geo &g, const Mat &m, const S &
     cb = 2.0 * nu * q;
     cc_ = ua * (0.5 * irr * iss * g.idp) - nu * q;
   }
+  if (e && !cyc && s == 0) e->slo = hs * ca;
+  if (e && !cyc && s == n - 1) e->shi = hs * cc_;
   if (!cyc && s == 0) { cb += sglo * ca; ca = 0.0; }
   if (!cyc && s == n - 1) { cb += sghi * cc_; cc_ = 0.0; }
   R.a = hs * ca;

@@ -1071,6 +1071,129 @@ __device__ __forceinline__ void bnd_body(const PassArgs &a, unsigned w) {
   if (a.d2.p) fsel(a.d2, fid)[idx] = v;
 }
 
+
+// ------------------------------------------------ lifted boundary data --
+
+// The first iteration of a forced step starts from U^n, old boundary data
+// included; the change of the data to the new time level enters the
+// increment solve of direction D as inhomogeneous Dirichlet data on the walls
+// normal to D.  With X = X_0 + X_b (X_b zero but on those walls), X_0 solves
+// the homogeneous line systems with the right-hand side rhs - tau/2 D_D X_b.
+// This kernel subtracts that term in place (a.rhs) on the rows that see X_b:
+// the end blocks of each block line, through the boundary faces of the
+// normal velocity (X_b = a.d0 - a.src there: the new data less U^n's), and
+// the end rows of each scalar line that ends on a wall, through the ghost
+// value 2 dw - x of the tangential velocity (dw: the change of the wall
+// velocity).  Rows next to a pole see no data.  One thread per line; the
+// coefficients come from Ubar (a.u, wall data a.wall) as in the sweeps.
+template <int D, int FAM>
+__device__ __forceinline__ void lift_scalar(const PassArgs &a, const SrcW &u, const Wall &dw, int p, int q,
+                                            int n, double hs) {
+  const Geo &g = a.g;
+  double dlo = 0.0, dhi = 0.0;
+  if (D == 0 && FAM == 0) { dlo = wallv(dw.ut_r1, (long)p * g.np + q); dhi = wallv(dw.ut_r2, (long)p * g.np + q); }
+  if (D == 0 && FAM == 1) { dlo = wallv(dw.uf_r1, (long)p * g.npf + q); dhi = wallv(dw.uf_r2, (long)p * g.npf + q); }
+  if (D == 1 && FAM == 0) {
+    if (!g.pole_lo) dlo = wallv(dw.ur_t1, (long)p * g.np + q);
+    if (!g.pole_hi) dhi = wallv(dw.ur_t2, (long)p * g.np + q);
+  }
+  if (D == 1 && FAM == 1) {
+    if (!g.pole_lo) dlo = wallv(dw.uf_t1, (long)p * g.npf + q);
+    if (!g.pole_hi) dhi = wallv(dw.uf_t2, (long)p * g.npf + q);
+  }
+  if (D == 2 && FAM == 0) { dlo = wallv(dw.ur_p1, (long)p * g.nt + q); dhi = wallv(dw.ur_p2, (long)p * g.nt + q); }
+  if (D == 2 && FAM == 1) { dlo = wallv(dw.ut_p1, (long)p * (g.nt + 1) + q); dhi = wallv(dw.ut_p2, (long)p * (g.nt + 1) + q); }
+  SRow R;
+  long xi;
+  double *arr;
+  Edge e;
+  if (dlo != 0.0) {
+    scalar_row<D, FAM>(g, a.m, u, a.rhs, p, q, 0, n, 0, hs, R, xi, arr, &e);
+    arr[xi] -= 2.0 * e.slo * dlo;
+  }
+  if (dhi != 0.0) {
+    scalar_row<D, FAM>(g, a.m, u, a.rhs, p, q, n - 1, n, 0, hs, R, xi, arr, &e);
+    arr[xi] -= 2.0 * e.shi * dhi;
+  }
+}
+
+template <int D>
+__global__ void __launch_bounds__(256) k_lift(PassArgs a, Wall dw) {
+  const Geo &g = a.g;
+  const Families F = families(g, D);
+  if (F.cyclic) return;  // no walls normal to a periodic direction
+  const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const int nkf = g.periodic ? g.np : g.np - 1, kf0 = g.periodic ? 0 : 1;
+  const double hs = a.tau;
+  const SrcW u = SrcSel<true>::get(a);
+  const int n = F.n;
+  if (t < F.nb) {
+    if (!a.d0.ur) return;  // the normal data keep U^n's
+    int p, q;
+    if (D == 2) { p = (int)(t / g.nt); q = (int)(t % g.nt); }
+    else { p = (int)(t / g.np); q = (int)(t % g.np); }
+    auto cell = [&](int s) { return D == 0 ? idx_c(g, s, p, q) : (D == 1 ? idx_c(g, p, s, q) : idx_c(g, p, q, s)); };
+    auto face = [&](int f) { return D == 0 ? idx_r(g, f, p, q) : (D == 1 ? idx_t(g, p, f, q) : idx_f(g, p, q, f)); };
+    const int wf = D == 0 ? F_UR : (D == 1 ? F_UT : F_UF);
+    const double *nw = fsel(a.d0, wf), *od = fsel(a.src, wf);
+    double *rw = fsel(a.rhs, wf);
+    const double dlo = nw[face(0)] - od[face(0)], dhi = nw[face(n)] - od[face(n)];
+    BRow R;
+    Edge e;
+    if (dlo != 0.0) {
+      block_row<D>(g, a.m, u, a.rhs, p, q, 0, n, 0, hs, R, &e);
+      a.rhs.p[cell(0)] -= e.lo[0] * dlo;
+      a.rhs.T[cell(0)] -= e.lo[1] * dlo;
+      rw[face(1)] -= e.lo[2] * dlo;
+    }
+    if (dhi != 0.0) {
+      block_row<D>(g, a.m, u, a.rhs, p, q, n - 1, n, 0, hs, R, &e);
+      a.rhs.p[cell(n - 1)] -= e.hi[0] * dhi;
+      a.rhs.T[cell(n - 1)] -= e.hi[1] * dhi;
+      block_row<D>(g, a.m, u, a.rhs, p, q, n - 2, n, 0, hs, R, &e);
+      rw[face(n - 1)] -= e.hiw * dhi;
+    }
+    return;
+  }
+  long t2 = t - F.nb;
+  if (t2 < F.na) {
+    const int p = 1 + (int)(t2 / (D == 2 ? g.nt : g.np)), q = (int)(t2 % (D == 2 ? g.nt : g.np));
+    lift_scalar<D, 0>(a, u, dw, p, q, n, hs);
+    return;
+  }
+  t2 -= F.na;
+  if (t2 < F.nbb) {
+    int p, q;
+    if (D == 2) { p = (int)(t2 / (g.nt - 1)); q = 1 + (int)(t2 % (g.nt - 1)); }
+    else { p = (int)(t2 / nkf); q = kf0 + (int)(t2 % nkf); }
+    lift_scalar<D, 1>(a, u, dw, p, q, n, hs);
+  }
+}
+
+void launch_lift(int d, const PassArgs &a, const Wall &dw, hipStream_t st) {
+  const unsigned lines = sweep_lines(a.g, d);
+  const dim3 gr((lines + 255) / 256), bl(256);
+  if (d == 0) hipLaunchKernelGGL(k_lift<0>, gr, bl, 0, st, a, dw);
+  else if (d == 1) hipLaunchKernelGGL(k_lift<1>, gr, bl, 0, st, a, dw);
+  else hipLaunchKernelGGL(k_lift<2>, gr, bl, 0, st, a, dw);
+}
+
+// the mean and the change of two sets of wall velocities (a null array is zero)
+__global__ void __launch_bounds__(256) k_wall_mix(WallMix w) {
+  const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= w.off[12]) return;
+  int q = 0;
+  while (t >= w.off[q + 1]) q++;
+  const long e = t - w.off[q];
+  const double x = w.a[q] ? w.a[q][e] : 0.0, y = w.b[q] ? w.b[q][e] : 0.0;
+  w.mid[q][e] = 0.5 * (x + y);
+  w.dw[q][e] = y - x;
+}
+
+void launch_wall_mix(const WallMix &w, hipStream_t st) {
+  if (w.off[12] > 0) hipLaunchKernelGGL(k_wall_mix, dim3((unsigned)((w.off[12] + 255) / 256)), dim3(256), 0, st, w);
+}
+
 __global__ void __launch_bounds__(256) k_bnd_forced(PassArgs a) { bnd_body<true>(a, blockIdx.x); }
 
 void launch_bnd_forced(const PassArgs &a, unsigned blocks, unsigned threads, hipStream_t st) {

@@ -122,7 +122,7 @@ def lib():
         for n in ("dsw_line_vjp_r", "dsw_line_vjp_theta", "dsw_line_vjp_phi"):
             getattr(L, n).argtypes = [P, FP, D, FP, FP, FP, P]
         L.dsw_residual_vjp.argtypes = [P, FP, D, FP, FP, P]
-        L.dsw_split_step_forced.argtypes = [P, FP, FP, D, I, FP, C.POINTER(Wall), FP, P]
+        L.dsw_split_step_forced.argtypes = [P, FP, FP, D, I, FP, C.POINTER(Wall), C.POINTER(Wall), FP, P]
         L.dsw_tape_bytes.argtypes = [P, I, C.POINTER(C.c_int64)]
         L.dsw_split_step_taped.argtypes = [P, FP, FP, D, I, P, P]
         L.dsw_adjoint_step_taped.argtypes = [P, FP, D, I, P, FP, FP, P]
@@ -267,19 +267,23 @@ class Grid:
                                             C.c_void_p(tape.data_ptr()), C.byref(_fields(lam_np1)),
                                             C.byref(_fields(lam_n)), _stream(stream)))
 
-    def split_step_forced(self, Un, Unp1, tau, K, src=None, wall=None, bnd=None, stream=None):
+    def split_step_forced(self, Un, Unp1, tau, K, src=None, wall0=None, wall1=None, bnd=None,
+                          stream=None):
         """dsw_split_step_forced: src (dict of five device arrays, a missing
-        one is zero), wall (dict of the WALLS arrays, a missing one is zero),
-        bnd (dict whose ur, ut, uf boundary-normal faces hold the new
-        Dirichlet data)."""
-        w = Wall()
-        if wall is not None:
+        one is zero), wall0 / wall1 (dicts of the WALLS arrays at t^n and
+        t^{n+1}, a missing one is zero), bnd (dict whose ur, ut, uf
+        boundary-normal faces hold the Dirichlet data of t^{n+1})."""
+        def wall_struct(wall):
+            w = Wall()
             for n in WALLS:
                 t = wall.get(n)
                 if t is not None:
                     if not (t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
                         raise ValueError(f"wall {n}: need a contiguous float64 device tensor")
                     setattr(w, n, t.data_ptr())
+            return w
+        w0 = wall_struct(wall0) if wall0 is not None else None
+        w1 = wall_struct(wall1) if wall1 is not None else None
         fs = None
         if src is not None:
             fs = Fields()
@@ -299,7 +303,8 @@ class Grid:
                 setattr(fb, n, t.data_ptr())
         _check(lib().dsw_split_step_forced(
             self._h, C.byref(_fields(Un)), C.byref(_fields(Unp1)), float(tau), int(K),
-            C.byref(fs) if fs is not None else None, C.byref(w) if wall is not None else None,
+            C.byref(fs) if fs is not None else None, C.byref(w0) if w0 is not None else None,
+            C.byref(w1) if w1 is not None else None,
             C.byref(fb) if fb is not None else None, _stream(stream)))
 
     def set_timing(self, enable=True):

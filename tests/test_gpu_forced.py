@@ -6,16 +6,14 @@ eq. (man_sol)):
 * parity with the oracle, element by element, on random forcing over a
   sector (theta and phi walls, their corners) and a full sphere (r walls,
   poles, periodic phi), and on manufactured-solution steps;
-* second-order convergence in space (the figure "conv": tau = 1e-5 up to
-  t = 1e-3, M0 = 1e-2 and 1e-4; at 1e-4 the pressure converges at second
-  order in the central region, near-wall errors dominate the whole box on
-  these grids);
+* second-order convergence in space over the whole box (the figure "conv":
+  tau = 1e-5 up to t = 1e-3, M0 = 1e-2, 1e-4 and 1e-6, where the pressure
+  meets round-off as the paper notes);
 * the time convergence rate by inverse Richardson extrapolation (Tables 1
   and 2: tau = 2e-3, 1e-3, 5e-4, M0 = 1e-2 and 1e-4);
 * the incompressible limit (Table 3: tau = 1e-3, grid diameter 0.12,
-  max (p - p0)/p0 after 1, 50, 100 steps against the closed form
-  (2 + sin 5t) gamma M0^2 and the printed values, over the cells off the
-  theta and phi walls).
+  max (p - p0)/p0 over all cells after 1, 50, 100 steps against the closed
+  form (2 + sin 5t) gamma M0^2 and the printed values, M0 = 1e-2 ... 1e-6).
 
 The manufactured sources come from tests/mms.py (automatic differentiation of
 the continuous equations, CPU); the GPU and the oracle receive the same
@@ -61,7 +59,7 @@ def _forcing(spec, U, seed):
     src = {k: scale[k] * rng.uniform(-1.0, 1.0, U[k].shape) for k in KEYS}
     bnd = {k: U[k] + rng.uniform(-2.0, 2.0, U[k].shape) for k in ("ur", "ut", "uf")}
     bnd["p"], bnd["T"] = U["p"], U["T"]  # not read
-    return src, random_wall(spec, seed + 1, scale=3.0), bnd
+    return src, random_wall(spec, seed + 1, scale=3.0), random_wall(spec, seed + 2, scale=3.0), bnd
 
 
 CASES = {
@@ -77,12 +75,12 @@ def test_forced_step_parity_random(name, dsw):
     print(f"[forced random] {name} {spec.nr}x{spec.nt}x{spec.np}", flush=True)
     gg, og, om = _grid(dsw, spec, I.AIR)
     U0, tau = random_state(spec, 301, mach=0.05)
-    src, wall, bnd = _forcing(spec, U0, 302)
+    src, w0, w1, bnd = _forcing(spec, U0, 302)
     K = 3
-    ref = oracle.split_step(og, om, U0, tau, K, wall=wall, src=src, bnd=bnd)
+    ref = oracle.split_step(og, om, U0, tau, K, wall0=w0, wall1=w1, src=src, bnd=bnd)
     out = gg.empty()
     gg.split_step_forced(dsw.to_device(U0), out, tau, K, src=dsw.to_device(src),
-                         wall=dsw.to_device(wall), bnd=dsw.to_device(bnd))
+                         wall0=dsw.to_device(w0), wall1=dsw.to_device(w1), bnd=dsw.to_device(bnd))
     torch.cuda.synchronize()
     gg.get_status()
     e = compare(f"{name} forced U1", dsw.to_host(out), ref, base=U0)
@@ -100,12 +98,14 @@ def test_forced_step_parity_random(name, dsw):
 
 EDGE = [
     # (case, K, which forcing inputs)
-    ("sector", 1, ("src", "wall", "bnd")),
+    ("sector", 1, ("src", "wall0", "wall1", "bnd")),
     ("sector-ragged", 2, ("src",)),
-    ("sector", 2, ("wall",)),
+    ("sector", 2, ("wall0", "wall1")),
+    ("sector", 1, ("wall1",)),
     ("sector-ragged", 2, ("bnd",)),
-    ("sector-min", 3, ("src", "wall", "bnd")),
-    ("sphere-chunks2", 2, ("src", "wall", "bnd")),
+    ("sector-ragged", 1, ("bnd",)),
+    ("sector-min", 3, ("src", "wall0", "wall1", "bnd")),
+    ("sphere-chunks2", 2, ("src", "wall0", "wall1", "bnd")),
 ]
 EDGE_GRIDS = {"sector-min": I.sector(3, 3, 3, 0.01, 0.01), "sphere-chunks2": I.full_sphere(4, 5, 8)}
 
@@ -117,8 +117,8 @@ def test_forced_step_parity_edges(name, K, which, dsw):
     print(f"[forced edge] {name} K={K} {'+'.join(which)}", flush=True)
     gg, og, om = _grid(dsw, spec, I.AIR)
     U0, tau = random_state(spec, 311, mach=0.05)
-    src, wall, bnd = _forcing(spec, U0, 312)
-    kw_o = {"src": src, "wall": wall, "bnd": bnd}
+    src, w0, w1, bnd = _forcing(spec, U0, 312)
+    kw_o = {"src": src, "wall0": w0, "wall1": w1, "bnd": bnd}
     kw_o = {k: v for k, v in kw_o.items() if k in which}
     ref = oracle.split_step(og, om, U0, tau, K, **kw_o)
     out = gg.empty()
@@ -157,10 +157,8 @@ def _run_mms_gpu(dsw, gg, og, M, tau, nsteps, K, nodes, record=(), progress=None
         tn, tn1 = n * tau, (n + 1) * tau
         s0, s1 = S(tn), S(tn1)
         src = {k: 0.5 * (s0[k] + s1[k]) for k in s0}
-        w0, w1 = M.wall(og, tn), M.wall(og, tn1)
-        wall = {k: 0.5 * (w0[k] + w1[k]) for k in w0}
-        gg.split_step_forced(U, V, tau, K, src=dsw.to_device(src), wall=dsw.to_device(wall),
-                             bnd=dsw.to_device(M.fields(og, tn1)))
+        gg.split_step_forced(U, V, tau, K, src=dsw.to_device(src), wall0=dsw.to_device(M.wall(og, tn)),
+                             wall1=dsw.to_device(M.wall(og, tn1)), bnd=dsw.to_device(M.fields(og, tn1)))
         U, V = V, U
         if n + 1 in record:
             torch.cuda.synchronize()
@@ -184,8 +182,7 @@ def test_forced_step_parity_mms(dsw):
     U = M.fields(og, 0.0)
     for q in range(n):
         s0, s1 = S(q * tau), S((q + 1) * tau)
-        w0, w1 = M.wall(og, q * tau), M.wall(og, (q + 1) * tau)
-        U = oracle.split_step(og, om, U, tau, K, wall={k: 0.5 * (w0[k] + w1[k]) for k in w0},
+        U = oracle.split_step(og, om, U, tau, K, wall0=M.wall(og, q * tau), wall1=M.wall(og, (q + 1) * tau),
                               src={k: np.ascontiguousarray(0.5 * (s0[k] + s1[k])) for k in s0},
                               bnd=M.fields(og, (q + 1) * tau))
     e = compare("mms forced", U_gpu, U, base=M.fields(og, 0.0))
@@ -197,52 +194,50 @@ def _orders(errs, k):
     return (math.log2(errs[0][k] / errs[1][k]), math.log2(errs[1][k] / errs[2][k]))
 
 
-@pytest.mark.parametrize("mach", [1e-2, 1e-4])
+@pytest.mark.parametrize("mach", [1e-2, 1e-4, 1e-6])
 def test_mms_second_order_in_space_gpu(mach, dsw):
-    """figure "conv": l2 error of every field at t = 1e-3 after 100 steps of
-    tau = 1e-5 (K = 2) on three grids.  M0 = 1e-2: every field, whole box,
-    observed order >= 1.8, then >= 1.9.  M0 = 1e-4: on these grids the
-    pressure (and T) error of the whole box is dominated by the cells at the
-    walls and only approaches second order (about 0.9, then 1.5; the oracle
-    gives the same numbers); in the fixed central region every field is
-    >= 1.85 on the finer pair, and the velocities are >= 1.9 over the whole
-    box"""
+    """figure "conv": l2 error of every field over the whole box at t = 1e-3
+    after 100 steps of tau = 1e-5 (K = 2) on three grids.  M0 = 1e-2 and
+    1e-4: every field, observed order >= 1.8, then >= 1.85 (the oracle gives
+    1.90 / 1.99 for p and T at 1e-4, the velocities 1.99-2.16).  M0 = 1e-6:
+    the paper finds second order with a departure at small grid sizes from
+    round-off (errors near e^-30); here u_phi (the velocity the paper plots)
+    keeps >= 1.9, while the pressure error (1e-10 against p0 = 6250, a few
+    hundred ulps) and the temperature's approach the round-off floor, and are
+    asserted only to converge (order >= 1.0, then >= 0.9 for p)."""
     M = mms.MMS(mach, I.MMS)
-    full, mid = [], []
+    full = []
     for N in (4, 8, 16):
         spec, gg, og = _mms_grid(dsw, N, 2 * N, 6 * N)
         print(f"[mms order M0={mach}] {N}x{2 * N}x{6 * N}", flush=True)
         U, _ = _run_mms_gpu(dsw, gg, og, M, 1e-5, 100, 2, nodes=5)
         E = M.fields(og, 1e-3)
         full.append({k: np.sqrt(np.mean((U[k] - E[k])[mms.unknown_mask(og, k)] ** 2)) for k in U})
-        mid.append({k: np.sqrt(np.mean((U[k] - E[k])[mms.region_mask(og, k)] ** 2)) for k in U})
         print("  l2 errors " + " ".join(f"{k}={v:.3e}" for k, v in full[-1].items()), flush=True)
     for k in KEYS:
-        of, om_ = _orders(full, k), _orders(mid, k)
-        print(f"  order {k}: box {of[0]:.2f} {of[1]:.2f}, central region {om_[0]:.2f} {om_[1]:.2f}",
-              flush=True)
-        if mach >= 1e-2:
-            assert of[0] > 1.8 and of[1] > 1.9, (k, of)
+        of = _orders(full, k)
+        print(f"  order {k}: box {of[0]:.2f} {of[1]:.2f}", flush=True)
+        if mach >= 1e-4:
+            assert of[0] > 1.8 and of[1] > 1.85, (k, of)
+        elif k in ("ur", "ut", "uf"):
+            assert of[0] > 1.3 and of[1] > 1.9, (k, of)
         else:
-            assert om_[1] > 1.85, (k, om_)
-            if k in ("ur", "ut", "uf"):
-                assert of[1] > 1.9, (k, of)
-            else:
-                assert of[1] > 1.4, (k, of)
+            assert of[0] > 1.0 and of[1] > 0.9, (k, of)
 
 
-@pytest.mark.parametrize("mach", [1e-2, 1e-3, 1e-4])
+@pytest.mark.parametrize("mach", [1e-2, 1e-3, 1e-4, 1e-5, 1e-6])
 def test_table3_incompressible_limit_gpu(mach, dsw):
     """Table 3 on a grid of diameter 0.12 (15 x 45 x 135 cells; the odd
     counts put cell centres on the maxima of cos^2(4 theta) and
-    cos^2(4 phi)): max (p - p0)/p0 after n = 1, 50, 100 steps of tau = 1e-3
-    within 1 % of the closed form (2 + sin 5t) gamma M0^2, and equal to the
-    printed value to the printed digit (M0 = 1e-4: within 4 % of both, the
-    band by which the printed values themselves differ from the closed
-    form).  The
-    maximum is taken over the cells off the theta and phi walls: the cells
-    where those walls meet hold a larger deviation at M0 <= 1e-3 on this
-    grid (3.60 against 3.19 at M0 = 1e-3, n = 1; the oracle gives the same)."""
+    cos^2(4 phi)): max over all cells of (p - p0)/p0 after n = 1, 50, 100
+    steps of tau = 1e-3.  M0 >= 1e-3: within 1 % of the closed form
+    (2 + sin 5t) gamma M0^2 and equal to the printed value to the printed
+    digit.  M0 = 1e-4: within 1 % of the closed form and 4.5 % of the
+    printed values (which themselves lie up to 4 % above the closed form).
+    M0 = 1e-5, 1e-6: O(M0^2), between the closed form and the printed value
+    (plus half its last digit): the paper's own columns grow above the closed
+    form there (to 4.9 and 14 after 100 steps); the oracle gives 4.15 and
+    6.01."""
     M = mms.MMS(mach, I.MMS)
     spec, gg, og = _mms_grid(dsw, 15, 45, 135)
     d = math.sqrt((1.0 / 15) ** 2 + (2.0 * (math.pi / 2) / 45) ** 2 + (2.0 * (1.5 * math.pi) / 135) ** 2)
@@ -253,20 +248,19 @@ def test_table3_incompressible_limit_gpu(mach, dsw):
         tab = json.load(fh)
     col = tab["columns_M0"].index(mach)
     printed = {int(n): v[col] / mach ** 2 for n, v in tab["rows"].items()}
-    off = np.zeros(spec.shapes()["p"], dtype=bool)
-    off[:, 1:-1, 1:-1] = True
     for n, U in sorted(rec.items()):
-        dev = np.abs(U["p"] - mms.P0) / mms.P0 / mach ** 2
-        dp = np.max(dev[off])
-        exact = np.max(np.abs(M.fields(og, n * 1e-3)["p"] - mms.P0)[off]) / mms.P0 / mach ** 2
-        print(f"  n={n}: max dp/p0/M0^2 = {dp:.4f} off the theta/phi walls, {np.max(dev):.4f} over all "
-              f"cells (closed form {exact:.4f}, printed {printed[n]:.2f})", flush=True)
+        dp = np.max(np.abs(U["p"] - mms.P0)) / mms.P0 / mach ** 2
+        exact = np.max(np.abs(M.fields(og, n * 1e-3)["p"] - mms.P0)) / mms.P0 / mach ** 2
+        print(f"  n={n}: max dp/p0/M0^2 = {dp:.4f} over all cells (closed form {exact:.4f}, "
+              f"printed {printed[n]:.2f})", flush=True)
         if mach >= 1e-3:
             assert abs(dp - exact) < 0.01 * exact, (n, dp, exact)
             assert round(dp, 1) == round(printed[n], 1), (n, dp)
-        else:  # the printed values drift above the closed form too
-            assert abs(dp - exact) < 0.04 * exact, (n, dp, exact)
+        elif mach >= 1e-4:
+            assert abs(dp - exact) < 0.01 * exact, (n, dp, exact)
             assert abs(dp - printed[n]) < 0.045 * printed[n], (n, dp, printed[n])
+        else:
+            assert exact <= dp <= printed[n] + 0.05, (n, dp, exact, printed[n])
 
 
 @pytest.mark.parametrize("mach", [1e-2, 1e-4])
@@ -278,9 +272,11 @@ def test_time_convergence_rate_gpu(mach, dsw):
     The paper's values scatter between 1.4 and 3.2 and are read as second
     order.  Here the smallest tau gives about 2 for every field at
     M0 = 1e-2 (asserted within [1.7, 2.4]); at M0 = 1e-4 the pressure and
-    temperature give about 2 and the velocities, whose tau^2 error constant
-    is small there, stay near 3 (asserted within [1.7, 3.5]); the larger
-    tau scatter as the paper's do (asserted within [1.0, 4.2])."""
+    temperature give about 2 and the velocities 2.1-2.7 (asserted within
+    [1.7, 3.5]).  The two larger tau are pre-asymptotic for single velocity
+    components at M0 = 1e-2 (u_phi 0.67 at 2e-3, u_r 0.98 at 1e-3: their
+    successive differences shrink by 1.6, then 3.7 and 4.0, the oracle alike):
+    asserted to converge, within (0.5, 4.2)."""
     M = mms.MMS(mach, I.MMS)
     spec, gg, og = _mms_grid(dsw, 8, 16, 48)
     tf = 0.064
@@ -301,7 +297,7 @@ def test_time_convergence_rate_gpu(mach, dsw):
         print(f"  tau={2e-3 / 2 ** q:.0e}: " + " ".join(f"{k}={v:.2f}" for k, v in tcr.items()), flush=True)
         for k, v in tcr.items():
             if q < 2:
-                lo, hi = 1.0, 4.2
+                lo, hi = 0.5, 4.2
             elif mach >= 1e-2 or k in ("p", "T"):
                 lo, hi = 1.7, 2.4
             else:
