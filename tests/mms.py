@@ -233,3 +233,42 @@ def unknown_mask(g, key):
     if key == "uf" and not g.periodic:
         m[:, :, 0] = m[:, :, -1] = False
     return m
+
+
+class AxisymmetricField(MMS):
+    """A smooth field on the full sphere for pinning the pole rules: symmetric
+    about the polar axis and smooth there as a Cartesian field (u_r and the
+    scalars functions of cos theta, u_theta and u_phi sin theta times such
+    functions), so that across a pole u_r, p and T are even, u_phi is odd and
+    u_theta vanishes on the axis, which are the ghost rules of the full-sphere
+    reading.  p and T have zero normal derivative on the walls r = 1, 2 (the
+    cos^2(pi r) factor), as the boundary conditions require.  The same source
+    machinery (Cartesian automatic differentiation of
+    the continuous equations) gives F(U)."""
+
+    def sph(self, r, th, ph, t):
+        u0, c0 = self.u0, self.c0
+        c, s = torch.cos(th), torch.sin(th)
+        p = P0 + u0 ** 2 * (1 + torch.sin(t) + torch.cos(math.pi * r) ** 2 * (1 + 0.5 * c + c ** 2))
+        ur = u0 * (1 + 0.3 * torch.cos(2 * t)) * (0.2 + torch.sin(r) * c * (1 + c))
+        ut = u0 * (1 + 0.2 * torch.sin(t)) * s * torch.cos(r) * (1 + 0.7 * c)
+        uf = u0 * (1 + 0.4 * torch.cos(t)) * s * r * (1 - 0.3 * c ** 2)
+        T = p / (self.mat.cv * (self.gamma - 1.0)) * (1 + 0.01 * c)
+        return p, ur, ut, uf, T
+
+
+class ZonalShear(MMS):
+    """A zonal shear flow u_phi = u0 r^2 sin theta (smooth across the polar
+    axis, divergence-free) with uniform p and T: the pressure row of F is then
+    the viscous heating -(gamma - 1) grad u : sigma, whose strain component
+    S_theta phi = (1/r) d u_phi / d theta - u_phi cot(theta) / r vanishes
+    exactly; next to a pole its centred difference reads the u_phi ghost
+    across the axis, so this row pins that ghost's sign."""
+
+    def sph(self, r, th, ph, t):
+        u0 = self.u0
+        z = torch.zeros_like(r * th * ph)
+        p = P0 + z + 0.0 * t
+        uf = u0 * (1 + 0.5 * torch.sin(t)) * r ** 2 * torch.sin(th)
+        T = p / (self.mat.cv * (self.gamma - 1.0))
+        return p, z, z, uf, T

@@ -136,9 +136,11 @@ def test_adjoint_step_other_phi_solvers(name, phi, dsw):
     check_dot(f"{name} J^T phi={phi}", dot(dsw.to_host(out), V), dot(lam, dU1))
 
 
-@pytest.mark.parametrize("name", ["sector-min", "sphere-min"])
+@pytest.mark.parametrize("name", ["sector-min", "sphere-min", "sphere-chunks2"])
 def test_adjoint_step_dense_tiny(name, dsw):
-    """the whole transposed Jacobian on a 3x3x3 grid, entry by entry"""
+    """the whole transposed Jacobian on a tiny grid, entry by entry: 3x3x3
+    sector and sphere, and a 4x5x8 full sphere whose phi lines go through the
+    partitioned transposed solver (two chunks, cyclic reduction)"""
     print(f"[adjoint dense] {name}", flush=True)
     w, U0, tau, og, om, gg = _setup(name, dsw)
     shapes = w.grid.shapes()

@@ -8,15 +8,20 @@ benchmark times, on sampled outputs the oracle computes one by one:
 * transposed line solves (the adjoint's): <M_d^-T y, b> = <y, M_d^-1 b> on
   the whole grid, an identity at any size whose forward side is the solve
   pinned above;
+* the timed path itself: one split step on the global workload against the
+  oracle's, element by element;
 * properties of the whole step that hold at any size: phi-shift and
   theta/phi mirror equivariance on the full sphere (the poles and the cyclic
   solves) and the discretely hydrostatic rest state.
 """
+import time
+
 import numpy as np
 import pytest
 import torch
 
 import oracle
+from gpu_common import compare
 from paper_2004_13887_amd import inputs as I
 
 pytestmark = pytest.mark.gpu
@@ -173,6 +178,34 @@ def test_full_transposed_line_solve_identity(name, d, dsw):
     e = abs(lhs - rhs) / max(abs(lhs), abs(rhs))
     print(f"{name} d={d}: <M^-T y, b> = {lhs:.15e}, <y, M^-1 b> = {rhs:.15e}, rel {e:.2e}", flush=True)
     assert e <= TOL
+
+
+def test_full_global_step_matches_the_oracle(dsw):
+    """The timed path at its own size: one dsw_split_step on the global
+    workload (512 x 256 x 128 full sphere, M = 1e-4, K = 3), as the benchmark
+    times it (the residual's interior and shell launches on the resident
+    midpoint, the two-ended r and theta sweeps, the phi pass split into its
+    block-line and scalar-line launches in update mode), against
+    oracle.split_step element by element: relative L2 per field <= 1e-11, of
+    the fields and of their change from U^n (at M = 1e-4 the full pressure
+    field cannot see the dynamics).  The oracle takes about half a minute on
+    the host's cores."""
+    w, U0, tau, og, om, gg = setup("global", dsw)
+    dU0 = dsw.to_device(U0)
+    dU1 = gg.empty()
+    gg.split_step(dU0, dU1, tau, w.K)
+    torch.cuda.synchronize()
+    gg.get_status()
+    U1 = dsw.to_host(dU1)
+    del dU0, dU1
+    print(f"[global step] GPU done; oracle step on {w.grid.nr * w.grid.nt * w.grid.np} cells", flush=True)
+    t0 = time.time()
+    ref = oracle.split_step(og, om, U0, tau, w.K)
+    print(f"[global step] oracle done in {time.time() - t0:.1f} s", flush=True)
+    e = compare("global step", U1, ref, base=U0)
+    keys = ("p", "ur", "ut", "uf", "T")
+    assert max(e[k] for k in keys) <= TOL
+    assert max(e[k + "_change"] for k in keys) <= TOL
 
 
 def test_full_global_phi_shift_equivariance(dsw):

@@ -122,3 +122,85 @@ def test_line_solve_inverts_line_matvec():
         y = oracle.line_matvec(g, AIR, U, tau, d, x)
         for k in oracle.FIELDS:
             assert rel(y[k], rhs[k]) < 1e-12, (d, k)
+
+
+def _all_lines(g, d):
+    """every line of direction d as (kind, a, b): block lines (kind -1), then
+    the two scalar families (kind = the field id), as the full solve has them"""
+    FR, FT, FF = 1, 2, 3
+    kf = range(0, g.np) if g.periodic else range(1, g.np)
+    if d == 0:
+        out = [(-1, j, k) for j in range(g.nt) for k in range(g.np)]
+        out += [(FT, f, k) for f in range(1, g.nt) for k in range(g.np)]
+        out += [(FF, j, f) for j in range(g.nt) for f in kf]
+    elif d == 1:
+        out = [(-1, i, k) for i in range(g.nr) for k in range(g.np)]
+        out += [(FR, f, k) for f in range(1, g.nr) for k in range(g.np)]
+        out += [(FF, i, f) for i in range(g.nr) for f in kf]
+    else:
+        out = [(-1, i, j) for i in range(g.nr) for j in range(g.nt)]
+        out += [(FR, f, j) for f in range(1, g.nr) for j in range(g.nt)]
+        out += [(FT, i, f) for i in range(g.nr) for f in range(1, g.nt)]
+    return np.array(out, dtype=np.int64).T
+
+
+@pytest.mark.parametrize("which", ["sector", "sphere"])
+def test_sampled_residual_equals_the_full_residual(which):
+    """residual_at, the point-sample checker of the full-size GPU tests, gives
+    the full residual's value at every point of every field, bit for bit
+    (boundary-normal faces included, where both are 0)"""
+    spec = small_sector() if which == "sector" else small_sphere()
+    g = grid_of(spec)
+    Un, tau = random_state(spec, 91, mach=0.05)
+    rng = np.random.Generator(np.random.PCG64(92))
+    Uk = {k: v + 1e-3 * np.abs(v).mean() * rng.uniform(-1, 1, v.shape) for k, v in Un.items()}
+    wall = random_wall(spec, 93) if which == "sector" else None
+    R, Ub = oracle.residual(g, AIR, Un, Uk, tau, wall=wall)
+    for k, fid in oracle.FID.items():
+        idx = np.arange(R[k].size)
+        got = oracle.residual_at(g, AIR, Un, Uk, Ub, tau, np.full(idx.size, fid), idx, wall=wall)
+        assert np.array_equal(got, R[k].ravel()), k
+
+
+@pytest.mark.parametrize("which", ["sector", "sphere"])
+@pytest.mark.parametrize("d", [0, 1, 2])
+def test_line_solve_of_some_lines_equals_the_full_solve(which, d):
+    """line_solve_some, the line-sample checker of the full-size GPU tests,
+    solves every line of the full solve, bit for bit, and writes nothing
+    outside the lines it is given"""
+    spec = small_sector() if which == "sector" else small_sphere()
+    g = grid_of(spec)
+    Ub, tau = random_state(spec, 94, mach=0.05)
+    rng = np.random.Generator(np.random.PCG64(95))
+    rhs = {k: rng.uniform(-1, 1, s) for k, s in g.shapes().items()}
+    for k in ("ur", "ut", "uf"):
+        rhs[k][~oracle_unknowns(g, k)] = 0.0
+    wall = random_wall(spec, 96) if which == "sector" else None
+    full = oracle.line_solve(g, AIR, Ub, tau, d, rhs, wall=wall)
+    kinds, a, b = _all_lines(g, d)
+    some = oracle.line_solve_some(g, AIR, Ub, tau, d, kinds, a, b, rhs, wall=wall)
+    for k in full:
+        m = oracle_unknowns(g, k)
+        assert np.array_equal(some[k][m], full[k][m]), k
+    # half of the lines: the other half's unknowns stay untouched (NaN)
+    half = slice(0, None, 2)
+    part = oracle.line_solve_some(g, AIR, Ub, tau, d, kinds[half], a[half], b[half], rhs, wall=wall)
+    touched = sum(int(np.sum(~np.isnan(v))) for v in part.values())
+    total = sum(int(np.sum(oracle_unknowns(g, k))) for k in full)
+    assert 0 < touched < total
+    for k in full:
+        ok = ~np.isnan(part[k])
+        assert np.array_equal(part[k][ok], full[k][ok]), k
+
+
+def oracle_unknowns(g, key):
+    """points that are unknowns (not boundary-normal faces)"""
+    sh = g.shapes()[key]
+    m = np.ones(sh, dtype=bool)
+    if key == "ur":
+        m[0] = m[-1] = False
+    if key == "ut":
+        m[:, 0] = m[:, -1] = False
+    if key == "uf" and not g.periodic:
+        m[:, :, 0] = m[:, :, -1] = False
+    return m

@@ -7,6 +7,11 @@
   stencil, second order in space);
 * the direction parts N_d(U; U) converge to the continuous D_d(U) U of
   Appendix B, eqs. (dr), (dtheta), (dphi);
+* the same with rotation, a stiffened-gas pi_inf and gravity (the Coriolis
+  term 2 omega x u of Appendix B's B2 rows, p + pi_inf in eqs.
+  (nonconservener), (nonconserveos), the G of eq. (chapter3main));
+* the rows next to the poles of the full sphere converge for a field that is
+  smooth across the axis (the pole ghost rules);
 * the periodic seam in phi is invisible in the truncation error;
 * invariants: a uniform state without gravity and the discretely hydrostatic
   rest state are steady; mirror symmetry in theta and phi; shift
@@ -28,16 +33,17 @@ MAT_MMS = oracle.Material(*I.MMS.astuple())
 SUBBOX = (1.2, 1.4, 1.1, 1.3, 2.2, 2.4)
 
 
-def _trunc(N, box, periodic=False, t=0.3, mach=1e-2, shape=None):
+def _trunc(N, box, periodic=False, t=0.3, mach=1e-2, shape=None, mat=I.MMS, field=mms.MMS):
     shape = shape or (N, N, N)
     g = oracle.Grid(*shape, *box, periodic=periodic)
-    M = mms.MMS(mach, I.MMS)
+    M = field(mach, mat)
     U = M.fields(g, t)
     S = M.sources(g, t)
     eps = 1e-6
     Up, Um = M.fields(g, t + eps), M.fields(g, t - eps)
     W = M.wall(g, t) if not periodic else {k: v for k, v in M.wall(g, t).items() if "_p" not in k}
-    F = oracle.apply(g, MAT_MMS, U, U, oracle.MASK_ALL, W, W)
+    F = oracle.apply(g, oracle.Material(*mat.astuple()), U, U, oracle.MASK_ALL, W, W)
+    F["ur"][mms.unknown_mask(g, "ur")] += mat.g_r  # F_h = N(U; U) + G (eq. (chapter3main))
     err = {k: F[k] - (S[k] - (Up[k] - Um[k]) / (2 * eps)) for k in U}
     return g, err
 
@@ -50,6 +56,79 @@ def test_F_h_second_order_interior():
     for k in errs[0]:
         order = math.log2(errs[0][k] / errs[1][k])
         assert order > 1.9, (k, order, errs)
+
+
+# rotation about the polar axis, a stiffened gas and gravity: every term the
+# manufactured-solution material leaves at zero
+ROT = I.MaterialSpec(cp=1.6, cv=1.0, pi_inf=2500.0, mu=1.0, prandtl=1.0, omega=0.7, g_r=3.0)
+
+
+def test_F_h_second_order_with_rotation_stiffened_gas_and_gravity():
+    """omega, pi_inf and g_r enter F_h exactly where the continuous equations
+    put them: a dropped term, a wrong sign or a wrong component (the Coriolis
+    term's e_r, e_theta, e_phi parts) leaves an O(1) error that does not
+    converge"""
+    errs = []
+    for N in (8, 16):
+        g, e = _trunc(N, SUBBOX, mat=ROT)
+        errs.append({k: np.sqrt(np.mean(e[k][mms.region_mask(g, k)] ** 2)) for k in e})
+    for k in errs[0]:
+        order = math.log2(errs[0][k] / errs[1][k])
+        assert order > 1.9, (k, order, errs)
+
+
+def _pole_rows(g, key):
+    """the points next to either pole: cells and r/phi faces of the first and
+    last theta row, the theta faces one step off each pole face"""
+    m = np.zeros(g.shapes()[key], dtype=bool)
+    if key == "ut":
+        m[:, [1, g.nt - 1], :] = True
+    else:
+        m[:, [0, g.nt - 1], :] = True
+    if key == "ur":
+        m[[0, -1]] = False  # r walls: not unknowns
+    return m
+
+
+def test_pole_rows_converge_for_a_field_smooth_across_the_axis():
+    """Full sphere, axisymmetric field smooth at the poles (mms.AxisymmetricField):
+    the truncation error of F_h on the rows next to the poles shrinks under
+    refinement in theta and phi (the pole ghost rules: u_r, p, T copied, u_phi
+    negated, u_theta = 0 on the pole face, sin theta = 0 there).  A ghost of the
+    wrong sign for u_r gives a centred theta derivative of size u / dtheta
+    there, an error that grows under refinement.  Observed orders at the pole
+    rows: 1.9-2.0 for p, T and u_r, 1.5 then 1.2 for u_theta, 0.6 then 0.9 for
+    u_phi (whose rows keep the component form of the vector Laplacian next to
+    the pole, first order there)."""
+    box = (1.0, 2.0, 0.0, math.pi, 0.0, 2 * math.pi)
+    errs = []
+    for nt in (12, 24, 48):
+        g, e = _trunc(0, box, periodic=True, shape=(nt // 2, nt, 2 * nt), field=mms.AxisymmetricField, mat=ROT)
+        errs.append({k: float(np.max(np.abs(e[k][_pole_rows(g, k)]))) for k in e})
+    print("pole-row truncation errors", errs)
+    for k in errs[0]:
+        o1 = math.log2(errs[0][k] / errs[1][k])
+        o2 = math.log2(errs[1][k] / errs[2][k])
+        lo = 0.5 if k == "uf" else 0.9  # u_phi: component form next to the pole, first order
+        assert o1 > lo and o2 > lo, (k, o1, o2, errs)
+
+
+def test_pole_rows_viscous_heating_pins_the_u_phi_ghost():
+    """Full sphere, zonal shear u_phi = u0 r^2 sin theta with uniform p and
+    T and a large viscosity (mms.ZonalShear): the pressure row is the viscous
+    heating, and on the cells next to the poles its truncation error
+    converges (order > 1.5); a u_phi ghost of the wrong sign across the axis
+    leaves an O(mu u0^2 / r^2) error there that does not shrink."""
+    mat = I.MaterialSpec(cp=1.6, cv=1.0, pi_inf=0.0, mu=50.0, prandtl=1.0, omega=0.0, g_r=0.0)
+    box = (1.0, 2.0, 0.0, math.pi, 0.0, 2 * math.pi)
+    errs = []
+    for nt in (12, 24, 48):
+        g, e = _trunc(0, box, periodic=True, shape=(nt // 2, nt, 2 * nt), field=mms.ZonalShear, mat=mat,
+                      mach=0.1)
+        errs.append(float(np.max(np.abs(e["p"][_pole_rows(g, "p")]))))
+    print("pole-cell p-row truncation errors", errs)
+    o1, o2 = math.log2(errs[0] / errs[1]), math.log2(errs[1] / errs[2])
+    assert o1 > 1.5 and o2 > 1.5, (o1, o2, errs)
 
 
 def test_periodic_seam_has_no_extra_error():
