@@ -8,7 +8,13 @@ Workload: 512 (phi, periodic) x 256 (theta, poles) x 128 (r) cells over a
 seeded synthetic initial data (hydrostatic isothermal atmosphere, Gaussian
 potential-temperature bubble, seeded velocity noise).  A "step" is one call of
 dsw_split_step (K x (residual + three line sweeps)); inputs are resident in
-HBM before the timed region.  Prints one JSON line.
+HBM before the timed region.  Prints one JSON line: the step rate, the
+roofline of the dominant pass (algorithmic bytes of the fixed four-pass
+model per launch over its average launch time, HIP events on the launch
+stream; HBM bytes from committed counter summaries when they match the
+kernel sources), the adjoint/forward time on the adjoint workload, and the
+CPU oracle built for the host, on all its cores at full size and on one core
+on a slab.
 
 --sweeps measures the line solves alone and the split step's passes on the
 1024 x 512 x 64 sector; --adjoint the adjoint step against the forward step
@@ -52,23 +58,34 @@ def kernel_sources_sha():
 
 
 def algorithmic_bytes(counts, K):
-    """algorithmic bytes per split step of each kernel kind: every array a
-    kernel reads or writes counted once (neighbour re-reads not counted);
-    S = one five-field state.
-      residual   k=0: U^n -> R (2S);  k>0: Ubar, U^k, U^n -> R (4S)
+    """Algorithmic bytes per split step of each pass, the fixed four-pass model
+    of the method (one read of every input state and one write of every output
+    state per pass; neighbour re-reads and this implementation's extra
+    buffers not counted); S = one five-field state at its real array sizes:
+      residual   k=0: U^n -> R (2S; Ubar = U^k = U^n);  k>0: U^n, U^k -> Ubar, R (4S)
       sweep r    Ubar, R -> X1 (3S);  sweep theta: Ubar, X1 -> X2 (3S)
-      sweep phi  k=0: U^n, X2 -> U^1, Ubar^1 (4S);  0<k<K-1: Ubar, X2, U^k,
-                 U^n -> U^{k+1}, Ubar^{k+1} (6S);  k=K-1>0: Ubar, X2, U^k -> U^K (4S)"""
+      sweep phi  k=0: Ubar = U^k = U^n, X2 -> U^1 (3S);  k>0: Ubar, X2, U^k -> U^{k+1} (4S)
+    i.e. 55 + 70 (K - 1) doubles per cell and step."""
     S = 8 * sum(counts)
-    res = 2 * S + 4 * S * (K - 1)
+    return {"residual": 2 * S + 4 * S * (K - 1), "sweep_r": 3 * S * K, "sweep_theta": 3 * S * K,
+            "sweep_phi_update": 3 * S + 4 * S * (K - 1), "boundary_copy": 0}
+
+
+def implementation_bytes(counts, K):
+    """The arrays this implementation's passes actually read and write once
+    each, per split step (S as above): the residual reads the resident
+    midpoint and forms -(U^k - U^n), and the phi pass also writes the next
+    iteration's midpoint (and reads U^n for it):
+      residual   k=0: U^n -> R (2S);  k>0: Ubar, U^k, U^n -> R (4S)
+      sweeps     3S each
+      sweep phi  k=0: U^n, X2 -> U^1, Ubar^1 (4S);  0<k<K-1: Ubar, X2, U^k, U^n
+                 -> U^{k+1}, Ubar^{k+1} (6S);  k=K-1>0: Ubar, X2, U^k -> U^K (4S)"""
+    S = 8 * sum(counts)
     phi = 0
     for k in range(K):
         last = k == K - 1
-        if k == 0:
-            phi += (3 if last else 4) * S
-        else:
-            phi += (4 if last else 6) * S
-    return {"residual": res, "sweep_r": 3 * S * K, "sweep_theta": 3 * S * K,
+        phi += ((3 if last else 4) if k == 0 else (4 if last else 6)) * S
+    return {"residual": 2 * S + 4 * S * (K - 1), "sweep_r": 3 * S * K, "sweep_theta": 3 * S * K,
             "sweep_phi_update": phi, "boundary_copy": 0}
 
 
@@ -86,30 +103,103 @@ def measured_traffic(kind, sha):
     return e.get("bytes_per_launch")
 
 
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline():
-    """The oracle timed on the host on a bounded sample of the same workload:
-    the global grid recipe with 48 radial levels (512 x 256 x 48 cells), one
-    split step with K = 3 (about 10-15 s on 16 host threads)."""
+    """The oracle timed on the host: built for this host (-O3 -march=native,
+    no FMA contraction, no fast-math), one split step (K = 3) of the global
+    workload at full size on all host cores, and on one core a bounded slab
+    of the same recipe (512 x 256 x 8 cells; about half a minute each)."""
     import oracle
     from paper_2004_13887_amd import inputs as I
-    nr = 48
-    w = I.scaled(I.WORKLOADS[WORKLOAD], nr, 256, 512, name=f"global-{nr}-levels")
-    U0, tau = I.initial_state(w)
-    g = oracle.Grid(*w.grid.args())
-    m = oracle.Material(*w.material.astuple())
-    t0 = time.perf_counter()
-    oracle.split_step(g, m, U0, tau, w.K)
-    dt = time.perf_counter() - t0
+    L = oracle.lib_bench()
+    oracle._lib = L  # the oracle calls below run the host-tuned build
     try:
-        cores = len(os.sched_getaffinity(0))
+        ncores = len(os.sched_getaffinity(0))
     except AttributeError:
-        cores = os.cpu_count()
+        ncores = os.cpu_count()
     if os.environ.get("OMP_NUM_THREADS"):
-        cores = min(cores, int(os.environ["OMP_NUM_THREADS"]))
-    return {"value": w.grid.ncells / dt, "unit": "grid-point updates/s", "cores": cores,
+        ncores = min(ncores, int(os.environ["OMP_NUM_THREADS"]))
+
+    def one_step(w, threads):
+        U0, tau = I.initial_state(w)
+        g = oracle.Grid(*w.grid.args())
+        m = oracle.Material(*w.material.astuple())
+        L.orc_set_threads(threads)
+        t0 = time.perf_counter()
+        oracle.split_step(g, m, U0, tau, w.K)
+        return time.perf_counter() - t0
+
+    w_all = I.WORKLOADS[WORKLOAD]
+    log(f"[bench] oracle: one step of {w_all.grid.ncells} cells on {ncores} threads")
+    dt_all = one_step(w_all, ncores)
+    w_one = I.scaled(w_all, 8, 256, 512, name="global-8-levels")
+    log(f"[bench] oracle: one step of {w_one.grid.ncells} cells on 1 thread")
+    dt_one = one_step(w_one, 1)
+    L.orc_set_threads(ncores)
+    return {"value": w_all.grid.ncells / dt_all, "unit": "grid-point updates/s", "cores": ncores,
             "kind": "oracle",
-            "sample": f"one split step (K={w.K}) of the global recipe on 512x256x{nr} cells "
-                      f"({w.grid.ncells} cells), {dt:.2f} s wall"}
+            "sample": f"one split step (K={w_all.K}) of the global workload at full size "
+                      f"(512x256x128, {w_all.grid.ncells} cells), {dt_all:.1f} s wall on {ncores} threads",
+            "one_core": {"value": w_one.grid.ncells / dt_one, "unit": "grid-point updates/s", "cores": 1,
+                         "sample": f"one split step (K={w_one.K}) of the global recipe on a 512x256x8 slab "
+                                   f"({w_one.grid.ncells} cells), {dt_one:.1f} s wall"},
+            "build": "gcc -O3 -march=native -fopenmp -ffp-contract=off -fno-fast-math",
+            "nproc": os.cpu_count(), "cpu_model": _cpu_model()}
+
+
+def adjoint_ratio(steps=5, warmup=2):
+    """adjoint / forward time on the adjoint workload (256 x 128 x 64 sector):
+    one dsw_adjoint_step (its forward recompute included) and the reverse pass
+    through the workload's steps from per-step checkpoints, each against one
+    dsw_split_step"""
+    import numpy as np
+    import torch
+    from paper_2004_13887_amd import dsw
+    from paper_2004_13887_amd import inputs as I
+
+    w = I.WORKLOADS["adjoint"]
+    U0, tau = I.initial_state(w)
+    grid = dsw.Grid.from_spec(w.grid, w.material)
+    A, B, out = dsw.to_device(U0), grid.empty(), grid.empty()
+    rng = np.random.Generator(np.random.PCG64(7))
+    lam = {k: torch.as_tensor(rng.uniform(-1.0, 1.0, v.shape), device="cuda") for k, v in U0.items()}
+    stream = torch.cuda.current_stream()
+    ck = [A]
+    for n in range(w.steps - 1):
+        nxt = grid.empty()
+        grid.split_step(ck[-1], nxt, tau, w.K, stream)
+        ck.append(nxt)
+
+    def timed(fn, n):
+        for q in range(warmup):
+            fn(q)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for q in range(n):
+            fn(warmup + q)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / n
+
+    fwd = timed(lambda q: grid.split_step(A if q % 2 == 0 else B, B if q % 2 == 0 else A, tau, w.K, stream),
+                steps)
+    adj = timed(lambda q: grid.adjoint_step(A, tau, w.K, lam, out, stream), steps)
+    traj = timed(lambda q: grid.adjoint_trajectory(ck, tau, w.K, lam, out, stream), 2) / w.steps
+    grid.get_status()
+    return {"workload": f"adjoint: 256x128x64 sector, K={w.K}, {w.steps} checkpointed steps",
+            "forward_ms": fwd, "adjoint_step_ms": adj, "adjoint_step_over_forward": adj / fwd,
+            "trajectory_ms_per_step": traj, "trajectory_over_forward": traj / fwd}
 
 
 def main():
@@ -118,6 +208,7 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint/forward measurement")
     ap.add_argument("--calib", action="store_true",
                     help="also run a plain 1 GiB device copy (to scale hardware byte counters)")
     ap.add_argument("--config", default=None,
@@ -196,23 +287,25 @@ def main():
 
     cells = w.grid.ncells
     value = cells * args.steps / (gpu_ms * 1e-3)
-    model_bytes = 8 * (55 + 70 * (w.K - 1)) * cells  # per split step, fixed traffic model
     alg = algorithmic_bytes(counts, w.K)  # per step
+    impl = implementation_bytes(counts, w.K)
     kstats = {}
     for k, (ms, n) in per_kernel.items():
         if n:
             avg = ms / n * 1e-3
             per_launch = alg[k] * args.steps / n  # average algorithmic bytes per launch
             kstats[k] = {"avg_ms": avg * 1e3, "launches": n, "total_ms": ms,
-                         "bytes_per_launch": per_launch, "GBps": per_launch / avg / 1e9}
+                         "bytes_per_launch": per_launch, "GBps": per_launch / avg / 1e9,
+                         "implementation_bytes_per_launch": impl[k] * args.steps / n}
             log(f"[bench] {k:17s} {n:4d} launches, avg {avg * 1e3:8.3f} ms, "
                 f"{per_launch / avg / 1e9:8.1f} GB/s algorithmic")
     dom = max(kstats, key=lambda k: kstats[k]["total_ms"])
     sha = kernel_sources_sha()
     achieved = kstats[dom]["GBps"]
     traffic = measured_traffic(dom, sha)
+    step_bytes = sum(alg.values())
     out = {
-        "metric": "grid-point updates/s per split step (FP64)",
+        "metric": "grid-point updates/s per split step (FP64) + % HBM roofline; adjoint/forward time",
         "value": value,
         "unit": "grid-point updates/s",
         "n_gpus": 1,
@@ -230,15 +323,22 @@ def main():
                    "launch_config": dict(zip(("residual_block", "sweep_block_r", "sweep_block_theta",
                                               "phi_rows_per_thread"), grid.get_config()))},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": PEAK_HBM / 1e9,
-                     "unit": "GB/s", "frac": achieved / (PEAK_HBM / 1e9),
-                     "traffic": traffic, "bytes_per_launch": kstats[dom]["bytes_per_launch"],
+                     "unit": "GB/s", "frac": achieved / (PEAK_HBM / 1e9), "traffic": traffic,
+                     "bytes_per_launch": kstats[dom]["bytes_per_launch"],
+                     "avg_launch_ms": kstats[dom]["avg_ms"],
+                     "implementation_bytes_per_launch": kstats[dom]["implementation_bytes_per_launch"],
                      "source_sha": sha},
-        "step_model_GBps": model_bytes / (ms_per_step * 1e-3) / 1e9,
-        "step_model_frac": model_bytes / (ms_per_step * 1e-3) / PEAK_HBM,
+        "step_algorithmic_GBps": step_bytes / (ms_per_step * 1e-3) / 1e9,
+        "step_frac": step_bytes / (ms_per_step * 1e-3) / PEAK_HBM,
         "kernels": kstats,
     }
+    if not args.no_adjoint:
+        log("[bench] adjoint / forward on the adjoint workload")
+        del bufs
+        torch.cuda.empty_cache()
+        out["adjoint"] = adjoint_ratio()
     if not args.no_cpu:
-        log("[bench] timing the CPU oracle on a bounded sample")
+        log("[bench] timing the CPU oracle")
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out), flush=True)
 
@@ -398,7 +498,7 @@ def bench_sweeps(args):
         solves[name] = {"avg_ms": ms, "GBps": 3 * S / (ms * 1e-3) / 1e9}
         log(f"[sweeps] dsw_line_solve_{name:5s} {ms:7.3f} ms, {3 * S / (ms * 1e-3) / 1e9:7.1f} GB/s")
     grid.get_status()
-    model_bytes = 8 * (55 + 70 * (w.K - 1)) * w.grid.ncells
+    model_bytes = sum(alg.values())
     out = {
         "metric": "GB/s per line solve (FP64, algorithmic bytes)",
         "value": min(v["GBps"] for v in solves.values()),

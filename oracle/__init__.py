@@ -51,6 +51,23 @@ def build(force: bool = False) -> str:
     return _build_one(_LIB, [], force)
 
 
+_LIB_BENCH = os.path.join(_HERE, "libdsw_oracle_bench.so")  # this host's CPU only
+
+
+def lib_bench():
+    """The FP64 oracle built for timing on this host: -O3 -march=native, still
+    without FMA contraction or fast-math (the same results as the test build).
+    Built where it runs, every time, since -march=native code is not portable."""
+    tmp = _LIB_BENCH + f".tmp{os.getpid()}"
+    subprocess.check_call(["gcc", "-O3", "-march=native", "-std=gnu11", "-fopenmp", "-ffp-contract=off",
+                           "-fno-fast-math", "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"])
+    os.replace(tmp, _LIB_BENCH)
+    L_ = _load(_LIB_BENCH)
+    L_.orc_set_threads.argtypes = [C.c_int]
+    L_.orc_max_threads.restype = C.c_int
+    return L_
+
+
 class _Mat(C.Structure):
     _fields_ = [(n, C.c_double) for n in ("cp", "cv", "pi_inf", "mu", "prandtl", "omega", "g_r")]
 

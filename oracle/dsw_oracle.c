@@ -44,6 +44,7 @@
  * Build: gcc -O2 -fopenmp -ffp-contract=off (no contraction, no fast-math).
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -1525,3 +1526,9 @@ int orc_block_solve(int n, int bs, int cyclic, const real *L, const real *D, con
   free(C);
   return rc;
 }
+
+/* Threads of the OpenMP loops in the calls that follow (for timing the oracle
+ * on a given number of host cores; no effect on the results, which depend on
+ * no reduction order). */
+void orc_set_threads(int n) { omp_set_num_threads(n > 0 ? n : 1); }
+int orc_max_threads(void) { return omp_get_max_threads(); }
