@@ -192,7 +192,9 @@ int dsw_split_step_forced(dsw_grid *grid, const dsw_fields *Un, dsw_fields *Unp1
  * total elapsed time and in launches[kind] the number of launches recorded
  * since the previous read (kind 0: residual, 1: r sweep, 2: theta sweep,
  * 3: phi sweep with update, 4: copy of the Dirichlet boundary faces), then
- * clears the record. */
+ * clears the record.  If an elapsed time cannot be read (e.g. the step ran on
+ * another stream that is still busy), it returns DSW_EHIP and keeps the
+ * record and its events for a later read. */
 #define DSW_TIMING_KINDS 5
 int dsw_set_timing(dsw_grid *grid, int32_t enable);
 int dsw_read_timing(dsw_grid *grid, void *stream, double ms[DSW_TIMING_KINDS],

@@ -755,15 +755,23 @@ extern "C" int dsw_read_timing(dsw_grid *G, void *stream, double ms[DSW_TIMING_K
   if (!G || !ms || !launches) return fail(DSW_EINVAL, "null argument");
   HIPCHK(hipStreamSynchronize((hipStream_t)stream));
   for (int q = 0; q < DSW_TIMING_KINDS; q++) { ms[q] = 0.0; launches[q] = 0; }
+  // read every pair first; the events return to the free list only once all
+  // reads succeeded, and the record is left as it was otherwise (a read can
+  // fail when the step ran on another stream that is still busy)
+  double acc[DSW_TIMING_KINDS] = {0.0};
+  int64_t cnt[DSW_TIMING_KINDS] = {0};
   for (auto &r : G->recs) {
     float t = 0.0f;
     HIPCHK(hipEventElapsedTime(&t, r.a, r.b));
-    ms[r.kind] += t;
-    launches[r.kind] += 1;
+    acc[r.kind] += t;
+    cnt[r.kind] += 1;
+  }
+  for (auto &r : G->recs) {
     G->ev_free.push_back(r.a);
     G->ev_free.push_back(r.b);
   }
   G->recs.clear();
+  for (int q = 0; q < DSW_TIMING_KINDS; q++) { ms[q] = acc[q]; launches[q] = cnt[q]; }
   return DSW_OK;
 }
 
