@@ -212,7 +212,7 @@ def main():
     ap.add_argument("--calib", action="store_true",
                     help="also run a plain 1 GiB device copy (to scale hardware byte counters)")
     ap.add_argument("--config", default=None,
-                    help="launch shapes residual_block,sweep_block_r,sweep_block_theta,phi_rows_per_thread")
+                    help="launch shapes residual_block,sweep_block_r,sweep_block_theta,phi_rows_per_thread[,rows_per_thread_r,rows_per_thread_theta]")
     ap.add_argument("--ensemble", action="store_true", help="measure the batched ensemble instead")
     ap.add_argument("--members", type=int, default=64)
     ap.add_argument("--adjoint", action="store_true",
@@ -321,7 +321,8 @@ def main():
                                "10 km shell, K=3, Mach 1e-4, seeded bubble + noise",
                    "cells": cells, "K": w.K, "tau_s": tau,
                    "launch_config": dict(zip(("residual_block", "sweep_block_r", "sweep_block_theta",
-                                              "phi_rows_per_thread"), grid.get_config()))},
+                                              "phi_rows_per_thread", "rows_per_thread_r",
+                                              "rows_per_thread_theta"), grid.get_config()))},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": PEAK_HBM / 1e9,
                      "unit": "GB/s", "frac": achieved / (PEAK_HBM / 1e9), "traffic": traffic,
                      "bytes_per_launch": kstats[dom]["bytes_per_launch"],
@@ -697,7 +698,8 @@ def bench_ensemble(args):
                                "direction, 100 m horizontal, K=3, seeded", "members": len(ws),
                    "cells": cells, "K": K,
                    "launch_config": dict(zip(("residual_block", "sweep_block_r", "sweep_block_theta",
-                                              "phi_rows_per_thread"), cfg))},
+                                              "phi_rows_per_thread", "rows_per_thread_r",
+                                              "rows_per_thread_theta"), cfg))},
         "per_member": {"value": cells / (times["per_member"] * 1e-3),
                        "ms_per_step": times["per_member"]},
         "speedup_vs_per_member": times["per_member"] / ms,

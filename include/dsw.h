@@ -283,10 +283,10 @@ int dsw_adjoint_trajectory(dsw_grid *grid, const dsw_fields *ckpts, int32_t nste
                            const dsw_fields *lam_end, dsw_fields *lam_0, void *stream);
 
 /* Launch shapes of a grid's kernels (the tunable parameters; they change
- * speed, and for the phi sweep the order of rounding, never the method):
+ * speed and the order of rounding, never the method):
  *   residual_block        threads per workgroup of the residual (64, 128, 256)
- *   sweep_block_r/_theta  lines per workgroup of the r / theta sweeps
- *                         (64, 128, 256; one thread per line)
+ *   sweep_block_r/_theta  threads per workgroup of the r / theta sweeps
+ *                         (64, 128, 256)
  *   phi_rows_per_thread   phi sweep: 2 or 4 = partitioned solver, one
  *                         workgroup per line, that many rows per thread,
  *                         separators by cyclic reduction in LDS; 0 = one
@@ -296,10 +296,25 @@ int dsw_adjoint_trajectory(dsw_grid *grid, const dsw_fields *ckpts, int32_t nste
  *                         to one thread per line.  The transposed phi
  *                         solves of the adjoint take two rows per thread
  *                         wherever the line allows it.
- * Default {64, 256, 256, 4}.  dsw_set_config returns DSW_EINVAL for other
- * values. */
+ *   rows_per_thread_r/_theta
+ *                         r / theta sweeps: 4 = partitioned solver (each
+ *                         workgroup on a few neighbouring lines split into
+ *                         chunks, 4 rows per thread on the 3x3-block lines
+ *                         and 8 on the scalar ones, separators by cyclic
+ *                         reduction in LDS; no scratch memory); 0 = two
+ *                         threads per line, eliminating from both ends,
+ *                         intermediates in a scratch array.  Lines of more
+ *                         than 4 x sweep_block rows fall back to the latter.
+ *                         The transposed solves of the adjoint always take
+ *                         the latter.  Measured on the 512 x 256 x 128 full
+ *                         sphere: r 1.39 ms partitioned, 1.42 ms two-ended
+ *                         (and 2.4x fewer HBM bytes); theta 1.74 ms
+ *                         partitioned, 1.63 ms two-ended.
+ * Default {64, 256, 256, 4, 4, 0}.  dsw_set_config returns DSW_EINVAL for
+ * other values. */
 typedef struct {
   int32_t residual_block, sweep_block_r, sweep_block_theta, phi_rows_per_thread;
+  int32_t rows_per_thread_r, rows_per_thread_theta;
 } dsw_config;
 int dsw_set_config(dsw_grid *grid, const dsw_config *cfg);
 int dsw_get_config(const dsw_grid *grid, dsw_config *cfg);

@@ -7,7 +7,7 @@ from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-SRC = [os.path.join(HERE, "csrc", f) for f in ("residual.hip", "sweeps.hip", "phi_part.hip", "adjoint.hip", "api.hip")]
+SRC = [os.path.join(HERE, "csrc", f) for f in ("residual.hip", "sweeps.hip", "rt_part.hip", "phi_part.hip", "adjoint.hip", "api.hip")]
 LIB = os.path.join(HERE, "libdsw.so")
 OBJ = os.path.join(HERE, "_build")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

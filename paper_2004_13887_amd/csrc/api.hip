@@ -22,7 +22,7 @@ struct dsw_grid {
   dsw_material mat;
   Geo geo;
   Mat m;
-  Cfg cfg{64, {256, 256}, 4}; // launch shapes
+  Cfg cfg{64, {256, 256}, 4, {4, 0}}; // launch shapes
   double *tables = nullptr; // rc | rf | sc | cc | sf | cf
   Fields ub{}, ub2{}, r{}, x1{}, x2{}; // ub, ub2: midpoint states of consecutive iterations
   double *fields_mem = nullptr;
@@ -354,14 +354,18 @@ struct Pass {
   PassArgs a;
 };
 
+// the kind of an r (d = 0) or theta (d = 1) pass under a configuration
+static int rt_kind(const Geo &g, const Cfg &c, int d) {
+  if (c.rt_pm[d] > 0 && rt_part_supported(g, d, (unsigned)c.sweep_bs[d], c.rt_pm[d])) return d == 0 ? PK_SW0P : PK_SW1P;
+  const bool tw = families(g, d).nb < TWIST_LINES;
+  return d == 0 ? (tw ? PK_SW0T : PK_SW0) : (tw ? PK_SW1T : PK_SW1);
+}
+
 static Pass sweep_pass(const dsw_grid *G, int d, const Fields &ubar, double tau, const Fields &rhs,
                        const Out &o) {
   Pass p;
   if (d == 2) p.kind = phi_kind(G->geo, G->cfg);
-  else {
-    const bool tw = families(G->geo, d).nb < TWIST_LINES;
-    p.kind = d == 0 ? (tw ? PK_SW0T : PK_SW0) : (tw ? PK_SW1T : PK_SW1);
-  }
+  else p.kind = rt_kind(G->geo, G->cfg, d);
   p.tk = 1 + d;
   p.a = base_args(G);
   p.a.u = src1(ubar);
@@ -431,9 +435,11 @@ static unsigned kind_threads(int kind, const Geo &g, const Cfg &c) {
   case PK_RES_IN:
   case PK_RES_INP: return (unsigned)c.res_bs;
   case PK_SW0:
-  case PK_SW0T: return (unsigned)c.sweep_bs[0];
+  case PK_SW0T:
+  case PK_SW0P: return (unsigned)c.sweep_bs[0];
   case PK_SW1:
-  case PK_SW1T: return (unsigned)c.sweep_bs[1];
+  case PK_SW1T:
+  case PK_SW1P: return (unsigned)c.sweep_bs[1];
   case PK_SW2_PART: return phi_part_threads(g, c.phi_pm);
   default: return 128u; // boundary copy, thread-per-line phi
   }
@@ -441,7 +447,7 @@ static unsigned kind_threads(int kind, const Geo &g, const Cfg &c) {
 
 static unsigned cdiv(unsigned long a, unsigned b) { return (unsigned)((a + b - 1) / b); }
 
-static unsigned kind_blocks(int kind, const Geo &g, unsigned threads) {
+static unsigned kind_blocks(int kind, const Geo &g, const Cfg &c, unsigned threads) {
   switch (kind) {
   case PK_BND: return cdiv(bnd_points(g), threads);
   case PK_RES: return cdiv((unsigned long)g.npf, threads) * (unsigned)(g.nt + 1) * (unsigned)(g.nr + 1);
@@ -451,12 +457,15 @@ static unsigned kind_blocks(int kind, const Geo &g, unsigned threads) {
   case PK_SW1: return cdiv(sweep_lines(g, 1), threads);
   case PK_SW0T: return sweep2_blocks(g, 0, threads);
   case PK_SW1T: return sweep2_blocks(g, 1, threads);
+  case PK_SW0P: return rt_part_blocks(g, 0, threads, c.rt_pm[0]);
+  case PK_SW1P: return rt_part_blocks(g, 1, threads, c.rt_pm[1]);
   case PK_SW2_LINE: return cdiv(sweep_lines(g, 2), threads);
   default: return (unsigned)g.nr * (unsigned)g.nt; // PK_SW2_PART
   }
 }
 
 static size_t kind_lds(int kind, const Geo &g, const Cfg &c) {
+  if (kind == PK_SW0P || kind == PK_SW1P) return rt_part_lds(kind_threads(kind, g, c));
   return kind == PK_SW2_PART ? phi_part_lds(g, c.phi_pm) : 0;
 }
 
@@ -471,6 +480,8 @@ static void launch_kind(int kind, const Cfg &c, const PassArgs &a, const Batch &
   case PK_SW1: launch_sweep_pass(1, a, b, blocks, threads, st); break;
   case PK_SW0T: launch_sweep2_pass(0, a, b, blocks, threads, st); break;
   case PK_SW1T: launch_sweep2_pass(1, a, b, blocks, threads, st); break;
+  case PK_SW0P: launch_rt_pass(0, c.rt_pm[0], a, b, blocks, threads, st); break;
+  case PK_SW1P: launch_rt_pass(1, c.rt_pm[1], a, b, blocks, threads, st); break;
   case PK_SW2_LINE: launch_sweep_pass(2, a, b, blocks, threads, st); break;
   default: launch_phi_pass(c.phi_pm, a, b, blocks, threads, lds, st); break;
   }
@@ -479,7 +490,7 @@ static void launch_kind(int kind, const Cfg &c, const PassArgs &a, const Batch &
 // one pass on one grid, arguments by value
 static void launch_single(const dsw_grid *G, const Pass &p, hipStream_t st) {
   const unsigned th = kind_threads(p.kind, G->geo, G->cfg);
-  const unsigned nb = kind_blocks(p.kind, G->geo, th);
+  const unsigned nb = kind_blocks(p.kind, G->geo, G->cfg, th);
   if (nb == 0) return;  // e.g. no interior workgroups on a tiny grid
   const Batch none{nullptr, nullptr, 0};
   launch_kind(p.kind, G->cfg, p.a, none, nb, th, kind_lds(p.kind, G->geo, G->cfg), st);
@@ -689,7 +700,8 @@ extern "C" int dsw_split_step_forced(dsw_grid *G, const dsw_fields *Un, dsw_fiel
       }
       if (d < 2) {
         const unsigned bs = (unsigned)G->cfg.sweep_bs[d];
-        launch_sweep2_forced(d, p.a, sweep2_blocks(g, d, bs), bs, st);
+        if (rt_kind(g, G->cfg, d) == (d == 0 ? PK_SW0P : PK_SW1P)) launch_rt_forced(d, G->cfg.rt_pm[d], p.a, bs, st);
+        else launch_sweep2_forced(d, p.a, sweep2_blocks(g, d, bs), bs, st);
       } else {
         launch_phi_forced(pm, p.a, (unsigned)g.nr * (unsigned)g.nt, phi_part_threads(g, pm), phi_part_lds(g, pm), st);
       }
@@ -714,11 +726,15 @@ static int check_cfg(const dsw_config *c) {
     return fail(DSW_EINVAL, "block sizes must be 64, 128 or 256");
   if (c->phi_rows_per_thread != 0 && c->phi_rows_per_thread != 2 && c->phi_rows_per_thread != 4)
     return fail(DSW_EINVAL, "phi_rows_per_thread must be 0, 2 or 4");
+  auto rt_ok = [](int v) { return v == 0 || v == 4; };
+  if (!rt_ok(c->rows_per_thread_r) || !rt_ok(c->rows_per_thread_theta))
+    return fail(DSW_EINVAL, "rows_per_thread_r and rows_per_thread_theta must be 0 or 4");
   return DSW_OK;
 }
 
 static Cfg to_cfg(const dsw_config *c) {
-  return Cfg{c->residual_block, {c->sweep_block_r, c->sweep_block_theta}, c->phi_rows_per_thread};
+  return Cfg{c->residual_block, {c->sweep_block_r, c->sweep_block_theta}, c->phi_rows_per_thread,
+             {c->rows_per_thread_r, c->rows_per_thread_theta}};
 }
 
 static dsw_config from_cfg(const Cfg &c) {
@@ -727,6 +743,8 @@ static dsw_config from_cfg(const Cfg &c) {
   o.sweep_block_r = c.sweep_bs[0];
   o.sweep_block_theta = c.sweep_bs[1];
   o.phi_rows_per_thread = c.phi_pm;
+  o.rows_per_thread_r = c.rt_pm[0];
+  o.rows_per_thread_theta = c.rt_pm[1];
   return o;
 }
 
@@ -1253,7 +1271,7 @@ extern "C" int dsw_adjoint_trajectory(dsw_grid *G, const dsw_fields *ckpts, int3
 
 struct dsw_ensemble {
   std::vector<dsw_grid *> mem;
-  Cfg cfg{64, {256, 256}, 4};
+  Cfg cfg{64, {256, 256}, 4, {4, 0}};
   hipStream_t cap = nullptr, cap2 = nullptr;  // capture streams of the two lanes
   hipEvent_t fork = nullptr, stagger = nullptr, join = nullptr;
   // one launch of a batched plan
@@ -1412,7 +1430,7 @@ static int build_plan(dsw_ensemble *E, const Cfg &cfg, const dsw_fields *Un, dsw
       unsigned long total = 0;
       for (int m : who) {
         tab.push_back(per[m][q].a);
-        total += kind_blocks(kind, mem[m]->geo, th);
+        total += kind_blocks(kind, mem[m]->geo, cfg, th);
         if (total > 0x7fffffffUL) return fail(DSW_EINVAL, "ensemble too large for one launch");
         woff.push_back((unsigned)total);
       }
@@ -1460,7 +1478,8 @@ static std::vector<uint64_t> plan_key(const dsw_ensemble *E, const Cfg &cfg, con
   std::vector<uint64_t> k;
   k.push_back((uint64_t)K);
   k.push_back((uint64_t)cfg.res_bs | ((uint64_t)cfg.sweep_bs[0] << 16) |
-              ((uint64_t)cfg.sweep_bs[1] << 32) | ((uint64_t)cfg.phi_pm << 48));
+              ((uint64_t)cfg.sweep_bs[1] << 32) | ((uint64_t)cfg.phi_pm << 48) |
+              ((uint64_t)cfg.rt_pm[0] << 52) | ((uint64_t)cfg.rt_pm[1] << 56));
   for (size_t m = 0; m < E->mem.size(); m++) {
     const double *pu[10] = {Un[m].p, Un[m].ur, Un[m].ut, Un[m].uf, Un[m].T,
                             Unp1[m].p, Unp1[m].ur, Unp1[m].ut, Unp1[m].uf, Unp1[m].T};
@@ -1574,13 +1593,16 @@ extern "C" int dsw_ensemble_tune(dsw_ensemble *E, const dsw_fields *Un, dsw_fiel
   if (rc) return rc;
   if (reps < 1) return fail(DSW_EINVAL, "reps must be >= 1");
   hipStream_t st = (hipStream_t)stream;
-  // candidate v sets every tunable to its v-th value; passes are timed
-  // separately, so each pass keeps its own best value
-  const int bsz[3] = {64, 128, 256}, pms[3] = {4, 2, 0};
+  // candidate (v, p) sets every workgroup width to its v-th value, the phi
+  // solver to its v-th kind and the r and theta solvers to kind p; passes
+  // are timed separately, so each pass keeps its own best value
+  const int bsz[3] = {64, 128, 256}, pms[3] = {4, 2, 0}, rts[2] = {4, 0};
   double tbest[4] = {1e300, 1e300, 1e300, 1e300};
   Cfg out = E->cfg;
-  for (int v = 0; v < 3; v++) {
-    const Cfg c{bsz[v], {bsz[v], bsz[v]}, pms[v]};
+  for (int vp = 0; vp < 6; vp++) {
+    const int v = vp % 3, pr = rts[vp / 3];
+    if (vp >= 3 && v == 0) continue;  // the two-ended solver: 128 and 256 only
+    const Cfg c{bsz[v], {bsz[v], bsz[v]}, pms[v], {pr, pr}};
     dsw_ensemble::Plan plan;
     if ((rc = build_plan(E, c, Un, Unp1, tau, K, plan))) return rc;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev(plan.groups.size());
@@ -1604,9 +1626,9 @@ extern "C" int dsw_ensemble_tune(dsw_ensemble *E, const dsw_fields *Un, dsw_fiel
     for (auto &e : ev) { (void)hipEventDestroy(e.first); (void)hipEventDestroy(e.second); }
     free_plan(plan);
     if (t[0] < tbest[0]) { tbest[0] = t[0]; out.res_bs = c.res_bs; }
-    if (t[1] < tbest[1]) { tbest[1] = t[1]; out.sweep_bs[0] = c.sweep_bs[0]; }
-    if (t[2] < tbest[2]) { tbest[2] = t[2]; out.sweep_bs[1] = c.sweep_bs[1]; }
-    if (t[3] < tbest[3]) { tbest[3] = t[3]; out.phi_pm = c.phi_pm; }
+    if (t[1] < tbest[1]) { tbest[1] = t[1]; out.sweep_bs[0] = c.sweep_bs[0]; out.rt_pm[0] = c.rt_pm[0]; }
+    if (t[2] < tbest[2]) { tbest[2] = t[2]; out.sweep_bs[1] = c.sweep_bs[1]; out.rt_pm[1] = c.rt_pm[1]; }
+    if (vp < 3 && t[3] < tbest[3]) { tbest[3] = t[3]; out.phi_pm = c.phi_pm; }
   }
   rc = check_launch("ensemble tuning kernels");
   if (rc) return rc;

@@ -118,10 +118,12 @@ struct Cfg {
   int sweep_bs[2]; // r and theta sweeps: lines per workgroup (64, 128, 256)
   int phi_pm;      // phi sweep: 0 = one thread per line, 2 or 4 = partitioned
                    // with that many rows per thread
+  int rt_pm[2];    // r and theta sweeps: 0 = two threads per line, 4 =
+                   // partitioned (4 rows per thread on the block lines)
 };
 
 enum PassKind { PK_BND = 0, PK_RES = 1, PK_SW0 = 2, PK_SW1 = 3, PK_SW2_LINE = 4, PK_SW2_PART = 5,
-                PK_RES_IN = 6, PK_SW0T = 7, PK_SW1T = 8, PK_RES_INP = 9 };
+                PK_RES_IN = 6, PK_SW0T = 7, PK_SW1T = 8, PK_RES_INP = 9, PK_SW0P = 10, PK_SW1P = 11 };
 
 // forced split step (source term, wall velocities, Dirichlet data at the new
 // time level): one grid, the general residual over every point, the
@@ -142,6 +144,7 @@ struct WallMix {
 void launch_wall_mix(const WallMix &w, hipStream_t st);
 void launch_phi_forced(int pm, const PassArgs &a, unsigned blocks, unsigned threads, size_t lds,
                        hipStream_t st);
+void launch_rt_forced(int d, int pm, const PassArgs &a, unsigned threads, hipStream_t st);
 
 // r and theta sweeps take two threads per line (two-ended elimination) on
 // grids with fewer block lines than this; measured faster than one thread
@@ -166,6 +169,14 @@ unsigned sweep_lines(const Geo &g, int d);   // lines of all families of sweep d
 void launch_sweep2_pass(int d, const PassArgs &a, const Batch &b, unsigned blocks, unsigned threads,
                         hipStream_t st);
 unsigned sweep2_blocks(const Geo &g, int d, unsigned bs);
+// r and theta sweeps, partitioned: workgroups of bs threads, each on a few
+// neighbouring lines split into chunks (block lines, then scalar lines)
+// (pm rows per thread on the block lines: 4)
+bool rt_part_supported(const Geo &g, int d, unsigned bs, int pm);
+unsigned rt_part_blocks(const Geo &g, int d, unsigned bs, int pm);
+size_t rt_part_lds(unsigned bs);
+void launch_rt_pass(int d, int pm, const PassArgs &a, const Batch &b, unsigned blocks, unsigned threads,
+                    hipStream_t st);
 unsigned bnd_points(const Geo &g);           // boundary-normal faces
 unsigned phi_part_threads(const Geo &g, int pm);
 size_t phi_part_lds(const Geo &g, int pm);

@@ -474,4 +474,45 @@ __device__ __forceinline__ void block_store(const Geo &g, const Out &o, int a, i
   else put(o, F_UF, idx_f(g, i, j, g.periodic ? wrapk(g, k + 1) : k + 1), v[2]);
 }
 
+// zero the boundary-normal faces of x that no line of this sweep writes:
+// every block line owns a short piece of them
+template <int D>
+__device__ __forceinline__ void zero_bnd(const Geo &g, const Fields &x, int a, int b) {
+  if (D == 0) { // line (j,k): ur faces 0 (nr written as last block); ut faces 0/nt; uf faces 0/np
+    const int j = a, k = b;
+    x.ur[idx_r(g, 0, j, k)] = 0.0;
+    for (int i = 0; i < g.nr; i++) {
+      if (j == 0) x.ut[idx_t(g, i, 0, k)] = 0.0;
+      if (j == g.nt - 1) x.ut[idx_t(g, i, g.nt, k)] = 0.0;
+      if (!g.periodic && k == 0) x.uf[idx_f(g, i, j, 0)] = 0.0;
+      if (!g.periodic && k == g.np - 1) x.uf[idx_f(g, i, j, g.np)] = 0.0;
+    }
+  } else if (D == 1) { // line (i,k)
+    const int i = a, k = b;
+    x.ut[idx_t(g, i, 0, k)] = 0.0;
+    for (int j = 0; j < g.nt; j++) {
+      if (i == 0) x.ur[idx_r(g, 0, j, k)] = 0.0;
+      if (i == g.nr - 1) x.ur[idx_r(g, g.nr, j, k)] = 0.0;
+      if (!g.periodic && k == 0) x.uf[idx_f(g, i, j, 0)] = 0.0;
+      if (!g.periodic && k == g.np - 1) x.uf[idx_f(g, i, j, g.np)] = 0.0;
+    }
+  } else { // line (i,j)
+    const int i = a, j = b;
+    if (!g.periodic) x.uf[idx_f(g, i, j, 0)] = 0.0;
+    for (int k = 0; k < g.np; k++) {
+      if (i == 0) x.ur[idx_r(g, 0, j, k)] = 0.0;
+      if (i == g.nr - 1) x.ur[idx_r(g, g.nr, j, k)] = 0.0;
+      if (j == 0) x.ut[idx_t(g, i, 0, k)] = 0.0;
+      if (j == g.nt - 1) x.ut[idx_t(g, i, g.nt, k)] = 0.0;
+    }
+  }
+}
+
+template <int D, int FAM>
+__device__ __forceinline__ long scalar_index(const Geo &g, int a, int b, int s) {
+  if (D == 0) return FAM == 0 ? idx_t(g, s, a, b) : idx_f(g, s, a, b);
+  if (D == 1) return FAM == 0 ? idx_r(g, a, s, b) : idx_f(g, a, s, b);
+  return FAM == 0 ? idx_r(g, a, b, s) : idx_t(g, a, b, s);
+}
+
 } // namespace dsw

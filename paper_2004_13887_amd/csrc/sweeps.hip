@@ -22,40 +22,6 @@
 
 namespace dsw {
 
-// zero the boundary-normal faces of x that no line of this sweep writes:
-// every block line owns a short piece of them
-template <int D>
-__device__ __forceinline__ void zero_bnd(const Geo &g, const Fields &x, int a, int b) {
-  if (D == 0) { // line (j,k): ur faces 0 (nr written as last block); ut faces 0/nt; uf faces 0/np
-    const int j = a, k = b;
-    x.ur[idx_r(g, 0, j, k)] = 0.0;
-    for (int i = 0; i < g.nr; i++) {
-      if (j == 0) x.ut[idx_t(g, i, 0, k)] = 0.0;
-      if (j == g.nt - 1) x.ut[idx_t(g, i, g.nt, k)] = 0.0;
-      if (!g.periodic && k == 0) x.uf[idx_f(g, i, j, 0)] = 0.0;
-      if (!g.periodic && k == g.np - 1) x.uf[idx_f(g, i, j, g.np)] = 0.0;
-    }
-  } else if (D == 1) { // line (i,k)
-    const int i = a, k = b;
-    x.ut[idx_t(g, i, 0, k)] = 0.0;
-    for (int j = 0; j < g.nt; j++) {
-      if (i == 0) x.ur[idx_r(g, 0, j, k)] = 0.0;
-      if (i == g.nr - 1) x.ur[idx_r(g, g.nr, j, k)] = 0.0;
-      if (!g.periodic && k == 0) x.uf[idx_f(g, i, j, 0)] = 0.0;
-      if (!g.periodic && k == g.np - 1) x.uf[idx_f(g, i, j, g.np)] = 0.0;
-    }
-  } else { // line (i,j)
-    const int i = a, j = b;
-    if (!g.periodic) x.uf[idx_f(g, i, j, 0)] = 0.0;
-    for (int k = 0; k < g.np; k++) {
-      if (i == 0) x.ur[idx_r(g, 0, j, k)] = 0.0;
-      if (i == g.nr - 1) x.ur[idx_r(g, g.nr, j, k)] = 0.0;
-      if (j == 0) x.ut[idx_t(g, i, 0, k)] = 0.0;
-      if (j == g.nt - 1) x.ut[idx_t(g, i, g.nt, k)] = 0.0;
-    }
-  }
-}
-
 template <int D, bool TR>
 __device__ __forceinline__ void solve_block_line(const Geo &g, const Mat &m, const SrcOne &u, const Fields &rhs,
                                  const Out &o, double *sc, long nl, long line, int a, int b,
@@ -251,12 +217,6 @@ __device__ __forceinline__ void solve_block_cyclic(const Geo &g, const Mat &m, c
 #undef SC
 }
 
-template <int D, int FAM>
-__device__ __forceinline__ long scalar_index(const Geo &g, int a, int b, int s) {
-  if (D == 0) return FAM == 0 ? idx_t(g, s, a, b) : idx_f(g, s, a, b);
-  if (D == 1) return FAM == 0 ? idx_r(g, a, s, b) : idx_f(g, a, s, b);
-  return FAM == 0 ? idx_r(g, a, b, s) : idx_t(g, a, b, s);
-}
 
 template <int D, int FAM, bool TR>
 __device__ __forceinline__ void solve_scalar_line(const Geo &g, const Mat &m, const SrcOne &u, const Fields &rhs,
@@ -442,13 +402,14 @@ __device__ __forceinline__ void twisted_block_line(const Geo &g, const Mat &m, c
                                    const Out &o, double *sc, long nl, long line, bool act, bool top,
                                    int a, int b, int n, double hs, double *lds, int lane, int *status) {
 #define SC(s, q) sc[((long)(s) * 12 + (q)) * nl + line]
+  constexpr int UNR = (D == 1 && !S::WALL) ? 2 : 1;  // theta lines: unrolled twice
   const int mid = n / 2;
   BRow R;
   double C[9], y[3], Ap[9], Ai[9], t9[9], t3[3];
   double *my = lds + (long)lane * 15;  // E'_{m+1} (9), z_{m+1} (3), x_m (3)
   if (act) {
     if (top) {
-      #pragma unroll (D == 1 && !S::WALL ? 2 : 1)
+      #pragma unroll UNR
       for (int s = 0; s < mid; s++) {
         block_row<D>(g, m, u, rhs, a, b, s, n, 0, hs, R);
         if (s == 0) {
@@ -474,7 +435,7 @@ __device__ __forceinline__ void twisted_block_line(const Geo &g, const Mat &m, c
         for (int q = 0; q < 3; q++) SC(s, 9 + q) = y[q];
       }
     } else {
-      #pragma unroll (D == 1 && !S::WALL ? 2 : 1)
+      #pragma unroll UNR
       for (int s = n - 1; s > mid; s--) {
         block_row<D>(g, m, u, rhs, a, b, s, n, 0, hs, R);
         if (s == n - 1) {
@@ -535,7 +496,7 @@ __device__ __forceinline__ void twisted_block_line(const Geo &g, const Mat &m, c
   if (!act) return;
   double x[3] = {my[12], my[13], my[14]};
   if (top) {
-    #pragma unroll (D == 1 && !S::WALL ? 2 : 1)
+    #pragma unroll UNR
     for (int s = mid - 1; s >= 0; s--) {
 #pragma unroll
       for (int q = 0; q < 9; q++) C[q] = SC(s, q);
@@ -546,7 +507,7 @@ __device__ __forceinline__ void twisted_block_line(const Geo &g, const Mat &m, c
       block_store<D>(g, o, a, b, s, x);
     }
   } else {
-    #pragma unroll (D == 1 && !S::WALL ? 2 : 1)
+    #pragma unroll UNR
     for (int s = mid + 1; s < n; s++) {
 #pragma unroll
       for (int q = 0; q < 9; q++) C[q] = SC(s, q);
@@ -727,6 +688,7 @@ __device__ __forceinline__ void twisted_scalar_line(const Geo &g, const Mat &m, 
   int ofid;
   if (D == 0) ofid = FAM == 0 ? F_UT : F_UF;
   else ofid = FAM == 0 ? F_UR : F_UF;
+  constexpr int UNR = (D == 1 && !S::WALL) ? 2 : 1;
   const int mid = n / 2;
   double *my = lds + (long)lane * 15;
   SRow R;
@@ -735,7 +697,7 @@ __device__ __forceinline__ void twisted_scalar_line(const Geo &g, const Mat &m, 
   double cv = 0.0, yv = 0.0;
   if (act) {
     if (top) {
-      #pragma unroll (D == 1 && !S::WALL ? 2 : 1)
+      #pragma unroll UNR
       for (int s = 0; s < mid; s++) {
         scalar_row<D, FAM>(g, m, u, rhs, a, b, s, n, 0, hs, R, xi, arr);
         const double den = R.b - R.a * cv;
@@ -747,7 +709,7 @@ __device__ __forceinline__ void twisted_scalar_line(const Geo &g, const Mat &m, 
         SC(s, 1) = yv;
       }
     } else {
-      #pragma unroll (D == 1 && !S::WALL ? 2 : 1)
+      #pragma unroll UNR
       for (int s = n - 1; s > mid; s--) {
         scalar_row<D, FAM>(g, m, u, rhs, a, b, s, n, 0, hs, R, xi, arr);
         const double den = R.b - R.c * cv;
@@ -775,13 +737,13 @@ __device__ __forceinline__ void twisted_scalar_line(const Geo &g, const Mat &m, 
   if (!act) return;
   double x = my[2];
   if (top) {
-    #pragma unroll (D == 1 && !S::WALL ? 2 : 1)
+    #pragma unroll UNR
     for (int s = mid - 1; s >= 0; s--) {
       x = SC(s, 1) - SC(s, 0) * x;
       put(o, ofid, scalar_index<D, FAM>(g, a, b, s), x);
     }
   } else {
-    #pragma unroll (D == 1 && !S::WALL ? 2 : 1)
+    #pragma unroll UNR
     for (int s = mid + 1; s < n; s++) {
       x = SC(s, 1) - SC(s, 0) * x;
       put(o, ofid, scalar_index<D, FAM>(g, a, b, s), x);

@@ -67,11 +67,12 @@ class Wall(C.Structure):
 
 class Config(C.Structure):
     _fields_ = [("residual_block", C.c_int32), ("sweep_block_r", C.c_int32),
-                ("sweep_block_theta", C.c_int32), ("phi_rows_per_thread", C.c_int32)]
+                ("sweep_block_theta", C.c_int32), ("phi_rows_per_thread", C.c_int32),
+                ("rows_per_thread_r", C.c_int32), ("rows_per_thread_theta", C.c_int32)]
 
     def astuple(self):
         return (self.residual_block, self.sweep_block_r, self.sweep_block_theta,
-                self.phi_rows_per_thread)
+                self.phi_rows_per_thread, self.rows_per_thread_r, self.rows_per_thread_theta)
 
 
 class LayoutInfo(C.Structure):
@@ -323,8 +324,9 @@ class Grid:
         return DSW_OK
 
     def set_config(self, residual_block=64, sweep_block_r=256, sweep_block_theta=256,
-                   phi_rows_per_thread=4):
-        c = Config(residual_block, sweep_block_r, sweep_block_theta, phi_rows_per_thread)
+                   phi_rows_per_thread=4, rows_per_thread_r=4, rows_per_thread_theta=0):
+        c = Config(residual_block, sweep_block_r, sweep_block_theta, phi_rows_per_thread,
+                   rows_per_thread_r, rows_per_thread_theta)
         _check(lib().dsw_set_config(self._h, C.byref(c)))
 
     def get_config(self):
@@ -385,8 +387,9 @@ class Ensemble:
         return c.astuple()
 
     def set_config(self, residual_block=64, sweep_block_r=256, sweep_block_theta=256,
-                   phi_rows_per_thread=4):
-        c = Config(residual_block, sweep_block_r, sweep_block_theta, phi_rows_per_thread)
+                   phi_rows_per_thread=4, rows_per_thread_r=4, rows_per_thread_theta=0):
+        c = Config(residual_block, sweep_block_r, sweep_block_theta, phi_rows_per_thread,
+                   rows_per_thread_r, rows_per_thread_theta)
         _check(lib().dsw_ensemble_set_config(self._h, C.byref(c)))
 
     def get_config(self):

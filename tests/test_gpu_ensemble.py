@@ -146,7 +146,8 @@ def test_graph_replays_and_ping_pong(dsw):
 def test_configs_give_oracle_parity(dsw):
     """every launch shape the autotuner may pick, on a single grid"""
     ws = small_members()
-    for cfg in ((64, 128, 128, 4), (128, 64, 256, 2), (256, 256, 64, 0)):
+    for cfg in ((64, 128, 128, 4, 4, 4), (128, 64, 256, 2, 4, 0), (256, 256, 64, 0, 0, 4),
+                (64, 256, 128, 4, 0, 0)):
         for m in (1, 3, 2):
             w = ws[m]
             g = dsw.Grid.from_spec(w.grid, w.material)
@@ -171,7 +172,13 @@ def test_bad_config_rejected(dsw):
         g.set_config(96, 128, 128, 4)
     with pytest.raises(dsw.DswError):
         g.set_config(64, 128, 128, 3)
-    assert g.get_config() == (64, 256, 256, 4)
+    with pytest.raises(dsw.DswError):
+        g.set_config(64, 128, 128, 4, 2, 4)
+    with pytest.raises(dsw.DswError):
+        g.set_config(64, 128, 128, 4, 4, 8)
+    with pytest.raises(dsw.DswError):
+        g.set_config(64, 128, 128, 4, 8, 0)
+    assert g.get_config() == (64, 256, 256, 4, 4, 0)
 
 
 def test_autotuner_then_bitwise_member_equality(dsw):
@@ -182,7 +189,7 @@ def test_autotuner_then_bitwise_member_equality(dsw):
     cfg = E.ensemble_tune(dU0, out, taus, K, reps=1)
     print("[ensemble] tuned config", cfg, flush=True)
     assert cfg[0] in (64, 128, 256) and cfg[1] in (64, 128, 256) and cfg[2] in (64, 128, 256)
-    assert cfg[3] in (0, 2, 4)
+    assert cfg[3] in (0, 2, 4) and cfg[4] in (0, 4) and cfg[5] in (0, 4)
     assert E.get_config() == cfg
     assert all(g.get_config() == cfg for g in E.members)
     E.ensemble_step(dU0, out, taus, K)

@@ -83,12 +83,18 @@ def test_residual_parity(name, dsw):
     assert max(e1.values()) <= TOL and max(e2.values()) <= TOL
 
 
-@pytest.mark.parametrize("d", [0, 1, 2])
+# (direction, r/theta solver): 4 the partitioned solver (the default), 0 the
+# two-ended one; the phi sweep has its own
+SOLVERS = [(0, 4), (0, 0), (1, 4), (1, 0), (2, 4)]
+
+
+@pytest.mark.parametrize("d,rt", SOLVERS)
 @pytest.mark.parametrize("name", list(CASES))
-def test_line_solve_parity(name, d, dsw):
+def test_line_solve_parity(name, d, rt, dsw):
     w = CASES[name]
-    print(f"[line_solve d={d}] {name}", flush=True)
+    print(f"[line_solve d={d} rt={rt}] {name}", flush=True)
     U0, tau, og, om, gg = _setup(w, dsw)
+    gg.set_config(rows_per_thread_r=rt, rows_per_thread_theta=rt)
     rhs = I.random_fields(w.grid, 11 + d)
     x_o = oracle.line_solve(og, om, U0, tau, d, rhs)
     x = gg.empty()
@@ -101,11 +107,13 @@ def test_line_solve_parity(name, d, dsw):
     assert max(e.values()) <= TOL
 
 
+@pytest.mark.parametrize("rt", [4, 0])
 @pytest.mark.parametrize("name", list(CASES))
-def test_split_step_parity(name, dsw):
+def test_split_step_parity(name, rt, dsw):
     w = CASES[name]
-    print(f"[split_step] {name} K={w.K}", flush=True)
+    print(f"[split_step rt={rt}] {name} K={w.K}", flush=True)
     U0, tau, og, om, gg = _setup(w, dsw)
+    gg.set_config(rows_per_thread_r=rt, rows_per_thread_theta=rt)
     U1_o = oracle.split_step(og, om, U0, tau, w.K)
     dU0 = dsw.to_device(U0)
     dU1 = gg.empty()
