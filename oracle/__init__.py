@@ -109,9 +109,14 @@ def _load(path):
     L_.orc_line_solve_some.argtypes = [P, MP, FP, WP, D, I, L, C.c_void_p, C.c_void_p,
                                          C.c_void_p, FP, FP]
     L_.orc_block_solve.argtypes = [I, I, I, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
+    L_.orc_split_step_pert.argtypes = [P, MP, C.c_void_p, C.c_void_p, FP, FP, D, I]
     for f in ("orc_block_solve", "orc_apply", "orc_residual", "orc_line_solve", "orc_line_matvec",
-              "orc_line_blocks", "orc_split_step", "orc_residual_at", "orc_line_solve_some"):
+              "orc_line_blocks", "orc_split_step", "orc_residual_at", "orc_line_solve_some",
+              "orc_split_step_pert"):
         getattr(L_, f).restype = I
+    if hasattr(L_, "orc_courant"):
+        L_.orc_courant.argtypes = [P, MP, FP, D, C.c_void_p]
+        L_.orc_courant.restype = None
     return L_
 
 
@@ -298,6 +303,33 @@ def split_step(g: Grid, mat: Material, Un, tau, K, wall0=None, wall1=None, src=N
     if rc != 0:
         raise ArithmeticError("zero pivot in a line solve")
     return out
+
+
+def split_step_pert(g: Grid, mat: Material, Un, pbar, Tbar, tau, K):
+    """The split step on the perturbation-pressure state: Un["p"] holds
+    p - pbar(r) for the discretely hydrostatic reference column (pbar, Tbar)
+    at the cell centres (see orc_split_step_pert); returns the same form."""
+    keep = []
+    out = g.zeros()
+    m = mat.c()
+    pb = np.ascontiguousarray(pbar, dtype=np.float64)
+    tb = np.ascontiguousarray(Tbar, dtype=np.float64)
+    assert pb.shape == (g.nr,) and tb.shape == (g.nr,)
+    rc = lib().orc_split_step_pert(g._h, C.byref(m), pb.ctypes.data, tb.ctypes.data,
+                                   _fields(g, Un, keep), _fields(g, out, keep), float(tau), int(K))
+    if rc != 0:
+        raise ArithmeticError("zero pivot in a line solve")
+    return out
+
+
+def courant(g: Grid, mat: Material, U, tau):
+    """(advective, acoustic) Courant numbers of U for the step tau (see
+    orc_courant)."""
+    keep = []
+    m = mat.c()
+    out = np.zeros(2)
+    lib().orc_courant(g._h, C.byref(m), _fields(g, U, keep), float(tau), out.ctypes.data)
+    return float(out[0]), float(out[1])
 
 
 def residual_at(g: Grid, mat: Material, Un, Uk, Ubar, tau, fids, idx, wall=None):

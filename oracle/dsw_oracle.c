@@ -1433,6 +1433,149 @@ int orc_split_step(const orc_grid *g, const orc_mat *m, const orc_fields *Un, or
   return rc ? -1 : 0;
 }
 
+/* ------------------------------------ perturbation-pressure form (f4) -- */
+
+/* Paper section 3.1 (remark after Table 3): with a large background pressure
+ * p0 the errors of the pressure derivatives scale with p0, and the pressure
+ * has to be rescaled a priori.  Here the state carries p' = p - pbar(r)
+ * instead of p, for a reference column (pbar_i, Tbar_i) at the cell centres
+ * that is discretely hydrostatic under the radial momentum row at rest:
+ *   (pbar_f - pbar_{f-1}) / dr + g_r (rhobar_{f-1} + rhobar_f) / 2 = 0,
+ *   rhobar_i = (pbar_i + pi_inf) / (R Tbar_i),   R = c_p - c_v.
+ * The step is the same scheme with that balance subtracted analytically:
+ *   - every coefficient (density, P, chi) sees the full p' + pbar;
+ *   - the radial row's pressure gradient plus gravity,
+ *       (p_f - p_{f-1}) / (rho_f dr) + g_r,
+ *     reads (p'_f - p'_{f-1}) / (rho_f dr) + g_r (rho_f - rhobar_f) / rho_f,
+ *     with rho_i - rhobar_i = (p'_i Tbar_i - (pbar_i + pi_inf)(T_i - Tbar_i))
+ *     / (R T_i Tbar_i) formed without a difference of large numbers;
+ *   - the advection of p gains the reference gradient, u_r (pbar_{i+1} -
+ *     pbar_{i-1}) / (2 dr), with the copy ghosts of p at the r walls;
+ *   - theta and phi differences of p are those of p' (pbar depends on r only).
+ * In exact arithmetic this is orc_split_step on p = p' + pbar.  Plain walls,
+ * no source term. */
+static real drho_ref(const orc_grid *g, const orc_mat *m, const double *pbar, const double *Tbar,
+                     const orc_fields *U, int i, int j, int k) {
+  long x = IC(g, i, j, k);
+  real T = U->T[x];
+  return (U->p[x] * Tbar[i] - (pbar[i] + m->pi_inf) * (T - Tbar[i])) / ((m->cp - m->cv) * T * Tbar[i]);
+}
+
+/* R for the perturbation state: Un, Uk and Ub carry p'; Uf receives the full
+ * midpoint (p' + pbar) that the line solves take as coefficients. */
+static void residual_pert(const orc_grid *g, const orc_mat *m, const double *pbar, const double *Tbar,
+                          const orc_fields *Un, const orc_fields *Uk, double tau, orc_fields *R,
+                          orc_fields *Ub, orc_fields *Uf) {
+  const real *un[5] = {Un->p, Un->ur, Un->ut, Un->uf, Un->T};
+  const real *uk[5] = {Uk->p, Uk->ur, Uk->ut, Uk->uf, Uk->T};
+  real *ub[5] = {Ub->p, Ub->ur, Ub->ut, Ub->uf, Ub->T};
+  real *uf[5] = {Uf->p, Uf->ur, Uf->ut, Uf->uf, Uf->T};
+  for (int q = 0; q < 5; q++) {
+    long n = fsize(g, q);
+    for (long x = 0; x < n; x++) ub[q][x] = 0.5 * (uk[q][x] + un[q][x]);
+    memcpy(uf[q], ub[q], sizeof(real) * n);
+  }
+  for (int i = 0; i < g->nr; i++)
+    for (int j = 0; j < g->nt; j++)
+      for (int k = 0; k < g->np; k++) Uf->p[IC(g, i, j, k)] += pbar[i];
+  orc_fields F;
+  alloc_fields(g, &F);
+  orc_apply(g, m, Uf, NULL, Ub, NULL, MALL, &F); /* coefficients of the full state, operand p' */
+  opnd u = mk_opnd(Uf, NULL);
+  real *rr[5] = {R->p, R->ur, R->ut, R->uf, R->T};
+  for (int q = 0; q < 5; q++) memset(rr[q], 0, sizeof(real) * fsize(g, q));
+  for (int i = 0; i < g->nr; i++) {
+    double dpb = (pbar[i + 1 < g->nr ? i + 1 : g->nr - 1] - pbar[i > 0 ? i - 1 : 0]) / (2.0 * g->dr);
+    for (int j = 0; j < g->nt; j++)
+      for (int k = 0; k < g->np; k++) {
+        long x = IC(g, i, j, k);
+        real Fp = F.p[x] + urc(g, &u, i, j, k) * dpb;
+        R->p[x] = -(uk[FP][x] - un[FP][x]) - tau * Fp;
+        R->T[x] = -(uk[FTT][x] - un[FTT][x]) - tau * F.T[x];
+      }
+  }
+  for (int f = 1; f < g->nr; f++)
+    for (int j = 0; j < g->nt; j++)
+      for (int k = 0; k < g->np; k++) {
+        long x = IR(g, f, j, k);
+        real rho_f = 0.5 * (rho_c(g, m, &u, f - 1, j, k) + rho_c(g, m, &u, f, j, k));
+        real drho_f = 0.5 * (drho_ref(g, m, pbar, Tbar, Ub, f - 1, j, k) + drho_ref(g, m, pbar, Tbar, Ub, f, j, k));
+        real Fx = F.ur[x] + m->g_r * drho_f / rho_f;
+        R->ur[x] = -(uk[FR][x] - un[FR][x]) - tau * Fx;
+      }
+  for (int i = 0; i < g->nr; i++)
+    for (int f = 1; f < g->nt; f++)
+      for (int k = 0; k < g->np; k++) {
+        long x = IT(g, i, f, k);
+        R->ut[x] = -(uk[FT][x] - un[FT][x]) - tau * F.ut[x];
+      }
+  for (int i = 0; i < g->nr; i++)
+    for (int j = 0; j < g->nt; j++)
+      for (int f = uf_lo(g); f <= uf_hi(g); f++) {
+        long x = IF(g, i, j, f);
+        R->uf[x] = -(uk[FF][x] - un[FF][x]) - tau * F.uf[x];
+      }
+  free_fields(&F);
+}
+
+int orc_split_step_pert(const orc_grid *g, const orc_mat *m, const double *pbar, const double *Tbar,
+                        const orc_fields *Un, orc_fields *Unp1, double tau, int K) {
+  orc_fields Uk, R, Ub, Uf, X1, X2, X3;
+  alloc_fields(g, &Uk); alloc_fields(g, &R); alloc_fields(g, &Ub); alloc_fields(g, &Uf);
+  alloc_fields(g, &X1); alloc_fields(g, &X2); alloc_fields(g, &X3);
+  const real *un[5] = {Un->p, Un->ur, Un->ut, Un->uf, Un->T};
+  real *uk[5] = {Uk.p, Uk.ur, Uk.ut, Uk.uf, Uk.T};
+  for (int q = 0; q < 5; q++) memcpy(uk[q], un[q], sizeof(real) * fsize(g, q));
+  int rc = 0;
+  for (int it = 0; it < K && !rc; it++) {
+    residual_pert(g, m, pbar, Tbar, Un, &Uk, tau, &R, &Ub, &Uf);
+    rc |= orc_line_solve(g, m, &Uf, NULL, tau, 0, &R, &X1);
+    rc |= orc_line_solve(g, m, &Uf, NULL, tau, 1, &X1, &X2);
+    rc |= orc_line_solve(g, m, &Uf, NULL, tau, 2, &X2, &X3);
+    real *x3[5] = {X3.p, X3.ur, X3.ut, X3.uf, X3.T};
+    for (int q = 0; q < 5; q++) {
+      long n = fsize(g, q);
+      for (long x = 0; x < n; x++) uk[q][x] += x3[q][x];
+    }
+  }
+  real *out[5] = {Unp1->p, Unp1->ur, Unp1->ut, Unp1->uf, Unp1->T};
+  for (int q = 0; q < 5; q++) memcpy(out[q], uk[q], sizeof(real) * fsize(g, q));
+  free_fields(&Uk); free_fields(&R); free_fields(&Ub); free_fields(&Uf);
+  free_fields(&X1); free_fields(&X2); free_fields(&X3);
+  return rc ? -1 : 0;
+}
+
+#ifndef ORC_COMPLEX_STEP
+/* Courant numbers of a state for the step tau (for a time-step controller:
+ * the paper's section 3.2 discussion of Thermal 1 calls for small or adaptive
+ * time steps once the bubble accelerates).  At every cell centre, with the
+ * centre-averaged velocity and the local spacings h_r = dr,
+ * h_t = r dtheta, h_f = r sin(theta) dphi:
+ *   advective  tau (|u_r| / h_r + |u_theta| / h_t + |u_phi| / h_f)
+ *   acoustic   tau c max(1/h_r, 1/h_t, 1/h_f),  c = sqrt(gamma R T)
+ *              (the sound speed of the stiffened gas, c^2 = gamma (p + pi_inf) / rho);
+ * out[0], out[1] = their maxima over the cells. */
+void orc_courant(const orc_grid *g, const orc_mat *m, const orc_fields *U, double tau, double *out) {
+  opnd u = mk_opnd(U, NULL);
+  double gam = m->cp / m->cv, Rg = m->cp - m->cv, ca = 0.0, cs = 0.0;
+  for (int i = 0; i < g->nr; i++)
+    for (int j = 0; j < g->nt; j++)
+      for (int k = 0; k < g->np; k++) {
+        double hr = g->dr, ht = g->rc[i] * g->dt, hf = g->rc[i] * g->sc[j] * g->dp;
+        double a = tau * (fabs(urc(g, &u, i, j, k)) / hr + fabs(utc(g, &u, i, j, k)) / ht +
+                          fabs(ufc(g, &u, i, j, k)) / hf);
+        double ih = 1.0 / hr;
+        if (1.0 / ht > ih) ih = 1.0 / ht;
+        if (1.0 / hf > ih) ih = 1.0 / hf;
+        double c = tau * sqrt(gam * Rg * U->T[IC(g, i, j, k)]) * ih;
+        if (a > ca) ca = a;
+        if (c > cs) cs = c;
+      }
+  out[0] = ca;
+  out[1] = cs;
+}
+#endif
+
 /* residual values at a list of sample points only (for full-size checks of a
  * GPU residual without a full oracle pass).  fids/idx: npts entries; Ub must
  * already hold the midpoint state (ghost data wall).  out: R at each point. */

@@ -212,6 +212,23 @@ def hydrostatic_pressure(g: GridSpec, mat: MaterialSpec, T_bg: float = T0):
     return p
 
 
+def reference_column(g: GridSpec, mat: MaterialSpec, T_bar, p_top=None):
+    """A discretely hydrostatic reference column (p_bar, T_bar) at the cell
+    centres for the perturbation-pressure form: the radial momentum row at
+    rest, (p_i - p_{i-1}) / dr + g (rho_{i-1} + rho_i) / 2 = 0 with
+    rho = (p + pi_inf) / (R T), solved upward for p_i from
+    p_0 = p00 exp(-g dr / (2 R T_0)) (or p_top given for the first centre).
+    T_bar: a scalar or nr values."""
+    dr = (g.r2 - g.r1) / g.nr
+    T = np.broadcast_to(np.asarray(T_bar, dtype=np.float64), (g.nr,)).copy()
+    a = mat.g_r * dr / (2.0 * mat.R * T)
+    p = np.empty(g.nr)
+    p[0] = P00 * math.exp(-a[0]) if p_top is None else float(p_top)
+    for i in range(1, g.nr):
+        p[i] = (p[i - 1] * (1.0 - a[i - 1]) - mat.pi_inf * (a[i - 1] + a[i])) / (1.0 + a[i])
+    return p, T
+
+
 def time_step(w: Workload, T_max: float) -> float:
     """tau at the workload's acoustic CFL number: cfl * d_min / c_max, with
     d_min = min(dr, r1 dtheta, r1 sin(theta_min) dphi) over cell centres."""
