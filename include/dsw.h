@@ -186,6 +186,47 @@ int dsw_split_step_forced(dsw_grid *grid, const dsw_fields *Un, dsw_fields *Unp1
                           int32_t K, const dsw_fields *src, const dsw_wall *wall0,
                           const dsw_wall *wall1, const dsw_fields *bnd, void *stream);
 
+/* Perturbation-pressure form (paper section 3.1, the remark after Table 3:
+ * with a large background pressure the errors of the pressure derivatives
+ * scale with it, and the pressure is rescaled a priori).  The state's p
+ * array holds p' = p - p_ref(r) instead of p, for a reference column
+ * (p_ref_i, T_ref_i) at the cell centres that is discretely hydrostatic under
+ * the radial momentum row at rest:
+ *   (p_ref_i - p_ref_{i-1}) / dr + g_r (rho_ref_{i-1} + rho_ref_i) / 2 = 0,
+ *   rho_ref_i = (p_ref_i + pi_inf) / ((c_p - c_v) T_ref_i).
+ * dsw_split_step_pert computes the step of dsw_split_step with that balance
+ * subtracted analytically: coefficients see p' + p_ref; the radial row's
+ * pressure gradient plus gravity is the gradient of p' plus the buoyancy
+ * g_r (rho_f - rho_ref_f) / rho_f, formed without a difference of large
+ * numbers; the advection of p gains u_r d p_ref / dr.  In exact arithmetic
+ * it equals dsw_split_step on p = p' + p_ref; in FP64 the pressure change
+ * keeps its relative precision at any background pressure, and a fluid at
+ * rest in an isothermal reference column stays exactly at rest.
+ *   dsw_set_reference  p_ref, T_ref: host arrays of n_r doubles (copied; the
+ *                      caller keeps them).  The discrete balance above is the
+ *                      caller's to satisfy: the step subtracts it as if
+ *                      exact.  DSW_EINVAL if p_ref + pi_inf or T_ref is not
+ *                      positive and finite; DSW_ENOMEM.
+ *   dsw_split_step_pert  Un, Unp1 as for dsw_split_step, p fields in the
+ *                      perturbation form; DSW_EINVAL before a reference is
+ *                      set.  Plain walls (no forcing); timed like
+ *                      dsw_split_step when timing is enabled. */
+int dsw_set_reference(dsw_grid *grid, const double *p_ref, const double *T_ref);
+int dsw_split_step_pert(dsw_grid *grid, const dsw_fields *Un, dsw_fields *Unp1, double tau, int32_t K,
+                        void *stream);
+
+/* Courant numbers of a state for a step tau, for a time-step controller
+ * (paper section 3.2: once the Thermal 1 bubble accelerates, the step must
+ * shrink or adapt).  At every cell centre, with the centre-averaged
+ * velocity and the spacings h_r = dr, h_t = r dtheta, h_f = r sin(theta) dphi:
+ *   out[0] = max tau (|u_r| / h_r + |u_theta| / h_t + |u_phi| / h_f)  (advective)
+ *   out[1] = max tau c max(1/h_r, 1/h_t, 1/h_f), c = sqrt(gamma R T) (acoustic).
+ * U: device state (the p field is not read, so either pressure form works);
+ * out: host, 2 doubles.  Synchronises the stream.  The first call allocates
+ * 16 bytes of device memory kept with the grid.  DSW_EINVAL for null
+ * arguments or tau <= 0. */
+int dsw_courant(dsw_grid *grid, const dsw_fields *U, double tau, double out[2], void *stream);
+
 /* Optional per-kernel timing of dsw_split_step.  While enabled, every kernel
  * the step enqueues is bracketed by a pair of HIP events recorded on the same
  * stream.  dsw_read_timing synchronises that stream, stores in ms[kind] the

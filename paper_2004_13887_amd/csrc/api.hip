@@ -30,6 +30,8 @@ struct dsw_grid {
   double *scratch_mem = nullptr;
   double *adj_mem = nullptr; // adjoint workspace, allocated on first use
   double *fwall_mem = nullptr; // forced step: mean and change of the wall data, on first use
+  double *ref_mem = nullptr;   // perturbation form: reference pressure | temperature [2 nr]
+  unsigned long long *cour_mem = nullptr; // Courant maxima, on first use
   int adj_states = 0;         // five-field states it holds
   // the adjoint's second stream (non-blocking, default priority), its
   // fork/join events and the sweep scratch of the work it runs
@@ -218,6 +220,8 @@ extern "C" int dsw_init_grid(const dsw_grid_desc *desc, const dsw_material *mat,
   g.irc = t + o_irc; g.irf = t + o_irf; g.isc = t + o_isc; g.ctc = t + o_ctc; g.isf = t + o_isf;
   g.ctf = t + o_ctf;
   g.scx = t + o_scx;
+  g.pref = nullptr;  // the plain form; dsw_split_step_pert passes the reference
+  g.tref = nullptr;
   Mat &m = G->m;
   m.gam = mat->cp / mat->cv;
   m.Rg = mat->cp - mat->cv;
@@ -269,6 +273,8 @@ extern "C" int dsw_free_grid(dsw_grid *G) {
   if (G->scratch_mem) (void)hipFree(G->scratch_mem);
   if (G->adj_mem) (void)hipFree(G->adj_mem);
   if (G->fwall_mem) (void)hipFree(G->fwall_mem);
+  if (G->ref_mem) (void)hipFree(G->ref_mem);
+  if (G->cour_mem) (void)hipFree(G->cour_mem);
   if (G->side) (void)hipStreamDestroy(G->side);
   if (G->fork_ev) (void)hipEventDestroy(G->fork_ev);
   if (G->join_ev) (void)hipEventDestroy(G->join_ev);
@@ -556,6 +562,59 @@ extern "C" int dsw_split_step(dsw_grid *G, const dsw_fields *Un, dsw_fields *Unp
     q = e;
   }
   return check_launch("split step kernels");
+}
+
+extern "C" int dsw_set_reference(dsw_grid *G, const double *p_ref, const double *T_ref) {
+  if (!G || !p_ref || !T_ref) return fail(DSW_EINVAL, "null argument");
+  const int nr = G->geo.nr;
+  for (int i = 0; i < nr; i++) {
+    if (!std::isfinite(p_ref[i]) || !(T_ref[i] > 0.0) || !std::isfinite(T_ref[i]) ||
+        !(p_ref[i] + G->m.pinf > 0.0))
+      return fail(DSW_EINVAL, "reference column: p_ref + pi_inf and T_ref must be positive and finite (row " +
+                                  std::to_string(i) + ")");
+  }
+  if (!G->ref_mem && hipMalloc(&G->ref_mem, 2 * (size_t)nr * sizeof(double)) != hipSuccess) {
+    G->ref_mem = nullptr;
+    return fail(DSW_ENOMEM, "reference column");
+  }
+  HIPCHK(hipMemcpy(G->ref_mem, p_ref, nr * sizeof(double), hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(G->ref_mem + nr, T_ref, nr * sizeof(double), hipMemcpyHostToDevice));
+  return DSW_OK;
+}
+
+extern "C" int dsw_split_step_pert(dsw_grid *G, const dsw_fields *Un, dsw_fields *Unp1, double tau,
+                                   int32_t K, void *stream) {
+  if (!G) return fail(DSW_EINVAL, "null handle");
+  const int rc = check_step_args(Un, Unp1, tau, K);
+  if (rc) return rc;
+  if (!G->ref_mem) return fail(DSW_EINVAL, "perturbation step: no reference column (dsw_set_reference)");
+  hipStream_t st = (hipStream_t)stream;
+  const double *pref = G->ref_mem, *tref = G->ref_mem + G->geo.nr;
+  plan_step(G, own_work(G), F(Un), F(Unp1), tau, K, [&](const Pass &p) {
+    Pass q = p;
+    q.a.g.pref = pref;
+    q.a.g.tref = tref;
+    timed(G, q.tk, st, [&] { launch_single(G, q, st); });
+  });
+  return check_launch("perturbation split step kernels");
+}
+
+extern "C" int dsw_courant(dsw_grid *G, const dsw_fields *U, double tau, double out[2], void *stream) {
+  if (!G || !out) return fail(DSW_EINVAL, "null argument");
+  int rc;
+  if ((rc = check_fields(U, "U"))) return rc;
+  if (!(tau > 0.0)) return fail(DSW_EINVAL, "tau must be > 0");
+  if (!G->cour_mem && hipMalloc(&G->cour_mem, 2 * sizeof(unsigned long long)) != hipSuccess) {
+    G->cour_mem = nullptr;
+    return fail(DSW_ENOMEM, "Courant maxima");
+  }
+  hipStream_t st = (hipStream_t)stream;
+  launch_courant(G->geo, G->m, F(U), tau, G->cour_mem, st);
+  unsigned long long h[2];
+  HIPCHK(hipMemcpyAsync(h, G->cour_mem, sizeof(h), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  std::memcpy(out, h, sizeof(h));
+  return check_launch("Courant kernel");
 }
 
 // the workspace of one split step carved from the allocation-free array

@@ -28,6 +28,9 @@ struct Geo {
   const double *isc, *ctc; // 1/sin, cot at centres
   const double *isf, *ctf; // 1/sin, cot at faces (0 at a pole face: never used there)
   const double *scx;       // sin of theta at centres j = -1 .. nt (ghosts included), at scx[j + 1]
+  // perturbation-pressure form (null: off): the state's p is p - pref(r), for
+  // a discretely hydrostatic reference column pref, tref at the centres [nr]
+  const double *pref, *tref;
 };
 
 struct Mat {
@@ -229,9 +232,15 @@ __device__ __forceinline__ double gF(const Geo &g, const S &s, int i, int j, int
   return sg * s.ld(F_UF, idx_f(g, i, j, f));
 }
 
+// the reference pressure at centre row i (ghost rows copy the nearest), 0
+// when the state holds the full pressure
+__device__ __forceinline__ double pref_at(const Geo &g, int i) {
+  return g.pref ? g.pref[clampi(i, 0, g.nr - 1)] : 0.0;
+}
+
 template <class S>
 __device__ __forceinline__ double rho_at(const Geo &g, const Mat &m, const S &s, int i, int j, int k) {
-  return (gC(g, s, F_P, i, j, k) + m.pinf) / (m.Rg * gC(g, s, F_T, i, j, k));
+  return (gC(g, s, F_P, i, j, k) + pref_at(g, i) + m.pinf) / (m.Rg * gC(g, s, F_T, i, j, k));
 }
 
 // Coefficient fields at a centre: centre-averaged velocities, thermodynamic
@@ -265,7 +274,7 @@ __device__ __forceinline__ void centre(const Geo &g, const Mat &m, const S &s, i
   c.ur = 0.5 * (r0 + r1);
   c.ut = 0.5 * (t0 + t1);
   c.uf = 0.5 * (f0 + f1);
-  c.P = gC(g, s, F_P, i, j, k) + m.pinf;
+  c.P = gC(g, s, F_P, i, j, k) + pref_at(g, i) + m.pinf;
   c.T = gC(g, s, F_T, i, j, k);
   c.chi = (m.gam - 1.0) * c.T / c.P;
   c.Grr = (r1 - r0) * g.idr;

@@ -201,6 +201,11 @@ void launch_axpy3(const long *cnt, double a, const Fields &x, double b, const Fi
 void launch_adj_mix(const Geo &g, const long *cnt, const Fields &L, const Fields &mu1, const Fields &ubb,
                     const Fields &Lnew, const Fields &lam, bool fold, bool first, hipStream_t st);
 
+// Courant numbers (advective, acoustic) of a state for the step tau into
+// out[0], out[1] (device, as the bit patterns of non-negative doubles)
+void launch_courant(const Geo &g, const Mat &m, const Fields &U, double tau, unsigned long long *out,
+                    hipStream_t st);
+
 // public residual: forms the midpoint on the fly from Un and Uk and writes it
 void launch_residual(const Geo &g, const Mat &m, const Fields &Un, const Fields &Uk, double tau,
                      const Fields &R, const Fields &Ub, int *status, hipStream_t st);

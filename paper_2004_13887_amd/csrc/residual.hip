@@ -25,6 +25,7 @@
 //   * inside a split step the midpoint is already resident (written by the
 //     previous iteration's last sweep, or U^n itself at the first iteration),
 //     so every neighbour read is a single load.
+#include <algorithm>
 #include <type_traits>
 
 #include "dsw_common.hpp"
@@ -38,7 +39,9 @@ __device__ __forceinline__ double F_p_T(const Geo &g, const Mat &m, const S &s, 
   centre(g, m, s, i, j, k, c);
   const double ir = g.irc[i], is = g.isc[j];
   const double hr = 0.5 * g.idr, ht = 0.5 * ir * g.idt, hp = 0.5 * ir * is * g.idp;
-  const double advp = c.ur * (gC(g, s, F_P, i + 1, j, k) - gC(g, s, F_P, i - 1, j, k)) * hr +
+  // perturbation form: the reference column's gradient joins the r difference
+  const double dpr = g.pref ? pref_at(g, i + 1) - pref_at(g, i - 1) : 0.0;
+  const double advp = c.ur * (gC(g, s, F_P, i + 1, j, k) - gC(g, s, F_P, i - 1, j, k) + dpr) * hr +
                       c.ut * (gC(g, s, F_P, i, j + 1, k) - gC(g, s, F_P, i, j - 1, k)) * ht +
                       c.uf * (gC(g, s, F_P, i, j, k + 1) - gC(g, s, F_P, i, j, k - 1)) * hp;
   const double Tim = gC(g, s, F_T, i - 1, j, k), Tip = gC(g, s, F_T, i + 1, j, k);
@@ -86,6 +89,16 @@ __device__ __forceinline__ double F_ur(const Geo &g, const Mat &m, const S &s, i
   const double C = ((g.sf[j + 1] * wp1 - g.sf[j] * wp0) * g.idt - (wt1 - wt0) * g.idp) * (irF * is);
   const double vis = gd - C;  // nu (vis + gd / 3) = nu ((4/3) gd - C)
   N += -2.0 * m.omega * g.sc[j] * ub;
+  if (g.pref) {
+    // perturbation form: the gradient of p' above, and gravity less the
+    // reference column's balanced gradient, g (rho_f - rhobar_f) / rho_f,
+    // with rho - rhobar = (p' Tbar - (pbar + pi_inf)(T - Tbar)) / (R T Tbar)
+    const double Ta = gC(g, s, F_T, f - 1, j, k), Tb = gC(g, s, F_T, f, j, k);
+    const double ta = g.tref[f - 1], tb = g.tref[f];
+    const double da = (gC(g, s, F_P, f - 1, j, k) * ta - (g.pref[f - 1] + m.pinf) * (Ta - ta)) / (m.Rg * Ta * ta);
+    const double db = (gC(g, s, F_P, f, j, k) * tb - (g.pref[f] + m.pinf) * (Tb - tb)) / (m.Rg * Tb * tb);
+    return N - nu * vis - nu / 3.0 * gd + m.g_r * (0.5 * (da + db)) * irho;
+  }
   return N - nu * vis - nu / 3.0 * gd + m.g_r;
 }
 
@@ -192,7 +205,7 @@ __device__ __forceinline__ void residual_point(const Geo &g, const Mat &m, const
     if (WRITE_UB) { Ub.p[x] = ubp; Ub.T[x] = ubT; }
     // finite and non-positive; a NaN or an infinity shows as a non-finite
     // residual below
-    if (ubT <= 0.0 || ubp + m.pinf <= 0.0) status[ST_NONPHYS] = 1; // plain vector store
+    if (ubT <= 0.0 || ubp + pref_at(g, i) + m.pinf <= 0.0) status[ST_NONPHYS] = 1; // plain vector store
     double FT;
     const double Fp = F_p_T(g, m, s, i, j, k, &FT);
     const double rp = -dU.at(F_P, x) - tau * forced(s, F_P, x, Fp);
@@ -362,6 +375,54 @@ void launch_residual_in_pass(bool periodic, const PassArgs &a, const Batch &b, u
     if (b.tab) hipLaunchKernelGGL((k_residual_in<true, false>), gr, bl, 0, st, a, b);
     else hipLaunchKernelGGL((k_residual_in<false, false>), gr, bl, 0, st, a, b);
   }
+}
+
+// Courant numbers of a state for the step tau (for a time-step controller):
+// at every centre, with the centre-averaged velocity and the spacings
+// h_r = dr, h_t = r dtheta, h_f = r sin(theta) dphi, the advective number
+// tau (|u_r| / h_r + |u_theta| / h_t + |u_phi| / h_f) and the acoustic one
+// tau c max(1/h_r, 1/h_t, 1/h_f), c = sqrt(gamma R T); their maxima over the
+// grid.  Non-negative doubles order as their bit patterns, so the maxima are
+// unsigned 64-bit atomic maxima (vector atomics) into out[0], out[1].
+__global__ void __launch_bounds__(256) k_courant(Geo g, Mat m, Fields U, double tau, unsigned long long *out) {
+  const long n = (long)g.nr * g.nt * g.np;
+  double ca = 0.0, cs = 0.0;
+  for (long x = (long)blockIdx.x * blockDim.x + threadIdx.x; x < n; x += (long)gridDim.x * blockDim.x) {
+    const int k = (int)(x % g.np), j = (int)((x / g.np) % g.nt), i = (int)(x / ((long)g.np * g.nt));
+    const double hr = g.dr, ht = g.rc[i] * g.dt, hf = g.rc[i] * g.sc[j] * g.dp;
+    const double ur = 0.5 * (U.ur[idx_r(g, i, j, k)] + U.ur[idx_r(g, i + 1, j, k)]);
+    const double ut = 0.5 * (U.ut[idx_t(g, i, j, k)] + U.ut[idx_t(g, i, j + 1, k)]);
+    const int k1 = g.periodic ? wrapk(g, k + 1) : k + 1;
+    const double uf = 0.5 * (U.uf[idx_f(g, i, j, k)] + U.uf[idx_f(g, i, j, k1)]);
+    const double a = tau * (fabs(ur) / hr + fabs(ut) / ht + fabs(uf) / hf);
+    double ih = 1.0 / hr;
+    if (1.0 / ht > ih) ih = 1.0 / ht;
+    if (1.0 / hf > ih) ih = 1.0 / hf;
+    const double c = tau * sqrt(m.gam * m.Rg * U.T[x]) * ih;
+    if (a > ca) ca = a;
+    if (c > cs) cs = c;
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    const double a = __shfl_xor(ca, o), c = __shfl_xor(cs, o);
+    if (a > ca) ca = a;
+    if (c > cs) cs = c;
+  }
+  if ((threadIdx.x & 63) == 0) {
+    atomicMax(&out[0], (unsigned long long)__double_as_longlong(ca));
+    atomicMax(&out[1], (unsigned long long)__double_as_longlong(cs));
+  }
+}
+
+__global__ void k_zero_u64(unsigned long long *p, int n) {
+  if ((int)threadIdx.x < n) p[threadIdx.x] = 0ull;
+}
+
+void launch_courant(const Geo &g, const Mat &m, const Fields &U, double tau, unsigned long long *out,
+                    hipStream_t st) {
+  hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, st, out, 2);
+  const long n = (long)g.nr * g.nt * g.np;
+  const unsigned blocks = (unsigned)std::min<long>((n + 255) / 256, 4096);
+  hipLaunchKernelGGL(k_courant, dim3(blocks), dim3(256), 0, st, g, m, U, tau, out);
 }
 
 } // namespace dsw

@@ -32,7 +32,7 @@ SYMBOLS = ("dsw_init_grid", "dsw_free_grid", "dsw_layout", "dsw_residual", "dsw_
            "dsw_line_solve_T_theta", "dsw_line_solve_T_phi", "dsw_line_vjp_r", "dsw_line_vjp_theta",
            "dsw_line_vjp_phi", "dsw_residual_vjp", "dsw_split_step_forced", "dsw_tape_bytes", "dsw_split_step_taped",
            "dsw_adjoint_step_taped", "dsw_adjoint_trajectory", "dsw_split_step_noalloc",
-           "dsw_last_error")
+           "dsw_set_reference", "dsw_split_step_pert", "dsw_courant", "dsw_last_error")
 TIMING_KINDS = ("residual", "sweep_r", "sweep_theta", "sweep_phi_update", "boundary_copy")
 
 
@@ -102,6 +102,9 @@ def lib():
             getattr(L, n).argtypes = [P, FP, D, FP, FP, P]
         L.dsw_split_step.argtypes = [P, FP, FP, D, I, P]
         L.dsw_split_step_noalloc.argtypes = [P, FP, FP, D, I, P]
+        L.dsw_set_reference.argtypes = [P, C.c_void_p, C.c_void_p]
+        L.dsw_split_step_pert.argtypes = [P, FP, FP, D, I, P]
+        L.dsw_courant.argtypes = [P, FP, D, C.c_void_p, P]
         L.dsw_get_status.argtypes = [P, P]
         L.dsw_set_timing.argtypes = [P, I]
         L.dsw_read_timing.argtypes = [P, P, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
@@ -248,6 +251,26 @@ class Grid:
         workspace)"""
         _check(lib().dsw_split_step_noalloc(self._h, C.byref(_fields(Un)), C.byref(_fields(Unp1)),
                                             float(tau), int(K), _stream(stream)))
+
+    def set_reference(self, p_ref, T_ref):
+        """dsw_set_reference: the reference column (n_r values each) of the
+        perturbation-pressure form"""
+        nr = int(self.desc.n_r)
+        pr, tr = [float(x) for x in p_ref], [float(x) for x in T_ref]
+        if len(pr) != nr or len(tr) != nr:
+            raise ValueError("p_ref and T_ref need n_r values each")
+        _check(lib().dsw_set_reference(self._h, (C.c_double * nr)(*pr), (C.c_double * nr)(*tr)))
+
+    def split_step_pert(self, Un, Unp1, tau, K, stream=None):
+        """dsw_split_step_pert: the split step on states whose p holds p - p_ref"""
+        _check(lib().dsw_split_step_pert(self._h, C.byref(_fields(Un)), C.byref(_fields(Unp1)),
+                                         float(tau), int(K), _stream(stream)))
+
+    def courant(self, U, tau, stream=None):
+        """dsw_courant: (advective, acoustic) Courant numbers of U for the step tau"""
+        out = (C.c_double * 2)()
+        _check(lib().dsw_courant(self._h, C.byref(_fields(U)), float(tau), out, _stream(stream)))
+        return float(out[0]), float(out[1])
 
     def tape_bytes(self, K):
         n = C.c_int64()
