@@ -51,7 +51,7 @@ def log(*a):
 def kernel_sources_sha():
     h = hashlib.sha256()
     for f in ("dsw_common.hpp", "dsw_internal.hpp", "rows.hpp", "residual.hip", "sweeps.hip",
-              "phi_part.hip", "api.hip"):
+              "rt_part.hip", "phi_part.hip", "api.hip"):
         with open(os.path.join(ROOT, "paper_2004_13887_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]

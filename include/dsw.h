@@ -346,13 +346,16 @@ int dsw_adjoint_trajectory(dsw_grid *grid, const dsw_fields *ckpts, int32_t nste
  *                         threads per line, eliminating from both ends,
  *                         intermediates in a scratch array.  Lines of more
  *                         than 4 x sweep_block rows fall back to the latter.
- *                         The transposed solves of the adjoint always take
- *                         the latter.  Measured on the 512 x 256 x 128 full
- *                         sphere: r 1.39 ms partitioned, 1.42 ms two-ended
- *                         (and 2.4x fewer HBM bytes); theta 1.74 ms
- *                         partitioned, 1.63 ms two-ended.
- * Default {64, 256, 256, 4, 4, 0}.  dsw_set_config returns DSW_EINVAL for
- * other values. */
+ *                         The transposed r solves of the adjoint take the
+ *                         same solver; the transposed theta solves always
+ *                         the two-ended one.  Measured: partitioned r 0.16 ms,
+ *                         theta 0.19 ms against 0.20 / 0.31 ms two-ended on
+ *                         the 256 x 128 x 64 sector; on the 512 x 256 x 128
+ *                         sphere r 1.39 / 1.42 ms (2.4x fewer HBM bytes
+ *                         partitioned) and theta 1.74 / 1.63 ms.
+ * Default {64, 256, 256, 4, a, b}: a, b = 4 where that direction's lines have
+ * at most 128 rows (32 chunks), else 0.  dsw_set_config returns DSW_EINVAL
+ * for other values. */
 typedef struct {
   int32_t residual_block, sweep_block_r, sweep_block_theta, phi_rows_per_thread;
   int32_t rows_per_thread_r, rows_per_thread_theta;

@@ -220,8 +220,8 @@ extern "C" int dsw_init_grid(const dsw_grid_desc *desc, const dsw_material *mat,
   g.irc = t + o_irc; g.irf = t + o_irf; g.isc = t + o_isc; g.ctc = t + o_ctc; g.isf = t + o_isf;
   g.ctf = t + o_ctf;
   g.scx = t + o_scx;
-  g.pref = nullptr;  // the plain form; dsw_split_step_pert passes the reference
-  g.tref = nullptr;
+  G->cfg.rt_pm[0] = rt_default_pm(g, 0);
+  G->cfg.rt_pm[1] = rt_default_pm(g, 1);
   Mat &m = G->m;
   m.gam = mat->cp / mat->cv;
   m.Rg = mat->cp - mat->cv;
@@ -588,14 +588,33 @@ extern "C" int dsw_split_step_pert(dsw_grid *G, const dsw_fields *Un, dsw_fields
   const int rc = check_step_args(Un, Unp1, tau, K);
   if (rc) return rc;
   if (!G->ref_mem) return fail(DSW_EINVAL, "perturbation step: no reference column (dsw_set_reference)");
+  const Geo &g = G->geo;
+  std::vector<Pass> plan;
+  plan_step(G, own_work(G), F(Un), F(Unp1), tau, K, [&](const Pass &p) { plan.push_back(p); });
+  for (const Pass &p : plan)  // the kernel kinds with a perturbation-form variant
+    if (p.kind == PK_SW0 || p.kind == PK_SW1 || p.kind == PK_SW2_LINE)
+      return fail(DSW_EINVAL, "perturbation step: the grid's lines need the thread-per-line solver, "
+                              "which has no perturbation form");
   hipStream_t st = (hipStream_t)stream;
-  const double *pref = G->ref_mem, *tref = G->ref_mem + G->geo.nr;
-  plan_step(G, own_work(G), F(Un), F(Unp1), tau, K, [&](const Pass &p) {
-    Pass q = p;
-    q.a.g.pref = pref;
-    q.a.g.tref = tref;
-    timed(G, q.tk, st, [&] { launch_single(G, q, st); });
-  });
+  for (const Pass &p : plan) {
+    if (p.kind == PK_RES_IN || p.kind == PK_RES_INP) continue;  // inside the PK_RES launch below
+    PassArgs a = p.a;
+    a.pref = G->ref_mem;
+    a.tref = G->ref_mem + g.nr;
+    timed(G, p.tk, st, [&] {
+      const unsigned th = kind_threads(p.kind, g, G->cfg);
+      switch (p.kind) {
+      case PK_BND: launch_single(G, p, st); break;
+      case PK_RES: launch_residual_pert(a, kind_blocks(PK_RES, g, G->cfg, th), th, st); break;
+      case PK_SW0P: launch_rt_pert(0, a, th, st); break;
+      case PK_SW1P: launch_rt_pert(1, a, th, st); break;
+      case PK_SW0T: launch_sweep2_pert(0, a, sweep2_blocks(g, 0, th), th, st); break;
+      case PK_SW1T: launch_sweep2_pert(1, a, sweep2_blocks(g, 1, th), th, st); break;
+      default:  // PK_SW2_PART
+        launch_phi_pert(G->cfg.phi_pm, a, kind_blocks(p.kind, g, G->cfg, th), th, kind_lds(p.kind, g, G->cfg), st);
+      }
+    });
+  }
   return check_launch("perturbation split step kernels");
 }
 
@@ -878,6 +897,11 @@ static void launch_T(const dsw_grid *G, int d, const Pass &p, hipStream_t st) {
     const int pm = phi_part_supported(G->geo, 2) ? 2 : G->cfg.phi_pm;
     launch_phi_T(pm, p.a, (unsigned)G->geo.nr * (unsigned)G->geo.nt, phi_part_threads(G->geo, pm),
                  phi_part_lds(G->geo, pm), st);
+  } else if (d == 0 && p.kind == PK_SW0P) {
+    // the transposed theta lines keep the two-ended solver: their row window
+    // costs the partitioned kernel its second wave per SIMD (theta 0.59 ms
+    // against 0.37 ms on the 256 x 128 x 64 sector; r 0.20 against 0.33 ms)
+    launch_rt_T(d, p.a, (unsigned)G->cfg.sweep_bs[d], st);
   } else if (d < 2 && families(G->geo, d).nb < TWIST_LINES) {
     const unsigned bs = (unsigned)G->cfg.sweep_bs[d];
     launch_sweep2_T(d, p.a, sweep2_blocks(G->geo, d, bs), bs, st);
@@ -1385,6 +1409,7 @@ extern "C" int dsw_ensemble_create(const dsw_grid_desc *descs, const dsw_materia
       dsw_ensemble_free(E);
       return fail(rc, msg);
     }
+    G->cfg = E->cfg;  // a member's own steps take the ensemble's launch shapes
     E->mem.push_back(G);
   }
   if (hipStreamCreateWithFlags(&E->cap, hipStreamNonBlocking) != hipSuccess ||

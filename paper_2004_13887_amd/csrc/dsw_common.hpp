@@ -28,9 +28,6 @@ struct Geo {
   const double *isc, *ctc; // 1/sin, cot at centres
   const double *isf, *ctf; // 1/sin, cot at faces (0 at a pole face: never used there)
   const double *scx;       // sin of theta at centres j = -1 .. nt (ghosts included), at scx[j + 1]
-  // perturbation-pressure form (null: off): the state's p is p - pref(r), for
-  // a discretely hydrostatic reference column pref, tref at the centres [nr]
-  const double *pref, *tref;
 };
 
 struct Mat {
@@ -65,6 +62,7 @@ struct SrcOneT {
   static constexpr bool INTERIOR = I;
   static constexpr bool PERIODIC = P; // interior sources: phi periodic (known at compile time)
   static constexpr bool WALL = false;  // tangential wall velocities are zero
+  static constexpr bool PERT = false;  // p holds the full pressure
   __device__ __forceinline__ double ld(int f, long x) const { return a[f][x]; }
 };
 using SrcOne = SrcOneT<false>;
@@ -75,6 +73,7 @@ struct SrcMid {
   static constexpr bool INTERIOR = false;
   static constexpr bool PERIODIC = false;
   static constexpr bool WALL = false;
+  static constexpr bool PERT = false;
   __device__ __forceinline__ double ld(int f, long x) const { return 0.5 * (k[f][x] + n[f][x]); }
 };
 
@@ -100,6 +99,7 @@ struct SrcW {
   static constexpr bool INTERIOR = false;
   static constexpr bool PERIODIC = false;
   static constexpr bool WALL = true;
+  static constexpr bool PERT = false;
   __device__ __forceinline__ double ld(int fid, long x) const { return a[fid][x]; }
 };
 
@@ -113,7 +113,20 @@ struct SrcInW {
   static constexpr bool INTERIOR = true;
   static constexpr bool PERIODIC = P;
   static constexpr bool WALL = true;
+  static constexpr bool PERT = false;
   __device__ __forceinline__ double ld(int fid, long x) const { return a[fid][x]; }
+};
+
+// The perturbation-pressure form of a plain source (dsw_split_step_pert):
+// the state's p holds p - pref(r) for a discretely hydrostatic reference
+// column (pref, tref) at the centres.  Where the pressure enters as a
+// coefficient (density, P), rho_at and centre add pref back; differences of
+// p stay differences of p' (pref depends on r only, and the r terms that
+// see it are written out in the residual).
+template <class B>
+struct SrcPert : B {
+  const double *pref, *tref;  // [nr]
+  static constexpr bool PERT = true;
 };
 
 // Velocity ghosts of a forced source: across a wall 2 g - u (g the wall's
@@ -232,15 +245,19 @@ __device__ __forceinline__ double gF(const Geo &g, const S &s, int i, int j, int
   return sg * s.ld(F_UF, idx_f(g, i, j, f));
 }
 
-// the reference pressure at centre row i (ghost rows copy the nearest), 0
-// when the state holds the full pressure
-__device__ __forceinline__ double pref_at(const Geo &g, int i) {
-  return g.pref ? g.pref[clampi(i, 0, g.nr - 1)] : 0.0;
+// the pressure at a (possibly ghost) centre as a coefficient: the stored
+// value, plus the reference column's (ghost rows copy the nearest) in the
+// perturbation form
+template <class S>
+__device__ __forceinline__ double pcoef(const Geo &g, const S &s, int i, int j, int k) {
+  double p = gC(g, s, F_P, i, j, k);
+  if constexpr (S::PERT) p += s.pref[clampi(i, 0, g.nr - 1)];
+  return p;
 }
 
 template <class S>
 __device__ __forceinline__ double rho_at(const Geo &g, const Mat &m, const S &s, int i, int j, int k) {
-  return (gC(g, s, F_P, i, j, k) + pref_at(g, i) + m.pinf) / (m.Rg * gC(g, s, F_T, i, j, k));
+  return (pcoef(g, s, i, j, k) + m.pinf) / (m.Rg * gC(g, s, F_T, i, j, k));
 }
 
 // Coefficient fields at a centre: centre-averaged velocities, thermodynamic
@@ -274,7 +291,7 @@ __device__ __forceinline__ void centre(const Geo &g, const Mat &m, const S &s, i
   c.ur = 0.5 * (r0 + r1);
   c.ut = 0.5 * (t0 + t1);
   c.uf = 0.5 * (f0 + f1);
-  c.P = gC(g, s, F_P, i, j, k) + pref_at(g, i) + m.pinf;
+  c.P = pcoef(g, s, i, j, k) + m.pinf;
   c.T = gC(g, s, F_T, i, j, k);
   c.chi = (m.gam - 1.0) * c.T / c.P;
   c.Grr = (r1 - r0) * g.idr;

@@ -68,16 +68,30 @@ struct PassArgs {
   Fields src, d0, d1, d2; // boundary-face copy: src -> d0, d1, d2
   Wall wall;              // forced passes: tangential wall velocities
   Fields fsrc;            // forced residual: source term (null entries: none)
+  const double *pref, *tref; // perturbation-pressure passes: reference column [nr]
 };
 
-// The state source of a pass: the plain midpoint (zero wall velocities), or
-// for a forced pass the midpoint with the wall velocities and the source.
-template <bool W>
+// The state source of a pass: the plain midpoint (zero wall velocities),
+// for a forced pass (W) the midpoint with the wall velocities and the
+// source, for a perturbation-pressure pass (PT) the midpoint with the
+// reference column.
+template <bool W, bool PT = false>
 struct SrcSel {
   __device__ static __forceinline__ const SrcOne &get(const PassArgs &a) { return a.u; }
 };
 template <>
-struct SrcSel<true> {
+struct SrcSel<false, true> {
+  __device__ static __forceinline__ SrcPert<SrcOne> get(const PassArgs &a) {
+    SrcPert<SrcOne> s;
+#pragma unroll
+    for (int q = 0; q < 5; q++) s.a[q] = a.u.a[q];
+    s.pref = a.pref;
+    s.tref = a.tref;
+    return s;
+  }
+};
+template <>
+struct SrcSel<true, false> {
   __device__ static __forceinline__ SrcW get(const PassArgs &a) {
     SrcW s;
 #pragma unroll
@@ -145,6 +159,10 @@ void launch_wall_mix(const WallMix &w, hipStream_t st);
 void launch_phi_forced(int pm, const PassArgs &a, unsigned blocks, unsigned threads, size_t lds,
                        hipStream_t st);
 void launch_rt_forced(int d, int pm, const PassArgs &a, unsigned threads, hipStream_t st);
+// transposed r systems (adjoint) by the partitioned solver (d = 0 only)
+void launch_rt_T(int d, const PassArgs &a, unsigned threads, hipStream_t st);
+// the r / theta solver a grid takes by default (4 partitioned, 0 two-ended)
+int rt_default_pm(const Geo &g, int d);
 
 // r and theta sweeps take two threads per line (two-ended elimination) on
 // grids with fewer block lines than this; measured faster than one thread
@@ -200,6 +218,15 @@ void launch_axpy3(const long *cnt, double a, const Fields &x, double b, const Fi
                   const Fields &z, const Fields &out, hipStream_t st);
 void launch_adj_mix(const Geo &g, const long *cnt, const Fields &L, const Fields &mu1, const Fields &ubb,
                     const Fields &Lnew, const Fields &lam, bool fold, bool first, hipStream_t st);
+
+// perturbation-pressure split step (one grid): the residual (interior and
+// general launches), the partitioned r / theta solver, the two-ended
+// r / theta solver and the partitioned phi solver with the reference column
+// (a.pref, a.tref) of the state's pressure
+void launch_residual_pert(const PassArgs &a, unsigned blocks, unsigned threads, hipStream_t st);
+void launch_rt_pert(int d, const PassArgs &a, unsigned threads, hipStream_t st);
+void launch_sweep2_pert(int d, const PassArgs &a, unsigned blocks, unsigned threads, hipStream_t st);
+void launch_phi_pert(int pm, const PassArgs &a, unsigned blocks, unsigned threads, size_t lds, hipStream_t st);
 
 // Courant numbers (advective, acoustic) of a state for the step tau into
 // out[0], out[1] (device, as the bit patterns of non-negative doubles)

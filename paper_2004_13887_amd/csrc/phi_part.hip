@@ -412,7 +412,7 @@ __device__ __forceinline__ void part_scalar_line(const Geo &g, const Mat &m, con
 // (1 <= i <= nr - 2, 1 <= j <= nt - 2), whose rows read no ghost across an
 // r or theta boundary, with the interior source (phi walls only; P: periodic
 // phi); 2 the other slots, with the general source.
-template <int PM, bool TR, int PART = 2, bool W = false, int MAP = 0, bool P = false>
+template <int PM, bool TR, int PART = 2, bool W = false, int MAP = 0, bool P = false, bool PT = false>
 __device__ __forceinline__ void phi_body(const PassArgs &a, unsigned w, double *lds) {
   const Geo &g = a.g;
   int i, j;
@@ -457,7 +457,8 @@ __device__ __forceinline__ void phi_body(const PassArgs &a, unsigned w, double *
       part_scalar_line<PM, 1, TR>(g, a.m, u, a.rhs, o, i, j, a.tau, lds, a.status);
     }
   } else {
-    decltype(auto) u = SrcSel<W>::get(a); // W: forced pass (wall velocities)
+    // W: forced pass (wall velocities); PT: perturbation-pressure form
+    decltype(auto) u = SrcSel<W, PT>::get(a);
     if (PART != 1) part_block_line<PM, TR>(g, a.m, u, a.rhs, o, i, j, a.tau, lds, a.status);
     if (PART != 0) {
       if (i >= 1) part_scalar_line<PM, 0, TR>(g, a.m, u, a.rhs, o, i, j, a.tau, lds, a.status);
@@ -480,6 +481,14 @@ __global__ void __launch_bounds__(256) DSW_OCC(DSW_WAVES_PHI) k_phi_part(PassArg
   } else {
     phi_body<PM, false, PART>(a, w, lds);
   }
+}
+
+// perturbation-pressure form, one grid (as the plain pass of one grid)
+template <int PM, int PART>
+__global__ void __launch_bounds__(256) DSW_OCC(DSW_WAVES_PHI) k_phi_partP(PassArgs a) {
+  extern __shared__ double lds[];
+  const unsigned w = PART == 1 ? xcd_contiguous(blockIdx.x, gridDim.x) : blockIdx.x;
+  phi_body<PM, false, PART, false, 0, false, true>(a, w, lds);
 }
 
 // forced split step, one grid: as the plain sweep, all three lines of a slot
@@ -573,6 +582,24 @@ void launch_phi_pass(int pm, const PassArgs &a, const Batch &b, unsigned blocks,
       hipLaunchKernelGGL((k_phi_part<4, false, 0>), gr, bl, lds, st, a, b);
       hipLaunchKernelGGL((k_phi_part<4, false, 1>), gr, bl, lds_s, st, a, b);
     }
+  }
+}
+
+void launch_phi_pert(int pm, const PassArgs &a, unsigned blocks, unsigned threads, size_t lds,
+                     hipStream_t st) {
+  const dim3 gr(blocks), bl(threads);
+  const size_t lds_s = sizeof(double) * (size_t)(pm > 5 ? pm : 5) * threads;
+  if (blocks < PHI_SPLIT_SLOTS) {
+    if (pm == 2) hipLaunchKernelGGL((k_phi_partP<2, 2>), gr, bl, lds, st, a);
+    else hipLaunchKernelGGL((k_phi_partP<4, 2>), gr, bl, lds, st, a);
+    return;
+  }
+  if (pm == 2) {
+    hipLaunchKernelGGL((k_phi_partP<2, 0>), gr, bl, lds, st, a);
+    hipLaunchKernelGGL((k_phi_partP<2, 1>), gr, bl, lds_s, st, a);
+  } else {
+    hipLaunchKernelGGL((k_phi_partP<4, 0>), gr, bl, lds, st, a);
+    hipLaunchKernelGGL((k_phi_partP<4, 1>), gr, bl, lds_s, st, a);
   }
 }
 

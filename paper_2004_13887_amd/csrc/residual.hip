@@ -39,9 +39,10 @@ __device__ __forceinline__ double F_p_T(const Geo &g, const Mat &m, const S &s, 
   centre(g, m, s, i, j, k, c);
   const double ir = g.irc[i], is = g.isc[j];
   const double hr = 0.5 * g.idr, ht = 0.5 * ir * g.idt, hp = 0.5 * ir * is * g.idp;
+  double dpr = gC(g, s, F_P, i + 1, j, k) - gC(g, s, F_P, i - 1, j, k);
   // perturbation form: the reference column's gradient joins the r difference
-  const double dpr = g.pref ? pref_at(g, i + 1) - pref_at(g, i - 1) : 0.0;
-  const double advp = c.ur * (gC(g, s, F_P, i + 1, j, k) - gC(g, s, F_P, i - 1, j, k) + dpr) * hr +
+  if constexpr (S::PERT) dpr += s.pref[min(i + 1, g.nr - 1)] - s.pref[max(i - 1, 0)];
+  const double advp = c.ur * dpr * hr +
                       c.ut * (gC(g, s, F_P, i, j + 1, k) - gC(g, s, F_P, i, j - 1, k)) * ht +
                       c.uf * (gC(g, s, F_P, i, j, k + 1) - gC(g, s, F_P, i, j, k - 1)) * hp;
   const double Tim = gC(g, s, F_T, i - 1, j, k), Tip = gC(g, s, F_T, i + 1, j, k);
@@ -89,17 +90,18 @@ __device__ __forceinline__ double F_ur(const Geo &g, const Mat &m, const S &s, i
   const double C = ((g.sf[j + 1] * wp1 - g.sf[j] * wp0) * g.idt - (wt1 - wt0) * g.idp) * (irF * is);
   const double vis = gd - C;  // nu (vis + gd / 3) = nu ((4/3) gd - C)
   N += -2.0 * m.omega * g.sc[j] * ub;
-  if (g.pref) {
+  if constexpr (S::PERT) {
     // perturbation form: the gradient of p' above, and gravity less the
     // reference column's balanced gradient, g (rho_f - rhobar_f) / rho_f,
     // with rho - rhobar = (p' Tbar - (pbar + pi_inf)(T - Tbar)) / (R T Tbar)
     const double Ta = gC(g, s, F_T, f - 1, j, k), Tb = gC(g, s, F_T, f, j, k);
-    const double ta = g.tref[f - 1], tb = g.tref[f];
-    const double da = (gC(g, s, F_P, f - 1, j, k) * ta - (g.pref[f - 1] + m.pinf) * (Ta - ta)) / (m.Rg * Ta * ta);
-    const double db = (gC(g, s, F_P, f, j, k) * tb - (g.pref[f] + m.pinf) * (Tb - tb)) / (m.Rg * Tb * tb);
+    const double ta = s.tref[f - 1], tb = s.tref[f];
+    const double da = (gC(g, s, F_P, f - 1, j, k) * ta - (s.pref[f - 1] + m.pinf) * (Ta - ta)) / (m.Rg * Ta * ta);
+    const double db = (gC(g, s, F_P, f, j, k) * tb - (s.pref[f] + m.pinf) * (Tb - tb)) / (m.Rg * Tb * tb);
     return N - nu * vis - nu / 3.0 * gd + m.g_r * (0.5 * (da + db)) * irho;
+  } else {
+    return N - nu * vis - nu / 3.0 * gd + m.g_r;
   }
-  return N - nu * vis - nu / 3.0 * gd + m.g_r;
 }
 
 template <class S>
@@ -205,7 +207,9 @@ __device__ __forceinline__ void residual_point(const Geo &g, const Mat &m, const
     if (WRITE_UB) { Ub.p[x] = ubp; Ub.T[x] = ubT; }
     // finite and non-positive; a NaN or an infinity shows as a non-finite
     // residual below
-    if (ubT <= 0.0 || ubp + pref_at(g, i) + m.pinf <= 0.0) status[ST_NONPHYS] = 1; // plain vector store
+    double pfull = ubp;
+    if constexpr (S::PERT) pfull += s.pref[i];
+    if (ubT <= 0.0 || pfull + m.pinf <= 0.0) status[ST_NONPHYS] = 1; // plain vector store
     double FT;
     const double Fp = F_p_T(g, m, s, i, j, k, &FT);
     const double rp = -dU.at(F_P, x) - tau * forced(s, F_P, x, Fp);
@@ -264,8 +268,9 @@ __host__ __device__ inline unsigned res_interior_blocks(const Geo &g, int bs) {
   return (unsigned)res_nk(g, bs) * (unsigned)(g.nt - 2) * (unsigned)(g.nr - 2);
 }
 
-// W: a forced pass (wall velocities and source term)
-template <bool W = false>
+// W: a forced pass (wall velocities and source term); PT: the
+// perturbation-pressure form
+template <bool W = false, bool PT = false>
 __device__ __forceinline__ void residual_body(const PassArgs &a, unsigned w) {
   const Geo &g = a.g;
   const unsigned nkb = (g.npf + blockDim.x - 1) / blockDim.x;
@@ -275,7 +280,7 @@ __device__ __forceinline__ void residual_body(const PassArgs &a, unsigned w) {
   const bool interior = res_interior_blocks(g, bs) > 0 && i >= 1 && i <= g.nr - 2 && j >= 1 &&
                         j <= g.nt - 2;
   if (interior) return;  // done by the interior launch
-  decltype(auto) s = SrcSel<W>::get(a);
+  decltype(auto) s = SrcSel<W, PT>::get(a);
   residual_point<std::decay_t<decltype(s)>, false>(g, a.m, s, a.d, a.tau, a.R, Fields{}, a.status, i, j,
                                                    (int)(kb * blockDim.x + threadIdx.x));
 }
@@ -294,6 +299,10 @@ __device__ __forceinline__ void residual_body_in(const PassArgs &a, unsigned w) 
     s.w = a.wall;
     s.f[F_P] = a.fsrc.p; s.f[F_UR] = a.fsrc.ur; s.f[F_UT] = a.fsrc.ut; s.f[F_UF] = a.fsrc.uf;
     s.f[F_T] = a.fsrc.T;
+  }
+  if constexpr (SI::PERT) {
+    s.pref = a.pref;
+    s.tref = a.tref;
   }
   residual_point<SI, false>(g, a.m, s, a.d, a.tau, a.R, Fields{}, a.status, i, j,
                             (int)(kb * blockDim.x + threadIdx.x));
@@ -324,6 +333,23 @@ void launch_residual_forced(const PassArgs &a, unsigned blocks, unsigned threads
     else hipLaunchKernelGGL(k_residual_in_forced<false>, dim3(nin), dim3(threads), 0, st, a);
   }
   hipLaunchKernelGGL(k_residual_forced, dim3(blocks), dim3(threads), 0, st, a);
+}
+
+// perturbation-pressure form, one grid: the interior workgroups (P:
+// periodic), then the rest
+template <bool P>
+__global__ void __launch_bounds__(256) k_residual_in_pert(PassArgs a) {
+  residual_body_in<SrcPert<SrcOneT<true, P>>>(a, blockIdx.x);
+}
+__global__ void __launch_bounds__(256) k_residual_pert(PassArgs a) { residual_body<false, true>(a, blockIdx.x); }
+
+void launch_residual_pert(const PassArgs &a, unsigned blocks, unsigned threads, hipStream_t st) {
+  const unsigned nin = res_interior_blocks(a.g, (int)threads);
+  if (nin) {
+    if (a.g.periodic) hipLaunchKernelGGL(k_residual_in_pert<true>, dim3(nin), dim3(threads), 0, st, a);
+    else hipLaunchKernelGGL(k_residual_in_pert<false>, dim3(nin), dim3(threads), 0, st, a);
+  }
+  hipLaunchKernelGGL(k_residual_pert, dim3(blocks), dim3(threads), 0, st, a);
 }
 
 // P: the grids of the launch are periodic in phi (full sphere)

@@ -129,7 +129,9 @@ __device__ __forceinline__ void rt_pcr_scalar(int c, int l, int T, int L, bool a
 // ------------------------------------------------------------ block lines --
 // The block lines [line0, line0 + L) of sweep D (line = a * np + b); LDS
 // 24 doubles per thread.
-template <int D, int PM, class US>
+// TR: the transposed system (adjoint): each chunk walks its rows once and
+// forms the transposed rows from them (TrWalk; u is then the plain source).
+template <int D, int PM, bool TR, class US>
 __device__ __forceinline__ void rt_block_lines(const Geo &g, const Mat &m, const US &u, const Fields &rhs,
                                                const Out &o, long line0, double hs, double *lds,
                                                int *status) {
@@ -144,12 +146,17 @@ __device__ __forceinline__ void rt_block_lines(const Geo &g, const Mat &m, const
   const int a0 = c * PM;
   const int len = act ? min(PM, n - a0) : 0;
   double Cm[PM - 1][9], Em[PM - 1][9], Ym[PM - 1][3];
+  TrWalk<D> tw;
+  if constexpr (TR) {
+    if (act) tw.init(g, m, u, rhs, pa, pb, a0, n, 0, hs);
+  }
   // 1. forward elimination over the interior rows with the left spike
 #pragma unroll
   for (int q = 0; q < PM - 1; q++) {
     if (q < len - 1) {
       BRow R;
-      block_row<D>(g, m, u, rhs, pa, pb, a0 + q, n, 0, hs, R);
+      if constexpr (TR) tw.next(g, m, u, rhs, pa, pb, n, 0, hs, R);
+      else block_row<D>(g, m, u, rhs, pa, pb, a0 + q, n, 0, hs, R);
       double Dp[9], rr[3], Lx[9], Ai[9];
       if (q == 0) {
 #pragma unroll
@@ -175,7 +182,10 @@ __device__ __forceinline__ void rt_block_lines(const Geo &g, const Mat &m, const
     }
   }
   BRow S;  // separator row (last row of the chunk)
-  if (act) block_row<D>(g, m, u, rhs, pa, pb, a0 + len - 1, n, 0, hs, S);
+  if (act) {
+    if constexpr (TR) tw.next(g, m, u, rhs, pa, pb, n, 0, hs, S);
+    else block_row<D>(g, m, u, rhs, pa, pb, a0 + len - 1, n, 0, hs, S);
+  }
   // backward sweep: (Y, E, C) -> (g, V, W)
 #pragma unroll
   for (int q = PM - 2; q >= 0; q--) {
@@ -286,7 +296,7 @@ __device__ __forceinline__ void rt_block_lines(const Geo &g, const Mat &m, const
 // ----------------------------------------------------------- scalar lines --
 // Lines [line0, line0 + L) of scalar family FAM of sweep D; LDS 4 doubles
 // per thread.
-template <int D, int FAM, int PM, class US>
+template <int D, int FAM, int PM, bool TR, class US>
 __device__ __forceinline__ void rt_scalar_lines(const Geo &g, const Mat &m, const US &u, const Fields &rhs,
                                                 const Out &o, long line0, double hs, double *lds,
                                                 int *status) {
@@ -310,11 +320,16 @@ __device__ __forceinline__ void rt_scalar_lines(const Geo &g, const Mat &m, cons
   double Cm[PM - 1], Em[PM - 1], Ym[PM - 1];
   long xi;
   double *arr;
+  TrWalkS<D, FAM> tw;
+  if constexpr (TR) {
+    if (act) tw.init(g, m, u, rhs, pa, pb, a0, n, 0, hs);
+  }
 #pragma unroll
   for (int q = 0; q < PM - 1; q++) {
     if (q < len - 1) {
       SRow R;
-      scalar_row<D, FAM>(g, m, u, rhs, pa, pb, a0 + q, n, 0, hs, R, xi, arr);
+      if constexpr (TR) tw.next(g, m, u, rhs, pa, pb, n, 0, hs, R);
+      else scalar_row<D, FAM>(g, m, u, rhs, pa, pb, a0 + q, n, 0, hs, R, xi, arr);
       double dp = R.b, rr = R.r, lx = R.a;
       if (q > 0) { dp -= R.a * Cm[q - 1]; rr -= R.a * Ym[q - 1]; lx = -R.a * Em[q - 1]; }
       if (!(dp != 0.0)) status[ST_SINGULAR] = 1;
@@ -325,7 +340,10 @@ __device__ __forceinline__ void rt_scalar_lines(const Geo &g, const Mat &m, cons
     }
   }
   SRow S{0, 1, 0, 0};
-  if (act) scalar_row<D, FAM>(g, m, u, rhs, pa, pb, a0 + len - 1, n, 0, hs, S, xi, arr);
+  if (act) {
+    if constexpr (TR) tw.next(g, m, u, rhs, pa, pb, n, 0, hs, S);
+    else scalar_row<D, FAM>(g, m, u, rhs, pa, pb, a0 + len - 1, n, 0, hs, S, xi, arr);
+  }
 #pragma unroll
   for (int q = PM - 2; q >= 0; q--) {
     if (q == len - 2) { Em[q] = -Em[q]; Cm[q] = -Cm[q]; }
@@ -395,23 +413,23 @@ __host__ __device__ inline unsigned rt_scalar_wgs(const Geo &g, int d, unsigned 
 
 // PART 0: block lines only; 1: scalar lines only; 2: block lines in
 // workgroups [0, nbw), then the scalar lines.  W: a forced pass.
-template <int D, int PM, int PART, bool W = false>
+template <int D, int PM, int PART, bool W = false, bool TR = false, bool PT = false>
 __device__ __forceinline__ void rt_body(const PassArgs &a, unsigned w, double *lds) {
   const Geo &g = a.g;
-  decltype(auto) u = SrcSel<W>::get(a);
+  decltype(auto) u = SrcSel<W, PT>::get(a);  // the plain source when TR
   const unsigned bs = blockDim.x;
   const unsigned nbw = PART == 1 ? 0u : rt_block_wgs(g, D, bs, PM);
   if (PART != 1 && w < nbw) {
     const unsigned L = bs / (unsigned)rt_chunks<PM>(families(g, D).n);
-    rt_block_lines<D, PM>(g, a.m, u, a.rhs, a.o, (long)w * L, a.tau, lds, a.status);
+    rt_block_lines<D, PM, TR>(g, a.m, u, a.rhs, a.o, (long)w * L, a.tau, lds, a.status);
     return;
   }
   if constexpr (PART != 0) {
     const unsigned w2 = w - nbw;
     const unsigned L = bs / (unsigned)rt_chunks<RT_PMS>(families(g, D).n);
     const unsigned nwa = rt_scalar_wgs_a(g, D, bs);
-    if (w2 < nwa) rt_scalar_lines<D, 0, RT_PMS>(g, a.m, u, a.rhs, a.o, (long)w2 * L, a.tau, lds, a.status);
-    else rt_scalar_lines<D, 1, RT_PMS>(g, a.m, u, a.rhs, a.o, (long)(w2 - nwa) * L, a.tau, lds, a.status);
+    if (w2 < nwa) rt_scalar_lines<D, 0, RT_PMS, TR>(g, a.m, u, a.rhs, a.o, (long)w2 * L, a.tau, lds, a.status);
+    else rt_scalar_lines<D, 1, RT_PMS, TR>(g, a.m, u, a.rhs, a.o, (long)(w2 - nwa) * L, a.tau, lds, a.status);
   }
 }
 
@@ -435,10 +453,26 @@ __global__ void __launch_bounds__(256) k_rt_partF(PassArgs a) {
   rt_body<D, PM, PART, true>(a, xcd_contiguous(blockIdx.x, gridDim.x), lds);
 }
 
+// perturbation-pressure form, one grid
+template <int D, int PM, int PART>
+__global__ void __launch_bounds__(256) k_rt_partP(PassArgs a) {
+  extern __shared__ double lds[];
+  rt_body<D, PM, PART, false, false, true>(a, xcd_contiguous(blockIdx.x, gridDim.x), lds);
+}
+
+// transposed systems (adjoint), one grid
+template <int D, int PM, int PART>
+__global__ void __launch_bounds__(256) k_rt_partT(PassArgs a) {
+  extern __shared__ double lds[];
+  rt_body<D, PM, PART, false, true>(a, xcd_contiguous(blockIdx.x, gridDim.x), lds);
+}
+
 // From this many workgroups on, one grid's block and scalar lines run as two
 // launches (the scalar lines need a fraction of the block lines' registers
-// and run at a higher occupancy on their own).
-constexpr unsigned RT_SPLIT_WGS = 4096;
+// and run at a higher occupancy on their own).  Measured on the 256 x 128 x 64
+// sector (4084 workgroups): r 0.22 -> 0.16 ms, theta 0.28 -> 0.19 ms; the
+// same from 256 to 1024.
+constexpr unsigned RT_SPLIT_WGS = 1024;
 
 bool rt_part_supported(const Geo &g, int d, unsigned bs, int pm) {
   const Families F = families(g, d);
@@ -473,6 +507,50 @@ void launch_rt_pass(int d, int pm, const PassArgs &a, const Batch &b, unsigned b
   (void)pm;  // 4: the only chunk size built (8 measured slower: one wave per SIMD)
   if (d == 0) launch_rt_d<0, 4>(a, b, blocks, threads, st);
   else launch_rt_d<1, 4>(a, b, blocks, threads, st);
+}
+
+template <int D, int PM>
+static void launch_rt_T_d(const PassArgs &a, unsigned threads, hipStream_t st) {
+  const size_t lds = rt_part_lds(threads), lds_s = sizeof(double) * 4 * (size_t)threads;
+  const unsigned nbw = rt_block_wgs(a.g, D, threads, PM), nsw = rt_scalar_wgs(a.g, D, threads);
+  if (nbw + nsw < RT_SPLIT_WGS) {
+    hipLaunchKernelGGL((k_rt_partT<D, PM, 2>), dim3(nbw + nsw), dim3(threads), lds, st, a);
+    return;
+  }
+  hipLaunchKernelGGL((k_rt_partT<D, PM, 0>), dim3(nbw), dim3(threads), lds, st, a);
+  hipLaunchKernelGGL((k_rt_partT<D, PM, 1>), dim3(nsw), dim3(threads), lds_s, st, a);
+}
+
+template <int D, int PM>
+static void launch_rt_pert_d(const PassArgs &a, unsigned threads, hipStream_t st) {
+  const size_t lds = rt_part_lds(threads), lds_s = sizeof(double) * 4 * (size_t)threads;
+  const unsigned nbw = rt_block_wgs(a.g, D, threads, PM), nsw = rt_scalar_wgs(a.g, D, threads);
+  if (nbw + nsw < RT_SPLIT_WGS) {
+    hipLaunchKernelGGL((k_rt_partP<D, PM, 2>), dim3(nbw + nsw), dim3(threads), lds, st, a);
+    return;
+  }
+  hipLaunchKernelGGL((k_rt_partP<D, PM, 0>), dim3(nbw), dim3(threads), lds, st, a);
+  hipLaunchKernelGGL((k_rt_partP<D, PM, 1>), dim3(nsw), dim3(threads), lds_s, st, a);
+}
+
+void launch_rt_pert(int d, const PassArgs &a, unsigned threads, hipStream_t st) {
+  if (d == 0) launch_rt_pert_d<0, 4>(a, threads, st);
+  else launch_rt_pert_d<1, 4>(a, threads, st);
+}
+
+void launch_rt_T(int d, const PassArgs &a, unsigned threads, hipStream_t st) {
+  (void)d;  // r only: see the transposed solve's launcher in the host code
+  launch_rt_T_d<0, 4>(a, threads, st);
+}
+
+// the solver a grid takes by default: partitioned where a block line
+// splits into at most 32 chunks (L >= 8 neighbouring lines per 256-thread
+// workgroup), else two-ended.  Measured: partitioned r 0.16 / theta 0.19 ms
+// against 0.20 / 0.31 ms two-ended on the 256 x 128 x 64 sector (64 and 128
+// rows); theta on the 512 x 256 x 128 sphere (256 rows, 64 chunks) 1.74
+// against 1.63 ms.
+int rt_default_pm(const Geo &g, int d) {
+  return rt_part_supported(g, d, 256, 4) && rt_block_chunks(families(g, d).n, 4) <= 32 ? 4 : 0;
 }
 
 template <int D, int PM>

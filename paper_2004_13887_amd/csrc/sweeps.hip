@@ -844,11 +844,12 @@ __host__ __device__ inline unsigned twisted_block_wgs(const Geo &g, int d, unsig
   return (unsigned)((F.nb + lpw - 1) / lpw);
 }
 
-// W: a forced pass (the coefficients see the wall velocities)
-template <int D, bool TR = false, bool W = false>
+// W: a forced pass (the coefficients see the wall velocities); PT: the
+// perturbation-pressure form
+template <int D, bool TR = false, bool W = false, bool PT = false>
 __device__ __forceinline__ void sweep2_body(const PassArgs &a, unsigned w, double *lds) {
   const Geo &g = a.g;
-  decltype(auto) u = SrcSel<W>::get(a);
+  decltype(auto) u = SrcSel<W, PT>::get(a);
   const Families F = families(g, D);
   const double hs = a.tau;
   const unsigned nbw = twisted_block_wgs(g, D, blockDim.x);
@@ -923,6 +924,18 @@ template <int D>
 __global__ void __launch_bounds__(256) DSW_OCC(DSW_WAVES_SWEEP) k_sweep2F(PassArgs a) {
   __shared__ double lds[128 * 15];
   sweep2_body<D, false, true>(a, blockIdx.x, lds);
+}
+
+// perturbation-pressure form, one grid
+template <int D>
+__global__ void __launch_bounds__(256) DSW_OCC(DSW_WAVES_SWEEP) k_sweep2P(PassArgs a) {
+  __shared__ double lds[128 * 15];
+  sweep2_body<D, false, false, true>(a, blockIdx.x, lds);
+}
+
+void launch_sweep2_pert(int d, const PassArgs &a, unsigned blocks, unsigned threads, hipStream_t st) {
+  if (d == 0) hipLaunchKernelGGL(k_sweep2P<0>, dim3(blocks), dim3(threads), 0, st, a);
+  else hipLaunchKernelGGL(k_sweep2P<1>, dim3(blocks), dim3(threads), 0, st, a);
 }
 
 void launch_sweep2_forced(int d, const PassArgs &a, unsigned blocks, unsigned threads, hipStream_t st) {

@@ -347,9 +347,13 @@ class Grid:
         return DSW_OK
 
     def set_config(self, residual_block=64, sweep_block_r=256, sweep_block_theta=256,
-                   phi_rows_per_thread=4, rows_per_thread_r=4, rows_per_thread_theta=0):
-        c = Config(residual_block, sweep_block_r, sweep_block_theta, phi_rows_per_thread,
-                   rows_per_thread_r, rows_per_thread_theta)
+                   phi_rows_per_thread=4, rows_per_thread_r=None, rows_per_thread_theta=None):
+        """dsw_set_config; the r / theta solver choices left as None keep the
+        grid's current ones"""
+        cur = self.get_config()
+        rr = cur[4] if rows_per_thread_r is None else rows_per_thread_r
+        rt = cur[5] if rows_per_thread_theta is None else rows_per_thread_theta
+        c = Config(residual_block, sweep_block_r, sweep_block_theta, phi_rows_per_thread, rr, rt)
         _check(lib().dsw_set_config(self._h, C.byref(c)))
 
     def get_config(self):
@@ -410,9 +414,13 @@ class Ensemble:
         return c.astuple()
 
     def set_config(self, residual_block=64, sweep_block_r=256, sweep_block_theta=256,
-                   phi_rows_per_thread=4, rows_per_thread_r=4, rows_per_thread_theta=0):
-        c = Config(residual_block, sweep_block_r, sweep_block_theta, phi_rows_per_thread,
-                   rows_per_thread_r, rows_per_thread_theta)
+                   phi_rows_per_thread=4, rows_per_thread_r=None, rows_per_thread_theta=None):
+        """dsw_ensemble_set_config; solver choices left as None keep the
+        ensemble's current ones"""
+        cur = self.get_config()
+        rr = cur[4] if rows_per_thread_r is None else rows_per_thread_r
+        rt = cur[5] if rows_per_thread_theta is None else rows_per_thread_theta
+        c = Config(residual_block, sweep_block_r, sweep_block_theta, phi_rows_per_thread, rr, rt)
         _check(lib().dsw_ensemble_set_config(self._h, C.byref(c)))
 
     def get_config(self):
