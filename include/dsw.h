@@ -344,18 +344,23 @@ int dsw_adjoint_trajectory(dsw_grid *grid, const dsw_fields *ckpts, int32_t nste
  *                         and 8 on the scalar ones, separators by cyclic
  *                         reduction in LDS; no scratch memory); 0 = two
  *                         threads per line, eliminating from both ends,
- *                         intermediates in a scratch array.  Lines of more
- *                         than 4 x sweep_block rows fall back to the latter.
+ *                         intermediates in a scratch array; -1 = by line
+ *                         length: partitioned where a line has at most 128
+ *                         rows (32 chunks), else two-ended (in an ensemble,
+ *                         member by member).  Lines of more than
+ *                         4 x sweep_block rows take the two-ended solver.
  *                         The transposed r solves of the adjoint take the
  *                         same solver; the transposed theta solves always
- *                         the two-ended one.  Measured: partitioned r 0.16 ms,
- *                         theta 0.19 ms against 0.20 / 0.31 ms two-ended on
- *                         the 256 x 128 x 64 sector; on the 512 x 256 x 128
- *                         sphere r 1.39 / 1.42 ms (2.4x fewer HBM bytes
- *                         partitioned) and theta 1.74 / 1.63 ms.
- * Default {64, 256, 256, 4, a, b}: a, b = 4 where that direction's lines have
- * at most 128 rows (32 chunks), else 0.  dsw_set_config returns DSW_EINVAL
- * for other values. */
+ *                         the two-ended one.  Measured: partitioned r
+ *                         0.16 ms, theta 0.19 ms against 0.20 / 0.31 ms
+ *                         two-ended on the 256 x 128 x 64 sector; on the
+ *                         512 x 256 x 128 sphere r 1.39 / 1.42 ms (2.4x
+ *                         fewer HBM bytes partitioned) and theta 1.74 /
+ *                         1.63 ms.
+ * Default {64, 256, 256, 4, -1, -1}.  dsw_set_config returns DSW_EINVAL for
+ * other values.  dsw_ensemble_tune times candidate shapes per pass and keeps
+ * each pass's best; its result is also kept for the process per set of member
+ * shapes and K, and a later tuning of the same shapes returns it untimed. */
 typedef struct {
   int32_t residual_block, sweep_block_r, sweep_block_theta, phi_rows_per_thread;
   int32_t rows_per_thread_r, rows_per_thread_theta;
@@ -388,7 +393,11 @@ int dsw_get_config(const dsw_grid *grid, dsw_config *cfg);
  *   result becomes the configuration of the ensemble and of every member
  *   (so that per-member dsw_split_step calls compute the same numbers) and
  *   is stored in *best if best is non-NULL.  Unp1 is overwritten.
- *   Synchronises the stream.
+ *   Synchronises the stream.  Candidates: each workgroup width with its
+ *   phi solver, and the r / theta solvers all partitioned, all two-ended or
+ *   by line length member by member.  The result is kept for the process per
+ *   set of member shapes and K; tuning the same shapes again returns it
+ *   without running anything.
  * dsw_ensemble_get_status: dsw_get_status over all members (first error). */
 typedef struct dsw_ensemble dsw_ensemble;
 int dsw_ensemble_create(const dsw_grid_desc *descs, const dsw_material *mats, int32_t n,

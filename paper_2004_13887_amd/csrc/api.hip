@@ -22,7 +22,7 @@ struct dsw_grid {
   dsw_material mat;
   Geo geo;
   Mat m;
-  Cfg cfg{64, {256, 256}, 4, {4, 0}}; // launch shapes
+  Cfg cfg{64, {256, 256}, 4, {-1, -1}}; // launch shapes
   double *tables = nullptr; // rc | rf | sc | cc | sf | cf
   Fields ub{}, ub2{}, r{}, x1{}, x2{}; // ub, ub2: midpoint states of consecutive iterations
   double *fields_mem = nullptr;
@@ -220,8 +220,6 @@ extern "C" int dsw_init_grid(const dsw_grid_desc *desc, const dsw_material *mat,
   g.irc = t + o_irc; g.irf = t + o_irf; g.isc = t + o_isc; g.ctc = t + o_ctc; g.isf = t + o_isf;
   g.ctf = t + o_ctf;
   g.scx = t + o_scx;
-  G->cfg.rt_pm[0] = rt_default_pm(g, 0);
-  G->cfg.rt_pm[1] = rt_default_pm(g, 1);
   Mat &m = G->m;
   m.gam = mat->cp / mat->cv;
   m.Rg = mat->cp - mat->cv;
@@ -362,7 +360,8 @@ struct Pass {
 
 // the kind of an r (d = 0) or theta (d = 1) pass under a configuration
 static int rt_kind(const Geo &g, const Cfg &c, int d) {
-  if (c.rt_pm[d] > 0 && rt_part_supported(g, d, (unsigned)c.sweep_bs[d], c.rt_pm[d])) return d == 0 ? PK_SW0P : PK_SW1P;
+  const int pm = c.rt_pm[d] < 0 ? rt_default_pm(g, d) : c.rt_pm[d];  // -1: by line length
+  if (pm > 0 && rt_part_supported(g, d, (unsigned)c.sweep_bs[d], pm)) return d == 0 ? PK_SW0P : PK_SW1P;
   const bool tw = families(g, d).nb < TWIST_LINES;
   return d == 0 ? (tw ? PK_SW0T : PK_SW0) : (tw ? PK_SW1T : PK_SW1);
 }
@@ -463,8 +462,8 @@ static unsigned kind_blocks(int kind, const Geo &g, const Cfg &c, unsigned threa
   case PK_SW1: return cdiv(sweep_lines(g, 1), threads);
   case PK_SW0T: return sweep2_blocks(g, 0, threads);
   case PK_SW1T: return sweep2_blocks(g, 1, threads);
-  case PK_SW0P: return rt_part_blocks(g, 0, threads, c.rt_pm[0]);
-  case PK_SW1P: return rt_part_blocks(g, 1, threads, c.rt_pm[1]);
+  case PK_SW0P: return rt_part_blocks(g, 0, threads, 4);
+  case PK_SW1P: return rt_part_blocks(g, 1, threads, 4);
   case PK_SW2_LINE: return cdiv(sweep_lines(g, 2), threads);
   default: return (unsigned)g.nr * (unsigned)g.nt; // PK_SW2_PART
   }
@@ -486,8 +485,8 @@ static void launch_kind(int kind, const Cfg &c, const PassArgs &a, const Batch &
   case PK_SW1: launch_sweep_pass(1, a, b, blocks, threads, st); break;
   case PK_SW0T: launch_sweep2_pass(0, a, b, blocks, threads, st); break;
   case PK_SW1T: launch_sweep2_pass(1, a, b, blocks, threads, st); break;
-  case PK_SW0P: launch_rt_pass(0, c.rt_pm[0], a, b, blocks, threads, st); break;
-  case PK_SW1P: launch_rt_pass(1, c.rt_pm[1], a, b, blocks, threads, st); break;
+  case PK_SW0P: launch_rt_pass(0, 4, a, b, blocks, threads, st); break;
+  case PK_SW1P: launch_rt_pass(1, 4, a, b, blocks, threads, st); break;
   case PK_SW2_LINE: launch_sweep_pass(2, a, b, blocks, threads, st); break;
   default: launch_phi_pass(c.phi_pm, a, b, blocks, threads, lds, st); break;
   }
@@ -778,7 +777,7 @@ extern "C" int dsw_split_step_forced(dsw_grid *G, const dsw_fields *Un, dsw_fiel
       }
       if (d < 2) {
         const unsigned bs = (unsigned)G->cfg.sweep_bs[d];
-        if (rt_kind(g, G->cfg, d) == (d == 0 ? PK_SW0P : PK_SW1P)) launch_rt_forced(d, G->cfg.rt_pm[d], p.a, bs, st);
+        if (rt_kind(g, G->cfg, d) == (d == 0 ? PK_SW0P : PK_SW1P)) launch_rt_forced(d, 4, p.a, bs, st);
         else launch_sweep2_forced(d, p.a, sweep2_blocks(g, d, bs), bs, st);
       } else {
         launch_phi_forced(pm, p.a, (unsigned)g.nr * (unsigned)g.nt, phi_part_threads(g, pm), phi_part_lds(g, pm), st);
@@ -804,9 +803,9 @@ static int check_cfg(const dsw_config *c) {
     return fail(DSW_EINVAL, "block sizes must be 64, 128 or 256");
   if (c->phi_rows_per_thread != 0 && c->phi_rows_per_thread != 2 && c->phi_rows_per_thread != 4)
     return fail(DSW_EINVAL, "phi_rows_per_thread must be 0, 2 or 4");
-  auto rt_ok = [](int v) { return v == 0 || v == 4; };
+  auto rt_ok = [](int v) { return v == -1 || v == 0 || v == 4; };
   if (!rt_ok(c->rows_per_thread_r) || !rt_ok(c->rows_per_thread_theta))
-    return fail(DSW_EINVAL, "rows_per_thread_r and rows_per_thread_theta must be 0 or 4");
+    return fail(DSW_EINVAL, "rows_per_thread_r and rows_per_thread_theta must be -1, 0 or 4");
   return DSW_OK;
 }
 
@@ -1354,7 +1353,7 @@ extern "C" int dsw_adjoint_trajectory(dsw_grid *G, const dsw_fields *ckpts, int3
 
 struct dsw_ensemble {
   std::vector<dsw_grid *> mem;
-  Cfg cfg{64, {256, 256}, 4, {4, 0}};
+  Cfg cfg{64, {256, 256}, 4, {-1, -1}};
   hipStream_t cap = nullptr, cap2 = nullptr;  // capture streams of the two lanes
   hipEvent_t fork = nullptr, stagger = nullptr, join = nullptr;
   // one launch of a batched plan
@@ -1563,7 +1562,7 @@ static std::vector<uint64_t> plan_key(const dsw_ensemble *E, const Cfg &cfg, con
   k.push_back((uint64_t)K);
   k.push_back((uint64_t)cfg.res_bs | ((uint64_t)cfg.sweep_bs[0] << 16) |
               ((uint64_t)cfg.sweep_bs[1] << 32) | ((uint64_t)cfg.phi_pm << 48) |
-              ((uint64_t)cfg.rt_pm[0] << 52) | ((uint64_t)cfg.rt_pm[1] << 56));
+              ((uint64_t)(cfg.rt_pm[0] + 1) << 52) | ((uint64_t)(cfg.rt_pm[1] + 1) << 56));
   for (size_t m = 0; m < E->mem.size(); m++) {
     const double *pu[10] = {Un[m].p, Un[m].ur, Un[m].ut, Un[m].uf, Un[m].T,
                             Unp1[m].p, Unp1[m].ur, Unp1[m].ut, Unp1[m].uf, Unp1[m].T};
@@ -1677,15 +1676,33 @@ extern "C" int dsw_ensemble_tune(dsw_ensemble *E, const dsw_fields *Un, dsw_fiel
   if (rc) return rc;
   if (reps < 1) return fail(DSW_EINVAL, "reps must be >= 1");
   hipStream_t st = (hipStream_t)stream;
+  // A tuned result is kept per set of member shapes (and K) for the process:
+  // a second ensemble of the same shapes takes it without timing.
+  static std::mutex cache_mu;
+  static std::vector<std::pair<std::vector<long>, Cfg>> cache;
+  std::vector<long> key{(long)K};
+  for (const dsw_grid *G : E->mem)
+    for (long v : {(long)G->geo.nr, (long)G->geo.nt, (long)G->geo.np, (long)G->geo.periodic}) key.push_back(v);
+  {
+    std::lock_guard<std::mutex> lk(cache_mu);
+    for (const auto &e : cache)
+      if (e.first == key) {
+        E->cfg = e.second;
+        for (dsw_grid *G : E->mem) G->cfg = e.second;
+        if (best) *best = from_cfg(e.second);
+        return DSW_OK;
+      }
+  }
   // candidate (v, p) sets every workgroup width to its v-th value, the phi
-  // solver to its v-th kind and the r and theta solvers to kind p; passes
-  // are timed separately, so each pass keeps its own best value
-  const int bsz[3] = {64, 128, 256}, pms[3] = {4, 2, 0}, rts[2] = {4, 0};
+  // solver to its v-th kind and the r and theta solvers to p (-1: each
+  // member by its line length, 4 partitioned, 0 two-ended); passes are timed
+  // separately, so each pass keeps its own best value
+  const int bsz[3] = {64, 128, 256}, pms[3] = {4, 2, 0}, rts[3] = {-1, 4, 0};
   double tbest[4] = {1e300, 1e300, 1e300, 1e300};
   Cfg out = E->cfg;
-  for (int vp = 0; vp < 6; vp++) {
+  for (int vp = 0; vp < 9; vp++) {
     const int v = vp % 3, pr = rts[vp / 3];
-    if (vp >= 3 && v == 0) continue;  // the two-ended solver: 128 and 256 only
+    if (pr == 0 && v == 0) continue;  // the two-ended solver: 128 and 256 only
     const Cfg c{bsz[v], {bsz[v], bsz[v]}, pms[v], {pr, pr}};
     dsw_ensemble::Plan plan;
     if ((rc = build_plan(E, c, Un, Unp1, tau, K, plan))) return rc;
@@ -1716,6 +1733,10 @@ extern "C" int dsw_ensemble_tune(dsw_ensemble *E, const dsw_fields *Un, dsw_fiel
   }
   rc = check_launch("ensemble tuning kernels");
   if (rc) return rc;
+  {
+    std::lock_guard<std::mutex> lk(cache_mu);
+    cache.emplace_back(key, out);
+  }
   E->cfg = out;
   for (dsw_grid *G : E->mem) G->cfg = out;
   if (best) *best = from_cfg(out);

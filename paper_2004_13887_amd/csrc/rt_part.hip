@@ -412,16 +412,21 @@ __host__ __device__ inline unsigned rt_scalar_wgs(const Geo &g, int d, unsigned 
 }
 
 // PART 0: block lines only; 1: scalar lines only; 2: block lines in
-// workgroups [0, nbw), then the scalar lines.  W: a forced pass.
-template <int D, int PM, int PART, bool W = false, bool TR = false, bool PT = false>
+// workgroups [0, nbw), then the scalar lines.  COMB: workgroups numbered as
+// for PART 2 whatever the part (a batched launch's member table counts both
+// kinds), those of the other part leaving at once; else PART 1 numbers the
+// scalar workgroups from 0.  W: a forced pass.
+template <int D, int PM, int PART, bool W = false, bool TR = false, bool PT = false, bool COMB = false>
 __device__ __forceinline__ void rt_body(const PassArgs &a, unsigned w, double *lds) {
   const Geo &g = a.g;
   decltype(auto) u = SrcSel<W, PT>::get(a);  // the plain source when TR
   const unsigned bs = blockDim.x;
-  const unsigned nbw = PART == 1 ? 0u : rt_block_wgs(g, D, bs, PM);
-  if (PART != 1 && w < nbw) {
-    const unsigned L = bs / (unsigned)rt_chunks<PM>(families(g, D).n);
-    rt_block_lines<D, PM, TR>(g, a.m, u, a.rhs, a.o, (long)w * L, a.tau, lds, a.status);
+  const unsigned nbw = (PART == 1 && !COMB) ? 0u : rt_block_wgs(g, D, bs, PM);
+  if (w < nbw) {
+    if constexpr (PART != 1) {
+      const unsigned L = bs / (unsigned)rt_chunks<PM>(families(g, D).n);
+      rt_block_lines<D, PM, TR>(g, a.m, u, a.rhs, a.o, (long)w * L, a.tau, lds, a.status);
+    }
     return;
   }
   if constexpr (PART != 0) {
@@ -441,7 +446,7 @@ __global__ void __launch_bounds__(256) k_rt_part(PassArgs a, Batch bt) {
   extern __shared__ double lds[];
   if constexpr (B) {
     const int mb = batch_member(bt, blockIdx.x);
-    rt_body<D, PM, PART>(batch_args(bt, mb), blockIdx.x - bt.woff[mb], lds);
+    rt_body<D, PM, PART, false, false, false, true>(batch_args(bt, mb), blockIdx.x - bt.woff[mb], lds);
   } else {
     rt_body<D, PM, PART>(a, xcd_contiguous(blockIdx.x, gridDim.x), lds);
   }
@@ -490,7 +495,14 @@ template <int D, int PM>
 static void launch_rt_d(const PassArgs &a, const Batch &b, unsigned blocks, unsigned threads, hipStream_t st) {
   const size_t lds = rt_part_lds(threads), lds_s = sizeof(double) * 4 * (size_t)threads;
   if (b.tab) {
-    hipLaunchKernelGGL((k_rt_part<D, PM, 2, true>), dim3(blocks), dim3(threads), lds, st, a, b);
+    // a batch: the members' block and scalar workgroups as two launches over
+    // the same table (each leaves the other kind's workgroups at once)
+    if (blocks < RT_SPLIT_WGS) {
+      hipLaunchKernelGGL((k_rt_part<D, PM, 2, true>), dim3(blocks), dim3(threads), lds, st, a, b);
+    } else {
+      hipLaunchKernelGGL((k_rt_part<D, PM, 0, true>), dim3(blocks), dim3(threads), lds, st, a, b);
+      hipLaunchKernelGGL((k_rt_part<D, PM, 1, true>), dim3(blocks), dim3(threads), lds_s, st, a, b);
+    }
     return;
   }
   if (blocks < RT_SPLIT_WGS) {
