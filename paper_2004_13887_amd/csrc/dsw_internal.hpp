@@ -103,6 +103,42 @@ struct SrcSel<true, false> {
   }
 };
 
+// The interior sources of a pass over slots whose stencils read no ghost
+// across an r or theta boundary (32-bit indices; P: periodic phi): plain,
+// perturbation-pressure form (PT) or forced (W).
+template <bool W, bool PT, bool P>
+struct SrcSelIn {
+  __device__ static __forceinline__ SrcOneT<true, P> get(const PassArgs &a) {
+    SrcOneT<true, P> s;
+#pragma unroll
+    for (int q = 0; q < 5; q++) s.a[q] = a.u.a[q];
+    return s;
+  }
+};
+template <bool P>
+struct SrcSelIn<false, true, P> {
+  __device__ static __forceinline__ SrcPert<SrcOneT<true, P>> get(const PassArgs &a) {
+    SrcPert<SrcOneT<true, P>> s;
+#pragma unroll
+    for (int q = 0; q < 5; q++) s.a[q] = a.u.a[q];
+    s.pref = a.pref;
+    s.tref = a.tref;
+    return s;
+  }
+};
+template <bool P>
+struct SrcSelIn<true, false, P> {
+  __device__ static __forceinline__ SrcInW<P> get(const PassArgs &a) {
+    SrcInW<P> s;
+#pragma unroll
+    for (int q = 0; q < 5; q++) s.a[q] = a.u.a[q];
+    s.w = a.wall;
+    s.f[F_P] = a.fsrc.p; s.f[F_UR] = a.fsrc.ur; s.f[F_UT] = a.fsrc.ut; s.f[F_UF] = a.fsrc.uf;
+    s.f[F_T] = a.fsrc.T;
+    return s;
+  }
+};
+
 // One launch over several grids.  Workgroup w belongs to member m with
 // woff[m] <= w < woff[m+1] (woff has n+1 entries, woff[0] = 0); tab[m] is
 // that member's PassArgs.  tab == nullptr: a single grid, passed by value.

@@ -299,6 +299,39 @@ __device__ __forceinline__ void scalar_row(const Geo &g, const Mat &m, const S &
 }
 
 
+// Forward elimination of one chunk of a scalar line (partitioned solvers):
+// rows a0 .. a0 + len - 2 with the left spike, x_q = Y_q - C_q x_{q+1} -
+// E_q x_left, and the chunk's last row (the separator) into S.  Every row of
+// the chunk is assembled first, without a branch (rows past the chunk's end
+// repeat its last row, clamped into the line; their results are not used),
+// so that the loads of all its rows are in flight together: a row assembled
+// under a branch on the chunk length waits for the previous row's
+// elimination before its loads issue.  row(s, R) assembles row s.  Returns
+// whether an eliminated row had a zero pivot.
+template <int PM, class RowFn>
+__device__ __forceinline__ bool scalar_chunk_fwd(const RowFn &row, int a0, int len, int n, double *Cm,
+                                                 double *Em, double *Ym, SRow &S) {
+  const int rl = min(a0 + max(len - 1, 0), n - 1);
+  SRow R[PM];
+#pragma unroll
+  for (int q = 0; q < PM; q++) row(min(a0 + q, rl), R[q]);
+  bool sing = false;
+#pragma unroll
+  for (int q = 0; q < PM - 1; q++) {
+    double dp = R[q].b, rr = R[q].r, lx = R[q].a;
+    if (q > 0) { dp -= R[q].a * Cm[q - 1]; rr -= R[q].a * Ym[q - 1]; lx = -R[q].a * Em[q - 1]; }
+    sing |= q < len - 1 && !(dp != 0.0);
+    const double id = 1.0 / dp;
+    Cm[q] = R[q].c * id;
+    Ym[q] = rr * id;
+    Em[q] = lx * id;
+  }
+#pragma unroll
+  for (int q = 0; q < PM; q++)
+    if (q == len - 1) S = R[q];
+  return sing;
+}
+
 // Row s of the line system, or of its transpose (TR): the transposed row s
 // has lower block U_{s-1}^T, diagonal D_s^T and upper block L_{s+1}^T, and
 // the right-hand side read at row s's unknowns.
