@@ -23,12 +23,13 @@ struct Edge {
   double lo[3], hi[2], hiw, slo, shi;
 };
 
-__device__ __forceinline__ void inv3(const double *A, double *X, int *status) {
+// X = A^{-1} (3x3); returns whether A is singular (a zero or non-finite
+// determinant)
+__device__ __forceinline__ bool inv3q(const double *A, double *X) {
   const double c00 = A[4] * A[8] - A[5] * A[7];
   const double c01 = A[5] * A[6] - A[3] * A[8];
   const double c02 = A[3] * A[7] - A[4] * A[6];
   const double det = A[0] * c00 + A[1] * c01 + A[2] * c02;
-  if (!(det != 0.0) || !isfinite(det)) status[ST_SINGULAR] = 1;
   const double id = 1.0 / det;
   X[0] = c00 * id;
   X[1] = (A[2] * A[7] - A[1] * A[8]) * id;
@@ -39,6 +40,11 @@ __device__ __forceinline__ void inv3(const double *A, double *X, int *status) {
   X[6] = c02 * id;
   X[7] = (A[1] * A[6] - A[0] * A[7]) * id;
   X[8] = (A[0] * A[4] - A[1] * A[3]) * id;
+  return !(det != 0.0) || !isfinite(det);
+}
+
+__device__ __forceinline__ void inv3(const double *A, double *X, int *status) {
+  if (inv3q(A, X)) status[ST_SINGULAR] = 1;
 }
 
 // C = A * B (3x3)

@@ -399,7 +399,7 @@ void launch_sweep_T(int d, const PassArgs &a, unsigned blocks, unsigned threads,
 // bottom half of a workgroup share a line; the middle data pass through LDS.
 template <int D, class S>
 __device__ __forceinline__ void twisted_block_line(const Geo &g, const Mat &m, const S &u, const Fields &rhs,
-                                   const Out &o, double *sc, long nl, long line, bool act, bool top,
+                                   const Out &o, double *__restrict__ sc, long nl, long line, bool act, bool top,
                                    int a, int b, int n, double hs, double *lds, int lane, int *status) {
 #define SC(s, q) sc[((long)(s) * 12 + (q)) * nl + line]
   constexpr int UNR = (D == 1 && !S::WALL) ? 2 : 1;  // theta lines: unrolled twice
@@ -407,6 +407,11 @@ __device__ __forceinline__ void twisted_block_line(const Geo &g, const Mat &m, c
   BRow R;
   double C[9], y[3], Ap[9], Ai[9], t9[9], t3[3];
   double *my = lds + (long)lane * 15;  // E'_{m+1} (9), z_{m+1} (3), x_m (3)
+  // A zero pivot is recorded once, after the elimination: a store (or a
+  // branch) inside the loop would hold the next row's loads back until the
+  // row before is done; so would the scratch stores, were the scratch array
+  // not declared unaliased.
+  bool sing = false;
   if (act) {
     if (top) {
       #pragma unroll UNR
@@ -426,7 +431,7 @@ __device__ __forceinline__ void twisted_block_line(const Geo &g, const Mat &m, c
 #pragma unroll
           for (int q = 0; q < 3; q++) t3[q] = R.b[q] - ly[q];
         }
-        inv3(Ap, Ai, status);
+        sing |= inv3q(Ap, Ai);
         mm3(Ai, R.U, C);
         mv3(Ai, t3, y);
 #pragma unroll
@@ -452,7 +457,7 @@ __device__ __forceinline__ void twisted_block_line(const Geo &g, const Mat &m, c
 #pragma unroll
           for (int q = 0; q < 3; q++) t3[q] = R.b[q] - uz[q];
         }
-        inv3(Ap, Ai, status);
+        sing |= inv3q(Ap, Ai);
         mm3(Ai, R.L, C);  // E'_s
         mv3(Ai, t3, y);   // z_s
 #pragma unroll
@@ -466,6 +471,7 @@ __device__ __forceinline__ void twisted_block_line(const Geo &g, const Mat &m, c
       for (int q = 0; q < 3; q++) my[9 + q] = y[q];
     }
   }
+  if (sing) status[ST_SINGULAR] = 1;
   __syncthreads();
   if (act && top) {  // middle row
     block_row<D>(g, m, u, rhs, a, b, mid, n, 0, hs, R);
@@ -528,7 +534,7 @@ __device__ __forceinline__ void twisted_block_line(const Geo &g, const Mat &m, c
 // row for the middle), not three times.  Lines have n >= 3, so 1 <= m < n - 1.
 template <int D>
 __device__ __forceinline__ void twisted_block_line_T(const Geo &g, const Mat &m, const SrcOne &u, const Fields &rhs,
-                                     const Out &o, double *sc, long nl, long line, bool act, bool top,
+                                     const Out &o, double *__restrict__ sc, long nl, long line, bool act, bool top,
                                      int a, int b, int n, double hs, double *lds, int lane, int *status) {
 #define SC(s, q) sc[((long)(s) * 12 + (q)) * nl + line]
   const int mid = n / 2;
@@ -540,6 +546,7 @@ __device__ __forceinline__ void twisted_block_line_T(const Geo &g, const Mat &m,
   for (int q = 0; q < 9; q++) C[q] = 0.0;
 #pragma unroll
   for (int q = 0; q < 3; q++) y[q] = 0.0;
+  bool sing = false;  // a zero pivot, recorded once after the elimination
   if (act) {
     if (top) {
       // window: Wa = U_{s-1}, Wd = D_s, Wb = U_s, wb = b_s
@@ -567,7 +574,7 @@ __device__ __forceinline__ void twisted_block_line_T(const Geo &g, const Mat &m,
 #pragma unroll
           for (int q = 0; q < 3; q++) t3[q] = wb[q] - ly[q];
         }
-        inv3(Ap, Ai, status);
+        sing |= inv3q(Ap, Ai);
         mm3(Ai, Ut, C);
         mv3(Ai, t3, y);
 #pragma unroll
@@ -605,7 +612,7 @@ __device__ __forceinline__ void twisted_block_line_T(const Geo &g, const Mat &m,
 #pragma unroll
           for (int q = 0; q < 3; q++) t3[q] = wb[q] - uz[q];
         }
-        inv3(Ap, Ai, status);
+        sing |= inv3q(Ap, Ai);
         mm3(Ai, Lt, C);  // E'_s
         mv3(Ai, t3, y);  // z_s
 #pragma unroll
@@ -623,6 +630,7 @@ __device__ __forceinline__ void twisted_block_line_T(const Geo &g, const Mat &m,
       for (int q = 0; q < 3; q++) my[9 + q] = y[q];
     }
   }
+  if (sing) status[ST_SINGULAR] = 1;
   __syncthreads();
   if (act && top) {  // middle row: the top window now holds U_{m-1}, D_m, U_m, b_m
     block_row<D>(g, m, u, rhs, a, b, mid + 1, n, 0, hs, R);
@@ -682,7 +690,7 @@ __device__ __forceinline__ void twisted_block_line_T(const Geo &g, const Mat &m,
 // z_{m+1}, x_m.
 template <int D, int FAM, class S>
 __device__ __forceinline__ void twisted_scalar_line(const Geo &g, const Mat &m, const S &u, const Fields &rhs,
-                                    const Out &o, double *sc, long nl, long line, bool act, bool top,
+                                    const Out &o, double *__restrict__ sc, long nl, long line, bool act, bool top,
                                     int a, int b, int n, double hs, double *lds, int lane, int *status) {
 #define SC(s, q) sc[((long)(s) * 2 + (q)) * nl + line]
   int ofid;
@@ -695,13 +703,14 @@ __device__ __forceinline__ void twisted_scalar_line(const Geo &g, const Mat &m, 
   long xi;
   double *arr;
   double cv = 0.0, yv = 0.0;
+  bool sing = false;  // recorded once, after the elimination (as for the block lines)
   if (act) {
     if (top) {
       #pragma unroll UNR
       for (int s = 0; s < mid; s++) {
         scalar_row<D, FAM>(g, m, u, rhs, a, b, s, n, 0, hs, R, xi, arr);
         const double den = R.b - R.a * cv;
-        if (!(den != 0.0)) status[ST_SINGULAR] = 1;
+        sing |= !(den != 0.0);
         const double id = 1.0 / den;
         yv = (R.r - R.a * yv) * id;
         cv = R.c * id;
@@ -713,7 +722,7 @@ __device__ __forceinline__ void twisted_scalar_line(const Geo &g, const Mat &m, 
       for (int s = n - 1; s > mid; s--) {
         scalar_row<D, FAM>(g, m, u, rhs, a, b, s, n, 0, hs, R, xi, arr);
         const double den = R.b - R.c * cv;
-        if (!(den != 0.0)) status[ST_SINGULAR] = 1;
+        sing |= !(den != 0.0);
         const double id = 1.0 / den;
         yv = (R.r - R.c * yv) * id;
         cv = R.a * id;
@@ -724,6 +733,7 @@ __device__ __forceinline__ void twisted_scalar_line(const Geo &g, const Mat &m, 
       my[1] = yv;
     }
   }
+  if (sing) status[ST_SINGULAR] = 1;
   __syncthreads();
   if (act && top) { // middle row
     scalar_row<D, FAM>(g, m, u, rhs, a, b, mid, n, 0, hs, R, xi, arr);
@@ -758,7 +768,7 @@ __device__ __forceinline__ void twisted_scalar_line(const Geo &g, const Mat &m, 
 // bottom: a_{s+1}, b_s, a_s, r_s), so every row is assembled once.
 template <int D, int FAM>
 __device__ __forceinline__ void twisted_scalar_line_T(const Geo &g, const Mat &m, const SrcOne &u, const Fields &rhs,
-                                      const Out &o, double *sc, long nl, long line, bool act, bool top,
+                                      const Out &o, double *__restrict__ sc, long nl, long line, bool act, bool top,
                                       int a, int b, int n, double hs, double *lds, int lane, int *status) {
 #define SC(s, q) sc[((long)(s) * 2 + (q)) * nl + line]
   int ofid;
@@ -771,6 +781,7 @@ __device__ __forceinline__ void twisted_scalar_line_T(const Geo &g, const Mat &m
   double *arr;
   double cv = 0.0, yv = 0.0;
   double w0 = 0.0, wb = 0.0, w1 = 0.0, wr = 0.0; // window
+  bool sing = false;  // a zero pivot, recorded once after the elimination
   if (act) {
     if (top) {
       // w0 = c_{s-1}, wb = b_s, w1 = c_s, wr = r_s
@@ -780,7 +791,7 @@ __device__ __forceinline__ void twisted_scalar_line_T(const Geo &g, const Mat &m
         scalar_row<D, FAM>(g, m, u, rhs, a, b, s + 1, n, 0, hs, R, xi, arr);
         const double at = w0, bt = wb, ct = R.a, rt = wr; // transposed row s
         const double den = bt - at * cv;
-        if (!(den != 0.0)) status[ST_SINGULAR] = 1;
+        sing |= !(den != 0.0);
         const double id = 1.0 / den;
         yv = (rt - at * yv) * id;
         cv = ct * id;
@@ -796,7 +807,7 @@ __device__ __forceinline__ void twisted_scalar_line_T(const Geo &g, const Mat &m
         scalar_row<D, FAM>(g, m, u, rhs, a, b, s - 1, n, 0, hs, R, xi, arr);
         const double at = R.c, bt = wb, ct = w0, rt = wr; // transposed row s
         const double den = bt - ct * cv;
-        if (!(den != 0.0)) status[ST_SINGULAR] = 1;
+        sing |= !(den != 0.0);
         const double id = 1.0 / den;
         yv = (rt - ct * yv) * id;
         cv = at * id;
@@ -808,6 +819,7 @@ __device__ __forceinline__ void twisted_scalar_line_T(const Geo &g, const Mat &m
       my[1] = yv;
     }
   }
+  if (sing) status[ST_SINGULAR] = 1;
   __syncthreads();
   if (act && top) { // middle row (c_{m-1}, b_m, a_{m+1}): the top window holds c_{m-1}, b_m, r_m
     scalar_row<D, FAM>(g, m, u, rhs, a, b, mid + 1, n, 0, hs, R, xi, arr);
