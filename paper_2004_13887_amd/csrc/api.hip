@@ -380,6 +380,32 @@ static Pass sweep_pass(const dsw_grid *G, int d, const Fields &ubar, double tau,
   return p;
 }
 
+// A two-ended r or theta pass as the passes that run it: where the
+// partitioned scalar-line solver takes the grid, the block lines two-ended
+// and then the scalar lines partitioned (which need no scratch), else the
+// pass itself.  Every plain sweep goes through here, so a grid's step, its
+// taped step, its line solves and an ensemble's batched launches all solve
+// the scalar lines the same way.  pad: every r and theta sweep gives two
+// passes, the second one PK_NONE where it has no scalar pass (an ensemble's
+// launch plan takes pass q of every member together).
+template <class Emit>
+static void emit_sweep(const dsw_grid *G, const Pass &p, Emit emit, bool pad = false) {
+  const int d = p.kind == PK_SW0T ? 0 : (p.kind == PK_SW1T ? 1 : -1);
+  Pass q = p;
+  if (d < 0 || !rt_scalar_supported(G->geo, d, (unsigned)G->cfg.sweep_bs[d])) {
+    emit(p);
+    if (pad && p.tk >= 1 && p.tk <= 2) {
+      q.kind = PK_NONE;
+      emit(q);
+    }
+    return;
+  }
+  q.kind = d == 0 ? PK_SW0B : PK_SW1B;
+  emit(q);
+  q.kind = d == 0 ? PK_SW0S : PK_SW1S;
+  emit(q);
+}
+
 // The workspace of one split step: the midpoint states of consecutive
 // iterations, the residual, the outputs of the r and theta sweeps, and the
 // sweep scratch.
@@ -408,7 +434,7 @@ static void plan_step(const dsw_grid *G, const Work &W, const Fields &un, const 
     Pass p = sweep_pass(G, d, ubar, tau, rhs, o);
     p.a.scb = W.sc.blk;
     p.a.scs = W.sc.sca;
-    emit(p);
+    emit_sweep(G, p, emit, true);
   };
   for (int it = 0; it < K; it++) {
     // midpoint state of this iteration: U^n itself at the first one, else the
@@ -441,9 +467,13 @@ static unsigned kind_threads(int kind, const Geo &g, const Cfg &c) {
   case PK_RES_INP: return (unsigned)c.res_bs;
   case PK_SW0:
   case PK_SW0T:
+  case PK_SW0B:
+  case PK_SW0S:
   case PK_SW0P: return (unsigned)c.sweep_bs[0];
   case PK_SW1:
   case PK_SW1T:
+  case PK_SW1B:
+  case PK_SW1S:
   case PK_SW1P: return (unsigned)c.sweep_bs[1];
   case PK_SW2_PART: return phi_part_threads(g, c.phi_pm);
   default: return 128u; // boundary copy, thread-per-line phi
@@ -462,6 +492,10 @@ static unsigned kind_blocks(int kind, const Geo &g, const Cfg &c, unsigned threa
   case PK_SW1: return cdiv(sweep_lines(g, 1), threads);
   case PK_SW0T: return sweep2_blocks(g, 0, threads);
   case PK_SW1T: return sweep2_blocks(g, 1, threads);
+  case PK_SW0B: return sweep2_block_blocks(g, 0, threads);
+  case PK_SW1B: return sweep2_block_blocks(g, 1, threads);
+  case PK_SW0S: return rt_scalar_blocks(g, 0, threads);
+  case PK_SW1S: return rt_scalar_blocks(g, 1, threads);
   case PK_SW0P: return rt_part_blocks(g, 0, threads, 4);
   case PK_SW1P: return rt_part_blocks(g, 1, threads, 4);
   case PK_SW2_LINE: return cdiv(sweep_lines(g, 2), threads);
@@ -471,6 +505,7 @@ static unsigned kind_blocks(int kind, const Geo &g, const Cfg &c, unsigned threa
 
 static size_t kind_lds(int kind, const Geo &g, const Cfg &c) {
   if (kind == PK_SW0P || kind == PK_SW1P) return rt_part_lds(kind_threads(kind, g, c));
+  if (kind == PK_SW0S || kind == PK_SW1S) return rt_scalar_lds(kind_threads(kind, g, c));
   return kind == PK_SW2_PART ? phi_part_lds(g, c.phi_pm) : 0;
 }
 
@@ -483,8 +518,12 @@ static void launch_kind(int kind, const Cfg &c, const PassArgs &a, const Batch &
   case PK_RES_INP: launch_residual_in_pass(true, a, b, blocks, threads, st); break;
   case PK_SW0: launch_sweep_pass(0, a, b, blocks, threads, st); break;
   case PK_SW1: launch_sweep_pass(1, a, b, blocks, threads, st); break;
-  case PK_SW0T: launch_sweep2_pass(0, a, b, blocks, threads, st); break;
-  case PK_SW1T: launch_sweep2_pass(1, a, b, blocks, threads, st); break;
+  case PK_SW0T:
+  case PK_SW0B: launch_sweep2_pass(0, a, b, blocks, threads, st); break;
+  case PK_SW1T:
+  case PK_SW1B: launch_sweep2_pass(1, a, b, blocks, threads, st); break;
+  case PK_SW0S: launch_rt_scalar_pass(0, a, b, blocks, threads, st); break;
+  case PK_SW1S: launch_rt_scalar_pass(1, a, b, blocks, threads, st); break;
   case PK_SW0P: launch_rt_pass(0, 4, a, b, blocks, threads, st); break;
   case PK_SW1P: launch_rt_pass(1, 4, a, b, blocks, threads, st); break;
   case PK_SW2_LINE: launch_sweep_pass(2, a, b, blocks, threads, st); break;
@@ -494,6 +533,7 @@ static void launch_kind(int kind, const Cfg &c, const PassArgs &a, const Batch &
 
 // one pass on one grid, arguments by value
 static void launch_single(const dsw_grid *G, const Pass &p, hipStream_t st) {
+  if (p.kind == PK_NONE) return;
   const unsigned th = kind_threads(p.kind, G->geo, G->cfg);
   const unsigned nb = kind_blocks(p.kind, G->geo, G->cfg, th);
   if (nb == 0) return;  // e.g. no interior workgroups on a tiny grid
@@ -513,7 +553,8 @@ static int line_solve(int d, dsw_grid *G, const dsw_fields *Ubar, double tau, co
   Out o{};
   o.x = F(x);
   o.mode = 0;
-  launch_single(G, sweep_pass(G, d, F(Ubar), tau, F(rhs), o), (hipStream_t)stream);
+  emit_sweep(G, sweep_pass(G, d, F(Ubar), tau, F(rhs), o),
+             [&](const Pass &q) { launch_single(G, q, (hipStream_t)stream); });
   return check_launch("sweep kernel");
 }
 
@@ -549,11 +590,17 @@ extern "C" int dsw_split_step(dsw_grid *G, const dsw_fields *Un, dsw_fields *Unp
   hipStream_t st = (hipStream_t)stream;
   std::vector<Pass> plan;
   plan_step(G, own_work(G), F(Un), F(Unp1), tau, K, [&](const Pass &p) { plan.push_back(p); });
-  // consecutive launches of one kind (the two residual launches) are timed together
+  // the launches of one pass (the residual's interior and boundary
+  // launches, a sweep's block and scalar lines) are timed together
   for (size_t q = 0; q < plan.size();) {
+    if (plan[q].kind == PK_NONE) {
+      q++;
+      continue;
+    }
     size_t e = q + 1;
     while (e < plan.size() && plan[e].tk == plan[q].tk && plan[e].kind != plan[q].kind &&
-           (plan[q].kind == PK_RES_IN || plan[q].kind == PK_RES_INP))
+           (plan[q].kind == PK_RES_IN || plan[q].kind == PK_RES_INP || plan[q].kind == PK_SW0B ||
+            plan[q].kind == PK_SW1B))
       e++;
     timed(G, plan[q].tk, st, [&] {
       for (size_t r = q; r < e; r++) launch_single(G, plan[r], st);
@@ -597,6 +644,7 @@ extern "C" int dsw_split_step_pert(dsw_grid *G, const dsw_fields *Un, dsw_fields
   hipStream_t st = (hipStream_t)stream;
   for (const Pass &p : plan) {
     if (p.kind == PK_RES_IN || p.kind == PK_RES_INP) continue;  // inside the PK_RES launch below
+    if (p.kind == PK_SW0S || p.kind == PK_SW1S || p.kind == PK_NONE) continue;  // inside the two-ended launch below
     PassArgs a = p.a;
     a.pref = G->ref_mem;
     a.tref = G->ref_mem + g.nr;
@@ -607,8 +655,10 @@ extern "C" int dsw_split_step_pert(dsw_grid *G, const dsw_fields *Un, dsw_fields
       case PK_RES: launch_residual_pert(a, kind_blocks(PK_RES, g, G->cfg, th), th, st); break;
       case PK_SW0P: launch_rt_pert(0, a, th, st); break;
       case PK_SW1P: launch_rt_pert(1, a, th, st); break;
-      case PK_SW0T: launch_sweep2_pert(0, a, sweep2_blocks(g, 0, th), th, st); break;
-      case PK_SW1T: launch_sweep2_pert(1, a, sweep2_blocks(g, 1, th), th, st); break;
+      case PK_SW0T:
+      case PK_SW0B: launch_sweep2_pert(0, a, sweep2_blocks(g, 0, th), th, st); break;
+      case PK_SW1T:
+      case PK_SW1B: launch_sweep2_pert(1, a, sweep2_blocks(g, 1, th), th, st); break;
       default:  // PK_SW2_PART
         launch_phi_pert(G->cfg.phi_pm, a, kind_blocks(p.kind, g, G->cfg, th), th, kind_lds(p.kind, g, G->cfg), st);
       }
@@ -1105,9 +1155,10 @@ static void adj_record_iter(const dsw_grid *G, const Fields &un, double tau, int
     p.a.scs = scr.sca;
     return p;
   };
-  launch_single(G, sw(0, G->r, o1), st);
-  launch_single(G, sw(1, t.x1[k], o2), st);
-  launch_single(G, sw(2, t.x2[k], o3), st);
+  const auto run = [&](const Pass &q) { launch_single(G, q, st); };
+  emit_sweep(G, sw(0, G->r, o1), run);
+  emit_sweep(G, sw(1, t.x1[k], o2), run);
+  emit_sweep(G, sw(2, t.x2[k], o3), run);
 }
 
 static void adj_record(const dsw_grid *G, const Fields &un, double tau, int K, const Tape &t,
@@ -1477,7 +1528,11 @@ static int build_plan(dsw_ensemble *E, const Cfg &cfg, const dsw_fields *Un, dsw
               [&](const Pass &p) { per[m].push_back(p); });
     G->cfg = keep;
   }
+  // plan_step gives every grid the same sequence of passes (PK_NONE where a
+  // grid's sweep has one pass fewer): pass q of every member runs together
   const size_t npass = per[0].size();
+  for (int m = 1; m < n; m++)
+    if (per[m].size() != npass) return fail(DSW_EINVAL, "ensemble members' steps do not align");
   std::vector<char> host;
   auto append = [&](const void *src, size_t bytes) {
     size_t off = (host.size() + 255) & ~size_t(255);
@@ -1488,7 +1543,8 @@ static int build_plan(dsw_ensemble *E, const Cfg &cfg, const dsw_fields *Un, dsw
   for (size_t q = 0; q < npass; q++) {
     std::vector<int> kinds;  // distinct kinds of pass q over the members, in order
     for (int m = 0; m < n; m++)
-      if (std::find(kinds.begin(), kinds.end(), per[m][q].kind) == kinds.end()) kinds.push_back(per[m][q].kind);
+      if (per[m][q].kind != PK_NONE && std::find(kinds.begin(), kinds.end(), per[m][q].kind) == kinds.end())
+        kinds.push_back(per[m][q].kind);
     for (const int kind : kinds) {
       // one launch per (kind, workgroup width): members whose phi lines need
       // narrower workgroups do not pay for the widest one

@@ -172,8 +172,14 @@ struct Cfg {
                    // partitioned (4 rows per thread on the block lines)
 };
 
+// PK_SW0T / PK_SW1T: a two-ended r / theta sweep over every line; where the
+// partitioned scalar-line solver takes the grid it runs as two passes, the
+// block lines two-ended (PK_SW0B / PK_SW1B) and then the scalar lines
+// partitioned (PK_SW0S / PK_SW1S).  PK_NONE: a pass that launches nothing
+// (it keeps the passes of different grids' steps aligned).
 enum PassKind { PK_BND = 0, PK_RES = 1, PK_SW0 = 2, PK_SW1 = 3, PK_SW2_LINE = 4, PK_SW2_PART = 5,
-                PK_RES_IN = 6, PK_SW0T = 7, PK_SW1T = 8, PK_RES_INP = 9, PK_SW0P = 10, PK_SW1P = 11 };
+                PK_RES_IN = 6, PK_SW0T = 7, PK_SW1T = 8, PK_RES_INP = 9, PK_SW0P = 10, PK_SW1P = 11,
+                PK_SW0B = 12, PK_SW1B = 13, PK_SW0S = 14, PK_SW1S = 15, PK_NONE = 16 };
 
 // forced split step (source term, wall velocities, Dirichlet data at the new
 // time level): one grid, the general residual over every point, the
@@ -197,6 +203,13 @@ void launch_phi_forced(int pm, const PassArgs &a, unsigned blocks, unsigned thre
 void launch_rt_forced(int d, int pm, const PassArgs &a, unsigned threads, hipStream_t st);
 // transposed r systems (adjoint) by the partitioned solver (d = 0 only)
 void launch_rt_T(int d, const PassArgs &a, unsigned threads, hipStream_t st);
+// the scalar lines of an r or theta sweep alone, partitioned (one grid or a
+// batch; workgroups numbered from 0 per grid)
+bool rt_scalar_supported(const Geo &g, int d, unsigned bs);
+unsigned rt_scalar_blocks(const Geo &g, int d, unsigned bs);
+size_t rt_scalar_lds(unsigned bs);
+void launch_rt_scalar_pass(int d, const PassArgs &a, const Batch &b, unsigned blocks, unsigned threads,
+                           hipStream_t st);
 // the r / theta solver a grid takes by default (4 partitioned, 0 two-ended)
 int rt_default_pm(const Geo &g, int d);
 
@@ -223,6 +236,8 @@ unsigned sweep_lines(const Geo &g, int d);   // lines of all families of sweep d
 void launch_sweep2_pass(int d, const PassArgs &a, const Batch &b, unsigned blocks, unsigned threads,
                         hipStream_t st);
 unsigned sweep2_blocks(const Geo &g, int d, unsigned bs);
+// the block-line workgroups alone of a two-ended r or theta sweep
+unsigned sweep2_block_blocks(const Geo &g, int d, unsigned bs);
 // r and theta sweeps, partitioned: workgroups of bs threads, each on a few
 // neighbouring lines split into chunks (block lines, then scalar lines)
 // (pm rows per thread on the block lines: 4)

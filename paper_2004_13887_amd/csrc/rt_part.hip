@@ -555,6 +555,43 @@ void launch_rt_T(int d, const PassArgs &a, unsigned threads, hipStream_t st) {
   launch_rt_T_d<0, 4>(a, threads, st);
 }
 
+bool rt_scalar_supported(const Geo &g, int d, unsigned bs) {
+  return d < 2 && bs <= 256 && rt_chunks<RT_PMS>(families(g, d).n) <= (int)bs && rt_scalar_wgs(g, d, bs) > 0;
+}
+
+unsigned rt_scalar_blocks(const Geo &g, int d, unsigned bs) { return rt_scalar_wgs(g, d, bs); }
+
+size_t rt_scalar_lds(unsigned bs) { return sizeof(double) * 4 * (size_t)bs; }
+
+// The scalar lines of an r or theta sweep alone (after a two-ended solve of
+// its block lines): one grid (workgroups numbered XCD-contiguously) or a
+// batch (each member's scalar workgroups from 0).  Without the scalar lines
+// the two-ended solve's scratch traffic drops by a sixth: theta on the
+// 512 x 256 x 128 sphere 1.53 -> 1.43 ms.
+template <int D, bool B>
+__global__ void __launch_bounds__(256) k_rt_scal(PassArgs a, Batch bt) {
+  extern __shared__ double lds[];
+  if constexpr (B) {
+    const int mb = batch_member(bt, blockIdx.x);
+    rt_body<D, 4, 1>(batch_args(bt, mb), blockIdx.x - bt.woff[mb], lds);
+  } else {
+    rt_body<D, 4, 1>(a, xcd_contiguous(blockIdx.x, gridDim.x), lds);
+  }
+}
+
+void launch_rt_scalar_pass(int d, const PassArgs &a, const Batch &b, unsigned blocks, unsigned threads,
+                           hipStream_t st) {
+  const size_t lds = rt_scalar_lds(threads);
+  const dim3 gr(blocks), bl(threads);
+  if (b.tab) {
+    if (d == 0) hipLaunchKernelGGL((k_rt_scal<0, true>), gr, bl, lds, st, a, b);
+    else hipLaunchKernelGGL((k_rt_scal<1, true>), gr, bl, lds, st, a, b);
+  } else {
+    if (d == 0) hipLaunchKernelGGL((k_rt_scal<0, false>), gr, bl, lds, st, a, b);
+    else hipLaunchKernelGGL((k_rt_scal<1, false>), gr, bl, lds, st, a, b);
+  }
+}
+
 // the solver a grid takes by default: partitioned where a block line
 // splits into at most 32 chunks (L >= 8 neighbouring lines per 256-thread
 // workgroup), else two-ended.  Measured: partitioned r 0.16 / theta 0.19 ms

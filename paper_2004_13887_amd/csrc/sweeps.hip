@@ -969,6 +969,8 @@ void launch_sweep2_T(int d, const PassArgs &a, unsigned blocks, unsigned threads
 
 // workgroups of a two-ended r or theta sweep: the block lines, then the
 // scalar lines of each family, two threads per line
+unsigned sweep2_block_blocks(const Geo &g, int d, unsigned bs) { return twisted_block_wgs(g, d, bs); }
+
 unsigned sweep2_blocks(const Geo &g, int d, unsigned bs) {
   const Families F = families(g, d);
   const long lpw = bs / 2;
