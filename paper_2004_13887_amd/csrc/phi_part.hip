@@ -14,6 +14,8 @@
 //      reduction, log2(#chunks) steps;
 //   3. interior rows are filled in from the separators.
 // All intermediates stay in registers and LDS: no scratch traffic.
+#include <algorithm>
+
 #include "rows.hpp"
 
 namespace dsw {
@@ -125,6 +127,56 @@ __device__ __forceinline__ void pcr_scalar(int t, int T, int cyc, double &A, dou
     const double S = A + B + C;
     if (!(S != 0.0)) status[ST_SINGULAR] = 1;
     x = r / S;
+  }
+}
+
+// Two independent scalar systems of the same size T, reduced side by side:
+// the steps of pcr_scalar for each, under one set of barriers.  LDS: system
+// f at lds + 4 T f (8 T doubles).
+__device__ __forceinline__ void pcr_scalar2(int t, int T, int cyc, double *A, double *B, double *C, double *r,
+                                            double *lds, double *x, int *status) {
+  const bool act = t < T;
+  for (int h = 1; h < T; h *= 2) {
+    if (act) {
+#pragma unroll
+      for (int f = 0; f < 2; f++) {
+        double *L = lds + 4 * T * f;
+        L[t] = A[f]; L[T + t] = C[f]; L[2 * T + t] = r[f]; L[3 * T + t] = B[f];
+      }
+    }
+    __syncthreads();
+    if (act) {
+      int lo = t - h, hi = t + h;
+      bool has_lo = lo >= 0, has_hi = hi < T;
+      if (cyc) { lo = (lo % T + T) % T; hi = hi % T; has_lo = has_hi = true; }
+#pragma unroll
+      for (int f = 0; f < 2; f++) {
+        const double *sA = lds + 4 * T * f, *sC = sA + T, *sR = sA + 2 * T, *sB = sA + 3 * T;
+        double nA = 0.0, nC = 0.0, nB = B[f], nr = r[f];
+        if (has_lo) {
+          const double al = -A[f] / sB[lo];
+          nA = al * sA[lo];
+          nB += al * sC[lo];
+          nr += al * sR[lo];
+        }
+        if (has_hi) {
+          const double be = -C[f] / sB[hi];
+          nC = be * sC[hi];
+          nB += be * sA[hi];
+          nr += be * sR[hi];
+        }
+        A[f] = nA; B[f] = nB; C[f] = nC; r[f] = nr;
+      }
+    }
+    __syncthreads();
+  }
+  if (act) {
+#pragma unroll
+    for (int f = 0; f < 2; f++) {
+      const double S = A[f] + B[f] + C[f];
+      if (!(S != 0.0)) status[ST_SINGULAR] = 1;
+      x[f] = r[f] / S;
+    }
   }
 }
 
@@ -400,6 +452,112 @@ __device__ __forceinline__ void part_scalar_line(const Geo &g, const Mat &m, con
   __syncthreads();
 }
 
+// Both scalar lines of slot (i, j) at once (u_r on r-face i, u_theta on
+// theta-face j; both must exist, as at the interior slots): the steps of
+// part_scalar_line for each line, with the rows of both lines assembled
+// before either is eliminated and one set of barriers for the two
+// reductions, so that each line's load and barrier latency overlaps the
+// other's.  LDS: 10 doubles per chunk (line f's exchange and reduction at
+// 4 T f, its separators at 8 T + T f; the staged lines at N f).
+template <int PM, class US>
+__device__ __forceinline__ void part_scalar_lines2(const Geo &g, const Mat &m, const US &u, const Fields &rhs,
+                                                   const Out &o, int i, int j, double hs, double *lds,
+                                                   int *status) {
+  const int N = g.np, T = part_chunks<PM>(N), cyc = g.periodic;
+  const int t = threadIdx.x;
+  const bool act = t < T;
+  const int a0 = t * PM;
+  const int len = act ? min(PM, N - a0) : 0;
+  double Cm[2][PM - 1], Em[2][PM - 1], Ym[2][PM - 1];
+  SRow S[2] = {{0, 1, 0, 0}, {0, 1, 0, 0}};
+  {
+    long xi;
+    double *arr;
+    const auto row0 = [&](int s, SRow &Q) { scalar_row<2, 0>(g, m, u, rhs, i, j, s, N, cyc, hs, Q, xi, arr); };
+    const auto row1 = [&](int s, SRow &Q) { scalar_row<2, 1>(g, m, u, rhs, i, j, s, N, cyc, hs, Q, xi, arr); };
+    const bool s0 = scalar_chunk_fwd<PM>(row0, a0, len, N, Cm[0], Em[0], Ym[0], S[0]);
+    const bool s1 = scalar_chunk_fwd<PM>(row1, a0, len, N, Cm[1], Em[1], Ym[1], S[1]);
+    if (s0 || s1) status[ST_SINGULAR] = 1;
+  }
+#pragma unroll
+  for (int f = 0; f < 2; f++) {
+#pragma unroll
+    for (int q = PM - 2; q >= 0; q--) {
+      if (q == len - 2) { Em[f][q] = -Em[f][q]; Cm[f][q] = -Cm[f][q]; }
+      else if (q < len - 2) {
+        Ym[f][q] -= Cm[f][q] * Ym[f][q + 1];
+        Em[f][q] = -Em[f][q] - Cm[f][q] * Em[f][q + 1];
+        Cm[f][q] = -Cm[f][q] * Cm[f][q + 1];
+      }
+    }
+  }
+  if (act) {
+#pragma unroll
+    for (int f = 0; f < 2; f++) {
+      double *sG = lds + 4 * T * f, *sV = sG + T, *sW = sG + 2 * T, *sL = sG + 3 * T;
+      sL[t] = (double)len;
+      if (len >= 2) { sG[t] = Ym[f][0]; sV[t] = Em[f][0]; sW[t] = Cm[f][0]; }
+    }
+  }
+  __syncthreads();
+  double A[2] = {0.0, 0.0}, B[2] = {1.0, 1.0}, C[2] = {0.0, 0.0}, r[2] = {0.0, 0.0};
+  if (act) {
+    int nt_ = t + 1;
+    bool has_next = nt_ < T;
+    if (cyc) { nt_ %= T; has_next = true; }
+#pragma unroll
+    for (int f = 0; f < 2; f++) {
+      const double *sG = lds + 4 * T * f, *sV = sG + T, *sW = sG + 2 * T, *sL = sG + 3 * T;
+      const int nlen = has_next ? (int)sL[nt_] : 0;
+      double Gl = 0.0, Vl = 0.0, Wl = 0.0;
+#pragma unroll
+      for (int q = 0; q < PM - 1; q++)
+        if (q == len - 2) { Gl = Ym[f][q]; Vl = Em[f][q]; Wl = Cm[f][q]; }
+      B[f] = S[f].b;
+      r[f] = S[f].r;
+      if (len >= 2) { A[f] = S[f].a * Vl; B[f] += S[f].a * Wl; r[f] -= S[f].a * Gl; }
+      else A[f] = S[f].a;
+      if (nlen >= 2) { B[f] += S[f].c * sV[nt_]; C[f] = S[f].c * sW[nt_]; r[f] -= S[f].c * sG[nt_]; }
+      else C[f] = S[f].c;
+    }
+  }
+  __syncthreads();
+  double xs[2] = {0.0, 0.0};
+  pcr_scalar2(t, T, cyc, A, B, C, r, lds, xs, status);
+  if (act) {
+    lds[8 * T + t] = xs[0];
+    lds[9 * T + t] = xs[1];
+  }
+  __syncthreads();
+  double val[2][PM];
+  if (act) {
+#pragma unroll
+    for (int f = 0; f < 2; f++) {
+      double xl = 0.0;
+      if (t > 0 || cyc) xl = lds[(8 + f) * T + (t > 0 ? t - 1 : T - 1)];
+#pragma unroll
+      for (int q = 0; q < PM - 1; q++)
+        if (q < len - 1) val[f][q] = Ym[f][q] + Em[f][q] * xl + Cm[f][q] * xs[f];
+    }
+  }
+  __syncthreads(); // the LDS is free: stage both lines, store them contiguously
+  if (act) {
+#pragma unroll
+    for (int f = 0; f < 2; f++) {
+#pragma unroll
+      for (int q = 0; q < PM - 1; q++)
+        if (q < len - 1) lds[f * N + a0 + q] = val[f][q];
+      lds[f * N + a0 + len - 1] = xs[f];
+    }
+  }
+  __syncthreads();
+  for (int s = t; s < N; s += blockDim.x) {
+    put(o, F_UR, idx_r(g, i, j, s), lds[s]);
+    put(o, F_UT, idx_t(g, i, j, s), lds[N + s]);
+  }
+  __syncthreads();
+}
+
 // one workgroup per (i, j): block line (i, j), u_r line on r-face i (i >= 1),
 // u_theta line on theta-face j (j >= 1).  Flat grid of nr * nt workgroups per
 // grid; one grid or a batch of grids.  The workgroup may be wider than the
@@ -449,8 +607,12 @@ __device__ __forceinline__ void phi_body(const PassArgs &a, unsigned w, double *
     const auto u = SrcSelIn<W, PT, P>::get(a);
     if (PART != 1) part_block_line<PM, TR>(g, a.m, u, a.rhs, o, i, j, a.tau, lds, a.status);
     if (PART != 0) {
-      part_scalar_line<PM, 0, TR>(g, a.m, u, a.rhs, o, i, j, a.tau, lds, a.status);
-      part_scalar_line<PM, 1, TR>(g, a.m, u, a.rhs, o, i, j, a.tau, lds, a.status);
+      if constexpr (TR) {
+        part_scalar_line<PM, 0, TR>(g, a.m, u, a.rhs, o, i, j, a.tau, lds, a.status);
+        part_scalar_line<PM, 1, TR>(g, a.m, u, a.rhs, o, i, j, a.tau, lds, a.status);
+      } else {
+        part_scalar_lines2<PM>(g, a.m, u, a.rhs, o, i, j, a.tau, lds, a.status);
+      }
     }
   } else {
     // W: forced pass (wall velocities); PT: perturbation-pressure form
@@ -568,13 +730,14 @@ static bool phi_interior_split(const Geo &g) {
 template <int PM, bool PT>
 static void launch_phi_in(const PassArgs &a, unsigned threads, size_t lds, size_t lds_s, hipStream_t st) {
   const Geo &g = a.g;
+  const size_t lds_s2 = sizeof(double) * 10 * (size_t)threads;  // both scalar lines of a slot at once
   const dim3 gin((unsigned)(g.nr - 2) * (unsigned)(g.nt - 2)), gbd(2u * (unsigned)g.nr + 2u * (unsigned)(g.nt - 2));
   const dim3 bl(threads);
   if (g.periodic) hipLaunchKernelGGL((k_phi_partI<PM, 0, 1, true, PT>), gin, bl, lds, st, a);
   else hipLaunchKernelGGL((k_phi_partI<PM, 0, 1, false, PT>), gin, bl, lds, st, a);
   hipLaunchKernelGGL((k_phi_partI<PM, 0, 2, false, PT>), gbd, bl, lds, st, a);
-  if (g.periodic) hipLaunchKernelGGL((k_phi_partI<PM, 1, 1, true, PT>), gin, bl, lds_s, st, a);
-  else hipLaunchKernelGGL((k_phi_partI<PM, 1, 1, false, PT>), gin, bl, lds_s, st, a);
+  if (g.periodic) hipLaunchKernelGGL((k_phi_partI<PM, 1, 1, true, PT>), gin, bl, lds_s2, st, a);
+  else hipLaunchKernelGGL((k_phi_partI<PM, 1, 1, false, PT>), gin, bl, lds_s2, st, a);
   hipLaunchKernelGGL((k_phi_partI<PM, 1, 2, false, PT>), gbd, bl, lds_s, st, a);
 }
 
@@ -647,6 +810,8 @@ template <int PM, int MAP>
 static void launch_phi_forced_map(const PassArgs &a, unsigned blocks, unsigned threads, size_t lds,
                                   size_t lds_s, bool split, hipStream_t st) {
   if (!blocks) return;
+  // the interior slots solve both scalar lines at once: 10 doubles per thread
+  if (MAP == 1) lds_s = std::max(lds_s, sizeof(double) * 10 * (size_t)threads);
   const dim3 gr(blocks), bl(threads);
   if constexpr (MAP == 1) {
     if (a.g.periodic) {
