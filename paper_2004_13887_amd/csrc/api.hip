@@ -485,7 +485,7 @@ static unsigned cdiv(unsigned long a, unsigned b) { return (unsigned)((a + b - 1
 static unsigned kind_blocks(int kind, const Geo &g, const Cfg &c, unsigned threads) {
   switch (kind) {
   case PK_BND: return cdiv(bnd_points(g), threads);
-  case PK_RES: return cdiv((unsigned long)g.npf, threads) * (unsigned)(g.nt + 1) * (unsigned)(g.nr + 1);
+  case PK_RES: return residual_general_blocks(g, (int)threads);
   case PK_RES_IN:
   case PK_RES_INP: return residual_interior_blocks(g, (int)threads);
   case PK_SW0: return cdiv(sweep_lines(g, 0), threads);
@@ -808,7 +808,7 @@ extern "C" int dsw_split_step_forced(dsw_grid *G, const dsw_fields *Un, dsw_fiel
     r.R = G->r;
     r.wall = w;
     if (src) r.fsrc = F(src);
-    launch_residual_forced(r, cdiv((unsigned long)g.npf, rbs) * (unsigned)(g.nt + 1) * (unsigned)(g.nr + 1), rbs, st);
+    launch_residual_forced(r, residual_general_blocks(g, (int)rbs), rbs, st);
     Out o1{}, o2{}, o3{};
     o1.x = G->x1; o1.mode = 0;
     o2.x = G->x2; o2.mode = 0;

@@ -225,6 +225,9 @@ void launch_residual_pass(const PassArgs &a, const Batch &b, unsigned blocks, un
 void launch_residual_in_pass(bool periodic, const PassArgs &a, const Batch &b, unsigned blocks,
                              unsigned threads, hipStream_t st);
 unsigned residual_interior_blocks(const Geo &g, int bs); // workgroups of the interior launch
+// workgroups of the general residual launch (the shell when the interior
+// launch runs, else every point)
+unsigned residual_general_blocks(const Geo &g, int bs);
 void launch_sweep_pass(int d, const PassArgs &a, const Batch &b, unsigned blocks, unsigned threads,
                        hipStream_t st);
 void launch_phi_pass(int pm, const PassArgs &a, const Batch &b, unsigned blocks, unsigned threads,

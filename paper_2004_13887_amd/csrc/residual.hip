@@ -268,18 +268,44 @@ __host__ __device__ inline unsigned res_interior_blocks(const Geo &g, int bs) {
   return (unsigned)res_nk(g, bs) * (unsigned)(g.nt - 2) * (unsigned)(g.nr - 2);
 }
 
+// The (i, j) pairs the general launch takes when the interior launch runs:
+// the shell around the interior, i in {0, nr-1, nr} for every j, then j in
+// {0, nt-1, nt} for 1 <= i <= nr-2; else every pair.  Workgroups per pair:
+// the phi blocks.
+__host__ __device__ inline unsigned res_shell_pairs(const Geo &g) {
+  return 3u * (unsigned)(g.nt + 1) + 3u * (unsigned)(g.nr - 2);
+}
+__host__ __device__ inline unsigned res_general_blocks(const Geo &g, int bs) {
+  const unsigned pairs = res_interior_blocks(g, bs) ? res_shell_pairs(g) : (unsigned)(g.nt + 1) * (unsigned)(g.nr + 1);
+  return (unsigned)res_nk(g, bs) * pairs;
+}
+
 // W: a forced pass (wall velocities and source term); PT: the
 // perturbation-pressure form
 template <bool W = false, bool PT = false>
 __device__ __forceinline__ void residual_body(const PassArgs &a, unsigned w) {
   const Geo &g = a.g;
-  const unsigned nkb = (g.npf + blockDim.x - 1) / blockDim.x;
-  const unsigned kb = w % nkb, rest = w / nkb;
-  const int j = (int)(rest % (g.nt + 1)), i = (int)(rest / (g.nt + 1));
   const int bs = (int)blockDim.x;
-  const bool interior = res_interior_blocks(g, bs) > 0 && i >= 1 && i <= g.nr - 2 && j >= 1 &&
-                        j <= g.nt - 2;
-  if (interior) return;  // done by the interior launch
+  const unsigned nkb = (unsigned)res_nk(g, bs);
+  const unsigned kb = w % nkb, rest = w / nkb;
+  int i, j;
+  if (res_interior_blocks(g, bs) > 0) {  // the shell (the interior launch does the rest)
+    const unsigned na = 3u * (unsigned)(g.nt + 1);
+    if (rest < na) {
+      const unsigned ia = rest / (unsigned)(g.nt + 1);
+      j = (int)(rest % (unsigned)(g.nt + 1));
+      i = ia == 0 ? 0 : (ia == 1 ? g.nr - 1 : g.nr);
+    } else {
+      const unsigned r2 = rest - na;
+      if (r2 >= 3u * (unsigned)(g.nr - 2)) return;
+      const unsigned jb = r2 % 3u;
+      i = 1 + (int)(r2 / 3u);
+      j = jb == 0 ? 0 : (jb == 1 ? g.nt - 1 : g.nt);
+    }
+  } else {
+    j = (int)(rest % (g.nt + 1));
+    i = (int)(rest / (g.nt + 1));
+  }
   decltype(auto) s = SrcSel<W, PT>::get(a);
   residual_point<std::decay_t<decltype(s)>, false>(g, a.m, s, a.d, a.tau, a.R, Fields{}, a.status, i, j,
                                                    (int)(kb * blockDim.x + threadIdx.x));
@@ -411,6 +437,7 @@ __global__ void __launch_bounds__(256) k_residual_in(PassArgs a, Batch bt) {
 }
 
 unsigned residual_interior_blocks(const Geo &g, int bs) { return res_interior_blocks(g, bs); }
+unsigned residual_general_blocks(const Geo &g, int bs) { return res_general_blocks(g, bs); }
 
 static void set5(const double **dst, const Fields &f) {
   dst[F_P] = f.p; dst[F_UR] = f.ur; dst[F_UT] = f.ut; dst[F_UF] = f.uf; dst[F_T] = f.T;
