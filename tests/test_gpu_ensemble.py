@@ -104,6 +104,36 @@ def test_ensemble_matches_oracle_and_member_steps(dsw):
         assert max(e[k] for k in FIELDS) <= TOL
 
 
+def test_members_whose_theta_sweeps_plan_different_passes(dsw):
+    """theta lines of 256 rows take the two-ended solver with the scalar
+    lines in a partitioned pass of their own; 200 rows, the two-ended solver
+    in one pass (its chunks would not fill a workgroup); 64 rows, the
+    partitioned solver.  The members' passes stay aligned in the batched
+    plan: bitwise equal to their own steps, and against the oracle."""
+    def sec(nr, nt, np_, seed):
+        return I.Workload(f"sec{seed}", I.sector(nr, nt, np_, math.radians(20) / nt,
+                                                 math.radians(24) / np_),
+                          mach=1e-2, amplitude=0.5, steps=1, K=K, seed=seed)
+
+    ws = [sec(4, 200, 6, 312), sec(4, 256, 8, 311), sec(5, 64, 10, 313)]
+    print("[ensemble] theta passes:", [(w.grid.nr, w.grid.nt, w.grid.np) for w in ws], flush=True)
+    E, U0, taus = _make(dsw, ws)
+    dU0 = [dsw.to_device(u) for u in U0]
+    out = [g.empty() for g in E.members]
+    E.ensemble_step(dU0, out, taus, K)
+    torch.cuda.synchronize()
+    E.get_status()
+    ref = _per_member(E, dU0, taus)
+    torch.cuda.synchronize()
+    _assert_same(out, ref, "ensemble vs split_step")
+    for m, w in enumerate(ws):
+        og = oracle.Grid(*w.grid.args())
+        om = oracle.Material(*w.material.astuple())
+        U1_o = oracle.split_step(og, om, U0[m], taus[m], K)
+        e = compare(f"member {m}", dsw.to_host(out[m]), U1_o, base=U0[m])
+        assert max(e[k] for k in FIELDS) <= TOL
+
+
 def test_graph_replays_and_ping_pong(dsw):
     """replay the captured graph several times with eager work and
     synchronisations in between; alternate two pointer sets (two graphs)"""
