@@ -649,13 +649,18 @@ __global__ void __launch_bounds__(256) DSW_OCC(DSW_WAVES_PHI) k_phi_partP(PassAr
   phi_body<PM, false, PART, false, 0, false, true>(a, w, lds);
 }
 
-// one grid, the interior slots (MAP 1; P: periodic phi) or the boundary ring
-// (MAP 2) as their own launches (PT: perturbation-pressure form)
-template <int PM, int PART, int MAP, bool P, bool PT>
-__global__ void __launch_bounds__(256) DSW_OCC(DSW_WAVES_PHI) k_phi_partI(PassArgs a) {
+// one grid, every slot: the boundary ring's slots (MAP 2, the general
+// source) in workgroups [0, ring), then the interior slots (MAP 1, the
+// interior source; P: periodic phi); PT: perturbation-pressure form.  One
+// launch instead of one per slot set: the ring's few hundred workgroups fill
+// the interior launch's tail instead of running as a launch of their own.
+template <int PM, int PART, bool P, bool PT>
+__global__ void __launch_bounds__(256) DSW_OCC(DSW_WAVES_PHI) k_phi_partC(PassArgs a) {
   extern __shared__ double lds[];
   const unsigned w = PART == 1 ? xcd_contiguous(blockIdx.x, gridDim.x) : blockIdx.x;
-  phi_body<PM, false, PART, false, MAP, P, PT>(a, w, lds);
+  const unsigned ring = 2u * (unsigned)a.g.nr + 2u * (unsigned)(a.g.nt - 2);
+  if (w < ring) phi_body<PM, false, PART, false, 2, false, PT>(a, w, lds);
+  else phi_body<PM, false, PART, false, 1, P, PT>(a, w - ring, lds);
 }
 
 // forced split step, one grid: as the plain sweep, all three lines of a slot
@@ -725,20 +730,23 @@ static bool phi_interior_split(const Geo &g) {
   return g.nr >= 3 && g.nt >= 3 && (long)(g.nr + 1) * (g.nt + 1) * g.npf < 0x7fffffffL;
 }
 
-// one grid, split: the block lines of the interior slots and of the boundary
-// ring, then their scalar lines
+// one grid, split: the block lines of every slot (ring, then interior), then
+// their scalar lines (at the interior slots both lines of a slot at once: 10
+// doubles of LDS per thread)
 template <int PM, bool PT>
 static void launch_phi_in(const PassArgs &a, unsigned threads, size_t lds, size_t lds_s, hipStream_t st) {
   const Geo &g = a.g;
-  const size_t lds_s2 = sizeof(double) * 10 * (size_t)threads;  // both scalar lines of a slot at once
-  const dim3 gin((unsigned)(g.nr - 2) * (unsigned)(g.nt - 2)), gbd(2u * (unsigned)g.nr + 2u * (unsigned)(g.nt - 2));
+  (void)lds_s;
+  const size_t lds_s2 = sizeof(double) * 10 * (size_t)threads;
+  const dim3 gall((unsigned)(g.nr - 2) * (unsigned)(g.nt - 2) + 2u * (unsigned)g.nr + 2u * (unsigned)(g.nt - 2));
   const dim3 bl(threads);
-  if (g.periodic) hipLaunchKernelGGL((k_phi_partI<PM, 0, 1, true, PT>), gin, bl, lds, st, a);
-  else hipLaunchKernelGGL((k_phi_partI<PM, 0, 1, false, PT>), gin, bl, lds, st, a);
-  hipLaunchKernelGGL((k_phi_partI<PM, 0, 2, false, PT>), gbd, bl, lds, st, a);
-  if (g.periodic) hipLaunchKernelGGL((k_phi_partI<PM, 1, 1, true, PT>), gin, bl, lds_s2, st, a);
-  else hipLaunchKernelGGL((k_phi_partI<PM, 1, 1, false, PT>), gin, bl, lds_s2, st, a);
-  hipLaunchKernelGGL((k_phi_partI<PM, 1, 2, false, PT>), gbd, bl, lds_s, st, a);
+  if (g.periodic) {
+    hipLaunchKernelGGL((k_phi_partC<PM, 0, true, PT>), gall, bl, lds, st, a);
+    hipLaunchKernelGGL((k_phi_partC<PM, 1, true, PT>), gall, bl, lds_s2, st, a);
+  } else {
+    hipLaunchKernelGGL((k_phi_partC<PM, 0, false, PT>), gall, bl, lds, st, a);
+    hipLaunchKernelGGL((k_phi_partC<PM, 1, false, PT>), gall, bl, lds_s2, st, a);
+  }
 }
 
 // the block lines, then the scalar lines (their LDS: the exchange and
