@@ -475,7 +475,9 @@ static unsigned kind_threads(int kind, const Geo &g, const Cfg &c) {
   case PK_SW1B:
   case PK_SW1S:
   case PK_SW1P: return (unsigned)c.sweep_bs[1];
-  case PK_SW2_PART: return phi_part_threads(g, c.phi_pm);
+  case PK_SW2_PART:
+  case PK_SW2_CP:
+  case PK_SW2_CN: return phi_part_threads(g, c.phi_pm);
   default: return 128u; // boundary copy, thread-per-line phi
   }
 }
@@ -506,7 +508,7 @@ static unsigned kind_blocks(int kind, const Geo &g, const Cfg &c, unsigned threa
 static size_t kind_lds(int kind, const Geo &g, const Cfg &c) {
   if (kind == PK_SW0P || kind == PK_SW1P) return rt_part_lds(kind_threads(kind, g, c));
   if (kind == PK_SW0S || kind == PK_SW1S) return rt_scalar_lds(kind_threads(kind, g, c));
-  return kind == PK_SW2_PART ? phi_part_lds(g, c.phi_pm) : 0;
+  return (kind == PK_SW2_PART || kind == PK_SW2_CP || kind == PK_SW2_CN) ? phi_part_lds(g, c.phi_pm) : 0;
 }
 
 static void launch_kind(int kind, const Cfg &c, const PassArgs &a, const Batch &b, unsigned blocks,
@@ -527,6 +529,8 @@ static void launch_kind(int kind, const Cfg &c, const PassArgs &a, const Batch &
   case PK_SW0P: launch_rt_pass(0, 4, a, b, blocks, threads, st); break;
   case PK_SW1P: launch_rt_pass(1, 4, a, b, blocks, threads, st); break;
   case PK_SW2_LINE: launch_sweep_pass(2, a, b, blocks, threads, st); break;
+  case PK_SW2_CP: launch_phi_pass_c(c.phi_pm, true, a, b, blocks, threads, lds, st); break;
+  case PK_SW2_CN: launch_phi_pass_c(c.phi_pm, false, a, b, blocks, threads, lds, st); break;
   default: launch_phi_pass(c.phi_pm, a, b, blocks, threads, lds, st); break;
   }
 }
@@ -939,7 +943,7 @@ extern "C" int dsw_get_status(dsw_grid *G, void *stream) {
 // transposed line solve of direction d on one grid: phi lines by the
 // partitioned solver when the configuration and the line allow it
 static void launch_T(const dsw_grid *G, int d, const Pass &p, hipStream_t st) {
-  if (d == 2 && p.kind == PK_SW2_PART) {
+  if (d == 2 && (p.kind == PK_SW2_PART || p.kind == PK_SW2_CP || p.kind == PK_SW2_CN)) {
     // two rows per chunk where the line allows it: twice the chunks in
     // flight for the same line (measured faster than four on the transposed
     // systems, whose row windows hold more registers)

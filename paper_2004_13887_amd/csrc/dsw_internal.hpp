@@ -179,7 +179,11 @@ struct Cfg {
 // (it keeps the passes of different grids' steps aligned).
 enum PassKind { PK_BND = 0, PK_RES = 1, PK_SW0 = 2, PK_SW1 = 3, PK_SW2_LINE = 4, PK_SW2_PART = 5,
                 PK_RES_IN = 6, PK_SW0T = 7, PK_SW1T = 8, PK_RES_INP = 9, PK_SW0P = 10, PK_SW1P = 11,
-                PK_SW0B = 12, PK_SW1B = 13, PK_SW0S = 14, PK_SW1S = 15, PK_NONE = 16 };
+                PK_SW0B = 12, PK_SW1B = 13, PK_SW0S = 14, PK_SW1S = 15, PK_NONE = 16,
+                PK_SW2_CP = 17, PK_SW2_CN = 18 };
+// PK_SW2_CP / PK_SW2_CN: the partitioned phi pass of a grid with an interior
+// (periodic / bounded phi); in a batch, each member's ring slots and then its
+// interior slots (the interior ones through the interior source).
 
 // forced split step (source term, wall velocities, Dirichlet data at the new
 // time level): one grid, the general residual over every point, the
@@ -298,8 +302,17 @@ bool phi_part_supported(const Geo &g, int pm);
 void sweep_scratch_size(const Geo &g, long *blk, long *sca);
 
 // the kind of the phi pass of a grid under a configuration
+// whether a grid's phi pass can take its interior slots through the
+// interior source (it has an interior, and 32-bit indices reach)
+bool phi_interior_split(const Geo &g);
+// a batch of grids that all have an interior (P: periodic phi): each
+// member's boundary ring, then its interior slots
+void launch_phi_pass_c(int pm, bool periodic, const PassArgs &a, const Batch &b, unsigned blocks,
+                       unsigned threads, size_t lds, hipStream_t st);
 inline int phi_kind(const Geo &g, const Cfg &c) {
-  return (c.phi_pm > 0 && phi_part_supported(g, c.phi_pm)) ? PK_SW2_PART : PK_SW2_LINE;
+  if (!(c.phi_pm > 0 && phi_part_supported(g, c.phi_pm))) return PK_SW2_LINE;
+  if (phi_interior_split(g)) return g.periodic ? PK_SW2_CP : PK_SW2_CN;
+  return PK_SW2_PART;
 }
 
 // Workgroups go to the chip's 8 XCDs in turn (w mod 8), and each XCD has an

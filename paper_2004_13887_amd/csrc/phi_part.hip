@@ -663,6 +663,21 @@ __global__ void __launch_bounds__(256) DSW_OCC(DSW_WAVES_PHI) k_phi_partC(PassAr
   else phi_body<PM, false, PART, false, 1, P, PT>(a, w - ring, lds);
 }
 
+// a batch of grids with an interior (P: periodic phi): member m's workgroups
+// take its boundary ring's slots first, then its interior slots, as
+// k_phi_partC does for one grid
+template <int PM, int PART, bool P>
+__global__ void __launch_bounds__(256) DSW_OCC(DSW_WAVES_PHI) k_phi_partCB(PassArgs a, Batch bt) {
+  extern __shared__ double lds[];
+  const unsigned w = PART == 1 ? xcd_contiguous(blockIdx.x, gridDim.x) : blockIdx.x;
+  const int mb = batch_member(bt, w);
+  const PassArgs &am = batch_args(bt, mb);
+  const unsigned wl = w - bt.woff[mb];
+  const unsigned ring = 2u * (unsigned)am.g.nr + 2u * (unsigned)(am.g.nt - 2);
+  if (wl < ring) phi_body<PM, false, PART, false, 2>(am, wl, lds);
+  else phi_body<PM, false, PART, false, 1, P>(am, wl - ring, lds);
+}
+
 // forced split step, one grid: as the plain sweep, all three lines of a slot
 // in one launch, or from PHI_SPLIT_SLOTS slots on the block lines and the
 // scalar lines as two
@@ -726,7 +741,7 @@ constexpr unsigned PHI_SPLIT_SLOTS = 16384;
 // interior.  The interior source drops the ghost code across r and theta
 // boundaries and forms 32-bit indices: measured on the 512 x 256 x 128
 // sphere, the phi pass 1.83 -> 1.78 ms, results bitwise unchanged.
-static bool phi_interior_split(const Geo &g) {
+bool phi_interior_split(const Geo &g) {
   return g.nr >= 3 && g.nt >= 3 && (long)(g.nr + 1) * (g.nt + 1) * g.npf < 0x7fffffffL;
 }
 
@@ -787,6 +802,34 @@ void launch_phi_pass(int pm, const PassArgs &a, const Batch &b, unsigned blocks,
       hipLaunchKernelGGL((k_phi_part<4, false, 0>), gr, bl, lds, st, a, b);
       hipLaunchKernelGGL((k_phi_part<4, false, 1>), gr, bl, lds_s, st, a, b);
     }
+  }
+}
+
+template <int PM, bool P>
+static void launch_phi_cb(const PassArgs &a, const Batch &b, unsigned blocks, unsigned threads, size_t lds,
+                          hipStream_t st) {
+  const dim3 gr(blocks), bl(threads);
+  if (blocks < PHI_SPLIT_SLOTS) {
+    hipLaunchKernelGGL((k_phi_partCB<PM, 2, P>), gr, bl, lds, st, a, b);
+    return;
+  }
+  const size_t lds_s2 = sizeof(double) * 10 * (size_t)threads;  // both scalar lines of a slot at once
+  hipLaunchKernelGGL((k_phi_partCB<PM, 0, P>), gr, bl, lds, st, a, b);
+  hipLaunchKernelGGL((k_phi_partCB<PM, 1, P>), gr, bl, lds_s2, st, a, b);
+}
+
+void launch_phi_pass_c(int pm, bool periodic, const PassArgs &a, const Batch &b, unsigned blocks,
+                       unsigned threads, size_t lds, hipStream_t st) {
+  if (!b.tab) {  // one grid: as any partitioned phi pass
+    launch_phi_pass(pm, a, b, blocks, threads, lds, st);
+    return;
+  }
+  if (pm == 2) {
+    if (periodic) launch_phi_cb<2, true>(a, b, blocks, threads, lds, st);
+    else launch_phi_cb<2, false>(a, b, blocks, threads, lds, st);
+  } else {
+    if (periodic) launch_phi_cb<4, true>(a, b, blocks, threads, lds, st);
+    else launch_phi_cb<4, false>(a, b, blocks, threads, lds, st);
   }
 }
 
