@@ -34,49 +34,54 @@ __device__ __forceinline__ void mm3s(const double *A, const double *B, double *C
 
 // ------------------------------------------------------- block: PCR step --
 // Solve the T separator rows A x_{t-1} + B x_t + C x_{t+1} = r (t < T) held
-// in registers of threads t < T; LDS holds T x 33 doubles.  Returns x_t.
+// in registers of threads t < T; returns x_t.  Each step, every row
+// publishes B^{-1} A, B^{-1} C and B^{-1} r (LDS: 21 T doubles) and
+// eliminates its neighbours h rows away from them.
 __device__ __forceinline__ void pcr_block(int t, int T, int cyc, double *A, double *B, double *C, double *r,
                           double *lds, double *x, int *status) {
-  double *sA = lds, *sC = lds + 9 * T, *sR = lds + 18 * T, *sBi = lds + 21 * T;
+  double *sPA = lds, *sPC = lds + 9 * T, *sPr = lds + 18 * T;
   const bool act = t < T;
   for (int h = 1; h < T; h *= 2) {
     if (act) {
-      double Bi[9];
+      double Bi[9], t9[9], t3[3];
       inv3(B, Bi, status);
+      mm3(Bi, A, t9);
 #pragma unroll
-      for (int q = 0; q < 9; q++) { sA[t * 9 + q] = A[q]; sC[t * 9 + q] = C[q]; sBi[t * 9 + q] = Bi[q]; }
+      for (int q = 0; q < 9; q++) sPA[t * 9 + q] = t9[q];
+      mm3(Bi, C, t9);
 #pragma unroll
-      for (int q = 0; q < 3; q++) sR[t * 3 + q] = r[q];
+      for (int q = 0; q < 9; q++) sPC[t * 9 + q] = t9[q];
+      mv3(Bi, r, t3);
+#pragma unroll
+      for (int q = 0; q < 3; q++) sPr[t * 3 + q] = t3[q];
     }
     __syncthreads();
     if (act) {
       int lo = t - h, hi = t + h;
       bool has_lo = lo >= 0, has_hi = hi < T;
       if (cyc) { lo = (lo % T + T) % T; hi = hi % T; has_lo = has_hi = true; }
-      double nA[9], nC[9], nB[9], nr[3], al[9], be[9], t9[9], t3[3];
+      double nA[9], nC[9], nB[9], nr[3], t9[9], t3[3];
 #pragma unroll
       for (int q = 0; q < 9; q++) { nA[q] = 0.0; nC[q] = 0.0; nB[q] = B[q]; }
 #pragma unroll
       for (int q = 0; q < 3; q++) nr[q] = r[q];
       if (has_lo) {
-        mm3s(A, &sBi[lo * 9], al, -1.0);        // alpha = -A B_lo^{-1}
-        mm3(al, &sA[lo * 9], nA);               // A' = alpha A_lo
-        mm3(al, &sC[lo * 9], t9);               // B' += alpha C_lo
+        mm3s(A, &sPA[lo * 9], nA, -1.0);       // A' = -A (B_lo^{-1} A_lo)
+        mm3(A, &sPC[lo * 9], t9);              // B' -= A (B_lo^{-1} C_lo)
 #pragma unroll
-        for (int q = 0; q < 9; q++) nB[q] += t9[q];
-        mv3(al, &sR[lo * 3], t3);
+        for (int q = 0; q < 9; q++) nB[q] -= t9[q];
+        mv3(A, &sPr[lo * 3], t3);
 #pragma unroll
-        for (int q = 0; q < 3; q++) nr[q] += t3[q];
+        for (int q = 0; q < 3; q++) nr[q] -= t3[q];
       }
       if (has_hi) {
-        mm3s(C, &sBi[hi * 9], be, -1.0);        // beta = -C B_hi^{-1}
-        mm3(be, &sC[hi * 9], nC);               // C' = beta C_hi
-        mm3(be, &sA[hi * 9], t9);               // B' += beta A_hi
+        mm3s(C, &sPC[hi * 9], nC, -1.0);       // C' = -C (B_hi^{-1} C_hi)
+        mm3(C, &sPA[hi * 9], t9);              // B' -= C (B_hi^{-1} A_hi)
 #pragma unroll
-        for (int q = 0; q < 9; q++) nB[q] += t9[q];
-        mv3(be, &sR[hi * 3], t3);
+        for (int q = 0; q < 9; q++) nB[q] -= t9[q];
+        mv3(C, &sPr[hi * 3], t3);
 #pragma unroll
-        for (int q = 0; q < 3; q++) nr[q] += t3[q];
+        for (int q = 0; q < 3; q++) nr[q] -= t3[q];
       }
 #pragma unroll
       for (int q = 0; q < 9; q++) { A[q] = nA[q]; B[q] = nB[q]; C[q] = nC[q]; }
@@ -312,7 +317,7 @@ __device__ __forceinline__ void part_block_line(const Geo &g, const Mat &m, cons
   double xs[3] = {0, 0, 0};
   pcr_block(t, T, cyc, A, B, Cc, r, lds, xs, status);
   // 3. fill in the interior rows
-  double *sX = lds + 30 * T;
+  double *sX = lds + 21 * T;
   if (act) {
 #pragma unroll
     for (int z = 0; z < 3; z++) sX[t * 3 + z] = xs[z];
@@ -728,7 +733,7 @@ unsigned phi_part_threads(const Geo &g, int pm) {
 
 size_t phi_part_lds(const Geo &g, int pm) {
   const int T = (g.np + pm - 1) / pm;
-  return sizeof(double) * 33 * (size_t)T;
+  return sizeof(double) * 24 * (size_t)T;
 }
 
 // From this many line slots on, the block and the scalar lines run as two
