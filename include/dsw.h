@@ -344,7 +344,9 @@ int dsw_adjoint_trajectory(dsw_grid *grid, const dsw_fields *ckpts, int32_t nste
  *                         and 8 on the scalar ones, separators by cyclic
  *                         reduction in LDS; no scratch memory); 0 = two
  *                         threads per line, eliminating from both ends,
- *                         intermediates in a scratch array; -1 = by line
+ *                         intermediates in a scratch array (the scalar
+ *                         lines of lines with 64, 128 or 256 rows run
+ *                         apart, by the partitioned solver); -1 = by line
  *                         length: partitioned where a line has at most 128
  *                         rows (32 chunks), else two-ended (in an ensemble,
  *                         member by member).  Lines of more than
@@ -354,9 +356,9 @@ int dsw_adjoint_trajectory(dsw_grid *grid, const dsw_fields *ckpts, int32_t nste
  *                         the two-ended one.  Measured: partitioned r
  *                         0.16 ms, theta 0.19 ms against 0.20 / 0.31 ms
  *                         two-ended on the 256 x 128 x 64 sector; on the
- *                         512 x 256 x 128 sphere r 1.39 / 1.42 ms (2.4x
+ *                         512 x 256 x 128 sphere r 1.39 / 1.44 ms (2.4x
  *                         fewer HBM bytes partitioned) and theta 1.74 /
- *                         1.63 ms.
+ *                         1.43 ms.
  * Default {64, 256, 256, 4, -1, -1}.  dsw_set_config returns DSW_EINVAL for
  * other values.  dsw_ensemble_tune times candidate shapes per pass and keeps
  * each pass's best; its result is also kept for the process per set of member
