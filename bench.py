@@ -636,7 +636,9 @@ def bench_ensemble(args):
         E.set_config(*cfg)
         log(f"[ensemble] launch shapes {cfg} (given)")
     else:
-        cfg = E.ensemble_tune(A, B, taus, K, reps=1, stream=stream)
+        # three timed runs per candidate: with one, timing noise between
+        # close candidates flipped the choice from run to run
+        cfg = E.ensemble_tune(A, B, taus, K, reps=3, stream=stream)
         log(f"[ensemble] tuned launch shapes {cfg}")
     # the per-member calls take the same launch shapes, so that both paths
     # run the same arithmetic (the phi solver's partition depends on them)
