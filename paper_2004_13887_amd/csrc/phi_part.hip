@@ -43,50 +43,31 @@ __device__ __forceinline__ void pcr_block(int t, int T, int cyc, double *A, doub
   const bool act = t < T;
   for (int h = 1; h < T; h *= 2) {
     if (act) {
-      double Bi[9], t9[9], t3[3];
+      double Bi[9];
       inv3(B, Bi, status);
-      mm3(Bi, A, t9);
-#pragma unroll
-      for (int q = 0; q < 9; q++) sPA[t * 9 + q] = t9[q];
-      mm3(Bi, C, t9);
-#pragma unroll
-      for (int q = 0; q < 9; q++) sPC[t * 9 + q] = t9[q];
-      mv3(Bi, r, t3);
-#pragma unroll
-      for (int q = 0; q < 3; q++) sPr[t * 3 + q] = t3[q];
+      mm3(Bi, A, &sPA[t * 9]);
+      mm3(Bi, C, &sPC[t * 9]);
+      mv3(Bi, r, &sPr[t * 3]);
     }
     __syncthreads();
     if (act) {
       int lo = t - h, hi = t + h;
       bool has_lo = lo >= 0, has_hi = hi < T;
       if (cyc) { lo = (lo % T + T) % T; hi = hi % T; has_lo = has_hi = true; }
-      double nA[9], nC[9], nB[9], nr[3], t9[9], t3[3];
+      // B' = B - A P_C(lo) - C P_A(hi), r' alike, A' = -A P_A(lo),
+      // C' = -C P_C(hi) (P = B^{-1} times the published row)
+      if (has_lo) { mm3_sub(A, &sPC[lo * 9], B); mv3_sub(A, &sPr[lo * 3], r); }
+      if (has_hi) { mm3_sub(C, &sPA[hi * 9], B); mv3_sub(C, &sPr[hi * 3], r); }
+      if (has_lo) mm3_neg_inplace(A, &sPA[lo * 9]);
+      else {
 #pragma unroll
-      for (int q = 0; q < 9; q++) { nA[q] = 0.0; nC[q] = 0.0; nB[q] = B[q]; }
-#pragma unroll
-      for (int q = 0; q < 3; q++) nr[q] = r[q];
-      if (has_lo) {
-        mm3s(A, &sPA[lo * 9], nA, -1.0);       // A' = -A (B_lo^{-1} A_lo)
-        mm3(A, &sPC[lo * 9], t9);              // B' -= A (B_lo^{-1} C_lo)
-#pragma unroll
-        for (int q = 0; q < 9; q++) nB[q] -= t9[q];
-        mv3(A, &sPr[lo * 3], t3);
-#pragma unroll
-        for (int q = 0; q < 3; q++) nr[q] -= t3[q];
+        for (int q = 0; q < 9; q++) A[q] = 0.0;
       }
-      if (has_hi) {
-        mm3s(C, &sPC[hi * 9], nC, -1.0);       // C' = -C (B_hi^{-1} C_hi)
-        mm3(C, &sPA[hi * 9], t9);              // B' -= C (B_hi^{-1} A_hi)
+      if (has_hi) mm3_neg_inplace(C, &sPC[hi * 9]);
+      else {
 #pragma unroll
-        for (int q = 0; q < 9; q++) nB[q] -= t9[q];
-        mv3(C, &sPr[hi * 3], t3);
-#pragma unroll
-        for (int q = 0; q < 3; q++) nr[q] -= t3[q];
+        for (int q = 0; q < 9; q++) C[q] = 0.0;
       }
-#pragma unroll
-      for (int q = 0; q < 9; q++) { A[q] = nA[q]; B[q] = nB[q]; C[q] = nC[q]; }
-#pragma unroll
-      for (int q = 0; q < 3; q++) r[q] = nr[q];
     }
     __syncthreads();
   }
@@ -195,6 +176,8 @@ __device__ __forceinline__ void part_block_line(const Geo &g, const Mat &m, cons
   const int a0 = t * PM;
   const int len = act ? min(PM, N - a0) : 0;
   double Cm[PM - 1][9], Em[PM - 1][9], Ym[PM - 1][3];
+  // structural non-zeros of the row blocks (transposed rows: L = U^T, U = L^T)
+  constexpr unsigned mL = TR ? nz_tr(NZ_U) : NZ_L, mU = TR ? nz_tr(NZ_L) : NZ_U;
   BRow R;
   TrWalk<2> tw; // transposed rows: each row of the line assembled once
   if constexpr (TR) {
@@ -209,23 +192,26 @@ __device__ __forceinline__ void part_block_line(const Geo &g, const Mat &m, cons
       double Dp[9], rr[3], Lx[9], Ai[9];
       if (q == 0) {
 #pragma unroll
-        for (int z = 0; z < 9; z++) { Dp[z] = R.D[z]; Lx[z] = R.L[z]; }
+        for (int z = 0; z < 9; z++) Dp[z] = R.D[z];
 #pragma unroll
         for (int z = 0; z < 3; z++) rr[z] = R.b[z];
       } else {
         double t9[9], t3[3];
-        mm3(R.L, Cm[q - 1], t9);
+        mm3m<mL, NZ_ALL>(R.L, Cm[q - 1], t9);
 #pragma unroll
         for (int z = 0; z < 9; z++) Dp[z] = R.D[z] - t9[z];
-        mv3(R.L, Ym[q - 1], t3);
+        mv3m<mL>(R.L, Ym[q - 1], t3);
 #pragma unroll
         for (int z = 0; z < 3; z++) rr[z] = R.b[z] - t3[z];
-        mm3s(R.L, Em[q - 1], Lx, -1.0);
+        mm3m<mL, NZ_ALL>(R.L, Em[q - 1], Lx);
+#pragma unroll
+        for (int z = 0; z < 9; z++) Lx[z] *= -1.0;
       }
       inv3(Dp, Ai, status);
-      mm3(Ai, R.U, Cm[q]);
+      mm3m<NZ_ALL, mU>(Ai, R.U, Cm[q]);
       mv3(Ai, rr, Ym[q]);
-      mm3(Ai, Lx, Em[q]);
+      if (q == 0) mm3m<NZ_ALL, mL>(Ai, R.L, Em[q]);
+      else mm3(Ai, Lx, Em[q]);
     }
   }
   // separator row (last row of the chunk)
@@ -289,11 +275,11 @@ __device__ __forceinline__ void part_block_line(const Geo &g, const Mat &m, cons
 #pragma unroll
     for (int z = 0; z < 3; z++) r[z] = S.b[z];
     if (len >= 2) {
-      mm3(S.L, Vl, A);
-      mm3(S.L, Wl, t9);
+      mm3m<mL, NZ_ALL>(S.L, Vl, A);
+      mm3m<mL, NZ_ALL>(S.L, Wl, t9);
 #pragma unroll
       for (int z = 0; z < 9; z++) B[z] += t9[z];
-      mv3(S.L, Gl, t3);
+      mv3m<mL>(S.L, Gl, t3);
 #pragma unroll
       for (int z = 0; z < 3; z++) r[z] -= t3[z];
     } else {
@@ -301,11 +287,11 @@ __device__ __forceinline__ void part_block_line(const Geo &g, const Mat &m, cons
       for (int z = 0; z < 9; z++) A[z] = S.L[z];
     }
     if (nlen >= 2) {
-      mm3(S.U, &sV[nt_ * 9], t9);
+      mm3m<mU, NZ_ALL>(S.U, &sV[nt_ * 9], t9);
 #pragma unroll
       for (int z = 0; z < 9; z++) B[z] += t9[z];
-      mm3(S.U, &sW[nt_ * 9], Cc);
-      mv3(S.U, &sG[nt_ * 3], t3);
+      mm3m<mU, NZ_ALL>(S.U, &sW[nt_ * 9], Cc);
+      mv3m<mU>(S.U, &sG[nt_ * 3], t3);
 #pragma unroll
       for (int z = 0; z < 3; z++) r[z] -= t3[z];
     } else {

@@ -60,6 +60,80 @@ __device__ __forceinline__ void mv3(const double *A, const double *x, double *y)
   for (int r = 0; r < 3; r++) y[r] = A[r * 3] * x[0] + A[r * 3 + 1] * x[1] + A[r * 3 + 2] * x[2];
 }
 
+// B -= A * P and y -= A * x, each product rounded as mm3 / mv3 round it;
+// A <- -(A * P) in place, a row at a time.  The reductions use these to keep
+// few registers live beside the rows they carry.
+__device__ __forceinline__ void mm3_sub(const double *A, const double *P, double *B) {
+#pragma unroll
+  for (int r = 0; r < 3; r++)
+#pragma unroll
+    for (int c = 0; c < 3; c++) B[r * 3 + c] -= A[r * 3] * P[c] + A[r * 3 + 1] * P[3 + c] + A[r * 3 + 2] * P[6 + c];
+}
+__device__ __forceinline__ void mv3_sub(const double *A, const double *x, double *y) {
+#pragma unroll
+  for (int r = 0; r < 3; r++) y[r] -= A[r * 3] * x[0] + A[r * 3 + 1] * x[1] + A[r * 3 + 2] * x[2];
+}
+__device__ __forceinline__ void mm3_neg_inplace(double *A, const double *P) {
+#pragma unroll
+  for (int r = 0; r < 3; r++) {
+    double t[3];
+#pragma unroll
+    for (int c = 0; c < 3; c++) t[c] = A[r * 3] * P[c] + A[r * 3 + 1] * P[3 + c] + A[r * 3 + 2] * P[6 + c];
+#pragma unroll
+    for (int c = 0; c < 3; c++) A[r * 3 + c] = -t[c];
+  }
+}
+
+// Structural non-zeros of the blocks that block_row assembles: bit 3r + c is
+// set where entry (r, c) can be non-zero (unknowns p, T, w).  The lower block
+// couples the p and T rows to p, T and w of the row before, the w row to w
+// only; the upper block couples p to p and T, T to T, and w to p and w.  The
+// zeros are computed as 0 * tau/2, which the compiler may not fold, so the
+// full products spend a third or more of their FMAs on them.
+constexpr unsigned NZ_ALL = 0x1FFu;
+constexpr unsigned NZ_L = 0x137u;  // (0,0) (0,1) (0,2) (1,1) (1,2) (2,2)
+constexpr unsigned NZ_U = 0x153u;  // (0,0) (0,1) (1,1) (2,0) (2,2)
+// mask of the transposed block
+__host__ __device__ constexpr unsigned nz_tr(unsigned m) {
+  unsigned t = 0;
+  for (int r = 0; r < 3; r++)
+    for (int c = 0; c < 3; c++)
+      if ((m >> (r * 3 + c)) & 1u) t |= 1u << (c * 3 + r);
+  return t;
+}
+
+// a0 b0 + a1 b1 + a2 b2 over the terms present (p0, p1, p2), rounded as
+// mm3 and mv3 round the full sum under FMA contraction,
+// fma(a2, b2, fma(a0, b0, a1 b1)): dropping a term whose factor is zero
+// leaves every finite result unchanged.
+__device__ __forceinline__ double dot3m(bool p0, bool p1, bool p2, double a0, double b0, double a1,
+                                        double b1, double a2, double b2) {
+  double s = 0.0;
+  if (p1) s = a1 * b1;
+  if (p0) s = p1 ? __builtin_fma(a0, b0, s) : a0 * b0;
+  if (p2) s = (p0 || p1) ? __builtin_fma(a2, b2, s) : a2 * b2;
+  return s;
+}
+// C = A * B (3x3) for A, B with the structural non-zeros MA, MB
+template <unsigned MA, unsigned MB>
+__device__ __forceinline__ void mm3m(const double *A, const double *B, double *C) {
+#pragma unroll
+  for (int r = 0; r < 3; r++)
+#pragma unroll
+    for (int c = 0; c < 3; c++)
+      C[r * 3 + c] = dot3m((MA >> (r * 3)) & (MB >> c) & 1u, (MA >> (r * 3 + 1)) & (MB >> (3 + c)) & 1u,
+                           (MA >> (r * 3 + 2)) & (MB >> (6 + c)) & 1u, A[r * 3], B[c], A[r * 3 + 1],
+                           B[3 + c], A[r * 3 + 2], B[6 + c]);
+}
+// y = A * x for A with the structural non-zeros MA
+template <unsigned MA>
+__device__ __forceinline__ void mv3m(const double *A, const double *x, double *y) {
+#pragma unroll
+  for (int r = 0; r < 3; r++)
+    y[r] = dot3m((MA >> (r * 3)) & 1u, (MA >> (r * 3 + 1)) & 1u, (MA >> (r * 3 + 2)) & 1u, A[r * 3], x[0],
+                 A[r * 3 + 1], x[1], A[r * 3 + 2], x[2]);
+}
+
 // ------------------------------------------------------------------ lines --
 
 // number of lines per family: block, scalar A, scalar B

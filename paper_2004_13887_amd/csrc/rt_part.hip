@@ -39,45 +39,30 @@ __device__ __forceinline__ void rt_pcr_block(int c, int l, int T, int L, bool ac
   double *sA = lds, *sC = lds + 9 * nt, *sR = lds + 18 * nt;
   for (int h = 1; h < T; h *= 2) {
     if (act) {
-      double Bi[9], t9[9], t3[3];
+      double Bi[9];
       inv3(B, Bi, status);
-      mm3(Bi, A, t9);
-#pragma unroll
-      for (int q = 0; q < 9; q++) sA[t * 9 + q] = t9[q];
-      mm3(Bi, C, t9);
-#pragma unroll
-      for (int q = 0; q < 9; q++) sC[t * 9 + q] = t9[q];
-      mv3(Bi, r, t3);
-#pragma unroll
-      for (int q = 0; q < 3; q++) sR[t * 3 + q] = t3[q];
+      mm3(Bi, A, &sA[t * 9]);
+      mm3(Bi, C, &sC[t * 9]);
+      mv3(Bi, r, &sR[t * 3]);
     }
     __syncthreads();
     if (act) {
-      double nA[9], nC[9], t9[9], t3[3];
+      // x_{c-h} = R' - A' x_{c-2h} - C' x_c and x_{c+h} alike: B' = B -
+      // A C'(c-h) - C A'(c+h), r' alike, A' = -A A'(c-h), C' = -C C'(c+h)
+      const bool has_lo = c - h >= 0, has_hi = c + h < T;
+      const int ul = (c - h) * L + l, uh = (c + h) * L + l;
+      if (has_lo) { mm3_sub(A, &sC[ul * 9], B); mv3_sub(A, &sR[ul * 3], r); }
+      if (has_hi) { mm3_sub(C, &sA[uh * 9], B); mv3_sub(C, &sR[uh * 3], r); }
+      if (has_lo) mm3_neg_inplace(A, &sA[ul * 9]);
+      else {
 #pragma unroll
-      for (int q = 0; q < 9; q++) { nA[q] = 0.0; nC[q] = 0.0; }
-      if (c - h >= 0) {  // x_{c-h} = R' - A' x_{c-2h} - C' x_c
-        const int u = (c - h) * L + l;
-        mm3(A, &sA[u * 9], nA);
-        mm3(A, &sC[u * 9], t9);
-        mv3(A, &sR[u * 3], t3);
-#pragma unroll
-        for (int q = 0; q < 9; q++) { nA[q] = -nA[q]; B[q] -= t9[q]; }
-#pragma unroll
-        for (int q = 0; q < 3; q++) r[q] -= t3[q];
+        for (int q = 0; q < 9; q++) A[q] = 0.0;
       }
-      if (c + h < T) {   // x_{c+h} = R' - A' x_c - C' x_{c+2h}
-        const int u = (c + h) * L + l;
-        mm3(C, &sC[u * 9], nC);
-        mm3(C, &sA[u * 9], t9);
-        mv3(C, &sR[u * 3], t3);
+      if (has_hi) mm3_neg_inplace(C, &sC[uh * 9]);
+      else {
 #pragma unroll
-        for (int q = 0; q < 9; q++) { nC[q] = -nC[q]; B[q] -= t9[q]; }
-#pragma unroll
-        for (int q = 0; q < 3; q++) r[q] -= t3[q];
+        for (int q = 0; q < 9; q++) C[q] = 0.0;
       }
-#pragma unroll
-      for (int q = 0; q < 9; q++) { A[q] = nA[q]; C[q] = nC[q]; }
     }
     __syncthreads();
   }
@@ -146,6 +131,8 @@ __device__ __forceinline__ void rt_block_lines(const Geo &g, const Mat &m, const
   const int a0 = c * PM;
   const int len = act ? min(PM, n - a0) : 0;
   double Cm[PM - 1][9], Em[PM - 1][9], Ym[PM - 1][3];
+  // structural non-zeros of the row blocks (transposed rows: L = U^T, U = L^T)
+  constexpr unsigned mL = TR ? nz_tr(NZ_U) : NZ_L, mU = TR ? nz_tr(NZ_L) : NZ_U;
   TrWalk<D> tw;
   if constexpr (TR) {
     if (act) tw.init(g, m, u, rhs, pa, pb, a0, n, 0, hs);
@@ -160,25 +147,26 @@ __device__ __forceinline__ void rt_block_lines(const Geo &g, const Mat &m, const
       double Dp[9], rr[3], Lx[9], Ai[9];
       if (q == 0) {
 #pragma unroll
-        for (int z = 0; z < 9; z++) { Dp[z] = R.D[z]; Lx[z] = R.L[z]; }
+        for (int z = 0; z < 9; z++) Dp[z] = R.D[z];
 #pragma unroll
         for (int z = 0; z < 3; z++) rr[z] = R.b[z];
       } else {
         double t9[9], t3[3];
-        mm3(R.L, Cm[q - 1], t9);
+        mm3m<mL, NZ_ALL>(R.L, Cm[q - 1], t9);
 #pragma unroll
         for (int z = 0; z < 9; z++) Dp[z] = R.D[z] - t9[z];
-        mv3(R.L, Ym[q - 1], t3);
+        mv3m<mL>(R.L, Ym[q - 1], t3);
 #pragma unroll
         for (int z = 0; z < 3; z++) rr[z] = R.b[z] - t3[z];
-        mm3(R.L, Em[q - 1], t9);
+        mm3m<mL, NZ_ALL>(R.L, Em[q - 1], t9);
 #pragma unroll
         for (int z = 0; z < 9; z++) Lx[z] = -t9[z];
       }
       inv3(Dp, Ai, status);
-      mm3(Ai, R.U, Cm[q]);
+      mm3m<NZ_ALL, mU>(Ai, R.U, Cm[q]);
       mv3(Ai, rr, Ym[q]);
-      mm3(Ai, Lx, Em[q]);
+      if (q == 0) mm3m<NZ_ALL, mL>(Ai, R.L, Em[q]);
+      else mm3(Ai, Lx, Em[q]);
     }
   }
   BRow S;  // separator row (last row of the chunk)
@@ -239,11 +227,11 @@ __device__ __forceinline__ void rt_block_lines(const Geo &g, const Mat &m, const
 #pragma unroll
     for (int z = 0; z < 3; z++) r[z] = S.b[z];
     if (len >= 2) {
-      mm3(S.L, Vl, A);
-      mm3(S.L, Wl, t9);
+      mm3m<mL, NZ_ALL>(S.L, Vl, A);
+      mm3m<mL, NZ_ALL>(S.L, Wl, t9);
 #pragma unroll
       for (int z = 0; z < 9; z++) B[z] += t9[z];
-      mv3(S.L, Gl, t3);
+      mv3m<mL>(S.L, Gl, t3);
 #pragma unroll
       for (int z = 0; z < 3; z++) r[z] -= t3[z];
     } else {
@@ -251,11 +239,11 @@ __device__ __forceinline__ void rt_block_lines(const Geo &g, const Mat &m, const
       for (int z = 0; z < 9; z++) A[z] = S.L[z];
     }
     if (nlen >= 2) {
-      mm3(S.U, &sV[tn * 9], t9);
+      mm3m<mU, NZ_ALL>(S.U, &sV[tn * 9], t9);
 #pragma unroll
       for (int z = 0; z < 9; z++) B[z] += t9[z];
-      mm3(S.U, &sW[tn * 9], Cc);
-      mv3(S.U, &sG[tn * 3], t3);
+      mm3m<mU, NZ_ALL>(S.U, &sW[tn * 9], Cc);
+      mv3m<mU>(S.U, &sG[tn * 3], t3);
 #pragma unroll
       for (int z = 0; z < 3; z++) r[z] -= t3[z];
     } else {

@@ -423,16 +423,16 @@ __device__ __forceinline__ void twisted_block_line(const Geo &g, const Mat &m, c
 #pragma unroll
           for (int q = 0; q < 3; q++) t3[q] = R.b[q];
         } else {
-          mm3(R.L, C, t9);
+          mm3m<NZ_L, NZ_ALL>(R.L, C, t9);
 #pragma unroll
           for (int q = 0; q < 9; q++) Ap[q] = R.D[q] - t9[q];
           double ly[3];
-          mv3(R.L, y, ly);
+          mv3m<NZ_L>(R.L, y, ly);
 #pragma unroll
           for (int q = 0; q < 3; q++) t3[q] = R.b[q] - ly[q];
         }
         sing |= inv3q(Ap, Ai);
-        mm3(Ai, R.U, C);
+        mm3m<NZ_ALL, NZ_U>(Ai, R.U, C);
         mv3(Ai, t3, y);
 #pragma unroll
         for (int q = 0; q < 9; q++) SC(s, q) = C[q];
@@ -449,16 +449,16 @@ __device__ __forceinline__ void twisted_block_line(const Geo &g, const Mat &m, c
 #pragma unroll
           for (int q = 0; q < 3; q++) t3[q] = R.b[q];
         } else {
-          mm3(R.U, C, t9);
+          mm3m<NZ_U, NZ_ALL>(R.U, C, t9);
 #pragma unroll
           for (int q = 0; q < 9; q++) Ap[q] = R.D[q] - t9[q];
           double uz[3];
-          mv3(R.U, y, uz);
+          mv3m<NZ_U>(R.U, y, uz);
 #pragma unroll
           for (int q = 0; q < 3; q++) t3[q] = R.b[q] - uz[q];
         }
         sing |= inv3q(Ap, Ai);
-        mm3(Ai, R.L, C);  // E'_s
+        mm3m<NZ_ALL, NZ_L>(Ai, R.L, C);  // E'_s
         mv3(Ai, t3, y);   // z_s
 #pragma unroll
         for (int q = 0; q < 9; q++) SC(s, q) = C[q];
@@ -476,11 +476,11 @@ __device__ __forceinline__ void twisted_block_line(const Geo &g, const Mat &m, c
   if (act && top) {  // middle row
     block_row<D>(g, m, u, rhs, a, b, mid, n, 0, hs, R);
     double Ub[9], t9b[9], uz[3], ly[3];
-    mm3(R.U, my, Ub);  // U_m E'_{m+1}
-    mv3(R.U, my + 9, uz);
+    mm3m<NZ_U, NZ_ALL>(R.U, my, Ub);  // U_m E'_{m+1}
+    mv3m<NZ_U>(R.U, my + 9, uz);
     if (mid > 0) {
-      mm3(R.L, C, t9b);
-      mv3(R.L, y, ly);
+      mm3m<NZ_L, NZ_ALL>(R.L, C, t9b);
+      mv3m<NZ_L>(R.L, y, ly);
     } else {
 #pragma unroll
       for (int q = 0; q < 9; q++) t9b[q] = 0.0;
