@@ -525,7 +525,7 @@ def bench_sweeps(args):
 def bench_forced(args):
     """sweeps workload (1024 x 512 x 64 sector: walls on every side), K = 3:
     dsw_split_step_forced with a seeded source term, seeded wall velocities
-    on all twelve wall arrays and new Dirichlet data, against dsw_split_step
+    on all twelve wall arrays at t^n and t^{n+1}, and new Dirichlet data, against dsw_split_step
     on the same grid; ms per step and grid-point updates/s of each"""
     import numpy as np
     import torch
@@ -552,8 +552,11 @@ def bench_forced(args):
            "uf_r2": (g.nt, g.npf), "uf_t1": (g.nr, g.npf), "uf_t2": (g.nr, g.npf)}
     wall = {k: us * rng.uniform(-1, 1, s) for k, s in shp.items()}
     bnd = {k: U0[k] + us * rng.uniform(-1, 1, U0[k].shape) for k in ("ur", "ut", "uf")}
-    dsrc, dwall, dbnd = dsw.to_device(src), dsw.to_device(wall), dsw.to_device(bnd)
-    del src, bnd
+    # the wall velocities at t^{n+1}: those at t^n plus a seeded change
+    wall1 = {k: v + 0.1 * us * rng.uniform(-1, 1, v.shape) for k, v in wall.items()}
+    dsrc, dwall, dwall1, dbnd = (dsw.to_device(src), dsw.to_device(wall), dsw.to_device(wall1),
+                                 dsw.to_device(bnd))
+    del src, bnd, wall1
     A, B = dsw.to_device(U0), grid.empty()
     stream = torch.cuda.current_stream()
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -565,7 +568,8 @@ def bench_forced(args):
                 torch.cuda.synchronize()
                 ev0.record(stream)
             if forced:
-                grid.split_step_forced(X, Y, tau, w.K, src=dsrc, wall=dwall, bnd=dbnd, stream=stream)
+                grid.split_step_forced(X, Y, tau, w.K, src=dsrc, wall0=dwall, wall1=dwall1, bnd=dbnd,
+                                       stream=stream)
             else:
                 grid.split_step(X, Y, tau, w.K, stream)
             X, Y = Y, X
