@@ -356,8 +356,8 @@ int dsw_adjoint_trajectory(dsw_grid *grid, const dsw_fields *ckpts, int32_t nste
  *                         the two-ended one.  Measured: partitioned r
  *                         0.16 ms, theta 0.19 ms against 0.20 / 0.31 ms
  *                         two-ended on the 256 x 128 x 64 sector; on the
- *                         512 x 256 x 128 sphere r 1.39 / 1.44 ms (2.4x
- *                         fewer HBM bytes partitioned) and theta 1.74 /
+ *                         512 x 256 x 128 sphere r 1.37 / 1.37 ms (2.4x
+ *                         fewer HBM bytes partitioned) and theta 1.71 /
  *                         1.43 ms.
  * Default {64, 256, 256, 4, -1, -1}.  dsw_set_config returns DSW_EINVAL for
  * other values.  dsw_ensemble_tune times candidate shapes per pass and keeps
