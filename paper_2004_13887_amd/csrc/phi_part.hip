@@ -183,6 +183,9 @@ __device__ __forceinline__ void part_block_line(const Geo &g, const Mat &m, cons
   if constexpr (TR) {
     if (act) tw.init(g, m, u, rhs, i, j, a0, N, cyc, hs);
   }
+  // a zero pivot is recorded after the loop: a store inside it would hold
+  // the next row's loads back
+  bool sing = false;
   // 1. forward elimination over interior rows with the left spike
 #pragma unroll
   for (int q = 0; q < PM - 1; q++) {
@@ -207,13 +210,14 @@ __device__ __forceinline__ void part_block_line(const Geo &g, const Mat &m, cons
 #pragma unroll
         for (int z = 0; z < 9; z++) Lx[z] *= -1.0;
       }
-      inv3(Dp, Ai, status);
+      sing |= inv3q(Dp, Ai);
       mm3m<NZ_ALL, mU>(Ai, R.U, Cm[q]);
       mv3(Ai, rr, Ym[q]);
       if (q == 0) mm3m<NZ_ALL, mL>(Ai, R.L, Em[q]);
       else mm3(Ai, Lx, Em[q]);
     }
   }
+  if (sing) status[ST_SINGULAR] = 1;
   // separator row (last row of the chunk)
   BRow S;
   if (act) {

@@ -137,6 +137,9 @@ __device__ __forceinline__ void rt_block_lines(const Geo &g, const Mat &m, const
   if constexpr (TR) {
     if (act) tw.init(g, m, u, rhs, pa, pb, a0, n, 0, hs);
   }
+  // a zero pivot is recorded after the loop: a store inside it would hold
+  // the next row's loads back
+  bool sing = false;
   // 1. forward elimination over the interior rows with the left spike
 #pragma unroll
   for (int q = 0; q < PM - 1; q++) {
@@ -162,13 +165,14 @@ __device__ __forceinline__ void rt_block_lines(const Geo &g, const Mat &m, const
 #pragma unroll
         for (int z = 0; z < 9; z++) Lx[z] = -t9[z];
       }
-      inv3(Dp, Ai, status);
+      sing |= inv3q(Dp, Ai);
       mm3m<NZ_ALL, mU>(Ai, R.U, Cm[q]);
       mv3(Ai, rr, Ym[q]);
       if (q == 0) mm3m<NZ_ALL, mL>(Ai, R.L, Em[q]);
       else mm3(Ai, Lx, Em[q]);
     }
   }
+  if (sing) status[ST_SINGULAR] = 1;
   BRow S;  // separator row (last row of the chunk)
   if (act) {
     if constexpr (TR) tw.next(g, m, u, rhs, pa, pb, n, 0, hs, S);
