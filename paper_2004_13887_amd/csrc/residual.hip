@@ -63,7 +63,7 @@ __device__ __forceinline__ double F_p_T(const Geo &g, const Mat &m, const S &s, 
 template <class S>
 __device__ __forceinline__ double F_ur(const Geo &g, const Mat &m, const S &s, int f, int j, int k) {
   const double irF = g.irf[f], is = g.isc[j];
-  const double irho = 1.0 / (0.5 * (rho_at(g, m, s, f - 1, j, k) + rho_at(g, m, s, f, j, k)));
+  const double irho = irho_mean(g, m, s, f - 1, j, k, f, j, k);
   const double nu = m.mu * irho;
   const double un = gR(g, s, f, j, k);
   const double ua = 0.25 * (gT(g, s, f - 1, j, k) + gT(g, s, f - 1, j + 1, k) + gT(g, s, f, j, k) +
@@ -98,9 +98,9 @@ __device__ __forceinline__ double F_ur(const Geo &g, const Mat &m, const S &s, i
     const double ta = s.tref[f - 1], tb = s.tref[f];
     const double da = (gC(g, s, F_P, f - 1, j, k) * ta - (s.pref[f - 1] + m.pinf) * (Ta - ta)) / (m.Rg * Ta * ta);
     const double db = (gC(g, s, F_P, f, j, k) * tb - (s.pref[f] + m.pinf) * (Tb - tb)) / (m.Rg * Tb * tb);
-    return N - nu * vis - nu / 3.0 * gd + m.g_r * (0.5 * (da + db)) * irho;
+    return N - nu * vis - nu * (1.0 / 3.0) * gd + m.g_r * (0.5 * (da + db)) * irho;
   } else {
-    return N - nu * vis - nu / 3.0 * gd + m.g_r;
+    return N - nu * vis - nu * (1.0 / 3.0) * gd + m.g_r;
   }
 }
 
@@ -108,7 +108,7 @@ template <class S>
 __device__ __forceinline__ double F_ut(const Geo &g, const Mat &m, const S &s, int i, int f, int k) {
   const double ir = g.irc[i], isF = g.isf[f], ctF = g.ctf[f];
   const int j0 = f - 1, j1 = f;
-  const double irho = 1.0 / (0.5 * (rho_at(g, m, s, i, j0, k) + rho_at(g, m, s, i, j1, k)));
+  const double irho = irho_mean(g, m, s, i, j0, k, i, j1, k);
   const double nu = m.mu * irho;
   const double un = gT(g, s, i, f, k);
   const double ua = 0.25 * (gR(g, s, i, j0, k) + gR(g, s, i, j1, k) + gR(g, s, i + 1, j0, k) +
@@ -136,14 +136,14 @@ __device__ __forceinline__ double F_ut(const Geo &g, const Mat &m, const S &s, i
   const double C = (wr1 - wr0) * (ir * isF * g.idp) - (g.rf[i + 1] * wp1 - g.rf[i] * wp0) * (ir * g.idr);
   const double vis = gd - C;
   N += -2.0 * m.omega * g.cf[f] * ub;
-  return N - nu * vis - nu / 3.0 * gd;
+  return N - nu * vis - nu * (1.0 / 3.0) * gd;
 }
 
 template <class S>
 __device__ __forceinline__ double F_uf(const Geo &g, const Mat &m, const S &s, int i, int j, int f) {
   const double ir = g.irc[i], is = g.isc[j], ct = g.ctc[j], ir2 = ir * ir;
   const int k0 = g.periodic ? wrapk(g, f - 1) : f - 1, k1 = g.periodic ? wrapk(g, f) : f;
-  const double irho = 1.0 / (0.5 * (rho_at(g, m, s, i, j, k0) + rho_at(g, m, s, i, j, k1)));
+  const double irho = irho_mean(g, m, s, i, j, k0, i, j, k1);
   const double nu = m.mu * irho;
   const double un = gF(g, s, i, j, f);
   const double ua = 0.25 * (gR(g, s, i, j, k0) + gR(g, s, i, j, k1) + gR(g, s, i + 1, j, k0) +
@@ -182,7 +182,7 @@ __device__ __forceinline__ double F_uf(const Geo &g, const Mat &m, const S &s, i
     vis = gd - C;
   }
   N += 2.0 * m.omega * (g.cc[j] * ub + g.sc[j] * ua);
-  return N - nu * vis - nu / 3.0 * gd;
+  return N - nu * vis - nu * (1.0 / 3.0) * gd;
 }
 
 // F_h at an unknown, less the source term of a forced state (manufactured

@@ -221,34 +221,34 @@ __device__ __forceinline__ void block_row(const Geo &g, const Mat &m, const S &u
   if (w_unknown) {
     if (D == 0) {
       const int f = i + 1;
-      const double irho = 1.0 / (0.5 * (rho_at(g, m, u, i, j, k) + rho_at(g, m, u, i + 1, j, k)));
+      const double irho = irho_mean(g, m, u, i, j, k, i + 1, j, k);
       const double nu = m.mu * irho, un = u.ld(F_UR, idx_r(g, f, j, k));
       const double irF2 = g.irf[f] * g.irf[f], d2 = g.idr * g.idr, rF2 = g.rf[f] * g.rf[f];
       const double ra2 = g.rc[i] * g.rc[i], rb2 = g.rc[i + 1] * g.rc[i + 1];
       const double ira2 = g.irc[i] * g.irc[i], irb2 = g.irc[i + 1] * g.irc[i + 1];
       gp = irho * g.idr;
-      cp = un * (0.5 * g.idr) - nu * rb2 * irF2 * d2 - nu / 3.0 * g.rf[i + 2] * g.rf[i + 2] * irb2 * d2;
-      c0 = nu * (rb2 + ra2) * irF2 * d2 + nu / 3.0 * rF2 * (irb2 + ira2) * d2;
-      cm = -un * (0.5 * g.idr) - nu * ra2 * irF2 * d2 - nu / 3.0 * g.rf[i] * g.rf[i] * ira2 * d2;
+      cp = un * (0.5 * g.idr) - nu * rb2 * irF2 * d2 - nu * (1.0 / 3.0) * g.rf[i + 2] * g.rf[i + 2] * irb2 * d2;
+      c0 = nu * (rb2 + ra2) * irF2 * d2 + nu * (1.0 / 3.0) * rF2 * (irb2 + ira2) * d2;
+      cm = -un * (0.5 * g.idr) - nu * ra2 * irF2 * d2 - nu * (1.0 / 3.0) * g.rf[i] * g.rf[i] * ira2 * d2;
     } else if (D == 1) {
       const int f = j + 1;
-      const double irho = 1.0 / (0.5 * (rho_at(g, m, u, i, j, k) + rho_at(g, m, u, i, j + 1, k)));
+      const double irho = irho_mean(g, m, u, i, j, k, i, j + 1, k);
       const double nu = m.mu * irho, un = u.ld(F_UT, idx_t(g, i, f, k));
       const double sF = g.sf[f], isF = g.isf[f], r2d2 = ir2 * g.idt * g.idt;
       const double sa = g.sc[j], sb = g.sc[j + 1], isa = g.isc[j], isb = g.isc[j + 1];
       gp = irho * ir * g.idt;
-      cp = un * (0.5 * ir * g.idt) - nu * sb * r2d2 * isF - nu / 3.0 * g.sf[j + 2] * r2d2 * isb;
-      c0 = nu * (sb + sa) * r2d2 * isF + nu / 3.0 * sF * (isb + isa) * r2d2;
-      cm = -un * (0.5 * ir * g.idt) - nu * sa * r2d2 * isF - nu / 3.0 * g.sf[j] * r2d2 * isa;
+      cp = un * (0.5 * ir * g.idt) - nu * sb * r2d2 * isF - nu * (1.0 / 3.0) * g.sf[j + 2] * r2d2 * isb;
+      c0 = nu * (sb + sa) * r2d2 * isF + nu * (1.0 / 3.0) * sF * (isb + isa) * r2d2;
+      cm = -un * (0.5 * ir * g.idt) - nu * sa * r2d2 * isF - nu * (1.0 / 3.0) * g.sf[j] * r2d2 * isa;
     } else {
       const int f = g.periodic ? wrapk(g, k + 1) : k + 1;
-      const double irho = 1.0 / (0.5 * (rho_at(g, m, u, i, j, k) + rho_at(g, m, u, i, j, k + 1)));
+      const double irho = irho_mean(g, m, u, i, j, k, i, j, k + 1);
       const double nu = m.mu * irho, un = u.ld(F_UF, idx_f(g, i, j, f));
       const double q2 = ir2 * is * is * g.idp * g.idp;
       gp = irho * ir * is * g.idp;
-      cp = un * (0.5 * ir * is * g.idp) - 4.0 * nu / 3.0 * q2;
-      c0 = 8.0 * nu / 3.0 * q2;
-      cm = -un * (0.5 * ir * is * g.idp) - 4.0 * nu / 3.0 * q2;
+      cp = un * (0.5 * ir * is * g.idp) - nu * (4.0 / 3.0) * q2;
+      c0 = nu * (8.0 / 3.0) * q2;
+      cm = -un * (0.5 * ir * is * g.idp) - nu * (4.0 / 3.0) * q2;
     }
     R.D[6] = -gp; R.U[6] = gp;
     R.L[8] = cm; R.D[8] = c0; R.U[8] = cp;
@@ -297,22 +297,22 @@ __device__ __forceinline__ void scalar_row(const Geo &g, const Mat &m, const S &
   if (D == 0) {
     const int i = s;
     const double ir = g.irc[i], r2d2 = ir * ir * g.idr * g.idr;
-    double ua, rho;
+    double ua, irho;
     if (FAM == 0) { // u_theta at theta-face (jf, k)
       const int jf = a, k = b;
       ua = 0.25 * (u.ld(F_UR, idx_r(g, i, jf - 1, k)) + u.ld(F_UR, idx_r(g, i, jf, k)) +
                    u.ld(F_UR, idx_r(g, i + 1, jf - 1, k)) + u.ld(F_UR, idx_r(g, i + 1, jf, k)));
-      rho = 0.5 * (rho_at(g, m, u, i, jf - 1, k) + rho_at(g, m, u, i, jf, k));
+      irho = irho_mean(g, m, u, i, jf - 1, k, i, jf, k);
       xi = idx_t(g, i, jf, k); arr = rhs.ut;
     } else { // u_phi at phi-face (j, kf)
       const int j = a, kf = b;
       const int k0 = g.periodic ? wrapk(g, kf - 1) : kf - 1, k1 = g.periodic ? wrapk(g, kf) : kf;
       ua = 0.25 * (u.ld(F_UR, idx_r(g, i, j, k0)) + u.ld(F_UR, idx_r(g, i, j, k1)) +
                    u.ld(F_UR, idx_r(g, i + 1, j, k0)) + u.ld(F_UR, idx_r(g, i + 1, j, k1)));
-      rho = 0.5 * (rho_at(g, m, u, i, j, k0) + rho_at(g, m, u, i, j, k1));
+      irho = irho_mean(g, m, u, i, j, k0, i, j, k1);
       xi = idx_f(g, i, j, kf); arr = rhs.uf;
     }
-    const double nu = m.mu / rho;
+    const double nu = m.mu * irho;
     const double fp = g.rf[i + 1] * g.rf[i + 1], fm = g.rf[i] * g.rf[i];
     ca = -ua * (0.5 * g.idr) - nu * fm * r2d2;
     cb = nu * (fp + fm) * r2d2;
@@ -320,13 +320,13 @@ __device__ __forceinline__ void scalar_row(const Geo &g, const Mat &m, const S &
   } else if (D == 1) {
     const int j = s;
     const double is = g.isc[j];
-    double ua, rho, irr;
+    double ua, irho, irr;
     if (FAM == 0) { // u_r at r-face (fr, k)
       const int fr = a, k = b;
       irr = g.irf[fr];
       ua = 0.25 * (u.ld(F_UT, idx_t(g, fr - 1, j, k)) + u.ld(F_UT, idx_t(g, fr - 1, j + 1, k)) +
                    u.ld(F_UT, idx_t(g, fr, j, k)) + u.ld(F_UT, idx_t(g, fr, j + 1, k)));
-      rho = 0.5 * (rho_at(g, m, u, fr - 1, j, k) + rho_at(g, m, u, fr, j, k));
+      irho = irho_mean(g, m, u, fr - 1, j, k, fr, j, k);
       xi = idx_r(g, fr, j, k); arr = rhs.ur;
       sglo = g.pole_lo ? 1.0 : -1.0;
       sghi = g.pole_hi ? 1.0 : -1.0;
@@ -336,23 +336,23 @@ __device__ __forceinline__ void scalar_row(const Geo &g, const Mat &m, const S &
       const int k0 = g.periodic ? wrapk(g, kf - 1) : kf - 1, k1 = g.periodic ? wrapk(g, kf) : kf;
       ua = 0.25 * (u.ld(F_UT, idx_t(g, i, j, k0)) + u.ld(F_UT, idx_t(g, i, j, k1)) +
                    u.ld(F_UT, idx_t(g, i, j + 1, k0)) + u.ld(F_UT, idx_t(g, i, j + 1, k1)));
-      rho = 0.5 * (rho_at(g, m, u, i, j, k0) + rho_at(g, m, u, i, j, k1));
+      irho = irho_mean(g, m, u, i, j, k0, i, j, k1);
       xi = idx_f(g, i, j, kf); arr = rhs.uf;
     }
-    const double nu = m.mu / rho, q = irr * irr * is * g.idt * g.idt;
+    const double nu = m.mu * irho, q = irr * irr * is * g.idt * g.idt;
     ca = -ua * (0.5 * irr * g.idt) - nu * g.sf[j] * q;
     cb = nu * (g.sf[j + 1] + g.sf[j]) * q;
     cc_ = ua * (0.5 * irr * g.idt) - nu * g.sf[j + 1] * q;
   } else {
     const int k = s;
-    double ua, rho, irr, iss;
+    double ua, irho, irr, iss;
     if (FAM == 0) { // u_r at r-face (fr, j)
       const int fr = a, j = b;
       irr = g.irf[fr]; iss = g.isc[j];
       const int kp = g.periodic ? wrapk(g, k + 1) : k + 1;
       ua = 0.25 * (u.ld(F_UF, idx_f(g, fr - 1, j, k)) + u.ld(F_UF, idx_f(g, fr - 1, j, kp)) +
                    u.ld(F_UF, idx_f(g, fr, j, k)) + u.ld(F_UF, idx_f(g, fr, j, kp)));
-      rho = 0.5 * (rho_at(g, m, u, fr - 1, j, k) + rho_at(g, m, u, fr, j, k));
+      irho = irho_mean(g, m, u, fr - 1, j, k, fr, j, k);
       xi = idx_r(g, fr, j, k); arr = rhs.ur;
     } else { // u_theta at theta-face (i, ft)
       const int i = a, ft = b;
@@ -360,10 +360,10 @@ __device__ __forceinline__ void scalar_row(const Geo &g, const Mat &m, const S &
       const int kp = g.periodic ? wrapk(g, k + 1) : k + 1;
       ua = 0.25 * (u.ld(F_UF, idx_f(g, i, ft - 1, k)) + u.ld(F_UF, idx_f(g, i, ft - 1, kp)) +
                    u.ld(F_UF, idx_f(g, i, ft, k)) + u.ld(F_UF, idx_f(g, i, ft, kp)));
-      rho = 0.5 * (rho_at(g, m, u, i, ft - 1, k) + rho_at(g, m, u, i, ft, k));
+      irho = irho_mean(g, m, u, i, ft - 1, k, i, ft, k);
       xi = idx_t(g, i, ft, k); arr = rhs.ut;
     }
-    const double nu = m.mu / rho, q = irr * irr * iss * iss * g.idp * g.idp;
+    const double nu = m.mu * irho, q = irr * irr * iss * iss * g.idp * g.idp;
     ca = -ua * (0.5 * irr * iss * g.idp) - nu * q;
     cb = 2.0 * nu * q;
     cc_ = ua * (0.5 * irr * iss * g.idp) - nu * q;
