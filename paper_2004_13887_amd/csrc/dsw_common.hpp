@@ -255,19 +255,31 @@ __device__ __forceinline__ double pcoef(const Geo &g, const S &s, int i, int j, 
   return p;
 }
 
+// 1 / x from the hardware reciprocal estimate refined by two Newton-Raphson
+// steps (e = 1 - x r, r <- r + r e): within an ulp of the rounded quotient
+// for normal x, with half the instructions of the IEEE division sequence;
+// x = 0 or a non-finite x gives a non-finite result.
+__device__ __forceinline__ double rcp_nr(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = __builtin_fma(-x, r, 1.0);
+  r = __builtin_fma(r, e, r);
+  e = __builtin_fma(-x, r, 1.0);
+  return __builtin_fma(r, e, r);
+}
+
 template <class S>
 __device__ __forceinline__ double rho_at(const Geo &g, const Mat &m, const S &s, int i, int j, int k) {
   return (pcoef(g, s, i, j, k) + m.pinf) / (m.Rg * gC(g, s, F_T, i, j, k));
 }
 
 // 1 / (0.5 (rho_a + rho_b)), the inverse mean density of two cells, with one
-// division instead of three: 2 R T_a T_b / ((p_a + pi_inf) T_b + (p_b + pi_inf) T_a)
+// reciprocal instead of three divisions: 2 R T_a T_b / ((p_a + pi_inf) T_b + (p_b + pi_inf) T_a)
 template <class S>
 __device__ __forceinline__ double irho_mean(const Geo &g, const Mat &m, const S &s, int ia, int ja, int ka,
                                             int ib, int jb, int kb) {
   const double pa = pcoef(g, s, ia, ja, ka) + m.pinf, pb = pcoef(g, s, ib, jb, kb) + m.pinf;
   const double ta = gC(g, s, F_T, ia, ja, ka), tb = gC(g, s, F_T, ib, jb, kb);
-  return 2.0 * m.Rg * ta * tb / (pa * tb + pb * ta);
+  return 2.0 * m.Rg * ta * tb * rcp_nr(pa * tb + pb * ta);
 }
 
 // Coefficient fields at a centre: centre-averaged velocities, thermodynamic
@@ -303,7 +315,7 @@ __device__ __forceinline__ void centre(const Geo &g, const Mat &m, const S &s, i
   c.uf = 0.5 * (f0 + f1);
   c.P = pcoef(g, s, i, j, k) + m.pinf;
   c.T = gC(g, s, F_T, i, j, k);
-  c.chi = (m.gam - 1.0) * c.T / c.P;
+  c.chi = (m.gam - 1.0) * c.T * rcp_nr(c.P);
   c.Grr = (r1 - r0) * g.idr;
   c.Gtt = (t1 - t0) * (ir * g.idt) + c.ur * ir;
   c.Gff = (f1 - f0) * (irs * g.idp) + c.ur * ir + c.ut * ct * ir;

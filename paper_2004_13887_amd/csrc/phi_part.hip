@@ -94,13 +94,13 @@ __device__ __forceinline__ void pcr_scalar(int t, int T, int cyc, double &A, dou
       if (cyc) { lo = (lo % T + T) % T; hi = hi % T; has_lo = has_hi = true; }
       double nA = 0.0, nC = 0.0, nB = B, nr = r;
       if (has_lo) {
-        const double al = -A / sB[lo];
+        const double al = -A * rcp_nr(sB[lo]);
         nA = al * sA[lo];
         nB += al * sC[lo];
         nr += al * sR[lo];
       }
       if (has_hi) {
-        const double be = -C / sB[hi];
+        const double be = -C * rcp_nr(sB[hi]);
         nC = be * sC[hi];
         nB += be * sA[hi];
         nr += be * sR[hi];
@@ -112,7 +112,7 @@ __device__ __forceinline__ void pcr_scalar(int t, int T, int cyc, double &A, dou
   if (act) {
     const double S = A + B + C;
     if (!(S != 0.0)) status[ST_SINGULAR] = 1;
-    x = r / S;
+    x = r * rcp_nr(S);
   }
 }
 
@@ -140,13 +140,13 @@ __device__ __forceinline__ void pcr_scalar2(int t, int T, int cyc, double *A, do
         const double *sA = lds + 4 * T * f, *sC = sA + T, *sR = sA + 2 * T, *sB = sA + 3 * T;
         double nA = 0.0, nC = 0.0, nB = B[f], nr = r[f];
         if (has_lo) {
-          const double al = -A[f] / sB[lo];
+          const double al = -A[f] * rcp_nr(sB[lo]);
           nA = al * sA[lo];
           nB += al * sC[lo];
           nr += al * sR[lo];
         }
         if (has_hi) {
-          const double be = -C[f] / sB[hi];
+          const double be = -C[f] * rcp_nr(sB[hi]);
           nC = be * sC[hi];
           nB += be * sA[hi];
           nr += be * sR[hi];
@@ -161,7 +161,7 @@ __device__ __forceinline__ void pcr_scalar2(int t, int T, int cyc, double *A, do
     for (int f = 0; f < 2; f++) {
       const double S = A[f] + B[f] + C[f];
       if (!(S != 0.0)) status[ST_SINGULAR] = 1;
-      x[f] = r[f] / S;
+      x[f] = r[f] * rcp_nr(S);
     }
   }
 }
@@ -377,7 +377,7 @@ __device__ __forceinline__ void part_scalar_line(const Geo &g, const Mat &m, con
         double dp = R.b, rr = R.r, lx = R.a;
         if (q > 0) { dp -= R.a * Cm[q - 1]; rr -= R.a * Ym[q - 1]; lx = -R.a * Em[q - 1]; }
         if (!(dp != 0.0)) status[ST_SINGULAR] = 1;
-        const double id = 1.0 / dp;
+        const double id = rcp_nr(dp);
         Cm[q] = R.c * id;
         Ym[q] = rr * id;
         Em[q] = lx * id;

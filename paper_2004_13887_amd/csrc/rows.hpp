@@ -30,7 +30,7 @@ __device__ __forceinline__ bool inv3q(const double *A, double *X) {
   const double c01 = A[5] * A[6] - A[3] * A[8];
   const double c02 = A[3] * A[7] - A[4] * A[6];
   const double det = A[0] * c00 + A[1] * c01 + A[2] * c02;
-  const double id = 1.0 / det;
+  const double id = rcp_nr(det);
   X[0] = c00 * id;
   X[1] = (A[2] * A[7] - A[1] * A[8]) * id;
   X[2] = (A[1] * A[5] - A[2] * A[4]) * id;
@@ -401,7 +401,7 @@ __device__ __forceinline__ bool scalar_chunk_fwd(const RowFn &row, int a0, int l
     double dp = R[q].b, rr = R[q].r, lx = R[q].a;
     if (q > 0) { dp -= R[q].a * Cm[q - 1]; rr -= R[q].a * Ym[q - 1]; lx = -R[q].a * Em[q - 1]; }
     sing |= q < len - 1 && !(dp != 0.0);
-    const double id = 1.0 / dp;
+    const double id = rcp_nr(dp);
     Cm[q] = R[q].c * id;
     Ym[q] = rr * id;
     Em[q] = lx * id;

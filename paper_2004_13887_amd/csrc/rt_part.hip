@@ -80,7 +80,7 @@ __device__ __forceinline__ void rt_pcr_scalar(int c, int l, int T, int L, bool a
   for (int h = 1; h < T; h *= 2) {
     if (act) {
       if (!(B != 0.0)) status[ST_SINGULAR] = 1;
-      const double ib = 1.0 / B;
+      const double ib = rcp_nr(B);
       sA[t] = A * ib;
       sC[t] = C * ib;
       sR[t] = r * ib;
@@ -107,7 +107,7 @@ __device__ __forceinline__ void rt_pcr_scalar(int c, int l, int T, int L, bool a
   }
   if (act) {
     if (!(B != 0.0)) status[ST_SINGULAR] = 1;
-    x = r / B;
+    x = r * rcp_nr(B);
   }
 }
 
@@ -325,7 +325,7 @@ __device__ __forceinline__ void rt_scalar_lines(const Geo &g, const Mat &m, cons
       double dp = R.b, rr = R.r, lx = R.a;
       if (q > 0) { dp -= R.a * Cm[q - 1]; rr -= R.a * Ym[q - 1]; lx = -R.a * Em[q - 1]; }
       if (!(dp != 0.0)) status[ST_SINGULAR] = 1;
-      const double id = 1.0 / dp;
+      const double id = rcp_nr(dp);
       Cm[q] = R.c * id;
       Ym[q] = rr * id;
       Em[q] = lx * id;

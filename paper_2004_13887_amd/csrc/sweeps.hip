@@ -239,7 +239,7 @@ __device__ __forceinline__ void solve_scalar_line(const Geo &g, const Mat &m, co
       scalar_row<D, FAM>(g, m, u, rhs, a, b, s, n, 0, hs, R, xi, arr);
       const double den = R.b - R.a * cpv;
       if (!(den != 0.0)) status[ST_SINGULAR] = 1;
-      id = 1.0 / den;
+      id = rcp_nr(den);
       zv = R.r - cpv * zv;
       cpv = R.c * id;
       av = R.a;
@@ -260,7 +260,7 @@ __device__ __forceinline__ void solve_scalar_line(const Geo &g, const Mat &m, co
       get_srow<D, FAM, TR>(g, m, u, rhs, a, b, s, n, 0, hs, R, xi, arr);
       const double den = R.b - R.a * cpv;
       if (!(den != 0.0)) status[ST_SINGULAR] = 1;
-      const double id = 1.0 / den;
+      const double id = rcp_nr(den);
       cpv = R.c * id;
       yv = (R.r - R.a * yv) * id;
       if (s < n - 1) { SC(s, 0) = cpv; SC(s, 1) = yv; }
@@ -284,7 +284,7 @@ __device__ __forceinline__ void solve_scalar_line(const Geo &g, const Mat &m, co
       else { den = R.b - R.a * cpv; e = -R.a * zv; }
       if (s == n - 2) { e += c; c = 0.0; }
       if (!(den != 0.0)) status[ST_SINGULAR] = 1;
-      const double id = 1.0 / den;
+      const double id = rcp_nr(den);
       yv = (s == 0 ? R.r : R.r - R.a * yv) * id;
       cpv = c * id;
       zv = e * id;
@@ -300,7 +300,7 @@ __device__ __forceinline__ void solve_scalar_line(const Geo &g, const Mat &m, co
     get_srow<D, FAM, TR>(g, m, u, rhs, a, b, n - 1, n, 1, hs, R, xi, arr);
     const double den = R.b - R.a * zl - R.c * zv;
     if (!(den != 0.0)) status[ST_SINGULAR] = 1;
-    const double xl = (R.r - R.a * yl - R.c * yv) / den;
+    const double xl = (R.r - R.a * yl - R.c * yv) * rcp_nr(den);
     put(o, ofid, xi, xl);
     for (int s = 0; s < n - 1; s++) {
       const double xv = SC(s, 1) - SC(s, 2) * xl;
@@ -711,7 +711,7 @@ __device__ __forceinline__ void twisted_scalar_line(const Geo &g, const Mat &m, 
         scalar_row<D, FAM>(g, m, u, rhs, a, b, s, n, 0, hs, R, xi, arr);
         const double den = R.b - R.a * cv;
         sing |= !(den != 0.0);
-        const double id = 1.0 / den;
+        const double id = rcp_nr(den);
         yv = (R.r - R.a * yv) * id;
         cv = R.c * id;
         SC(s, 0) = cv;
@@ -723,7 +723,7 @@ __device__ __forceinline__ void twisted_scalar_line(const Geo &g, const Mat &m, 
         scalar_row<D, FAM>(g, m, u, rhs, a, b, s, n, 0, hs, R, xi, arr);
         const double den = R.b - R.c * cv;
         sing |= !(den != 0.0);
-        const double id = 1.0 / den;
+        const double id = rcp_nr(den);
         yv = (R.r - R.c * yv) * id;
         cv = R.a * id;
         SC(s, 0) = cv;
@@ -739,7 +739,7 @@ __device__ __forceinline__ void twisted_scalar_line(const Geo &g, const Mat &m, 
     scalar_row<D, FAM>(g, m, u, rhs, a, b, mid, n, 0, hs, R, xi, arr);
     const double den = R.b - R.a * cv - R.c * my[0];
     if (!(den != 0.0)) status[ST_SINGULAR] = 1;
-    const double xm = (R.r - R.a * yv - R.c * my[1]) / den;
+    const double xm = (R.r - R.a * yv - R.c * my[1]) * rcp_nr(den);
     put(o, ofid, xi, xm);
     my[2] = xm;
   }
@@ -792,7 +792,7 @@ __device__ __forceinline__ void twisted_scalar_line_T(const Geo &g, const Mat &m
         const double at = w0, bt = wb, ct = R.a, rt = wr; // transposed row s
         const double den = bt - at * cv;
         sing |= !(den != 0.0);
-        const double id = 1.0 / den;
+        const double id = rcp_nr(den);
         yv = (rt - at * yv) * id;
         cv = ct * id;
         SC(s, 0) = cv;
@@ -808,7 +808,7 @@ __device__ __forceinline__ void twisted_scalar_line_T(const Geo &g, const Mat &m
         const double at = R.c, bt = wb, ct = w0, rt = wr; // transposed row s
         const double den = bt - ct * cv;
         sing |= !(den != 0.0);
-        const double id = 1.0 / den;
+        const double id = rcp_nr(den);
         yv = (rt - ct * yv) * id;
         cv = at * id;
         SC(s, 0) = cv;
@@ -826,7 +826,7 @@ __device__ __forceinline__ void twisted_scalar_line_T(const Geo &g, const Mat &m
     const double at = w0, bt = wb, ct = R.a, rt = wr;
     const double den = bt - at * cv - ct * my[0];
     if (!(den != 0.0)) status[ST_SINGULAR] = 1;
-    const double xm = (rt - at * yv - ct * my[1]) / den;
+    const double xm = (rt - at * yv - ct * my[1]) * rcp_nr(den);
     put(o, ofid, scalar_index<D, FAM>(g, a, b, mid), xm);
     my[2] = xm;
   }
