@@ -53,7 +53,7 @@ __device__ __forceinline__ void pcr_block(int t, int T, int cyc, double *A, doub
     if (act) {
       int lo = t - h, hi = t + h;
       bool has_lo = lo >= 0, has_hi = hi < T;
-      if (cyc) { lo = (lo % T + T) % T; hi = hi % T; has_lo = has_hi = true; }
+      if (cyc) { lo &= T - 1; hi &= T - 1; has_lo = has_hi = true; }  // cyclic: T a power of two
       // B' = B - A P_C(lo) - C P_A(hi), r' alike, A' = -A P_A(lo),
       // C' = -C P_C(hi) (P = B^{-1} times the published row)
       if (has_lo) { mm3_sub(A, &sPC[lo * 9], B); mv3_sub(A, &sPr[lo * 3], r); }
@@ -91,7 +91,7 @@ __device__ __forceinline__ void pcr_scalar(int t, int T, int cyc, double &A, dou
     if (act) {
       int lo = t - h, hi = t + h;
       bool has_lo = lo >= 0, has_hi = hi < T;
-      if (cyc) { lo = (lo % T + T) % T; hi = hi % T; has_lo = has_hi = true; }
+      if (cyc) { lo &= T - 1; hi &= T - 1; has_lo = has_hi = true; }  // cyclic: T a power of two
       double nA = 0.0, nC = 0.0, nB = B, nr = r;
       if (has_lo) {
         const double al = -A * rcp_nr(sB[lo]);
@@ -134,7 +134,7 @@ __device__ __forceinline__ void pcr_scalar2(int t, int T, int cyc, double *A, do
     if (act) {
       int lo = t - h, hi = t + h;
       bool has_lo = lo >= 0, has_hi = hi < T;
-      if (cyc) { lo = (lo % T + T) % T; hi = hi % T; has_lo = has_hi = true; }
+      if (cyc) { lo &= T - 1; hi &= T - 1; has_lo = has_hi = true; }  // cyclic: T a power of two
 #pragma unroll
       for (int f = 0; f < 2; f++) {
         const double *sA = lds + 4 * T * f, *sC = sA + T, *sR = sA + 2 * T, *sB = sA + 3 * T;
