@@ -358,12 +358,8 @@ __device__ __forceinline__ void residual_point_in(const Geo &g, const Mat &m, co
 }
 
 template <class SI>
-__device__ __forceinline__ void residual_body_in(const PassArgs &a, unsigned w) {
+__device__ __forceinline__ void residual_at_in(const PassArgs &a, unsigned kb, int j, int i) {
   const Geo &g = a.g;
-  const int bs = (int)blockDim.x;
-  const unsigned nkin = (unsigned)res_nk(g, bs);
-  const unsigned kb = w % nkin, rest = w / nkin;
-  const int j = 1 + (int)(rest % (unsigned)(g.nt - 2)), i = 1 + (int)(rest / (unsigned)(g.nt - 2));
   SI s;
 #pragma unroll
   for (int q = 0; q < 5; q++) s.a[q] = a.u.a[q];
@@ -377,6 +373,17 @@ __device__ __forceinline__ void residual_body_in(const PassArgs &a, unsigned w) 
     s.tref = a.tref;
   }
   residual_point_in<SI>(g, a.m, s, a.d, a.tau, a.R, a.status, i, j, (int)(kb * blockDim.x + threadIdx.x));
+}
+
+// workgroup w of a one-dimensional launch: phi block fastest, then j, then i
+template <class SI>
+__device__ __forceinline__ void residual_body_in(const PassArgs &a, unsigned w) {
+  const Geo &g = a.g;
+  const int bs = (int)blockDim.x;
+  const unsigned nkin = (unsigned)res_nk(g, bs);
+  const unsigned kb = w % nkin, rest = w / nkin;
+  const int j = 1 + (int)(rest % (unsigned)(g.nt - 2)), i = 1 + (int)(rest / (unsigned)(g.nt - 2));
+  residual_at_in<SI>(a, kb, j, i);
 }
 
 template <bool B>
@@ -432,7 +439,10 @@ __global__ void __launch_bounds__(256) k_residual_in(PassArgs a, Batch bt) {
     const PassArgs am = batch_args(bt, mb);  // loaded once, before any store
     residual_body_in<SI>(am, blockIdx.x - bt.woff[mb]);
   } else {
-    residual_body_in<SI>(a, blockIdx.x);
+    // one grid: a three-dimensional launch (phi block, j - 1, i - 1), so the
+    // workgroup's indices need no integer division (on this GPU a division
+    // of even uniform integers runs on the vector unit)
+    residual_at_in<SI>(a, blockIdx.x, 1 + (int)blockIdx.y, 1 + (int)blockIdx.z);
   }
 }
 
@@ -465,7 +475,11 @@ void launch_residual_pass(const PassArgs &a, const Batch &b, unsigned blocks, un
 
 void launch_residual_in_pass(bool periodic, const PassArgs &a, const Batch &b, unsigned blocks,
                              unsigned threads, hipStream_t st) {
-  const dim3 gr(blocks), bl(threads);
+  const dim3 bl(threads);
+  // a batch numbers its members' workgroups in one dimension; one grid takes
+  // the same workgroups, in the same order, as (phi block, j - 1, i - 1)
+  const dim3 gr = b.tab ? dim3(blocks)
+                        : dim3((unsigned)res_nk(a.g, (int)threads), (unsigned)(a.g.nt - 2), (unsigned)(a.g.nr - 2));
   if (periodic) {
     if (b.tab) hipLaunchKernelGGL((k_residual_in<true, true>), gr, bl, 0, st, a, b);
     else hipLaunchKernelGGL((k_residual_in<false, true>), gr, bl, 0, st, a, b);
